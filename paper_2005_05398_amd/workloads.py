@@ -1,0 +1,105 @@
+"""Problem descriptions and seeded inputs shared by the oracle tests, the HIP
+path's tests and the benchmark.
+
+This module holds data only: particle sets, grid sizes, domains, energies and
+seeded random right-hand sides.  It contains none of the method's arithmetic,
+so both sides of every parity test can take their inputs from here without
+sharing code.
+
+A problem description is a plain dict:
+
+    masses   (m1, m2, m3)              particle masses (Sec. 2.1)
+    charges  (Z1, Z2, Z3)              particle charges (Sec. 2.1)
+    J, tau                             total orbital momentum and parity (Sec. 2.2)
+    x, y, z  [dim, dim, dim]           one 1D basis per Faddeev component alpha
+             dim = {"degree": 3|5, "n": int, "R": float, "map": str}
+    x0, y0, nu                         Merkuriev cut-off parameters, eq. (Mcutoff0)
+    vhat                               0: Vhat_a(y) = Z_a(Z_b+Z_c) sqrt(2 mu_a(bc)) / (y+1)
+
+"map" is "uniform" or "quadratic" for x, y and "sin" or "uniform" for z.
+"""
+import math
+
+import numpy as np
+
+INF = math.inf
+
+
+def _dims(degree, n, R, mapname):
+    return [{"degree": degree, "n": n, "R": R, "map": mapname} for _ in range(3)]
+
+
+def make_desc(masses, charges, nxy, nz, *, J=0, tau=1, deg_xy=5, deg_z=5,
+              R=20.0, xy_map="uniform", z_map="sin", x0=5.0, y0=INF, nu=2.01,
+              vhat=0):
+    """A description with the same grid for all three components."""
+    return {
+        "masses": tuple(float(m) for m in masses),
+        "charges": tuple(float(c) for c in charges),
+        "J": int(J), "tau": int(tau),
+        "x": _dims(deg_xy, nxy, R, xy_map),
+        "y": _dims(deg_xy, nxy, R, xy_map),
+        "z": _dims(deg_z, nz, 2.0, z_map),
+        "x0": float(x0), "y0": float(y0), "nu": float(nu), "vhat": int(vhat),
+    }
+
+
+def admissible_xy(n, degree=5):
+    """Nearest admissible x/y basis size: quintic n = 3K+1, cubic n = 2K."""
+    if degree == 3:
+        return n + (n % 2)
+    cands = [m for m in range(max(4, n - 3), n + 4) if m % 3 == 1]
+    return min(cands, key=lambda m: (abs(m - n), m))
+
+
+# Particle sets of the workloads.
+PS_MINUS = ((1.0, 1.0, 1.0), (1.0, -1.0, -1.0))       # e+ e- e- : particles 2, 3 identical
+H_MINUS = ((1.0, 1.0, 1836.0), (-1.0, -1.0, 1.0))     # e- e- p  : particles 1, 2 identical
+
+
+def cfg1():
+    """FP64, L=0, cubic 16 x 16 x 8 on [0,20]^2 x [-1,1], E=-0.25, one RHS."""
+    d = make_desc(*PS_MINUS, 16, 8, deg_xy=3, deg_z=3, R=20.0)
+    return {"name": "cfg1_cubic_16x16x8_L0", "desc": d, "E": [-0.25], "seeds": [1001]}
+
+
+def cfg2():
+    """FP64, L=0, quintic 64 x 64 x 24, x,y in [0,40] graded quadratically
+    toward 0, energy scan of 32 values in [-0.6, -0.1], one RHS per energy."""
+    d = make_desc(*H_MINUS, 64, 24, deg_xy=5, deg_z=5, R=40.0, xy_map="quadratic")
+    E = list(np.linspace(-0.6, -0.1, 32))
+    return {"name": "cfg2_quintic_64x64x24_L0_scan32", "desc": d, "E": E,
+            "seeds": [2001 + i for i in range(32)]}
+
+
+def cfg3():
+    """Mixed precision, L=0, quintic x,y (nominal 128, taken as 127 = 3*42+1,
+    uniform on [0,20]) x cubic z 32."""
+    d = make_desc(*PS_MINUS, admissible_xy(128), 32, deg_xy=5, deg_z=3, R=20.0)
+    return {"name": "cfg3_quintic128_cubicz32_L0", "desc": d, "E": [-0.25], "seeds": [3001]}
+
+
+def cfg4():
+    """L=2, tau=+1 (three M' blocks), quintic x,y (nominal 96, taken as
+    97 = 3*32+1) x cubic z 32, E=-0.2."""
+    d = make_desc(*PS_MINUS, admissible_xy(96), 32, J=2, tau=1, deg_xy=5, deg_z=3, R=20.0)
+    return {"name": "cfg4_L2_quintic96_cubicz32", "desc": d, "E": [-0.2], "seeds": [4001]}
+
+
+CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}
+
+
+def n_unknowns(desc):
+    """N = n_M * sum_alpha n_z n_x n_y with n_M = J - M0 + 1, M0 = (1 - tau)/2."""
+    m0 = (1 - desc["tau"]) // 2
+    n_m = desc["J"] - m0 + 1
+    return n_m * sum(desc["z"][a]["n"] * desc["x"][a]["n"] * desc["y"][a]["n"] for a in range(3))
+
+
+def rhs(seed, n):
+    """Seeded N(0,1) right-hand side in collocation-row space (PCG64)."""
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)
+
+
+def rhs_batch(seeds, n):
+    return np.stack([rhs(s, n) for s in seeds])

@@ -1,0 +1,176 @@
+"""Pins for the oracle's collocation matrix A(E) = H - E S (paper Sec. 3.1-3.3).
+
+P10 (manufactured solution): take each partial component psi-hat in the spline
+space (a product of polynomials of the spline degree meeting the closures).
+Then A c must equal the operator of eq. (FM-pre), moved to the left side,
+applied analytically to those polynomials and evaluated at the collocation
+points, including the coupling to the other components at the rotated
+points (zero outside a component's box).  The analytic side differentiates
+the polynomials directly; the assembly goes through the spline basis.
+
+P9 (identical particles): with two identical particles the operator commutes
+with their permutation, which swaps the two components, reflects z and
+multiplies by (-1)^{M'} (Sec. 2.3, eq. (2-sym-part)).
+
+Block form: the diagonal blocks of A equal the paper's Kronecker-product
+left-hand operator L_alpha (Sec. 3.2) plus the rest of the potential,
+(sum_b V_b^(l) - Vhat_a) S.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import physics as ph
+from oracle.assemble import Problem
+from oracle.wigner import F_rot, lam_hat_minus, lam_hat_plus, w_angle
+from paper_2005_05398_amd import workloads as W
+
+P = np.polynomial.polynomial
+
+
+def small_desc(masses_charges, nxy=7, nz=6, J=0, tau=1, deg_xy=5, deg_z=5, R=12.0, xy_map="uniform"):
+    return W.make_desc(*masses_charges, nxy, nz, J=J, tau=tau, deg_xy=deg_xy, deg_z=deg_z, R=R,
+                       xy_map=xy_map, x0=3.0)
+
+
+def manufactured(prob, rng):
+    """Random polynomial factors per (alpha, M') and the coefficient vector."""
+    polys = {}
+    c = np.zeros(prob.N)
+    for a in range(3):
+        for iM in range(prob.nM):
+            bx, by, bz = prob.bx[a], prob.by[a], prob.bz[a]
+            px = P.polymul(P.polymul([0, 1], [bx.R, -1]), rng.standard_normal(2 * bx.q - 2))
+            py = P.polymul(P.polymul([0, 1], [by.R, -1]), rng.standard_normal(2 * by.q - 2))
+            pz = rng.standard_normal(2 * bz.q)
+            polys[a, iM] = (px, py, pz)
+            cx = bx.coefficients_of(lambda d, t: P.polyval(t, P.polyder(px, d)))
+            cy = by.coefficients_of(lambda d, t: P.polyval(t, P.polyder(py, d)))
+            cz = bz.coefficients_of(lambda d, t: P.polyval(t, P.polyder(pz, d)))
+            o = prob.offsets[a][iM]
+            c[o:o + prob.block[a]] = np.einsum("k,i,j->kij", cz, cx, cy).ravel()
+    return polys, c
+
+
+def analytic(prob, polys, E):
+    d = prob.desc
+    J = prob.J
+    out = np.zeros(prob.N)
+    ev = lambda p, t, k=0: P.polyval(t, P.polyder(p, k))
+    for a in range(3):
+        z, x, y = prob.points(a)
+        for iM, Mp in enumerate(prob.Mps):
+            px, py, pz = polys[a, iM]
+            val = (-ev(px, x) * ev(py, y, 2) * ev(pz, z) - ev(px, x, 2) * ev(py, y) * ev(pz, z)
+                   - (1 / x ** 2 + 1 / y ** 2) * ((1 - z * z) * ev(pz, z, 2) - 2 * (Mp + 1) * z * ev(pz, z, 1)
+                                                   - Mp * (Mp + 1) * ev(pz, z)) * ev(px, x) * ev(py, y)
+                   + ((J * (J + 1) - 2 * Mp * Mp) / y ** 2 + ph.potential_field(d, a, x, y, z) - E)
+                   * ev(px, x) * ev(py, y) * ev(pz, z))
+            if iM + 1 < prob.nM:
+                qx, qy, qz = polys[a, iM + 1]
+                val += (lam_hat_plus(J, Mp) / y ** 2 * (-(1 - z * z) * ev(qz, z, 1) + 2 * (Mp + 1) * z * ev(qz, z))
+                        * ev(qx, x) * ev(qy, y))
+            if iM >= 1:
+                qx, qy, qz = polys[a, iM - 1]
+                val += lam_hat_minus(J, Mp) / y ** 2 * ev(qz, z, 1) * ev(qx, x) * ev(qy, y)
+            vs = ph.v_short(d, a, x, y)
+            for b in ph.others(a):
+                c_, s_ = ph.rotation_cs(d["masses"], b, a)
+                xb, yb, zb = ph.rotated_coords(x, y, z, c_, s_)
+                inside = (xb <= prob.bx[b].R) & (yb <= prob.by[b].R)
+                w = w_angle(d["masses"], b, a, x, y, z, yb)
+                for jM, Mpp in enumerate(prob.Mps):
+                    qx, qy, qz = polys[b, jM]
+                    f = vs * x * y / (xb * yb)
+                    if J > 0:
+                        f = (f * (1 - zb * zb) ** (Mpp / 2) / (1 - z * z) ** (Mp / 2) * (-1.0) ** (Mpp - Mp)
+                             * 2 / math.sqrt(2 + 2 * (Mpp == 0)) * F_rot(J, prob.tau, Mpp, Mp, w))
+                    val += np.where(inside, f * ev(qx, xb) * ev(qy, yb) * ev(qz, zb), 0.0)
+            o = prob.offsets[a][iM]
+            out[o:o + prob.block[a]] = val
+    return out
+
+
+@pytest.mark.parametrize("mc,J,tau,deg_xy,deg_z,nxy,nz,xy_map", [
+    (W.PS_MINUS, 0, 1, 5, 5, 7, 6, "uniform"),
+    (W.H_MINUS, 0, 1, 5, 5, 10, 9, "quadratic"),
+    (W.PS_MINUS, 0, 1, 3, 3, 6, 4, "uniform"),
+    (W.PS_MINUS, 2, 1, 5, 3, 7, 4, "uniform"),
+    (W.H_MINUS, 1, -1, 3, 5, 6, 6, "uniform"),
+])
+def test_manufactured_solution(mc, J, tau, deg_xy, deg_z, nxy, nz, xy_map):
+    prob = Problem(small_desc(mc, nxy, nz, J, tau, deg_xy, deg_z, xy_map=xy_map))
+    rng = np.random.default_rng(3 + J)
+    polys, c = manufactured(prob, rng)
+    E = -0.3
+    got = prob.assemble(E) @ c
+    want = analytic(prob, polys, E)
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def reflect_z_coeffs(bz):
+    """Permutation and signs of the coefficients of f(-z): c'_(m,d) = (-1)^d c_(K-m,d)."""
+    perm = np.array([bz.index[(bz.K - m, d)] for (m, d) in bz.funcs])
+    sign = np.array([(-1.0) ** d for (m, d) in bz.funcs])
+    return perm, sign
+
+
+def permutation_maps(prob, swap):
+    """Index/sign arrays of the identical-particle permutation on coefficients
+    (P_c) and on collocation rows (P_r)."""
+    N = prob.N
+    pc_idx, pc_sgn = np.zeros(N, dtype=np.int64), np.zeros(N)
+    pr_idx, pr_sgn = np.zeros(N, dtype=np.int64), np.zeros(N)
+    sigma = {a: a for a in range(3)}
+    sigma[swap[0]], sigma[swap[1]] = swap[1], swap[0]
+    for a in range(3):
+        b = sigma[a]
+        bz = prob.bz[a]
+        nz, nx, ny = bz.n, prob.bx[a].n, prob.by[a].n
+        zperm, zsign = reflect_z_coeffs(bz)
+        pmirror = np.arange(nz)[::-1]          # z points are symmetric
+        for iM, Mp in enumerate(prob.Mps):
+            oa, ob = prob.offsets[a][iM], prob.offsets[b][iM]
+            k, i, j = np.meshgrid(np.arange(nz), np.arange(nx), np.arange(ny), indexing="ij")
+            dst = oa + (k * nx + i) * ny + j
+            pc_idx[dst.ravel()] = (ob + (zperm[k] * nx + i) * ny + j).ravel()
+            pc_sgn[dst.ravel()] = ((-1.0) ** Mp * zsign[k]).ravel()
+            pr_idx[dst.ravel()] = (ob + (pmirror[k] * nx + i) * ny + j).ravel()
+            pr_sgn[dst.ravel()] = (-1.0) ** Mp
+    return (pc_idx, pc_sgn), (pr_idx, pr_sgn)
+
+
+@pytest.mark.parametrize("mc,swap,J", [(W.PS_MINUS, (1, 2), 0), (W.H_MINUS, (0, 1), 0),
+                                       (W.PS_MINUS, (1, 2), 2)])
+def test_identical_particle_symmetry(mc, swap, J):
+    prob = Problem(small_desc(mc, 7, 6 if J == 0 else 4, J=J, deg_z=5 if J == 0 else 3))
+    A = prob.assemble(-0.27).toarray()
+    (ci, cs), (ri, rs) = permutation_maps(prob, swap)
+    rng = np.random.default_rng(11)
+    c = rng.standard_normal(prob.N)
+    lhs = A @ (cs * c[ci])
+    rhs = rs * (A @ c)[ri]
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+    # and the solution of A c = b commutes with it
+    b = rng.standard_normal(prob.N)
+    x = np.linalg.solve(A, b)
+    xp = np.linalg.solve(A, rs * b[ri])
+    assert np.abs(xp - cs * x[ci]).max() <= 1e-9 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("J", [0, 2])
+def test_block_form_matches_pointwise_assembly(J):
+    prob = Problem(small_desc(W.PS_MINUS, 7, 6 if J == 0 else 4, J=J, deg_z=5 if J == 0 else 3))
+    E = -0.31
+    A = prob.assemble(E).toarray()
+    d = prob.desc
+    for a in range(3):
+        L = prob.separable_block(a, E, couple_m=True).toarray()
+        o = prob.offsets[a][0]
+        n = prob.nM * prob.block[a]
+        z, x, y = prob.points(a)
+        extra = ph.potential_field(d, a, x, y, z) - ph.coulomb(d["masses"], d["charges"], a, x) - ph.v_hat(d, a, y)
+        Sa = (prob.rows(0.0, np.arange(o, o + n)) - prob.rows(1.0, np.arange(o, o + n))).toarray()[:, o:o + n]
+        want = L + np.tile(extra, prob.nM)[:, None] * Sa
+        assert np.abs(A[o:o + n, o:o + n] - want).max() <= 1e-11 * np.abs(want).max()
