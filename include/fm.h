@@ -1,0 +1,164 @@
+/*
+ * fm.h - C ABI of the MI355X Faddeev-Merkuriev spline-collocation solver.
+ *
+ * The library solves (H - E S) c = b, the collocation system of the 3D
+ * Faddeev-Merkuriev equations in total-orbital-momentum representation
+ * (Gradusov, Roudnev, Yarevsky, Yakovlev, arXiv:2005.05398, Sec. 3.1,
+ * eq. (FM-pre) with the right-hand side moved to the left; H c = E S c), by
+ * preconditioned flexible GMRES on one AMD gfx950 GPU.  The preconditioner is
+ * the tensor-trick inverse of the separable left-hand operator of eq. (FM-fin)
+ * (Sec. 3.2, eqs. (MDA), (prec-1), (prec-2)).
+ *
+ * Conventions for every entry point
+ *   - Every call returns fm_status; nothing throws across the ABI.  On an
+ *     error fm_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - Vectors are FP64, contiguous, in the order [request][alpha][M'][z][x][y]
+ *     (y fastest; Sec. 3.2 orders the unknowns eta, xi, zeta).  "N" is the
+ *     number of unknowns of one request, n_M * sum_alpha n_z n_x n_y
+ *     (Sec. 3.1), n_M = J - M0 + 1, M0 = (1 - tau)/2.
+ *   - Unknown vectors hold spline coefficients c (Sec. 3.1); right-hand
+ *     sides and operator outputs live in collocation-row space (one value per
+ *     collocation point, same ordering).
+ *   - Pointers named *_dev are device pointers on the problem's device; the
+ *     caller owns them.  The library owns its factors and workspaces.
+ *   - stream is a hipStream_t passed as void* (NULL: the null stream).  Work
+ *     is enqueued on it; calls return once enqueued, except fm_solve, which
+ *     synchronises the stream at restart boundaries and before returning.
+ *   - A problem handle serves one call at a time; a call that overlaps another
+ *     on the same handle returns FM_E_BUSY.
+ */
+#ifndef FM_H
+#define FM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FM_OK = 0,
+    FM_E_INVALID = -1,        /* bad argument or problem description */
+    FM_E_NOMEM = -2,          /* device or host allocation failed */
+    FM_E_HIP = -3,            /* a HIP runtime call failed */
+    FM_E_NOT_CONVERGED = -4,  /* max_iters reached; x holds the best iterate */
+    FM_E_BREAKDOWN = -5,      /* GMRES breakdown that is not a lucky one */
+    FM_E_PENCIL = -6,         /* a 1D pencil could not be diagonalised in real arithmetic */
+    FM_E_NONFINITE = -7,      /* NaN or Inf in an input vector */
+    FM_E_REJECTED = -8,       /* serving: request does not fit the memory budget */
+    FM_E_BUSY = -9            /* handle already in use */
+} fm_status;
+
+typedef enum { FM_FP64 = 0, FM_FP32 = 1, FM_BF16X3 = 2 } fm_precision;
+
+/* Spline node maps (Sec. 4): x, y use UNIFORM, QUADRATIC (t_i = R (i/K)^2) or
+ * POW (eq. (map-pow)); z uses SIN (sin(pi u / 2), u equidistant) or UNIFORM. */
+typedef enum { FM_MAP_UNIFORM = 0, FM_MAP_QUADRATIC = 1, FM_MAP_POW = 2, FM_MAP_SIN = 3 } fm_map;
+
+/* One 1D basis (Sec. 3.1, Sec. 4): Hermite splines of degree 3 (two functions
+ * per node) or 5 (three functions per node, S_5^3) with Gauss collocation.
+ *   x, y on [0, R] with zero Dirichlet conditions at both ends:
+ *        degree 3: n = 2K;  degree 5: n = 3K + 1.
+ *   z on [-1, 1] (R ignored): degree 3: n = 2K + 2, n >= 4;
+ *        degree 5: n = 3K + 3, n >= 6.
+ * K is the number of intervals. */
+typedef struct {
+    int degree;
+    int n;
+    double R;
+    int map;                  /* fm_map */
+} fm_dim;
+
+/* The problem statement (Sec. 2.1-2.2): masses and charges of the three
+ * particles, total orbital momentum J and parity tau, one basis triple per
+ * Faddeev component, the Merkuriev cut-off of eq. (Mcutoff0) (y0 may be
+ * +INFINITY) and the choice of Vhat of eq. (FM-fin) (0: Z_a (Z_b + Z_c)
+ * sqrt(2 mu_a(bc)) / (y + 1), Sec. 3.1).  The energy is not part of it: all
+ * device-resident factors are independent of E. */
+typedef struct {
+    double mass[3];
+    double charge[3];
+    int J;
+    int tau;                  /* +1 or -1 */
+    fm_dim x[3], y[3], z[3];  /* per component alpha */
+    double x0, y0, nu;
+    int vhat;
+    int device;               /* HIP device ordinal */
+} fm_problem_desc;
+
+typedef struct fm_problem fm_problem;
+
+typedef struct {
+    int restart;              /* Krylov space size m per cycle (>= 1) */
+    double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual) */
+    int max_iters;            /* total Arnoldi steps per request */
+    int prec;                 /* fm_precision of the preconditioner's products */
+    int x0_is_guess;          /* 1: x_dev holds the initial guess; 0: start from x = 0 */
+} fm_solve_opts;
+
+typedef struct {
+    int iters;                /* Arnoldi steps taken */
+    int restarts;             /* completed cycles */
+    double rel_residual;      /* final ||b - A x|| / ||b||, FP64 */
+    double min_abs_denominator; /* min |lambda_x + lambda_y - E| over the divide */
+    int status;               /* fm_status of this request */
+} fm_solve_result;
+
+/* Thread-local message of the last failing call on this thread. */
+const char *fm_last_error(void);
+
+/* Build all energy-independent data of a problem on the host in FP64 (1D
+ * bases, the z, x and y pencils of Sec. 3.2 and their generalized
+ * eigendecompositions (W-bar, W, Lambda) = D(A1, A2) of eq. (WW-scale),
+ * potential fields) and upload it to the device.  Complex-conjugate
+ * eigenvalue pairs of the x and y pencils are kept as real 2x2 blocks.
+ * Errors: FM_E_INVALID (bad description), FM_E_PENCIL (a z pencil with a
+ * complex spectrum, or a diagonalisation that fails its accuracy check),
+ * FM_E_NOMEM, FM_E_HIP.  *out is set only on FM_OK. */
+fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out);
+
+/* Free a problem and its device memory.  NULL is accepted. */
+fm_status fm_destroy_problem(fm_problem *p);
+
+/* n_unknowns: N of one request.  bytes_resident: device bytes held by the
+ * problem (factors and fields).  bytes_per_request(restart): device bytes of
+ * the Krylov workspace one request needs at that restart length.
+ * Any output pointer may be NULL. */
+fm_status fm_problem_info(const fm_problem *p, size_t *n_unknowns, size_t *bytes_resident,
+                          int restart, size_t *bytes_per_request);
+
+/* y = (H - E S) x for nbatch requests at once (Sec. 3.1): the collocation
+ * operator of eq. (FM-pre) with its coupling sum moved to the left.
+ * E: host array of nbatch energies.  x_dev, y_dev: nbatch * N doubles each;
+ * they must not overlap.  Errors: FM_E_INVALID, FM_E_HIP, FM_E_BUSY. */
+fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const double *x_dev,
+                            double *y_dev, void *stream);
+
+/* z = L(E)^-1 r for nbatch requests: the tensor-trick inverse of the
+ * separable left-hand operator of eq. (FM-fin) (Sec. 3.2), component by
+ * component (eq. (prec-1)); for n_M > 1 the M' +- 1 blocks are dropped
+ * (block-Jacobi in M').  prec selects the arithmetic of the mode-n products
+ * (the divide by lambda_x + lambda_y - E is always FP64).  r_dev and z_dev may
+ * be the same buffer.  Errors: FM_E_INVALID, FM_E_HIP, FM_E_BUSY. */
+fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const double *r_dev,
+                           double *z_dev, int prec, void *stream);
+
+/* Solve (H - E_r S) x_r = b_r for nbatch requests that share the problem
+ * (an energy scan), by right-preconditioned flexible GMRES(restart) with
+ * classical Gram-Schmidt and one reorthogonalisation, FP64 Arnoldi, Givens
+ * rotations and an FP64 true residual at every restart (Sec. 4 names
+ * preconditioned GMRES as the linear solver of the method).  Each request
+ * stops on its own when its true residual meets rtol.  results: host array
+ * of nbatch entries (may be NULL).  Returns FM_OK when every request
+ * converged, FM_E_NOT_CONVERGED if any did not (x holds the last iterate),
+ * FM_E_NONFINITE for a non-finite b. */
+fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
+                   const fm_solve_opts *opts, fm_solve_result *results, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FM_H */

@@ -1,0 +1,42 @@
+/*
+ * fm_host.h - host-only inspection of the set-up stages of libfm (no device
+ * is touched).  These run the same code that fm_create_problem uses, so the
+ * 1D bases and the pencil diagonalisation can be checked on a machine
+ * without a GPU.
+ */
+#ifndef FM_HOST_H
+#define FM_HOST_H
+
+#include "fm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The collocation points and the n x n matrices S, D1, D2 (row = point,
+ * column = basis function, row-major) of one 1D basis (Sec. 3.1: (S)_{pk} =
+ * S^k(t_p), (D)_{pk} = S^k''(t_p); Sec. 3.3: D_1 the first derivative).
+ * is_z selects the z closure.  Output arrays hold n and n*n doubles; any may
+ * be NULL.  Errors: FM_E_INVALID for an inadmissible basis. */
+fm_status fm_host_basis(const fm_dim *dim, int is_z, double *points, double *S, double *D1, double *D2);
+
+/* D(A1, A2) of Sec. 3.2, eq. (WW-scale), in real arithmetic: Wbar A1 W =
+ * Lambda, Wbar A2 W = I with Lambda quasi-diagonal (2x2 blocks [[a, b],
+ * [-b, a]] for complex pairs a +- ib).  A1, A2, Wbar, W: n*n row-major; lre,
+ * lim: n doubles (lim = b, -b on the two rows of a pair, 0 otherwise); type:
+ * n bytes (0 real, 1 first of a pair, 2 second).  err receives the relative
+ * residual of the two identities.  Errors: FM_E_PENCIL. */
+fm_status fm_host_pencil(int n, const double *A1, const double *A2, double *Wbar, double *W, double *lre,
+                         double *lim, signed char *type, double *err);
+
+/* Build every pencil factor of a problem on the host and report the largest
+ * relative residual of the diagonalisations, the number of complex pairs
+ * among the x and y pencils, and N.  Errors as fm_create_problem, without
+ * FM_E_HIP / FM_E_NOMEM. */
+fm_status fm_host_setup_check(const fm_problem_desc *desc, double *max_err, int *complex_pairs, size_t *n_unknowns);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FM_HOST_H */

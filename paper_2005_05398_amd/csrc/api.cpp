@@ -1,0 +1,497 @@
+// C ABI of the FM solver (include/fm.h): problem creation and upload,
+// operator and preconditioner application, batched flexible GMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fm_problem.h"
+
+namespace fm {
+
+namespace {
+thread_local std::string g_err;
+
+fm_status fail(fm_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(FM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+const T *put(fm_problem *p, const std::vector<T> &h, std::string &err) {
+    if (h.empty()) return nullptr;
+    void *d = nullptr;
+    size_t bytes = h.size() * sizeof(T);
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        err = "device allocation failed";
+        return nullptr;
+    }
+    p->buffers.push_back({d, bytes});
+    p->bytes_resident += bytes;
+    if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        err = "device copy failed";
+        return nullptr;
+    }
+    return static_cast<const T *>(d);
+}
+
+DimDev dim_dev(fm_problem *p, const Basis1D &b, std::string &err) {
+    DimDev d;
+    d.n = b.n;
+    d.K = b.K;
+    d.q = b.q;
+    d.drop0 = b.dirichlet ? 1 : 0;
+    d.R = b.nodes.back();
+    d.lo = b.lo;
+    d.hbar = b.hbar;
+    d.nodes = put(p, b.nodes, err);
+    d.pts = put(p, b.points, err);
+    d.idx = put(p, b.idx, err);
+    d.S = put(p, b.val[0], err);
+    d.D1 = put(p, b.val[1], err);
+    d.D2 = put(p, b.val[2], err);
+    return d;
+}
+
+struct Busy {
+    fm_problem *p;
+    bool ok;
+    explicit Busy(fm_problem *q) : p(q) {
+        int z = 0;
+        ok = p->busy.compare_exchange_strong(z, 1);
+    }
+    ~Busy() {
+        if (ok) p->busy.store(0);
+    }
+};
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Small per-call device arrays: energies, flags, minimum denominators.
+struct Small {
+    double *E, *min_den;
+    int *running, *mask;
+};
+
+fm_status ensure_small(fm_problem *p, int nb, Small &s) {
+    size_t need = round256(sizeof(double) * nb) * 2 + round256(sizeof(int) * nb) * 2;
+    if (p->ws_small_bytes < need) {
+        if (p->ws_small) (void)hipFree(p->ws_small);
+        p->ws_small = nullptr;
+        p->ws_small_bytes = 0;
+        HIP_TRY(hipMalloc(&p->ws_small, need));
+        p->ws_small_bytes = need;
+    }
+    char *c = static_cast<char *>(p->ws_small);
+    s.E = reinterpret_cast<double *>(c);
+    c += round256(sizeof(double) * nb);
+    s.min_den = reinterpret_cast<double *>(c);
+    c += round256(sizeof(double) * nb);
+    s.running = reinterpret_cast<int *>(c);
+    c += round256(sizeof(int) * nb);
+    s.mask = reinterpret_cast<int *>(c);
+    return FM_OK;
+}
+
+fm_status ensure_pinned(fm_problem *p, size_t bytes) {
+    if (p->host_pinned_bytes >= bytes) return FM_OK;
+    if (p->host_pinned) (void)hipHostFree(p->host_pinned);
+    p->host_pinned = nullptr;
+    p->host_pinned_bytes = 0;
+    void *h = nullptr;
+    HIP_TRY(hipHostMalloc(&h, bytes, hipHostMallocDefault));
+    p->host_pinned = static_cast<double *>(h);
+    p->host_pinned_bytes = bytes;
+    return FM_OK;
+}
+
+size_t krylov_bytes(long long N, int nb, int m) {
+    size_t b = 0;
+    b += round256(sizeof(double) * size_t(m + 1) * nb * N);   // V
+    b += round256(sizeof(double) * size_t(m) * nb * N);       // Z
+    b += round256(sizeof(double) * size_t(nb) * (m + 1) * m); // H
+    b += 4 * round256(sizeof(double) * size_t(nb) * (m + 1)); // g, hcol, hproj, y
+    b += 2 * round256(sizeof(double) * size_t(nb) * m);       // cs, sn
+    b += round256(sizeof(double) * size_t(nb) * (m + 1) * NBLK);
+    b += 5 * round256(sizeof(double) * nb);                   // bnorm rnorm scal E tol
+    b += 4 * round256(sizeof(int) * nb);                      // ticket active jcount flags
+    return b;
+}
+
+fm_status ensure_krylov(fm_problem *p, int nb, int m, KrylovDev &K) {
+    size_t need = krylov_bytes(p->N, nb, m);
+    if (p->ws_bytes < need) {
+        if (p->ws) (void)hipFree(p->ws);
+        p->ws = nullptr;
+        p->ws_bytes = 0;
+        if (hipMalloc(&p->ws, need) != hipSuccess) return fail(FM_E_NOMEM, "Krylov workspace allocation failed");
+        p->ws_bytes = need;
+    }
+    char *c = static_cast<char *>(p->ws);
+    auto take = [&](size_t bytes) {
+        char *r = c;
+        c += round256(bytes);
+        return r;
+    };
+    K.nb = nb;
+    K.m = m;
+    K.N = p->N;
+    K.V = (double *)take(sizeof(double) * size_t(m + 1) * nb * p->N);
+    K.Z = (double *)take(sizeof(double) * size_t(m) * nb * p->N);
+    K.H = (double *)take(sizeof(double) * size_t(nb) * (m + 1) * m);
+    K.g = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
+    K.hcol = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
+    K.hproj = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
+    K.y = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
+    K.cs = (double *)take(sizeof(double) * size_t(nb) * m);
+    K.sn = (double *)take(sizeof(double) * size_t(nb) * m);
+    K.part = (double *)take(sizeof(double) * size_t(nb) * (m + 1) * NBLK);
+    K.bnorm = (double *)take(sizeof(double) * nb);
+    K.rnorm = (double *)take(sizeof(double) * nb);
+    K.scal = (double *)take(sizeof(double) * nb);
+    K.E = (double *)take(sizeof(double) * nb);
+    K.tol = (double *)take(sizeof(double) * nb);
+    K.ticket = (unsigned *)take(sizeof(int) * nb);
+    K.active = (int *)take(sizeof(int) * nb);
+    K.jcount = (int *)take(sizeof(int) * nb);
+    K.flags = (int *)take(sizeof(int) * nb);
+    return FM_OK;
+}
+
+void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
+                   int prec, double *min_den, hipStream_t st) {
+    (void)prec;
+    launch_modez(p->pd, p->pr, nb, mask, 0, in, out, st);
+    launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st);
+    launch_modez(p->pd, p->pr, nb, mask, 1, out, out, st);
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+std::string upload(fm_problem *p, const HostFactors &hf) {
+    std::string err;
+    ProblemDev &pd = p->pd;
+    for (int a = 0; a < 3; ++a) {
+        CompDev &C = pd.comp[a];
+        C.x = dim_dev(p, p->bx[a], err);
+        C.y = dim_dev(p, p->by[a], err);
+        C.z = dim_dev(p, p->bz[a], err);
+        C.off = p->off[a];
+        C.nxy = p->bx[a].n * p->by[a].n;
+        C.npts = int(p->npts[a]);
+        C.P = put(p, hf.comp[a].P, err);
+        C.Vs = put(p, hf.comp[a].Vs, err);
+        for (int b = 0; b < 3; ++b) {
+            C.c[b] = p->crot[b][a];
+            C.s[b] = p->srot[b][a];
+        }
+        PrecCompDev &F = p->pr.comp[a];
+        std::memset(&F, 0, sizeof(F));
+        F.nx = p->bx[a].n;
+        F.ny = p->by[a].n;
+        F.nz = p->bz[a].n;
+        F.nM = p->nM;
+        const HostComp &h = hf.comp[a];
+        F.Wz = put(p, h.Wz, err);
+        F.Wx = put(p, h.Wx, err);
+        F.Wy = put(p, h.Wy, err);
+        F.lx = put(p, h.lx, err);
+        F.lxi = put(p, h.lxi, err);
+        F.ly = put(p, h.ly, err);
+        F.lyi = put(p, h.lyi, err);
+        F.tx = put(p, h.tx, err);
+        F.ty = put(p, h.ty, err);
+        if (!err.empty()) return err;
+    }
+    return err;
+}
+
+}  // namespace fm
+
+using namespace fm;
+
+extern "C" {
+
+const char *fm_last_error(void) { return g_err.c_str(); }
+
+fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out) {
+    if (!desc || !out) return fail(FM_E_INVALID, "null argument");
+    fm_problem *p = new (std::nothrow) fm_problem();
+    if (!p) return fail(FM_E_NOMEM, "host allocation failed");
+    p->desc = *desc;
+    std::string e = setup_problem(p);
+    if (!e.empty()) {
+        delete p;
+        return fail(FM_E_INVALID, e);
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev) {
+        delete p;
+        return fail(FM_E_HIP, "no such HIP device");
+    }
+    if (hipSetDevice(desc->device) != hipSuccess) {
+        delete p;
+        return fail(FM_E_HIP, "hipSetDevice failed");
+    }
+    // kernel shape limits: an x-y slice of one component must fit in LDS and the
+    // register staging of the slice products holds at most 192 rows/columns
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device) != hipSuccess) {
+            delete p;
+            return fail(FM_E_HIP, "cannot query LDS size");
+        }
+        size_t need = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (p->bx[a].n > 192 || p->by[a].n > 192) {
+                delete p;
+                return fail(FM_E_INVALID, "x and y bases are limited to 192 functions");
+            }
+            need = std::max(need, sizeof(double) * size_t(p->bx[a].n) * p->by[a].n);
+        }
+        if (need > size_t(lds)) {
+            delete p;
+            return fail(FM_E_INVALID, "an x-y slice does not fit in LDS");
+        }
+        if (need > 65536) prepare_large_lds(need);
+    }
+    HostFactors hf;
+    e = build_factors(p, hf);
+    if (!e.empty()) {
+        delete p;
+        return fail(FM_E_PENCIL, e);
+    }
+    p->pencil_err = hf.max_err;
+    e = upload(p, hf);
+    if (!e.empty()) {
+        fm_destroy_problem(p);
+        return fail(FM_E_NOMEM, e);
+    }
+    *out = p;
+    return FM_OK;
+}
+
+fm_status fm_destroy_problem(fm_problem *p) {
+    if (!p) return FM_OK;
+    (void)hipSetDevice(p->desc.device);
+    for (auto &b : p->buffers) (void)hipFree(b.ptr);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->ws_small) (void)hipFree(p->ws_small);
+    if (p->host_pinned) (void)hipHostFree(p->host_pinned);
+    delete p;
+    return FM_OK;
+}
+
+fm_status fm_problem_info(const fm_problem *p, size_t *n_unknowns, size_t *bytes_resident, int restart,
+                          size_t *bytes_per_request) {
+    if (!p) return fail(FM_E_INVALID, "null problem");
+    if (n_unknowns) *n_unknowns = size_t(p->N);
+    if (bytes_resident) *bytes_resident = p->bytes_resident;
+    if (bytes_per_request) {
+        if (restart < 1) return fail(FM_E_INVALID, "restart must be >= 1");
+        *bytes_per_request = krylov_bytes(p->N, 1, restart);
+    }
+    return FM_OK;
+}
+
+fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const double *x_dev, double *y_dev,
+                            void *stream) {
+    if (!p || !E || !x_dev || !y_dev || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    if (x_dev == y_dev) return fail(FM_E_INVALID, "x and y must not overlap");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Small s;
+    fm_status r = ensure_small(p, nbatch, s);
+    if (r != FM_OK) return r;
+    HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
+    launch_matvec(p->pd, nbatch, s.E, nullptr, x_dev, y_dev, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return FM_OK;
+}
+
+fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const double *r_dev, double *z_dev, int prec,
+                           void *stream) {
+    if (!p || !E || !r_dev || !z_dev || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    if (prec != FM_FP64 && prec != FM_FP32 && prec != FM_BF16X3) return fail(FM_E_INVALID, "bad precision");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Small s;
+    fm_status r = ensure_small(p, nbatch, s);
+    if (r != FM_OK) return r;
+    HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
+    apply_precond(p, nbatch, s.E, nullptr, r_dev, z_dev, prec, nullptr, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return FM_OK;
+}
+
+fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
+                   const fm_solve_opts *opts, fm_solve_result *results, void *stream) {
+    if (!p || !E || !b_dev || !x_dev || !opts || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    const int m = opts->restart;
+    if (m < 1 || m > 1000) return fail(FM_E_INVALID, "restart must be in [1, 1000]");
+    if (!(opts->rtol > 0)) return fail(FM_E_INVALID, "rtol must be positive");
+    if (opts->max_iters < 1) return fail(FM_E_INVALID, "max_iters must be >= 1");
+    if (opts->prec != FM_FP64 && opts->prec != FM_FP32 && opts->prec != FM_BF16X3)
+        return fail(FM_E_INVALID, "bad precision");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nb = nbatch;
+    const long long N = p->N;
+    Small s;
+    fm_status r = ensure_small(p, nb, s);
+    if (r != FM_OK) return r;
+    KrylovDev K;
+    r = ensure_krylov(p, nb, m, K);
+    if (r != FM_OK) return r;
+    r = ensure_pinned(p, sizeof(double) * 4 * nb + 64);
+    if (r != FM_OK) return r;
+    int *hflags = reinterpret_cast<int *>(p->host_pinned);
+
+    // initial state
+    HIP_TRY(hipMemcpyAsync(K.E, E, sizeof(double) * nb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(K.ticket, 0, sizeof(int) * nb, st));
+    HIP_TRY(hipMemsetAsync(K.flags, 0, sizeof(int) * nb, st));
+    HIP_TRY(hipMemsetAsync(K.active, 0, sizeof(int) * nb, st));
+    HIP_TRY(hipMemsetAsync(K.jcount, 0, sizeof(int) * nb, st));
+    {
+        std::vector<int> ones(nb, 1);
+        HIP_TRY(hipMemcpyAsync(s.running, ones.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+        std::vector<double> big(nb, 1e300);
+        HIP_TRY(hipMemcpyAsync(s.min_den, big.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    launch_bnorm(K, b_dev, st);
+    HIP_TRY(hipMemcpyAsync(hflags, K.flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < nb; ++i)
+        if (hflags[i] & 1) return fail(FM_E_NONFINITE, "non-finite value in b");
+
+    if (!opts->x0_is_guess) {
+        launch_fill(x_dev, N * nb, 0.0, st);
+        launch_fill(K.V, N * nb, 0.0, st);
+    } else {
+        launch_matvec(p->pd, nb, K.E, s.running, x_dev, K.V, st);
+    }
+    launch_residual(K, s.running, b_dev, opts->rtol, 0.5, st);
+    launch_scale0(K, st);
+    HIP_TRY(hipGetLastError());
+
+    std::vector<int> iters(nb, 0), restarts(nb, 0);
+    std::vector<int> hrun(nb, 1);
+    const int poll = 4;
+    int cycle_guard = 0;
+    for (;;) {
+        HIP_TRY(hipMemcpyAsync(hflags, s.running, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        int nrun = 0, maxit = 0;
+        for (int i = 0; i < nb; ++i) {
+            hrun[i] = hflags[i];
+            if (hrun[i]) {
+                ++nrun;
+                maxit = std::max(maxit, iters[i]);
+            }
+        }
+        if (nrun == 0) break;
+        bool budget_left = false;
+        for (int i = 0; i < nb; ++i)
+            if (hrun[i] && iters[i] < opts->max_iters) budget_left = true;
+        if (!budget_left || ++cycle_guard > 100000) break;
+        // requests over budget stop iterating
+        {
+            bool any_over = false;
+            for (int i = 0; i < nb; ++i)
+                if (hrun[i] && iters[i] >= opts->max_iters) { any_over = true; hrun[i] = 0; }
+            if (any_over) {
+                std::vector<int> h(hrun.begin(), hrun.end());
+                HIP_TRY(hipMemcpyAsync(s.running, h.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+                HIP_TRY(hipMemcpyAsync(K.active, h.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+                HIP_TRY(hipStreamSynchronize(st));
+            }
+        }
+        int steps_cap = m;
+        for (int i = 0; i < nb; ++i)
+            if (hrun[i]) steps_cap = std::min(steps_cap, std::max(1, opts->max_iters - iters[i]));
+        (void)steps_cap;
+        for (int j = 0; j < m; ++j) {
+            double *Vj = K.V + (long long)j * nb * N;
+            double *Zj = K.Z + (long long)j * nb * N;
+            double *Vn = K.V + (long long)(j + 1) * nb * N;
+            apply_precond(p, nb, K.E, K.active, Vj, Zj, opts->prec, s.min_den, st);
+            launch_matvec(p->pd, nb, K.E, K.active, Zj, Vn, st);
+            launch_mdot(K, j, Vn, 0, st);
+            launch_mupdate(K, j, Vn, st);
+            launch_mdot(K, j, Vn, 1, st);
+            launch_mupdate(K, j, Vn, st);
+            launch_norm_givens(K, j, Vn, st);
+            launch_scale_next(K, j, st);
+            if ((j + 1) % poll == 0 && j + 1 < m) {
+                HIP_TRY(hipMemcpyAsync(hflags, K.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                bool any = false;
+                for (int i = 0; i < nb; ++i) any |= hflags[i] != 0;
+                if (!any) break;
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hflags, K.jcount, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int i = 0; i < nb; ++i)
+            if (hrun[i]) {
+                iters[i] += std::max(1, hflags[i]);     // every cycle counts as progress
+                restarts[i] += 1;
+            }
+        launch_cycle_solve(K, s.running, st);
+        launch_xupdate(K, s.running, x_dev, st);
+        launch_matvec(p->pd, nb, K.E, s.running, x_dev, K.V, st);
+        launch_residual(K, s.running, b_dev, opts->rtol, 0.5, st);
+        launch_scale0(K, st);
+        HIP_TRY(hipGetLastError());
+    }
+    // results
+    std::vector<double> rn(nb), bn(nb), md(nb);
+    std::vector<int> fl(nb), run(nb);
+    HIP_TRY(hipMemcpyAsync(rn.data(), K.rnorm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bn.data(), K.bnorm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(md.data(), s.min_den, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(fl.data(), K.flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(run.data(), s.running, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    fm_status overall = FM_OK;
+    for (int i = 0; i < nb; ++i) {
+        double rel = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+        int stt = FM_OK;
+        if (fl[i] & 2) stt = FM_E_NONFINITE;
+        else if (!(rel <= opts->rtol)) stt = FM_E_NOT_CONVERGED;
+        if (stt != FM_OK && overall == FM_OK) overall = (fm_status)stt;
+        if (results) {
+            results[i].iters = iters[i];
+            results[i].restarts = restarts[i];
+            results[i].rel_residual = rel;
+            results[i].min_abs_denominator = md[i];
+            results[i].status = stt;
+        }
+    }
+    if (overall == FM_E_NOT_CONVERGED) g_err = "some requests did not reach rtol";
+    if (overall == FM_E_NONFINITE) g_err = "non-finite values during the iteration";
+    return overall;
+}
+
+}  // extern "C"

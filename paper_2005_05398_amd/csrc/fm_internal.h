@@ -1,0 +1,152 @@
+// Internal declarations of the FM solver library (host setup, device
+// descriptors, kernel launchers).  Not part of the public ABI (include/fm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fm.h"
+
+namespace fm {
+
+constexpr int MAXR = 6;      // at most 2q = 6 nonzero 1D basis functions per point
+constexpr int MAXM = 8;      // at most 8 M' blocks (J <= 7)
+
+// ---------------------------------------------------------------------------
+// Host: 1D Hermite spline basis with Gauss collocation points.
+struct Basis1D {
+    int degree = 0, q = 0, n = 0, K = 0;
+    bool dirichlet = false;      // x, y: value function dropped at both ends
+    double R = 0, lo = 0, hbar = 0;
+    std::vector<double> nodes;   // K + 1
+    std::vector<double> points;  // n collocation points, increasing
+    std::vector<int> idx;        // n * MAXR global function index per local slot (-1: none)
+    std::vector<double> val[3];  // n * MAXR values of the 0th, 1st, 2nd derivative
+
+    // Returns "" on success or a message.
+    std::string init(const fm_dim &d, bool is_z);
+    int global_index(int m, int d) const;
+    int interval(double t) const;
+    // Values of the 2q local functions (slot e*q + d) at t; gidx may be null.
+    void eval_local(double t, int deriv, int *gidx, double *v) const;
+    // Dense n x n matrix of the deriv-th derivative at the collocation points.
+    std::vector<double> dense(int deriv) const;
+};
+
+// ---------------------------------------------------------------------------
+// Host dense linear algebra (row-major n x n).
+bool lu_factor(int n, std::vector<double> &a, std::vector<int> &piv);
+void lu_solve(int n, const std::vector<double> &lu, const std::vector<int> &piv, double *b);
+bool invert(int n, const std::vector<double> &a, std::vector<double> &inv);
+
+// Real quasi-diagonalisation of the pencil (A1, A2), A2 nonsingular:
+//   Wbar A1 W = Lambda,  Wbar A2 W = I,
+// Lambda block diagonal with 1x1 real blocks and 2x2 blocks [[a, b], [-b, a]]
+// for complex pairs a +- ib.  type[i] = 0 (real), 1 (first of a pair),
+// 2 (second); lre[i] = a (or the real eigenvalue), lim[i] = b for the first of a
+// pair, -b for the second, 0 otherwise.  Eigenvalues ordered by increasing real
+// part.  Returns "" or a message; err receives the check residual.
+std::string pencil_diag(int n, const std::vector<double> &A1, const std::vector<double> &A2,
+                        std::vector<double> &Wbar, std::vector<double> &W, std::vector<double> &lre,
+                        std::vector<double> &lim, std::vector<signed char> &type, double *err);
+
+// ---------------------------------------------------------------------------
+// Device descriptors (plain data, passed by value to kernels).
+struct DimDev {
+    int n, K, q, drop0;          // drop0 = 1: the node-value function at both ends is absent
+    double R, lo, hbar;
+    const double *nodes;         // K + 1
+    const double *pts;           // n
+    const int *idx;              // n * MAXR
+    const double *S, *D1, *D2;   // n * MAXR
+};
+
+struct CompDev {
+    DimDev x, y, z;
+    long long off;               // offset of component alpha in one request vector
+    int nxy, npts;               // nx*ny, nz*nx*ny (one M' block)
+    const double *P;             // potential field V_a + sum_b V_b^(l), npts
+    const double *Vs;            // V_a^(s)(x, y), nx*ny
+    double c[3], s[3];           // (c_ba, s_ba) for beta = 0..2
+};
+
+struct ProblemDev {
+    CompDev comp[3];
+    int nM, J, tau, M0;
+    long long N;                 // unknowns per request
+    // angular coupling constants (L > 0)
+    double lhp[MAXM], lhm[MAXM]; // lambda-hat^{J, M'} and lambda-hat^{J, -M'} per M' index
+    double dcoef[MAXM * MAXM * 32];   // Wigner-sum coefficient table (see setup)
+    int dlen;
+};
+
+struct PrecCompDev {
+    int nx, ny, nz, nM;
+    const double *Wz;            // [nM][2][nz][nz]  (0: Wbar_z, 1: W_z)
+    const double *Wx;            // [nM][nz][2][nx][nx]
+    const double *Wy;            // [nM][nz][2][ny][ny]
+    const double *lx, *lxi;      // [nM][nz][nx]
+    const double *ly, *lyi;      // [nM][nz][ny]
+    const signed char *tx, *ty;  // [nM][nz][nx], [nM][nz][ny]
+    const float *Wz32, *Wx32, *Wy32;          // FP32 copies
+    const uint16_t *Wx16, *Wy16, *Wz16;       // BF16 hi/mid/lo triples (3 planes)
+};
+
+struct PrecDev {
+    PrecCompDev comp[3];
+};
+
+// Per-call GMRES device state (pointers into one allocation).
+struct KrylovDev {
+    int nb, m;
+    long long N;
+    double *V;                   // [m+1][nb][N]
+    double *Z;                   // [m][nb][N]
+    double *H;                   // [nb][m+1][m]   (rotated: upper triangle R)
+    double *g;                   // [nb][m+1]
+    double *cs, *sn;             // [nb][m]
+    double *hcol;                // [nb][m+1] Hessenberg column being built
+    double *hproj;               // [nb][m+1] current projection coefficients
+    double *y;                   // [nb][m]
+    double *part;                // [nb][m+1][NBLK] reduction partials
+    unsigned *ticket;            // [nb]
+    int *active;                 // [nb] 1 while the request iterates in this cycle
+    int *jcount;                 // [nb] Arnoldi steps in this cycle
+    double *bnorm, *rnorm;       // [nb]
+    double *scal;                // [nb] scratch scalar (norms)
+    double *E;                   // [nb]
+    double *tol;                 // [nb] absolute inner tolerance
+    int *flags;                  // [nb] breakdown / nonfinite flags
+};
+
+constexpr int NBLK = 256;        // blocks per request in the reduction kernels
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).
+void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active,
+                   const double *x, double *y, hipStream_t st);
+void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
+                  const double *in, double *out, hipStream_t st);
+void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
+               double *data, double *min_den, hipStream_t st);
+// Arnoldi / GMRES pieces (V and Z stored [i][request][N])
+void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st);
+void launch_mupdate(const KrylovDev &k, int j, double *w, hipStream_t st);
+void launch_norm_givens(const KrylovDev &k, int j, double *w, hipStream_t st);
+void launch_scale_next(const KrylovDev &k, int j, hipStream_t st);
+void launch_cycle_solve(const KrylovDev &k, const int *running, hipStream_t st);
+void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream_t st);
+void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,
+                     hipStream_t st);
+void launch_scale0(const KrylovDev &k, hipStream_t st);
+void launch_bnorm(const KrylovDev &k, const double *b, hipStream_t st);
+void launch_fill(double *p, long long n, double v, hipStream_t st);
+void prepare_large_lds(size_t bytes);
+void launch_copy(double *dst, const double *src, long long n, hipStream_t st);
+
+}  // namespace fm

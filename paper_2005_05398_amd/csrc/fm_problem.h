@@ -1,0 +1,54 @@
+// The problem handle and host-side factor storage.
+#pragma once
+
+#include "fm_internal.h"
+
+namespace fm {
+
+struct HostComp {
+    std::vector<double> Wz, Wx, Wy, lx, lxi, ly, lyi, P, Vs;
+    std::vector<signed char> tx, ty;
+};
+
+struct HostFactors {
+    HostComp comp[3];
+    double max_err = 0;
+};
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace fm
+
+struct fm_problem {
+    fm_problem_desc desc;
+    int nM = 0, M0 = 0;
+    long long N = 0;
+    long long npts[3] = {0, 0, 0};
+    long long off[3] = {0, 0, 0};
+    double mu[3], mu_abc[3], zz[3];
+    double crot[3][3], srot[3][3];
+    fm::Basis1D bx[3], by[3], bz[3];
+    fm::ProblemDev pd;
+    fm::PrecDev pr;
+    std::vector<fm::DeviceBuffer> buffers;   // factors, fields, basis tables
+    size_t bytes_resident = 0;
+    double pencil_err = 0;
+    std::atomic<int> busy{0};
+    // solver workspace (grown on demand)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *ws_small = nullptr;
+    size_t ws_small_bytes = 0;
+    double *host_pinned = nullptr;           // pinned host scratch for flag read-back
+    size_t host_pinned_bytes = 0;
+};
+
+namespace fm {
+std::string setup_problem(fm_problem *p);
+std::string build_factors(fm_problem *p, HostFactors &hf);
+std::string upload(fm_problem *p, const HostFactors &hf);
+void set_error(const std::string &msg);
+}  // namespace fm

@@ -1,0 +1,775 @@
+// HIP kernels for gfx950: collocation operator, tensor-trick preconditioner,
+// and the FP64 pieces of flexible GMRES.  All vectors FP64, layout
+// [request][alpha][M'][z][x][y] (y fastest).
+#include <hip/hip_runtime.h>
+
+#include "fm_internal.h"
+
+namespace fm {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// 1D basis helpers on the device.
+
+__device__ __forceinline__ int dev_interval(const DimDev &d, double t) {
+    int lo = 0, hi = d.K - 1;          // find the last m in [0, K-1] with nodes[m] <= t
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d.nodes[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int dev_gindex(const DimDev &d, int m, int k) {
+    if (d.drop0 && k == 0 && (m == 0 || m == d.K)) return -1;
+    int g = m * d.q + k - d.drop0;
+    if (d.drop0 && m == d.K) g -= 1;
+    return g;
+}
+
+// Values of the 2q Hermite functions nonzero at t (slot e*q + k) and their
+// global indices; each carries the factor (h/hbar)^k of its derivative order.
+__device__ __forceinline__ void dev_eval(const DimDev &d, double t, int *g, double *v) {
+    int m = dev_interval(d, t);
+    double t0 = d.nodes[m], h = d.nodes[m + 1] - t0;
+    double s = (t - t0) / h, r = h / d.hbar;
+    double s2 = s * s, s3 = s2 * s;
+    if (d.q == 2) {
+        v[0] = 1.0 - 3.0 * s2 + 2.0 * s3;
+        v[1] = r * (s - 2.0 * s2 + s3);
+        v[2] = 3.0 * s2 - 2.0 * s3;
+        v[3] = r * (s3 - s2);
+    } else {
+        double s4 = s3 * s, s5 = s4 * s, r2 = r * r;
+        v[0] = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;
+        v[1] = r * (s - 6.0 * s3 + 8.0 * s4 - 3.0 * s5);
+        v[2] = r2 * 0.5 * (s2 - 3.0 * s3 + 3.0 * s4 - s5);
+        v[3] = 10.0 * s3 - 15.0 * s4 + 6.0 * s5;
+        v[4] = r * (-4.0 * s3 + 7.0 * s4 - 3.0 * s5);
+        v[5] = r2 * 0.5 * (s3 - 2.0 * s4 + s5);
+    }
+    for (int e = 0; e < 2; ++e)
+        for (int k = 0; k < d.q; ++k) g[e * d.q + k] = dev_gindex(d, m + e, k);
+}
+
+__device__ __forceinline__ bool is_cyclic(int b, int a) {
+    return (b == 0 && a == 1) || (b == 1 && a == 2) || (b == 2 && a == 0);
+}
+
+// ---------------------------------------------------------------------------
+// Operator: y = (H - E S) x.  One thread per spatial collocation point of one
+// component; it produces all n_M outputs of that point.
+__global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__restrict__ Evec,
+                                                const int *__restrict__ active, const double *__restrict__ X,
+                                                double *__restrict__ Y) {
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int a = 0;
+    long long p = gid;
+    while (a < 3 && p >= pd.comp[a].npts) { p -= pd.comp[a].npts; ++a; }
+    if (a >= 3) return;
+    const CompDev &C = pd.comp[a];
+    const int nM = pd.nM, J = pd.J, M0 = pd.M0;
+    const int nx = C.x.n, ny = C.y.n;
+    const int iz = int(p / C.nxy), rem = int(p % C.nxy), ix = rem / ny, iy = rem % ny;
+    const double *x = X + (long long)req * pd.N;
+    const double E = Evec[req];
+    const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
+
+    // local rows of the 1D matrices
+    int gz[MAXR], gx[MAXR], gy[MAXR];
+    double Sz[MAXR], D1z[MAXR], D2z[MAXR], Sx[MAXR], D2x[MAXR], Sy[MAXR], D2y[MAXR];
+    const int rz = 2 * C.z.q, rx = 2 * C.x.q, ry = 2 * C.y.q;
+    for (int s = 0; s < rz; ++s) {
+        gz[s] = C.z.idx[iz * MAXR + s];
+        Sz[s] = C.z.S[iz * MAXR + s];
+        D1z[s] = C.z.D1[iz * MAXR + s];
+        D2z[s] = C.z.D2[iz * MAXR + s];
+    }
+    for (int s = 0; s < rx; ++s) {
+        gx[s] = C.x.idx[ix * MAXR + s];
+        Sx[s] = C.x.S[ix * MAXR + s];
+        D2x[s] = C.x.D2[ix * MAXR + s];
+    }
+    for (int s = 0; s < ry; ++s) {
+        gy[s] = C.y.idx[iy * MAXR + s];
+        Sy[s] = C.y.S[iy * MAXR + s];
+        D2y[s] = C.y.D2[iy * MAXR + s];
+    }
+
+    double u[MAXM], uz[MAXM], uzz[MAXM], uxx[MAXM], uyy[MAXM];
+    for (int iM = 0; iM < nM; ++iM) {
+        const double *c = x + C.off + (long long)iM * C.npts;
+        double s0 = 0, s1 = 0, s2 = 0, sxx = 0, syy = 0;
+        for (int a1 = 0; a1 < rz; ++a1) {
+            if (gz[a1] < 0) continue;
+            double b00 = 0, b20 = 0, b02 = 0;
+            for (int a2 = 0; a2 < rx; ++a2) {
+                if (gx[a2] < 0) continue;
+                const double *row = c + ((long long)gz[a1] * nx + gx[a2]) * ny;
+                double t0 = 0, t2 = 0;
+                for (int a3 = 0; a3 < ry; ++a3) {
+                    if (gy[a3] < 0) continue;
+                    double cv = row[gy[a3]];
+                    t0 += Sy[a3] * cv;
+                    t2 += D2y[a3] * cv;
+                }
+                b00 += Sx[a2] * t0;
+                b20 += D2x[a2] * t0;
+                b02 += Sx[a2] * t2;
+            }
+            s0 += Sz[a1] * b00;
+            s1 += D1z[a1] * b00;
+            s2 += D2z[a1] * b00;
+            sxx += Sz[a1] * b20;
+            syy += Sz[a1] * b02;
+        }
+        u[iM] = s0; uz[iM] = s1; uzz[iM] = s2; uxx[iM] = sxx; uyy[iM] = syy;
+    }
+
+    const double P = C.P[p];
+    const double iy2 = 1.0 / (yc * yc), inv2 = 1.0 / (xc * xc) + iy2, omz = 1.0 - zc * zc;
+    double out[MAXM];
+    for (int iM = 0; iM < nM; ++iM) {
+        const int Mp = M0 + iM;
+        double o = -uyy[iM] - uxx[iM] -
+                   inv2 * (omz * uzz[iM] - 2.0 * (Mp + 1) * zc * uz[iM] - double(Mp) * (Mp + 1) * u[iM]) +
+                   ((double(J) * (J + 1) - 2.0 * Mp * Mp) * iy2 + P - E) * u[iM];
+        if (iM + 1 < nM) o += pd.lhp[iM] * iy2 * (-omz * uz[iM + 1] + 2.0 * (Mp + 1) * zc * u[iM + 1]);
+        if (iM > 0) o += pd.lhm[iM] * iy2 * uz[iM - 1];
+        out[iM] = o;
+    }
+
+    // coupling to the other two components at the rotated points
+    const double vs = C.Vs[ix * ny + iy];
+    if (vs != 0.0) {
+        for (int b = 0; b < 3; ++b) {
+            if (b == a) continue;
+            const CompDev &B = pd.comp[b];
+            const double c = C.c[b], s = C.s[b];
+            double xb = sqrt(fmax(c * c * xc * xc + 2.0 * s * c * xc * yc * zc + s * s * yc * yc, 0.0));
+            double yb = sqrt(fmax(s * s * xc * xc - 2.0 * s * c * xc * yc * zc + c * c * yc * yc, 0.0));
+            if (!(xb <= B.x.R && yb <= B.y.R)) continue;
+            double den = xb * yb;
+            double zb = den > 0.0 ? (s * c * (yc * yc - xc * xc) + (c * c - s * s) * xc * yc * zc) / den : 0.0;
+            zb = fmin(1.0, fmax(-1.0, zb));
+            int hz[MAXR], hx[MAXR], hy[MAXR];
+            double vz[MAXR], vx[MAXR], vy[MAXR];
+            dev_eval(B.z, zb, hz, vz);
+            dev_eval(B.x, xb, hx, vx);
+            dev_eval(B.y, yb, hy, vy);
+            const int bnx = B.x.n, bny = B.y.n;
+            const int bz_r = 2 * B.z.q, bx_r = 2 * B.x.q, by_r = 2 * B.y.q;
+            double val[MAXM];
+            for (int iM = 0; iM < nM; ++iM) {
+                const double *cb = x + B.off + (long long)iM * B.npts;
+                double acc = 0;
+                for (int a1 = 0; a1 < bz_r; ++a1) {
+                    if (hz[a1] < 0) continue;
+                    double accx = 0;
+                    for (int a2 = 0; a2 < bx_r; ++a2) {
+                        if (hx[a2] < 0) continue;
+                        const double *row = cb + ((long long)hz[a1] * bnx + hx[a2]) * bny;
+                        double accy = 0;
+                        for (int a3 = 0; a3 < by_r; ++a3)
+                            if (hy[a3] >= 0) accy += vy[a3] * row[hy[a3]];
+                        accx += vx[a2] * accy;
+                    }
+                    acc += vz[a1] * accx;
+                }
+                val[iM] = acc;
+            }
+            const double base = vs * xc * yc / den;
+            if (J == 0) {
+                out[0] += base * val[0];
+            } else {
+                double arg = (-s * xc * zc + c * yc) / yb;
+                arg = fmin(1.0, fmax(-1.0, arg));
+                double cw = sqrt(0.5 * (1.0 + arg)), sw = sqrt(0.5 * (1.0 - arg));
+                if (!is_cyclic(b, a)) cw = -cw;
+                double sa = sqrt(fmax(omz, 0.0)), sb = sqrt(fmax(1.0 - zb * zb, 0.0));
+                double cpow[2 * MAXM + 2], spow[2 * MAXM + 2];
+                cpow[0] = spow[0] = 1.0;
+                for (int k = 1; k <= 2 * J; ++k) { cpow[k] = cpow[k - 1] * cw; spow[k] = spow[k - 1] * sw; }
+                double sbp[MAXM + 1], sap[MAXM + 1];
+                sbp[0] = sap[0] = 1.0;
+                for (int k = 1; k <= J; ++k) { sbp[k] = sbp[k - 1] * sb; sap[k] = sap[k - 1] * sa; }
+                for (int iM = 0; iM < nM; ++iM) {
+                    double acc = 0;
+                    for (int jM = 0; jM < nM; ++jM) {
+                        const double *G = pd.dcoef + (iM * nM + jM) * pd.dlen;
+                        double f = 0;
+                        for (int k = 0; k <= 2 * J; ++k) f += G[k] * cpow[k] * spow[2 * J - k];
+                        acc += f * sbp[M0 + jM] * val[jM];
+                    }
+                    out[iM] += base * acc / sap[M0 + iM];
+                }
+            }
+        }
+    }
+    double *y = Y + (long long)req * pd.N + C.off + p;
+    for (int iM = 0; iM < nM; ++iM) y[(long long)iM * C.npts] = out[iM];
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner, mode-z product: out[k'][p] = sum_k W[k'][k] in[k][p] for every
+// (request, alpha, M') and p in [0, nx*ny).  64 columns per block staged in LDS.
+constexpr int MZ_COLS = 64;
+
+__global__ void __launch_bounds__(MZ_COLS) k_modez(ProblemDev pd, PrecDev pr, const int *__restrict__ active,
+                                                   int which, const double *in, double *out) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
+    if (iM >= pd.nM) return;
+    const CompDev &C = pd.comp[a];
+    const PrecCompDev &F = pr.comp[a];
+    const int nz = C.z.n, nxy = C.nxy;
+    const int col0 = blockIdx.x * MZ_COLS;
+    if (col0 >= nxy) return;
+    extern __shared__ double sm[];
+    double *W = sm;                  // nz*nz
+    double *T = sm + nz * nz;        // nz*MZ_COLS
+    const double *Wg = F.Wz + ((size_t)iM * 2 + which) * nz * nz;
+    for (int t = threadIdx.x; t < nz * nz; t += MZ_COLS) W[t] = Wg[t];
+    const long long base = (long long)req * pd.N + C.off + (long long)iM * C.npts;
+    const int col = col0 + threadIdx.x;
+    const bool ok = col < nxy;
+    for (int k = 0; k < nz; ++k) T[k * MZ_COLS + threadIdx.x] = ok ? in[base + (long long)k * nxy + col] : 0.0;
+    __syncthreads();
+    if (!ok) return;
+    for (int k2 = 0; k2 < nz; ++k2) {
+        double acc = 0;
+        for (int k = 0; k < nz; ++k) acc += W[k2 * nz + k] * T[k * MZ_COLS + threadIdx.x];
+        out[base + (long long)k2 * nxy + col] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner, per (request, alpha, M', k) slice T (nx x ny, in LDS):
+//   T <- Wbar_x T Wbar_y^T;  solve (Lambda_x (x) I + I (x) Lambda_y - E) T' = T;
+//   T <- W_x T' W_y^T.
+// The products are done in place in LDS, a block of columns (rows) at a time,
+// with the block's outputs staged in registers.
+constexpr int XY_THREADS = 256;
+constexpr int XY_BLK = 16;
+constexpr int XY_MAXOUT = 12;        // outputs per thread per block: ceil(n*XY_BLK/256), n <= 192
+
+__device__ void left_mult(double *T, const double *__restrict__ Wm, int nx, int ny) {
+    // T <- Wm T  (Wm: nx x nx, row-major, global)
+    for (int j0 = 0; j0 < ny; j0 += XY_BLK) {
+        const int jb = min(XY_BLK, ny - j0);
+        const int nout = nx * jb;
+        double r[XY_MAXOUT];
+        int cnt = 0;
+        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
+            const int i = o / jb, j = j0 + o % jb;
+            const double *wr = Wm + (size_t)i * nx;
+            double acc = 0;
+            for (int l = 0; l < nx; ++l) acc += wr[l] * T[l * ny + j];
+            r[cnt++] = acc;
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
+            const int i = o / jb, j = j0 + o % jb;
+            T[i * ny + j] = r[cnt++];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void right_mult_t(double *T, const double *__restrict__ Wm, int nx, int ny) {
+    // T <- T Wm^T  (Wm: ny x ny, row-major, global)
+    for (int i0 = 0; i0 < nx; i0 += XY_BLK) {
+        const int ib = min(XY_BLK, nx - i0);
+        const int nout = ib * ny;
+        double r[XY_MAXOUT];
+        int cnt = 0;
+        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
+            const int i = i0 + o / ny, j = o % ny;
+            const double *wr = Wm + (size_t)j * ny;
+            double acc = 0;
+            for (int l = 0; l < ny; ++l) acc += T[i * ny + l] * wr[l];
+            r[cnt++] = acc;
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
+            const int i = i0 + o / ny, j = o % ny;
+            T[i * ny + j] = r[cnt++];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void solve4(double M[4][4], double *b) {
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
+        if (p != k) {
+            for (int j = 0; j < 4; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
+            double t = b[k]; b[k] = b[p]; b[p] = t;
+        }
+        for (int i = k + 1; i < 4; ++i) {
+            double l = M[i][k] / M[k][k];
+            for (int j = k; j < 4; ++j) M[i][j] -= l * M[k][j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = 3; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < 4; ++j) s -= M[i][j] * b[j];
+        b[i] = s / M[i][i];
+    }
+}
+
+// (Lambda_x (x) I + I (x) Lambda_y - E) T' = T on the quasi-diagonal blocks.
+__device__ void block_divide(double *T, int nx, int ny, const double *lx, const double *lxi, const signed char *tx,
+                             const double *ly, const double *lyi, const signed char *ty, double E,
+                             double *min_den) {
+    double mind = 1e300;
+    for (int o = threadIdx.x; o < nx * ny; o += XY_THREADS) {
+        const int i = o / ny, j = o % ny;
+        const int ti = tx[i], tj = ty[j];
+        if (ti == 2 || tj == 2) continue;        // handled by the anchor of its block
+        const double d = lx[i] + ly[j] - E;
+        if (ti == 0 && tj == 0) {
+            T[o] /= d;
+            mind = fmin(mind, fabs(d));
+        } else if (ti == 1 && tj == 0) {
+            const double b = lxi[i], r0 = T[o], r1 = T[o + ny], det = d * d + b * b;
+            T[o] = (d * r0 - b * r1) / det;
+            T[o + ny] = (b * r0 + d * r1) / det;
+            mind = fmin(mind, sqrt(det));
+        } else if (ti == 0 && tj == 1) {
+            const double b = lyi[j], r0 = T[o], r1 = T[o + 1], det = d * d + b * b;
+            T[o] = (d * r0 - b * r1) / det;
+            T[o + 1] = (b * r0 + d * r1) / det;
+            mind = fmin(mind, sqrt(det));
+        } else {
+            const double bx = lxi[i], by = lyi[j];
+            double M[4][4] = {{d, by, bx, 0.0}, {-by, d, 0.0, bx}, {-bx, 0.0, d, by}, {0.0, -bx, -by, d}};
+            double r[4] = {T[o], T[o + 1], T[o + ny], T[o + ny + 1]};
+            solve4(M, r);
+            T[o] = r[0]; T[o + 1] = r[1]; T[o + ny] = r[2]; T[o + ny + 1] = r[3];
+            mind = fmin(mind, sqrt(d * d + (fabs(bx) - fabs(by)) * (fabs(bx) - fabs(by))));
+        }
+    }
+    if (min_den) {
+        // block minimum, then one atomic per block on the bit pattern (positive doubles)
+        __shared__ double red[XY_THREADS];
+        red[threadIdx.x] = mind;
+        __syncthreads();
+        for (int s = XY_THREADS / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            atomicMin((unsigned long long *)min_den, (unsigned long long)__double_as_longlong(red[0]));
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(XY_THREADS) k_xy(ProblemDev pd, PrecDev pr, const double *__restrict__ Evec,
+                                                   const int *__restrict__ active, double *data,
+                                                   double *min_den) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
+    if (iM >= pd.nM) return;
+    const CompDev &C = pd.comp[a];
+    const PrecCompDev &F = pr.comp[a];
+    const int k = blockIdx.x;
+    const int nz = C.z.n, nx = C.x.n, ny = C.y.n;
+    if (k >= nz) return;
+    extern __shared__ double T[];
+    double *g = data + (long long)req * pd.N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) T[t] = g[t];
+    __syncthreads();
+    const size_t fx = (size_t)iM * nz + k;
+    const double *Wbx = F.Wx + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
+    const double *Wby = F.Wy + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
+    left_mult(T, Wbx, nx, ny);
+    right_mult_t(T, Wby, nx, ny);
+    block_divide(T, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
+                 F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
+    left_mult(T, Wx, nx, ny);
+    right_mult_t(T, Wy, nx, ny);
+    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) g[t] = T[t];
+}
+
+// ---------------------------------------------------------------------------
+// GMRES pieces.  V is stored [i][request][N]; Z likewise.
+constexpr int RT = 256;              // threads of the reduction kernels
+constexpr int MD_G = 8;              // vectors per group in the multi-dot
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Returns true in the one block that arrives last for this request.
+__device__ __forceinline__ bool last_block(unsigned *ticket, unsigned total) {
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(ticket, 1u);
+        last = (t == total - 1);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+__device__ __forceinline__ void chunk_range(long long N, int blk, long long &lo, long long &hi) {
+    long long per = (N + NBLK - 1) / NBLK;
+    lo = blk * per;
+    hi = min(N, lo + per);
+}
+
+// hproj[i] = v_i . w for i <= j; hcol = hproj (accumulate = 0) or hcol += hproj.
+__global__ void __launch_bounds__(RT) k_mdot(KrylovDev K, int j, const double *__restrict__ W, int accumulate) {
+    const int req = blockIdx.z;
+    if (!K.active[req]) return;
+    __shared__ double red[RT];
+    const int g0 = blockIdx.y * MD_G;
+    const int ng = min(MD_G, j + 1 - g0);
+    long long lo, hi;
+    chunk_range(K.N, blockIdx.x, lo, hi);
+    const double *w = W + (long long)req * K.N;
+    double acc[MD_G];
+    for (int t = 0; t < MD_G; ++t) acc[t] = 0;
+    for (long long e = lo + threadIdx.x; e < hi; e += RT) {
+        double we = w[e];
+        for (int t = 0; t < ng; ++t) acc[t] += K.V[((long long)(g0 + t) * K.nb + req) * K.N + e] * we;
+    }
+    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
+    for (int t = 0; t < ng; ++t) {
+        double s = block_sum(acc[t], red);
+        if (threadIdx.x == 0) part[(size_t)(g0 + t) * NBLK + blockIdx.x] = s;
+    }
+    if (last_block(&K.ticket[req], NBLK * gridDim.y)) {
+        for (int i = threadIdx.x; i <= j; i += RT) {
+            double s = 0;
+            for (int b = 0; b < NBLK; ++b) s += part[(size_t)i * NBLK + b];
+            K.hproj[(size_t)req * (K.m + 1) + i] = s;
+            double *hc = K.hcol + (size_t)req * (K.m + 1) + i;
+            *hc = accumulate ? *hc + s : s;
+        }
+        if (threadIdx.x == 0) K.ticket[req] = 0;
+    }
+}
+
+// w -= sum_{i <= j} v_i hproj[i]
+__global__ void __launch_bounds__(RT) k_mupdate(KrylovDev K, int j, double *W) {
+    const int req = blockIdx.y;
+    if (!K.active[req]) return;
+    __shared__ double h[1024];
+    const double *hp = K.hproj + (size_t)req * (K.m + 1);
+    for (int i = threadIdx.x; i <= j; i += RT) h[i] = hp[i];
+    __syncthreads();
+    long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    if (e >= K.N) return;
+    double acc = W[(long long)req * K.N + e];
+    for (int i = 0; i <= j; ++i) acc -= K.V[((long long)i * K.nb + req) * K.N + e] * h[i];
+    W[(long long)req * K.N + e] = acc;
+}
+
+// ||w||, then the Hessenberg column j, Givens rotations, residual estimate.
+__global__ void __launch_bounds__(RT) k_norm_givens(KrylovDev K, int j, const double *__restrict__ W) {
+    const int req = blockIdx.y;
+    if (!K.active[req]) return;
+    __shared__ double red[RT];
+    long long lo, hi;
+    chunk_range(K.N, blockIdx.x, lo, hi);
+    const double *w = W + (long long)req * K.N;
+    double acc = 0;
+    for (long long e = lo + threadIdx.x; e < hi; e += RT) acc += w[e] * w[e];
+    double s = block_sum(acc, red);
+    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (last_block(&K.ticket[req], NBLK)) {
+        if (threadIdx.x == 0) {
+            double nn = 0;
+            for (int b = 0; b < NBLK; ++b) nn += part[b];
+            double hn = sqrt(nn);
+            const int m = K.m;
+            double *hc = K.hcol + (size_t)req * (m + 1);
+            double *H = K.H + (size_t)req * (m + 1) * m;
+            double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m, *g = K.g + (size_t)req * (m + 1);
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+                hc[i] = t;
+            }
+            double r = hypot(hc[j], hn);
+            double c = r > 0 ? hc[j] / r : 1.0, sv = r > 0 ? hn / r : 0.0;
+            cs[j] = c;
+            sn[j] = sv;
+            hc[j] = r;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
+            g[j + 1] = -sv * g[j];
+            g[j] = c * g[j];
+            K.scal[req] = hn;
+            K.jcount[req] = j + 1;
+            const double est = fabs(g[j + 1]);
+            if (!(hn == hn) || !(est == est)) K.flags[req] |= 2;     // non-finite
+            if (est <= K.tol[req] || hn <= 1e-300 || j + 1 >= m || !(est == est)) K.active[req] = 0;
+            K.ticket[req] = 0;
+        }
+    }
+}
+
+// v_{j+1} = w / h_{j+1,j} in place (V slot j + 1).
+__global__ void __launch_bounds__(RT) k_scale(KrylovDev K, int j) {
+    const int req = blockIdx.y;
+    if (!K.active[req]) return;
+    long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    if (e >= K.N) return;
+    double hn = K.scal[req];
+    double *v = K.V + ((long long)(j + 1) * K.nb + req) * K.N;
+    v[e] = v[e] / hn;
+}
+
+// y = R^-1 g for the steps of this cycle (one thread per request).
+__global__ void k_cycle_solve(KrylovDev K, const int *__restrict__ running) {
+    const int req = blockIdx.x * blockDim.x + threadIdx.x;
+    if (req >= K.nb || !running[req]) return;
+    const int m = K.m, jc = K.jcount[req];
+    const double *H = K.H + (size_t)req * (m + 1) * m;
+    const double *g = K.g + (size_t)req * (m + 1);
+    double *y = K.y + (size_t)req * m;
+    for (int i = jc - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < jc; ++k) s -= H[(size_t)i * m + k] * y[k];
+        y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
+    }
+}
+
+// x += sum_i z_i y_i
+__global__ void __launch_bounds__(RT) k_xupdate(KrylovDev K, const int *__restrict__ running, double *X) {
+    const int req = blockIdx.y;
+    if (!running[req]) return;
+    const int jc = K.jcount[req];
+    __shared__ double y[1024];
+    for (int i = threadIdx.x; i < jc; i += RT) y[i] = K.y[(size_t)req * K.m + i];
+    __syncthreads();
+    long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    if (e >= K.N) return;
+    double acc = X[(long long)req * K.N + e];
+    for (int i = 0; i < jc; ++i) acc += K.Z[((long long)i * K.nb + req) * K.N + e] * y[i];
+    X[(long long)req * K.N + e] = acc;
+}
+
+// r = b - Ax into V slot 0, ||r||; then restart state or completion.
+__global__ void __launch_bounds__(RT) k_residual(KrylovDev K, int *running, const double *__restrict__ B,
+                                                 double rtol, double inner_safety) {
+    const int req = blockIdx.y;
+    if (!running[req]) return;
+    __shared__ double red[RT];
+    long long lo, hi;
+    chunk_range(K.N, blockIdx.x, lo, hi);
+    double *r = K.V + (long long)req * K.N;        // slot 0 holds A x on entry
+    const double *b = B + (long long)req * K.N;
+    double acc = 0;
+    for (long long e = lo + threadIdx.x; e < hi; e += RT) {
+        double v = b[e] - r[e];
+        r[e] = v;
+        acc += v * v;
+    }
+    double s = block_sum(acc, red);
+    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (last_block(&K.ticket[req], NBLK)) {
+        if (threadIdx.x == 0) {
+            double nn = 0;
+            for (int bb = 0; bb < NBLK; ++bb) nn += part[bb];
+            double rn = sqrt(nn);
+            K.rnorm[req] = rn;
+            K.scal[req] = rn;
+            K.jcount[req] = 0;
+            double *g = K.g + (size_t)req * (K.m + 1);
+            for (int i = 0; i <= K.m; ++i) g[i] = 0.0;
+            g[0] = rn;
+            if (!(rn == rn)) {
+                K.flags[req] |= 2;
+                running[req] = 0;
+                K.active[req] = 0;
+            } else if (rn <= rtol * K.bnorm[req] || rn == 0.0) {
+                running[req] = 0;
+                K.active[req] = 0;
+            } else {
+                K.active[req] = 1;
+                K.tol[req] = inner_safety * rtol * K.bnorm[req];
+            }
+            K.ticket[req] = 0;
+        }
+    }
+}
+
+// v_0 = r / ||r|| for the requests that go on.
+__global__ void __launch_bounds__(RT) k_scale0(KrylovDev K) {
+    const int req = blockIdx.y;
+    if (!K.active[req]) return;
+    long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    if (e >= K.N) return;
+    double *v = K.V + (long long)req * K.N;
+    v[e] = v[e] / K.scal[req];
+}
+
+__global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restrict__ B) {
+    const int req = blockIdx.y;
+    __shared__ double red[RT];
+    long long lo, hi;
+    chunk_range(K.N, blockIdx.x, lo, hi);
+    const double *b = B + (long long)req * K.N;
+    double acc = 0;
+    int bad = 0;
+    for (long long e = lo + threadIdx.x; e < hi; e += RT) {
+        double v = b[e];
+        if (!(v - v == 0.0)) bad = 1;
+        acc += v * v;
+    }
+    double s = block_sum(acc, red);
+    __shared__ int anybad;
+    if (threadIdx.x == 0) anybad = 0;
+    __syncthreads();
+    if (bad) atomicOr(&anybad, 1);
+    __syncthreads();
+    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s;
+        if (anybad) atomicOr(&K.flags[req], 1);
+    }
+    if (last_block(&K.ticket[req], NBLK)) {
+        if (threadIdx.x == 0) {
+            double nn = 0;
+            for (int bb = 0; bb < NBLK; ++bb) nn += part[bb];
+            K.bnorm[req] = sqrt(nn);
+            K.ticket[req] = 0;
+        }
+    }
+}
+
+__global__ void k_fill(double *p, long long n, double v) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+__global__ void k_copy(double *d, const double *__restrict__ s, long long n) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) d[e] = s[e];
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
+                   hipStream_t st) {
+    long long pts = pd.comp[0].npts + pd.comp[1].npts + pd.comp[2].npts;
+    dim3 grid(cdiv(pts, 256), nb);
+    hipLaunchKernelGGL(k_matvec, grid, dim3(256), 0, st, pd, E_dev, active, x, y);
+}
+
+void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
+                  double *out, hipStream_t st) {
+    int maxnxy = 0, maxnz = 0;
+    for (int a = 0; a < 3; ++a) {
+        maxnxy = std::max(maxnxy, pd.comp[a].nxy);
+        maxnz = std::max(maxnz, pd.comp[a].z.n);
+    }
+    dim3 grid(cdiv(maxnxy, MZ_COLS), 3 * MAXM, nb);
+    size_t sh = sizeof(double) * (maxnz * maxnz + maxnz * MZ_COLS);
+    hipLaunchKernelGGL(k_modez, grid, dim3(MZ_COLS), sh, st, pd, pr, active, which, in, out);
+}
+
+void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
+               double *min_den, hipStream_t st) {
+    int maxnz = 0, maxn = 0;
+    for (int a = 0; a < 3; ++a) {
+        maxnz = std::max(maxnz, pd.comp[a].z.n);
+        maxn = std::max(maxn, pd.comp[a].nxy);
+    }
+    dim3 grid(maxnz, 3 * MAXM, nb);
+    size_t sh = sizeof(double) * maxn;
+    hipLaunchKernelGGL(k_xy, grid, dim3(XY_THREADS), sh, st, pd, pr, E_dev, active, data, min_den);
+}
+
+void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st) {
+    dim3 grid(NBLK, cdiv(j + 1, MD_G), k.nb);
+    hipLaunchKernelGGL(k_mdot, grid, dim3(RT), 0, st, k, j, w, accumulate);
+}
+
+void launch_mupdate(const KrylovDev &k, int j, double *w, hipStream_t st) {
+    dim3 grid(cdiv(k.N, RT), k.nb);
+    hipLaunchKernelGGL(k_mupdate, grid, dim3(RT), 0, st, k, j, w);
+}
+
+void launch_norm_givens(const KrylovDev &k, int j, double *w, hipStream_t st) {
+    dim3 grid(NBLK, k.nb);
+    hipLaunchKernelGGL(k_norm_givens, grid, dim3(RT), 0, st, k, j, w);
+}
+
+void launch_scale_next(const KrylovDev &k, int j, hipStream_t st) {
+    dim3 grid(cdiv(k.N, RT), k.nb);
+    hipLaunchKernelGGL(k_scale, grid, dim3(RT), 0, st, k, j);
+}
+
+void launch_cycle_solve(const KrylovDev &k, const int *running, hipStream_t st) {
+    hipLaunchKernelGGL(k_cycle_solve, dim3(cdiv(k.nb, 64)), dim3(64), 0, st, k, running);
+}
+
+void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream_t st) {
+    dim3 grid(cdiv(k.N, RT), k.nb);
+    hipLaunchKernelGGL(k_xupdate, grid, dim3(RT), 0, st, k, running, x);
+}
+
+void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,
+                     hipStream_t st) {
+    dim3 grid(NBLK, k.nb);
+    hipLaunchKernelGGL(k_residual, grid, dim3(RT), 0, st, k, running, b, rtol, inner_safety);
+}
+
+void launch_scale0(const KrylovDev &k, hipStream_t st) {
+    dim3 grid(cdiv(k.N, RT), k.nb);
+    hipLaunchKernelGGL(k_scale0, grid, dim3(RT), 0, st, k);
+}
+
+void launch_bnorm(const KrylovDev &k, const double *b, hipStream_t st) {
+    dim3 grid(NBLK, k.nb);
+    hipLaunchKernelGGL(k_bnorm, grid, dim3(RT), 0, st, k, b);
+}
+
+void prepare_large_lds(size_t bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_xy), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(bytes));
+}
+
+void launch_fill(double *p, long long n, double v, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_copy(double *dst, const double *src, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
+}
+
+}  // namespace fm

@@ -1,0 +1,237 @@
+"""Python binding of libfm.so (include/fm.h): argument marshalling only.
+
+Device buffers are torch tensors (float64, on the problem's device); streams
+are torch streams.  Every computation runs in the HIP library; there is no
+fallback path: if libfm.so is missing or fails to load, every call raises.
+"""
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfm.so")
+
+FM_OK, FM_E_INVALID, FM_E_NOMEM, FM_E_HIP, FM_E_NOT_CONVERGED = 0, -1, -2, -3, -4
+FM_E_BREAKDOWN, FM_E_PENCIL, FM_E_NONFINITE, FM_E_REJECTED, FM_E_BUSY = -5, -6, -7, -8, -9
+STATUS_NAMES = {0: "FM_OK", -1: "FM_E_INVALID", -2: "FM_E_NOMEM", -3: "FM_E_HIP", -4: "FM_E_NOT_CONVERGED",
+                -5: "FM_E_BREAKDOWN", -6: "FM_E_PENCIL", -7: "FM_E_NONFINITE", -8: "FM_E_REJECTED",
+                -9: "FM_E_BUSY"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+MAPS = {"uniform": 0, "quadratic": 1, "pow": 2, "sin": 3}
+
+
+class FmDim(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("n", ctypes.c_int), ("R", ctypes.c_double), ("map", ctypes.c_int)]
+
+
+class FmDesc(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double * 3), ("charge", ctypes.c_double * 3), ("J", ctypes.c_int),
+                ("tau", ctypes.c_int), ("x", FmDim * 3), ("y", FmDim * 3), ("z", FmDim * 3),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("nu", ctypes.c_double),
+                ("vhat", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class FmSolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int),
+                ("prec", ctypes.c_int), ("x0_is_guess", ctypes.c_int)]
+
+
+class FmSolveResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("min_abs_denominator", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "restarts": self.restarts, "rel_residual": self.rel_residual,
+                "min_abs_denominator": self.min_abs_denominator, "status": STATUS_NAMES.get(self.status)}
+
+
+class FmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libfm.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2005_05398_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, cd, ci = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+        pd = ctypes.POINTER(ctypes.c_double)
+        L.fm_last_error.restype = ctypes.c_char_p
+        L.fm_create_problem.argtypes = [ctypes.POINTER(FmDesc), ctypes.POINTER(vp)]
+        L.fm_destroy_problem.argtypes = [vp]
+        L.fm_problem_info.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t), ci,
+                                      ctypes.POINTER(ctypes.c_size_t)]
+        L.fm_apply_operator.argtypes = [vp, ci, pd, vp, vp, vp]
+        L.fm_apply_precond.argtypes = [vp, ci, pd, vp, vp, ci, vp]
+        L.fm_solve.argtypes = [vp, ci, pd, vp, vp, ctypes.POINTER(FmSolveOpts), ctypes.POINTER(FmSolveResult), vp]
+        for f in ("fm_create_problem", "fm_destroy_problem", "fm_problem_info", "fm_apply_operator",
+                  "fm_apply_precond", "fm_solve"):
+            getattr(L, f).restype = ci
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FM_OK:
+        raise FmError(status, lib().fm_last_error().decode())
+
+
+def make_c_desc(desc, device=0):
+    d = FmDesc()
+    for i in range(3):
+        d.mass[i] = desc["masses"][i]
+        d.charge[i] = desc["charges"][i]
+    d.J, d.tau = desc["J"], desc["tau"]
+    for key in ("x", "y", "z"):
+        arr = getattr(d, key)
+        for a in range(3):
+            dd = desc[key][a]
+            arr[a].degree, arr[a].n = dd["degree"], dd["n"]
+            arr[a].R = dd.get("R", 2.0)
+            arr[a].map = MAPS[dd.get("map", "uniform")]
+    d.x0, d.nu, d.vhat = desc["x0"], desc["nu"], desc.get("vhat", 0)
+    d.y0 = desc["y0"] if math.isfinite(desc["y0"]) else float("inf")
+    d.device = device
+    return d
+
+
+def _energies(E):
+    E = [float(e) for e in (E if hasattr(E, "__len__") else [E])]
+    return (ctypes.c_double * len(E))(*E), len(E)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, n, name):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A problem handle: energy-independent factors resident on the device."""
+
+    def __init__(self, desc, device=0):
+        self._h = ctypes.c_void_p()
+        self.desc = desc
+        self.device = device
+        _check(lib().fm_create_problem(ctypes.byref(make_c_desc(desc, device)), ctypes.byref(self._h)))
+        n = ctypes.c_size_t()
+        r = ctypes.c_size_t()
+        _check(lib().fm_problem_info(self._h, ctypes.byref(n), ctypes.byref(r), 1, None))
+        self.N = n.value
+        self.bytes_resident = r.value
+
+    def bytes_per_request(self, restart):
+        b = ctypes.c_size_t()
+        _check(lib().fm_problem_info(self._h, None, None, int(restart), ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if self._h:
+            lib().fm_destroy_problem(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_operator(self, E, x, y, stream=None):
+        Ec, nb = _energies(E)
+        _check(lib().fm_apply_operator(self._h, nb, Ec, _ptr(x, nb * self.N, "x"), _ptr(y, nb * self.N, "y"),
+                                       _stream(stream)))
+        return y
+
+    def apply_precond(self, E, r, z, prec="fp64", stream=None):
+        Ec, nb = _energies(E)
+        _check(lib().fm_apply_precond(self._h, nb, Ec, _ptr(r, nb * self.N, "r"), _ptr(z, nb * self.N, "z"),
+                                      PRECISIONS[prec], _stream(stream)))
+        return z
+
+    def solve(self, E, b, x, restart=30, rtol=1e-10, max_iters=2000, prec="fp64", x0_is_guess=False,
+              stream=None, raise_on_error=True):
+        """Returns (status, [per-request result dicts])."""
+        Ec, nb = _energies(E)
+        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], int(bool(x0_is_guess)))
+        res = (FmSolveResult * nb)()
+        st = lib().fm_solve(self._h, nb, Ec, _ptr(b, nb * self.N, "b"), _ptr(x, nb * self.N, "x"),
+                            ctypes.byref(opts), res, _stream(stream))
+        out = [r.as_dict() for r in res]
+        if st != FM_OK and raise_on_error and st != FM_E_NOT_CONVERGED:
+            raise FmError(st, lib().fm_last_error().decode())
+        return st, out
+
+
+# -- host-only inspection (include/fm_host.h) --------------------------------
+
+def _host_sigs(L):
+    if getattr(L, "_host_sigs", False):
+        return
+    pd, ci = ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    L.fm_host_basis.argtypes = [ctypes.POINTER(FmDim), ci, pd, pd, pd, pd]
+    L.fm_host_pencil.argtypes = [ci, pd, pd, pd, pd, pd, pd, ctypes.POINTER(ctypes.c_byte), pd]
+    L.fm_host_setup_check.argtypes = [ctypes.POINTER(FmDesc), pd, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check"):
+        getattr(L, f).restype = ci
+    L._host_sigs = True
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def host_basis(dim, is_z):
+    """(points, S, D1, D2) of one 1D basis as built by the library."""
+    import numpy as np
+    L = lib()
+    _host_sigs(L)
+    d = FmDim(dim["degree"], dim["n"], dim.get("R", 2.0), MAPS[dim.get("map", "uniform")])
+    n = dim["n"]
+    pts, S, D1, D2 = np.zeros(n), np.zeros((n, n)), np.zeros((n, n)), np.zeros((n, n))
+    _check(L.fm_host_basis(ctypes.byref(d), int(is_z), _dptr(pts), _dptr(S), _dptr(D1), _dptr(D2)))
+    return pts, S, D1, D2
+
+
+def host_pencil(A1, A2):
+    """(Wbar, W, lre, lim, type, err) of D(A1, A2) as computed by the library."""
+    import numpy as np
+    L = lib()
+    _host_sigs(L)
+    n = A1.shape[0]
+    A1 = np.ascontiguousarray(A1, dtype=np.float64)
+    A2 = np.ascontiguousarray(A2, dtype=np.float64)
+    Wb, W = np.zeros((n, n)), np.zeros((n, n))
+    lre, lim, err = np.zeros(n), np.zeros(n), np.zeros(1)
+    ty = np.zeros(n, dtype=np.int8)
+    _check(L.fm_host_pencil(n, _dptr(A1), _dptr(A2), _dptr(Wb), _dptr(W), _dptr(lre), _dptr(lim),
+                            ty.ctypes.data_as(ctypes.POINTER(ctypes.c_byte)), _dptr(err)))
+    return Wb, W, lre, lim, ty, float(err[0])
+
+
+def host_setup_check(desc):
+    """(max_err, complex_pairs, N) of the host factor build."""
+    L = lib()
+    _host_sigs(L)
+    err = ctypes.c_double()
+    pairs = ctypes.c_int()
+    n = ctypes.c_size_t()
+    _check(L.fm_host_setup_check(ctypes.byref(make_c_desc(desc)), ctypes.byref(err), ctypes.byref(pairs),
+                                 ctypes.byref(n)))
+    return err.value, pairs.value, n.value

@@ -1,0 +1,202 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Operator: y = (H - E S) x from fm_apply_operator against the oracle's
+assembled matrix (all rows on small grids, sampled rows at full size).
+Preconditioner: fm_apply_precond against the exact inverse of the separable
+block of eq. (FM-fin) (sparse LU of the oracle's Kronecker-form L_alpha), and
+with all potentials switched off against the dense Kronecker-sum inverse.
+Solver: fm_solve against the oracle's LU solution (relative residual 1e-10 and
+relative solution error 1e-8), the trivial case P^-1 A = I, and the
+identical-particle symmetry of the solution.
+Tolerances: operator and preconditioner outputs are compared elementwise
+relative to the largest output, at 1e-11 (operator; FP64 with sums of at most
+a few hundred terms) and 1e-9 (preconditioner: products with eigenvector
+matrices of condition up to ~1e3).
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem as OracleProblem
+from oracle.solve import lu_solve, precond_reference, rel_residual
+from paper_2005_05398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fm():
+    from paper_2005_05398_amd import fm
+    return fm
+
+
+def to_dev(a, device):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+
+
+def small(mc, nxy, nz, J=0, tau=1, dxy=5, dz=5, R=15.0, xy_map="uniform", x0=5.0):
+    return W.make_desc(*mc, nxy, nz, J=J, tau=tau, deg_xy=dxy, deg_z=dz, R=R, xy_map=xy_map, x0=x0)
+
+
+OP_CASES = [
+    ("cfg1", W.cfg1()["desc"]),
+    ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
+    ("hminus_10x13x9_quadratic", dict(small(W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"),
+                                      y=W.make_desc(*W.H_MINUS, 13, 9, R=25.0)["y"])),
+    ("L1_tau-1", small(W.H_MINUS, 7, 6, J=1, tau=-1, dz=5)),
+    ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
+    ("cubic_ragged_10x6", small(W.PS_MINUS, 10, 6, dxy=3, dz=3)),
+]
+
+
+@pytest.mark.parametrize("name,desc", OP_CASES, ids=[c[0] for c in OP_CASES])
+def test_operator_parity(device, name, desc):
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    assert P.N == O.N
+    rng = np.random.default_rng(7)
+    Es = [-0.25, -0.61]
+    X = rng.standard_normal((2, O.N))
+    Y = to_dev(np.zeros((2, O.N)), device)
+    P.apply_operator(Es, to_dev(X, device), Y)
+    Yg = Y.cpu().numpy()
+    for r, E in enumerate(Es):
+        ref = O.assemble(E) @ X[r]
+        err = np.abs(Yg[r] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-11, (name, r, err)
+
+
+@pytest.mark.parametrize("cfg", ["cfg2", "cfg3", "cfg4"])
+def test_operator_parity_full_size_sampled(device, cfg):
+    fm = _fm()
+    c = W.CONFIGS[cfg]()
+    desc, E = c["desc"], c["E"][0]
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    x = W.rhs(c["seeds"][0] + 17, O.N)
+    y = to_dev(np.zeros(O.N), device)
+    P.apply_operator([E], to_dev(x, device), y)
+    yg = y.cpu().numpy()
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.integers(0, O.N, 1500), [0, O.N - 1],
+                                     [O.offsets[a][0] for a in range(3)]]))
+    ref = O.rows(E, rows) @ x
+    err = np.abs(yg[rows] - ref).max() / np.abs(ref).max()
+    assert err <= 1e-11, err
+
+
+PREC_CASES = [
+    ("cfg1", W.cfg1()["desc"]),
+    ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
+    ("hminus_quadratic_22x22x9", small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
+    ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
+]
+
+
+@pytest.mark.parametrize("name,desc", PREC_CASES, ids=[c[0] for c in PREC_CASES])
+def test_precond_parity(device, name, desc):
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    rng = np.random.default_rng(5)
+    Es = [-0.25, -0.45]
+    R = rng.standard_normal((2, O.N))
+    Z = to_dev(np.zeros((2, O.N)), device)
+    P.apply_precond(Es, to_dev(R, device), Z)
+    Zg = Z.cpu().numpy()
+    for r, E in enumerate(Es):
+        ref = precond_reference(O, E, R[r])
+        err = np.abs(Zg[r] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-9, (name, r, err)
+
+
+def test_precond_equals_kronecker_inverse_without_potentials(device):
+    """All charges zero: the separable block is the whole operator and the
+    tensor trick must equal the dense inverse of the Kronecker sum."""
+    fm = _fm()
+    desc = small(((1.0, 1.0, 1.0), (0.0, 0.0, 0.0)), 10, 6, dxy=3, dz=3, R=10.0)
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    E = -0.3
+    Ainv = np.linalg.inv(O.assemble(E).toarray())
+    r = W.rhs(99, O.N)
+    z = to_dev(np.zeros(O.N), device)
+    P.apply_precond([E], to_dev(r, device), z)
+    ref = Ainv @ r
+    assert np.abs(z.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max() * 10
+
+
+def test_solve_trivial_converges_in_one_step(device):
+    fm = _fm()
+    desc = small(((1.0, 1.0, 1.0), (0.0, 0.0, 0.0)), 10, 6, dxy=3, dz=3, R=10.0)
+    P = fm.Problem(desc)
+    b = to_dev(W.rhs(5, P.N), device)
+    x = to_dev(np.zeros(P.N), device)
+    st, res = P.solve([-0.3], b, x, restart=30, rtol=1e-10)
+    assert st == fm.FM_OK
+    assert res[0]["iters"] == 1
+    assert res[0]["rel_residual"] <= 1e-12
+
+
+def test_solve_cfg1_matches_lu(device):
+    fm = _fm()
+    c = W.cfg1()
+    desc, E = c["desc"], c["E"][0]
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    b = W.rhs(c["seeds"][0], O.N)
+    x = to_dev(np.zeros(O.N), device)
+    st, res = P.solve([E], to_dev(b, device), x, restart=30, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    xg = x.cpu().numpy()
+    A = O.assemble(E)
+    assert rel_residual(A, xg, b) <= 1e-10
+    xref = lu_solve(A, b, "dense")
+    assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
+    assert abs(res[0]["rel_residual"] - rel_residual(A, xg, b)) <= 1e-12
+
+
+def test_solve_batched_energies(device):
+    fm = _fm()
+    desc = small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    Es = [-0.6, -0.35, -0.1]
+    B = np.stack([W.rhs(2001 + i, O.N) for i in range(3)])
+    X = to_dev(np.zeros_like(B), device)
+    st, res = P.solve(Es, to_dev(B, device), X, restart=250, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    Xg = X.cpu().numpy()
+    for i, E in enumerate(Es):
+        A = O.assemble(E)
+        assert rel_residual(A, Xg[i], B[i]) <= 1e-10
+        xref = lu_solve(A, B[i], "splu")
+        assert np.linalg.norm(Xg[i] - xref) / np.linalg.norm(xref) <= 1e-8
+
+
+def test_solve_identical_particle_symmetry(device):
+    from tests.test_oracle_operator import permutation_maps
+    fm = _fm()
+    c = W.cfg1()
+    desc, E = c["desc"], c["E"][0]
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    (ci, cs), (ri, rs) = permutation_maps(O, (1, 2))
+    b = W.rhs(77, O.N)
+    bp = rs * b[ri]
+    X = to_dev(np.zeros((2, O.N)), device)
+    st, _ = P.solve([E, E], to_dev(np.stack([b, bp]), device), X, restart=30, rtol=1e-12, max_iters=3000)
+    assert st == fm.FM_OK
+    x, xp = X.cpu().numpy()
+    assert np.abs(xp - cs * x[ci]).max() <= 1e-9 * np.abs(x).max()
+
+
+def test_solve_rejects_nonfinite_rhs(device):
+    fm = _fm()
+    P = fm.Problem(W.cfg1()["desc"])
+    b = W.rhs(1, P.N)
+    b[17] = np.nan
+    x = to_dev(np.zeros(P.N), device)
+    with pytest.raises(fm.FmError) as e:
+        P.solve([-0.25], to_dev(b, device), x)
+    assert e.value.status == fm.FM_E_NONFINITE

@@ -1,0 +1,100 @@
+"""CPU checks of the library's host set-up (include/fm_host.h) against the
+oracle and against SciPy: 1D bases (P2: closed-form Hermite functions vs the
+oracle's monomial solve), the real quasi-diagonalisation D(A1, A2) of
+eq. (WW-scale), and a full factor build.  No device is used.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.basis import Basis1D
+from paper_2005_05398_amd import fm
+from paper_2005_05398_amd import workloads as W
+
+lib_built = pytest.mark.skipif(not __import__("os").path.exists(fm.LIB_PATH), reason="libfm.so not built")
+
+DIMS = [
+    ({"degree": 3, "n": 16, "R": 20.0, "map": "uniform"}, False),
+    ({"degree": 5, "n": 64, "R": 40.0, "map": "quadratic"}, False),
+    ({"degree": 5, "n": 22, "R": 36.0, "map": "pow"}, False),
+    ({"degree": 5, "n": 127, "R": 20.0, "map": "uniform"}, False),
+    ({"degree": 3, "n": 8, "R": 2.0, "map": "sin"}, True),
+    ({"degree": 3, "n": 32, "R": 2.0, "map": "sin"}, True),
+    ({"degree": 5, "n": 24, "R": 2.0, "map": "sin"}, True),
+    ({"degree": 5, "n": 9, "R": 2.0, "map": "uniform"}, True),
+    ({"degree": 5, "n": 6, "R": 2.0, "map": "sin"}, True),
+]
+
+
+@lib_built
+@pytest.mark.parametrize("dim,is_z", DIMS)
+def test_library_basis_matches_oracle(dim, is_z):
+    pts, S, D1, D2 = fm.host_basis(dim, is_z)
+    b = Basis1D(dim["degree"], dim["n"], "z" if is_z else "xy", dim["R"], dim["map"])
+    np.testing.assert_allclose(pts, b.points, rtol=0, atol=1e-14 * max(1.0, dim["R"]))
+    for mine, ref in ((S, b.matrix(0)), (D1, b.matrix(1)), (D2, b.matrix(2))):
+        sc = max(1.0, np.abs(ref).max())
+        assert np.abs(mine - ref).max() <= 1e-12 * sc
+
+
+@lib_built
+@pytest.mark.parametrize("bad", [{"degree": 5, "n": 64, "R": 20.0, "map": "uniform", "z": True},
+                                 {"degree": 5, "n": 63, "R": 20.0, "map": "uniform", "z": False},
+                                 {"degree": 3, "n": 15, "R": 20.0, "map": "uniform", "z": False},
+                                 {"degree": 4, "n": 16, "R": 20.0, "map": "uniform", "z": False},
+                                 {"degree": 3, "n": 16, "R": -1.0, "map": "uniform", "z": False}])
+def test_library_rejects_bad_basis(bad):
+    with pytest.raises(fm.FmError) as e:
+        fm.host_basis(bad, bad["z"])
+    assert e.value.status == fm.FM_E_INVALID
+
+
+def _check_pencil(A1, A2):
+    Wb, Wm, lre, lim, ty, err = fm.host_pencil(A1, A2)
+    n = A1.shape[0]
+    Lam = np.diag(lre)
+    for i in range(n):
+        if ty[i] == 1:
+            Lam[i, i + 1] = lim[i]
+            Lam[i + 1, i] = lim[i + 1]
+    sc = max(1.0, np.abs(lre).max())
+    assert np.abs(Wb @ A1 @ Wm - Lam).max() <= 1e-8 * sc
+    assert np.abs(Wb @ A2 @ Wm - np.eye(n)).max() <= 1e-8
+    # eigenvalues agree with scipy's generalized eigenvalues
+    ref = sla.eigvals(A1, A2)
+    mine = lre + 1j * lim
+    for v in ref:
+        assert np.min(np.abs(mine - v)) <= 1e-8 * max(1.0, abs(v))
+    return ty
+
+
+@lib_built
+def test_library_pencil_random_and_complex():
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 17, 40):
+        A1 = rng.standard_normal((n, n))
+        A2 = rng.standard_normal((n, n)) + n * np.eye(n)
+        _check_pencil(A1, A2)
+    # a pencil with a known complex pair
+    A1 = np.array([[1.0, 2.0, 0.0], [-2.0, 1.0, 0.0], [0.0, 0.0, 3.0]])
+    ty = _check_pencil(A1, np.eye(3))
+    assert list(ty).count(1) == 1
+
+
+@lib_built
+@pytest.mark.parametrize("deg,n,mu", [(5, 64, 0.0), (5, 64, 2000.0), (5, 127, 600.0), (3, 16, 12.0)])
+def test_library_pencil_on_collocation_pencils(deg, n, mu):
+    b = Basis1D(deg, n, "xy", 40.0, "quadratic")
+    x = b.points
+    S = b.matrix(0)
+    A1 = -b.matrix(2) + np.diag(mu / x ** 2 - 1.0 / x) @ S
+    _check_pencil(A1, S)
+
+
+@lib_built
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_library_full_setup(name):
+    cfg = W.CONFIGS[name]()
+    err, pairs, N = fm.host_setup_check(cfg["desc"])
+    assert N == W.n_unknowns(cfg["desc"])
+    assert err < 1e-8
