@@ -157,6 +157,32 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
 fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
                    const fm_solve_opts *opts, fm_solve_result *results, void *stream);
 
+/* Per-kernel-class timing of the calls above, for roofline accounting.
+ * While enabled, HIP events are recorded on the caller's stream around every
+ * kernel launch (a few microseconds per launch), and the algorithmic bytes
+ * and flops of each launch are added up from the problem sizes and the number
+ * of Arnoldi steps each request took (unique FP64 words read and written by
+ * the operation's definition; caches and re-reads not counted).
+ * fm_profile(p, 1) resets the counters and enables; fm_profile(p, 0) disables.
+ * fm_profile_read returns, for one class, the summed kernel time in ms, the
+ * number of launches, and the algorithmic bytes and flops. */
+typedef enum {
+    FM_K_MATVEC = 0,    /* operator (H - E S) x */
+    FM_K_MODEZ = 1,     /* preconditioner z-mode products */
+    FM_K_XY = 2,        /* preconditioner x-y slice products and divide */
+    FM_K_MDOT = 3,      /* Arnoldi projections V^T w */
+    FM_K_MUPDATE = 4,   /* Arnoldi updates w -= V h */
+    FM_K_NORM = 5,      /* norm, Givens rotation, residual estimate */
+    FM_K_SCALE = 6,     /* v_{j+1} = w / h */
+    FM_K_RESTART = 7,   /* per-cycle solution update and true residual */
+    FM_K_COUPLING = 8,  /* operator: coupling to the other components (FM_K_MATVEC: the rest) */
+    FM_K_COUNT = 9
+} fm_kernel_class;
+
+fm_status fm_profile(fm_problem *p, int enable);
+fm_status fm_profile_read(const fm_problem *p, int kclass, double *total_ms, long long *launches, double *bytes,
+                          double *flops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,20 @@ DimDev dim_dev(fm_problem *p, const Basis1D &b, std::string &err) {
     d.S = put(p, b.val[0], err);
     d.D1 = put(p, b.val[1], err);
     d.D2 = put(p, b.val[2], err);
+    std::vector<int> lo(b.n), hi(b.n);
+    for (int i = 0; i < b.n; ++i) {
+        lo[i] = 1 << 30;
+        hi[i] = -1;
+        for (int s = 0; s < MAXR; ++s) {
+            int g = b.idx[size_t(i) * MAXR + s];
+            if (g >= 0) {
+                lo[i] = std::min(lo[i], g);
+                hi[i] = std::max(hi[i], g);
+            }
+        }
+    }
+    d.first = put(p, lo, err);
+    d.last = put(p, hi, err);
     return d;
 }
 
@@ -166,12 +180,109 @@ fm_status ensure_krylov(fm_problem *p, int nb, int m, KrylovDev &K) {
     return FM_OK;
 }
 
+// -- per-kernel-class timing ---------------------------------------------
+size_t prof_mark(fm_problem *p, hipStream_t st) {
+    Profile &pf = p->prof;
+    if (!pf.on) return SIZE_MAX;
+    if (pf.next == pf.ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
+        pf.ev.push_back(e);
+    }
+    if (hipEventRecord(pf.ev[pf.next], st) != hipSuccess) return SIZE_MAX;
+    return pf.next++;
+}
+
+template <class F>
+void timed(fm_problem *p, hipStream_t st, int cls, F &&f) {
+    size_t a = prof_mark(p, st);
+    f();
+    size_t b = prof_mark(p, st);
+    if (a != SIZE_MAX && b != SIZE_MAX) p->prof.recs.push_back({cls, a, b});
+}
+
+void prof_work(fm_problem *p, int cls, double bytes, double flops) {
+    if (!p->prof.on) return;
+    p->prof.bytes[cls] += bytes;
+    p->prof.flops[cls] += flops;
+}
+
+// Reads the elapsed times of the recorded launches; the stream must be idle.
+void prof_collect(fm_problem *p) {
+    Profile &pf = p->prof;
+    for (auto &r : pf.recs) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, pf.ev[r.e0], pf.ev[r.e1]) == hipSuccess) pf.ms[r.cls] += ms;
+        pf.launches[r.cls] += 1;
+    }
+    pf.recs.clear();
+    pf.next = 0;
+}
+
+// Algorithmic work of one request (unique FP64 words of each operation's definition).
+struct Work {
+    double N, pts, xyflops, localflops, coupflops;
+    explicit Work(const fm_problem *p) {
+        N = double(p->N);
+        pts = double(p->npts[0] + p->npts[1] + p->npts[2]);
+        xyflops = 0;
+        localflops = 0;
+        coupflops = 0;
+        const int nM = p->nM;
+        for (int a = 0; a < 3; ++a) {
+            const double np = double(p->npts[a]);
+            xyflops += 4.0 * nM * p->bz[a].n * double(p->bx[a].n) * p->by[a].n * (p->bx[a].n + p->by[a].n);
+            // local stencil as separable banded passes: 9 passes of 2q terms (2 flops each) per
+            // unknown, plus the pointwise combination (about 20 flops) and the M'+-1 terms
+            const double r = 2.0 * std::max(p->bx[a].q, std::max(p->by[a].q, p->bz[a].q));
+            localflops += np * nM * (9 * 2 * r + 20 + (nM > 1 ? 12 : 0));
+            // coupling: per beta the r_z r_x r_y contraction (2 flops each) for each M'', plus
+            // the M'' -> M' weights
+            for (int b = 0; b < 3; ++b)
+                if (b != a)
+                    coupflops += np * (nM * 2.0 * (2 * p->bz[b].q) * (2 * p->bx[b].q) * (2 * p->by[b].q) +
+                                       2.0 * nM * nM);
+        }
+    }
+    double matvec() const { return 8 * (2 * N + pts); }
+    double coupling() const { return 8 * 3 * N; }
+    double modez() const { return 8 * 2 * N; }
+    double xy() const { return 8 * 2 * N; }
+    double mdot(int j) const { return 8 * (j + 2) * N; }
+    double mupdate(int j) const { return 8 * (j + 3) * N; }
+};
+
+void add_precond_work(fm_problem *p, const Work &w, double nreq) {
+    prof_work(p, FM_K_MODEZ, 2 * w.modez() * nreq, 0);
+    prof_work(p, FM_K_XY, w.xy() * nreq, w.xyflops * nreq);
+}
+
+void add_matvec_work(fm_problem *p, const Work &w, double nreq) {
+    prof_work(p, FM_K_MATVEC, w.matvec() * nreq, w.localflops * nreq);
+    prof_work(p, FM_K_COUPLING, w.coupling() * nreq, w.coupflops * nreq);
+}
+
+void apply_operator(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *x, double *y,
+                    hipStream_t st) {
+    timed(p, st, FM_K_MATVEC, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, st, 1); });
+    timed(p, st, FM_K_COUPLING, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, st, 2); });
+}
+
+void add_step_work(fm_problem *p, const Work &w, int j) {
+    add_precond_work(p, w, 1);
+    add_matvec_work(p, w, 1);
+    prof_work(p, FM_K_MDOT, 2 * w.mdot(j), 4.0 * (j + 1) * w.N);
+    prof_work(p, FM_K_MUPDATE, 2 * w.mupdate(j), 4.0 * (j + 1) * w.N);
+    prof_work(p, FM_K_NORM, 8 * w.N, 2 * w.N);
+    prof_work(p, FM_K_SCALE, 16 * w.N, 0);
+}
+
 void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
                    int prec, double *min_den, hipStream_t st) {
     (void)prec;
-    launch_modez(p->pd, p->pr, nb, mask, 0, in, out, st);
-    launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st);
-    launch_modez(p->pd, p->pr, nb, mask, 1, out, out, st);
+    timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 0, in, out, st); });
+    timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st); });
+    timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 1, out, out, st); });
 }
 
 }  // namespace
@@ -181,6 +292,17 @@ void set_error(const std::string &msg) { g_err = msg; }
 std::string upload(fm_problem *p, const HostFactors &hf) {
     std::string err;
     ProblemDev &pd = p->pd;
+    pd.tile_lds = 0;
+    pd.nodes_total = 0;
+    for (int a = 0; a < 3; ++a) pd.nodes_total += 3 + p->bx[a].K + p->by[a].K + p->bz[a].K;
+    pd.q[0] = p->bx[0].q;
+    pd.q[1] = p->by[0].q;
+    pd.q[2] = p->bz[0].q;
+    for (int a = 1; a < 3; ++a) {
+        if (p->bx[a].q != pd.q[0]) pd.q[0] = 0;
+        if (p->by[a].q != pd.q[1]) pd.q[1] = 0;
+        if (p->bz[a].q != pd.q[2]) pd.q[2] = 0;
+    }
     for (int a = 0; a < 3; ++a) {
         CompDev &C = pd.comp[a];
         C.x = dim_dev(p, p->bx[a], err);
@@ -194,6 +316,32 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         for (int b = 0; b < 3; ++b) {
             C.c[b] = p->crot[b][a];
             C.s[b] = p->srot[b][a];
+        }
+        C.xt = std::max(1, 256 / p->by[a].n);
+        C.xt = std::min(C.xt, p->bx[a].n);
+        C.ntiles = p->bz[a].n * ((p->bx[a].n + C.xt - 1) / C.xt);
+        // largest coefficient tile: z support x (x support of xt consecutive points) x ny
+        {
+            const Basis1D &bz = p->bz[a], &bx = p->bx[a];
+            int rz = 0, rx = 0;
+            for (int i = 0; i < bz.n; ++i) {
+                int lo = 1 << 30, hi = -1;
+                for (int s = 0; s < MAXR; ++s) {
+                    int g = bz.idx[size_t(i) * MAXR + s];
+                    if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
+                }
+                rz = std::max(rz, hi - lo + 1);
+            }
+            for (int i0 = 0; i0 < bx.n; i0 += C.xt) {
+                int lo = 1 << 30, hi = -1;
+                for (int i = i0; i < std::min(bx.n, i0 + C.xt); ++i)
+                    for (int s = 0; s < MAXR; ++s) {
+                        int g = bx.idx[size_t(i) * MAXR + s];
+                        if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
+                    }
+                rx = std::max(rx, hi - lo + 1);
+            }
+            pd.tile_lds = std::max(pd.tile_lds, rz * rx * p->by[a].n);
         }
         PrecCompDev &F = p->pr.comp[a];
         std::memset(&F, 0, sizeof(F));
@@ -213,6 +361,13 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         F.ty = put(p, h.ty, err);
         if (!err.empty()) return err;
     }
+    // device copies of the two descriptors
+    pd.dev = nullptr;
+    p->pr.dev = nullptr;
+    std::vector<ProblemDev> pdv(1, pd);
+    std::vector<PrecDev> prv(1, p->pr);
+    pd.dev = put(p, pdv, err);
+    p->pr.dev = put(p, prv, err);
     return err;
 }
 
@@ -258,6 +413,8 @@ fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out) {
                 return fail(FM_E_INVALID, "x and y bases are limited to 192 functions");
             }
             need = std::max(need, sizeof(double) * size_t(p->bx[a].n) * p->by[a].n);
+            size_t padded = sizeof(double) * size_t((p->bx[a].n + 15) & ~15) * (((p->by[a].n + 15) & ~15) + 4);
+            if (padded <= size_t(lds)) prepare_large_lds(padded);
         }
         if (need > size_t(lds)) {
             delete p;
@@ -288,6 +445,7 @@ fm_status fm_destroy_problem(fm_problem *p) {
     if (p->ws) (void)hipFree(p->ws);
     if (p->ws_small) (void)hipFree(p->ws_small);
     if (p->host_pinned) (void)hipHostFree(p->host_pinned);
+    for (auto e : p->prof.ev) (void)hipEventDestroy(e);
     delete p;
     return FM_OK;
 }
@@ -316,9 +474,11 @@ fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const do
     fm_status r = ensure_small(p, nbatch, s);
     if (r != FM_OK) return r;
     HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
-    launch_matvec(p->pd, nbatch, s.E, nullptr, x_dev, y_dev, st);
+    apply_operator(p, nbatch, s.E, nullptr, x_dev, y_dev, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
+    add_matvec_work(p, Work(p), nbatch);
+    prof_collect(p);
     return FM_OK;
 }
 
@@ -337,6 +497,8 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
     apply_precond(p, nbatch, s.E, nullptr, r_dev, z_dev, prec, nullptr, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
+    add_precond_work(p, Work(p), nbatch);
+    prof_collect(p);
     return FM_OK;
 }
 
@@ -435,13 +597,13 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
             double *Zj = K.Z + (long long)j * nb * N;
             double *Vn = K.V + (long long)(j + 1) * nb * N;
             apply_precond(p, nb, K.E, K.active, Vj, Zj, opts->prec, s.min_den, st);
-            launch_matvec(p->pd, nb, K.E, K.active, Zj, Vn, st);
-            launch_mdot(K, j, Vn, 0, st);
-            launch_mupdate(K, j, Vn, st);
-            launch_mdot(K, j, Vn, 1, st);
-            launch_mupdate(K, j, Vn, st);
-            launch_norm_givens(K, j, Vn, st);
-            launch_scale_next(K, j, st);
+            apply_operator(p, nb, K.E, K.active, Zj, Vn, st);
+            timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 0, st); });
+            timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
+            timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 1, st); });
+            timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
+            timed(p, st, FM_K_NORM, [&] { launch_norm_givens(K, j, Vn, st); });
+            timed(p, st, FM_K_SCALE, [&] { launch_scale_next(K, j, st); });
             if ((j + 1) % poll == 0 && j + 1 < m) {
                 HIP_TRY(hipMemcpyAsync(hflags, K.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
@@ -453,16 +615,24 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(hflags, K.jcount, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        for (int i = 0; i < nb; ++i)
-            if (hrun[i]) {
-                iters[i] += std::max(1, hflags[i]);     // every cycle counts as progress
-                restarts[i] += 1;
-            }
-        launch_cycle_solve(K, s.running, st);
-        launch_xupdate(K, s.running, x_dev, st);
-        launch_matvec(p->pd, nb, K.E, s.running, x_dev, K.V, st);
-        launch_residual(K, s.running, b_dev, opts->rtol, 0.5, st);
-        launch_scale0(K, st);
+        prof_collect(p);
+        {
+            Work w(p);
+            for (int i = 0; i < nb; ++i)
+                if (hrun[i]) {
+                    for (int j = 0; j < hflags[i]; ++j) add_step_work(p, w, j);
+                    prof_work(p, FM_K_RESTART, 8 * (hflags[i] + 2) * w.N + w.matvec() + 8 * 3 * w.N + 16 * w.N, 0);
+                    iters[i] += std::max(1, hflags[i]);     // every cycle counts as progress
+                    restarts[i] += 1;
+                }
+        }
+        timed(p, st, FM_K_RESTART, [&] {
+            launch_cycle_solve(K, s.running, st);
+            launch_xupdate(K, s.running, x_dev, st);
+            launch_matvec(p->pd, nb, K.E, s.running, x_dev, K.V, st);
+            launch_residual(K, s.running, b_dev, opts->rtol, 0.5, st);
+            launch_scale0(K, st);
+        });
         HIP_TRY(hipGetLastError());
     }
     // results
@@ -474,6 +644,7 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
     HIP_TRY(hipMemcpyAsync(fl.data(), K.flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(run.data(), s.running, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    prof_collect(p);
     fm_status overall = FM_OK;
     for (int i = 0; i < nb; ++i) {
         double rel = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
@@ -492,6 +663,32 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
     if (overall == FM_E_NOT_CONVERGED) g_err = "some requests did not reach rtol";
     if (overall == FM_E_NONFINITE) g_err = "non-finite values during the iteration";
     return overall;
+}
+
+fm_status fm_profile(fm_problem *p, int enable) {
+    if (!p) return fail(FM_E_INVALID, "null problem");
+    Profile &pf = p->prof;
+    pf.on = enable != 0;
+    pf.recs.clear();
+    pf.next = 0;
+    for (int c = 0; c < FM_K_COUNT; ++c) {
+        pf.ms[c] = 0;
+        pf.launches[c] = 0;
+        pf.bytes[c] = 0;
+        pf.flops[c] = 0;
+    }
+    return FM_OK;
+}
+
+fm_status fm_profile_read(const fm_problem *p, int kclass, double *total_ms, long long *launches, double *bytes,
+                          double *flops) {
+    if (!p || kclass < 0 || kclass >= FM_K_COUNT) return fail(FM_E_INVALID, "bad argument");
+    const Profile &pf = p->prof;
+    if (total_ms) *total_ms = pf.ms[kclass];
+    if (launches) *launches = pf.launches[kclass];
+    if (bytes) *bytes = pf.bytes[kclass];
+    if (flops) *flops = pf.flops[kclass];
+    return FM_OK;
 }
 
 }  // extern "C"

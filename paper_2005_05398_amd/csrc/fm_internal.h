@@ -64,6 +64,7 @@ struct DimDev {
     const double *pts;           // n
     const int *idx;              // n * MAXR
     const double *S, *D1, *D2;   // n * MAXR
+    const int *first, *last;     // n: first and last global function index nonzero at each point
 };
 
 struct CompDev {
@@ -73,6 +74,8 @@ struct CompDev {
     const double *P;             // potential field V_a + sum_b V_b^(l), npts
     const double *Vs;            // V_a^(s)(x, y), nx*ny
     double c[3], s[3];           // (c_ba, s_ba) for beta = 0..2
+    int xt;                      // x points per matvec tile
+    int ntiles;                  // matvec tiles of this component: nz * ceil(nx / xt)
 };
 
 struct ProblemDev {
@@ -81,8 +84,12 @@ struct ProblemDev {
     long long N;                 // unknowns per request
     // angular coupling constants (L > 0)
     double lhp[MAXM], lhm[MAXM]; // lambda-hat^{J, M'} and lambda-hat^{J, -M'} per M' index
-    double dcoef[MAXM * MAXM * 32];   // Wigner-sum coefficient table (see setup)
+    double dcoef[MAXM * MAXM * 16];   // Wigner-sum coefficient table (see setup)
     int dlen;
+    int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
+    int tile_lds;                // doubles of LDS for the largest coefficient tile
+    int nodes_total;             // doubles of LDS for all node tables
+    const ProblemDev *dev;       // device copy of this descriptor (kernels take this pointer)
 };
 
 struct PrecCompDev {
@@ -99,6 +106,7 @@ struct PrecCompDev {
 
 struct PrecDev {
     PrecCompDev comp[3];
+    const PrecDev *dev;          // device copy of this descriptor
 };
 
 // Per-call GMRES device state (pointers into one allocation).
@@ -128,8 +136,9 @@ constexpr int NBLK = 256;        // blocks per request in the reduction kernels
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).
+// part: 0 whole operator, 1 everything but the coupling, 2 the coupling (added to y)
 void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active,
-                   const double *x, double *y, hipStream_t st);
+                   const double *x, double *y, hipStream_t st, int part = 0);
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
                   const double *in, double *out, hipStream_t st);
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
@@ -147,6 +156,7 @@ void launch_scale0(const KrylovDev &k, hipStream_t st);
 void launch_bnorm(const KrylovDev &k, const double *b, hipStream_t st);
 void launch_fill(double *p, long long n, double v, hipStream_t st);
 void prepare_large_lds(size_t bytes);
+size_t xy_lds_limit();
 void launch_copy(double *dst, const double *src, long long n, hipStream_t st);
 
 }  // namespace fm

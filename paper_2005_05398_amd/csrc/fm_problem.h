@@ -15,6 +15,21 @@ struct HostFactors {
     double max_err = 0;
 };
 
+struct Profile {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    size_t next = 0;
+    struct Rec {
+        int cls;
+        size_t e0, e1;
+    };
+    std::vector<Rec> recs;
+    double ms[FM_K_COUNT] = {0};
+    long long launches[FM_K_COUNT] = {0};
+    double bytes[FM_K_COUNT] = {0};
+    double flops[FM_K_COUNT] = {0};
+};
+
 struct DeviceBuffer {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -44,6 +59,7 @@ struct fm_problem {
     size_t ws_small_bytes = 0;
     double *host_pinned = nullptr;           // pinned host scratch for flag read-back
     size_t host_pinned_bytes = 0;
+    fm::Profile prof;
 };
 
 namespace fm {

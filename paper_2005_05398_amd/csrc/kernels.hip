@@ -61,7 +61,7 @@ __device__ __forceinline__ bool is_cyclic(int b, int a) {
 // ---------------------------------------------------------------------------
 // Operator: y = (H - E S) x.  One thread per spatial collocation point of one
 // component; it produces all n_M outputs of that point.
-__global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__restrict__ Evec,
+__global__ void __launch_bounds__(256) k_matvec(const ProblemDev *__restrict__ pd, const double *__restrict__ Evec,
                                                 const int *__restrict__ active, const double *__restrict__ X,
                                                 double *__restrict__ Y) {
     const int req = blockIdx.y;
@@ -69,13 +69,13 @@ __global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__r
     long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int a = 0;
     long long p = gid;
-    while (a < 3 && p >= pd.comp[a].npts) { p -= pd.comp[a].npts; ++a; }
+    while (a < 3 && p >= pd->comp[a].npts) { p -= pd->comp[a].npts; ++a; }
     if (a >= 3) return;
-    const CompDev &C = pd.comp[a];
-    const int nM = pd.nM, J = pd.J, M0 = pd.M0;
+    const CompDev &C = pd->comp[a];
+    const int nM = pd->nM, J = pd->J, M0 = pd->M0;
     const int nx = C.x.n, ny = C.y.n;
     const int iz = int(p / C.nxy), rem = int(p % C.nxy), ix = rem / ny, iy = rem % ny;
-    const double *x = X + (long long)req * pd.N;
+    const double *x = X + (long long)req * pd->N;
     const double E = Evec[req];
     const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
 
@@ -138,8 +138,8 @@ __global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__r
         double o = -uyy[iM] - uxx[iM] -
                    inv2 * (omz * uzz[iM] - 2.0 * (Mp + 1) * zc * uz[iM] - double(Mp) * (Mp + 1) * u[iM]) +
                    ((double(J) * (J + 1) - 2.0 * Mp * Mp) * iy2 + P - E) * u[iM];
-        if (iM + 1 < nM) o += pd.lhp[iM] * iy2 * (-omz * uz[iM + 1] + 2.0 * (Mp + 1) * zc * u[iM + 1]);
-        if (iM > 0) o += pd.lhm[iM] * iy2 * uz[iM - 1];
+        if (iM + 1 < nM) o += pd->lhp[iM] * iy2 * (-omz * uz[iM + 1] + 2.0 * (Mp + 1) * zc * u[iM + 1]);
+        if (iM > 0) o += pd->lhm[iM] * iy2 * uz[iM - 1];
         out[iM] = o;
     }
 
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__r
     if (vs != 0.0) {
         for (int b = 0; b < 3; ++b) {
             if (b == a) continue;
-            const CompDev &B = pd.comp[b];
+            const CompDev &B = pd->comp[b];
             const double c = C.c[b], s = C.s[b];
             double xb = sqrt(fmax(c * c * xc * xc + 2.0 * s * c * xc * yc * zc + s * s * yc * yc, 0.0));
             double yb = sqrt(fmax(s * s * xc * xc - 2.0 * s * c * xc * yc * zc + c * c * yc * yc, 0.0));
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__r
                 for (int iM = 0; iM < nM; ++iM) {
                     double acc = 0;
                     for (int jM = 0; jM < nM; ++jM) {
-                        const double *G = pd.dcoef + (iM * nM + jM) * pd.dlen;
+                        const double *G = pd->dcoef + (iM * nM + jM) * pd->dlen;
                         double f = 0;
                         for (int k = 0; k <= 2 * J; ++k) f += G[k] * cpow[k] * spow[2 * J - k];
                         acc += f * sbp[M0 + jM] * val[jM];
@@ -210,8 +210,281 @@ __global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__r
             }
         }
     }
-    double *y = Y + (long long)req * pd.N + C.off + p;
+    double *y = Y + (long long)req * pd->N + C.off + p;
     for (int iM = 0; iM < nM; ++iM) y[(long long)iM * C.npts] = out[iM];
+}
+
+// ---------------------------------------------------------------------------
+// Operator, tiled: one block per (request, component, z point, XT consecutive
+// x points); threads cover the tile's (x, y) points.  The coefficients of the
+// tile's local stencil (z support x x support x all y) are staged in LDS once
+// per M' block; node tables sit in LDS for the coupling's interval search.
+// Q*: spline orders (2 cubic, 3 quintic); NM: number of M' blocks.
+
+// Hermite values at t of the 2Q functions nonzero there; dropped functions get
+// index 0 and value 0 so that every slot can be read unconditionally.
+template <int Q>
+__device__ __forceinline__ void eval_lds(const double *__restrict__ nodes, int K, double hbar, int drop0, double t,
+                                         int *g, double *v) {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (nodes[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int m = lo;
+    const double t0 = nodes[m], h = nodes[m + 1] - t0;
+    const double s = (t - t0) / h, r = h / hbar;
+    const double s2 = s * s, s3 = s2 * s;
+    if (Q == 2) {
+        v[0] = 1.0 - 3.0 * s2 + 2.0 * s3;
+        v[1] = r * (s - 2.0 * s2 + s3);
+        v[2] = 3.0 * s2 - 2.0 * s3;
+        v[3] = r * (s3 - s2);
+    } else {
+        const double s4 = s3 * s, s5 = s4 * s, r2 = r * r;
+        v[0] = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;
+        v[1] = r * (s - 6.0 * s3 + 8.0 * s4 - 3.0 * s5);
+        v[2] = r2 * 0.5 * (s2 - 3.0 * s3 + 3.0 * s4 - s5);
+        v[3] = 10.0 * s3 - 15.0 * s4 + 6.0 * s5;
+        v[4] = r * (-4.0 * s3 + 7.0 * s4 - 3.0 * s5);
+        v[5] = r2 * 0.5 * (s3 - 2.0 * s4 + s5);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int node = m + e;
+            int gi = node * Q + k - drop0 - ((drop0 && node == K) ? 1 : 0);
+            const bool dropped = drop0 && k == 0 && (node == 0 || node == K);
+            g[e * Q + k] = dropped ? 0 : gi;
+            if (dropped) v[e * Q + k] = 0.0;
+        }
+}
+
+template <int QX, int QY, int QZ, int NM>
+__global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restrict__ pd, const double *__restrict__ Evec,
+                                                      const int *__restrict__ active, const double *__restrict__ X,
+                                                      double *__restrict__ Y) {
+    constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    extern __shared__ double sm[];
+    int t = blockIdx.x, a = 0;
+    while (a < 3 && t >= pd->comp[a].ntiles) { t -= pd->comp[a].ntiles; ++a; }
+    if (a >= 3) return;
+    double *tile = sm;
+    const CompDev &C = pd->comp[a];
+    const int nx = C.x.n, ny = C.y.n, xt = C.xt;
+    const int ntx = (nx + xt - 1) / xt;
+    const int iz = t / ntx, ix0 = (t % ntx) * xt;
+    const int nxt = min(xt, nx - ix0);
+    const int kzlo = C.z.first[iz], kzhi = C.z.last[iz];
+    const int kxlo = C.x.first[ix0], kxhi = C.x.last[ix0 + nxt - 1];
+    const int Rz = kzhi - kzlo + 1, Rx = kxhi - kxlo + 1;
+    const int tile_n = Rz * Rx * ny;
+    const bool has = threadIdx.x < nxt * ny;
+    const int ixl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
+    const int ix = ix0 + ixl;
+    const double *x = X + (long long)req * pd->N;
+    const double E = Evec[req];
+    const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
+
+    // local rows (tile-relative indices; dropped functions have value 0)
+    // z row: the same for the whole block (read inside the z loop)
+    const int *zidx = C.z.idx + iz * MAXR;
+    const double *zS = C.z.S + iz * MAXR, *zD1 = C.z.D1 + iz * MAXR, *zD2 = C.z.D2 + iz * MAXR;
+    int lx[RX], ly[RY];
+    double Sx[RX], D2x[RX], Sy[RY], D2y[RY];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+        const int g = C.x.idx[ix * MAXR + s];
+        lx[s] = g >= 0 ? g - kxlo : 0;
+        Sx[s] = C.x.S[ix * MAXR + s];
+        D2x[s] = C.x.D2[ix * MAXR + s];
+    }
+#pragma unroll
+    for (int s = 0; s < RY; ++s) {
+        const int g = C.y.idx[iy * MAXR + s];
+        ly[s] = g >= 0 ? g : 0;
+        Sy[s] = C.y.S[iy * MAXR + s];
+        D2y[s] = C.y.D2[iy * MAXR + s];
+    }
+
+    double u[NM], uz[NM], uzz[NM], uxx[NM], uyy[NM];
+#pragma unroll
+    for (int iM = 0; iM < NM; ++iM) {
+        __syncthreads();
+        const double *c = x + C.off + (long long)iM * C.npts;
+        for (int e = threadIdx.x; e < tile_n; e += 256) {
+            const int kz = e / (Rx * ny), rest = e - kz * (Rx * ny);
+            tile[e] = c[((long long)(kzlo + kz) * nx + kxlo) * ny + rest];
+        }
+        __syncthreads();
+        double s0 = 0, s1 = 0, s2 = 0, sxx = 0, syy = 0;
+#pragma unroll 1
+        for (int a1 = 0; a1 < RZ; ++a1) {
+            const int gzz = zidx[a1];
+            const int lz = gzz >= 0 ? gzz - kzlo : 0;
+            double b00 = 0, b20 = 0, b02 = 0;
+#pragma unroll
+            for (int a2 = 0; a2 < RX; ++a2) {
+                const double *row = tile + (lz * Rx + lx[a2]) * ny;
+                double t0 = 0, t2 = 0;
+#pragma unroll
+                for (int a3 = 0; a3 < RY; ++a3) {
+                    const double cv = row[ly[a3]];
+                    t0 += Sy[a3] * cv;
+                    t2 += D2y[a3] * cv;
+                }
+                b00 += Sx[a2] * t0;
+                b20 += D2x[a2] * t0;
+                b02 += Sx[a2] * t2;
+            }
+            const double sz = zS[a1], d1 = zD1[a1], d2 = zD2[a1];
+            s0 += sz * b00;
+            s1 += d1 * b00;
+            s2 += d2 * b00;
+            sxx += sz * b20;
+            syy += sz * b02;
+        }
+        u[iM] = s0; uz[iM] = s1; uzz[iM] = s2; uxx[iM] = sxx; uyy[iM] = syy;
+    }
+    if (!has) return;
+
+    const long long p = (long long)iz * C.nxy + ix * ny + iy;
+    const double P = C.P[p];
+    const double iy2 = 1.0 / (yc * yc), inv2 = 1.0 / (xc * xc) + iy2, omz = 1.0 - zc * zc;
+    const int J = pd->J, M0 = pd->M0;
+    double out[NM];
+#pragma unroll
+    for (int iM = 0; iM < NM; ++iM) {
+        const int Mp = M0 + iM;
+        double o = -uyy[iM] - uxx[iM] -
+                   inv2 * (omz * uzz[iM] - 2.0 * (Mp + 1) * zc * uz[iM] - double(Mp) * (Mp + 1) * u[iM]) +
+                   ((double(J) * (J + 1) - 2.0 * Mp * Mp) * iy2 + P - E) * u[iM];
+        if (iM + 1 < NM) o += pd->lhp[iM] * iy2 * (-omz * uz[iM + 1] + 2.0 * (Mp + 1) * zc * u[iM + 1]);
+        if (iM > 0) o += pd->lhm[iM] * iy2 * uz[iM - 1];
+        out[iM] = o;
+    }
+
+    double *y = Y + (long long)req * pd->N + C.off + p;
+#pragma unroll
+    for (int iM = 0; iM < NM; ++iM) y[(long long)iM * C.npts] = out[iM];
+}
+
+// Coupling term of the operator, added to y: for every point of component
+// alpha and both beta != alpha, the beta expansion at the rotated point (zero
+// outside beta's box) times V_a^(s) x y / (x_b y_b) and, for L > 0, the
+// angular factors of eq. (FM-pre).  One thread per spatial point.
+template <int QX, int QY, int QZ, int NM>
+__global__ void __launch_bounds__(256) k_coupling(const ProblemDev *__restrict__ pd, const int *__restrict__ active,
+                                                  const double *__restrict__ X, double *__restrict__ Y) {
+    constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    extern __shared__ double sm[];
+    int noff[3][3];
+    {
+        int off = 0;
+        for (int b = 0; b < 3; ++b) {
+            const DimDev *dd[3] = {&pd->comp[b].x, &pd->comp[b].y, &pd->comp[b].z};
+            for (int d = 0; d < 3; ++d) {
+                noff[b][d] = off;
+                for (int i = threadIdx.x; i <= dd[d]->K; i += 256) sm[off + i] = dd[d]->nodes[i];
+                off += dd[d]->K + 1;
+            }
+        }
+    }
+    __syncthreads();
+    long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    int a = 0;
+    while (a < 3 && p >= pd->comp[a].npts) { p -= pd->comp[a].npts; ++a; }
+    if (a >= 3) return;
+    const CompDev &C = pd->comp[a];
+    const int ny = C.y.n;
+    const int iz = int(p / C.nxy), rem = int(p % C.nxy), ix = rem / ny, iy = rem % ny;
+    const double vs = C.Vs[rem];
+    if (vs == 0.0) return;
+    const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
+    const double *x = X + (long long)req * pd->N;
+    const int J = pd->J, M0 = pd->M0;
+    const double omz = 1.0 - zc * zc;
+    double out[NM];
+#pragma unroll
+    for (int iM = 0; iM < NM; ++iM) out[iM] = 0.0;
+#pragma unroll 1
+    for (int bb = 0; bb < 2; ++bb) {
+        const int b = (a + 1 + bb) % 3;
+        const CompDev &B = pd->comp[b];
+        const double c = C.c[b], s = C.s[b];
+        const double xb = sqrt(fmax(c * c * xc * xc + 2.0 * s * c * xc * yc * zc + s * s * yc * yc, 0.0));
+        const double yb = sqrt(fmax(s * s * xc * xc - 2.0 * s * c * xc * yc * zc + c * c * yc * yc, 0.0));
+        if (!(xb <= B.x.R && yb <= B.y.R)) continue;
+        const double den = xb * yb;
+        double zb = den > 0.0 ? (s * c * (yc * yc - xc * xc) + (c * c - s * s) * xc * yc * zc) / den : 0.0;
+        zb = fmin(1.0, fmax(-1.0, zb));
+        int hz[RZ], hx[RX], hy[RY];
+        double vz[RZ], vx[RX], vy[RY];
+        eval_lds<QZ>(sm + noff[b][2], B.z.K, B.z.hbar, B.z.drop0, zb, hz, vz);
+        eval_lds<QX>(sm + noff[b][0], B.x.K, B.x.hbar, B.x.drop0, xb, hx, vx);
+        eval_lds<QY>(sm + noff[b][1], B.y.K, B.y.hbar, B.y.drop0, yb, hy, vy);
+        const int bnx = B.x.n, bny = B.y.n;
+        double val[NM];
+#pragma unroll
+        for (int iM = 0; iM < NM; ++iM) {
+            const double *cb = x + B.off + (long long)iM * B.npts;
+            double acc = 0;
+#pragma unroll 2
+            for (int a1 = 0; a1 < RZ; ++a1) {
+                double accx = 0;
+#pragma unroll
+                for (int a2 = 0; a2 < RX; ++a2) {
+                    const double *row = cb + ((long long)hz[a1] * bnx + hx[a2]) * bny;
+                    double accy = 0;
+#pragma unroll
+                    for (int a3 = 0; a3 < RY; ++a3) accy += vy[a3] * row[hy[a3]];
+                    accx += vx[a2] * accy;
+                }
+                acc += vz[a1] * accx;
+            }
+            val[iM] = acc;
+        }
+        const double base = vs * xc * yc / den;
+        if (J == 0) {
+            out[0] += base * val[0];
+        } else {
+            double arg = (-s * xc * zc + c * yc) / yb;
+            arg = fmin(1.0, fmax(-1.0, arg));
+            double cw = sqrt(0.5 * (1.0 + arg)), sw = sqrt(0.5 * (1.0 - arg));
+            if (!is_cyclic(b, a)) cw = -cw;
+            const double sa = sqrt(fmax(omz, 0.0)), sb = sqrt(fmax(1.0 - zb * zb, 0.0));
+            double sbp[NM], sap[NM];
+            sbp[0] = M0 ? sb : 1.0;
+            sap[0] = M0 ? sa : 1.0;
+#pragma unroll
+            for (int k = 1; k < NM; ++k) { sbp[k] = sbp[k - 1] * sb; sap[k] = sap[k - 1] * sa; }
+#pragma unroll
+            for (int iM = 0; iM < NM; ++iM) {
+                double acc = 0;
+#pragma unroll
+                for (int jM = 0; jM < NM; ++jM) {
+                    const double *G = pd->dcoef + (iM * NM + jM) * pd->dlen;
+                    // sum_k G[k] cw^k sw^(2J-k) by Horner in cw
+                    double f = G[2 * J], sp = 1.0;
+                    for (int k = 2 * J - 1; k >= 0; --k) {
+                        sp *= sw;
+                        f = f * cw + G[k] * sp;
+                    }
+                    acc += f * sbp[jM] * val[jM];
+                }
+                out[iM] += base * acc / sap[iM];
+            }
+        }
+    }
+    double *y = Y + (long long)req * pd->N + C.off + p;
+#pragma unroll
+    for (int iM = 0; iM < NM; ++iM) y[(long long)iM * C.npts] += out[iM];
 }
 
 // ---------------------------------------------------------------------------
@@ -219,14 +492,14 @@ __global__ void __launch_bounds__(256) k_matvec(ProblemDev pd, const double *__r
 // (request, alpha, M') and p in [0, nx*ny).  64 columns per block staged in LDS.
 constexpr int MZ_COLS = 64;
 
-__global__ void __launch_bounds__(MZ_COLS) k_modez(ProblemDev pd, PrecDev pr, const int *__restrict__ active,
+__global__ void __launch_bounds__(MZ_COLS) k_modez(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr, const int *__restrict__ active,
                                                    int which, const double *in, double *out) {
     const int req = blockIdx.z;
     if (active && !active[req]) return;
     const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
-    if (iM >= pd.nM) return;
-    const CompDev &C = pd.comp[a];
-    const PrecCompDev &F = pr.comp[a];
+    if (iM >= pd->nM) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
     const int nz = C.z.n, nxy = C.nxy;
     const int col0 = blockIdx.x * MZ_COLS;
     if (col0 >= nxy) return;
@@ -235,7 +508,7 @@ __global__ void __launch_bounds__(MZ_COLS) k_modez(ProblemDev pd, PrecDev pr, co
     double *T = sm + nz * nz;        // nz*MZ_COLS
     const double *Wg = F.Wz + ((size_t)iM * 2 + which) * nz * nz;
     for (int t = threadIdx.x; t < nz * nz; t += MZ_COLS) W[t] = Wg[t];
-    const long long base = (long long)req * pd.N + C.off + (long long)iM * C.npts;
+    const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts;
     const int col = col0 + threadIdx.x;
     const bool ok = col < nxy;
     for (int k = 0; k < nz; ++k) T[k * MZ_COLS + threadIdx.x] = ok ? in[base + (long long)k * nxy + col] : 0.0;
@@ -306,35 +579,14 @@ __device__ void right_mult_t(double *T, const double *__restrict__ Wm, int nx, i
     }
 }
 
-__device__ void solve4(double M[4][4], double *b) {
-    for (int k = 0; k < 4; ++k) {
-        int p = k;
-        for (int i = k + 1; i < 4; ++i)
-            if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
-        if (p != k) {
-            for (int j = 0; j < 4; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
-            double t = b[k]; b[k] = b[p]; b[p] = t;
-        }
-        for (int i = k + 1; i < 4; ++i) {
-            double l = M[i][k] / M[k][k];
-            for (int j = k; j < 4; ++j) M[i][j] -= l * M[k][j];
-            b[i] -= l * b[k];
-        }
-    }
-    for (int i = 3; i >= 0; --i) {
-        double s = b[i];
-        for (int j = i + 1; j < 4; ++j) s -= M[i][j] * b[j];
-        b[i] = s / M[i][i];
-    }
-}
-
 // (Lambda_x (x) I + I (x) Lambda_y - E) T' = T on the quasi-diagonal blocks.
-__device__ void block_divide(double *T, int nx, int ny, const double *lx, const double *lxi, const signed char *tx,
-                             const double *ly, const double *lyi, const signed char *ty, double E,
-                             double *min_den) {
+__device__ void block_divide(double *T, int ld, int nx, int ny, const double *lx, const double *lxi,
+                             const signed char *tx, const double *ly, const double *lyi, const signed char *ty,
+                             double E, double *min_den) {
     double mind = 1e300;
-    for (int o = threadIdx.x; o < nx * ny; o += XY_THREADS) {
-        const int i = o / ny, j = o % ny;
+    for (int oo = threadIdx.x; oo < nx * ny; oo += XY_THREADS) {
+        const int i = oo / ny, j = oo % ny;
+        const int o = i * ld + j;
         const int ti = tx[i], tj = ty[j];
         if (ti == 2 || tj == 2) continue;        // handled by the anchor of its block
         const double d = lx[i] + ly[j] - E;
@@ -342,9 +594,9 @@ __device__ void block_divide(double *T, int nx, int ny, const double *lx, const 
             T[o] /= d;
             mind = fmin(mind, fabs(d));
         } else if (ti == 1 && tj == 0) {
-            const double b = lxi[i], r0 = T[o], r1 = T[o + ny], det = d * d + b * b;
+            const double b = lxi[i], r0 = T[o], r1 = T[o + ld], det = d * d + b * b;
             T[o] = (d * r0 - b * r1) / det;
-            T[o + ny] = (b * r0 + d * r1) / det;
+            T[o + ld] = (b * r0 + d * r1) / det;
             mind = fmin(mind, sqrt(det));
         } else if (ti == 0 && tj == 1) {
             const double b = lyi[j], r0 = T[o], r1 = T[o + 1], det = d * d + b * b;
@@ -352,12 +604,22 @@ __device__ void block_divide(double *T, int nx, int ny, const double *lx, const 
             T[o + 1] = (b * r0 + d * r1) / det;
             mind = fmin(mind, sqrt(det));
         } else {
+            // Both indices in complex pairs: the x and y 2x2 blocks act as two
+            // commuting complex structures J1, J2; the 4x4 system splits on the
+            // eigenspaces of J1 J2 into two complex divisions by
+            // d + i (bx - by) and d + i (bx + by).
             const double bx = lxi[i], by = lyi[j];
-            double M[4][4] = {{d, by, bx, 0.0}, {-by, d, 0.0, bx}, {-bx, 0.0, d, by}, {0.0, -bx, -by, d}};
-            double r[4] = {T[o], T[o + 1], T[o + ny], T[o + ny + 1]};
-            solve4(M, r);
-            T[o] = r[0]; T[o + 1] = r[1]; T[o + ny] = r[2]; T[o + ny + 1] = r[3];
-            mind = fmin(mind, sqrt(d * d + (fabs(bx) - fabs(by)) * (fabs(bx) - fabs(by))));
+            const double r00 = T[o], r01 = T[o + 1], r10 = T[o + ld], r11 = T[o + ld + 1];
+            const double p00 = 0.5 * (r00 + r11), p01 = 0.5 * (r01 - r10);   // (1 + J1 J2) R / 2
+            const double m00 = 0.5 * (r00 - r11), m01 = 0.5 * (r01 + r10);   // (1 - J1 J2) R / 2
+            const double bp = bx - by, bm = bx + by;
+            const double Dp = d * d + bp * bp, Dm = d * d + bm * bm;
+            // rows of P+R: (p00, p01), (-p01, p00); of P-R: (m00, m01), (m01, -m00)
+            T[o] = (d * p00 + bp * p01) / Dp + (d * m00 - bm * m01) / Dm;
+            T[o + 1] = (d * p01 - bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
+            T[o + ld] = (-d * p01 + bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
+            T[o + ld + 1] = (d * p00 + bp * p01) / Dp + (-d * m00 + bm * m01) / Dm;
+            mind = fmin(mind, sqrt(fmin(Dp, Dm)));
         }
     }
     if (min_den) {
@@ -375,20 +637,20 @@ __device__ void block_divide(double *T, int nx, int ny, const double *lx, const 
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(XY_THREADS) k_xy(ProblemDev pd, PrecDev pr, const double *__restrict__ Evec,
+__global__ void __launch_bounds__(XY_THREADS) k_xy(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr, const double *__restrict__ Evec,
                                                    const int *__restrict__ active, double *data,
                                                    double *min_den) {
     const int req = blockIdx.z;
     if (active && !active[req]) return;
     const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
-    if (iM >= pd.nM) return;
-    const CompDev &C = pd.comp[a];
-    const PrecCompDev &F = pr.comp[a];
+    if (iM >= pd->nM) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
     const int k = blockIdx.x;
     const int nz = C.z.n, nx = C.x.n, ny = C.y.n;
     if (k >= nz) return;
     extern __shared__ double T[];
-    double *g = data + (long long)req * pd.N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
     for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) T[t] = g[t];
     __syncthreads();
     const size_t fx = (size_t)iM * nz + k;
@@ -396,7 +658,7 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy(ProblemDev pd, PrecDev pr, co
     const double *Wby = F.Wy + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
     left_mult(T, Wbx, nx, ny);
     right_mult_t(T, Wby, nx, ny);
-    block_divide(T, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
+    block_divide(T, ny, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
                  F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
     left_mult(T, Wx, nx, ny);
     right_mult_t(T, Wy, nx, ny);
@@ -404,18 +666,112 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy(ProblemDev pd, PrecDev pr, co
 }
 
 // ---------------------------------------------------------------------------
+// Preconditioner x-y slice on FP64 MFMA (v_mfma_f64_16x16x4f64).  The slice is
+// held in LDS zero-padded to multiples of 16 (row stride ld); each of the 4
+// waves accumulates its 16x16 output tiles in registers over the whole K
+// range, then, after a barrier, writes them back in place.
+// Operand layout of the 16x16x4 FP64 MFMA: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it receives D[4*(l/16)+v][l%16], v = 0..3.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int XYM_MAXT = 16;        // tiles per wave: (128/16)^2 / 4
+
+// T <- Wm T (LEFT, Wm: nx x nx) or T <- T Wm^T (!LEFT, Wm: ny x ny); at most
+// MAXT output tiles per wave.
+template <bool LEFT, int MAXT>
+__device__ void mfma_slice_mult(double *T, int ld, int nxp, int nyp, const double *__restrict__ Wm, int nw) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int tcols = nyp >> 4, ntiles = (nxp >> 4) * tcols;
+    const int K = LEFT ? nxp : nyp;
+    dbl4 acc[MAXT];
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + k4;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            const int t = wave + 4 * q;
+            if (t < ntiles) {
+                const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
+                double a, b;
+                if (LEFT) {
+                    const int row = i0 + r16;
+                    a = (row < nw && kk < nw) ? Wm[(size_t)row * nw + kk] : 0.0;
+                    b = T[kk * ld + j0 + r16];
+                } else {
+                    const int col = j0 + r16;
+                    a = T[(i0 + r16) * ld + kk];
+                    b = (col < nw && kk < nw) ? Wm[(size_t)col * nw + kk] : 0.0;
+                }
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+        const int t = wave + 4 * q;
+        if (t < ntiles) {
+            const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[(i0 + 4 * k4 + v) * ld + j0 + r16] = acc[q][v];
+        }
+    }
+    __syncthreads();
+}
+
+template <int MAXT>
+__global__ void __launch_bounds__(XY_THREADS) k_xy_mfma(const ProblemDev *__restrict__ pd,
+                                                        const PrecDev *__restrict__ pr,
+                                                        const double *__restrict__ Evec,
+                                                        const int *__restrict__ active, double *data,
+                                                        double *min_den) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
+    if (iM >= pd->nM) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int k = blockIdx.x;
+    const int nz = C.z.n, nx = C.x.n, ny = C.y.n;
+    if (k >= nz) return;
+    const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, ld = nyp + 4;
+    extern __shared__ double T[];
+    double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    for (int t = threadIdx.x; t < nxp * ld; t += XY_THREADS) {
+        const int i = t / ld, j = t % ld;
+        T[t] = (i < nx && j < ny) ? g[i * ny + j] : 0.0;
+    }
+    __syncthreads();
+    const size_t fx = (size_t)iM * nz + k;
+    const double *Wbx = F.Wx + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
+    const double *Wby = F.Wy + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
+    mfma_slice_mult<true, MAXT>(T, ld, nxp, nyp, Wbx, nx);
+    mfma_slice_mult<false, MAXT>(T, ld, nxp, nyp, Wby, ny);
+    block_divide(T, ld, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
+                 F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
+    mfma_slice_mult<true, MAXT>(T, ld, nxp, nyp, Wx, nx);
+    mfma_slice_mult<false, MAXT>(T, ld, nxp, nyp, Wy, ny);
+    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) g[t] = T[(t / ny) * ld + t % ny];
+}
+
+// ---------------------------------------------------------------------------
 // GMRES pieces.  V is stored [i][request][N]; Z likewise.
 constexpr int RT = 256;              // threads of the reduction kernels
-constexpr int MD_G = 8;              // vectors per group in the multi-dot
+constexpr int MD_G = 16;             // vectors per group in the multi-dot
 
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block (RT threads); the result is valid in every thread.
 __device__ __forceinline__ double block_sum(double v, double *red) {
-    red[threadIdx.x] = v;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = RT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = red[0];
+    double r = 0;
+    for (int wv = 0; wv < RT / 64; ++wv) r += red[wv];
     __syncthreads();
     return r;
 }
@@ -435,36 +791,59 @@ __device__ __forceinline__ bool last_block(unsigned *ticket, unsigned total) {
 }
 
 __device__ __forceinline__ void chunk_range(long long N, int blk, long long &lo, long long &hi) {
-    long long per = (N + NBLK - 1) / NBLK;
+    long long per = (N + gridDim.x - 1) / gridDim.x;
     lo = blk * per;
     hi = min(N, lo + per);
 }
 
 // hproj[i] = v_i . w for i <= j; hcol = hproj (accumulate = 0) or hcol += hproj.
+// Grid: (blocks per request, groups of MD_G vectors, requests).  Each thread
+// keeps MD_G partial sums; one wave-level and one cross-wave reduction per block.
 __global__ void __launch_bounds__(RT) k_mdot(KrylovDev K, int j, const double *__restrict__ W, int accumulate) {
     const int req = blockIdx.z;
     if (!K.active[req]) return;
-    __shared__ double red[RT];
+    __shared__ double red[MD_G][RT / 64];
     const int g0 = blockIdx.y * MD_G;
     const int ng = min(MD_G, j + 1 - g0);
-    long long lo, hi;
-    chunk_range(K.N, blockIdx.x, lo, hi);
+    const int nblk = gridDim.x;
+    const long long per = (K.N + nblk - 1) / nblk;
+    const long long lo = blockIdx.x * per, hi = min(K.N, lo + per);
     const double *w = W + (long long)req * K.N;
+    const long long vstride = (long long)K.nb * K.N;
+    const double *v0 = K.V + (long long)g0 * vstride + (long long)req * K.N;
     double acc[MD_G];
+#pragma unroll
     for (int t = 0; t < MD_G; ++t) acc[t] = 0;
-    for (long long e = lo + threadIdx.x; e < hi; e += RT) {
-        double we = w[e];
-        for (int t = 0; t < ng; ++t) acc[t] += K.V[((long long)(g0 + t) * K.nb + req) * K.N + e] * we;
+    long long e = lo + threadIdx.x;
+    for (; e + RT < hi; e += 2 * RT) {
+        const double we0 = w[e], we1 = w[e + RT];
+#pragma unroll
+        for (int t = 0; t < MD_G; ++t)
+            if (t < ng) acc[t] += v0[t * vstride + e] * we0 + v0[t * vstride + e + RT] * we1;
     }
+    if (e < hi) {
+        const double we = w[e];
+#pragma unroll
+        for (int t = 0; t < MD_G; ++t)
+            if (t < ng) acc[t] += v0[t * vstride + e] * we;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < MD_G; ++t) {
+        double s = wave_sum(acc[t]);
+        if (lane == 0) red[t][wave] = s;
+    }
+    __syncthreads();
     double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
-    for (int t = 0; t < ng; ++t) {
-        double s = block_sum(acc[t], red);
-        if (threadIdx.x == 0) part[(size_t)(g0 + t) * NBLK + blockIdx.x] = s;
+    if (threadIdx.x < ng) {
+        double s = 0;
+        for (int wv = 0; wv < RT / 64; ++wv) s += red[threadIdx.x][wv];
+        part[(size_t)(g0 + threadIdx.x) * NBLK + blockIdx.x] = s;
     }
-    if (last_block(&K.ticket[req], NBLK * gridDim.y)) {
+    if (last_block(&K.ticket[req], nblk * gridDim.y)) {
         for (int i = threadIdx.x; i <= j; i += RT) {
             double s = 0;
-            for (int b = 0; b < NBLK; ++b) s += part[(size_t)i * NBLK + b];
+            for (int b = 0; b < nblk; ++b) s += part[(size_t)i * NBLK + b];
             K.hproj[(size_t)req * (K.m + 1) + i] = s;
             double *hc = K.hcol + (size_t)req * (K.m + 1) + i;
             *hc = accumulate ? *hc + s : s;
@@ -501,10 +880,10 @@ __global__ void __launch_bounds__(RT) k_norm_givens(KrylovDev K, int j, const do
     double s = block_sum(acc, red);
     double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(&K.ticket[req], NBLK)) {
+    if (last_block(&K.ticket[req], gridDim.x)) {
         if (threadIdx.x == 0) {
             double nn = 0;
-            for (int b = 0; b < NBLK; ++b) nn += part[b];
+            for (int b = 0; b < (int)gridDim.x; ++b) nn += part[b];
             double hn = sqrt(nn);
             const int m = K.m;
             double *hc = K.hcol + (size_t)req * (m + 1);
@@ -593,10 +972,10 @@ __global__ void __launch_bounds__(RT) k_residual(KrylovDev K, int *running, cons
     double s = block_sum(acc, red);
     double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(&K.ticket[req], NBLK)) {
+    if (last_block(&K.ticket[req], gridDim.x)) {
         if (threadIdx.x == 0) {
             double nn = 0;
-            for (int bb = 0; bb < NBLK; ++bb) nn += part[bb];
+            for (int bb = 0; bb < (int)gridDim.x; ++bb) nn += part[bb];
             double rn = sqrt(nn);
             K.rnorm[req] = rn;
             K.scal[req] = rn;
@@ -654,10 +1033,10 @@ __global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restr
         part[blockIdx.x] = s;
         if (anybad) atomicOr(&K.flags[req], 1);
     }
-    if (last_block(&K.ticket[req], NBLK)) {
+    if (last_block(&K.ticket[req], gridDim.x)) {
         if (threadIdx.x == 0) {
             double nn = 0;
-            for (int bb = 0; bb < NBLK; ++bb) nn += part[bb];
+            for (int bb = 0; bb < (int)gridDim.x; ++bb) nn += part[bb];
             K.bnorm[req] = sqrt(nn);
             K.ticket[req] = 0;
         }
@@ -681,11 +1060,46 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 // ---------------------------------------------------------------------------
 // Launchers.
 
+template <int QXY, int QZ, int NM>
+void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
+                  hipStream_t st, int part) {
+    if (part != 2) {
+        const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
+        hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
+                           sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y);
+    }
+    if (part != 1) {
+        const long long pts = pd.comp[0].npts + pd.comp[1].npts + pd.comp[2].npts;
+        hipLaunchKernelGGL((k_coupling<QXY, QXY, QZ, NM>), dim3(cdiv(pts, 256), nb), dim3(256),
+                           sizeof(double) * pd.nodes_total, st, pd.dev, active, x, y);
+    }
+}
+
+bool matvec_tiled_ok(const ProblemDev &pd) {
+    const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
+    const size_t sh = sizeof(double) * std::max(pd.nodes_total, pd.tile_lds);
+    return same_xy && pd.q[2] != 0 && pd.nM <= 3 && sh <= 64 * 1024;
+}
+
 void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
-                   hipStream_t st) {
+                   hipStream_t st, int part) {
+    if (matvec_tiled_ok(pd)) {
+        const int key = (pd.q[0] == 3 ? 4 : 0) + (pd.q[2] == 3 ? 2 : 0);
+        switch (key * 4 + pd.nM) {
+#define FM_TILED(QXY, QZ, NM) \
+    case ((QXY == 3 ? 4 : 0) + (QZ == 3 ? 2 : 0)) * 4 + NM: launch_tiled<QXY, QZ, NM>(pd, nb, E_dev, active, x, y, st, part); return;
+            FM_TILED(3, 3, 1) FM_TILED(3, 3, 2) FM_TILED(3, 3, 3)
+            FM_TILED(3, 2, 1) FM_TILED(3, 2, 2) FM_TILED(3, 2, 3)
+            FM_TILED(2, 3, 1) FM_TILED(2, 3, 2) FM_TILED(2, 3, 3)
+            FM_TILED(2, 2, 1) FM_TILED(2, 2, 2) FM_TILED(2, 2, 3)
+#undef FM_TILED
+            default: break;
+        }
+    }
+    if (part == 2) return;            // the generic kernel computes the coupling with the rest
     long long pts = pd.comp[0].npts + pd.comp[1].npts + pd.comp[2].npts;
     dim3 grid(cdiv(pts, 256), nb);
-    hipLaunchKernelGGL(k_matvec, grid, dim3(256), 0, st, pd, E_dev, active, x, y);
+    hipLaunchKernelGGL(k_matvec, grid, dim3(256), 0, st, pd.dev, E_dev, active, x, y);
 }
 
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
@@ -697,7 +1111,7 @@ void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *ac
     }
     dim3 grid(cdiv(maxnxy, MZ_COLS), 3 * MAXM, nb);
     size_t sh = sizeof(double) * (maxnz * maxnz + maxnz * MZ_COLS);
-    hipLaunchKernelGGL(k_modez, grid, dim3(MZ_COLS), sh, st, pd, pr, active, which, in, out);
+    hipLaunchKernelGGL(k_modez, grid, dim3(MZ_COLS), sh, st, pd.dev, pr.dev, active, which, in, out);
 }
 
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
@@ -708,12 +1122,34 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         maxn = std::max(maxn, pd.comp[a].nxy);
     }
     dim3 grid(maxnz, 3 * MAXM, nb);
+    size_t shm = 0;
+    int tpw = 0;                      // output tiles per wave
+    for (int a = 0; a < 3; ++a) {
+        const int nxp = (pd.comp[a].x.n + 15) & ~15, nyp = (pd.comp[a].y.n + 15) & ~15;
+        shm = std::max(shm, sizeof(double) * nxp * (nyp + 4));
+        tpw = std::max(tpw, ((nxp / 16) * (nyp / 16) + 3) / 4);
+    }
+    if (tpw <= XYM_MAXT && shm <= xy_lds_limit()) {
+#define FM_XYM(T) hipLaunchKernelGGL(k_xy_mfma<T>, grid, dim3(XY_THREADS), shm, st, pd.dev, pr.dev, E_dev, active, data, min_den)
+        if (tpw <= 1) FM_XYM(1);
+        else if (tpw <= 2) FM_XYM(2);
+        else if (tpw <= 4) FM_XYM(4);
+        else if (tpw <= 8) FM_XYM(8);
+        else if (tpw <= 12) FM_XYM(12);
+        else FM_XYM(16);
+#undef FM_XYM
+        return;
+    }
     size_t sh = sizeof(double) * maxn;
-    hipLaunchKernelGGL(k_xy, grid, dim3(XY_THREADS), sh, st, pd, pr, E_dev, active, data, min_den);
+    hipLaunchKernelGGL(k_xy, grid, dim3(XY_THREADS), sh, st, pd.dev, pr.dev, E_dev, active, data, min_den);
 }
 
 void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st) {
-    dim3 grid(NBLK, cdiv(j + 1, MD_G), k.nb);
+    // about 2048 blocks in flight, at most 64 elements per thread, at most NBLK per request
+    const long long groups = cdiv(j + 1, MD_G);
+    long long nblk = std::max<long long>(cdiv(2048, (long long)k.nb * groups), cdiv(k.N, (long long)RT * 64));
+    nblk = std::max<long long>(1, std::min<long long>(NBLK, nblk));
+    dim3 grid((unsigned)nblk, (unsigned)groups, k.nb);
     hipLaunchKernelGGL(k_mdot, grid, dim3(RT), 0, st, k, j, w, accumulate);
 }
 
@@ -722,8 +1158,13 @@ void launch_mupdate(const KrylovDev &k, int j, double *w, hipStream_t st) {
     hipLaunchKernelGGL(k_mupdate, grid, dim3(RT), 0, st, k, j, w);
 }
 
+unsigned reduce_blocks(const KrylovDev &k) {
+    long long nblk = std::max<long long>(cdiv(1024, k.nb), cdiv(k.N, (long long)RT * 16));
+    return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
+}
+
 void launch_norm_givens(const KrylovDev &k, int j, double *w, hipStream_t st) {
-    dim3 grid(NBLK, k.nb);
+    dim3 grid(reduce_blocks(k), k.nb);
     hipLaunchKernelGGL(k_norm_givens, grid, dim3(RT), 0, st, k, j, w);
 }
 
@@ -743,7 +1184,7 @@ void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream
 
 void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,
                      hipStream_t st) {
-    dim3 grid(NBLK, k.nb);
+    dim3 grid(reduce_blocks(k), k.nb);
     hipLaunchKernelGGL(k_residual, grid, dim3(RT), 0, st, k, running, b, rtol, inner_safety);
 }
 
@@ -753,13 +1194,22 @@ void launch_scale0(const KrylovDev &k, hipStream_t st) {
 }
 
 void launch_bnorm(const KrylovDev &k, const double *b, hipStream_t st) {
-    dim3 grid(NBLK, k.nb);
+    dim3 grid(reduce_blocks(k), k.nb);
     hipLaunchKernelGGL(k_bnorm, grid, dim3(RT), 0, st, k, b);
 }
 
+size_t g_lds_limit = 65536;
+
+size_t xy_lds_limit() { return g_lds_limit; }
+
 void prepare_large_lds(size_t bytes) {
+    if (bytes > g_lds_limit) g_lds_limit = bytes;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_xy), hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(bytes));
+    const void *fns[] = {reinterpret_cast<const void *>(k_xy_mfma<1>), reinterpret_cast<const void *>(k_xy_mfma<2>),
+                         reinterpret_cast<const void *>(k_xy_mfma<4>), reinterpret_cast<const void *>(k_xy_mfma<8>),
+                         reinterpret_cast<const void *>(k_xy_mfma<12>), reinterpret_cast<const void *>(k_xy_mfma<16>)};
+    for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t st) {

@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "FM_OK", -1: "FM_E_INVALID", -2: "FM_E_NOMEM", -3: "FM_E_HIP"
                 -5: "FM_E_BREAKDOWN", -6: "FM_E_PENCIL", -7: "FM_E_NONFINITE", -8: "FM_E_REJECTED",
                 -9: "FM_E_BUSY"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+KERNEL_CLASSES = ["matvec", "modez", "xy", "mdot", "mupdate", "norm", "scale", "restart", "coupling"]
 MAPS = {"uniform": 0, "quadratic": 1, "pow": 2, "sin": 3}
 
 
@@ -71,8 +72,10 @@ def lib():
         L.fm_apply_operator.argtypes = [vp, ci, pd, vp, vp, vp]
         L.fm_apply_precond.argtypes = [vp, ci, pd, vp, vp, ci, vp]
         L.fm_solve.argtypes = [vp, ci, pd, vp, vp, ctypes.POINTER(FmSolveOpts), ctypes.POINTER(FmSolveResult), vp]
+        L.fm_profile.argtypes = [vp, ci]
+        L.fm_profile_read.argtypes = [vp, ci, pd, ctypes.POINTER(ctypes.c_longlong), pd, pd]
         for f in ("fm_create_problem", "fm_destroy_problem", "fm_problem_info", "fm_apply_operator",
-                  "fm_apply_precond", "fm_solve"):
+                  "fm_apply_precond", "fm_solve", "fm_profile", "fm_profile_read"):
             getattr(L, f).restype = ci
         _lib = L
     return _lib
@@ -163,6 +166,20 @@ class Problem:
         _check(lib().fm_apply_precond(self._h, nb, Ec, _ptr(r, nb * self.N, "r"), _ptr(z, nb * self.N, "z"),
                                       PRECISIONS[prec], _stream(stream)))
         return z
+
+    def profile(self, enable=True):
+        """Enable (and reset) or disable per-kernel-class timing."""
+        _check(lib().fm_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{class: {"ms", "launches", "bytes", "flops"}} accumulated since profile(True)."""
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            ms, n, by, fl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+            _check(lib().fm_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by),
+                                         ctypes.byref(fl)))
+            out[name] = {"ms": ms.value, "launches": n.value, "bytes": by.value, "flops": fl.value}
+        return out
 
     def solve(self, E, b, x, restart=30, rtol=1e-10, max_iters=2000, prec="fp64", x0_is_guess=False,
               stream=None, raise_on_error=True):
