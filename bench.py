@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--restart", type=int, default=300)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the reduced-precision comparison runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
@@ -160,6 +161,31 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    if not args.no_mixed:
+        # the same workload with the preconditioner's products in FP32 / BF16x3 MFMA; FP64 Arnoldi,
+        # residual and divide; error of each solution against the FP64 GPU solution
+        X64 = X.clone()
+        mixed = {}
+        for prec in ("fp32", "bf16x3"):
+            def step_lp():
+                st, res = P.solve(Es, B, X, restart=args.restart, rtol=1e-10, max_iters=20000, prec=prec,
+                                  stream=stream)
+                if st != fm.FM_OK:
+                    raise RuntimeError(f"solve failed: {fm.STATUS_NAMES.get(st)} {res}")
+                return res
+            step_lp()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                res_lp = step_lp()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            err = (torch.linalg.norm(X - X64, dim=1) / torch.linalg.norm(X64, dim=1)).max().item()
+            mixed[prec] = {"solves_per_s": nreq * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                           "iters_mean": float(np.mean([r["iters"] for r in res_lp])),
+                           "max_rel_residual": max(r["rel_residual"] for r in res_lp),
+                           "max_rel_error_vs_fp64_gpu": err}
+        line["mixed_precision"] = mixed
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))

@@ -89,6 +89,19 @@ struct Busy {
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// bfloat16 round to nearest even, and back
+unsigned short bf16_rne(float f) {
+    unsigned u;
+    std::memcpy(&u, &f, 4);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+float bf16_value(unsigned short h) {
+    unsigned u = unsigned(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
 // Small per-call device arrays: energies, flags, minimum denominators.
 struct Small {
     double *E, *min_den;
@@ -279,7 +292,14 @@ void add_step_work(fm_problem *p, const Work &w, int j) {
 
 void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
                    int prec, double *min_den, hipStream_t st) {
-    (void)prec;
+    if (prec != FM_FP64) {
+        bool ok = true;
+        timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 0, in, out, st); });
+        timed(p, st, FM_K_XY, [&] { ok = launch_xy_lp(p->pd, p->pr, nb, E_dev, mask, out, prec, st); });
+        if (!ok) timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st); });
+        timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 1, out, out, st); });
+        return;
+    }
     timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 0, in, out, st); });
     timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st); });
     timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 1, out, out, st); });
@@ -359,6 +379,23 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         F.lyi = put(p, h.lyi, err);
         F.tx = put(p, h.tx, err);
         F.ty = put(p, h.ty, err);
+        // FP32 copies and bfloat16 (hi, mid) planes of the factors
+        auto to32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
+        auto to16 = [](const std::vector<double> &v) {
+            std::vector<unsigned short> o(2 * v.size());
+            for (size_t i = 0; i < v.size(); ++i) {
+                float f = float(v[i]);
+                unsigned short hi = bf16_rne(f);
+                o[i] = hi;
+                o[v.size() + i] = bf16_rne(f - bf16_value(hi));
+            }
+            return o;
+        };
+        F.Wz32 = put(p, to32(h.Wz), err);
+        F.Wx32 = put(p, to32(h.Wx), err);
+        F.Wy32 = put(p, to32(h.Wy), err);
+        F.Wx16 = put(p, to16(h.Wx), err);
+        F.Wy16 = put(p, to16(h.Wy), err);
         if (!err.empty()) return err;
     }
     // device copies of the two descriptors

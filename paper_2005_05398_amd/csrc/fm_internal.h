@@ -101,7 +101,7 @@ struct PrecCompDev {
     const double *ly, *lyi;      // [nM][nz][ny]
     const signed char *tx, *ty;  // [nM][nz][nx], [nM][nz][ny]
     const float *Wz32, *Wx32, *Wy32;          // FP32 copies
-    const uint16_t *Wx16, *Wy16, *Wz16;       // BF16 hi/mid/lo triples (3 planes)
+    const unsigned short *Wx16, *Wy16;        // BF16 planes [hi | mid], each laid out as Wx / Wy
 };
 
 struct PrecDev {
@@ -143,6 +143,11 @@ void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *ac
                   const double *in, double *out, hipStream_t st);
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
                double *data, double *min_den, hipStream_t st);
+// reduced-precision products (mode 1: FP32 MFMA, 2: BF16x3 MFMA); false if the slice does not fit
+void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
+                     const double *in, double *out, hipStream_t st);
+bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
+                  double *data, int mode, hipStream_t st);
 // Arnoldi / GMRES pieces (V and Z stored [i][request][N])
 void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st);
 void launch_mupdate(const KrylovDev &k, int j, double *w, hipStream_t st);

@@ -756,6 +756,241 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy_mfma(const ProblemDev *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Reduced-precision preconditioner products (the divide stays FP64).
+//   MODE 1: FP32 MFMA v_mfma_f32_16x16x4f32 (lane layout as the FP64 one).
+//   MODE 2: BF16x3: each operand a = a_hi + a_mid (+ a_lo) in bfloat16, the
+//           product taken as a_hi b_hi + a_hi b_mid + a_mid b_hi with FP32
+//           accumulation (Henry, Tang, Heinecke, ARITH 2019), on
+//           v_mfma_f32_16x16x16bf16_1k: lane l supplies A[l%16][4(l/16)+0..3]
+//           and B[4(l/16)+0..3][l%16]; D as above.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short sht4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {   // round to nearest even
+    const unsigned u = __float_as_uint(f);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+__device__ __forceinline__ void split_bf16(float a, short &hi, short &mid) {
+    const unsigned short h = f32_to_bf16(a);
+    hi = (short)h;
+    mid = (short)f32_to_bf16(a - bf16_to_f32(h));
+}
+
+template <bool LEFT, int MAXT>
+__device__ void mfma32_slice_mult(float *T, int ld, int nxp, int nyp, const float *__restrict__ Wm, int nw) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int tcols = nyp >> 4, ntiles = (nxp >> 4) * tcols;
+    const int K = LEFT ? nxp : nyp;
+    flt4 acc[MAXT];
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) acc[q] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + k4;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            const int t = wave + 4 * q;
+            if (t < ntiles) {
+                const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
+                float a, b;
+                if (LEFT) {
+                    const int row = i0 + r16;
+                    a = (row < nw && kk < nw) ? Wm[(size_t)row * nw + kk] : 0.f;
+                    b = T[kk * ld + j0 + r16];
+                } else {
+                    const int col = j0 + r16;
+                    a = T[(i0 + r16) * ld + kk];
+                    b = (col < nw && kk < nw) ? Wm[(size_t)col * nw + kk] : 0.f;
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+        const int t = wave + 4 * q;
+        if (t < ntiles) {
+            const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[(i0 + 4 * k4 + v) * ld + j0 + r16] = acc[q][v];
+        }
+    }
+    __syncthreads();
+}
+
+// W16: bfloat16 planes of Wm, [0] = hi, [1] = mid (plane stride pstride).
+template <bool LEFT, int MAXT>
+__device__ void mfma_bf3_slice_mult(float *T, int ld, int nxp, int nyp, const unsigned short *__restrict__ W16,
+                                    size_t pstride, int nw) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
+    const int tcols = nyp >> 4, ntiles = (nxp >> 4) * tcols;
+    const int K = LEFT ? nxp : nyp;
+    flt4 acc[MAXT];
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) acc[q] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int kk = k0 + g4;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            const int t = wave + 4 * q;
+            if (t < ntiles) {
+                const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
+                sht4 dhi, dmid, whi, wmid;       // data and factor operands
+                const int wrow = LEFT ? i0 + r16 : j0 + r16;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int kc = kk + e;
+                    const bool ok = wrow < nw && kc < nw;
+                    whi[e] = ok ? (short)W16[(size_t)wrow * nw + kc] : (short)0;
+                    wmid[e] = ok ? (short)W16[pstride + (size_t)wrow * nw + kc] : (short)0;
+                    const float dv = LEFT ? T[kc * ld + j0 + r16] : T[(i0 + r16) * ld + kc];
+                    short h, m;
+                    split_bf16(dv, h, m);
+                    dhi[e] = h;
+                    dmid[e] = m;
+                }
+                if (LEFT) {      // A = W, B = T
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wmid, dhi, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(whi, dmid, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(whi, dhi, acc[q], 0, 0, 0);
+                } else {         // A = T, B = W^T
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dmid, whi, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dhi, wmid, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dhi, whi, acc[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+        const int t = wave + 4 * q;
+        if (t < ntiles) {
+            const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[(i0 + 4 * (lane >> 4) + v) * ld + j0 + r16] = acc[q][v];
+        }
+    }
+    __syncthreads();
+}
+
+// The FP64 block divide on an FP32 slice: values are widened, divided, narrowed.
+__device__ void block_divide_f32(float *T, int ld, int nx, int ny, const double *lx, const double *lxi,
+                                 const signed char *tx, const double *ly, const double *lyi, const signed char *ty,
+                                 double E) {
+    for (int oo = threadIdx.x; oo < nx * ny; oo += XY_THREADS) {
+        const int i = oo / ny, j = oo % ny;
+        const int o = i * ld + j;
+        const int ti = tx[i], tj = ty[j];
+        if (ti == 2 || tj == 2) continue;
+        const double d = lx[i] + ly[j] - E;
+        if (ti == 0 && tj == 0) {
+            T[o] = (float)((double)T[o] / d);
+        } else if (ti == 1 && tj == 0) {
+            const double b = lxi[i], r0 = T[o], r1 = T[o + ld], det = d * d + b * b;
+            T[o] = (float)((d * r0 - b * r1) / det);
+            T[o + ld] = (float)((b * r0 + d * r1) / det);
+        } else if (ti == 0 && tj == 1) {
+            const double b = lyi[j], r0 = T[o], r1 = T[o + 1], det = d * d + b * b;
+            T[o] = (float)((d * r0 - b * r1) / det);
+            T[o + 1] = (float)((b * r0 + d * r1) / det);
+        } else {
+            const double bx = lxi[i], by = lyi[j];
+            const double r00 = T[o], r01 = T[o + 1], r10 = T[o + ld], r11 = T[o + ld + 1];
+            const double p00 = 0.5 * (r00 + r11), p01 = 0.5 * (r01 - r10);
+            const double m00 = 0.5 * (r00 - r11), m01 = 0.5 * (r01 + r10);
+            const double bp = bx - by, bm = bx + by;
+            const double Dp = d * d + bp * bp, Dm = d * d + bm * bm;
+            T[o] = (float)((d * p00 + bp * p01) / Dp + (d * m00 - bm * m01) / Dm);
+            T[o + 1] = (float)((d * p01 - bp * p00) / Dp + (d * m01 + bm * m00) / Dm);
+            T[o + ld] = (float)((-d * p01 + bp * p00) / Dp + (d * m01 + bm * m00) / Dm);
+            T[o + ld + 1] = (float)((d * p00 + bp * p01) / Dp + (-d * m00 + bm * m01) / Dm);
+        }
+    }
+    __syncthreads();
+}
+
+template <int MAXT, int MODE>
+__global__ void __launch_bounds__(XY_THREADS) k_xy_lp(const ProblemDev *__restrict__ pd,
+                                                      const PrecDev *__restrict__ pr,
+                                                      const double *__restrict__ Evec,
+                                                      const int *__restrict__ active, double *data) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
+    if (iM >= pd->nM) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int k = blockIdx.x;
+    const int nz = C.z.n, nx = C.x.n, ny = C.y.n;
+    if (k >= nz) return;
+    const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, ld = nyp + 4;
+    extern __shared__ float Tf[];
+    double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    for (int t = threadIdx.x; t < nxp * ld; t += XY_THREADS) {
+        const int i = t / ld, j = t % ld;
+        Tf[t] = (i < nx && j < ny) ? (float)g[i * ny + j] : 0.f;
+    }
+    __syncthreads();
+    const size_t fx = (size_t)iM * nz + k;
+    if (MODE == 1) {
+        const float *Wbx = F.Wx32 + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
+        const float *Wby = F.Wy32 + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
+        mfma32_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wbx, nx);
+        mfma32_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wby, ny);
+        block_divide_f32(Tf, ld, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny,
+                         F.lyi + fx * ny, F.ty + fx * ny, Evec[req]);
+        mfma32_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wx, nx);
+        mfma32_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wy, ny);
+    } else {
+        const size_t px = (size_t)pd->nM * nz * 2 * nx * nx, py = (size_t)pd->nM * nz * 2 * ny * ny;
+        const unsigned short *Wbx = F.Wx16 + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
+        const unsigned short *Wby = F.Wy16 + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
+        mfma_bf3_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wbx, px, nx);
+        mfma_bf3_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wby, py, ny);
+        block_divide_f32(Tf, ld, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny,
+                         F.lyi + fx * ny, F.ty + fx * ny, Evec[req]);
+        mfma_bf3_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wx, px, nx);
+        mfma_bf3_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wy, py, ny);
+    }
+    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) g[t] = (double)Tf[(t / ny) * ld + t % ny];
+}
+
+// Mode-z products in FP32 (the pass is bound by HBM traffic of FP64 vectors).
+__global__ void __launch_bounds__(MZ_COLS) k_modez32(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
+                                                     const int *__restrict__ active, int which, const double *in,
+                                                     double *out) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
+    if (iM >= pd->nM) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nz = C.z.n, nxy = C.nxy;
+    const int col0 = blockIdx.x * MZ_COLS;
+    if (col0 >= nxy) return;
+    extern __shared__ float smf[];
+    float *W = smf;
+    float *T = smf + nz * nz;
+    const float *Wg = F.Wz32 + ((size_t)iM * 2 + which) * nz * nz;
+    for (int t = threadIdx.x; t < nz * nz; t += MZ_COLS) W[t] = Wg[t];
+    const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts;
+    const int col = col0 + threadIdx.x;
+    const bool ok = col < nxy;
+    for (int k = 0; k < nz; ++k) T[k * MZ_COLS + threadIdx.x] = ok ? (float)in[base + (long long)k * nxy + col] : 0.f;
+    __syncthreads();
+    if (!ok) return;
+    for (int k2 = 0; k2 < nz; ++k2) {
+        float acc = 0;
+        for (int k = 0; k < nz; ++k) acc += W[k2 * nz + k] * T[k * MZ_COLS + threadIdx.x];
+        out[base + (long long)k2 * nxy + col] = (double)acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // GMRES pieces.  V is stored [i][request][N]; Z likewise.
 constexpr int RT = 256;              // threads of the reduction kernels
 constexpr int MD_G = 16;             // vectors per group in the multi-dot
@@ -1144,6 +1379,45 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
     hipLaunchKernelGGL(k_xy, grid, dim3(XY_THREADS), sh, st, pd.dev, pr.dev, E_dev, active, data, min_den);
 }
 
+void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
+                     double *out, hipStream_t st) {
+    int maxnxy = 0, maxnz = 0;
+    for (int a = 0; a < 3; ++a) {
+        maxnxy = std::max(maxnxy, pd.comp[a].nxy);
+        maxnz = std::max(maxnz, pd.comp[a].z.n);
+    }
+    dim3 grid(cdiv(maxnxy, MZ_COLS), 3 * MAXM, nb);
+    size_t sh = sizeof(float) * (maxnz * maxnz + maxnz * MZ_COLS);
+    hipLaunchKernelGGL(k_modez32, grid, dim3(MZ_COLS), sh, st, pd.dev, pr.dev, active, which, in, out);
+}
+
+bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
+                  int mode, hipStream_t st) {
+    int maxnz = 0, tpw = 0;
+    size_t shm = 0;
+    for (int a = 0; a < 3; ++a) {
+        maxnz = std::max(maxnz, pd.comp[a].z.n);
+        const int nxp = (pd.comp[a].x.n + 15) & ~15, nyp = (pd.comp[a].y.n + 15) & ~15;
+        shm = std::max(shm, sizeof(float) * nxp * (nyp + 4));
+        tpw = std::max(tpw, ((nxp / 16) * (nyp / 16) + 3) / 4);
+    }
+    if (tpw > XYM_MAXT || shm > xy_lds_limit()) return false;
+    dim3 grid(maxnz, 3 * MAXM, nb);
+#define FM_XYLP(T)                                                                                             \
+    {                                                                                                          \
+        if (mode == 1) hipLaunchKernelGGL((k_xy_lp<T, 1>), grid, dim3(XY_THREADS), shm, st, pd.dev, pr.dev, E_dev, active, data); \
+        else hipLaunchKernelGGL((k_xy_lp<T, 2>), grid, dim3(XY_THREADS), shm, st, pd.dev, pr.dev, E_dev, active, data); \
+    }
+    if (tpw <= 1) FM_XYLP(1)
+    else if (tpw <= 2) FM_XYLP(2)
+    else if (tpw <= 4) FM_XYLP(4)
+    else if (tpw <= 8) FM_XYLP(8)
+    else if (tpw <= 12) FM_XYLP(12)
+    else FM_XYLP(16)
+#undef FM_XYLP
+    return true;
+}
+
 void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st) {
     // about 2048 blocks in flight, at most 64 elements per thread, at most NBLK per request
     const long long groups = cdiv(j + 1, MD_G);
@@ -1210,6 +1484,13 @@ void prepare_large_lds(size_t bytes) {
                          reinterpret_cast<const void *>(k_xy_mfma<4>), reinterpret_cast<const void *>(k_xy_mfma<8>),
                          reinterpret_cast<const void *>(k_xy_mfma<12>), reinterpret_cast<const void *>(k_xy_mfma<16>)};
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    const void *lp[] = {reinterpret_cast<const void *>(k_xy_lp<1, 1>), reinterpret_cast<const void *>(k_xy_lp<2, 1>),
+                        reinterpret_cast<const void *>(k_xy_lp<4, 1>), reinterpret_cast<const void *>(k_xy_lp<8, 1>),
+                        reinterpret_cast<const void *>(k_xy_lp<12, 1>), reinterpret_cast<const void *>(k_xy_lp<16, 1>),
+                        reinterpret_cast<const void *>(k_xy_lp<1, 2>), reinterpret_cast<const void *>(k_xy_lp<2, 2>),
+                        reinterpret_cast<const void *>(k_xy_lp<4, 2>), reinterpret_cast<const void *>(k_xy_lp<8, 2>),
+                        reinterpret_cast<const void *>(k_xy_lp<12, 2>), reinterpret_cast<const void *>(k_xy_lp<16, 2>)};
+    for (const void *f : lp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t st) {

@@ -1,0 +1,68 @@
+"""Reduced-precision preconditioner products inside the FP64 flexible GMRES.
+
+The FP32-MFMA and BF16x3-MFMA preconditioners must agree with the FP64 one to
+their arithmetic's accuracy (FP32: unit roundoff 6e-8 times the conditioning of
+the eigenvector products, bounded here by 1e-4; BF16x3 with three products:
+about 2^-16 per product, bounded by 1e-3), and the mixed-precision solves must
+meet the same FP64 bar as the FP64 path: true relative residual 1e-10 against
+the oracle's matrix and relative solution error 1e-8 against the oracle's LU.
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem as OracleProblem
+from oracle.solve import lu_solve, rel_residual
+from paper_2005_05398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fm():
+    from paper_2005_05398_amd import fm
+    return fm
+
+
+def to_dev(a, device):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+
+
+CASES = [("cfg1", W.cfg1()["desc"]),
+         ("hminus_22x22x9", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
+         ("L2_quintic7_cubic4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0))]
+
+
+@pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 1e-3)])
+def test_precond_reduced_precision(device, name, desc, prec, tol):
+    import torch
+    fm = _fm()
+    P = fm.Problem(desc)
+    r = to_dev(np.stack([W.rhs(11, P.N), W.rhs(12, P.N)]), device)
+    z64 = torch.zeros_like(r)
+    zlp = torch.zeros_like(r)
+    Es = [-0.25, -0.5]
+    P.apply_precond(Es, r, z64, prec="fp64")
+    P.apply_precond(Es, r, zlp, prec=prec)
+    for i in range(2):
+        err = (torch.linalg.norm(zlp[i] - z64[i]) / torch.linalg.norm(z64[i])).item()
+        assert err <= tol, (name, prec, err)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,desc,E,restart", [
+    ("cfg1", W.cfg1()["desc"], -0.25, 30),
+    ("hminus_22x22x9", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic"), -0.35, 250)])
+def test_solve_mixed_precision(device, prec, name, desc, E, restart):
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    b = W.rhs(1001, O.N)
+    x = to_dev(np.zeros(O.N), device)
+    st, res = P.solve([E], to_dev(b, device), x, restart=restart, rtol=1e-10, max_iters=4000, prec=prec)
+    assert st == fm.FM_OK, res
+    A = O.assemble(E)
+    xg = x.cpu().numpy()
+    assert rel_residual(A, xg, b) <= 1e-10
+    xref = lu_solve(A, b)
+    assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
