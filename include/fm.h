@@ -157,6 +157,55 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
 fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
                    const fm_solve_opts *opts, fm_solve_result *results, void *stream);
 
+/* ---- Serving: continuous batching of solve requests --------------------
+ *
+ * A server owns a device-memory budget and a set of lanes.  A lane is one
+ * (problem description, precision, restart length) with its own HIP stream,
+ * host thread and Krylov workspace of max_batch slots; lanes run
+ * concurrently, so their kernels overlap on the device.  Problems (the
+ * energy-independent factors of fm_create_problem) are cached by description.
+ * A submitted request is admitted when its lane has a free slot and the
+ * budget covers the lane's workspace (and the problem, if it is new); it joins
+ * the lane at the lane's next restart boundary (a lane ends its cycle early,
+ * after at least 24 Arnoldi steps, when requests wait for its free slots).
+ * Each request is the same flexible GMRES solve as fm_solve; restarts may
+ * differ from a solve alone, so a result alone and in a mix agree to the
+ * solve's accuracy, not bitwise.  A request whose footprint exceeds the whole
+ * budget is finished with FM_E_REJECTED. */
+typedef struct fm_server fm_server;
+
+typedef struct {
+    uint64_t tag;             /* the caller's tag from fm_submit */
+    int status;               /* fm_status of the request */
+    int iters;                /* Arnoldi steps */
+    double rel_residual;      /* final true ||b - A x|| / ||b|| */
+    double t_submit, t_start, t_done;  /* seconds (steady clock): submitted, joined a lane, finished */
+} fm_request_result;
+
+/* hbm_budget_bytes: device bytes the server may hold (factors + workspaces).
+ * max_batch: slots per lane (>= 1).  device: HIP device ordinal.
+ * Errors: FM_E_INVALID, FM_E_HIP, FM_E_NOMEM. */
+fm_status fm_server_create(size_t hbm_budget_bytes, int max_batch, int device, fm_server **out);
+
+/* Queue one solve.  b_host (N doubles) is copied before the call returns;
+ * x_host (N doubles) receives the solution and must stay valid until the
+ * request's result has been returned by fm_poll.  Non-blocking.
+ * Errors: FM_E_INVALID (bad arguments, server shutting down), FM_E_NOMEM. */
+fm_status fm_submit(fm_server *s, const fm_problem_desc *desc, double E, const double *b_host, double *x_host,
+                    const fm_solve_opts *opts, uint64_t tag);
+
+/* Move up to max finished results into results[], *n_done of them.  With
+ * block != 0, wait until at least one result is ready or nothing is
+ * outstanding.  Errors: FM_E_INVALID. */
+fm_status fm_poll(fm_server *s, fm_request_result *results, int max, int *n_done, int block);
+
+/* Device bytes held, live lanes, requests submitted and not yet finished. */
+fm_status fm_server_stats(fm_server *s, size_t *bytes_in_use, int *lanes, long long *outstanding);
+
+/* Drain: every submitted request is finished, then all threads, lanes and
+ * cached problems are released.  Results not yet polled are discarded. */
+fm_status fm_server_destroy(fm_server *s);
+
 /* Per-kernel-class timing of the calls above, for roofline accounting.
  * While enabled, HIP events are recorded on the caller's stream around every
  * kernel launch (a few microseconds per launch), and the algorithmic bytes

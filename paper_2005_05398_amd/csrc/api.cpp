@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 
+#include "batch.h"
 #include "fm_problem.h"
 
 namespace fm {
@@ -153,16 +154,8 @@ size_t krylov_bytes(long long N, int nb, int m) {
     return b;
 }
 
-fm_status ensure_krylov(fm_problem *p, int nb, int m, KrylovDev &K) {
-    size_t need = krylov_bytes(p->N, nb, m);
-    if (p->ws_bytes < need) {
-        if (p->ws) (void)hipFree(p->ws);
-        p->ws = nullptr;
-        p->ws_bytes = 0;
-        if (hipMalloc(&p->ws, need) != hipSuccess) return fail(FM_E_NOMEM, "Krylov workspace allocation failed");
-        p->ws_bytes = need;
-    }
-    char *c = static_cast<char *>(p->ws);
+// Lays the Krylov arrays out in one allocation starting at c.
+char *carve_krylov(char *c, long long N, int nb, int m, KrylovDev &K) {
     auto take = [&](size_t bytes) {
         char *r = c;
         c += round256(bytes);
@@ -170,9 +163,9 @@ fm_status ensure_krylov(fm_problem *p, int nb, int m, KrylovDev &K) {
     };
     K.nb = nb;
     K.m = m;
-    K.N = p->N;
-    K.V = (double *)take(sizeof(double) * size_t(m + 1) * nb * p->N);
-    K.Z = (double *)take(sizeof(double) * size_t(m) * nb * p->N);
+    K.N = N;
+    K.V = (double *)take(sizeof(double) * size_t(m + 1) * nb * N);
+    K.Z = (double *)take(sizeof(double) * size_t(m) * nb * N);
     K.H = (double *)take(sizeof(double) * size_t(nb) * (m + 1) * m);
     K.g = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
     K.hcol = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
@@ -190,7 +183,7 @@ fm_status ensure_krylov(fm_problem *p, int nb, int m, KrylovDev &K) {
     K.active = (int *)take(sizeof(int) * nb);
     K.jcount = (int *)take(sizeof(int) * nb);
     K.flags = (int *)take(sizeof(int) * nb);
-    return FM_OK;
+    return c;
 }
 
 // -- per-kernel-class timing ---------------------------------------------
@@ -306,6 +299,186 @@ void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, 
 }
 
 }  // namespace
+
+// -- Batch -----------------------------------------------------------------
+
+size_t Batch::footprint(const fm_problem *p, int cap, int m) {
+    return krylov_bytes(p->N, cap, m) + 3 * round256(sizeof(int) * cap) + round256(sizeof(double) * cap);
+}
+
+fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
+    p = pp;
+    cap = c;
+    m = mm;
+    st = s;
+    bytes = footprint(p, cap, m);
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        mem = nullptr;
+        return fail(FM_E_NOMEM, "Krylov workspace allocation failed");
+    }
+    char *q = carve_krylov(static_cast<char *>(mem), p->N, cap, m, K);
+    running = reinterpret_cast<int *>(q);
+    q += round256(sizeof(int) * cap);
+    cont = reinterpret_cast<int *>(q);
+    q += round256(sizeof(int) * cap);
+    fresh = reinterpret_cast<int *>(q);
+    q += round256(sizeof(int) * cap);
+    min_den = reinterpret_cast<double *>(q);
+    void *h = nullptr;
+    HIP_TRY(hipHostMalloc(&h, sizeof(int) * cap, hipHostMallocDefault));
+    hbuf = static_cast<int *>(h);
+    HIP_TRY(hipMemsetAsync(mem, 0, bytes, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    run.assign(cap, 0);
+    iters.assign(cap, 0);
+    restarts.assign(cap, 0);
+    limit.assign(cap, 1 << 30);
+    last_steps.assign(cap, 0);
+    E.assign(cap, 0.0);
+    return FM_OK;
+}
+
+void Batch::release() {
+    if (mem) (void)hipFree(mem);
+    if (hbuf) (void)hipHostFree(hbuf);
+    mem = nullptr;
+    hbuf = nullptr;
+}
+
+bool Batch::any_running() const {
+    for (int v : run)
+        if (v) return true;
+    return false;
+}
+
+fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
+    std::vector<int> hcont(run), hfresh(cap, 0);
+    bool any_cont = false, any_fresh = !joining.empty();
+    for (int v : hcont) any_cont |= v != 0;
+    std::vector<double> big(cap, 1e300);
+    for (int s : joining) {
+        hfresh[s] = 1;
+        run[s] = 1;
+        iters[s] = 0;
+        restarts[s] = 0;
+    }
+    HIP_TRY(hipMemcpyAsync(K.E, E.data(), sizeof(double) * cap, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(cont, hcont.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(fresh, hfresh.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(running, run.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+    if (any_fresh) {
+        // per-slot reset of flags and minimum denominators
+        std::vector<int> zero_flags(cap, 0);
+        HIP_TRY(hipMemcpyAsync(hbuf, K.flags, sizeof(int) * cap, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<double> md(cap);
+        HIP_TRY(hipMemcpyAsync(md.data(), min_den, sizeof(double) * cap, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int s : joining) {
+            hbuf[s] = 0;
+            md[s] = 1e300;
+        }
+        HIP_TRY(hipMemcpyAsync(K.flags, hbuf, sizeof(int) * cap, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(min_den, md.data(), sizeof(double) * cap, hipMemcpyHostToDevice, st));
+    }
+    timed(p, st, FM_K_RESTART, [&] {
+        if (any_cont) {
+            launch_cycle_solve(K, cont, st);
+            launch_xupdate(K, cont, X, st);
+        }
+        if (any_fresh) {
+            launch_zero_start(K, X, fresh, x0_is_guess ? 0 : 1, st);
+            launch_bnorm(K, B, fresh, st);
+        }
+        launch_matvec(p->pd, cap, K.E, running, X, K.V, st);
+        launch_residual(K, running, B, rtol, 0.5, st);
+        launch_scale0(K, st);
+    });
+    HIP_TRY(hipGetLastError());
+    if (any_cont) {
+        Work w(p);
+        for (int s = 0; s < cap; ++s)
+            if (hcont[s]) prof_work(p, FM_K_RESTART, 8.0 * (last_steps[s] + 2) * w.N + w.matvec() + 8 * 5 * w.N, 0);
+    }
+    HIP_TRY(hipMemcpyAsync(hbuf, running, sizeof(int) * cap, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    prof_collect(p);
+    std::vector<int> over;
+    for (int s = 0; s < cap; ++s) {
+        run[s] = hbuf[s];
+        if (run[s] && iters[s] >= limit[s]) {
+            run[s] = 0;
+            over.push_back(s);
+        }
+    }
+    if (!over.empty()) {
+        HIP_TRY(hipMemcpyAsync(running, run.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+        std::vector<int> act(cap);
+        HIP_TRY(hipMemcpyAsync(act.data(), K.active, sizeof(int) * cap, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int s : over) act[s] = 0;
+        HIP_TRY(hipMemcpyAsync(K.active, act.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return FM_OK;
+}
+
+fm_status Batch::cycle(const std::function<bool()> &want_cut, int min_steps) {
+    const int nb = cap;
+    const long long N = p->N;
+    const int poll = 4;
+    for (int j = 0; j < m; ++j) {
+        double *Vj = K.V + (long long)j * nb * N;
+        double *Zj = K.Z + (long long)j * nb * N;
+        double *Vn = K.V + (long long)(j + 1) * nb * N;
+        apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, st);
+        apply_operator(p, nb, K.E, K.active, Zj, Vn, st);
+        timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 0, st); });
+        timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
+        timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 1, st); });
+        timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
+        timed(p, st, FM_K_NORM, [&] { launch_norm_givens(K, j, Vn, st); });
+        timed(p, st, FM_K_SCALE, [&] { launch_scale_next(K, j, st); });
+        if ((j + 1) % poll == 0 && j + 1 < m) {
+            HIP_TRY(hipMemcpyAsync(hbuf, K.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            bool any = false;
+            for (int i = 0; i < nb; ++i) any |= hbuf[i] != 0;
+            if (!any) break;
+            if (want_cut && j + 1 >= min_steps && want_cut()) {
+                HIP_TRY(hipMemsetAsync(K.active, 0, sizeof(int) * nb, st));
+                break;
+            }
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(hbuf, K.jcount, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    prof_collect(p);
+    Work w(p);
+    for (int i = 0; i < nb; ++i)
+        if (run[i]) {
+            last_steps[i] = hbuf[i];
+            for (int j = 0; j < hbuf[i]; ++j) add_step_work(p, w, j);
+            iters[i] += std::max(1, hbuf[i]);     // every cycle counts as progress
+            restarts[i] += 1;
+        }
+    return FM_OK;
+}
+
+fm_status Batch::read_results(std::vector<double> &rel, std::vector<double> &mind, std::vector<int> &flags) {
+    std::vector<double> rn(cap), bn(cap);
+    mind.assign(cap, 0.0);
+    flags.assign(cap, 0);
+    HIP_TRY(hipMemcpyAsync(rn.data(), K.rnorm, sizeof(double) * cap, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bn.data(), K.bnorm, sizeof(double) * cap, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(mind.data(), min_den, sizeof(double) * cap, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(flags.data(), K.flags, sizeof(int) * cap, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    rel.assign(cap, 0.0);
+    for (int i = 0; i < cap; ++i) rel[i] = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+    return FM_OK;
+}
 
 void set_error(const std::string &msg) { g_err = msg; }
 
@@ -483,6 +656,10 @@ fm_status fm_destroy_problem(fm_problem *p) {
     if (p->ws_small) (void)hipFree(p->ws_small);
     if (p->host_pinned) (void)hipHostFree(p->host_pinned);
     for (auto e : p->prof.ev) (void)hipEventDestroy(e);
+    if (p->solve_batch) {
+        p->solve_batch->release();
+        delete p->solve_batch;
+    }
     delete p;
     return FM_OK;
 }
@@ -548,157 +725,70 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
     if (opts->max_iters < 1) return fail(FM_E_INVALID, "max_iters must be >= 1");
     if (opts->prec != FM_FP64 && opts->prec != FM_FP32 && opts->prec != FM_BF16X3)
         return fail(FM_E_INVALID, "bad precision");
+    for (int i = 0; i < nbatch; ++i)
+        if (!std::isfinite(E[i])) return fail(FM_E_INVALID, "non-finite energy");
     Busy busy(p);
     if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
     HIP_TRY(hipSetDevice(p->desc.device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int nb = nbatch;
-    const long long N = p->N;
-    Small s;
-    fm_status r = ensure_small(p, nb, s);
-    if (r != FM_OK) return r;
-    KrylovDev K;
-    r = ensure_krylov(p, nb, m, K);
-    if (r != FM_OK) return r;
-    r = ensure_pinned(p, sizeof(double) * 4 * nb + 64);
-    if (r != FM_OK) return r;
-    int *hflags = reinterpret_cast<int *>(p->host_pinned);
-
-    // initial state
-    HIP_TRY(hipMemcpyAsync(K.E, E, sizeof(double) * nb, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(K.ticket, 0, sizeof(int) * nb, st));
-    HIP_TRY(hipMemsetAsync(K.flags, 0, sizeof(int) * nb, st));
-    HIP_TRY(hipMemsetAsync(K.active, 0, sizeof(int) * nb, st));
-    HIP_TRY(hipMemsetAsync(K.jcount, 0, sizeof(int) * nb, st));
-    {
-        std::vector<int> ones(nb, 1);
-        HIP_TRY(hipMemcpyAsync(s.running, ones.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-        std::vector<double> big(nb, 1e300);
-        HIP_TRY(hipMemcpyAsync(s.min_den, big.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
+    // the problem keeps the batch of its last solve for reuse
+    Batch *b = p->solve_batch;
+    if (!b || b->cap != nbatch || b->m != m) {
+        if (b) {
+            b->release();
+            delete b;
+            p->solve_batch = nullptr;
+        }
+        b = new (std::nothrow) Batch();
+        if (!b) return fail(FM_E_NOMEM, "host allocation failed");
+        fm_status r = b->create(p, nbatch, m, st);
+        if (r != FM_OK) {
+            delete b;
+            return r;
+        }
+        p->solve_batch = b;
     }
-    launch_bnorm(K, b_dev, st);
-    HIP_TRY(hipMemcpyAsync(hflags, K.flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < nb; ++i)
-        if (hflags[i] & 1) return fail(FM_E_NONFINITE, "non-finite value in b");
-
-    if (!opts->x0_is_guess) {
-        launch_fill(x_dev, N * nb, 0.0, st);
-        launch_fill(K.V, N * nb, 0.0, st);
-    } else {
-        launch_matvec(p->pd, nb, K.E, s.running, x_dev, K.V, st);
+    b->st = st;
+    b->B = b_dev;
+    b->X = x_dev;
+    b->prec = opts->prec;
+    b->rtol = opts->rtol;
+    std::vector<int> all(nbatch);
+    for (int i = 0; i < nbatch; ++i) {
+        all[i] = i;
+        b->E[i] = E[i];
+        b->limit[i] = opts->max_iters;
     }
-    launch_residual(K, s.running, b_dev, opts->rtol, 0.5, st);
-    launch_scale0(K, st);
-    HIP_TRY(hipGetLastError());
-
-    std::vector<int> iters(nb, 0), restarts(nb, 0);
-    std::vector<int> hrun(nb, 1);
-    const int poll = 4;
-    int cycle_guard = 0;
-    for (;;) {
-        HIP_TRY(hipMemcpyAsync(hflags, s.running, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        int nrun = 0, maxit = 0;
-        for (int i = 0; i < nb; ++i) {
-            hrun[i] = hflags[i];
-            if (hrun[i]) {
-                ++nrun;
-                maxit = std::max(maxit, iters[i]);
-            }
-        }
-        if (nrun == 0) break;
-        bool budget_left = false;
-        for (int i = 0; i < nb; ++i)
-            if (hrun[i] && iters[i] < opts->max_iters) budget_left = true;
-        if (!budget_left || ++cycle_guard > 100000) break;
-        // requests over budget stop iterating
-        {
-            bool any_over = false;
-            for (int i = 0; i < nb; ++i)
-                if (hrun[i] && iters[i] >= opts->max_iters) { any_over = true; hrun[i] = 0; }
-            if (any_over) {
-                std::vector<int> h(hrun.begin(), hrun.end());
-                HIP_TRY(hipMemcpyAsync(s.running, h.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-                HIP_TRY(hipMemcpyAsync(K.active, h.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-                HIP_TRY(hipStreamSynchronize(st));
-            }
-        }
-        int steps_cap = m;
-        for (int i = 0; i < nb; ++i)
-            if (hrun[i]) steps_cap = std::min(steps_cap, std::max(1, opts->max_iters - iters[i]));
-        (void)steps_cap;
-        for (int j = 0; j < m; ++j) {
-            double *Vj = K.V + (long long)j * nb * N;
-            double *Zj = K.Z + (long long)j * nb * N;
-            double *Vn = K.V + (long long)(j + 1) * nb * N;
-            apply_precond(p, nb, K.E, K.active, Vj, Zj, opts->prec, s.min_den, st);
-            apply_operator(p, nb, K.E, K.active, Zj, Vn, st);
-            timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 0, st); });
-            timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
-            timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 1, st); });
-            timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
-            timed(p, st, FM_K_NORM, [&] { launch_norm_givens(K, j, Vn, st); });
-            timed(p, st, FM_K_SCALE, [&] { launch_scale_next(K, j, st); });
-            if ((j + 1) % poll == 0 && j + 1 < m) {
-                HIP_TRY(hipMemcpyAsync(hflags, K.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipStreamSynchronize(st));
-                bool any = false;
-                for (int i = 0; i < nb; ++i) any |= hflags[i] != 0;
-                if (!any) break;
-            }
-        }
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(hflags, K.jcount, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        prof_collect(p);
-        {
-            Work w(p);
-            for (int i = 0; i < nb; ++i)
-                if (hrun[i]) {
-                    for (int j = 0; j < hflags[i]; ++j) add_step_work(p, w, j);
-                    prof_work(p, FM_K_RESTART, 8 * (hflags[i] + 2) * w.N + w.matvec() + 8 * 3 * w.N + 16 * w.N, 0);
-                    iters[i] += std::max(1, hflags[i]);     // every cycle counts as progress
-                    restarts[i] += 1;
-                }
-        }
-        timed(p, st, FM_K_RESTART, [&] {
-            launch_cycle_solve(K, s.running, st);
-            launch_xupdate(K, s.running, x_dev, st);
-            launch_matvec(p->pd, nb, K.E, s.running, x_dev, K.V, st);
-            launch_residual(K, s.running, b_dev, opts->rtol, 0.5, st);
-            launch_scale0(K, st);
-        });
-        HIP_TRY(hipGetLastError());
+    fm_status r = b->boundary(all, opts->x0_is_guess);
+    if (r != FM_OK) return r;
+    int guard = 0;
+    while (b->any_running() && ++guard < 1000000) {
+        r = b->cycle(nullptr, 0);
+        if (r != FM_OK) return r;
+        r = b->boundary({}, opts->x0_is_guess);
+        if (r != FM_OK) return r;
     }
-    // results
-    std::vector<double> rn(nb), bn(nb), md(nb);
-    std::vector<int> fl(nb), run(nb);
-    HIP_TRY(hipMemcpyAsync(rn.data(), K.rnorm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(bn.data(), K.bnorm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(md.data(), s.min_den, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(fl.data(), K.flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(run.data(), s.running, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    prof_collect(p);
+    std::vector<double> rel, md;
+    std::vector<int> fl;
+    r = b->read_results(rel, md, fl);
+    if (r != FM_OK) return r;
     fm_status overall = FM_OK;
-    for (int i = 0; i < nb; ++i) {
-        double rel = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+    for (int i = 0; i < nbatch; ++i) {
         int stt = FM_OK;
-        if (fl[i] & 2) stt = FM_E_NONFINITE;
-        else if (!(rel <= opts->rtol)) stt = FM_E_NOT_CONVERGED;
-        if (stt != FM_OK && overall == FM_OK) overall = (fm_status)stt;
+        if (fl[i] & 1) stt = FM_E_NONFINITE;
+        else if (fl[i] & 2) stt = FM_E_NONFINITE;
+        else if (!(rel[i] <= opts->rtol)) stt = FM_E_NOT_CONVERGED;
+        if (stt != FM_OK && (overall == FM_OK || stt == FM_E_NONFINITE)) overall = (fm_status)stt;
         if (results) {
-            results[i].iters = iters[i];
-            results[i].restarts = restarts[i];
-            results[i].rel_residual = rel;
+            results[i].iters = b->iters[i];
+            results[i].restarts = b->restarts[i];
+            results[i].rel_residual = rel[i];
             results[i].min_abs_denominator = md[i];
             results[i].status = stt;
         }
     }
     if (overall == FM_E_NOT_CONVERGED) g_err = "some requests did not reach rtol";
-    if (overall == FM_E_NONFINITE) g_err = "non-finite values during the iteration";
+    if (overall == FM_E_NONFINITE) g_err = "non-finite value in b or during the iteration";
     return overall;
 }
 

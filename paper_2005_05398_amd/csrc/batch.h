@@ -1,0 +1,45 @@
+// A batch of flexible-GMRES solve slots of one problem sharing one Krylov
+// workspace.  Every slot has its own energy, right-hand side (row of B) and
+// solution (row of X); slots start at restart boundaries, so requests can join
+// a batch that is already iterating.
+#pragma once
+
+#include <functional>
+
+#include "fm_problem.h"
+
+namespace fm {
+
+struct Batch {
+    fm_problem *p = nullptr;
+    int cap = 0, m = 0;
+    hipStream_t st = nullptr;
+    KrylovDev K{};
+    void *mem = nullptr;
+    size_t bytes = 0;
+    int *running = nullptr, *cont = nullptr, *fresh = nullptr;   // device masks [cap]
+    double *min_den = nullptr;                                   // device [cap]
+    int *hbuf = nullptr;                                         // pinned host scratch [cap]
+    const double *B = nullptr;                                   // [cap][N]
+    double *X = nullptr;                                         // [cap][N]
+    int prec = FM_FP64;
+    double rtol = 1e-10;
+    std::vector<int> run, iters, restarts, limit, last_steps;    // host view per slot
+    std::vector<double> E;
+
+    static size_t footprint(const fm_problem *p, int cap, int m);
+    fm_status create(fm_problem *p, int cap, int m, hipStream_t st);
+    void release();
+    // Ends the cycle of the running slots (x += Z y, then the FP64 true
+    // residual decides convergence) and starts the slots in `joining`, whose E
+    // and B rows must already be set.  A slot over its step limit stops here.
+    fm_status boundary(const std::vector<int> &joining, int x0_is_guess);
+    // Arnoldi steps for the active slots until every slot stops, j reaches m,
+    // or want_cut() holds after at least min_steps steps.
+    fm_status cycle(const std::function<bool()> &want_cut, int min_steps);
+    bool any_running() const;
+    // Per slot: relative true residual, min |denominator|, status flags.
+    fm_status read_results(std::vector<double> &rel, std::vector<double> &min_abs_den, std::vector<int> &flags);
+};
+
+}  // namespace fm

@@ -158,7 +158,8 @@ void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream
 void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,
                      hipStream_t st);
 void launch_scale0(const KrylovDev &k, hipStream_t st);
-void launch_bnorm(const KrylovDev &k, const double *b, hipStream_t st);
+void launch_bnorm(const KrylovDev &k, const double *b, const int *mask, hipStream_t st);
+void launch_zero_start(const KrylovDev &k, double *x, const int *mask, int zero_x, hipStream_t st);
 void launch_fill(double *p, long long n, double v, hipStream_t st);
 void prepare_large_lds(size_t bytes);
 size_t xy_lds_limit();

@@ -30,6 +30,8 @@ struct Profile {
     double flops[FM_K_COUNT] = {0};
 };
 
+struct Batch;
+
 struct DeviceBuffer {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -60,6 +62,7 @@ struct fm_problem {
     double *host_pinned = nullptr;           // pinned host scratch for flag read-back
     size_t host_pinned_bytes = 0;
     fm::Profile prof;
+    fm::Batch *solve_batch = nullptr;        // workspace of the last fm_solve, reused
 };
 
 namespace fm {

@@ -1244,8 +1244,9 @@ __global__ void __launch_bounds__(RT) k_scale0(KrylovDev K) {
     v[e] = v[e] / K.scal[req];
 }
 
-__global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restrict__ B) {
+__global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restrict__ B, const int *__restrict__ mask) {
     const int req = blockIdx.y;
+    if (mask && !mask[req]) return;
     __shared__ double red[RT];
     long long lo, hi;
     chunk_range(K.N, blockIdx.x, lo, hi);
@@ -1276,6 +1277,16 @@ __global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restr
             K.ticket[req] = 0;
         }
     }
+}
+
+// x = 0 and A x = 0 (Krylov slot 0) for the masked requests.
+__global__ void k_zero_start(KrylovDev K, double *X, const int *__restrict__ mask, int zero_x) {
+    const int req = blockIdx.y;
+    if (!mask[req]) return;
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K.N) return;
+    if (zero_x) X[(long long)req * K.N + e] = 0.0;
+    K.V[(long long)req * K.N + e] = 0.0;
 }
 
 __global__ void k_fill(double *p, long long n, double v) {
@@ -1467,9 +1478,9 @@ void launch_scale0(const KrylovDev &k, hipStream_t st) {
     hipLaunchKernelGGL(k_scale0, grid, dim3(RT), 0, st, k);
 }
 
-void launch_bnorm(const KrylovDev &k, const double *b, hipStream_t st) {
+void launch_bnorm(const KrylovDev &k, const double *b, const int *mask, hipStream_t st) {
     dim3 grid(reduce_blocks(k), k.nb);
-    hipLaunchKernelGGL(k_bnorm, grid, dim3(RT), 0, st, k, b);
+    hipLaunchKernelGGL(k_bnorm, grid, dim3(RT), 0, st, k, b, mask);
 }
 
 size_t g_lds_limit = 65536;
@@ -1491,6 +1502,11 @@ void prepare_large_lds(size_t bytes) {
                         reinterpret_cast<const void *>(k_xy_lp<4, 2>), reinterpret_cast<const void *>(k_xy_lp<8, 2>),
                         reinterpret_cast<const void *>(k_xy_lp<12, 2>), reinterpret_cast<const void *>(k_xy_lp<16, 2>)};
     for (const void *f : lp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+void launch_zero_start(const KrylovDev &k, double *x, const int *mask, int zero_x, hipStream_t st) {
+    dim3 grid(cdiv(k.N, 256), k.nb);
+    hipLaunchKernelGGL(k_zero_start, grid, dim3(256), 0, st, k, x, mask, zero_x);
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t st) {

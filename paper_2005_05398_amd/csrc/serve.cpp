@@ -1,0 +1,462 @@
+// Serving loop: continuous batching of solve requests (include/fm.h, fm_server_*).
+//
+// A dispatcher thread admits submitted requests by device-memory footprint and
+// routes each to a lane: one lane per (problem description, precision,
+// restart length), each with its own HIP stream, its own Krylov workspace
+// (a Batch of max_batch slots) and its own host thread, so the lanes' kernels
+// overlap on the device.  Problems (the energy-independent factors) are cached
+// by description.  A request joins its lane at the lane's next restart
+// boundary; a lane with waiting requests and free slots ends its cycle early
+// (after at least a minimum number of Arnoldi steps) so that they can join.
+// Finished requests leave their slot, their solution is copied to the caller's
+// host buffer, and a result is queued for fm_poll.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "batch.h"
+
+namespace fm {
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+std::string desc_key(const fm_problem_desc &d) {
+    fm_problem_desc c = d;
+    c.device = 0;
+    return std::string(reinterpret_cast<const char *>(&c), sizeof(c));
+}
+
+long long unknowns_of(const fm_problem_desc &d) {
+    int M0 = (1 - d.tau) / 2;
+    long long nM = d.J - M0 + 1, s = 0;
+    for (int a = 0; a < 3; ++a) s += (long long)d.x[a].n * d.y[a].n * d.z[a].n;
+    return nM * s;
+}
+
+}  // namespace
+
+struct ServeReq {
+    uint64_t tag = 0;
+    fm_problem_desc desc{};
+    double E = 0;
+    std::vector<double> b;
+    double *x_host = nullptr;
+    fm_solve_opts opts{};
+    double t_submit = 0, t_start = 0, t_done = 0;
+    int status = FM_OK, iters = 0;
+    double rel = 0;
+};
+
+struct Lane {
+    std::string key;
+    fm_problem *prob = nullptr;
+    Batch batch;
+    double *B = nullptr, *X = nullptr;
+    std::vector<ServeReq *> slot;
+    std::deque<ServeReq *> joinq;      // guarded by the server mutex
+    std::thread th;
+    hipStream_t st = nullptr;
+    bool finished = false;             // thread has exited
+    size_t bytes = 0;
+};
+
+}  // namespace fm
+
+struct fm_server {
+    size_t budget = 0;
+    int max_batch = 1;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv;        // dispatcher and lanes wait here
+    std::condition_variable done_cv;   // fm_poll waits here
+    std::deque<fm::ServeReq *> pending;
+    std::deque<fm::ServeReq *> finished;
+    std::map<std::string, fm_problem *> cache;
+    std::vector<fm::Lane *> lanes;
+    size_t in_use = 0;
+    long long outstanding = 0;         // submitted and not yet finished
+    bool stop = false;
+    std::thread dispatcher;
+    std::string error;
+};
+
+namespace fm {
+
+namespace {
+
+void finish(fm_server *S, ServeReq *r) {
+    r->t_done = now_s();
+    S->finished.push_back(r);
+    S->outstanding -= 1;
+    S->done_cv.notify_all();
+}
+
+void lane_loop(fm_server *S, Lane *L) {
+    (void)hipSetDevice(S->device);
+    const long long N = L->prob->N;
+    const int cap = L->batch.cap;
+    for (;;) {
+        std::vector<std::pair<int, ServeReq *>> joiners;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (;;) {
+                for (int s = 0; s < cap && !L->joinq.empty(); ++s)
+                    if (!L->slot[s]) {
+                        L->slot[s] = L->joinq.front();
+                        L->joinq.pop_front();
+                        joiners.push_back({s, L->slot[s]});
+                    }
+                bool busy = L->batch.any_running() || !joiners.empty();
+                if (busy) break;
+                if (S->stop) {
+                    L->finished = true;
+                    S->cv.notify_all();
+                    return;
+                }
+                // idle: give the lane back when nothing has arrived for a while
+                if (S->cv.wait_for(lk, std::chrono::milliseconds(200)) == std::cv_status::timeout &&
+                    L->joinq.empty() && !L->batch.any_running()) {
+                    L->finished = true;
+                    S->cv.notify_all();
+                    return;
+                }
+            }
+        }
+        std::vector<int> js;
+        for (auto &pr : joiners) {
+            ServeReq *r = pr.second;
+            r->t_start = now_s();
+            (void)hipMemcpyAsync(L->B + (long long)pr.first * N, r->b.data(), sizeof(double) * N,
+                                 hipMemcpyHostToDevice, L->st);
+            L->batch.E[pr.first] = r->E;
+            L->batch.limit[pr.first] = r->opts.max_iters;
+            js.push_back(pr.first);
+        }
+        std::vector<int> was(L->batch.run);
+        fm_status st = L->batch.boundary(js, 0);
+        std::vector<int> done;
+        for (int s = 0; s < cap; ++s)
+            if (L->slot[s] && (was[s] || std::find(js.begin(), js.end(), s) != js.end()) &&
+                (!L->batch.run[s] || st != FM_OK))
+                done.push_back(s);
+        if (!done.empty()) {
+            std::vector<double> rel, md;
+            std::vector<int> fl;
+            if (L->batch.read_results(rel, md, fl) != FM_OK) st = FM_E_HIP;
+            for (int s : done) {
+                ServeReq *r = L->slot[s];
+                (void)hipMemcpyAsync(r->x_host, L->X + (long long)s * N, sizeof(double) * N, hipMemcpyDeviceToHost,
+                                     L->st);
+                (void)hipStreamSynchronize(L->st);
+                r->iters = L->batch.iters[s];
+                r->rel = rel.empty() ? 0.0 : rel[s];
+                if (st != FM_OK) r->status = st;
+                else if (fl[s]) r->status = FM_E_NONFINITE;
+                else r->status = r->rel <= r->opts.rtol ? FM_OK : FM_E_NOT_CONVERGED;
+                std::lock_guard<std::mutex> lk(S->mu);
+                L->slot[s] = nullptr;
+                finish(S, r);
+            }
+        }
+        if (st != FM_OK) {
+            // a failed device call ends the lane: report every occupant
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (int s = 0; s < cap; ++s)
+                if (L->slot[s]) {
+                    L->slot[s]->status = st;
+                    finish(S, L->slot[s]);
+                    L->slot[s] = nullptr;
+                }
+            for (auto *r : L->joinq) {
+                r->status = st;
+                finish(S, r);
+            }
+            L->joinq.clear();
+            std::fill(L->batch.run.begin(), L->batch.run.end(), 0);
+            L->finished = true;
+            S->error = "lane stopped after a HIP error";
+            S->cv.notify_all();
+            return;
+        }
+        if (L->batch.any_running()) {
+            auto want_cut = [S, L, cap]() {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (L->joinq.empty()) return false;
+                for (int s = 0; s < cap; ++s)
+                    if (!L->slot[s]) return true;
+                return false;
+            };
+            if (L->batch.cycle(want_cut, 24) != FM_OK) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->error = "lane cycle failed";
+            }
+        }
+    }
+}
+
+void reap_lanes(fm_server *S) {
+    // called with the mutex held
+    for (size_t i = 0; i < S->lanes.size();) {
+        Lane *L = S->lanes[i];
+        if (L->finished) {
+            if (L->th.joinable()) L->th.join();
+            L->batch.release();
+            (void)hipFree(L->B);
+            (void)hipFree(L->X);
+            (void)hipStreamDestroy(L->st);
+            S->in_use -= L->bytes;
+            delete L;
+            S->lanes.erase(S->lanes.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+void dispatch_loop(fm_server *S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        reap_lanes(S);
+        if (S->stop && S->pending.empty()) {
+            bool all = true;
+            for (auto *L : S->lanes) all &= L->finished;
+            if (all) {
+                reap_lanes(S);
+                return;
+            }
+            S->cv.notify_all();
+            S->cv.wait_for(lk, std::chrono::milliseconds(20));
+            continue;
+        }
+        bool progressed = false;
+        for (auto it = S->pending.begin(); it != S->pending.end();) {
+            ServeReq *r = *it;
+            std::string pkey = desc_key(r->desc);
+            std::string lkey = pkey + std::to_string(r->opts.prec) + ":" + std::to_string(r->opts.restart);
+            Lane *lane = nullptr;
+            for (auto *L : S->lanes)
+                if (L->key == lkey && !L->finished) lane = L;
+            if (lane) {
+                lane->joinq.push_back(r);
+                it = S->pending.erase(it);
+                progressed = true;
+                S->cv.notify_all();
+                continue;
+            }
+            // a new lane: problem (cached) plus a batch of max_batch slots
+            fm_problem *prob = nullptr;
+            auto c = S->cache.find(pkey);
+            long long N = unknowns_of(r->desc);
+            size_t prob_bytes = 0;
+            if (c == S->cache.end()) {
+                // factor sizes: 2 n_z (n_x^2 + n_y^2) per component and M', in FP64, FP32 and 2 x BF16
+                for (int a = 0; a < 3; ++a)
+                    prob_bytes += size_t(r->desc.J + 2) * 2 * r->desc.z[a].n *
+                                  (size_t(r->desc.x[a].n) * r->desc.x[a].n + size_t(r->desc.y[a].n) * r->desc.y[a].n) *
+                                  (8 + 4 + 4);
+                prob_bytes += size_t(N) * 8;
+            }
+            fm_problem tmp;
+            tmp.N = N;
+            size_t lane_bytes = Batch::footprint(&tmp, S->max_batch, r->opts.restart) + 2 * size_t(N) * 8 * S->max_batch;
+            size_t need = lane_bytes + prob_bytes;
+            if (need > S->budget) {
+                r->status = FM_E_REJECTED;
+                it = S->pending.erase(it);
+                finish(S, r);
+                continue;
+            }
+            if (S->in_use + need > S->budget) {
+                ++it;                      // wait for memory
+                continue;
+            }
+            if (c == S->cache.end()) {
+                fm_problem_desc d = r->desc;
+                d.device = S->device;
+                lk.unlock();
+                fm_status st = fm_create_problem(&d, &prob);
+                lk.lock();
+                // submissions may have grown the queue meanwhile: find r again
+                it = std::find(S->pending.begin(), S->pending.end(), r);
+                if (st != FM_OK) {
+                    r->status = st;
+                    it = S->pending.erase(it);
+                    finish(S, r);
+                    continue;
+                }
+                S->cache[pkey] = prob;
+                size_t res = 0;
+                fm_problem_info(prob, nullptr, &res, 1, nullptr);
+                S->in_use += res;
+            } else {
+                prob = c->second;
+            }
+            Lane *L = new Lane();
+            L->key = lkey;
+            L->prob = prob;
+            L->slot.assign(S->max_batch, nullptr);
+            bool ok = hipStreamCreate(&L->st) == hipSuccess;
+            ok = ok && hipMalloc(reinterpret_cast<void **>(&L->B), sizeof(double) * N * S->max_batch) == hipSuccess;
+            ok = ok && hipMalloc(reinterpret_cast<void **>(&L->X), sizeof(double) * N * S->max_batch) == hipSuccess;
+            ok = ok && L->batch.create(prob, S->max_batch, r->opts.restart, L->st) == FM_OK;
+            if (!ok) {
+                if (L->B) (void)hipFree(L->B);
+                if (L->X) (void)hipFree(L->X);
+                if (L->st) (void)hipStreamDestroy(L->st);
+                L->batch.release();
+                delete L;
+                r->status = FM_E_NOMEM;
+                it = S->pending.erase(it);
+                finish(S, r);
+                continue;
+            }
+            L->batch.B = L->B;
+            L->batch.X = L->X;
+            L->batch.prec = r->opts.prec;
+            L->batch.rtol = r->opts.rtol;
+            L->bytes = L->batch.bytes + 2 * sizeof(double) * N * S->max_batch;
+            S->in_use += L->bytes;
+            L->joinq.push_back(r);
+            it = S->pending.erase(it);
+            S->lanes.push_back(L);
+            L->th = std::thread(lane_loop, S, L);
+            progressed = true;
+        }
+        if (!progressed) S->cv.wait_for(lk, std::chrono::milliseconds(5));
+    }
+}
+
+}  // namespace
+
+}  // namespace fm
+
+using namespace fm;
+
+extern "C" {
+
+fm_status fm_server_create(size_t hbm_budget_bytes, int max_batch, int device, fm_server **out) {
+    if (!out || max_batch < 1 || max_batch > 4096 || hbm_budget_bytes == 0) {
+        set_error("bad argument");
+        return FM_E_INVALID;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        set_error("no such HIP device");
+        return FM_E_HIP;
+    }
+    fm_server *S = new (std::nothrow) fm_server();
+    if (!S) {
+        set_error("host allocation failed");
+        return FM_E_NOMEM;
+    }
+    S->budget = hbm_budget_bytes;
+    S->max_batch = max_batch;
+    S->device = device;
+    S->dispatcher = std::thread(dispatch_loop, S);
+    *out = S;
+    return FM_OK;
+}
+
+fm_status fm_submit(fm_server *S, const fm_problem_desc *desc, double E, const double *b_host, double *x_host,
+                    const fm_solve_opts *opts, uint64_t tag) {
+    if (!S || !desc || !b_host || !x_host || !opts || !std::isfinite(E) || opts->restart < 1 || opts->restart > 1000 ||
+        !(opts->rtol > 0) || opts->max_iters < 1 ||
+        (opts->prec != FM_FP64 && opts->prec != FM_FP32 && opts->prec != FM_BF16X3)) {
+        set_error("bad argument");
+        return FM_E_INVALID;
+    }
+    long long N = unknowns_of(*desc);
+    if (N <= 0 || N > (1LL << 31)) {
+        set_error("bad problem size");
+        return FM_E_INVALID;
+    }
+    ServeReq *r = new (std::nothrow) ServeReq();
+    if (!r) {
+        set_error("host allocation failed");
+        return FM_E_NOMEM;
+    }
+    r->tag = tag;
+    r->desc = *desc;
+    r->E = E;
+    r->b.assign(b_host, b_host + N);
+    r->x_host = x_host;
+    r->opts = *opts;
+    r->t_submit = now_s();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+        delete r;
+        set_error("server is shutting down");
+        return FM_E_INVALID;
+    }
+    S->pending.push_back(r);
+    S->outstanding += 1;
+    S->cv.notify_all();
+    return FM_OK;
+}
+
+fm_status fm_poll(fm_server *S, fm_request_result *results, int max, int *n_done, int block) {
+    if (!S || !results || max < 1 || !n_done) {
+        set_error("bad argument");
+        return FM_E_INVALID;
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (block)
+        S->done_cv.wait(lk, [S] { return !S->finished.empty() || S->outstanding == 0; });
+    int n = 0;
+    while (n < max && !S->finished.empty()) {
+        ServeReq *r = S->finished.front();
+        S->finished.pop_front();
+        fm_request_result &o = results[n++];
+        o.tag = r->tag;
+        o.status = r->status;
+        o.iters = r->iters;
+        o.rel_residual = r->rel;
+        o.t_submit = r->t_submit;
+        o.t_start = r->t_start;
+        o.t_done = r->t_done;
+        delete r;
+    }
+    *n_done = n;
+    return FM_OK;
+}
+
+fm_status fm_server_stats(fm_server *S, size_t *bytes_in_use, int *lanes, long long *outstanding) {
+    if (!S) {
+        set_error("null server");
+        return FM_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (bytes_in_use) *bytes_in_use = S->in_use;
+    if (lanes) *lanes = int(S->lanes.size());
+    if (outstanding) *outstanding = S->outstanding;
+    return FM_OK;
+}
+
+fm_status fm_server_destroy(fm_server *S) {
+    if (!S) return FM_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->dispatcher.joinable()) S->dispatcher.join();
+    for (auto &kv : S->cache) fm_destroy_problem(kv.second);
+    for (auto *r : S->finished) delete r;
+    for (auto *r : S->pending) delete r;
+    delete S;
+    return FM_OK;
+}
+
+}  // extern "C"

@@ -252,3 +252,77 @@ def host_setup_check(desc):
     _check(L.fm_host_setup_check(ctypes.byref(make_c_desc(desc)), ctypes.byref(err), ctypes.byref(pairs),
                                  ctypes.byref(n)))
     return err.value, pairs.value, n.value
+
+
+# -- serving (fm_server_*) ----------------------------------------------------
+
+class FmRequestResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+def _server_sigs(L):
+    if getattr(L, "_server_sigs", False):
+        return
+    vp, ci = ctypes.c_void_p, ctypes.c_int
+    L.fm_server_create.argtypes = [ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
+    L.fm_submit.argtypes = [vp, ctypes.POINTER(FmDesc), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FmSolveOpts), ctypes.c_uint64]
+    L.fm_poll.argtypes = [vp, ctypes.POINTER(FmRequestResult), ci, ctypes.POINTER(ci), ci]
+    L.fm_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ci),
+                                  ctypes.POINTER(ctypes.c_longlong)]
+    L.fm_server_destroy.argtypes = [vp]
+    for f in ("fm_server_create", "fm_submit", "fm_poll", "fm_server_stats", "fm_server_destroy"):
+        getattr(L, f).restype = ci
+    L._server_sigs = True
+
+
+class Server:
+    """Continuous-batching solve server (host buffers in, host buffers out)."""
+
+    def __init__(self, hbm_budget_bytes, max_batch=8, device=0):
+        L = lib()
+        _server_sigs(L)
+        self._h = ctypes.c_void_p()
+        _check(L.fm_server_create(int(hbm_budget_bytes), int(max_batch), int(device), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, desc, E, b, x, tag, restart=60, rtol=1e-10, max_iters=4000, prec="fp64"):
+        """b, x: contiguous float64 numpy arrays of N; x is written when the result is polled."""
+        import numpy as np
+        assert b.dtype == np.float64 and x.dtype == np.float64 and b.flags.c_contiguous and x.flags.c_contiguous
+        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], 0)
+        self._keep[int(tag)] = (b, x)
+        _check(lib().fm_submit(self._h, ctypes.byref(make_c_desc(desc)), float(E), _dptr(b), _dptr(x),
+                               ctypes.byref(opts), ctypes.c_uint64(int(tag))))
+
+    def poll(self, block=False, max_results=256):
+        buf = (FmRequestResult * max_results)()
+        n = ctypes.c_int()
+        _check(lib().fm_poll(self._h, buf, max_results, ctypes.byref(n), int(bool(block))))
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            self._keep.pop(int(r.tag), None)
+            out.append({"tag": int(r.tag), "status": STATUS_NAMES.get(r.status, r.status), "iters": r.iters,
+                        "rel_residual": r.rel_residual, "t_submit": r.t_submit, "t_start": r.t_start,
+                        "t_done": r.t_done})
+        return out
+
+    def stats(self):
+        b, l, o = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_longlong()
+        _check(lib().fm_server_stats(self._h, ctypes.byref(b), ctypes.byref(l), ctypes.byref(o)))
+        return {"bytes_in_use": b.value, "lanes": l.value, "outstanding": o.value}
+
+    def close(self):
+        if self._h:
+            lib().fm_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

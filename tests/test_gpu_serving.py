@@ -1,0 +1,80 @@
+"""Serving (continuous batching) through the C ABI.
+
+Each served result must equal the same request solved alone with fm_solve, to
+the solve's own accuracy (relative difference 1e-8, the solution-error bar),
+and meet the FP64 residual bar against the oracle; requests submitted while
+others iterate must join before those finish; a request larger than the whole
+memory budget is rejected.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem as OracleProblem
+from oracle.solve import rel_residual
+from paper_2005_05398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fm():
+    from paper_2005_05398_amd import fm
+    return fm
+
+
+DESCS = [W.cfg1()["desc"], W.make_desc(*W.H_MINUS, 13, 6, R=30.0, xy_map="quadratic"),
+         W.make_desc(*W.PS_MINUS, 7, 4, J=1, deg_z=3, R=15.0)]
+
+
+def test_serving_results_match_solo_and_batch_continuously(device):
+    import torch
+    fm = _fm()
+    rng = np.random.default_rng(123)
+    reqs = []
+    for i in range(18):
+        d = DESCS[i % len(DESCS)]
+        N = W.n_unknowns(d)
+        reqs.append({"tag": i, "desc": d, "E": float(rng.uniform(-0.55, -0.2)), "b": W.rhs(7000 + i, N),
+                     "x": np.zeros(N)})
+    srv = fm.Server(hbm_budget_bytes=8 << 30, max_batch=4)
+    results = {}
+    for i, r in enumerate(reqs):
+        srv.submit(r["desc"], r["E"], r["b"], r["x"], r["tag"], restart=60, rtol=1e-10)
+        if i % 3 == 2:
+            time.sleep(0.02)              # arrivals while earlier requests iterate
+            for o in srv.poll():
+                results[o["tag"]] = o
+    while len(results) < len(reqs):
+        for o in srv.poll(block=True):
+            results[o["tag"]] = o
+    srv.close()
+    assert all(o["status"] == "FM_OK" for o in results.values()), results
+    # continuous batching: some request started before an earlier-submitted one finished
+    order = sorted(results.values(), key=lambda o: o["t_submit"])
+    assert any(later["t_start"] < earlier["t_done"] for k, earlier in enumerate(order) for later in order[k + 1:])
+    # same result alone (fm_solve) and in the mix
+    probs = {}
+    for r in reqs:
+        key = id(r["desc"])
+        if key not in probs:
+            probs[key] = (fm.Problem(r["desc"]), OracleProblem(r["desc"]))
+        P, O = probs[key]
+        x = torch.zeros(P.N, dtype=torch.float64, device=device)
+        st, _ = P.solve([r["E"]], torch.as_tensor(r["b"], device=device), x, restart=60, rtol=1e-10)
+        assert st == fm.FM_OK
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(r["x"] - xs) / np.linalg.norm(xs) <= 1e-8
+        assert rel_residual(O.assemble(r["E"]), r["x"], r["b"]) <= 1e-10
+
+
+def test_serving_rejects_oversize_request(device):
+    fm = _fm()
+    d = W.cfg1()["desc"]
+    N = W.n_unknowns(d)
+    srv = fm.Server(hbm_budget_bytes=1 << 20, max_batch=2)
+    b, x = W.rhs(1, N), np.zeros(N)
+    srv.submit(d, -0.25, b, x, 5)
+    out = srv.poll(block=True)
+    srv.close()
+    assert out and out[0]["tag"] == 5 and out[0]["status"] == "FM_E_REJECTED"
