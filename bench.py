@@ -25,6 +25,13 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector and matrix
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+
+WORKLOAD_TEXT = {
+    "cfg2": "H- energy scan, L=0, quintic 64x64x24, x,y in [0,40] quadratic, 32 energies in [-0.6,-0.1], "
+            "seeded N(0,1) RHS",
+    "cfg3": "Ps- like (1,1,1)/(+1,-1,-1), L=0, quintic x,y 127 on [0,20] x cubic z 32, E=-0.25, seeded RHS",
+    "cfg4": "Ps- like, L=2 tau=+1 (3 M' blocks), quintic x,y 97 on [0,20] x cubic z 32, E=-0.2, seeded RHS",
+}
 sys.path.insert(0, ROOT)
 
 
@@ -60,20 +67,93 @@ def cpu_baseline(seconds_cap=30.0):
                       f"(N={O.N}), {n_done} of the 32 energies, {dt:.1f} s"}
 
 
+def serve_bench(args):
+    """Serving: the seeded request stream, first all at once (saturation
+    throughput), then with Poisson arrivals at 0.8 x that throughput; p50/p99
+    of submit-to-done latency and solves/s of the Poisson phase."""
+    import numpy as np
+    from paper_2005_05398_amd import fm
+    from paper_2005_05398_amd import workloads as W
+
+    reqs = [W.cfg5_request(i) for i in range(args.requests)]
+
+    def run(indices, arrivals):
+        srv = fm.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
+        done = {}
+        t0 = time.perf_counter()
+        k = 0
+        while len(done) < len(indices):
+            now = time.perf_counter() - t0
+            while k < len(indices) and arrivals[k] <= now:
+                r = reqs[indices[k]]
+                N = W.n_unknowns(r["desc"])
+                b = W.rhs(r["seed"], N)
+                srv.submit(r["desc"], r["E"], b, np.zeros(N), indices[k], restart=args.serve_restart,
+                           rtol=1e-10, max_iters=3000, prec=args.prec)
+                k += 1
+            block = k >= len(indices)
+            for o in srv.poll(block=block):
+                done[o["tag"]] = o
+            if not block:
+                time.sleep(0.002)
+        wall = time.perf_counter() - t0
+        srv.close()
+        return done, wall
+
+    nsat = min(len(reqs), args.saturation_requests)
+    sat, sat_wall = run(list(range(nsat)), np.zeros(nsat))
+    sat_rate = nsat / sat_wall
+    rate = 0.8 * sat_rate
+    arrivals = W.cfg5_arrivals(len(reqs), rate)
+    done, wall = run(list(range(len(reqs))), arrivals)
+    lat = np.array([o["t_done"] - o["t_submit"] for o in done.values()])
+    status = {}
+    for o in done.values():
+        status[o["status"]] = status.get(o["status"], 0) + 1
+    ok = [o for o in done.values() if o["status"] == "FM_OK"]
+    line = {
+        "metric": "serving: solves/s at rel. residual 1e-10 and p50/p99 latency (Poisson arrivals)",
+        "value": len(ok) / wall, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}", "data": "synthetic",
+        "config": {"workload": "seeded stream: quintic x,y {31,64,97,127} x cubic z {8,16,32}, L in {0,1,2}, "
+                               "E in [-0.6,-0.05], two particle sets, seeded N(0,1) RHS",
+                   "requests": len(reqs), "max_batch": args.max_batch, "restart": args.serve_restart,
+                   "budget_gb": args.budget_gb},
+        "saturation": {"requests": nsat, "solves_per_s": sat_rate, "wall_s": sat_wall},
+        "arrival_rate_per_s": rate,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean()), "max": float(lat.max())},
+        "status_counts": status,
+        "wall_s": wall,
+        "iters_mean": float(np.mean([o["iters"] for o in ok])) if ok else None,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--restart", type=int, default=300)
+    ap.add_argument("--restart", type=int, default=None, help="default: 300 (cfg2), 60 (cfg3, cfg4)")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the reduced-precision comparison runs")
+    ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--saturation-requests", type=int, default=64)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--serve-restart", type=int, default=100)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch
@@ -82,8 +162,10 @@ def main():
     from paper_2005_05398_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    c = W.cfg2()
+    c = W.CONFIGS[args.workload]()
     desc, Es, seeds = c["desc"], c["E"], c["seeds"]
+    if args.restart is None:
+        args.restart = 300 if args.workload == "cfg2" else 60
     t_setup = time.perf_counter()
     P = fm.Problem(desc)
     t_setup = time.perf_counter() - t_setup
@@ -138,7 +220,8 @@ def main():
     roof.update({"kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"], "traffic": None})
     total_kernel_ms = sum(v["ms"] for v in prof.values())
     line = {
-        "metric": "solves/s to rel. residual 1e-10 (FP64, batched energy scan)",
+        "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "cfg2"
+                   else f"solves/s to rel. residual 1e-10 ({args.workload})"),
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
@@ -150,8 +233,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}",
         "data": "synthetic",
-        "config": {"workload": "H- energy scan, L=0, quintic 64x64x24, x,y in [0,40] quadratic, "
-                               "32 energies in [-0.6,-0.1], seeded N(0,1) RHS",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "N_per_request": P.N, "requests_per_step": nreq, "restart": args.restart,
                    "precond_products": args.prec, "rtol": 1e-10},
         "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
@@ -186,7 +268,7 @@ def main():
                            "max_rel_residual": max(r["rel_residual"] for r in res_lp),
                            "max_rel_error_vs_fp64_gpu": err}
         line["mixed_precision"] = mixed
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "cfg2":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))
 

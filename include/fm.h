@@ -146,10 +146,13 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
                            double *z_dev, int prec, void *stream);
 
 /* Solve (H - E_r S) x_r = b_r for nbatch requests that share the problem
- * (an energy scan), by right-preconditioned flexible GMRES(restart) with
- * classical Gram-Schmidt and one reorthogonalisation, FP64 Arnoldi, Givens
- * rotations and an FP64 true residual at every restart (Sec. 4 names
- * preconditioned GMRES as the linear solver of the method).  Each request
+ * (an energy scan), by right-preconditioned flexible GMRES(restart) with an
+ * FP64 Arnoldi process that orthogonalises twice (classical Gram-Schmidt, the
+ * second projection of each direction delayed to the next step so that one
+ * step makes one pass of dot products and one pass of updates over the
+ * basis), Givens rotations and an FP64 true residual at every restart (Sec. 4
+ * names preconditioned GMRES as the linear solver of the method).  restart:
+ * 1..1000.  Each request
  * stops on its own when its true residual meets rtol.  results: host array
  * of nbatch entries (may be NULL).  Returns FM_OK when every request
  * converged, FM_E_NOT_CONVERGED if any did not (x holds the last iterate),
@@ -219,13 +222,12 @@ typedef enum {
     FM_K_MATVEC = 0,    /* operator (H - E S) x */
     FM_K_MODEZ = 1,     /* preconditioner z-mode products */
     FM_K_XY = 2,        /* preconditioner x-y slice products and divide */
-    FM_K_MDOT = 3,      /* Arnoldi projections V^T w */
-    FM_K_MUPDATE = 4,   /* Arnoldi updates w -= V h */
-    FM_K_NORM = 5,      /* norm, Givens rotation, residual estimate */
-    FM_K_SCALE = 6,     /* v_{j+1} = w / h */
-    FM_K_RESTART = 7,   /* per-cycle solution update and true residual */
-    FM_K_COUPLING = 8,  /* operator: coupling to the other components (FM_K_MATVEC: the rest) */
-    FM_K_COUNT = 9
+    FM_K_MDOT = 3,      /* Arnoldi dot pass: basis^T [new direction, its image] */
+    FM_K_MUPDATE = 4,   /* Arnoldi update pass: normalise the direction, project the image */
+    FM_K_FINISH = 5,    /* per-request step completion: Hessenberg column, Givens, residual estimate */
+    FM_K_RESTART = 6,   /* per-cycle solution update and true residual */
+    FM_K_COUPLING = 7,  /* operator: coupling to the other components (FM_K_MATVEC: the rest) */
+    FM_K_COUNT = 8
 } fm_kernel_class;
 
 fm_status fm_profile(fm_problem *p, int enable);

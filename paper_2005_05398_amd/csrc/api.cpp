@@ -148,9 +148,9 @@ size_t krylov_bytes(long long N, int nb, int m) {
     b += round256(sizeof(double) * size_t(nb) * (m + 1) * m); // H
     b += 4 * round256(sizeof(double) * size_t(nb) * (m + 1)); // g, hcol, hproj, y
     b += 2 * round256(sizeof(double) * size_t(nb) * m);       // cs, sn
-    b += round256(sizeof(double) * size_t(nb) * (m + 1) * NBLK);
-    b += 5 * round256(sizeof(double) * nb);                   // bnorm rnorm scal E tol
-    b += 4 * round256(sizeof(int) * nb);                      // ticket active jcount flags
+    b += round256(sizeof(double) * size_t(nb) * (2 * m + 3) * NBLK);
+    b += 6 * round256(sizeof(double) * nb);                   // bnorm rnorm scal rho E tol
+    b += 5 * round256(sizeof(int) * nb);                      // ticket active jcount flags closed
     return b;
 }
 
@@ -173,16 +173,18 @@ char *carve_krylov(char *c, long long N, int nb, int m, KrylovDev &K) {
     K.y = (double *)take(sizeof(double) * size_t(nb) * (m + 1));
     K.cs = (double *)take(sizeof(double) * size_t(nb) * m);
     K.sn = (double *)take(sizeof(double) * size_t(nb) * m);
-    K.part = (double *)take(sizeof(double) * size_t(nb) * (m + 1) * NBLK);
+    K.part = (double *)take(sizeof(double) * size_t(nb) * (2 * m + 3) * NBLK);
     K.bnorm = (double *)take(sizeof(double) * nb);
     K.rnorm = (double *)take(sizeof(double) * nb);
     K.scal = (double *)take(sizeof(double) * nb);
+    K.rho = (double *)take(sizeof(double) * nb);
     K.E = (double *)take(sizeof(double) * nb);
     K.tol = (double *)take(sizeof(double) * nb);
     K.ticket = (unsigned *)take(sizeof(int) * nb);
     K.active = (int *)take(sizeof(int) * nb);
     K.jcount = (int *)take(sizeof(int) * nb);
     K.flags = (int *)take(sizeof(int) * nb);
+    K.closed = (int *)take(sizeof(int) * nb);
     return c;
 }
 
@@ -254,8 +256,10 @@ struct Work {
     double coupling() const { return 8 * 3 * N; }
     double modez() const { return 8 * 2 * N; }
     double xy() const { return 8 * 2 * N; }
-    double mdot(int j) const { return 8 * (j + 2) * N; }
-    double mupdate(int j) const { return 8 * (j + 3) * N; }
+    // Arnoldi step j: the dot pass reads Q (j vectors), U and W; the update pass
+    // reads them too and writes U and W
+    double dots(int j) const { return 8 * (j + 2) * N; }
+    double update(int j) const { return 8 * (j + 4) * N; }
 };
 
 void add_precond_work(fm_problem *p, const Work &w, double nreq) {
@@ -274,13 +278,20 @@ void apply_operator(fm_problem *p, int nb, const double *E_dev, const int *mask,
     timed(p, st, FM_K_COUPLING, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, st, 2); });
 }
 
-void add_step_work(fm_problem *p, const Work &w, int j) {
+// Work of Arnoldi step j for one request: update = false for the step on which
+// the request met its tolerance (no update pass follows).
+void add_step_work(fm_problem *p, const Work &w, int j, bool update) {
     add_precond_work(p, w, 1);
     add_matvec_work(p, w, 1);
-    prof_work(p, FM_K_MDOT, 2 * w.mdot(j), 4.0 * (j + 1) * w.N);
-    prof_work(p, FM_K_MUPDATE, 2 * w.mupdate(j), 4.0 * (j + 1) * w.N);
-    prof_work(p, FM_K_NORM, 8 * w.N, 2 * w.N);
-    prof_work(p, FM_K_SCALE, 16 * w.N, 0);
+    prof_work(p, FM_K_MDOT, w.dots(j), 2.0 * (2 * j + 2) * w.N);
+    prof_work(p, FM_K_FINISH, 0, 6.0 * j + 4.0 * j);
+    if (update) prof_work(p, FM_K_MUPDATE, w.update(j), (4.0 * j + 4) * w.N);
+}
+
+// Closing pass after `steps` steps: dots over Q and U only, then the finish.
+void add_closing_work(fm_problem *p, const Work &w, int steps) {
+    prof_work(p, FM_K_MDOT, 8.0 * (steps + 1) * w.N, 2.0 * (steps + 1) * w.N);
+    prof_work(p, FM_K_FINISH, 0, 10.0 * steps);
 }
 
 void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
@@ -427,40 +438,46 @@ fm_status Batch::cycle(const std::function<bool()> &want_cut, int min_steps) {
     const int nb = cap;
     const long long N = p->N;
     const int poll = 4;
+    int steps = 0;
     for (int j = 0; j < m; ++j) {
         double *Vj = K.V + (long long)j * nb * N;
         double *Zj = K.Z + (long long)j * nb * N;
         double *Vn = K.V + (long long)(j + 1) * nb * N;
         apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, st);
         apply_operator(p, nb, K.E, K.active, Zj, Vn, st);
-        timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 0, st); });
-        timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
-        timed(p, st, FM_K_MDOT, [&] { launch_mdot(K, j, Vn, 1, st); });
-        timed(p, st, FM_K_MUPDATE, [&] { launch_mupdate(K, j, Vn, st); });
-        timed(p, st, FM_K_NORM, [&] { launch_norm_givens(K, j, Vn, st); });
-        timed(p, st, FM_K_SCALE, [&] { launch_scale_next(K, j, st); });
-        if ((j + 1) % poll == 0 && j + 1 < m) {
+        timed(p, st, FM_K_MDOT, [&] { launch_arnoldi_dots(K, j, 0, st); });
+        timed(p, st, FM_K_FINISH, [&] { launch_arnoldi_finish(K, j, 0, st); });
+        timed(p, st, FM_K_MUPDATE, [&] { launch_arnoldi_update(K, j, st); });
+        steps = j + 1;
+        if (steps % poll == 0 && steps < m) {
             HIP_TRY(hipMemcpyAsync(hbuf, K.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             bool any = false;
             for (int i = 0; i < nb; ++i) any |= hbuf[i] != 0;
             if (!any) break;
-            if (want_cut && j + 1 >= min_steps && want_cut()) {
-                HIP_TRY(hipMemsetAsync(K.active, 0, sizeof(int) * nb, st));
-                break;
-            }
+            if (want_cut && steps >= min_steps && want_cut()) break;
         }
     }
+    // the last column of the requests still iterating
+    timed(p, st, FM_K_MDOT, [&] { launch_arnoldi_dots(K, steps, 1, st); });
+    timed(p, st, FM_K_FINISH, [&] { launch_arnoldi_finish(K, steps, 1, st); });
     HIP_TRY(hipGetLastError());
+    std::vector<int> closed(nb);
     HIP_TRY(hipMemcpyAsync(hbuf, K.jcount, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(closed.data(), K.closed, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     prof_collect(p);
     Work w(p);
     for (int i = 0; i < nb; ++i)
         if (run[i]) {
-            last_steps[i] = hbuf[i];
-            for (int j = 0; j < hbuf[i]; ++j) add_step_work(p, w, j);
-            iters[i] += std::max(1, hbuf[i]);     // every cycle counts as progress
+            const int jc = hbuf[i];
+            last_steps[i] = jc;
+            if (p->prof.on) {
+                for (int j = 0; j < jc; ++j) add_step_work(p, w, j, true);
+                if (closed[i]) add_closing_work(p, w, jc);
+                else add_step_work(p, w, jc, false);
+            }
+            iters[i] += std::max(1, jc);     // every cycle counts as progress
             restarts[i] += 1;
         }
     return FM_OK;
@@ -720,7 +737,7 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
                    const fm_solve_opts *opts, fm_solve_result *results, void *stream) {
     if (!p || !E || !b_dev || !x_dev || !opts || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
     const int m = opts->restart;
-    if (m < 1 || m > 1000) return fail(FM_E_INVALID, "restart must be in [1, 1000]");
+    if (m < 1 || m > MAX_RESTART) return fail(FM_E_INVALID, "restart must be in [1, 1000]");
     if (!(opts->rtol > 0)) return fail(FM_E_INVALID, "rtol must be positive");
     if (opts->max_iters < 1) return fail(FM_E_INVALID, "max_iters must be >= 1");
     if (opts->prec != FM_FP64 && opts->prec != FM_FP32 && opts->prec != FM_BF16X3)

@@ -118,21 +118,24 @@ struct KrylovDev {
     double *H;                   // [nb][m+1][m]   (rotated: upper triangle R)
     double *g;                   // [nb][m+1]
     double *cs, *sn;             // [nb][m]
-    double *hcol;                // [nb][m+1] Hessenberg column being built
-    double *hproj;               // [nb][m+1] current projection coefficients
+    double *hcol;                // [nb][m+1] t and c of the last step (its column before the delayed part)
+    double *hproj;               // [nb][m+1] s of the last step (second projection of its direction)
     double *y;                   // [nb][m]
-    double *part;                // [nb][m+1][NBLK] reduction partials
+    double *part;                // [nb][2m+3][NBLK] reduction partials
     unsigned *ticket;            // [nb]
     int *active;                 // [nb] 1 while the request iterates in this cycle
     int *jcount;                 // [nb] Arnoldi steps in this cycle
     double *bnorm, *rnorm;       // [nb]
-    double *scal;                // [nb] scratch scalar (norms)
+    double *scal;                // [nb] r_j of the last step
+    double *rho;                 // [nb] scale of the newest direction
     double *E;                   // [nb]
     double *tol;                 // [nb] absolute inner tolerance
     int *flags;                  // [nb] breakdown / nonfinite flags
+    int *closed;                 // [nb] 1: the cycle ended on its closing pass (not on convergence)
 };
 
-constexpr int NBLK = 256;        // blocks per request in the reduction kernels
+constexpr int NBLK = 1024;       // at most this many blocks per request in the reduction kernels
+constexpr int MAX_RESTART = 1000;
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).
@@ -149,10 +152,11 @@ void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int 
 bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
                   double *data, int mode, hipStream_t st);
 // Arnoldi / GMRES pieces (V and Z stored [i][request][N])
-void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st);
-void launch_mupdate(const KrylovDev &k, int j, double *w, hipStream_t st);
-void launch_norm_givens(const KrylovDev &k, int j, double *w, hipStream_t st);
-void launch_scale_next(const KrylovDev &k, int j, hipStream_t st);
+// Step j: dot pass over slots 0..j+1 (0..j when closing), then the per-request
+// finish (Hessenberg column j - 1, Givens, stop test), then the update pass.
+void launch_arnoldi_dots(const KrylovDev &k, int j, int closing, hipStream_t st);
+void launch_arnoldi_finish(const KrylovDev &k, int j, int closing, hipStream_t st);
+void launch_arnoldi_update(const KrylovDev &k, int j, hipStream_t st);
 void launch_cycle_solve(const KrylovDev &k, const int *running, hipStream_t st);
 void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream_t st);
 void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,

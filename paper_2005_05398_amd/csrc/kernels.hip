@@ -584,7 +584,7 @@ __device__ void block_divide(double *T, int ld, int nx, int ny, const double *lx
                              const signed char *tx, const double *ly, const double *lyi, const signed char *ty,
                              double E, double *min_den) {
     double mind = 1e300;
-    for (int oo = threadIdx.x; oo < nx * ny; oo += XY_THREADS) {
+    for (int oo = threadIdx.x; oo < nx * ny; oo += blockDim.x) {
         const int i = oo / ny, j = oo % ny;
         const int o = i * ld + j;
         const int ti = tx[i], tj = ty[j];
@@ -624,10 +624,10 @@ __device__ void block_divide(double *T, int ld, int nx, int ny, const double *lx
     }
     if (min_den) {
         // block minimum, then one atomic per block on the bit pattern (positive doubles)
-        __shared__ double red[XY_THREADS];
+        __shared__ double red[512];
         red[threadIdx.x] = mind;
         __syncthreads();
-        for (int s = XY_THREADS / 2; s > 0; s >>= 1) {
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
             if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
             __syncthreads();
         }
@@ -677,7 +677,7 @@ constexpr int XYM_MAXT = 16;        // tiles per wave: (128/16)^2 / 4
 
 // T <- Wm T (LEFT, Wm: nx x nx) or T <- T Wm^T (!LEFT, Wm: ny x ny); at most
 // MAXT output tiles per wave.
-template <bool LEFT, int MAXT>
+template <bool LEFT, int MAXT, int NW>
 __device__ void mfma_slice_mult(double *T, int ld, int nxp, int nyp, const double *__restrict__ Wm, int nw) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r16 = lane & 15, k4 = lane >> 4;
@@ -690,7 +690,7 @@ __device__ void mfma_slice_mult(double *T, int ld, int nxp, int nyp, const doubl
         const int kk = k0 + k4;
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
-            const int t = wave + 4 * q;
+            const int t = wave + NW * q;
             if (t < ntiles) {
                 const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
                 double a, b;
@@ -710,7 +710,7 @@ __device__ void mfma_slice_mult(double *T, int ld, int nxp, int nyp, const doubl
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) {
-        const int t = wave + 4 * q;
+        const int t = wave + NW * q;
         if (t < ntiles) {
             const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
 #pragma unroll
@@ -720,8 +720,8 @@ __device__ void mfma_slice_mult(double *T, int ld, int nxp, int nyp, const doubl
     __syncthreads();
 }
 
-template <int MAXT>
-__global__ void __launch_bounds__(XY_THREADS) k_xy_mfma(const ProblemDev *__restrict__ pd,
+template <int MAXT, int NW>
+__global__ void __launch_bounds__(NW * 64) k_xy_mfma(const ProblemDev *__restrict__ pd,
                                                         const PrecDev *__restrict__ pr,
                                                         const double *__restrict__ Evec,
                                                         const int *__restrict__ active, double *data,
@@ -738,7 +738,7 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy_mfma(const ProblemDev *__rest
     const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, ld = nyp + 4;
     extern __shared__ double T[];
     double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
-    for (int t = threadIdx.x; t < nxp * ld; t += XY_THREADS) {
+    for (int t = threadIdx.x; t < nxp * ld; t += NW * 64) {
         const int i = t / ld, j = t % ld;
         T[t] = (i < nx && j < ny) ? g[i * ny + j] : 0.0;
     }
@@ -746,13 +746,13 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy_mfma(const ProblemDev *__rest
     const size_t fx = (size_t)iM * nz + k;
     const double *Wbx = F.Wx + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
     const double *Wby = F.Wy + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
-    mfma_slice_mult<true, MAXT>(T, ld, nxp, nyp, Wbx, nx);
-    mfma_slice_mult<false, MAXT>(T, ld, nxp, nyp, Wby, ny);
+    mfma_slice_mult<true, MAXT, NW>(T, ld, nxp, nyp, Wbx, nx);
+    mfma_slice_mult<false, MAXT, NW>(T, ld, nxp, nyp, Wby, ny);
     block_divide(T, ld, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
                  F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
-    mfma_slice_mult<true, MAXT>(T, ld, nxp, nyp, Wx, nx);
-    mfma_slice_mult<false, MAXT>(T, ld, nxp, nyp, Wy, ny);
-    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) g[t] = T[(t / ny) * ld + t % ny];
+    mfma_slice_mult<true, MAXT, NW>(T, ld, nxp, nyp, Wx, nx);
+    mfma_slice_mult<false, MAXT, NW>(T, ld, nxp, nyp, Wy, ny);
+    for (int t = threadIdx.x; t < nx * ny; t += NW * 64) g[t] = T[(t / ny) * ld + t % ny];
 }
 
 // ---------------------------------------------------------------------------
@@ -777,7 +777,7 @@ __device__ __forceinline__ void split_bf16(float a, short &hi, short &mid) {
     mid = (short)f32_to_bf16(a - bf16_to_f32(h));
 }
 
-template <bool LEFT, int MAXT>
+template <bool LEFT, int MAXT, int NW>
 __device__ void mfma32_slice_mult(float *T, int ld, int nxp, int nyp, const float *__restrict__ Wm, int nw) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r16 = lane & 15, k4 = lane >> 4;
@@ -790,7 +790,7 @@ __device__ void mfma32_slice_mult(float *T, int ld, int nxp, int nyp, const floa
         const int kk = k0 + k4;
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
-            const int t = wave + 4 * q;
+            const int t = wave + NW * q;
             if (t < ntiles) {
                 const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
                 float a, b;
@@ -810,7 +810,7 @@ __device__ void mfma32_slice_mult(float *T, int ld, int nxp, int nyp, const floa
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) {
-        const int t = wave + 4 * q;
+        const int t = wave + NW * q;
         if (t < ntiles) {
             const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
 #pragma unroll
@@ -821,7 +821,7 @@ __device__ void mfma32_slice_mult(float *T, int ld, int nxp, int nyp, const floa
 }
 
 // W16: bfloat16 planes of Wm, [0] = hi, [1] = mid (plane stride pstride).
-template <bool LEFT, int MAXT>
+template <bool LEFT, int MAXT, int NW>
 __device__ void mfma_bf3_slice_mult(float *T, int ld, int nxp, int nyp, const unsigned short *__restrict__ W16,
                                     size_t pstride, int nw) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -835,7 +835,7 @@ __device__ void mfma_bf3_slice_mult(float *T, int ld, int nxp, int nyp, const un
         const int kk = k0 + g4;
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
-            const int t = wave + 4 * q;
+            const int t = wave + NW * q;
             if (t < ntiles) {
                 const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
                 sht4 dhi, dmid, whi, wmid;       // data and factor operands
@@ -867,7 +867,7 @@ __device__ void mfma_bf3_slice_mult(float *T, int ld, int nxp, int nyp, const un
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) {
-        const int t = wave + 4 * q;
+        const int t = wave + NW * q;
         if (t < ntiles) {
             const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
 #pragma unroll
@@ -881,7 +881,7 @@ __device__ void mfma_bf3_slice_mult(float *T, int ld, int nxp, int nyp, const un
 __device__ void block_divide_f32(float *T, int ld, int nx, int ny, const double *lx, const double *lxi,
                                  const signed char *tx, const double *ly, const double *lyi, const signed char *ty,
                                  double E) {
-    for (int oo = threadIdx.x; oo < nx * ny; oo += XY_THREADS) {
+    for (int oo = threadIdx.x; oo < nx * ny; oo += blockDim.x) {
         const int i = oo / ny, j = oo % ny;
         const int o = i * ld + j;
         const int ti = tx[i], tj = ty[j];
@@ -913,8 +913,8 @@ __device__ void block_divide_f32(float *T, int ld, int nx, int ny, const double 
     __syncthreads();
 }
 
-template <int MAXT, int MODE>
-__global__ void __launch_bounds__(XY_THREADS) k_xy_lp(const ProblemDev *__restrict__ pd,
+template <int MAXT, int MODE, int NW>
+__global__ void __launch_bounds__(NW * 64) k_xy_lp(const ProblemDev *__restrict__ pd,
                                                       const PrecDev *__restrict__ pr,
                                                       const double *__restrict__ Evec,
                                                       const int *__restrict__ active, double *data) {
@@ -930,7 +930,7 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy_lp(const ProblemDev *__restri
     const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, ld = nyp + 4;
     extern __shared__ float Tf[];
     double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
-    for (int t = threadIdx.x; t < nxp * ld; t += XY_THREADS) {
+    for (int t = threadIdx.x; t < nxp * ld; t += NW * 64) {
         const int i = t / ld, j = t % ld;
         Tf[t] = (i < nx && j < ny) ? (float)g[i * ny + j] : 0.f;
     }
@@ -939,24 +939,24 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy_lp(const ProblemDev *__restri
     if (MODE == 1) {
         const float *Wbx = F.Wx32 + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
         const float *Wby = F.Wy32 + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
-        mfma32_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wbx, nx);
-        mfma32_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wby, ny);
+        mfma32_slice_mult<true, MAXT, NW>(Tf, ld, nxp, nyp, Wbx, nx);
+        mfma32_slice_mult<false, MAXT, NW>(Tf, ld, nxp, nyp, Wby, ny);
         block_divide_f32(Tf, ld, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny,
                          F.lyi + fx * ny, F.ty + fx * ny, Evec[req]);
-        mfma32_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wx, nx);
-        mfma32_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wy, ny);
+        mfma32_slice_mult<true, MAXT, NW>(Tf, ld, nxp, nyp, Wx, nx);
+        mfma32_slice_mult<false, MAXT, NW>(Tf, ld, nxp, nyp, Wy, ny);
     } else {
         const size_t px = (size_t)pd->nM * nz * 2 * nx * nx, py = (size_t)pd->nM * nz * 2 * ny * ny;
         const unsigned short *Wbx = F.Wx16 + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
         const unsigned short *Wby = F.Wy16 + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
-        mfma_bf3_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wbx, px, nx);
-        mfma_bf3_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wby, py, ny);
+        mfma_bf3_slice_mult<true, MAXT, NW>(Tf, ld, nxp, nyp, Wbx, px, nx);
+        mfma_bf3_slice_mult<false, MAXT, NW>(Tf, ld, nxp, nyp, Wby, py, ny);
         block_divide_f32(Tf, ld, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny,
                          F.lyi + fx * ny, F.ty + fx * ny, Evec[req]);
-        mfma_bf3_slice_mult<true, MAXT>(Tf, ld, nxp, nyp, Wx, px, nx);
-        mfma_bf3_slice_mult<false, MAXT>(Tf, ld, nxp, nyp, Wy, py, ny);
+        mfma_bf3_slice_mult<true, MAXT, NW>(Tf, ld, nxp, nyp, Wx, px, nx);
+        mfma_bf3_slice_mult<false, MAXT, NW>(Tf, ld, nxp, nyp, Wy, py, ny);
     }
-    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) g[t] = (double)Tf[(t / ny) * ld + t % ny];
+    for (int t = threadIdx.x; t < nx * ny; t += NW * 64) g[t] = (double)Tf[(t / ny) * ld + t % ny];
 }
 
 // Mode-z products in FP32 (the pass is bound by HBM traffic of FP64 vectors).
@@ -1031,131 +1031,255 @@ __device__ __forceinline__ void chunk_range(long long N, int blk, long long &lo,
     hi = min(N, lo + per);
 }
 
-// hproj[i] = v_i . w for i <= j; hcol = hproj (accumulate = 0) or hcol += hproj.
-// Grid: (blocks per request, groups of MD_G vectors, requests).  Each thread
-// keeps MD_G partial sums; one wave-level and one cross-wave reduction per block.
-__global__ void __launch_bounds__(RT) k_mdot(KrylovDev K, int j, const double *__restrict__ W, int accumulate) {
+// Sum of the n partials p[0..n) by one wave; the result is valid in every lane.
+__device__ __forceinline__ double wave_sum_parts(const double *__restrict__ p, int n) {
+    double s = 0;
+    for (int b = threadIdx.x & 63; b < n; b += 64) s += p[b];
+    return wave_sum(s);
+}
+
+// Sum of the n partials p[0..n) by the block; valid in every thread.
+__device__ __forceinline__ double block_sum_parts(const double *__restrict__ p, int n, double *red) {
+    double s = 0;
+    for (int b = threadIdx.x; b < n; b += RT) s += p[b];
+    return block_sum(s, red);
+}
+
+// Arnoldi with delayed reorthogonalisation (one dot pass and one update pass
+// per step).  At step j the Krylov slots hold Q = v_0..v_{j-1} (orthonormal),
+// U = v_j (the new direction, projected once against Q, not yet normalised) and
+// W = v_{j+1} = A M^-1 U.  The dot pass forms s = Q^T U, t = Q^T W, U.U, U.W
+// and W.W together; U then receives its second projection, q_j = (U - Q s) / r_j
+// with r_j^2 = U.U - s.s, and W its first, (W - Q t - c_j q_j) / rho_j with
+// c_j = q_j.W = (U.W - s.t) / r_j and rho_j^2 = W.W - t.t - c_j^2 (the norm of
+// the projected W by Pythagoras; the scaling keeps the directions near unit
+// length, so that their size does not grow or shrink step after step).  The
+// Hessenberg column of step j - 1 is complete once s and r_j are known:
+// h_{i,j-1} = t_i + rho_{j-1} s_i (with t_{j-1} = c_{j-1}) and
+// h_{j,j-1} = rho_{j-1} r_j.  Since the preconditioner is applied to U,
+// A M^-1 U is expressed in the orthonormal basis by exactly this column, and
+// the solution update uses the stored M^-1 U directly.
+//
+// Dot pass partials, stride nblk per row: s_i at row i, t_i at row j + i,
+// U.U at row 2j, U.W at 2j + 1, W.W at 2j + 2.  CLOSING: no W (the last
+// column of a cycle).
+// Grid: (blocks per request, groups of MD_G vectors of Q, requests).
+template <bool CLOSING>
+__global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     const int req = blockIdx.z;
     if (!K.active[req]) return;
-    __shared__ double red[MD_G][RT / 64];
+    __shared__ double red[2 * MD_G + 3][RT / 64];
     const int g0 = blockIdx.y * MD_G;
-    const int ng = min(MD_G, j + 1 - g0);
+    const int ng = max(0, min(MD_G, j - g0));
+    const bool lead = blockIdx.y == 0;
     const int nblk = gridDim.x;
-    const long long per = (K.N + nblk - 1) / nblk;
-    const long long lo = blockIdx.x * per, hi = min(K.N, lo + per);
-    const double *w = W + (long long)req * K.N;
+    long long lo, hi;
+    chunk_range(K.N, blockIdx.x, lo, hi);
     const long long vstride = (long long)K.nb * K.N;
-    const double *v0 = K.V + (long long)g0 * vstride + (long long)req * K.N;
-    double acc[MD_G];
+    const double *U = K.V + (long long)j * vstride + (long long)req * K.N;
+    const double *W = U + vstride;
+    const double *q0 = K.V + (long long)g0 * vstride + (long long)req * K.N;
+    double as[MD_G], at[MD_G];
+    double uu = 0, uw = 0, ww = 0;
 #pragma unroll
-    for (int t = 0; t < MD_G; ++t) acc[t] = 0;
+    for (int t = 0; t < MD_G; ++t) as[t] = at[t] = 0;
     long long e = lo + threadIdx.x;
     for (; e + RT < hi; e += 2 * RT) {
-        const double we0 = w[e], we1 = w[e + RT];
+        const double u0 = U[e], u1 = U[e + RT];
+        const double w0 = CLOSING ? 0.0 : W[e], w1 = CLOSING ? 0.0 : W[e + RT];
+        uu += u0 * u0 + u1 * u1;
+        uw += u0 * w0 + u1 * w1;
+        ww += w0 * w0 + w1 * w1;
 #pragma unroll
         for (int t = 0; t < MD_G; ++t)
-            if (t < ng) acc[t] += v0[t * vstride + e] * we0 + v0[t * vstride + e + RT] * we1;
+            if (t < ng) {
+                const double *q = q0 + t * vstride + e;
+                const double a0 = q[0], a1 = q[RT];
+                as[t] += a0 * u0 + a1 * u1;
+                if (!CLOSING) at[t] += a0 * w0 + a1 * w1;
+            }
     }
-    if (e < hi) {
-        const double we = w[e];
+    for (; e < hi; e += RT) {
+        const double u0 = U[e], w0 = CLOSING ? 0.0 : W[e];
+        uu += u0 * u0;
+        uw += u0 * w0;
+        ww += w0 * w0;
 #pragma unroll
         for (int t = 0; t < MD_G; ++t)
-            if (t < ng) acc[t] += v0[t * vstride + e] * we;
+            if (t < ng) {
+                const double a0 = q0[t * vstride + e];
+                as[t] += a0 * u0;
+                if (!CLOSING) at[t] += a0 * w0;
+            }
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int t = 0; t < MD_G; ++t) {
-        double s = wave_sum(acc[t]);
-        if (lane == 0) red[t][wave] = s;
-    }
-    __syncthreads();
-    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
-    if (threadIdx.x < ng) {
-        double s = 0;
-        for (int wv = 0; wv < RT / 64; ++wv) s += red[threadIdx.x][wv];
-        part[(size_t)(g0 + threadIdx.x) * NBLK + blockIdx.x] = s;
-    }
-    if (last_block(&K.ticket[req], nblk * gridDim.y)) {
-        for (int i = threadIdx.x; i <= j; i += RT) {
-            double s = 0;
-            for (int b = 0; b < nblk; ++b) s += part[(size_t)i * NBLK + b];
-            K.hproj[(size_t)req * (K.m + 1) + i] = s;
-            double *hc = K.hcol + (size_t)req * (K.m + 1) + i;
-            *hc = accumulate ? *hc + s : s;
-        }
-        if (threadIdx.x == 0) K.ticket[req] = 0;
-    }
-}
-
-// w -= sum_{i <= j} v_i hproj[i]
-__global__ void __launch_bounds__(RT) k_mupdate(KrylovDev K, int j, double *W) {
-    const int req = blockIdx.y;
-    if (!K.active[req]) return;
-    __shared__ double h[1024];
-    const double *hp = K.hproj + (size_t)req * (K.m + 1);
-    for (int i = threadIdx.x; i <= j; i += RT) h[i] = hp[i];
-    __syncthreads();
-    long long e = (long long)blockIdx.x * RT + threadIdx.x;
-    if (e >= K.N) return;
-    double acc = W[(long long)req * K.N + e];
-    for (int i = 0; i <= j; ++i) acc -= K.V[((long long)i * K.nb + req) * K.N + e] * h[i];
-    W[(long long)req * K.N + e] = acc;
-}
-
-// ||w||, then the Hessenberg column j, Givens rotations, residual estimate.
-__global__ void __launch_bounds__(RT) k_norm_givens(KrylovDev K, int j, const double *__restrict__ W) {
-    const int req = blockIdx.y;
-    if (!K.active[req]) return;
-    __shared__ double red[RT];
-    long long lo, hi;
-    chunk_range(K.N, blockIdx.x, lo, hi);
-    const double *w = W + (long long)req * K.N;
-    double acc = 0;
-    for (long long e = lo + threadIdx.x; e < hi; e += RT) acc += w[e] * w[e];
-    double s = block_sum(acc, red);
-    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(&K.ticket[req], gridDim.x)) {
-        if (threadIdx.x == 0) {
-            double nn = 0;
-            for (int b = 0; b < (int)gridDim.x; ++b) nn += part[b];
-            double hn = sqrt(nn);
-            const int m = K.m;
-            double *hc = K.hcol + (size_t)req * (m + 1);
-            double *H = K.H + (size_t)req * (m + 1) * m;
-            double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m, *g = K.g + (size_t)req * (m + 1);
-            for (int i = 0; i < j; ++i) {
-                double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
-                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-                hc[i] = t;
+    for (int t = 0; t < MD_G; ++t)
+        if (t < ng) {
+            const double a = wave_sum(as[t]), b = wave_sum(at[t]);
+            if (lane == 0) {
+                red[t][wave] = a;
+                red[MD_G + t][wave] = b;
             }
-            double r = hypot(hc[j], hn);
-            double c = r > 0 ? hc[j] / r : 1.0, sv = r > 0 ? hn / r : 0.0;
-            cs[j] = c;
-            sn[j] = sv;
-            hc[j] = r;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
-            g[j + 1] = -sv * g[j];
-            g[j] = c * g[j];
-            K.scal[req] = hn;
-            K.jcount[req] = j + 1;
-            const double est = fabs(g[j + 1]);
-            if (!(hn == hn) || !(est == est)) K.flags[req] |= 2;     // non-finite
-            if (est <= K.tol[req] || hn <= 1e-300 || j + 1 >= m || !(est == est)) K.active[req] = 0;
-            K.ticket[req] = 0;
         }
+    if (lead) {
+        const double a = wave_sum(uu), b = wave_sum(uw), c = wave_sum(ww);
+        if (lane == 0) {
+            red[2 * MD_G][wave] = a;
+            red[2 * MD_G + 1][wave] = b;
+            red[2 * MD_G + 2][wave] = c;
+        }
+    }
+    __syncthreads();
+    double *part = K.part + (size_t)req * (2 * K.m + 3) * NBLK;
+    const int r = threadIdx.x;
+    int row = -1;
+    if (r < ng) row = g0 + r;
+    else if (r >= MD_G && r < MD_G + ng) row = j + g0 + (r - MD_G);
+    else if (lead && r == 2 * MD_G) row = 2 * j;
+    else if (lead && r == 2 * MD_G + 1) row = 2 * j + 1;
+    else if (lead && r == 2 * MD_G + 2) row = 2 * j + 2;
+    if (row >= 0) {
+        double s = 0;
+        for (int wv = 0; wv < RT / 64; ++wv) s += red[r][wv];
+        part[(size_t)row * nblk + blockIdx.x] = s;
     }
 }
 
-// v_{j+1} = w / h_{j+1,j} in place (V slot j + 1).
-__global__ void __launch_bounds__(RT) k_scale(KrylovDev K, int j) {
+// Completes step j of every active request from the dot-pass partials: s, t,
+// r_j by Pythagoras (r_j = 0 when U.U - s.s is below 1e-20 U.U: U lies in the
+// span of Q), the Hessenberg column j - 1 with its Givens rotation and the
+// residual estimate |g_j|; a request leaves the cycle when that estimate meets
+// its tolerance, on breakdown, or when closing.  Otherwise stores s (hproj),
+// t and c_j (hcol), r_j (scal) and rho_j (rho; at least 1e-8 |W|, and 1 for
+// W = 0) for the update pass.  rho holds rho_{j-1} on entry (for j = 0 the
+// norm of the residual that v_0 was scaled by).  One block per request.
+__global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int nblk, int closing) {
+    const int req = blockIdx.x;
+    if (!K.active[req]) return;
+    __shared__ double sv[MAX_RESTART + 1], tv[MAX_RESTART + 1], col[MAX_RESTART + 1];
+    __shared__ double csv[MAX_RESTART], snv[MAX_RESTART];
+    __shared__ double red[RT / 64], uu_uw[3];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = K.m;
+    const double *part = K.part + (size_t)req * (2 * m + 3) * NBLK;
+    for (int row = wave; row < 2 * j + 3; row += RT / 64) {
+        const double s = wave_sum_parts(part + (size_t)row * nblk, nblk);
+        if (lane == 0) {
+            if (row < j) sv[row] = s;
+            else if (row < 2 * j) tv[row - j] = s;
+            else uu_uw[row - 2 * j] = s;
+        }
+    }
+    double *hc = K.hcol + (size_t)req * (m + 1);
+    double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m;
+    for (int i = threadIdx.x; i < j; i += RT) col[i] = hc[i];
+    for (int i = threadIdx.x; i + 1 < j; i += RT) {
+        csv[i] = cs[i];
+        snv[i] = sn[i];
+    }
+    __syncthreads();
+    const double rho = K.rho[req];
+    double ss = 0, st = 0, tt = 0;
+    for (int i = threadIdx.x; i < j; i += RT) {
+        ss += sv[i] * sv[i];
+        st += sv[i] * tv[i];
+        tt += tv[i] * tv[i];
+        col[i] += rho * sv[i];
+    }
+    ss = block_sum(ss, red);
+    st = block_sum(st, red);
+    tt = block_sum(tt, red);
+    const double uu = uu_uw[0], uw = uu_uw[1], ww = uu_uw[2];
+    const double r2 = uu - ss;
+    const double r = (r2 > 1e-20 * uu) ? sqrt(r2) : 0.0;
+    double *g = K.g + (size_t)req * (m + 1);
+    if (threadIdx.x == 0) {
+        bool stop = closing != 0 || r == 0.0;
+        if (j == 0) {
+            g[0] = rho * r;
+        } else {
+            double *H = K.H + (size_t)req * (m + 1) * m;
+            double carry = col[0];
+            for (int i = 0; i + 1 < j; ++i) {
+                const double b = col[i + 1], c = csv[i], s = snv[i];
+                H[(size_t)i * m + (j - 1)] = c * carry + s * b;
+                carry = -s * carry + c * b;
+            }
+            const double rr = hypot(carry, rho * r);
+            const double c = rr > 0 ? carry / rr : 1.0, s = rr > 0 ? rho * r / rr : 0.0;
+            cs[j - 1] = c;
+            sn[j - 1] = s;
+            H[(size_t)(j - 1) * m + (j - 1)] = rr;
+            const double gj = -s * g[j - 1];
+            g[j] = gj;
+            g[j - 1] = c * g[j - 1];
+            const double est = fabs(gj);
+            if (!(est == est) || !(rr == rr)) {
+                K.flags[req] |= 2;
+                stop = true;
+            }
+            if (est <= K.tol[req]) stop = true;
+        }
+        K.jcount[req] = j;
+        if (!(r == r)) {
+            K.flags[req] |= 2;
+            stop = true;
+        }
+        if (closing) K.closed[req] = 1;
+        if (stop) K.active[req] = 0;
+        else K.scal[req] = r;
+        red[0] = stop ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (red[0] != 0.0) return;
+    double *hp = K.hproj + (size_t)req * (m + 1);
+    for (int i = threadIdx.x; i < j; i += RT) {
+        hp[i] = sv[i];
+        hc[i] = tv[i];
+    }
+    if (threadIdx.x == 0) {
+        const double c = (uw - st) / r;
+        hc[j] = c;
+        const double p2 = ww - tt - c * c;
+        K.rho[req] = ww > 0 ? sqrt(fmax(p2, 1e-16 * ww)) : 1.0;
+    }
+}
+
+// q_j = (U - Q s) / r_j over U and W = (W - Q t - c_j q_j) / rho_j, both in
+// place: one pass over Q.  Dynamic LDS: s (j values) and t, c_j (j + 1 values).
+__global__ void __launch_bounds__(RT) k_arnoldi_update(KrylovDev K, int j) {
     const int req = blockIdx.y;
     if (!K.active[req]) return;
-    long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    extern __shared__ double coef[];
+    double *s = coef, *t = coef + j;
+    const double *hp = K.hproj + (size_t)req * (K.m + 1), *hc = K.hcol + (size_t)req * (K.m + 1);
+    for (int i = threadIdx.x; i < j; i += RT) s[i] = hp[i];
+    for (int i = threadIdx.x; i <= j; i += RT) t[i] = hc[i];
+    __syncthreads();
+    const long long e = (long long)blockIdx.x * RT + threadIdx.x;
     if (e >= K.N) return;
-    double hn = K.scal[req];
-    double *v = K.V + ((long long)(j + 1) * K.nb + req) * K.N;
-    v[e] = v[e] / hn;
+    const long long vstride = (long long)K.nb * K.N;
+    const double *q = K.V + (long long)req * K.N + e;
+    double qs = 0, qt = 0;
+    int i = 0;
+    for (; i + 3 < j; i += 4) {
+        const double a0 = q[i * vstride], a1 = q[(i + 1) * vstride], a2 = q[(i + 2) * vstride],
+                     a3 = q[(i + 3) * vstride];
+        qs += a0 * s[i] + a1 * s[i + 1] + a2 * s[i + 2] + a3 * s[i + 3];
+        qt += a0 * t[i] + a1 * t[i + 1] + a2 * t[i + 2] + a3 * t[i + 3];
+    }
+    for (; i < j; ++i) {
+        const double a = q[i * vstride];
+        qs += a * s[i];
+        qt += a * t[i];
+    }
+    double *U = K.V + (long long)j * vstride + (long long)req * K.N + e;
+    double *W = U + vstride;
+    const double inv = 1.0 / K.scal[req];
+    const double qj = (*U - qs) * inv;
+    *U = qj;
+    *W = (*W - qt - t[j] * qj) * (1.0 / K.rho[req]);
 }
 
 // y = R^-1 g for the steps of this cycle (one thread per request).
@@ -1205,19 +1329,17 @@ __global__ void __launch_bounds__(RT) k_residual(KrylovDev K, int *running, cons
         acc += v * v;
     }
     double s = block_sum(acc, red);
-    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
+    double *part = K.part + (size_t)req * (2 * K.m + 3) * NBLK;
     if (threadIdx.x == 0) part[blockIdx.x] = s;
     if (last_block(&K.ticket[req], gridDim.x)) {
+        const double rn = sqrt(block_sum_parts(part, gridDim.x, red));
+        double *g = K.g + (size_t)req * (K.m + 1);
+        for (int i = threadIdx.x; i <= K.m; i += RT) g[i] = i == 0 ? rn : 0.0;
         if (threadIdx.x == 0) {
-            double nn = 0;
-            for (int bb = 0; bb < (int)gridDim.x; ++bb) nn += part[bb];
-            double rn = sqrt(nn);
             K.rnorm[req] = rn;
-            K.scal[req] = rn;
+            K.rho[req] = rn;
             K.jcount[req] = 0;
-            double *g = K.g + (size_t)req * (K.m + 1);
-            for (int i = 0; i <= K.m; ++i) g[i] = 0.0;
-            g[0] = rn;
+            K.closed[req] = 0;
             if (!(rn == rn)) {
                 K.flags[req] |= 2;
                 running[req] = 0;
@@ -1238,10 +1360,10 @@ __global__ void __launch_bounds__(RT) k_residual(KrylovDev K, int *running, cons
 __global__ void __launch_bounds__(RT) k_scale0(KrylovDev K) {
     const int req = blockIdx.y;
     if (!K.active[req]) return;
-    long long e = (long long)blockIdx.x * RT + threadIdx.x;
+    const long long e = (long long)blockIdx.x * RT + threadIdx.x;
     if (e >= K.N) return;
     double *v = K.V + (long long)req * K.N;
-    v[e] = v[e] / K.scal[req];
+    v[e] = v[e] / K.rho[req];
 }
 
 __global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restrict__ B, const int *__restrict__ mask) {
@@ -1264,15 +1386,14 @@ __global__ void __launch_bounds__(RT) k_bnorm(KrylovDev K, const double *__restr
     __syncthreads();
     if (bad) atomicOr(&anybad, 1);
     __syncthreads();
-    double *part = K.part + (size_t)req * (K.m + 1) * NBLK;
+    double *part = K.part + (size_t)req * (2 * K.m + 3) * NBLK;
     if (threadIdx.x == 0) {
         part[blockIdx.x] = s;
         if (anybad) atomicOr(&K.flags[req], 1);
     }
     if (last_block(&K.ticket[req], gridDim.x)) {
+        const double nn = block_sum_parts(part, gridDim.x, red);
         if (threadIdx.x == 0) {
-            double nn = 0;
-            for (int bb = 0; bb < (int)gridDim.x; ++bb) nn += part[bb];
             K.bnorm[req] = sqrt(nn);
             K.ticket[req] = 0;
         }
@@ -1376,13 +1497,14 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         tpw = std::max(tpw, ((nxp / 16) * (nyp / 16) + 3) / 4);
     }
     if (tpw <= XYM_MAXT && shm <= xy_lds_limit()) {
-#define FM_XYM(T) hipLaunchKernelGGL(k_xy_mfma<T>, grid, dim3(XY_THREADS), shm, st, pd.dev, pr.dev, E_dev, active, data, min_den)
-        if (tpw <= 1) FM_XYM(1);
-        else if (tpw <= 2) FM_XYM(2);
-        else if (tpw <= 4) FM_XYM(4);
-        else if (tpw <= 8) FM_XYM(8);
-        else if (tpw <= 12) FM_XYM(12);
-        else FM_XYM(16);
+        // tpw: output tiles per wave with 4 waves; large slices use 8 waves
+#define FM_XYM(T, NW) hipLaunchKernelGGL((k_xy_mfma<T, NW>), grid, dim3(NW * 64), shm, st, pd.dev, pr.dev, E_dev, active, data, min_den)
+        if (tpw <= 1) FM_XYM(1, 4);
+        else if (tpw <= 2) FM_XYM(2, 4);
+        else if (tpw <= 4) FM_XYM(4, 4);
+        else if (tpw <= 8) FM_XYM(4, 8);
+        else if (tpw <= 12) FM_XYM(6, 8);
+        else FM_XYM(8, 8);
 #undef FM_XYM
         return;
     }
@@ -1414,48 +1536,46 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
     }
     if (tpw > XYM_MAXT || shm > xy_lds_limit()) return false;
     dim3 grid(maxnz, 3 * MAXM, nb);
-#define FM_XYLP(T)                                                                                             \
+#define FM_XYLP(T, NW)                                                                                         \
     {                                                                                                          \
-        if (mode == 1) hipLaunchKernelGGL((k_xy_lp<T, 1>), grid, dim3(XY_THREADS), shm, st, pd.dev, pr.dev, E_dev, active, data); \
-        else hipLaunchKernelGGL((k_xy_lp<T, 2>), grid, dim3(XY_THREADS), shm, st, pd.dev, pr.dev, E_dev, active, data); \
+        if (mode == 1) hipLaunchKernelGGL((k_xy_lp<T, 1, NW>), grid, dim3(NW * 64), shm, st, pd.dev, pr.dev, E_dev, active, data); \
+        else hipLaunchKernelGGL((k_xy_lp<T, 2, NW>), grid, dim3(NW * 64), shm, st, pd.dev, pr.dev, E_dev, active, data); \
     }
-    if (tpw <= 1) FM_XYLP(1)
-    else if (tpw <= 2) FM_XYLP(2)
-    else if (tpw <= 4) FM_XYLP(4)
-    else if (tpw <= 8) FM_XYLP(8)
-    else if (tpw <= 12) FM_XYLP(12)
-    else FM_XYLP(16)
+    if (tpw <= 1) FM_XYLP(1, 4)
+    else if (tpw <= 2) FM_XYLP(2, 4)
+    else if (tpw <= 4) FM_XYLP(4, 4)
+    else if (tpw <= 8) FM_XYLP(4, 8)
+    else if (tpw <= 12) FM_XYLP(6, 8)
+    else FM_XYLP(8, 8)
 #undef FM_XYLP
     return true;
 }
 
-void launch_mdot(const KrylovDev &k, int j, const double *w, int accumulate, hipStream_t st) {
+unsigned dots_blocks(const KrylovDev &k, int j) {
     // about 2048 blocks in flight, at most 64 elements per thread, at most NBLK per request
-    const long long groups = cdiv(j + 1, MD_G);
+    const long long groups = std::max<long long>(1, cdiv(j, MD_G));
     long long nblk = std::max<long long>(cdiv(2048, (long long)k.nb * groups), cdiv(k.N, (long long)RT * 64));
-    nblk = std::max<long long>(1, std::min<long long>(NBLK, nblk));
-    dim3 grid((unsigned)nblk, (unsigned)groups, k.nb);
-    hipLaunchKernelGGL(k_mdot, grid, dim3(RT), 0, st, k, j, w, accumulate);
+    return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
 }
 
-void launch_mupdate(const KrylovDev &k, int j, double *w, hipStream_t st) {
+void launch_arnoldi_dots(const KrylovDev &k, int j, int closing, hipStream_t st) {
+    dim3 grid(dots_blocks(k, j), (unsigned)std::max(1, (int)cdiv(j, MD_G)), k.nb);
+    if (closing) hipLaunchKernelGGL(k_arnoldi_dots<true>, grid, dim3(RT), 0, st, k, j);
+    else hipLaunchKernelGGL(k_arnoldi_dots<false>, grid, dim3(RT), 0, st, k, j);
+}
+
+void launch_arnoldi_finish(const KrylovDev &k, int j, int closing, hipStream_t st) {
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(k.nb), dim3(RT), 0, st, k, j, (int)dots_blocks(k, j), closing);
+}
+
+void launch_arnoldi_update(const KrylovDev &k, int j, hipStream_t st) {
     dim3 grid(cdiv(k.N, RT), k.nb);
-    hipLaunchKernelGGL(k_mupdate, grid, dim3(RT), 0, st, k, j, w);
+    hipLaunchKernelGGL(k_arnoldi_update, grid, dim3(RT), sizeof(double) * (2 * j + 1), st, k, j);
 }
 
 unsigned reduce_blocks(const KrylovDev &k) {
     long long nblk = std::max<long long>(cdiv(1024, k.nb), cdiv(k.N, (long long)RT * 16));
     return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
-}
-
-void launch_norm_givens(const KrylovDev &k, int j, double *w, hipStream_t st) {
-    dim3 grid(reduce_blocks(k), k.nb);
-    hipLaunchKernelGGL(k_norm_givens, grid, dim3(RT), 0, st, k, j, w);
-}
-
-void launch_scale_next(const KrylovDev &k, int j, hipStream_t st) {
-    dim3 grid(cdiv(k.N, RT), k.nb);
-    hipLaunchKernelGGL(k_scale, grid, dim3(RT), 0, st, k, j);
 }
 
 void launch_cycle_solve(const KrylovDev &k, const int *running, hipStream_t st) {
@@ -1491,16 +1611,16 @@ void prepare_large_lds(size_t bytes) {
     if (bytes > g_lds_limit) g_lds_limit = bytes;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_xy), hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(bytes));
-    const void *fns[] = {reinterpret_cast<const void *>(k_xy_mfma<1>), reinterpret_cast<const void *>(k_xy_mfma<2>),
-                         reinterpret_cast<const void *>(k_xy_mfma<4>), reinterpret_cast<const void *>(k_xy_mfma<8>),
-                         reinterpret_cast<const void *>(k_xy_mfma<12>), reinterpret_cast<const void *>(k_xy_mfma<16>)};
+    const void *fns[] = {reinterpret_cast<const void *>(k_xy_mfma<1, 4>), reinterpret_cast<const void *>(k_xy_mfma<2, 4>),
+                         reinterpret_cast<const void *>(k_xy_mfma<4, 4>), reinterpret_cast<const void *>(k_xy_mfma<4, 8>),
+                         reinterpret_cast<const void *>(k_xy_mfma<6, 8>), reinterpret_cast<const void *>(k_xy_mfma<8, 8>)};
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-    const void *lp[] = {reinterpret_cast<const void *>(k_xy_lp<1, 1>), reinterpret_cast<const void *>(k_xy_lp<2, 1>),
-                        reinterpret_cast<const void *>(k_xy_lp<4, 1>), reinterpret_cast<const void *>(k_xy_lp<8, 1>),
-                        reinterpret_cast<const void *>(k_xy_lp<12, 1>), reinterpret_cast<const void *>(k_xy_lp<16, 1>),
-                        reinterpret_cast<const void *>(k_xy_lp<1, 2>), reinterpret_cast<const void *>(k_xy_lp<2, 2>),
-                        reinterpret_cast<const void *>(k_xy_lp<4, 2>), reinterpret_cast<const void *>(k_xy_lp<8, 2>),
-                        reinterpret_cast<const void *>(k_xy_lp<12, 2>), reinterpret_cast<const void *>(k_xy_lp<16, 2>)};
+    const void *lp[] = {reinterpret_cast<const void *>(k_xy_lp<1, 1, 4>), reinterpret_cast<const void *>(k_xy_lp<2, 1, 4>),
+                        reinterpret_cast<const void *>(k_xy_lp<4, 1, 4>), reinterpret_cast<const void *>(k_xy_lp<4, 1, 8>),
+                        reinterpret_cast<const void *>(k_xy_lp<6, 1, 8>), reinterpret_cast<const void *>(k_xy_lp<8, 1, 8>),
+                        reinterpret_cast<const void *>(k_xy_lp<1, 2, 4>), reinterpret_cast<const void *>(k_xy_lp<2, 2, 4>),
+                        reinterpret_cast<const void *>(k_xy_lp<4, 2, 4>), reinterpret_cast<const void *>(k_xy_lp<4, 2, 8>),
+                        reinterpret_cast<const void *>(k_xy_lp<6, 2, 8>), reinterpret_cast<const void *>(k_xy_lp<8, 2, 8>)};
     for (const void *f : lp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 

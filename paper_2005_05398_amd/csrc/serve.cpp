@@ -371,7 +371,7 @@ fm_status fm_server_create(size_t hbm_budget_bytes, int max_batch, int device, f
 
 fm_status fm_submit(fm_server *S, const fm_problem_desc *desc, double E, const double *b_host, double *x_host,
                     const fm_solve_opts *opts, uint64_t tag) {
-    if (!S || !desc || !b_host || !x_host || !opts || !std::isfinite(E) || opts->restart < 1 || opts->restart > 1000 ||
+    if (!S || !desc || !b_host || !x_host || !opts || !std::isfinite(E) || opts->restart < 1 || opts->restart > MAX_RESTART ||
         !(opts->rtol > 0) || opts->max_iters < 1 ||
         (opts->prec != FM_FP64 && opts->prec != FM_FP32 && opts->prec != FM_BF16X3)) {
         set_error("bad argument");

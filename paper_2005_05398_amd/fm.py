@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "FM_OK", -1: "FM_E_INVALID", -2: "FM_E_NOMEM", -3: "FM_E_HIP"
                 -5: "FM_E_BREAKDOWN", -6: "FM_E_PENCIL", -7: "FM_E_NONFINITE", -8: "FM_E_REJECTED",
                 -9: "FM_E_BUSY"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-KERNEL_CLASSES = ["matvec", "modez", "xy", "mdot", "mupdate", "norm", "scale", "restart", "coupling"]
+KERNEL_CLASSES = ["matvec", "modez", "xy", "mdot", "mupdate", "finish", "restart", "coupling"]
 MAPS = {"uniform": 0, "quadratic": 1, "pow": 2, "sin": 3}
 
 

@@ -89,6 +89,31 @@ def cfg4():
 CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}
 
 
+def cfg5_request(i):
+    """Request i of the serving stream (seed 5001 + i): nominal x,y size in
+    {32, 64, 96, 128} (quintic, taken to the nearest 3K+1), cubic z in
+    {8, 16, 32}, L in {0, 1, 2} with tau = +1, E uniform in [-0.6, -0.05], and
+    one of the two particle sets with its own domain and map."""
+    rr = np.random.Generator(np.random.PCG64(5001 + i))
+    nxy = int(rr.choice([32, 64, 96, 128]))
+    nz = int(rr.choice([8, 16, 32]))
+    L = int(rr.choice([0, 1, 2]))
+    E = float(rr.uniform(-0.6, -0.05))
+    heavy = bool(rr.integers(2))
+    if heavy:
+        mc, R, xy_map = H_MINUS, 40.0, "quadratic"
+    else:
+        mc, R, xy_map = PS_MINUS, 20.0, "uniform"
+    desc = make_desc(*mc, admissible_xy(nxy), nz, J=L, tau=1, deg_xy=5, deg_z=3, R=R, xy_map=xy_map)
+    return {"desc": desc, "E": E, "seed": 5001 + i, "nominal": {"nxy": nxy, "nz": nz, "L": L, "heavy": heavy}}
+
+
+def cfg5_arrivals(n, rate):
+    """Poisson arrival times (seconds from start) of n requests at `rate` per second."""
+    gaps = np.random.Generator(np.random.PCG64(5000)).exponential(1.0 / rate, n)
+    return np.cumsum(gaps) - gaps[0]
+
+
 def n_unknowns(desc):
     """N = n_M * sum_alpha n_z n_x n_y with n_M = J - M0 + 1, M0 = (1 - tau)/2."""
     m0 = (1 - desc["tau"]) // 2

@@ -66,3 +66,28 @@ def test_solve_mixed_precision(device, prec, name, desc, E, restart):
     assert rel_residual(A, xg, b) <= 1e-10
     xref = lu_solve(A, b)
     assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_long_cycle_reduced_precision_full_size(device, prec):
+    """Full-size H- scan energies that take 100+ Arnoldi steps in one cycle of
+    300: the newest Krylov direction is rescaled every step, so its size must
+    not drift out of the reduced-precision range over the cycle.  Reduced- and
+    full-precision solutions agree to the solve's accuracy."""
+    import torch
+    fm = _fm()
+    cfg = W.cfg2()
+    P = fm.Problem(cfg["desc"])
+    Es = [float(e) for e in np.asarray(cfg["E"])[-4:]]
+    B = to_dev(np.stack([W.rhs(s, P.N) for s in cfg["seeds"][-4:]]), device)
+    x64 = torch.zeros_like(B)
+    xlp = torch.zeros_like(B)
+    st, res = P.solve(Es, B, x64, restart=300, rtol=1e-10, max_iters=3000, prec="fp64")
+    assert st == fm.FM_OK, res
+    st, res_lp = P.solve(Es, B, xlp, restart=300, rtol=1e-10, max_iters=3000, prec=prec)
+    assert st == fm.FM_OK, res_lp
+    assert max(r["iters"] for r in res_lp) >= 100
+    for i in range(4):
+        assert res_lp[i]["rel_residual"] <= 1e-10
+        err = (torch.linalg.norm(xlp[i] - x64[i]) / torch.linalg.norm(x64[i])).item()
+        assert err <= 1e-8, (prec, i, err)
