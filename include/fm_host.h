@@ -35,6 +35,15 @@ fm_status fm_host_pencil(int n, const double *A1, const double *A2, double *Wbar
  * FM_E_HIP / FM_E_NOMEM. */
 fm_status fm_host_setup_check(const fm_problem_desc *desc, double *max_err, int *complex_pairs, size_t *n_unknowns);
 
+/* The coupling term of the operator (the off-diagonal blocks in alpha of
+ * H - E S: V_alpha^(s) times the partners' expansions at the rotated points,
+ * Sec. 2 and eq. (FM-pre)) applied to x, evaluated on the host from the same
+ * grouped coupling pairs that the device operator uses: y = C x (N doubles
+ * each; both may be NULL to count only).  npairs: (point, partner) pairs with
+ * a nonzero factor inside the partner's box; ntasks: groups of at most 64
+ * pairs that share one partner cell.  Errors as fm_host_setup_check. */
+fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double *y, long long *npairs, int *ntasks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -273,9 +273,9 @@ void add_matvec_work(fm_problem *p, const Work &w, double nreq) {
 }
 
 void apply_operator(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *x, double *y,
-                    hipStream_t st) {
-    timed(p, st, FM_K_MATVEC, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, st, 1); });
-    timed(p, st, FM_K_COUPLING, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, st, 2); });
+                    double *cbuf, hipStream_t st) {
+    timed(p, st, FM_K_COUPLING, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, cbuf, st, 2); });
+    timed(p, st, FM_K_MATVEC, [&] { launch_matvec(p->pd, nb, E_dev, mask, x, y, cbuf, st, 1); });
 }
 
 // Work of Arnoldi step j for one request: update = false for the step on which
@@ -314,7 +314,8 @@ void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, 
 // -- Batch -----------------------------------------------------------------
 
 size_t Batch::footprint(const fm_problem *p, int cap, int m) {
-    return krylov_bytes(p->N, cap, m) + 3 * round256(sizeof(int) * cap) + round256(sizeof(double) * cap);
+    return krylov_bytes(p->N, cap, m) + 3 * round256(sizeof(int) * cap) + round256(sizeof(double) * cap) +
+           round256(sizeof(double) * 2 * size_t(cap) * size_t(p->N));
 }
 
 fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
@@ -335,6 +336,8 @@ fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
     fresh = reinterpret_cast<int *>(q);
     q += round256(sizeof(int) * cap);
     min_den = reinterpret_cast<double *>(q);
+    q += round256(sizeof(double) * cap);
+    cbuf = reinterpret_cast<double *>(q);
     void *h = nullptr;
     HIP_TRY(hipHostMalloc(&h, sizeof(int) * cap, hipHostMallocDefault));
     hbuf = static_cast<int *>(h);
@@ -401,7 +404,7 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
             launch_zero_start(K, X, fresh, x0_is_guess ? 0 : 1, st);
             launch_bnorm(K, B, fresh, st);
         }
-        launch_matvec(p->pd, cap, K.E, running, X, K.V, st);
+        launch_matvec(p->pd, cap, K.E, running, X, K.V, cbuf, st);
         launch_residual(K, running, B, rtol, 0.5, st);
         launch_scale0(K, st);
     });
@@ -444,7 +447,7 @@ fm_status Batch::cycle(const std::function<bool()> &want_cut, int min_steps) {
         double *Zj = K.Z + (long long)j * nb * N;
         double *Vn = K.V + (long long)(j + 1) * nb * N;
         apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, st);
-        apply_operator(p, nb, K.E, K.active, Zj, Vn, st);
+        apply_operator(p, nb, K.E, K.active, Zj, Vn, cbuf, st);
         timed(p, st, FM_K_MDOT, [&] { launch_arnoldi_dots(K, j, 0, st); });
         timed(p, st, FM_K_FINISH, [&] { launch_arnoldi_finish(K, j, 0, st); });
         timed(p, st, FM_K_MUPDATE, [&] { launch_arnoldi_update(K, j, st); });
@@ -588,6 +591,21 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         F.Wy16 = put(p, to16(h.Wy), err);
         if (!err.empty()) return err;
     }
+    // coupling pairs for the tiled operator
+    pd.cpl = CouplingDev{};
+    if (matvec_tiled_ok(pd)) {
+        if (2 * p->N >= (1LL << 31)) return "problem too large for the tiled operator";
+        CouplingHost ch;
+        err = build_coupling(p, hf, ch);
+        if (!err.empty()) return err;
+        pd.cpl.ntasks = ch.ntasks;
+        pd.cpl.npairs = ch.npairs;
+        pd.cpl.task = put(p, ch.task, err);
+        pd.cpl.out = put(p, ch.out, err);
+        pd.cpl.s = put(p, ch.s, err);
+        pd.cpl.F = put(p, ch.F, err);
+        if (!err.empty()) return err;
+    }
     // device copies of the two descriptors
     pd.dev = nullptr;
     p->pr.dev = nullptr;
@@ -671,6 +689,7 @@ fm_status fm_destroy_problem(fm_problem *p) {
     for (auto &b : p->buffers) (void)hipFree(b.ptr);
     if (p->ws) (void)hipFree(p->ws);
     if (p->ws_small) (void)hipFree(p->ws_small);
+    if (p->cbuf) (void)hipFree(p->cbuf);
     if (p->host_pinned) (void)hipHostFree(p->host_pinned);
     for (auto e : p->prof.ev) (void)hipEventDestroy(e);
     if (p->solve_batch) {
@@ -705,7 +724,16 @@ fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const do
     fm_status r = ensure_small(p, nbatch, s);
     if (r != FM_OK) return r;
     HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
-    apply_operator(p, nbatch, s.E, nullptr, x_dev, y_dev, st);
+    const size_t cb = sizeof(double) * 2 * size_t(nbatch) * size_t(p->N);
+    if (p->cbuf_bytes < cb) {
+        if (p->cbuf) (void)hipFree(p->cbuf);
+        p->cbuf = nullptr;
+        p->cbuf_bytes = 0;
+        HIP_TRY(hipMalloc(&p->cbuf, cb));
+        p->cbuf_bytes = cb;
+        HIP_TRY(hipMemsetAsync(p->cbuf, 0, cb, st));
+    }
+    apply_operator(p, nbatch, s.E, nullptr, x_dev, y_dev, p->cbuf, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     add_matvec_work(p, Work(p), nbatch);

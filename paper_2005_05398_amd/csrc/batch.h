@@ -19,6 +19,7 @@ struct Batch {
     size_t bytes = 0;
     int *running = nullptr, *cont = nullptr, *fresh = nullptr;   // device masks [cap]
     double *min_den = nullptr;                                   // device [cap]
+    double *cbuf = nullptr;                                      // device [cap][2][N] operator coupling
     int *hbuf = nullptr;                                         // pinned host scratch [cap]
     const double *B = nullptr;                                   // [cap][N]
     double *X = nullptr;                                         // [cap][N]

@@ -1,0 +1,175 @@
+// Coupling geometry of the operator, built once per problem (independent of
+// the energy and of the right-hand sides).
+//
+// The coupling term of component alpha at a collocation point needs both
+// partners' expansions at the point's image in the partner's Jacobi
+// coordinates (the rotation of Sec. 2 between Jacobi sets, with the cosine of
+// the angle from the relation between the two triangles).  For every point
+// with a nonzero short-range potential and every partner beta whose box holds
+// the image, this records the spline cell of beta that contains the image, the
+// image's position inside that cell (0..1 per dimension), and the n_M x n_M
+// factor that multiplies beta's values there: V_alpha^(s) x y / (x_beta y_beta)
+// times, for L > 0, the Wigner-function weights between the M' blocks
+// (eq. (FM-pre)).  The pairs are grouped by (beta, cell) and the groups are cut
+// into tasks of at most 64 pairs: a wave evaluates one task from one cell's
+// coefficients.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "fm_problem.h"
+
+namespace fm {
+
+namespace {
+
+bool cyclic(int b, int a) { return (b == 0 && a == 1) || (b == 1 && a == 2) || (b == 2 && a == 0); }
+
+struct Rec {
+    int key;
+    int out;
+    double s[3];
+};
+
+}  // namespace
+
+std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingHost &ch) {
+    const int nM = p->nM, J = p->desc.J, M0 = p->M0;
+    const int nf = nM * nM;
+    const ProblemDev &pd = p->pd;
+    int keyoff[4] = {0, 0, 0, 0};
+    for (int b = 0; b < 3; ++b) keyoff[b + 1] = keyoff[b] + p->bz[b].K * p->bx[b].K * p->by[b].K;
+
+    // one work item per (alpha, z point); each thread keeps its own records
+    struct Item { int a, iz; };
+    std::vector<Item> items;
+    for (int a = 0; a < 3; ++a)
+        for (int iz = 0; iz < p->bz[a].n; ++iz) items.push_back({a, iz});
+    const int nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::vector<Rec>> recs(nth);
+    std::vector<std::vector<double>> facs(nth);
+    auto work = [&](int t) {
+        for (size_t it = t; it < items.size(); it += nth) {
+            const int a = items[it].a, iz = items[it].iz;
+            const Basis1D &ax = p->bx[a], &ay = p->by[a], &az = p->bz[a];
+            const int nx = ax.n, ny = ay.n;
+            const double zc = az.points[iz], omz = 1.0 - zc * zc;
+            const std::vector<double> &Vs = hf.comp[a].Vs;
+            for (int ix = 0; ix < nx; ++ix)
+                for (int iy = 0; iy < ny; ++iy) {
+                    const double vs = Vs[size_t(ix) * ny + iy];
+                    if (vs == 0.0) continue;
+                    const double xc = ax.points[ix], yc = ay.points[iy];
+                    for (int bb = 0; bb < 2; ++bb) {
+                        const int b = (a + 1 + bb) % 3;
+                        const Basis1D &bx = p->bx[b], &by = p->by[b], &bz = p->bz[b];
+                        const double c = p->crot[b][a], s = p->srot[b][a];
+                        const double xb =
+                            std::sqrt(std::fmax(c * c * xc * xc + 2.0 * s * c * xc * yc * zc + s * s * yc * yc, 0.0));
+                        const double yb =
+                            std::sqrt(std::fmax(s * s * xc * xc - 2.0 * s * c * xc * yc * zc + c * c * yc * yc, 0.0));
+                        if (!(xb <= bx.nodes.back() && yb <= by.nodes.back())) continue;
+                        const double den = xb * yb;
+                        double zb = den > 0.0 ? (s * c * (yc * yc - xc * xc) + (c * c - s * s) * xc * yc * zc) / den
+                                              : 0.0;
+                        zb = std::fmin(1.0, std::fmax(-1.0, zb));
+                        const int mz = bz.interval(zb), mx = bx.interval(xb), my = by.interval(yb);
+                        Rec r;
+                        r.key = keyoff[b] + (mz * bx.K + mx) * by.K + my;
+                        r.out = int((p->off[a] + (long long)(iz * nx + ix) * ny + iy) * 2 + bb);
+                        r.s[0] = (zb - bz.nodes[mz]) / (bz.nodes[mz + 1] - bz.nodes[mz]);
+                        r.s[1] = (xb - bx.nodes[mx]) / (bx.nodes[mx + 1] - bx.nodes[mx]);
+                        r.s[2] = (yb - by.nodes[my]) / (by.nodes[my + 1] - by.nodes[my]);
+                        recs[t].push_back(r);
+                        const double base = vs * xc * yc / den;
+                        if (J == 0) {
+                            facs[t].push_back(base);
+                            continue;
+                        }
+                        double arg = (-s * xc * zc + c * yc) / yb;
+                        arg = std::fmin(1.0, std::fmax(-1.0, arg));
+                        double cw = std::sqrt(0.5 * (1.0 + arg)), sw = std::sqrt(0.5 * (1.0 - arg));
+                        if (!cyclic(b, a)) cw = -cw;
+                        const double sa = std::sqrt(std::fmax(omz, 0.0)), sb = std::sqrt(std::fmax(1.0 - zb * zb, 0.0));
+                        double sbp[MAXM], sap[MAXM];
+                        sbp[0] = M0 ? sb : 1.0;
+                        sap[0] = M0 ? sa : 1.0;
+                        for (int k = 1; k < nM; ++k) {
+                            sbp[k] = sbp[k - 1] * sb;
+                            sap[k] = sap[k - 1] * sa;
+                        }
+                        for (int iM = 0; iM < nM; ++iM)
+                            for (int jM = 0; jM < nM; ++jM) {
+                                const double *G = pd.dcoef + (iM * nM + jM) * pd.dlen;
+                                // sum_k G[k] cw^k sw^(2J-k) by Horner in cw
+                                double f = G[2 * J], sp = 1.0;
+                                for (int k = 2 * J - 1; k >= 0; --k) {
+                                    sp *= sw;
+                                    f = f * cw + G[k] * sp;
+                                }
+                                facs[t].push_back(base * f * sbp[jM] / sap[iM]);
+                            }
+                    }
+                }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(work, t);
+    for (auto &x : th) x.join();
+
+    // counting sort by cell (stable within a cell: alpha order)
+    long long np = 0;
+    for (auto &v : recs) np += (long long)v.size();
+    if (np >= (1LL << 31)) return "too many coupling pairs";
+    std::vector<long long> start(keyoff[3] + 1, 0);
+    for (auto &v : recs)
+        for (const Rec &r : v) start[r.key + 1]++;
+    for (int k = 0; k < keyoff[3]; ++k) start[k + 1] += start[k];
+    std::vector<long long> pos(start.begin(), start.end() - 1);
+    ch.npairs = np;
+    ch.out.assign(np, 0);
+    ch.s.assign(3 * np, 0.0);
+    ch.F.assign(size_t(nf) * np, 0.0);
+    // each thread holds its items' records in item order; walking the items in
+    // order and taking each one's records from its thread keeps alpha order
+    {
+        std::vector<size_t> ri(nth, 0);
+        for (size_t it = 0; it < items.size(); ++it) {
+            const int t = int(it % nth);
+            const int a = items[it].a, iz = items[it].iz;
+            const long long lo = p->off[a] + (long long)iz * p->bx[a].n * p->by[a].n;
+            const long long hi = lo + (long long)p->bx[a].n * p->by[a].n;
+            while (ri[t] < recs[t].size()) {
+                const Rec &r = recs[t][ri[t]];
+                const long long o = r.out >> 1;
+                if (o < lo || o >= hi) break;
+                const long long d = pos[r.key]++;
+                ch.out[d] = r.out;
+                for (int k = 0; k < 3; ++k) ch.s[size_t(k) * np + d] = r.s[k];
+                for (int f = 0; f < nf; ++f) ch.F[size_t(f) * np + d] = facs[t][ri[t] * nf + f];
+                ++ri[t];
+            }
+        }
+        for (int t = 0; t < nth; ++t)
+            if (ri[t] != recs[t].size()) return "coupling pair merge failed";
+    }
+    // tasks: (beta, cell) groups cut into chunks of at most 64 pairs
+    ch.task.clear();
+    for (int b = 0; b < 3; ++b) {
+        const int Kz = p->bz[b].K, Kx = p->bx[b].K, Ky = p->by[b].K;
+        for (int mz = 0; mz < Kz; ++mz)
+            for (int mx = 0; mx < Kx; ++mx)
+                for (int my = 0; my < Ky; ++my) {
+                    const int key = keyoff[b] + (mz * Kx + mx) * Ky + my;
+                    for (long long q = start[key]; q < start[key + 1]; q += 64) {
+                        const int cnt = int(std::min<long long>(64, start[key + 1] - q));
+                        const int t8[8] = {b, mz, mx, my, int(q), cnt, 0, 0};
+                        ch.task.insert(ch.task.end(), t8, t8 + 8);
+                    }
+                }
+    }
+    ch.ntasks = int(ch.task.size() / 8);
+    return "";
+}
+
+}  // namespace fm

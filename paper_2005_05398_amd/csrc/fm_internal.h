@@ -78,6 +78,16 @@ struct CompDev {
     int ntiles;                  // matvec tiles of this component: nz * ceil(nx / xt)
 };
 
+// Coupling pairs grouped by (beta, cell of beta); built on the host.
+struct CouplingDev {
+    int ntasks;
+    long long npairs;
+    const int *task;             // [ntasks][8]: beta, mz, mx, my, first pair, pair count (<= 64)
+    const int *out;              // [npairs] 2 * (alpha output index of M' block 0) + slot
+    const double *s;             // [3][npairs] position inside the cell: z, x, y
+    const double *F;             // [nM * nM][npairs] factor of beta's M'' value in alpha's M' row
+};
+
 struct ProblemDev {
     CompDev comp[3];
     int nM, J, tau, M0;
@@ -89,8 +99,18 @@ struct ProblemDev {
     int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
     int tile_lds;                // doubles of LDS for the largest coefficient tile
     int nodes_total;             // doubles of LDS for all node tables
+    CouplingDev cpl;             // tiled path only
     const ProblemDev *dev;       // device copy of this descriptor (kernels take this pointer)
 };
+
+// The operator runs as two tiled kernels (coupling into a two-slot buffer, then
+// the local stencil plus that buffer) when x and y share one spline order in
+// all components, z one order, n_M <= 3 and the stencil tile fits 64 KB of LDS;
+// otherwise one generic kernel does everything.
+inline bool matvec_tiled_ok(const ProblemDev &pd) {
+    const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
+    return same_xy && pd.q[2] != 0 && pd.nM <= 3 && sizeof(double) * size_t(pd.tile_lds) <= 64 * 1024;
+}
 
 struct PrecCompDev {
     int nx, ny, nz, nM;
@@ -139,9 +159,13 @@ constexpr int MAX_RESTART = 1000;
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).
-// part: 0 whole operator, 1 everything but the coupling, 2 the coupling (added to y)
+// part: 0 whole operator, 1 everything but the coupling, 2 the coupling.  On the
+// tiled path part 2 writes the coupling of every request into cbuf
+// ([nb][2][N], slot = which partner) and part 1 adds cbuf to the local operator,
+// so part 2 must run first; entries of cbuf that no coupling pair writes must be
+// zero (they stay so).  The generic path ignores cbuf and does it all in part 1.
 void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active,
-                   const double *x, double *y, hipStream_t st, int part = 0);
+                   const double *x, double *y, double *cbuf, hipStream_t st, int part = 0);
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
                   const double *in, double *out, hipStream_t st);
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,

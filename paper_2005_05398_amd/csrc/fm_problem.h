@@ -15,6 +15,13 @@ struct HostFactors {
     double max_err = 0;
 };
 
+struct CouplingHost {
+    std::vector<int> task, out;
+    std::vector<double> s, F;
+    long long npairs = 0;
+    int ntasks = 0;
+};
+
 struct Profile {
     bool on = false;
     std::vector<hipEvent_t> ev;
@@ -59,6 +66,8 @@ struct fm_problem {
     size_t ws_bytes = 0;
     void *ws_small = nullptr;
     size_t ws_small_bytes = 0;
+    double *cbuf = nullptr;                  // coupling buffer of fm_apply_operator ([nb][2][N], zeroed)
+    size_t cbuf_bytes = 0;
     double *host_pinned = nullptr;           // pinned host scratch for flag read-back
     size_t host_pinned_bytes = 0;
     fm::Profile prof;
@@ -69,5 +78,6 @@ namespace fm {
 std::string setup_problem(fm_problem *p);
 std::string build_factors(fm_problem *p, HostFactors &hf);
 std::string upload(fm_problem *p, const HostFactors &hf);
+std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingHost &ch);
 void set_error(const std::string &msg);
 }  // namespace fm

@@ -81,4 +81,99 @@ fm_status fm_host_setup_check(const fm_problem_desc *desc, double *max_err, int 
     return FM_OK;
 }
 
+fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double *y, long long *npairs, int *ntasks) {
+    if (!desc) {
+        set_error("null argument");
+        return FM_E_INVALID;
+    }
+    fm_problem p;
+    p.desc = *desc;
+    std::string e = setup_problem(&p);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_INVALID;
+    }
+    HostFactors hf;
+    e = build_factors(&p, hf);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_PENCIL;
+    }
+    CouplingHost ch;
+    e = build_coupling(&p, hf, ch);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_INVALID;
+    }
+    if (npairs) *npairs = ch.npairs;
+    if (ntasks) *ntasks = ch.ntasks;
+    if (!x || !y) return FM_OK;
+    const int nM = p.nM;
+    const long long N = p.N, np = ch.npairs;
+    std::vector<double> c0(N, 0.0), c1(N, 0.0);
+    auto shapes = [](int q, double s, double r, double *v) {
+        const double s2 = s * s, s3 = s2 * s;
+        if (q == 2) {
+            v[0] = 1.0 - 3.0 * s2 + 2.0 * s3;
+            v[1] = r * (s - 2.0 * s2 + s3);
+            v[2] = 3.0 * s2 - 2.0 * s3;
+            v[3] = r * (s3 - s2);
+        } else {
+            const double s4 = s3 * s, s5 = s4 * s, r2 = r * r;
+            v[0] = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;
+            v[1] = r * (s - 6.0 * s3 + 8.0 * s4 - 3.0 * s5);
+            v[2] = r2 * 0.5 * (s2 - 3.0 * s3 + 3.0 * s4 - s5);
+            v[3] = 10.0 * s3 - 15.0 * s4 + 6.0 * s5;
+            v[4] = r * (-4.0 * s3 + 7.0 * s4 - 3.0 * s5);
+            v[5] = r2 * 0.5 * (s3 - 2.0 * s4 + s5);
+        }
+    };
+    for (int t = 0; t < ch.ntasks; ++t) {
+        const int *tk = &ch.task[size_t(t) * 8];
+        const int b = tk[0], mz = tk[1], mx = tk[2], my = tk[3], first = tk[4], cnt = tk[5];
+        const Basis1D &bz = p.bz[b], &bx = p.bx[b], &by = p.by[b];
+        const double rz = (bz.nodes[mz + 1] - bz.nodes[mz]) / bz.hbar;
+        const double rx = (bx.nodes[mx + 1] - bx.nodes[mx]) / bx.hbar;
+        const double ry = (by.nodes[my + 1] - by.nodes[my]) / by.hbar;
+        int gz[MAXR], gx[MAXR], gy[MAXR];
+        for (int k = 0; k < 2 * bz.q; ++k) gz[k] = bz.global_index(mz + k / bz.q, k % bz.q);
+        for (int k = 0; k < 2 * bx.q; ++k) gx[k] = bx.global_index(mx + k / bx.q, k % bx.q);
+        for (int k = 0; k < 2 * by.q; ++k) gy[k] = by.global_index(my + k / by.q, k % by.q);
+        for (long long pr = first; pr < first + cnt; ++pr) {
+            double vz[MAXR], vx[MAXR], vy[MAXR];
+            shapes(bz.q, ch.s[pr], rz, vz);
+            shapes(bx.q, ch.s[np + pr], rx, vx);
+            shapes(by.q, ch.s[2 * np + pr], ry, vy);
+            double val[MAXM];
+            for (int jM = 0; jM < nM; ++jM) {
+                const double *cb = x + p.off[b] + (long long)jM * p.npts[b];
+                double acc = 0;
+                for (int cz = 0; cz < 2 * bz.q; ++cz) {
+                    if (gz[cz] < 0) continue;
+                    double accx = 0;
+                    for (int ax = 0; ax < 2 * bx.q; ++ax) {
+                        if (gx[ax] < 0) continue;
+                        double accy = 0;
+                        for (int ay = 0; ay < 2 * by.q; ++ay)
+                            if (gy[ay] >= 0) accy += vy[ay] * cb[((long long)gz[cz] * bx.n + gx[ax]) * by.n + gy[ay]];
+                        accx += vx[ax] * accy;
+                    }
+                    acc += vz[cz] * accx;
+                }
+                val[jM] = acc;
+            }
+            const int o = ch.out[pr], outp = o >> 1, slot = o & 1;
+            const int a = slot == 0 ? (b + 2) % 3 : (b + 1) % 3;
+            std::vector<double> &dst = slot == 0 ? c0 : c1;
+            for (int iM = 0; iM < nM; ++iM) {
+                double v = 0;
+                for (int jM = 0; jM < nM; ++jM) v += ch.F[size_t(iM * nM + jM) * np + pr] * val[jM];
+                dst[outp + (long long)iM * p.npts[a]] = v;
+            }
+        }
+    }
+    for (long long i = 0; i < N; ++i) y[i] = c0[i] + c1[i];
+    return FM_OK;
+}
+
 }  // extern "C"

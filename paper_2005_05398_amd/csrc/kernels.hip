@@ -218,54 +218,14 @@ __global__ void __launch_bounds__(256) k_matvec(const ProblemDev *__restrict__ p
 // Operator, tiled: one block per (request, component, z point, XT consecutive
 // x points); threads cover the tile's (x, y) points.  The coefficients of the
 // tile's local stencil (z support x x support x all y) are staged in LDS once
-// per M' block; node tables sit in LDS for the coupling's interval search.
-// Q*: spline orders (2 cubic, 3 quintic); NM: number of M' blocks.
-
-// Hermite values at t of the 2Q functions nonzero there; dropped functions get
-// index 0 and value 0 so that every slot can be read unconditionally.
-template <int Q>
-__device__ __forceinline__ void eval_lds(const double *__restrict__ nodes, int K, double hbar, int drop0, double t,
-                                         int *g, double *v) {
-    int lo = 0, hi = K - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (nodes[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    const int m = lo;
-    const double t0 = nodes[m], h = nodes[m + 1] - t0;
-    const double s = (t - t0) / h, r = h / hbar;
-    const double s2 = s * s, s3 = s2 * s;
-    if (Q == 2) {
-        v[0] = 1.0 - 3.0 * s2 + 2.0 * s3;
-        v[1] = r * (s - 2.0 * s2 + s3);
-        v[2] = 3.0 * s2 - 2.0 * s3;
-        v[3] = r * (s3 - s2);
-    } else {
-        const double s4 = s3 * s, s5 = s4 * s, r2 = r * r;
-        v[0] = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;
-        v[1] = r * (s - 6.0 * s3 + 8.0 * s4 - 3.0 * s5);
-        v[2] = r2 * 0.5 * (s2 - 3.0 * s3 + 3.0 * s4 - s5);
-        v[3] = 10.0 * s3 - 15.0 * s4 + 6.0 * s5;
-        v[4] = r * (-4.0 * s3 + 7.0 * s4 - 3.0 * s5);
-        v[5] = r2 * 0.5 * (s3 - 2.0 * s4 + s5);
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const int node = m + e;
-            int gi = node * Q + k - drop0 - ((drop0 && node == K) ? 1 : 0);
-            const bool dropped = drop0 && k == 0 && (node == 0 || node == K);
-            g[e * Q + k] = dropped ? 0 : gi;
-            if (dropped) v[e * Q + k] = 0.0;
-        }
-}
-
+// per M' block.  The coupling comes from the two-slot buffer that the coupling
+// kernel filled before.  Q*: spline orders (2 cubic, 3 quintic); NM: number of
+// M' blocks.
 template <int QX, int QY, int QZ, int NM>
 __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restrict__ pd, const double *__restrict__ Evec,
                                                       const int *__restrict__ active, const double *__restrict__ X,
-                                                      double *__restrict__ Y) {
+                                                      double *__restrict__ Y, const double *__restrict__ cbuf,
+                                                      int nb) {
     constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
     const int req = blockIdx.y;
     if (active && !active[req]) return;
@@ -368,123 +328,149 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
         out[iM] = o;
     }
 
+    // plus the coupling of both partners (slot 0, then slot 1)
+    const double *c0 = cbuf + (long long)req * 2 * pd->N + C.off + p, *c1 = c0 + pd->N;
     double *y = Y + (long long)req * pd->N + C.off + p;
 #pragma unroll
-    for (int iM = 0; iM < NM; ++iM) y[(long long)iM * C.npts] = out[iM];
+    for (int iM = 0; iM < NM; ++iM) y[(long long)iM * C.npts] = out[iM] + c0[(long long)iM * C.npts] + c1[(long long)iM * C.npts];
 }
 
-// Coupling term of the operator, added to y: for every point of component
-// alpha and both beta != alpha, the beta expansion at the rotated point (zero
-// outside beta's box) times V_a^(s) x y / (x_b y_b) and, for L > 0, the
-// angular factors of eq. (FM-pre).  One thread per spatial point.
-template <int QX, int QY, int QZ, int NM>
-__global__ void __launch_bounds__(256) k_coupling(const ProblemDev *__restrict__ pd, const int *__restrict__ active,
-                                                  const double *__restrict__ X, double *__restrict__ Y) {
-    constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
-    const int req = blockIdx.y;
-    if (active && !active[req]) return;
-    extern __shared__ double sm[];
-    int noff[3][3];
-    {
-        int off = 0;
-        for (int b = 0; b < 3; ++b) {
-            const DimDev *dd[3] = {&pd->comp[b].x, &pd->comp[b].y, &pd->comp[b].z};
-            for (int d = 0; d < 3; ++d) {
-                noff[b][d] = off;
-                for (int i = threadIdx.x; i <= dd[d]->K; i += 256) sm[off + i] = dd[d]->nodes[i];
-                off += dd[d]->K + 1;
+// Hermite values at s in [0, 1] of the 2Q functions of one cell of width h,
+// r = h / hbar (each function carries (h/hbar)^k of its derivative order k).
+template <int Q>
+__device__ __forceinline__ void hermite_cell(double s, double r, double *v) {
+    const double s2 = s * s, s3 = s2 * s;
+    if (Q == 2) {
+        v[0] = 1.0 - 3.0 * s2 + 2.0 * s3;
+        v[1] = r * (s - 2.0 * s2 + s3);
+        v[2] = 3.0 * s2 - 2.0 * s3;
+        v[3] = r * (s3 - s2);
+    } else {
+        const double s4 = s3 * s, s5 = s4 * s, r2 = r * r;
+        v[0] = 1.0 - 10.0 * s3 + 15.0 * s4 - 6.0 * s5;
+        v[1] = r * (s - 6.0 * s3 + 8.0 * s4 - 3.0 * s5);
+        v[2] = r2 * 0.5 * (s2 - 3.0 * s3 + 3.0 * s4 - s5);
+        v[3] = 10.0 * s3 - 15.0 * s4 + 6.0 * s5;
+        v[4] = r * (-4.0 * s3 + 7.0 * s4 - 3.0 * s5);
+        v[5] = r2 * 0.5 * (s3 - 2.0 * s4 + s5);
+    }
+}
+
+// Global index of the k-th function of node `node` of a dimension, -1 if dropped.
+__device__ __forceinline__ int cell_fn(const DimDev &d, int node, int k) {
+    if (d.drop0 && k == 0 && (node == 0 || node == d.K)) return -1;
+    return node * d.q + k - d.drop0 - ((d.drop0 && node == d.K) ? 1 : 0);
+}
+
+constexpr int CPL_WAVES = 4;         // waves per block of the coupling kernel
+constexpr int CPL_REQ = 8;           // requests per block (grid y covers the rest)
+
+// Coupling term of the operator for the pairs of one (beta, cell) task per
+// wave: the wave stages the cell's (2QZ x 2QXY x 2QXY) coefficients of every
+// M'' block of one request in LDS (zero for dropped functions), then each lane
+// evaluates beta's expansion at its pair's image by the separable sum
+// sum_c v_z[c] sum_a v_x[a] sum_b v_y[b] coef[c][a][b] (LDS reads are the same
+// for the whole wave) and writes F val to cbuf[request][slot][alpha point].
+// The basis values and factors of a pair stay in registers over the requests.
+template <int QXY, int QZ, int NM>
+__global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const ProblemDev *__restrict__ pd,
+                                                                   const int *__restrict__ active, int nb,
+                                                                   const double *__restrict__ X,
+                                                                   double *__restrict__ cbuf) {
+    constexpr int RXY = 2 * QXY, RZ = 2 * QZ, TS = RZ * RXY * RXY;
+    __shared__ __align__(16) double tile[CPL_WAVES][NM * TS];
+    __shared__ int fidx[CPL_WAVES][RZ + 2 * RXY];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const CouplingDev &cp = pd->cpl;
+    // XCD-aware order: consecutive tasks (neighbouring cells) on one XCD's L2
+    const int nblk = gridDim.x, xcd = blockIdx.x % 8, per = (nblk + 7) / 8;
+    const int full = nblk % 8 == 0 ? 8 : nblk % 8;     // XCDs that get `per` blocks
+    const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
+    const int task = bid * CPL_WAVES + wave;
+    const bool has = task < cp.ntasks;
+    int b = 0, count = 0;
+    long long first = 0;
+    double r_z = 0, r_x = 0, r_y = 0;
+    if (has) {
+        const int *t = cp.task + (size_t)task * 8;
+        b = t[0];
+        const int mz = t[1], mx = t[2], my = t[3];
+        first = t[4];
+        count = t[5];
+        const CompDev &B = pd->comp[b];
+        r_z = (B.z.nodes[mz + 1] - B.z.nodes[mz]) / B.z.hbar;
+        r_x = (B.x.nodes[mx + 1] - B.x.nodes[mx]) / B.x.hbar;
+        r_y = (B.y.nodes[my + 1] - B.y.nodes[my]) / B.y.hbar;
+        if (lane < RZ) fidx[wave][lane] = cell_fn(B.z, mz + lane / QZ, lane % QZ);
+        else if (lane < RZ + RXY) fidx[wave][lane] = cell_fn(B.x, mx + (lane - RZ) / QXY, (lane - RZ) % QXY);
+        else if (lane < RZ + 2 * RXY)
+            fidx[wave][lane] = cell_fn(B.y, my + (lane - RZ - RXY) / QXY, (lane - RZ - RXY) % QXY);
+    }
+    const bool mine = has && lane < count;
+    const long long pr = first + lane;
+    double vz[RZ], vx[RXY], vy[RXY], F[NM * NM];
+    int outp = 0, slot = 0, npa = 0;
+    if (mine) {
+        hermite_cell<QZ>(cp.s[pr], r_z, vz);
+        hermite_cell<QXY>(cp.s[cp.npairs + pr], r_x, vx);
+        hermite_cell<QXY>(cp.s[2 * cp.npairs + pr], r_y, vy);
+#pragma unroll
+        for (int f = 0; f < NM * NM; ++f) F[f] = cp.F[(size_t)f * cp.npairs + pr];
+        const int o = cp.out[pr];
+        outp = o >> 1;
+        slot = o & 1;
+        const int a = slot == 0 ? (b + 2) % 3 : (b + 1) % 3;
+        npa = pd->comp[a].npts;
+    }
+    const CompDev &B = pd->comp[b];
+    const int bnx = B.x.n, bny = B.y.n;
+    const long long N = pd->N;
+    const int r0 = blockIdx.y * CPL_REQ, r1 = min(nb, r0 + CPL_REQ);
+    for (int req = r0; req < r1; ++req) {
+        if (active && !active[req]) continue;          // the same for the whole block
+        __syncthreads();
+        if (has) {
+            const double *x = X + (long long)req * N + B.off;
+            for (int e = lane; e < NM * TS; e += 64) {
+                const int iM = e / TS, rem = e - iM * TS;
+                const int c = rem / (RXY * RXY), a = (rem / RXY) % RXY, bq = rem % RXY;
+                const int gz = fidx[wave][c], gx = fidx[wave][RZ + a], gy = fidx[wave][RZ + RXY + bq];
+                tile[wave][e] = (gz < 0 || gx < 0 || gy < 0)
+                                    ? 0.0
+                                    : x[(long long)iM * B.npts + ((long long)gz * bnx + gx) * bny + gy];
             }
         }
-    }
-    __syncthreads();
-    long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-    int a = 0;
-    while (a < 3 && p >= pd->comp[a].npts) { p -= pd->comp[a].npts; ++a; }
-    if (a >= 3) return;
-    const CompDev &C = pd->comp[a];
-    const int ny = C.y.n;
-    const int iz = int(p / C.nxy), rem = int(p % C.nxy), ix = rem / ny, iy = rem % ny;
-    const double vs = C.Vs[rem];
-    if (vs == 0.0) return;
-    const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
-    const double *x = X + (long long)req * pd->N;
-    const int J = pd->J, M0 = pd->M0;
-    const double omz = 1.0 - zc * zc;
-    double out[NM];
-#pragma unroll
-    for (int iM = 0; iM < NM; ++iM) out[iM] = 0.0;
-#pragma unroll 1
-    for (int bb = 0; bb < 2; ++bb) {
-        const int b = (a + 1 + bb) % 3;
-        const CompDev &B = pd->comp[b];
-        const double c = C.c[b], s = C.s[b];
-        const double xb = sqrt(fmax(c * c * xc * xc + 2.0 * s * c * xc * yc * zc + s * s * yc * yc, 0.0));
-        const double yb = sqrt(fmax(s * s * xc * xc - 2.0 * s * c * xc * yc * zc + c * c * yc * yc, 0.0));
-        if (!(xb <= B.x.R && yb <= B.y.R)) continue;
-        const double den = xb * yb;
-        double zb = den > 0.0 ? (s * c * (yc * yc - xc * xc) + (c * c - s * s) * xc * yc * zc) / den : 0.0;
-        zb = fmin(1.0, fmax(-1.0, zb));
-        int hz[RZ], hx[RX], hy[RY];
-        double vz[RZ], vx[RX], vy[RY];
-        eval_lds<QZ>(sm + noff[b][2], B.z.K, B.z.hbar, B.z.drop0, zb, hz, vz);
-        eval_lds<QX>(sm + noff[b][0], B.x.K, B.x.hbar, B.x.drop0, xb, hx, vx);
-        eval_lds<QY>(sm + noff[b][1], B.y.K, B.y.hbar, B.y.drop0, yb, hy, vy);
-        const int bnx = B.x.n, bny = B.y.n;
+        __syncthreads();
+        if (!mine) continue;
         double val[NM];
 #pragma unroll
         for (int iM = 0; iM < NM; ++iM) {
-            const double *cb = x + B.off + (long long)iM * B.npts;
+            const double *T = tile[wave] + iM * TS;
             double acc = 0;
-#pragma unroll 2
-            for (int a1 = 0; a1 < RZ; ++a1) {
+#pragma unroll
+            for (int c = 0; c < RZ; ++c) {
                 double accx = 0;
 #pragma unroll
-                for (int a2 = 0; a2 < RX; ++a2) {
-                    const double *row = cb + ((long long)hz[a1] * bnx + hx[a2]) * bny;
+                for (int a = 0; a < RXY; ++a) {
+                    const double *row = T + (c * RXY + a) * RXY;
                     double accy = 0;
 #pragma unroll
-                    for (int a3 = 0; a3 < RY; ++a3) accy += vy[a3] * row[hy[a3]];
-                    accx += vx[a2] * accy;
+                    for (int bq = 0; bq < RXY; ++bq) accy += vy[bq] * row[bq];
+                    accx += vx[a] * accy;
                 }
-                acc += vz[a1] * accx;
+                acc += vz[c] * accx;
             }
             val[iM] = acc;
         }
-        const double base = vs * xc * yc / den;
-        if (J == 0) {
-            out[0] += base * val[0];
-        } else {
-            double arg = (-s * xc * zc + c * yc) / yb;
-            arg = fmin(1.0, fmax(-1.0, arg));
-            double cw = sqrt(0.5 * (1.0 + arg)), sw = sqrt(0.5 * (1.0 - arg));
-            if (!is_cyclic(b, a)) cw = -cw;
-            const double sa = sqrt(fmax(omz, 0.0)), sb = sqrt(fmax(1.0 - zb * zb, 0.0));
-            double sbp[NM], sap[NM];
-            sbp[0] = M0 ? sb : 1.0;
-            sap[0] = M0 ? sa : 1.0;
+        double *y = cbuf + ((long long)req * 2 + slot) * N + outp;
 #pragma unroll
-            for (int k = 1; k < NM; ++k) { sbp[k] = sbp[k - 1] * sb; sap[k] = sap[k - 1] * sa; }
+        for (int iM = 0; iM < NM; ++iM) {
+            double o = 0;
 #pragma unroll
-            for (int iM = 0; iM < NM; ++iM) {
-                double acc = 0;
-#pragma unroll
-                for (int jM = 0; jM < NM; ++jM) {
-                    const double *G = pd->dcoef + (iM * NM + jM) * pd->dlen;
-                    // sum_k G[k] cw^k sw^(2J-k) by Horner in cw
-                    double f = G[2 * J], sp = 1.0;
-                    for (int k = 2 * J - 1; k >= 0; --k) {
-                        sp *= sw;
-                        f = f * cw + G[k] * sp;
-                    }
-                    acc += f * sbp[jM] * val[jM];
-                }
-                out[iM] += base * acc / sap[iM];
-            }
+            for (int jM = 0; jM < NM; ++jM) o += F[iM * NM + jM] * val[jM];
+            y[(long long)iM * npa] = o;
         }
     }
-    double *y = Y + (long long)req * pd->N + C.off + p;
-#pragma unroll
-    for (int iM = 0; iM < NM; ++iM) y[(long long)iM * C.npts] += out[iM];
 }
 
 // ---------------------------------------------------------------------------
@@ -1429,32 +1415,26 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 
 template <int QXY, int QZ, int NM>
 void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
-                  hipStream_t st, int part) {
+                  double *cbuf, hipStream_t st, int part) {
+    if (part != 1 && pd.cpl.ntasks > 0) {
+        dim3 grid(cdiv(pd.cpl.ntasks, CPL_WAVES), cdiv(nb, CPL_REQ));
+        hipLaunchKernelGGL((k_coupling_cells<QXY, QZ, NM>), grid, dim3(64 * CPL_WAVES), 0, st, pd.dev, active, nb, x,
+                           cbuf);
+    }
     if (part != 2) {
         const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
         hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
-                           sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y);
+                           sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y, cbuf, nb);
     }
-    if (part != 1) {
-        const long long pts = pd.comp[0].npts + pd.comp[1].npts + pd.comp[2].npts;
-        hipLaunchKernelGGL((k_coupling<QXY, QXY, QZ, NM>), dim3(cdiv(pts, 256), nb), dim3(256),
-                           sizeof(double) * pd.nodes_total, st, pd.dev, active, x, y);
-    }
-}
-
-bool matvec_tiled_ok(const ProblemDev &pd) {
-    const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
-    const size_t sh = sizeof(double) * std::max(pd.nodes_total, pd.tile_lds);
-    return same_xy && pd.q[2] != 0 && pd.nM <= 3 && sh <= 64 * 1024;
 }
 
 void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
-                   hipStream_t st, int part) {
+                   double *cbuf, hipStream_t st, int part) {
     if (matvec_tiled_ok(pd)) {
         const int key = (pd.q[0] == 3 ? 4 : 0) + (pd.q[2] == 3 ? 2 : 0);
         switch (key * 4 + pd.nM) {
 #define FM_TILED(QXY, QZ, NM) \
-    case ((QXY == 3 ? 4 : 0) + (QZ == 3 ? 2 : 0)) * 4 + NM: launch_tiled<QXY, QZ, NM>(pd, nb, E_dev, active, x, y, st, part); return;
+    case ((QXY == 3 ? 4 : 0) + (QZ == 3 ? 2 : 0)) * 4 + NM: launch_tiled<QXY, QZ, NM>(pd, nb, E_dev, active, x, y, cbuf, st, part); return;
             FM_TILED(3, 3, 1) FM_TILED(3, 3, 2) FM_TILED(3, 3, 3)
             FM_TILED(3, 2, 1) FM_TILED(3, 2, 2) FM_TILED(3, 2, 3)
             FM_TILED(2, 3, 1) FM_TILED(2, 3, 2) FM_TILED(2, 3, 3)

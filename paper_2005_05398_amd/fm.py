@@ -205,7 +205,9 @@ def _host_sigs(L):
     L.fm_host_pencil.argtypes = [ci, pd, pd, pd, pd, pd, pd, ctypes.POINTER(ctypes.c_byte), pd]
     L.fm_host_setup_check.argtypes = [ctypes.POINTER(FmDesc), pd, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_size_t)]
-    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check"):
+    L.fm_host_coupling.argtypes = [ctypes.POINTER(FmDesc), pd, pd, ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(ctypes.c_int)]
+    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check", "fm_host_coupling"):
         getattr(L, f).restype = ci
     L._host_sigs = True
 
@@ -252,6 +254,26 @@ def host_setup_check(desc):
     _check(L.fm_host_setup_check(ctypes.byref(make_c_desc(desc)), ctypes.byref(err), ctypes.byref(pairs),
                                  ctypes.byref(n)))
     return err.value, pairs.value, n.value
+
+
+def host_coupling(desc, x=None):
+    """(C x or None, number of coupling pairs, number of cell tasks): the
+    coupling term evaluated on the host from the library's grouped pairs."""
+    import numpy as np
+    L = lib()
+    _host_sigs(L)
+    npairs = ctypes.c_longlong()
+    ntasks = ctypes.c_int()
+    y = None
+    if x is not None:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(x)
+        _check(L.fm_host_coupling(ctypes.byref(make_c_desc(desc)), _dptr(x), _dptr(y), ctypes.byref(npairs),
+                                  ctypes.byref(ntasks)))
+    else:
+        _check(L.fm_host_coupling(ctypes.byref(make_c_desc(desc)), None, None, ctypes.byref(npairs),
+                                  ctypes.byref(ntasks)))
+    return y, npairs.value, ntasks.value
 
 
 # -- serving (fm_server_*) ----------------------------------------------------

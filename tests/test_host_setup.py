@@ -98,3 +98,40 @@ def test_library_full_setup(name):
     err, pairs, N = fm.host_setup_check(cfg["desc"])
     assert N == W.n_unknowns(cfg["desc"])
     assert err < 1e-8
+
+
+def _oracle_coupling(desc, x):
+    """C x from the oracle: the off-diagonal (alpha != beta) blocks of A(E)."""
+    from oracle.assemble import Problem as OracleProblem
+    O = OracleProblem(desc)
+    A = O.assemble(-0.3).tocoo()
+    comp = np.empty(O.N, dtype=np.int64)
+    for a in range(3):
+        lo = O.offsets[a][0]
+        comp[lo:lo + O.nM * O.block[a]] = a
+    keep = comp[A.row] != comp[A.col]
+    import scipy.sparse as sp
+    C = sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
+    return C @ x
+
+
+COUPLING_CASES = [
+    ("cubic_L0", W.cfg1()["desc"]),
+    ("quintic_hminus_L0", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic")),
+    ("quintic_cubicz_L1", W.make_desc(*W.PS_MINUS, 10, 6, J=1, deg_z=3, R=15.0)),
+    ("quintic_L1_odd", W.make_desc(*W.PS_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0)),
+    ("quintic_L2", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0)),
+]
+
+
+@lib_built
+@pytest.mark.parametrize("name,desc", COUPLING_CASES, ids=[c[0] for c in COUPLING_CASES])
+def test_host_coupling_pairs_match_oracle(name, desc):
+    """The grouped (point, partner) pairs that the device coupling kernel
+    evaluates reproduce the oracle's inter-component blocks."""
+    N = fm.host_setup_check(desc)[2]
+    x = W.rhs(77, N)
+    y, npairs, ntasks = fm.host_coupling(desc, x)
+    assert npairs > 0 and 64 * ntasks >= npairs and ntasks <= npairs
+    ref = _oracle_coupling(desc, x)
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref), name
