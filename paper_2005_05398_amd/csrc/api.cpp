@@ -294,18 +294,19 @@ void add_closing_work(fm_problem *p, const Work &w, int steps) {
     prof_work(p, FM_K_FINISH, 0, 10.0 * steps);
 }
 
+// tmp: [nb][N] scratch for the staged x-y products (may be null).
 void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
-                   int prec, double *min_den, hipStream_t st) {
+                   int prec, double *min_den, double *tmp, hipStream_t st) {
     if (prec != FM_FP64) {
         bool ok = true;
         timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 0, in, out, st); });
         timed(p, st, FM_K_XY, [&] { ok = launch_xy_lp(p->pd, p->pr, nb, E_dev, mask, out, prec, st); });
-        if (!ok) timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st); });
+        if (!ok) timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, tmp, st); });
         timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 1, out, out, st); });
         return;
     }
     timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 0, in, out, st); });
-    timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, st); });
+    timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, tmp, st); });
     timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 1, out, out, st); });
 }
 
@@ -315,7 +316,7 @@ void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, 
 
 size_t Batch::footprint(const fm_problem *p, int cap, int m) {
     return krylov_bytes(p->N, cap, m) + 3 * round256(sizeof(int) * cap) + round256(sizeof(double) * cap) +
-           round256(sizeof(double) * 2 * size_t(cap) * size_t(p->N));
+           round256(sizeof(double) * 2 * size_t(cap) * size_t(p->N)) + round256(sizeof(double) * size_t(cap) * size_t(p->N));
 }
 
 fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
@@ -338,6 +339,8 @@ fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
     min_den = reinterpret_cast<double *>(q);
     q += round256(sizeof(double) * cap);
     cbuf = reinterpret_cast<double *>(q);
+    q += round256(sizeof(double) * 2 * size_t(cap) * size_t(p->N));
+    ptmp = reinterpret_cast<double *>(q);
     void *h = nullptr;
     HIP_TRY(hipHostMalloc(&h, sizeof(int) * cap, hipHostMallocDefault));
     hbuf = static_cast<int *>(h);
@@ -446,7 +449,7 @@ fm_status Batch::cycle(const std::function<bool()> &want_cut, int min_steps) {
         double *Vj = K.V + (long long)j * nb * N;
         double *Zj = K.Z + (long long)j * nb * N;
         double *Vn = K.V + (long long)(j + 1) * nb * N;
-        apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, st);
+        apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, ptmp, st);
         apply_operator(p, nb, K.E, K.active, Zj, Vn, cbuf, st);
         timed(p, st, FM_K_MDOT, [&] { launch_arnoldi_dots(K, j, 0, st); });
         timed(p, st, FM_K_FINISH, [&] { launch_arnoldi_finish(K, j, 0, st); });
@@ -690,6 +693,7 @@ fm_status fm_destroy_problem(fm_problem *p) {
     if (p->ws) (void)hipFree(p->ws);
     if (p->ws_small) (void)hipFree(p->ws_small);
     if (p->cbuf) (void)hipFree(p->cbuf);
+    if (p->ptmp) (void)hipFree(p->ptmp);
     if (p->host_pinned) (void)hipHostFree(p->host_pinned);
     for (auto e : p->prof.ev) (void)hipEventDestroy(e);
     if (p->solve_batch) {
@@ -727,6 +731,7 @@ fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const do
     const size_t cb = sizeof(double) * 2 * size_t(nbatch) * size_t(p->N);
     if (p->cbuf_bytes < cb) {
         if (p->cbuf) (void)hipFree(p->cbuf);
+    if (p->ptmp) (void)hipFree(p->ptmp);
         p->cbuf = nullptr;
         p->cbuf_bytes = 0;
         HIP_TRY(hipMalloc(&p->cbuf, cb));
@@ -753,7 +758,15 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
     fm_status r = ensure_small(p, nbatch, s);
     if (r != FM_OK) return r;
     HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
-    apply_precond(p, nbatch, s.E, nullptr, r_dev, z_dev, prec, nullptr, st);
+    const size_t tb = sizeof(double) * size_t(nbatch) * size_t(p->N);
+    if (p->ptmp_bytes < tb) {
+        if (p->ptmp) (void)hipFree(p->ptmp);
+        p->ptmp = nullptr;
+        p->ptmp_bytes = 0;
+        HIP_TRY(hipMalloc(&p->ptmp, tb));
+        p->ptmp_bytes = tb;
+    }
+    apply_precond(p, nbatch, s.E, nullptr, r_dev, z_dev, prec, nullptr, p->ptmp, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     add_precond_work(p, Work(p), nbatch);

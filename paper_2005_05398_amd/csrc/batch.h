@@ -20,6 +20,7 @@ struct Batch {
     int *running = nullptr, *cont = nullptr, *fresh = nullptr;   // device masks [cap]
     double *min_den = nullptr;                                   // device [cap]
     double *cbuf = nullptr;                                      // device [cap][2][N] operator coupling
+    double *ptmp = nullptr;                                      // device [cap][N] preconditioner scratch
     int *hbuf = nullptr;                                         // pinned host scratch [cap]
     const double *B = nullptr;                                   // [cap][N]
     double *X = nullptr;                                         // [cap][N]

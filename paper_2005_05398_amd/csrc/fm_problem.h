@@ -68,6 +68,8 @@ struct fm_problem {
     size_t ws_small_bytes = 0;
     double *cbuf = nullptr;                  // coupling buffer of fm_apply_operator ([nb][2][N], zeroed)
     size_t cbuf_bytes = 0;
+    double *ptmp = nullptr;                  // scratch of fm_apply_precond ([nb][N])
+    size_t ptmp_bytes = 0;
     double *host_pinned = nullptr;           // pinned host scratch for flag read-back
     size_t host_pinned_bytes = 0;
     fm::Profile prof;

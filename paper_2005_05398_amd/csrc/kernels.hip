@@ -3,6 +3,8 @@
 // [request][alpha][M'][z][x][y] (y fastest).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fm_internal.h"
 
 namespace fm {
@@ -507,6 +509,52 @@ __global__ void __launch_bounds__(MZ_COLS) k_modez(const ProblemDev *__restrict_
     }
 }
 
+// Mode-z product with one (x, y) column per thread held in registers (nz <=
+// MAXNZ) and W in LDS (read by the whole wave at once): out[k'][p] =
+// sum_k W[k'][k] in[k][p].  Grid: (columns / 256, alpha x M', request); in and
+// out may alias (a thread reads its whole column before writing it).
+// F32: the products in FP32 (inputs rounded to FP32, outputs widened).
+constexpr int MZ2_THREADS = 256;
+
+template <int MAXNZ, bool F32>
+__global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__restrict__ pd,
+                                                           const PrecDev *__restrict__ pr,
+                                                           const int *__restrict__ active, int which,
+                                                           const double *in, double *out) {
+    using T = typename std::conditional<F32, float, double>::type;
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    const int nM = pd->nM;
+    const int a = blockIdx.y / nM, iM = blockIdx.y % nM;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nz = C.z.n, nxy = C.nxy;
+    if ((int)blockIdx.x * MZ2_THREADS >= nxy) return;
+    __shared__ T W[MAXNZ * MAXNZ];
+    if (F32) {
+        const float *Wg = F.Wz32 + ((size_t)iM * 2 + which) * nz * nz;
+        for (int t = threadIdx.x; t < nz * nz; t += MZ2_THREADS) W[t] = (T)Wg[t];
+    } else {
+        const double *Wg = F.Wz + ((size_t)iM * 2 + which) * nz * nz;
+        for (int t = threadIdx.x; t < nz * nz; t += MZ2_THREADS) W[t] = (T)Wg[t];
+    }
+    __syncthreads();
+    const int col = blockIdx.x * MZ2_THREADS + threadIdx.x;
+    if (col >= nxy) return;
+    const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts + col;
+    T v[MAXNZ];
+#pragma unroll
+    for (int k = 0; k < MAXNZ; ++k) v[k] = k < nz ? (T)in[base + (long long)k * nxy] : (T)0;
+    for (int k2 = 0; k2 < nz; ++k2) {
+        const T *w = W + k2 * nz;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < MAXNZ; ++k)
+            if (k < nz) acc += w[k] * v[k];
+        out[base + (long long)k2 * nxy] = (double)acc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Preconditioner, per (request, alpha, M', k) slice T (nx x ny, in LDS):
 //   T <- Wbar_x T Wbar_y^T;  solve (Lambda_x (x) I + I (x) Lambda_y - E) T' = T;
@@ -657,7 +705,9 @@ __global__ void __launch_bounds__(XY_THREADS) k_xy(const ProblemDev *__restrict_
 // waves accumulates its 16x16 output tiles in registers over the whole K
 // range, then, after a barrier, writes them back in place.
 // Operand layout of the 16x16x4 FP64 MFMA: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; it receives D[4*(l/16)+v][l%16], v = 0..3.
+// B[l/16][l%16]; it receives D[l/16 + 4v][l%16], v = 0..3 (each 64-bit
+// accumulator register holds four rows that are 4 apart; the FP32 16x16
+// MFMAs instead hold rows 4(l/16) + v).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int XYM_MAXT = 16;        // tiles per wave: (128/16)^2 / 4
 
@@ -700,7 +750,7 @@ __device__ void mfma_slice_mult(double *T, int ld, int nxp, int nyp, const doubl
         if (t < ntiles) {
             const int i0 = (t / tcols) << 4, j0 = (t % tcols) << 4;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) T[(i0 + 4 * k4 + v) * ld + j0 + r16] = acc[q][v];
+            for (int v = 0; v < 4; ++v) T[(i0 + k4 + 4 * v) * ld + j0 + r16] = acc[q][v];
         }
     }
     __syncthreads();
@@ -739,6 +789,107 @@ __global__ void __launch_bounds__(NW * 64) k_xy_mfma(const ProblemDev *__restric
     mfma_slice_mult<true, MAXT, NW>(T, ld, nxp, nyp, Wx, nx);
     mfma_slice_mult<false, MAXT, NW>(T, ld, nxp, nyp, Wy, ny);
     for (int t = threadIdx.x; t < nx * ny; t += NW * 64) g[t] = T[(t / ny) * ld + t % ny];
+}
+
+// ---------------------------------------------------------------------------
+// Staged x-y products, for batches with too few slices to fill the chip at one
+// block per slice: each of the four products is a batched FP64 MFMA GEMM over
+// all (request, alpha, M', k) slices with 32 x 32 output tiles (a 16 x 16 tile
+// per wave), reading one buffer and writing the other; the divide is a pass of
+// its own in between.  Slices are numbered alpha-major, then M', then k.
+constexpr int SG_T = 32, SG_KC = 16;
+
+__device__ __forceinline__ bool slice_decode(const ProblemDev *pd, int s, int &a, int &iM, int &k) {
+    a = 0;
+    while (a < 3 && s >= pd->nM * pd->comp[a].z.n) {
+        s -= pd->nM * pd->comp[a].z.n;
+        ++a;
+    }
+    if (a >= 3) return false;
+    iM = s / pd->comp[a].z.n;
+    k = s % pd->comp[a].z.n;
+    return true;
+}
+
+// LEFT: out = W in (W: nx x nx); RIGHT: out = in W^T (W: ny x ny); which
+// selects Wbar (0) or W (1) of the slice's pencil.  Grid: (tiles, slices,
+// requests); 256 threads.
+template <bool LEFT>
+__global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
+                                                    const int *__restrict__ active, int which,
+                                                    const double *__restrict__ in, double *__restrict__ out) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    int a, iM, k;
+    if (!slice_decode(pd, blockIdx.y, a, iM, k)) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
+    const int tc = (ny + SG_T - 1) / SG_T;
+    const int t = blockIdx.x;
+    if (t >= ((nx + SG_T - 1) / SG_T) * tc) return;
+    const int i0 = (t / tc) * SG_T, j0 = (t % tc) * SG_T;
+    const size_t fx = (size_t)iM * nz + k;
+    const double *Wm = LEFT ? F.Wx + (fx * 2 + which) * nx * nx : F.Wy + (fx * 2 + which) * ny * ny;
+    const long long off = (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    const double *g = in + off;
+    double *o = out + off;
+    const int K = LEFT ? nx : ny;
+    __shared__ double As[SG_T][SG_KC + 1];   // [row][k]
+    __shared__ double Bs[SG_KC][SG_T + 1];   // [k][col]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += SG_KC) {
+        for (int e = threadIdx.x; e < SG_T * SG_KC; e += 256) {
+            const int r = e / SG_KC, c = e % SG_KC;         // A[r][c]: row i0 + r, k0 + c
+            const int row = i0 + r, kk = k0 + c;
+            double av = 0.0;
+            if (row < nx && kk < K) av = LEFT ? Wm[(size_t)row * nx + kk] : g[(size_t)row * ny + kk];
+            As[r][c] = av;
+            double bv = 0.0;
+            if (LEFT) {
+                const int kb = e / SG_T, cb = e % SG_T;     // B[kb][cb] = in[k0 + kb][j0 + cb]
+                if (k0 + kb < K && j0 + cb < ny) bv = g[(size_t)(k0 + kb) * ny + j0 + cb];
+                Bs[kb][cb] = bv;
+            } else {
+                const int cb = e / SG_KC, kb = e % SG_KC;   // B[kb][cb] = W[j0 + cb][k0 + kb]
+                if (k0 + kb < K && j0 + cb < ny) bv = Wm[(size_t)(j0 + cb) * ny + k0 + kb];
+                Bs[kb][cb] = bv;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < SG_KC; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[16 * wi + r16][kk + k4], Bs[kk + k4][16 * wj + r16], acc,
+                                                       0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = i0 + 16 * wi + k4 + 4 * v, col = j0 + 16 * wj + r16;
+        if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[v];
+    }
+}
+
+// The divide by lambda_x + lambda_y - E of every slice in place (global
+// memory).  Grid: (slices, requests); 256 threads.
+__global__ void __launch_bounds__(256) k_slice_divide(const ProblemDev *__restrict__ pd,
+                                                      const PrecDev *__restrict__ pr,
+                                                      const double *__restrict__ Evec,
+                                                      const int *__restrict__ active, double *data,
+                                                      double *min_den) {
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    int a, iM, k;
+    if (!slice_decode(pd, blockIdx.x, a, iM, k)) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nx = C.x.n, ny = C.y.n;
+    const size_t fx = (size_t)iM * C.z.n + k;
+    double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    block_divide(g, ny, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
+                 F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1449,8 +1600,29 @@ void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int 
     hipLaunchKernelGGL(k_matvec, grid, dim3(256), 0, st, pd.dev, E_dev, active, x, y);
 }
 
+// Launches the register-column mode-z kernel for nz <= 64, else the LDS one.
+template <bool F32>
+bool launch_modez_reg(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
+                      const double *in, double *out, hipStream_t st) {
+    int maxnxy = 0, maxnz = 0;
+    for (int a = 0; a < 3; ++a) {
+        maxnxy = std::max(maxnxy, pd.comp[a].nxy);
+        maxnz = std::max(maxnz, pd.comp[a].z.n);
+    }
+    dim3 grid(cdiv(maxnxy, MZ2_THREADS), 3 * pd.nM, nb);
+#define FM_MZ(M) hipLaunchKernelGGL((k_modez_reg<M, F32>), grid, dim3(MZ2_THREADS), 0, st, pd.dev, pr.dev, active, which, in, out)
+    if (maxnz <= 16) FM_MZ(16);
+    else if (maxnz <= 32) FM_MZ(32);
+    else if (maxnz <= 48) FM_MZ(48);
+    else if (maxnz <= 64) FM_MZ(64);
+    else return false;
+#undef FM_MZ
+    return true;
+}
+
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
                   double *out, hipStream_t st) {
+    if (launch_modez_reg<false>(pd, pr, nb, active, which, in, out, st)) return;
     int maxnxy = 0, maxnz = 0;
     for (int a = 0; a < 3; ++a) {
         maxnxy = std::max(maxnxy, pd.comp[a].nxy);
@@ -1462,7 +1634,22 @@ void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *ac
 }
 
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
-               double *min_den, hipStream_t st) {
+               double *min_den, double *tmp, hipStream_t st) {
+    int slices = 0, tiles = 0;
+    for (int a = 0; a < 3; ++a) {
+        slices += pd.nM * pd.comp[a].z.n;
+        tiles = std::max(tiles, (int)(cdiv(pd.comp[a].x.n, SG_T) * cdiv(pd.comp[a].y.n, SG_T)));
+    }
+    if (tmp && (long long)slices * nb < XY_STAGED_BELOW) {
+        const dim3 g(tiles, slices, nb);
+        hipLaunchKernelGGL(k_slice_gemm<true>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 0, data, tmp);
+        hipLaunchKernelGGL(k_slice_gemm<false>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 0, tmp, data);
+        hipLaunchKernelGGL(k_slice_divide, dim3(slices, nb), dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, data,
+                           min_den);
+        hipLaunchKernelGGL(k_slice_gemm<true>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 1, data, tmp);
+        hipLaunchKernelGGL(k_slice_gemm<false>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 1, tmp, data);
+        return;
+    }
     int maxnz = 0, maxn = 0;
     for (int a = 0; a < 3; ++a) {
         maxnz = std::max(maxnz, pd.comp[a].z.n);
@@ -1494,6 +1681,7 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
 
 void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
                      double *out, hipStream_t st) {
+    if (launch_modez_reg<true>(pd, pr, nb, active, which, in, out, st)) return;
     int maxnxy = 0, maxnz = 0;
     for (int a = 0; a < 3; ++a) {
         maxnxy = std::max(maxnxy, pd.comp[a].nxy);

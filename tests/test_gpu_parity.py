@@ -200,3 +200,32 @@ def test_solve_rejects_nonfinite_rhs(device):
     with pytest.raises(fm.FmError) as e:
         P.solve([-0.25], to_dev(b, device), x)
     assert e.value.status == fm.FM_E_NONFINITE
+
+
+@pytest.mark.parametrize("name,desc", PREC_CASES, ids=[c[0] for c in PREC_CASES])
+def test_precond_one_block_per_slice_and_staged_paths(device, name, desc):
+    """Large batches run the x-y products with one block per slice, small ones
+    as batched GEMMs over all slices (fewer than 512 slices).  Both must match
+    the oracle's separable inverse, and each other.  Slices whose sides are
+    not multiples of 16 exercise the MFMA output rows that fall outside the
+    slice (they must map back inside it)."""
+    import torch
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    slices = sum(O.nM * O.bz[a].n for a in range(3))
+    nb_big = -(-512 // slices) + 1                      # one block per slice
+    rng = np.random.default_rng(9)
+    Es = list(np.linspace(-0.6, -0.1, nb_big))
+    R = rng.standard_normal((nb_big, O.N))
+    Zbig = to_dev(np.zeros((nb_big, O.N)), device)
+    P.apply_precond(Es, to_dev(R, device), Zbig)
+    Zsmall = to_dev(np.zeros((2, O.N)), device)           # staged
+    P.apply_precond(Es[:2], to_dev(R[:2], device), Zsmall)
+    Zb = Zbig.cpu().numpy()
+    for r in (0, 1, nb_big - 1):
+        ref = precond_reference(O, Es[r], R[r])
+        err = np.abs(Zb[r] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-9, (name, r, err)
+    d = (torch.linalg.norm(Zsmall - Zbig[:2]) / torch.linalg.norm(Zbig[:2])).item()
+    assert d <= 1e-11, d
