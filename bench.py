@@ -130,6 +130,31 @@ def serve_bench(args):
     print(json.dumps(line))
 
 
+COPY_BYTES = 512 << 20
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.json")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2005_05398_amd", "csrc",
+                             "kernels.hip")
+
+
+def measured_traffic(workload, kclass):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy factor),
+    or None when there is none for this workload and class or the kernel
+    source changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    e = rec.get("entries", {}).get(f"{workload}:{kclass}")
+    if not e or e.get("kernels_hip_sha256") != sha:
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +171,8 @@ def main():
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--serve-restart", type=int, default=100)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
@@ -181,6 +208,13 @@ def main():
             raise RuntimeError(f"solve failed: {fm.STATUS_NAMES.get(st)} {res}")
         return res
 
+    if args.calibrate_copy:
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -217,7 +251,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GB/s"] / HBM_PEAK_GBS}
-    roof.update({"kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"], "traffic": None})
+    roof.update({"kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
+                 "traffic": measured_traffic(args.workload, dom)})
     total_kernel_ms = sum(v["ms"] for v in prof.values())
     line = {
         "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "cfg2"
