@@ -68,45 +68,61 @@ def cpu_baseline(seconds_cap=30.0):
 
 
 def serve_bench(args):
-    """Serving: the seeded request stream, first all at once (saturation
-    throughput), then with Poisson arrivals at 0.8 x that throughput; p50/p99
-    of submit-to-done latency and solves/s of the Poisson phase."""
+    """Serving: the seeded request stream against one server.  Phase 1 submits
+    the first requests all at once (saturation throughput; it also builds the
+    problems of the shapes it meets, as a running service would have them);
+    phase 2 submits the whole stream with Poisson arrivals at 0.8 x the
+    saturated rate.  Reported: solves/s and p50/p99 of submit-to-done latency
+    in phase 2, and how many requests met the tolerance."""
     import numpy as np
     from paper_2005_05398_amd import fm
     from paper_2005_05398_amd import workloads as W
 
     reqs = [W.cfg5_request(i) for i in range(args.requests)]
+    t_gen = time.perf_counter()
+    rhs = [W.rhs(r["seed"], W.n_unknowns(r["desc"])) for r in reqs]
+    t_gen = time.perf_counter() - t_gen
+    print(f"serve: {len(reqs)} requests, right-hand sides built in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    srv = fm.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
 
-    def run(indices, arrivals):
-        srv = fm.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
+    def run(indices, arrivals, label):
         done = {}
+        xs = {}
         t0 = time.perf_counter()
+        t_report = t0
         k = 0
         while len(done) < len(indices):
             now = time.perf_counter() - t0
             while k < len(indices) and arrivals[k] <= now:
-                r = reqs[indices[k]]
-                N = W.n_unknowns(r["desc"])
-                b = W.rhs(r["seed"], N)
-                srv.submit(r["desc"], r["E"], b, np.zeros(N), indices[k], restart=args.serve_restart,
-                           rtol=1e-10, max_iters=3000, prec=args.prec)
+                i = indices[k]
+                r = reqs[i]
+                xs[(label, i)] = np.zeros(rhs[i].size)
+                srv.submit(r["desc"], r["E"], rhs[i], xs[(label, i)], i, restart=args.serve_restart,
+                           rtol=1e-10, max_iters=args.serve_max_iters, prec=args.prec)
                 k += 1
             block = k >= len(indices)
             for o in srv.poll(block=block):
                 done[o["tag"]] = o
+            if time.perf_counter() - t_report > 20:
+                t_report = time.perf_counter()
+                print(f"serve {label}: {len(done)}/{len(indices)} done, {k} submitted, "
+                      f"{t_report - t0:.0f} s", file=sys.stderr, flush=True)
             if not block:
-                time.sleep(0.002)
-        wall = time.perf_counter() - t0
-        srv.close()
-        return done, wall
+                time.sleep(0.001)
+        return done, time.perf_counter() - t0
 
-    nsat = min(len(reqs), args.saturation_requests)
-    sat, sat_wall = run(list(range(nsat)), np.zeros(nsat))
+    nsat = min(len(reqs), args.saturation_requests) if args.saturation_requests > 0 else len(reqs)
+    sat, sat_wall = run(list(range(nsat)), np.zeros(nsat), "saturation")
     sat_rate = nsat / sat_wall
+    print(f"serve saturation: {nsat} requests in {sat_wall:.1f} s ({sat_rate:.2f} solves/s)", file=sys.stderr,
+          flush=True)
     rate = 0.8 * sat_rate
     arrivals = W.cfg5_arrivals(len(reqs), rate)
-    done, wall = run(list(range(len(reqs))), arrivals)
+    done, wall = run(list(range(len(reqs))), arrivals, "poisson")
+    stats = srv.stats()
+    srv.close()
     lat = np.array([o["t_done"] - o["t_submit"] for o in done.values()])
+    wait = np.array([o["t_start"] - o["t_submit"] for o in done.values() if o["t_start"] > 0])
     status = {}
     for o in done.values():
         status[o["status"]] = status.get(o["status"], 0) + 1
@@ -118,14 +134,19 @@ def serve_bench(args):
         "config": {"workload": "seeded stream: quintic x,y {31,64,97,127} x cubic z {8,16,32}, L in {0,1,2}, "
                                "E in [-0.6,-0.05], two particle sets, seeded N(0,1) RHS",
                    "requests": len(reqs), "max_batch": args.max_batch, "restart": args.serve_restart,
-                   "budget_gb": args.budget_gb},
-        "saturation": {"requests": nsat, "solves_per_s": sat_rate, "wall_s": sat_wall},
+                   "max_iters": args.serve_max_iters, "budget_gb": args.budget_gb},
+        "saturation": {"requests": nsat, "solves_per_s": sat_rate, "wall_s": sat_wall,
+                       "ok": sum(1 for o in sat.values() if o["status"] == "FM_OK")},
         "arrival_rate_per_s": rate,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
+        "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))}
+        if wait.size else None,
         "status_counts": status,
         "wall_s": wall,
         "iters_mean": float(np.mean([o["iters"] for o in ok])) if ok else None,
+        "max_rel_residual_ok": max(o["rel_residual"] for o in ok) if ok else None,
+        "server_end": stats,
     }
     print(json.dumps(line))
 
@@ -167,9 +188,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the reduced-precision comparison runs")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--saturation-requests", type=int, default=64)
+    ap.add_argument("--saturation-requests", type=int, default=0, help="requests of the saturation phase (0: all)")
     ap.add_argument("--max-batch", type=int, default=8)
-    ap.add_argument("--serve-restart", type=int, default=100)
+    ap.add_argument("--serve-restart", type=int, default=200)
+    ap.add_argument("--serve-max-iters", type=int, default=6000)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counter scaling)")

@@ -344,7 +344,13 @@ fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
     void *h = nullptr;
     HIP_TRY(hipHostMalloc(&h, sizeof(int) * cap, hipHostMallocDefault));
     hbuf = static_cast<int *>(h);
-    HIP_TRY(hipMemsetAsync(mem, 0, bytes, st));
+    // zero everything but the Krylov bases and the preconditioner scratch, which
+    // are written before they are read (the coupling buffer must start at zero)
+    {
+        char *z0 = reinterpret_cast<char *>(K.H);
+        char *z1 = reinterpret_cast<char *>(ptmp);
+        HIP_TRY(hipMemsetAsync(z0, 0, size_t(z1 - z0), st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
     run.assign(cap, 0);
     iters.assign(cap, 0);

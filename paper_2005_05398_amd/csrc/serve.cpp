@@ -83,6 +83,10 @@ struct fm_server {
     std::deque<fm::ServeReq *> pending;
     std::deque<fm::ServeReq *> finished;
     std::map<std::string, fm_problem *> cache;
+    std::map<std::string, int> setting_up;   // problem keys being built (value unused)
+    int setups_running = 0;
+    std::vector<std::thread> setup_threads;  // joined when the dispatcher ends
+    bool evict_idle = false;           // set when a new lane waits for memory
     std::vector<fm::Lane *> lanes;
     size_t in_use = 0;
     long long outstanding = 0;         // submitted and not yet finished
@@ -124,9 +128,10 @@ void lane_loop(fm_server *S, Lane *L) {
                     S->cv.notify_all();
                     return;
                 }
-                // idle: give the lane back when nothing has arrived for a while
-                if (S->cv.wait_for(lk, std::chrono::milliseconds(200)) == std::cv_status::timeout &&
-                    L->joinq.empty() && !L->batch.any_running()) {
+                // idle: keep the workspace for the next request of this shape
+                // until a new lane needs the memory
+                S->cv.wait_for(lk, std::chrono::milliseconds(50));
+                if (S->evict_idle && L->joinq.empty() && !L->batch.any_running()) {
                     L->finished = true;
                     S->cv.notify_all();
                     return;
@@ -224,16 +229,51 @@ void reap_lanes(fm_server *S) {
     }
 }
 
+// Builds a problem off the dispatcher thread; the result goes to the cache (or
+// its failure to every pending request of that description).
+void setup_problem_async(fm_server *S, std::string pkey, fm_problem_desc d) {
+    (void)hipSetDevice(S->device);
+    d.device = S->device;
+    fm_problem *prob = nullptr;
+    fm_status st = fm_create_problem(&d, &prob);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->setting_up.erase(pkey);
+    S->setups_running -= 1;
+    if (st == FM_OK) {
+        S->cache[pkey] = prob;
+        size_t res = 0;
+        fm_problem_info(prob, nullptr, &res, 1, nullptr);
+        S->in_use += res;
+    } else {
+        for (auto it = S->pending.begin(); it != S->pending.end();) {
+            if (desc_key((*it)->desc) == pkey) {
+                (*it)->status = st;
+                finish(S, *it);
+                it = S->pending.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    S->cv.notify_all();
+}
+
+constexpr int MAX_SETUPS = 2;          // problem builds in flight (each is multi-threaded)
+
 void dispatch_loop(fm_server *S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         reap_lanes(S);
-        if (S->stop && S->pending.empty()) {
+        if (S->stop && S->pending.empty() && S->setups_running == 0) {
             bool all = true;
             for (auto *L : S->lanes) all &= L->finished;
             if (all) {
                 reap_lanes(S);
+                std::vector<std::thread> th;
+                th.swap(S->setup_threads);
+                lk.unlock();
+                for (auto &t : th) t.join();
                 return;
             }
             S->cv.notify_all();
@@ -241,10 +281,11 @@ void dispatch_loop(fm_server *S) {
             continue;
         }
         bool progressed = false;
+        // first every request whose lane exists, then at most one new lane (its
+        // problem set-up can take a while and must not hold up the others)
         for (auto it = S->pending.begin(); it != S->pending.end();) {
             ServeReq *r = *it;
-            std::string pkey = desc_key(r->desc);
-            std::string lkey = pkey + std::to_string(r->opts.prec) + ":" + std::to_string(r->opts.restart);
+            std::string lkey = desc_key(r->desc) + std::to_string(r->opts.prec) + ":" + std::to_string(r->opts.restart);
             Lane *lane = nullptr;
             for (auto *L : S->lanes)
                 if (L->key == lkey && !L->finished) lane = L;
@@ -253,25 +294,51 @@ void dispatch_loop(fm_server *S) {
                 it = S->pending.erase(it);
                 progressed = true;
                 S->cv.notify_all();
+            } else {
+                ++it;
+            }
+        }
+        for (auto it = S->pending.begin(); it != S->pending.end();) {
+            ServeReq *r = *it;
+            std::string pkey = desc_key(r->desc);
+            std::string lkey = pkey + std::to_string(r->opts.prec) + ":" + std::to_string(r->opts.restart);
+            bool has_lane = false;
+            for (auto *L : S->lanes)
+                if (L->key == lkey && !L->finished) has_lane = true;
+            if (has_lane) {
+                ++it;                      // attached on the next pass
                 continue;
             }
-            // a new lane: problem (cached) plus a batch of max_batch slots
-            fm_problem *prob = nullptr;
-            auto c = S->cache.find(pkey);
-            long long N = unknowns_of(r->desc);
-            size_t prob_bytes = 0;
-            if (c == S->cache.end()) {
-                // factor sizes: 2 n_z (n_x^2 + n_y^2) per component and M', in FP64, FP32 and 2 x BF16
-                for (int a = 0; a < 3; ++a)
-                    prob_bytes += size_t(r->desc.J + 2) * 2 * r->desc.z[a].n *
-                                  (size_t(r->desc.x[a].n) * r->desc.x[a].n + size_t(r->desc.y[a].n) * r->desc.y[a].n) *
-                                  (8 + 4 + 4);
-                prob_bytes += size_t(N) * 8;
+            // a new lane: problem (cached, else built off this thread) plus a batch
+            {
+                fm_problem one;
+                one.N = unknowns_of(r->desc);
+                if (Batch::footprint(&one, 1, r->opts.restart) + 2 * size_t(one.N) * 8 > S->budget) {
+                    r->status = FM_E_REJECTED;
+                    it = S->pending.erase(it);
+                    finish(S, r);
+                    continue;
+                }
             }
+            auto c = S->cache.find(pkey);
+            if (c == S->cache.end()) {
+                if (!S->setting_up.count(pkey) && S->setups_running < MAX_SETUPS) {
+                    S->setting_up[pkey] = 1;
+                    S->setups_running += 1;
+                    S->setup_threads.emplace_back(setup_problem_async, S, pkey, r->desc);
+                }
+                ++it;                      // the lane is made once the problem exists
+                continue;
+            }
+            fm_problem *prob = c->second;
+            long long N = unknowns_of(r->desc);
+            // slots: max_batch, fewer when one slot's workspace is large (a lane
+            // takes at most a quarter of the budget unless one slot needs more)
             fm_problem tmp;
             tmp.N = N;
-            size_t lane_bytes = Batch::footprint(&tmp, S->max_batch, r->opts.restart) + 2 * size_t(N) * 8 * S->max_batch;
-            size_t need = lane_bytes + prob_bytes;
+            const size_t per_slot = Batch::footprint(&tmp, 1, r->opts.restart) + 2 * size_t(N) * 8;
+            const int slots = int(std::max<size_t>(1, std::min<size_t>(S->max_batch, (S->budget / 4) / per_slot)));
+            size_t need = Batch::footprint(&tmp, slots, r->opts.restart) + 2 * size_t(N) * 8 * slots;
             if (need > S->budget) {
                 r->status = FM_E_REJECTED;
                 it = S->pending.erase(it);
@@ -279,38 +346,19 @@ void dispatch_loop(fm_server *S) {
                 continue;
             }
             if (S->in_use + need > S->budget) {
-                ++it;                      // wait for memory
+                S->evict_idle = true;      // idle lanes give their memory back
+                S->cv.notify_all();
+                ++it;
                 continue;
-            }
-            if (c == S->cache.end()) {
-                fm_problem_desc d = r->desc;
-                d.device = S->device;
-                lk.unlock();
-                fm_status st = fm_create_problem(&d, &prob);
-                lk.lock();
-                // submissions may have grown the queue meanwhile: find r again
-                it = std::find(S->pending.begin(), S->pending.end(), r);
-                if (st != FM_OK) {
-                    r->status = st;
-                    it = S->pending.erase(it);
-                    finish(S, r);
-                    continue;
-                }
-                S->cache[pkey] = prob;
-                size_t res = 0;
-                fm_problem_info(prob, nullptr, &res, 1, nullptr);
-                S->in_use += res;
-            } else {
-                prob = c->second;
             }
             Lane *L = new Lane();
             L->key = lkey;
             L->prob = prob;
-            L->slot.assign(S->max_batch, nullptr);
+            L->slot.assign(slots, nullptr);
             bool ok = hipStreamCreate(&L->st) == hipSuccess;
-            ok = ok && hipMalloc(reinterpret_cast<void **>(&L->B), sizeof(double) * N * S->max_batch) == hipSuccess;
-            ok = ok && hipMalloc(reinterpret_cast<void **>(&L->X), sizeof(double) * N * S->max_batch) == hipSuccess;
-            ok = ok && L->batch.create(prob, S->max_batch, r->opts.restart, L->st) == FM_OK;
+            ok = ok && hipMalloc(reinterpret_cast<void **>(&L->B), sizeof(double) * N * slots) == hipSuccess;
+            ok = ok && hipMalloc(reinterpret_cast<void **>(&L->X), sizeof(double) * N * slots) == hipSuccess;
+            ok = ok && L->batch.create(prob, slots, r->opts.restart, L->st) == FM_OK;
             if (!ok) {
                 if (L->B) (void)hipFree(L->B);
                 if (L->X) (void)hipFree(L->X);
@@ -326,13 +374,15 @@ void dispatch_loop(fm_server *S) {
             L->batch.X = L->X;
             L->batch.prec = r->opts.prec;
             L->batch.rtol = r->opts.rtol;
-            L->bytes = L->batch.bytes + 2 * sizeof(double) * N * S->max_batch;
+            L->bytes = L->batch.bytes + 2 * sizeof(double) * N * slots;
             S->in_use += L->bytes;
             L->joinq.push_back(r);
             it = S->pending.erase(it);
             S->lanes.push_back(L);
             L->th = std::thread(lane_loop, S, L);
+            S->evict_idle = false;
             progressed = true;
+            break;                         // back to the attach pass
         }
         if (!progressed) S->cv.wait_for(lk, std::chrono::milliseconds(5));
     }
