@@ -564,6 +564,29 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
                 rx = std::max(rx, hi - lo + 1);
             }
             pd.tile_lds = std::max(pd.tile_lds, rz * rx * p->by[a].n);
+            // x groups and the grouped tiles (stencil tile plus the x rows of its points)
+            std::vector<int> xg;
+            for (int i = 0; i < bx.n; ++i) {
+                const bool same = i > 0 && int(i - xg.back()) < 4 &&
+                                  std::equal(bx.idx.begin() + size_t(i) * MAXR, bx.idx.begin() + size_t(i + 1) * MAXR,
+                                             bx.idx.begin() + size_t(i - 1) * MAXR);
+                if (!same) xg.push_back(i);
+            }
+            C.ngx = int(xg.size());
+            xg.push_back(bx.n);
+            C.gt = std::max(1, std::min(C.ngx, 256 / p->by[a].n));
+            C.ntiles_g = bz.n * ((C.ngx + C.gt - 1) / C.gt);
+            for (int g0 = 0; g0 < C.ngx; g0 += C.gt) {
+                const int i0 = xg[g0], i1 = xg[std::min(C.ngx, g0 + C.gt)];
+                int lo = 1 << 30, hi = -1;
+                for (int i = i0; i < i1; ++i)
+                    for (int s = 0; s < MAXR; ++s) {
+                        int g = bx.idx[size_t(i) * MAXR + s];
+                        if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
+                    }
+                pd.tile_lds = std::max(pd.tile_lds, rz * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR);
+            }
+            C.xg = put(p, xg, err);
         }
         PrecCompDev &F = p->pr.comp[a];
         std::memset(&F, 0, sizeof(F));

@@ -76,6 +76,10 @@ struct CompDev {
     double c[3], s[3];           // (c_ba, s_ba) for beta = 0..2
     int xt;                      // x points per matvec tile
     int ntiles;                  // matvec tiles of this component: nz * ceil(nx / xt)
+    // x groups: runs of consecutive points with the same x support (<= 4 points)
+    const int *xg;               // ngx + 1 group starts (xg[ngx] = nx)
+    int ngx, gt;                 // number of groups, groups per grouped tile
+    int ntiles_g;                // grouped tiles: nz * ceil(ngx / gt)
 };
 
 // Coupling pairs grouped by (beta, cell of beta); built on the host.

@@ -223,6 +223,132 @@ __global__ void __launch_bounds__(256) k_matvec(const ProblemDev *__restrict__ p
 // per M' block.  The coupling comes from the two-slot buffer that the coupling
 // kernel filled before.  Q*: spline orders (2 cubic, 3 quintic); NM: number of
 // M' blocks.
+// n_M = 1: one thread per (x group, y point).  The points of an x group share
+// their x support, so each stencil row's y contractions (values and second
+// derivatives) are formed once and used for all of the group's points (<= 4).
+// Block: (component, z point, gt consecutive x groups); LDS holds the stencil
+// tile (z support x x support of the groups x all y) and the x rows of the
+// block's points.
+constexpr int XG_MAX = 4;
+
+template <int QX, int QY, int QZ>
+__global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restrict__ pd,
+                                                       const double *__restrict__ Evec,
+                                                       const int *__restrict__ active,
+                                                       const double *__restrict__ X, double *__restrict__ Y,
+                                                       const double *__restrict__ cbuf) {
+    constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    extern __shared__ double sm[];
+    int t = blockIdx.x, a = 0;
+    while (a < 3 && t >= pd->comp[a].ntiles_g) { t -= pd->comp[a].ntiles_g; ++a; }
+    if (a >= 3) return;
+    const CompDev &C = pd->comp[a];
+    const int nx = C.x.n, ny = C.y.n, gt = C.gt, ngx = C.ngx;
+    const int ntg = (ngx + gt - 1) / gt;
+    const int iz = t / ntg, g0 = (t % ntg) * gt;
+    const int ngt = min(gt, ngx - g0);
+    const int ixs = C.xg[g0], ixe = C.xg[g0 + ngt];
+    const int kzlo = C.z.first[iz], kzhi = C.z.last[iz];
+    const int kxlo = C.x.first[ixs], kxhi = C.x.last[ixe - 1];
+    const int Rz = kzhi - kzlo + 1, Rx = kxhi - kxlo + 1;
+    const int tile_n = Rz * Rx * ny;
+    double *tile = sm;
+    double *xS = sm + tile_n, *xD = xS + (ixe - ixs) * RX;
+    const bool has = threadIdx.x < ngt * ny;
+    const int gl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
+    const int px0 = C.xg[g0 + gl], pn = C.xg[g0 + gl + 1] - px0;
+    const double *x = X + (long long)req * pd->N + C.off;
+
+    int lx[RX], ly[RY];
+    double Sy[RY], D2y[RY];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+        const int g = C.x.idx[px0 * MAXR + s];
+        lx[s] = g >= 0 ? g - kxlo : 0;
+    }
+#pragma unroll
+    for (int s = 0; s < RY; ++s) {
+        const int g = C.y.idx[iy * MAXR + s];
+        ly[s] = g >= 0 ? g : 0;
+        Sy[s] = C.y.S[iy * MAXR + s];
+        D2y[s] = C.y.D2[iy * MAXR + s];
+    }
+    for (int e = threadIdx.x; e < tile_n; e += 256) {
+        const int kz = e / (Rx * ny), rest = e - kz * (Rx * ny);
+        tile[e] = x[((long long)(kzlo + kz) * nx + kxlo) * ny + rest];
+    }
+    for (int e = threadIdx.x; e < (ixe - ixs) * RX; e += 256) {
+        const int pp = e / RX, s = e % RX;
+        xS[e] = C.x.S[(ixs + pp) * MAXR + s];
+        xD[e] = C.x.D2[(ixs + pp) * MAXR + s];
+    }
+    __syncthreads();
+    if (!has) return;
+    const double *gS = xS + (px0 - ixs) * RX, *gD = xD + (px0 - ixs) * RX;
+    const int *zidx = C.z.idx + iz * MAXR;
+    const double *zS = C.z.S + iz * MAXR, *zD1 = C.z.D1 + iz * MAXR, *zD2 = C.z.D2 + iz * MAXR;
+    double s0[XG_MAX], s1[XG_MAX], s2[XG_MAX], sxx[XG_MAX], syy[XG_MAX];
+#pragma unroll
+    for (int q = 0; q < XG_MAX; ++q) s0[q] = s1[q] = s2[q] = sxx[q] = syy[q] = 0.0;
+#pragma unroll 1
+    for (int a1 = 0; a1 < RZ; ++a1) {
+        const int gzz = zidx[a1];
+        const int lz = gzz >= 0 ? gzz - kzlo : 0;
+        double b00[XG_MAX], b20[XG_MAX], b02[XG_MAX];
+#pragma unroll
+        for (int q = 0; q < XG_MAX; ++q) b00[q] = b20[q] = b02[q] = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < RX; ++a2) {
+            const double *row = tile + (lz * Rx + lx[a2]) * ny;
+            double t0 = 0, t2 = 0;
+#pragma unroll
+            for (int a3 = 0; a3 < RY; ++a3) {
+                const double cv = row[ly[a3]];
+                t0 += Sy[a3] * cv;
+                t2 += D2y[a3] * cv;
+            }
+#pragma unroll
+            for (int q = 0; q < XG_MAX; ++q)
+                if (q < pn) {
+                    const double sx = gS[q * RX + a2], dx = gD[q * RX + a2];
+                    b00[q] += sx * t0;
+                    b20[q] += dx * t0;
+                    b02[q] += sx * t2;
+                }
+        }
+        const double sz = zS[a1], d1 = zD1[a1], d2 = zD2[a1];
+#pragma unroll
+        for (int q = 0; q < XG_MAX; ++q) {
+            s0[q] += sz * b00[q];
+            s1[q] += d1 * b00[q];
+            s2[q] += d2 * b00[q];
+            sxx[q] += sz * b20[q];
+            syy[q] += sz * b02[q];
+        }
+    }
+    const double E = Evec[req];
+    const double zc = C.z.pts[iz], yc = C.y.pts[iy];
+    const double iy2 = 1.0 / (yc * yc), omz = 1.0 - zc * zc;
+    const int J = pd->J, Mp = pd->M0;
+    const double cJ = (double(J) * (J + 1) - 2.0 * Mp * Mp) * iy2 - E;
+    const double *c0 = cbuf + (long long)req * 2 * pd->N + C.off, *c1 = c0 + pd->N;
+    double *y = Y + (long long)req * pd->N + C.off;
+#pragma unroll
+    for (int q = 0; q < XG_MAX; ++q)
+        if (q < pn) {
+            const int ix = px0 + q;
+            const long long p = (long long)iz * C.nxy + ix * ny + iy;
+            const double xc = C.x.pts[ix];
+            const double inv2 = 1.0 / (xc * xc) + iy2;
+            const double o = -syy[q] - sxx[q] -
+                             inv2 * (omz * s2[q] - 2.0 * (Mp + 1) * zc * s1[q] - double(Mp) * (Mp + 1) * s0[q]) +
+                             (cJ + C.P[p]) * s0[q];
+            y[p] = o + c0[p] + c1[p];
+        }
+}
+
 template <int QX, int QY, int QZ, int NM>
 __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restrict__ pd, const double *__restrict__ Evec,
                                                       const int *__restrict__ active, const double *__restrict__ X,
@@ -1168,13 +1294,6 @@ __device__ __forceinline__ void chunk_range(long long N, int blk, long long &lo,
     hi = min(N, lo + per);
 }
 
-// Sum of the n partials p[0..n) by one wave; the result is valid in every lane.
-__device__ __forceinline__ double wave_sum_parts(const double *__restrict__ p, int n) {
-    double s = 0;
-    for (int b = threadIdx.x & 63; b < n; b += 64) s += p[b];
-    return wave_sum(s);
-}
-
 // Sum of the n partials p[0..n) by the block; valid in every thread.
 __device__ __forceinline__ double block_sum_parts(const double *__restrict__ p, int n, double *red) {
     double s = 0;
@@ -1221,33 +1340,49 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
 #pragma unroll
     for (int t = 0; t < MD_G; ++t) as[t] = at[t] = 0;
     long long e = lo + threadIdx.x;
-    for (; e + RT < hi; e += 2 * RT) {
-        const double u0 = U[e], u1 = U[e + RT];
-        const double w0 = CLOSING ? 0.0 : W[e], w1 = CLOSING ? 0.0 : W[e + RT];
-        uu += u0 * u0 + u1 * u1;
-        uw += u0 * w0 + u1 * w1;
-        ww += w0 * w0 + w1 * w1;
+    if (ng > 0) {
+        // every vector slot loads (slots past the group repeat its last vector,
+        // whose sums are dropped), so all loads of an iteration are in flight at once
+        const double *qp[MD_G];
 #pragma unroll
-        for (int t = 0; t < MD_G; ++t)
-            if (t < ng) {
-                const double *q = q0 + t * vstride + e;
-                const double a0 = q[0], a1 = q[RT];
-                as[t] += a0 * u0 + a1 * u1;
-                if (!CLOSING) at[t] += a0 * w0 + a1 * w1;
-            }
-    }
-    for (; e < hi; e += RT) {
-        const double u0 = U[e], w0 = CLOSING ? 0.0 : W[e];
-        uu += u0 * u0;
-        uw += u0 * w0;
-        ww += w0 * w0;
+        for (int t = 0; t < MD_G; ++t) qp[t] = q0 + (long long)min(t, ng - 1) * vstride;
+        for (; e + RT < hi; e += 2 * RT) {
+            const double u0 = U[e], u1 = U[e + RT];
+            const double w0 = CLOSING ? 0.0 : W[e], w1 = CLOSING ? 0.0 : W[e + RT];
+            double a0[MD_G], a1[MD_G];
 #pragma unroll
-        for (int t = 0; t < MD_G; ++t)
-            if (t < ng) {
-                const double a0 = q0[t * vstride + e];
-                as[t] += a0 * u0;
-                if (!CLOSING) at[t] += a0 * w0;
+            for (int t = 0; t < MD_G; ++t) {
+                a0[t] = qp[t][e];
+                a1[t] = qp[t][e + RT];
             }
+            uu += u0 * u0 + u1 * u1;
+            uw += u0 * w0 + u1 * w1;
+            ww += w0 * w0 + w1 * w1;
+#pragma unroll
+            for (int t = 0; t < MD_G; ++t) {
+                as[t] += a0[t] * u0 + a1[t] * u1;
+                if (!CLOSING) at[t] += a0[t] * w0 + a1[t] * w1;
+            }
+        }
+        for (; e < hi; e += RT) {
+            const double u0 = U[e], w0 = CLOSING ? 0.0 : W[e];
+            uu += u0 * u0;
+            uw += u0 * w0;
+            ww += w0 * w0;
+#pragma unroll
+            for (int t = 0; t < MD_G; ++t) {
+                const double a = qp[t][e];
+                as[t] += a * u0;
+                if (!CLOSING) at[t] += a * w0;
+            }
+        }
+    } else {
+        for (; e < hi; e += RT) {
+            const double u0 = U[e], w0 = CLOSING ? 0.0 : W[e];
+            uu += u0 * u0;
+            uw += u0 * w0;
+            ww += w0 * w0;
+        }
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -1300,13 +1435,32 @@ __global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int n
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = K.m;
     const double *part = K.part + (size_t)req * (2 * m + 3) * NBLK;
-    for (int row = wave; row < 2 * j + 3; row += RT / 64) {
-        const double s = wave_sum_parts(part + (size_t)row * nblk, nblk);
-        if (lane == 0) {
+    // row sums of the partials, 64 rows at a time: lane = row, the waves split
+    // the blocks (fixed assignment, so the sums are deterministic)
+    __shared__ double rsum[RT / 64][64];
+    const int nrows = 2 * j + 3;
+    for (int r0 = 0; r0 < nrows; r0 += 64) {
+        const int row = r0 + lane;
+        double a0 = 0, a1 = 0;
+        if (row < nrows) {
+            const double *pr = part + (size_t)row * nblk;
+            int b = wave;
+            for (; b + RT / 64 < nblk; b += 2 * (RT / 64)) {
+                a0 += pr[b];
+                a1 += pr[b + RT / 64];
+            }
+            for (; b < nblk; b += RT / 64) a0 += pr[b];
+        }
+        rsum[wave][lane] = a0 + a1;
+        __syncthreads();
+        if (wave == 0 && row < nrows) {
+            double s = 0;
+            for (int w = 0; w < RT / 64; ++w) s += rsum[w][lane];
             if (row < j) sv[row] = s;
             else if (row < 2 * j) tv[row - j] = s;
             else uu_uw[row - 2 * j] = s;
         }
+        __syncthreads();
     }
     double *hc = K.hcol + (size_t)req * (m + 1);
     double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m;
@@ -1400,11 +1554,15 @@ __global__ void __launch_bounds__(RT) k_arnoldi_update(KrylovDev K, int j) {
     const double *q = K.V + (long long)req * K.N + e;
     double qs = 0, qt = 0;
     int i = 0;
-    for (; i + 3 < j; i += 4) {
-        const double a0 = q[i * vstride], a1 = q[(i + 1) * vstride], a2 = q[(i + 2) * vstride],
-                     a3 = q[(i + 3) * vstride];
-        qs += a0 * s[i] + a1 * s[i + 1] + a2 * s[i + 2] + a3 * s[i + 3];
-        qt += a0 * t[i] + a1 * t[i + 1] + a2 * t[i + 2] + a3 * t[i + 3];
+    for (; i + 7 < j; i += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = q[(i + u) * vstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            qs += a[u] * s[i + u];
+            qt += a[u] * t[i + u];
+        }
     }
     for (; i < j; ++i) {
         const double a = q[i * vstride];
@@ -1573,9 +1731,15 @@ void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *
                            cbuf);
     }
     if (part != 2) {
-        const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
-        hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
-                           sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y, cbuf, nb);
+        if (NM == 1) {
+            const unsigned tiles = pd.comp[0].ntiles_g + pd.comp[1].ntiles_g + pd.comp[2].ntiles_g;
+            hipLaunchKernelGGL((k_local_grouped<QXY, QXY, QZ>), dim3(tiles, nb), dim3(256),
+                               sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y, cbuf);
+        } else {
+            const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
+            hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
+                               sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y, cbuf, nb);
+        }
     }
 }
 
