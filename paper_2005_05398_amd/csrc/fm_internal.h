@@ -172,10 +172,12 @@ void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int 
                    const double *x, double *y, double *cbuf, hipStream_t st, int part = 0);
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
                   const double *in, double *out, hipStream_t st);
-// tmp ([nb][N], may be null): with fewer than XY_STAGED_BELOW slices in the
-// batch the four products run as batched GEMMs through tmp (all slices at
-// once), else one block per slice.
+// tmp ([nb][N] scratch): the four products run as batched GEMMs through tmp
+// over all slices at once when a slice side exceeds XY_FUSED_MAX_SIDE or the
+// batch has fewer than XY_STAGED_BELOW slices; otherwise (many small slices)
+// one block per slice does all four in LDS.
 constexpr long long XY_STAGED_BELOW = 512;
+constexpr int XY_FUSED_MAX_SIDE = 32;
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
                double *data, double *min_den, double *tmp, hipStream_t st);
 // reduced-precision products (mode 1: FP32 MFMA, 2: BF16x3 MFMA); false if the slice does not fit

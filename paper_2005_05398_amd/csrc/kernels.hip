@@ -656,13 +656,13 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     const PrecCompDev &F = pr->comp[a];
     const int nz = C.z.n, nxy = C.nxy;
     if ((int)blockIdx.x * MZ2_THREADS >= nxy) return;
-    __shared__ T W[MAXNZ * MAXNZ];
+    __shared__ T W[(MAXNZ + 3) * MAXNZ];
     if (F32) {
         const float *Wg = F.Wz32 + ((size_t)iM * 2 + which) * nz * nz;
-        for (int t = threadIdx.x; t < nz * nz; t += MZ2_THREADS) W[t] = (T)Wg[t];
+        for (int t = threadIdx.x; t < (nz + 3) * nz; t += MZ2_THREADS) W[t] = t < nz * nz ? (T)Wg[t] : (T)0;
     } else {
         const double *Wg = F.Wz + ((size_t)iM * 2 + which) * nz * nz;
-        for (int t = threadIdx.x; t < nz * nz; t += MZ2_THREADS) W[t] = (T)Wg[t];
+        for (int t = threadIdx.x; t < (nz + 3) * nz; t += MZ2_THREADS) W[t] = t < nz * nz ? (T)Wg[t] : (T)0;
     }
     __syncthreads();
     const int col = blockIdx.x * MZ2_THREADS + threadIdx.x;
@@ -671,75 +671,25 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     T v[MAXNZ];
 #pragma unroll
     for (int k = 0; k < MAXNZ; ++k) v[k] = k < nz ? (T)in[base + (long long)k * nxy] : (T)0;
-    for (int k2 = 0; k2 < nz; ++k2) {
-        const T *w = W + k2 * nz;
-        T acc = 0;
+    // four outputs at a time (independent sums; rows past nz read zeros)
+    for (int k2 = 0; k2 < nz; k2 += 4) {
+        T acc[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < MAXNZ; ++k)
-            if (k < nz) acc += w[k] * v[k];
-        out[base + (long long)k2 * nxy] = (double)acc;
+            if (k < nz) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] += W[(k2 + u) * nz + k] * v[k];
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k2 + u < nz) out[base + (long long)(k2 + u) * nxy] = (double)acc[u];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioner, per (request, alpha, M', k) slice T (nx x ny, in LDS):
+// Preconditioner, per (request, alpha, M', k) slice T (nx x ny):
 //   T <- Wbar_x T Wbar_y^T;  solve (Lambda_x (x) I + I (x) Lambda_y - E) T' = T;
 //   T <- W_x T' W_y^T.
-// The products are done in place in LDS, a block of columns (rows) at a time,
-// with the block's outputs staged in registers.
-constexpr int XY_THREADS = 256;
-constexpr int XY_BLK = 16;
-constexpr int XY_MAXOUT = 12;        // outputs per thread per block: ceil(n*XY_BLK/256), n <= 192
-
-__device__ void left_mult(double *T, const double *__restrict__ Wm, int nx, int ny) {
-    // T <- Wm T  (Wm: nx x nx, row-major, global)
-    for (int j0 = 0; j0 < ny; j0 += XY_BLK) {
-        const int jb = min(XY_BLK, ny - j0);
-        const int nout = nx * jb;
-        double r[XY_MAXOUT];
-        int cnt = 0;
-        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
-            const int i = o / jb, j = j0 + o % jb;
-            const double *wr = Wm + (size_t)i * nx;
-            double acc = 0;
-            for (int l = 0; l < nx; ++l) acc += wr[l] * T[l * ny + j];
-            r[cnt++] = acc;
-        }
-        __syncthreads();
-        cnt = 0;
-        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
-            const int i = o / jb, j = j0 + o % jb;
-            T[i * ny + j] = r[cnt++];
-        }
-        __syncthreads();
-    }
-}
-
-__device__ void right_mult_t(double *T, const double *__restrict__ Wm, int nx, int ny) {
-    // T <- T Wm^T  (Wm: ny x ny, row-major, global)
-    for (int i0 = 0; i0 < nx; i0 += XY_BLK) {
-        const int ib = min(XY_BLK, nx - i0);
-        const int nout = ib * ny;
-        double r[XY_MAXOUT];
-        int cnt = 0;
-        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
-            const int i = i0 + o / ny, j = o % ny;
-            const double *wr = Wm + (size_t)j * ny;
-            double acc = 0;
-            for (int l = 0; l < ny; ++l) acc += T[i * ny + l] * wr[l];
-            r[cnt++] = acc;
-        }
-        __syncthreads();
-        cnt = 0;
-        for (int o = threadIdx.x; o < nout; o += XY_THREADS) {
-            const int i = i0 + o / ny, j = o % ny;
-            T[i * ny + j] = r[cnt++];
-        }
-        __syncthreads();
-    }
-}
-
-// (Lambda_x (x) I + I (x) Lambda_y - E) T' = T on the quasi-diagonal blocks.
 __device__ void block_divide(double *T, int ld, int nx, int ny, const double *lx, const double *lxi,
                              const signed char *tx, const double *ly, const double *lyi, const signed char *ty,
                              double E, double *min_den) {
@@ -795,34 +745,6 @@ __device__ void block_divide(double *T, int ld, int nx, int ny, const double *lx
             atomicMin((unsigned long long *)min_den, (unsigned long long)__double_as_longlong(red[0]));
     }
     __syncthreads();
-}
-
-__global__ void __launch_bounds__(XY_THREADS) k_xy(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr, const double *__restrict__ Evec,
-                                                   const int *__restrict__ active, double *data,
-                                                   double *min_den) {
-    const int req = blockIdx.z;
-    if (active && !active[req]) return;
-    const int a = blockIdx.y / MAXM, iM = blockIdx.y % MAXM;
-    if (iM >= pd->nM) return;
-    const CompDev &C = pd->comp[a];
-    const PrecCompDev &F = pr->comp[a];
-    const int k = blockIdx.x;
-    const int nz = C.z.n, nx = C.x.n, ny = C.y.n;
-    if (k >= nz) return;
-    extern __shared__ double T[];
-    double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
-    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) T[t] = g[t];
-    __syncthreads();
-    const size_t fx = (size_t)iM * nz + k;
-    const double *Wbx = F.Wx + fx * 2 * nx * nx, *Wx = Wbx + (size_t)nx * nx;
-    const double *Wby = F.Wy + fx * 2 * ny * ny, *Wy = Wby + (size_t)ny * ny;
-    left_mult(T, Wbx, nx, ny);
-    right_mult_t(T, Wby, nx, ny);
-    block_divide(T, ny, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
-                 F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
-    left_mult(T, Wx, nx, ny);
-    right_mult_t(T, Wy, nx, ny);
-    for (int t = threadIdx.x; t < nx * ny; t += XY_THREADS) g[t] = T[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -1319,9 +1241,11 @@ __device__ __forceinline__ double block_sum_parts(const double *__restrict__ p, 
 // Dot pass partials, stride nblk per row: s_i at row i, t_i at row j + i,
 // U.U at row 2j, U.W at 2j + 1, W.W at 2j + 2.  CLOSING: no W (the last
 // column of a cycle).
-// Grid: (blocks per request, groups of MD_G vectors of Q, requests).
-template <bool CLOSING>
+// Grid: (blocks per request, groups of G vectors of Q, requests); G = 4, 8 or
+// 16 by j, so that few vector slots repeat.
+template <bool CLOSING, int G>
 __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
+    constexpr int MD_G = G;
     const int req = blockIdx.z;
     if (!K.active[req]) return;
     __shared__ double red[2 * MD_G + 3][RT / 64];
@@ -1799,12 +1723,13 @@ void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *ac
 
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
                double *min_den, double *tmp, hipStream_t st) {
-    int slices = 0, tiles = 0;
+    int slices = 0, tiles = 0, side = 0;
     for (int a = 0; a < 3; ++a) {
         slices += pd.nM * pd.comp[a].z.n;
         tiles = std::max(tiles, (int)(cdiv(pd.comp[a].x.n, SG_T) * cdiv(pd.comp[a].y.n, SG_T)));
+        side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
     }
-    if (tmp && (long long)slices * nb < XY_STAGED_BELOW) {
+    if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
         const dim3 g(tiles, slices, nb);
         hipLaunchKernelGGL(k_slice_gemm<true>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 0, data, tmp);
         hipLaunchKernelGGL(k_slice_gemm<false>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 0, tmp, data);
@@ -1814,33 +1739,16 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         hipLaunchKernelGGL(k_slice_gemm<false>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 1, tmp, data);
         return;
     }
-    int maxnz = 0, maxn = 0;
+    // many slices of side <= 32: one block per slice, one 16 x 16 output tile per wave
+    int maxnz = 0;
+    size_t shm = 0;
     for (int a = 0; a < 3; ++a) {
         maxnz = std::max(maxnz, pd.comp[a].z.n);
-        maxn = std::max(maxn, pd.comp[a].nxy);
-    }
-    dim3 grid(maxnz, 3 * MAXM, nb);
-    size_t shm = 0;
-    int tpw = 0;                      // output tiles per wave
-    for (int a = 0; a < 3; ++a) {
         const int nxp = (pd.comp[a].x.n + 15) & ~15, nyp = (pd.comp[a].y.n + 15) & ~15;
         shm = std::max(shm, sizeof(double) * nxp * (nyp + 4));
-        tpw = std::max(tpw, ((nxp / 16) * (nyp / 16) + 3) / 4);
     }
-    if (tpw <= XYM_MAXT && shm <= xy_lds_limit()) {
-        // tpw: output tiles per wave with 4 waves; large slices use 8 waves
-#define FM_XYM(T, NW) hipLaunchKernelGGL((k_xy_mfma<T, NW>), grid, dim3(NW * 64), shm, st, pd.dev, pr.dev, E_dev, active, data, min_den)
-        if (tpw <= 1) FM_XYM(1, 4);
-        else if (tpw <= 2) FM_XYM(2, 4);
-        else if (tpw <= 4) FM_XYM(4, 4);
-        else if (tpw <= 8) FM_XYM(4, 8);
-        else if (tpw <= 12) FM_XYM(6, 8);
-        else FM_XYM(8, 8);
-#undef FM_XYM
-        return;
-    }
-    size_t sh = sizeof(double) * maxn;
-    hipLaunchKernelGGL(k_xy, grid, dim3(XY_THREADS), sh, st, pd.dev, pr.dev, E_dev, active, data, min_den);
+    dim3 grid(maxnz, 3 * MAXM, nb);
+    hipLaunchKernelGGL((k_xy_mfma<1, 4>), grid, dim3(256), shm, st, pd.dev, pr.dev, E_dev, active, data, min_den);
 }
 
 void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
@@ -1883,17 +1791,29 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
     return true;
 }
 
+int dots_group(int j) { return j <= 4 ? 4 : j <= 8 ? 8 : MD_G; }
+
 unsigned dots_blocks(const KrylovDev &k, int j) {
     // about 2048 blocks in flight, at most 64 elements per thread, at most NBLK per request
-    const long long groups = std::max<long long>(1, cdiv(j, MD_G));
+    const long long groups = std::max<long long>(1, cdiv(j, dots_group(j)));
     long long nblk = std::max<long long>(cdiv(2048, (long long)k.nb * groups), cdiv(k.N, (long long)RT * 64));
     return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
 }
 
 void launch_arnoldi_dots(const KrylovDev &k, int j, int closing, hipStream_t st) {
-    dim3 grid(dots_blocks(k, j), (unsigned)std::max(1, (int)cdiv(j, MD_G)), k.nb);
-    if (closing) hipLaunchKernelGGL(k_arnoldi_dots<true>, grid, dim3(RT), 0, st, k, j);
-    else hipLaunchKernelGGL(k_arnoldi_dots<false>, grid, dim3(RT), 0, st, k, j);
+    const int G = dots_group(j);
+    dim3 grid(dots_blocks(k, j), (unsigned)std::max(1, (int)cdiv(j, G)), k.nb);
+#define FM_DOTS(C, GG) hipLaunchKernelGGL((k_arnoldi_dots<C, GG>), grid, dim3(RT), 0, st, k, j)
+    if (closing) {
+        if (G == 4) FM_DOTS(true, 4);
+        else if (G == 8) FM_DOTS(true, 8);
+        else FM_DOTS(true, MD_G);
+    } else {
+        if (G == 4) FM_DOTS(false, 4);
+        else if (G == 8) FM_DOTS(false, 8);
+        else FM_DOTS(false, MD_G);
+    }
+#undef FM_DOTS
 }
 
 void launch_arnoldi_finish(const KrylovDev &k, int j, int closing, hipStream_t st) {
@@ -1941,12 +1861,6 @@ size_t xy_lds_limit() { return g_lds_limit; }
 
 void prepare_large_lds(size_t bytes) {
     if (bytes > g_lds_limit) g_lds_limit = bytes;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_xy), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(bytes));
-    const void *fns[] = {reinterpret_cast<const void *>(k_xy_mfma<1, 4>), reinterpret_cast<const void *>(k_xy_mfma<2, 4>),
-                         reinterpret_cast<const void *>(k_xy_mfma<4, 4>), reinterpret_cast<const void *>(k_xy_mfma<4, 8>),
-                         reinterpret_cast<const void *>(k_xy_mfma<6, 8>), reinterpret_cast<const void *>(k_xy_mfma<8, 8>)};
-    for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
     const void *lp[] = {reinterpret_cast<const void *>(k_xy_lp<1, 1, 4>), reinterpret_cast<const void *>(k_xy_lp<2, 1, 4>),
                         reinterpret_cast<const void *>(k_xy_lp<4, 1, 4>), reinterpret_cast<const void *>(k_xy_lp<4, 1, 8>),
                         reinterpret_cast<const void *>(k_xy_lp<6, 1, 8>), reinterpret_cast<const void *>(k_xy_lp<8, 1, 8>),

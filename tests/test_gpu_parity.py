@@ -204,11 +204,11 @@ def test_solve_rejects_nonfinite_rhs(device):
 
 @pytest.mark.parametrize("name,desc", PREC_CASES, ids=[c[0] for c in PREC_CASES])
 def test_precond_one_block_per_slice_and_staged_paths(device, name, desc):
-    """Large batches run the x-y products with one block per slice, small ones
-    as batched GEMMs over all slices (fewer than 512 slices).  Both must match
-    the oracle's separable inverse, and each other.  Slices whose sides are
-    not multiples of 16 exercise the MFMA output rows that fall outside the
-    slice (they must map back inside it)."""
+    """Batches of many small slices (side <= 32, 512 slices or more) run the
+    x-y products with one block per slice, the others as batched GEMMs over
+    all slices.  Both must match the oracle's separable inverse, and each
+    other.  Slices whose sides are not multiples of 16 exercise the MFMA
+    output rows that fall outside the slice (they must map back inside it)."""
     import torch
     fm = _fm()
     P = fm.Problem(desc)
