@@ -859,13 +859,57 @@ __device__ __forceinline__ bool slice_decode(const ProblemDev *pd, int s, int &a
     return true;
 }
 
+// One element of the divided slice, (Lambda_x (x) I + I (x) Lambda_y - E)^-1 T
+// at (i, j), from T and the 2x2 / 4x4 blocks of complex pairs it belongs to
+// (the same closed forms as block_divide); mind tracks min |denominator|.
+__device__ __forceinline__ double divided_at(const double *__restrict__ T, int ld, int i, int j,
+                                             const double *__restrict__ lx, const double *__restrict__ lxi,
+                                             const signed char *__restrict__ tx, const double *__restrict__ ly,
+                                             const double *__restrict__ lyi, const signed char *__restrict__ ty,
+                                             double E, double &mind) {
+    const int ti = tx[i], tj = ty[j];
+    const int i0 = ti == 2 ? i - 1 : i, j0 = tj == 2 ? j - 1 : j;
+    const double d = lx[i0] + ly[j0] - E;
+    if (ti == 0 && tj == 0) {
+        mind = fmin(mind, fabs(d));
+        return T[(size_t)i * ld + j] / d;
+    }
+    if (tj == 0) {
+        const double b = lxi[i0], r0 = T[(size_t)i0 * ld + j], r1 = T[(size_t)(i0 + 1) * ld + j], det = d * d + b * b;
+        mind = fmin(mind, sqrt(det));
+        return ti == 1 ? (d * r0 - b * r1) / det : (b * r0 + d * r1) / det;
+    }
+    if (ti == 0) {
+        const double b = lyi[j0], r0 = T[(size_t)i * ld + j0], r1 = T[(size_t)i * ld + j0 + 1], det = d * d + b * b;
+        mind = fmin(mind, sqrt(det));
+        return tj == 1 ? (d * r0 - b * r1) / det : (b * r0 + d * r1) / det;
+    }
+    const double bx = lxi[i0], by = lyi[j0];
+    const double r00 = T[(size_t)i0 * ld + j0], r01 = T[(size_t)i0 * ld + j0 + 1];
+    const double r10 = T[(size_t)(i0 + 1) * ld + j0], r11 = T[(size_t)(i0 + 1) * ld + j0 + 1];
+    const double p00 = 0.5 * (r00 + r11), p01 = 0.5 * (r01 - r10);
+    const double m00 = 0.5 * (r00 - r11), m01 = 0.5 * (r01 + r10);
+    const double bp = bx - by, bm = bx + by;
+    const double Dp = d * d + bp * bp, Dm = d * d + bm * bm;
+    mind = fmin(mind, sqrt(fmin(Dp, Dm)));
+    if (ti == 1 && tj == 1) return (d * p00 + bp * p01) / Dp + (d * m00 - bm * m01) / Dm;
+    if (ti == 1) return (d * p01 - bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
+    if (tj == 1) return (-d * p01 + bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
+    return (d * p00 + bp * p01) / Dp + (-d * m00 + bm * m01) / Dm;
+}
+
 // LEFT: out = W in (W: nx x nx); RIGHT: out = in W^T (W: ny x ny); which
-// selects Wbar (0) or W (1) of the slice's pencil.  Grid: (tiles, slices,
-// requests); 256 threads.
-template <bool LEFT>
+// selects Wbar (0) or W (1) of the slice's pencil.  DIV (LEFT only): the
+// input is divided by lambda_x + lambda_y - E element by element as it is
+// loaded (the divide of the tensor trick between the two product pairs);
+// min_den (may be null) receives the smallest |denominator| met.  Grid:
+// (tiles, slices, requests); 256 threads.
+template <bool LEFT, bool DIV>
 __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
+                                                    const double *__restrict__ Evec,
                                                     const int *__restrict__ active, int which,
-                                                    const double *__restrict__ in, double *__restrict__ out) {
+                                                    const double *__restrict__ in, double *__restrict__ out,
+                                                    double *min_den) {
     const int req = blockIdx.z;
     if (active && !active[req]) return;
     int a, iM, k;
@@ -883,6 +927,8 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const double *g = in + off;
     double *o = out + off;
     const int K = LEFT ? nx : ny;
+    const double E = DIV ? Evec[req] : 0.0;
+    double mind = 1e300;
     __shared__ double As[SG_T][SG_KC + 1];   // [row][k]
     __shared__ double Bs[SG_KC][SG_T + 1];   // [k][col]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -898,7 +944,10 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             double bv = 0.0;
             if (LEFT) {
                 const int kb = e / SG_T, cb = e % SG_T;     // B[kb][cb] = in[k0 + kb][j0 + cb]
-                if (k0 + kb < K && j0 + cb < ny) bv = g[(size_t)(k0 + kb) * ny + j0 + cb];
+                if (k0 + kb < K && j0 + cb < ny)
+                    bv = DIV ? divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
+                                          F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind)
+                             : g[(size_t)(k0 + kb) * ny + j0 + cb];
                 Bs[kb][cb] = bv;
             } else {
                 const int cb = e / SG_KC, kb = e % SG_KC;   // B[kb][cb] = W[j0 + cb][k0 + kb]
@@ -918,27 +967,20 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         const int row = i0 + 16 * wi + k4 + 4 * v, col = j0 + 16 * wj + r16;
         if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[v];
     }
+    if (DIV && min_den) {
+        // block minimum, then one atomic per block on the bit pattern (positive doubles)
+        __shared__ double red[256];
+        red[threadIdx.x] = mind;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            atomicMin((unsigned long long *)(min_den + req), (unsigned long long)__double_as_longlong(red[0]));
+    }
 }
 
-// The divide by lambda_x + lambda_y - E of every slice in place (global
-// memory).  Grid: (slices, requests); 256 threads.
-__global__ void __launch_bounds__(256) k_slice_divide(const ProblemDev *__restrict__ pd,
-                                                      const PrecDev *__restrict__ pr,
-                                                      const double *__restrict__ Evec,
-                                                      const int *__restrict__ active, double *data,
-                                                      double *min_den) {
-    const int req = blockIdx.y;
-    if (active && !active[req]) return;
-    int a, iM, k;
-    if (!slice_decode(pd, blockIdx.x, a, iM, k)) return;
-    const CompDev &C = pd->comp[a];
-    const PrecCompDev &F = pr->comp[a];
-    const int nx = C.x.n, ny = C.y.n;
-    const size_t fx = (size_t)iM * C.z.n + k;
-    double *g = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
-    block_divide(g, ny, nx, ny, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny,
-                 F.ty + fx * ny, Evec[req], min_den ? min_den + req : nullptr);
-}
 
 // ---------------------------------------------------------------------------
 // Reduced-precision preconditioner products (the divide stays FP64).
@@ -1238,8 +1280,8 @@ __device__ __forceinline__ double block_sum_parts(const double *__restrict__ p, 
 // A M^-1 U is expressed in the orthonormal basis by exactly this column, and
 // the solution update uses the stored M^-1 U directly.
 //
-// Dot pass partials, stride nblk per row: s_i at row i, t_i at row j + i,
-// U.U at row 2j, U.W at 2j + 1, W.W at 2j + 2.  CLOSING: no W (the last
+// Dot pass partials, per block a row of 2m + 3 values: s_i at i, t_i at j + i,
+// U.U at 2j, U.W at 2j + 1, W.W at 2j + 2.  CLOSING: no W (the last
 // column of a cycle).
 // Grid: (blocks per request, groups of G vectors of Q, requests); G = 4, 8 or
 // 16 by j, so that few vector slots repeat.
@@ -1252,7 +1294,6 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     const int g0 = blockIdx.y * MD_G;
     const int ng = max(0, min(MD_G, j - g0));
     const bool lead = blockIdx.y == 0;
-    const int nblk = gridDim.x;
     long long lo, hi;
     chunk_range(K.N, blockIdx.x, lo, hi);
     const long long vstride = (long long)K.nb * K.N;
@@ -1270,24 +1311,6 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
         const double *qp[MD_G];
 #pragma unroll
         for (int t = 0; t < MD_G; ++t) qp[t] = q0 + (long long)min(t, ng - 1) * vstride;
-        for (; e + RT < hi; e += 2 * RT) {
-            const double u0 = U[e], u1 = U[e + RT];
-            const double w0 = CLOSING ? 0.0 : W[e], w1 = CLOSING ? 0.0 : W[e + RT];
-            double a0[MD_G], a1[MD_G];
-#pragma unroll
-            for (int t = 0; t < MD_G; ++t) {
-                a0[t] = qp[t][e];
-                a1[t] = qp[t][e + RT];
-            }
-            uu += u0 * u0 + u1 * u1;
-            uw += u0 * w0 + u1 * w1;
-            ww += w0 * w0 + w1 * w1;
-#pragma unroll
-            for (int t = 0; t < MD_G; ++t) {
-                as[t] += a0[t] * u0 + a1[t] * u1;
-                if (!CLOSING) at[t] += a0[t] * w0 + a1[t] * w1;
-            }
-        }
         for (; e < hi; e += RT) {
             const double u0 = U[e], w0 = CLOSING ? 0.0 : W[e];
             uu += u0 * u0;
@@ -1327,7 +1350,8 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
         }
     }
     __syncthreads();
-    double *part = K.part + (size_t)req * (2 * K.m + 3) * NBLK;
+    // partials block-major: part[block][row], row stride 2m + 3
+    double *part = K.part + (size_t)req * (2 * K.m + 3) * NBLK + (size_t)blockIdx.x * (2 * K.m + 3);
     const int r = threadIdx.x;
     int row = -1;
     if (r < ng) row = g0 + r;
@@ -1338,7 +1362,7 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     if (row >= 0) {
         double s = 0;
         for (int wv = 0; wv < RT / 64; ++wv) s += red[r][wv];
-        part[(size_t)row * nblk + blockIdx.x] = s;
+        part[row] = s;
     }
 }
 
@@ -1365,17 +1389,26 @@ __global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int n
     const int nrows = 2 * j + 3;
     for (int r0 = 0; r0 < nrows; r0 += 64) {
         const int row = r0 + lane;
-        double a0 = 0, a1 = 0;
+        constexpr int NW = RT / 64, ILP = 8;
+        double a[ILP];
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) a[u] = 0;
         if (row < nrows) {
-            const double *pr = part + (size_t)row * nblk;
+            const size_t rs = 2 * m + 3;
             int b = wave;
-            for (; b + RT / 64 < nblk; b += 2 * (RT / 64)) {
-                a0 += pr[b];
-                a1 += pr[b + RT / 64];
+            for (; b + (ILP - 1) * NW < nblk; b += ILP * NW) {
+                double v[ILP];
+#pragma unroll
+                for (int u = 0; u < ILP; ++u) v[u] = part[(size_t)(b + u * NW) * rs + row];
+#pragma unroll
+                for (int u = 0; u < ILP; ++u) a[u] += v[u];
             }
-            for (; b < nblk; b += RT / 64) a0 += pr[b];
+            for (; b < nblk; b += NW) a[0] += part[(size_t)b * rs + row];
         }
-        rsum[wave][lane] = a0 + a1;
+        double tot = 0;
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) tot += a[u];
+        rsum[wave][lane] = tot;
         __syncthreads();
         if (wave == 0 && row < nrows) {
             double s = 0;
@@ -1731,12 +1764,14 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
     }
     if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
         const dim3 g(tiles, slices, nb);
-        hipLaunchKernelGGL(k_slice_gemm<true>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 0, data, tmp);
-        hipLaunchKernelGGL(k_slice_gemm<false>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 0, tmp, data);
-        hipLaunchKernelGGL(k_slice_divide, dim3(slices, nb), dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, data,
-                           min_den);
-        hipLaunchKernelGGL(k_slice_gemm<true>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 1, data, tmp);
-        hipLaunchKernelGGL(k_slice_gemm<false>, g, dim3(256), 0, st, pd.dev, pr.dev, active, 1, tmp, data);
+        hipLaunchKernelGGL((k_slice_gemm<true, false>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 0, data,
+                           tmp, nullptr);
+        hipLaunchKernelGGL((k_slice_gemm<false, false>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 0, tmp,
+                           data, nullptr);
+        hipLaunchKernelGGL((k_slice_gemm<true, true>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 1, data,
+                           tmp, min_den);
+        hipLaunchKernelGGL((k_slice_gemm<false, false>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 1, tmp,
+                           data, nullptr);
         return;
     }
     // many slices of side <= 32: one block per slice, one 16 x 16 output tile per wave
@@ -1794,9 +1829,11 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
 int dots_group(int j) { return j <= 4 ? 4 : j <= 8 ? 8 : MD_G; }
 
 unsigned dots_blocks(const KrylovDev &k, int j) {
-    // about 2048 blocks in flight, at most 64 elements per thread, at most NBLK per request
+    // about 2048 blocks in flight, but 16 to 64 elements per thread and at most NBLK per request
     const long long groups = std::max<long long>(1, cdiv(j, dots_group(j)));
-    long long nblk = std::max<long long>(cdiv(2048, (long long)k.nb * groups), cdiv(k.N, (long long)RT * 64));
+    long long nblk = std::max<long long>(std::min<long long>(cdiv(2048, (long long)k.nb * groups),
+                                                             cdiv(k.N, (long long)RT * 16)),
+                                         cdiv(k.N, (long long)RT * 64));
     return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
 }
 
