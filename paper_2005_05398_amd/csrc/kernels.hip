@@ -845,7 +845,7 @@ __global__ void __launch_bounds__(NW * 64) k_xy_mfma(const ProblemDev *__restric
 // all (request, alpha, M', k) slices with 32 x 32 output tiles (a 16 x 16 tile
 // per wave), reading one buffer and writing the other; the divide is a pass of
 // its own in between.  Slices are numbered alpha-major, then M', then k.
-constexpr int SG_T = 32, SG_KC = 16;
+constexpr int SG_T = 32, SG_KC = 32;
 
 __device__ __forceinline__ bool slice_decode(const ProblemDev *pd, int s, int &a, int &iM, int &k) {
     a = 0;
@@ -933,29 +933,47 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     __shared__ double Bs[SG_KC][SG_T + 1];   // [k][col]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
-    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += SG_KC) {
-        for (int e = threadIdx.x; e < SG_T * SG_KC; e += 256) {
-            const int r = e / SG_KC, c = e % SG_KC;         // A[r][c]: row i0 + r, k0 + c
+    constexpr int PER = SG_T * SG_KC / 256;   // A and B values per thread per chunk
+    double ra[PER], rb[PER];
+    // the next chunk is fetched into registers while the current one is multiplied
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / SG_KC, c = e % SG_KC;          // A[r][c]: row i0 + r, k0 + c
             const int row = i0 + r, kk = k0 + c;
             double av = 0.0;
             if (row < nx && kk < K) av = LEFT ? Wm[(size_t)row * nx + kk] : g[(size_t)row * ny + kk];
-            As[r][c] = av;
+            ra[q] = av;
             double bv = 0.0;
             if (LEFT) {
-                const int kb = e / SG_T, cb = e % SG_T;     // B[kb][cb] = in[k0 + kb][j0 + cb]
+                const int kb = e / SG_T, cb = e % SG_T;      // B[kb][cb] = in[k0 + kb][j0 + cb]
                 if (k0 + kb < K && j0 + cb < ny)
                     bv = DIV ? divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
                                           F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind)
                              : g[(size_t)(k0 + kb) * ny + j0 + cb];
-                Bs[kb][cb] = bv;
             } else {
-                const int cb = e / SG_KC, kb = e % SG_KC;   // B[kb][cb] = W[j0 + cb][k0 + kb]
+                const int cb = e / SG_KC, kb = e % SG_KC;    // B[kb][cb] = W[j0 + cb][k0 + kb]
                 if (k0 + kb < K && j0 + cb < ny) bv = Wm[(size_t)(j0 + cb) * ny + k0 + kb];
-                Bs[kb][cb] = bv;
             }
+            rb[q] = bv;
         }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            As[e / SG_KC][e % SG_KC] = ra[q];
+            if (LEFT) Bs[e / SG_T][e % SG_T] = rb[q];
+            else Bs[e % SG_KC][e / SG_KC] = rb[q];
+        }
+    };
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += SG_KC) {
+        stash();
         __syncthreads();
+        if (k0 + SG_KC < K) fetch(k0 + SG_KC);
 #pragma unroll
         for (int kk = 0; kk < SG_KC; kk += 4)
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[16 * wi + r16][kk + k4], Bs[kk + k4][16 * wj + r16], acc,
