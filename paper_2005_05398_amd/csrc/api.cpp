@@ -300,7 +300,7 @@ void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, 
     if (prec != FM_FP64) {
         bool ok = true;
         timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 0, in, out, st); });
-        timed(p, st, FM_K_XY, [&] { ok = launch_xy_lp(p->pd, p->pr, nb, E_dev, mask, out, prec, st); });
+        timed(p, st, FM_K_XY, [&] { ok = launch_xy_lp(p->pd, p->pr, nb, E_dev, mask, out, prec, tmp, st); });
         if (!ok) timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, out, min_den, tmp, st); });
         timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 1, out, out, st); });
         return;

@@ -184,7 +184,7 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
 void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
                      const double *in, double *out, hipStream_t st);
 bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
-                  double *data, int mode, hipStream_t st);
+                  double *data, int mode, double *tmp, hipStream_t st);
 // Arnoldi / GMRES pieces (V and Z stored [i][request][N])
 // Step j: dot pass over slots 0..j+1 (0..j when closing), then the per-request
 // finish (Hessenberg column j - 1, Givens, stop test), then the update pass.

@@ -1158,6 +1158,114 @@ __device__ void block_divide_f32(float *T, int ld, int nx, int ny, const double 
     __syncthreads();
 }
 
+// Staged x-y products in reduced precision (same tiling and pipelining as
+// k_slice_gemm): MODE 1 FP32 MFMA, MODE 2 BF16x3 MFMA (each operand split into
+// bfloat16 hi + mid on the fly, three products, FP32 sums).  Storage between
+// the products stays FP64; DIV applies the FP64 divide while loading.
+template <bool LEFT, bool DIV, int MODE>
+__global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restrict__ pd,
+                                                       const PrecDev *__restrict__ pr,
+                                                       const double *__restrict__ Evec,
+                                                       const int *__restrict__ active, int which,
+                                                       const double *__restrict__ in, double *__restrict__ out) {
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    int a, iM, k;
+    if (!slice_decode(pd, blockIdx.y, a, iM, k)) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
+    const int tc = (ny + SG_T - 1) / SG_T;
+    const int t = blockIdx.x;
+    if (t >= ((nx + SG_T - 1) / SG_T) * tc) return;
+    const int i0 = (t / tc) * SG_T, j0 = (t % tc) * SG_T;
+    const size_t fx = (size_t)iM * nz + k;
+    const float *Wm = LEFT ? F.Wx32 + (fx * 2 + which) * nx * nx : F.Wy32 + (fx * 2 + which) * ny * ny;
+    const long long off = (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    const double *g = in + off;
+    double *o = out + off;
+    const int K = LEFT ? nx : ny;
+    const double E = DIV ? Evec[req] : 0.0;
+    double mind = 1e300;
+    __shared__ float As[SG_T][SG_KC + 1];   // [row][k]
+    __shared__ float Bs[SG_KC][SG_T + 1];   // [k][col]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
+    constexpr int PER = SG_T * SG_KC / 256;
+    float ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / SG_KC, c = e % SG_KC;
+            const int row = i0 + r, kk = k0 + c;
+            float av = 0.f;
+            if (row < nx && kk < K) av = LEFT ? Wm[(size_t)row * nx + kk] : (float)g[(size_t)row * ny + kk];
+            ra[q] = av;
+            float bv = 0.f;
+            if (LEFT) {
+                const int kb = e / SG_T, cb = e % SG_T;
+                if (k0 + kb < K && j0 + cb < ny)
+                    bv = (float)(DIV ? divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx,
+                                                  F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E,
+                                                  mind)
+                                     : g[(size_t)(k0 + kb) * ny + j0 + cb]);
+            } else {
+                const int cb = e / SG_KC, kb = e % SG_KC;
+                if (k0 + kb < K && j0 + cb < ny) bv = Wm[(size_t)(j0 + cb) * ny + k0 + kb];
+            }
+            rb[q] = bv;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            As[e / SG_KC][e % SG_KC] = ra[q];
+            if (LEFT) Bs[e / SG_T][e % SG_T] = rb[q];
+            else Bs[e % SG_KC][e / SG_KC] = rb[q];
+        }
+    };
+    flt4 acc = flt4{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += SG_KC) {
+        stash();
+        __syncthreads();
+        if (k0 + SG_KC < K) fetch(k0 + SG_KC);
+        if (MODE == 1) {
+#pragma unroll
+            for (int kk = 0; kk < SG_KC; kk += 4)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(As[16 * wi + r16][kk + k4], Bs[kk + k4][16 * wj + r16], acc,
+                                                           0, 0, 0);
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < SG_KC; kb += 16) {
+                sht4 ahi, amid, bhi, bmid;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    short h, m;
+                    split_bf16(As[16 * wi + r16][kb + 4 * k4 + e], h, m);
+                    ahi[e] = h;
+                    amid[e] = m;
+                    split_bf16(Bs[kb + 4 * k4 + e][16 * wj + r16], h, m);
+                    bhi[e] = h;
+                    bmid[e] = m;
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(amid, bhi, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bmid, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    (void)mind;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = i0 + 16 * wi + 4 * k4 + v, col = j0 + 16 * wj + r16;
+        if (row < nx && col < ny) o[(size_t)row * ny + col] = (double)acc[v];
+    }
+}
+
 template <int MAXT, int MODE, int NW>
 __global__ void __launch_bounds__(NW * 64) k_xy_lp(const ProblemDev *__restrict__ pd,
                                                       const PrecDev *__restrict__ pr,
@@ -1818,7 +1926,33 @@ void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int 
 }
 
 bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
-                  int mode, hipStream_t st) {
+                  int mode, double *tmp, hipStream_t st) {
+    {
+        int slices = 0, tiles = 0, side = 0;
+        for (int a = 0; a < 3; ++a) {
+            slices += pd.nM * pd.comp[a].z.n;
+            tiles = std::max(tiles, (int)(cdiv(pd.comp[a].x.n, SG_T) * cdiv(pd.comp[a].y.n, SG_T)));
+            side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
+        }
+        if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
+            const dim3 g(tiles, slices, nb);
+#define FM_SGLP(L, D, M, W, I, O) \
+    hipLaunchKernelGGL((k_slice_gemm_lp<L, D, M>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, W, I, O)
+            if (mode == 1) {
+                FM_SGLP(true, false, 1, 0, data, tmp);
+                FM_SGLP(false, false, 1, 0, tmp, data);
+                FM_SGLP(true, true, 1, 1, data, tmp);
+                FM_SGLP(false, false, 1, 1, tmp, data);
+            } else {
+                FM_SGLP(true, false, 2, 0, data, tmp);
+                FM_SGLP(false, false, 2, 0, tmp, data);
+                FM_SGLP(true, true, 2, 1, data, tmp);
+                FM_SGLP(false, false, 2, 1, tmp, data);
+            }
+#undef FM_SGLP
+            return true;
+        }
+    }
     int maxnz = 0, tpw = 0;
     size_t shm = 0;
     for (int a = 0; a < 3; ++a) {
