@@ -109,11 +109,13 @@ struct ProblemDev {
 
 // The operator runs as two tiled kernels (coupling into a two-slot buffer, then
 // the local stencil plus that buffer) when x and y share one spline order in
-// all components, z one order, n_M <= 3 and the stencil tile fits 64 KB of LDS;
-// otherwise one generic kernel does everything.
+// all components, z one order, n_M <= 3, n_y <= 256 and the stencil tile fits
+// 64 KB of LDS; otherwise one generic kernel does everything.
 inline bool matvec_tiled_ok(const ProblemDev &pd) {
     const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
-    return same_xy && pd.q[2] != 0 && pd.nM <= 3 && sizeof(double) * size_t(pd.tile_lds) <= 64 * 1024;
+    bool rows_fit = true;                // one block of 256 threads covers the y points
+    for (int a = 0; a < 3; ++a) rows_fit = rows_fit && pd.comp[a].y.n <= 256;
+    return same_xy && rows_fit && pd.q[2] != 0 && pd.nM <= 3 && sizeof(double) * size_t(pd.tile_lds) <= 64 * 1024;
 }
 
 struct PrecCompDev {

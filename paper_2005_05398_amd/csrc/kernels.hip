@@ -275,9 +275,20 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
         Sy[s] = C.y.S[iy * MAXR + s];
         D2y[s] = C.y.D2[iy * MAXR + s];
     }
-    for (int e = threadIdx.x; e < tile_n; e += 256) {
-        const int kz = e / (Rx * ny), rest = e - kz * (Rx * ny);
-        tile[e] = x[((long long)(kzlo + kz) * nx + kxlo) * ny + rest];
+    {
+        // rows (kz, kx) of the tile, ny values each; rows advance without divisions
+        const int rpp = 256 / ny, sub = threadIdx.x / ny, yy = threadIdx.x - sub * ny;
+        if (sub < rpp) {
+            int kz = sub / Rx, kx = sub - kz * Rx;
+            for (int rr = sub; rr < Rz * Rx; rr += rpp) {
+                tile[rr * ny + yy] = x[((long long)(kzlo + kz) * nx + kxlo + kx) * ny + yy];
+                kx += rpp;
+                while (kx >= Rx) {
+                    kx -= Rx;
+                    ++kz;
+                }
+            }
+        }
     }
     for (int e = threadIdx.x; e < (ixe - ixs) * RX; e += 256) {
         const int pp = e / RX, s = e % RX;
@@ -370,7 +381,6 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
     const int kzlo = C.z.first[iz], kzhi = C.z.last[iz];
     const int kxlo = C.x.first[ix0], kxhi = C.x.last[ix0 + nxt - 1];
     const int Rz = kzhi - kzlo + 1, Rx = kxhi - kxlo + 1;
-    const int tile_n = Rz * Rx * ny;
     const bool has = threadIdx.x < nxt * ny;
     const int ixl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
     const int ix = ix0 + ixl;
@@ -404,6 +414,7 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
     for (int iM = 0; iM < NM; ++iM) {
         __syncthreads();
         const double *c = x + C.off + (long long)iM * C.npts;
+        const int tile_n = Rz * Rx * ny;
         for (int e = threadIdx.x; e < tile_n; e += 256) {
             const int kz = e / (Rx * ny), rest = e - kz * (Rx * ny);
             tile[e] = c[((long long)(kzlo + kz) * nx + kxlo) * ny + rest];
@@ -554,18 +565,31 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     const int bnx = B.x.n, bny = B.y.n;
     const long long N = pd->N;
     const int r0 = blockIdx.y * CPL_REQ, r1 = min(nb, r0 + CPL_REQ);
+    // this lane's tile entries (e = lane + 64 q): offsets into beta's block of
+    // one request, -1 for a dropped function; worked out once for all requests
+    constexpr int EPL = (NM * TS + 63) / 64;
+    int goff[EPL];
+    __syncthreads();                                   // fidx written
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+        const int e = lane + 64 * q;
+        goff[q] = -1;
+        if (has && e < NM * TS) {
+            const int iM = e / TS, rem = e - iM * TS;
+            const int c = rem / (RXY * RXY), a = (rem / RXY) % RXY, bq = rem % RXY;
+            const int gz = fidx[wave][c], gx = fidx[wave][RZ + a], gy = fidx[wave][RZ + RXY + bq];
+            if (gz >= 0 && gx >= 0 && gy >= 0) goff[q] = iM * B.npts + (gz * bnx + gx) * bny + gy;
+        }
+    }
     for (int req = r0; req < r1; ++req) {
         if (active && !active[req]) continue;          // the same for the whole block
         __syncthreads();
         if (has) {
             const double *x = X + (long long)req * N + B.off;
-            for (int e = lane; e < NM * TS; e += 64) {
-                const int iM = e / TS, rem = e - iM * TS;
-                const int c = rem / (RXY * RXY), a = (rem / RXY) % RXY, bq = rem % RXY;
-                const int gz = fidx[wave][c], gx = fidx[wave][RZ + a], gy = fidx[wave][RZ + RXY + bq];
-                tile[wave][e] = (gz < 0 || gx < 0 || gy < 0)
-                                    ? 0.0
-                                    : x[(long long)iM * B.npts + ((long long)gz * bnx + gx) * bny + gy];
+#pragma unroll
+            for (int q = 0; q < EPL; ++q) {
+                const int e = lane + 64 * q;
+                if (e < NM * TS) tile[wave][e] = goff[q] >= 0 ? x[goff[q]] : 0.0;
             }
         }
         __syncthreads();
