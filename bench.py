@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--restart", type=int, default=None, help="default: 300 (cfg2), 60 (cfg3, cfg4)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "coupled"],
+                    help="preconditioner variant (coupled: the approximate matrix with its M'+-1 blocks, L > 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the reduced-precision comparison runs")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
@@ -216,7 +218,7 @@ def main():
     if args.restart is None:
         args.restart = 300 if args.workload == "cfg2" else 60
     t_setup = time.perf_counter()
-    P = fm.Problem(desc)
+    P = fm.Problem(dict(desc, precond=args.precond))
     t_setup = time.perf_counter() - t_setup
     nreq = len(Es)
     B = torch.as_tensor(W.rhs_batch(seeds, P.N), device=dev)
@@ -292,7 +294,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "N_per_request": P.N, "requests_per_step": nreq, "restart": args.restart,
-                   "precond_products": args.prec, "rtol": 1e-10},
+                   "precond": args.precond, "precond_products": args.prec, "rtol": 1e-10},
         "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
         "max_rel_residual": max(relres),
         "setup_s": t_setup,

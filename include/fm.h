@@ -75,8 +75,12 @@ typedef struct {
  * particles, total orbital momentum J and parity tau, one basis triple per
  * Faddeev component, the Merkuriev cut-off of eq. (Mcutoff0) (y0 may be
  * +INFINITY) and the choice of Vhat of eq. (FM-fin) (0: Z_a (Z_b + Z_c)
- * sqrt(2 mu_a(bc)) / (y + 1), Sec. 3.1).  The energy is not part of it: all
- * device-resident factors are independent of E. */
+ * sqrt(2 mu_a(bc)) / (y + 1), Sec. 3.1), and the preconditioner variant
+ * (FM_PREC_BLOCK_JACOBI or FM_PREC_COUPLED, see fm_apply_precond; 0 selects
+ * the block-Jacobi one).  The energy is not part of it: all device-resident
+ * factors are independent of E. */
+typedef enum { FM_PREC_BLOCK_JACOBI = 1, FM_PREC_COUPLED = 2 } fm_prec_variant;
+
 typedef struct {
     double mass[3];
     double charge[3];
@@ -86,6 +90,7 @@ typedef struct {
     double x0, y0, nu;
     int vhat;
     int device;               /* HIP device ordinal */
+    int precond;              /* fm_prec_variant (0: FM_PREC_BLOCK_JACOBI) */
 } fm_problem_desc;
 
 typedef struct fm_problem fm_problem;
@@ -136,12 +141,19 @@ fm_status fm_problem_info(const fm_problem *p, size_t *n_unknowns, size_t *bytes
 fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const double *x_dev,
                             double *y_dev, void *stream);
 
-/* z = L(E)^-1 r for nbatch requests: the tensor-trick inverse of the
- * separable left-hand operator of eq. (FM-fin) (Sec. 3.2), component by
- * component (eq. (prec-1)); for n_M > 1 the M' +- 1 blocks are dropped
- * (block-Jacobi in M').  prec selects the arithmetic of the mode-n products
- * (the divide by lambda_x + lambda_y - E is always FP64).  r_dev and z_dev may
- * be the same buffer.  Errors: FM_E_INVALID, FM_E_HIP, FM_E_BUSY. */
+/* z = L(E)^-1 r for nbatch requests, component by component (eq. (prec-1)).
+ * FM_PREC_BLOCK_JACOBI: the tensor-trick inverse of the separable left-hand
+ * operator of eq. (FM-fin) (Sec. 3.2) with the M' +- 1 blocks dropped
+ * (block-Jacobi in M'; exact for n_M = 1).  FM_PREC_COUPLED: the inverse of
+ * the paper's approximate matrix script-L of Sec. 3.2, which keeps the M' +- 1
+ * blocks with the z eigenvalues replaced by -l(l+1) and the transformed
+ * M' +- 1 blocks by the bidiagonal Lambda^{M'+-} (eq. (prop-eq); the z
+ * eigenvectors ordered by |lambda| and scaled to the functions g_l^{M'} of
+ * the Appendix).  prec selects the arithmetic of the x-y products (and, for
+ * the block-Jacobi variant, of the z products); the divide by
+ * lambda_x + lambda_y - E and the coupled variant's z products are always
+ * FP64.  r_dev and z_dev may be the same buffer.  Errors: FM_E_INVALID,
+ * FM_E_HIP, FM_E_BUSY. */
 fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const double *r_dev,
                            double *z_dev, int prec, void *stream);
 

@@ -44,6 +44,16 @@ fm_status fm_host_setup_check(const fm_problem_desc *desc, double *max_err, int 
  * pairs that share one partner cell.  Errors as fm_host_setup_check. */
 fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double *y, long long *npairs, int *ntasks);
 
+/* z = L(E)^-1 r for one request on the host, from the same factor tables that
+ * fm_create_problem uploads and in the order the device applies them: the z
+ * transform (per M' block, or the coupled variant's joint matrix), then per
+ * x-y slice Wbar_x T Wbar_y^T, the divide by lambda_x + lambda_y - E and
+ * W_x T W_y^T, then the z transform back (fm_apply_precond describes both
+ * variants).  r, z: N doubles each, not overlapping.  For checking the set-up
+ * only: plain loops, small problems.  Errors as fm_host_setup_check, and
+ * FM_E_PENCIL when an x or y pencil has complex pairs (not handled here). */
+fm_status fm_host_precond(const fm_problem_desc *desc, double E, const double *r, double *z);
+
 #ifdef __cplusplus
 }
 #endif

@@ -229,17 +229,20 @@ void prof_collect(fm_problem *p) {
 
 // Algorithmic work of one request (unique FP64 words of each operation's definition).
 struct Work {
-    double N, pts, xyflops, localflops, coupflops;
+    double N, pts, xyflops, localflops, coupflops, zflops;
     explicit Work(const fm_problem *p) {
         N = double(p->N);
         pts = double(p->npts[0] + p->npts[1] + p->npts[2]);
         xyflops = 0;
+        zflops = 0;
         localflops = 0;
         coupflops = 0;
         const int nM = p->nM;
         for (int a = 0; a < 3; ++a) {
             const double np = double(p->npts[a]);
             xyflops += 4.0 * nM * p->bz[a].n * double(p->bx[a].n) * p->by[a].n * (p->bx[a].n + p->by[a].n);
+            // one z product per direction: n_z (block-Jacobi) or n_M n_z (joint) terms per unknown
+            zflops += 2.0 * 2.0 * (p->variant == 2 ? nM * p->bz[a].n : p->bz[a].n) * nM * np;
             // local stencil as separable banded passes: 9 passes of 2q terms (2 flops each) per
             // unknown, plus the pointwise combination (about 20 flops) and the M'+-1 terms
             const double r = 2.0 * std::max(p->bx[a].q, std::max(p->by[a].q, p->bz[a].q));
@@ -263,7 +266,7 @@ struct Work {
 };
 
 void add_precond_work(fm_problem *p, const Work &w, double nreq) {
-    prof_work(p, FM_K_MODEZ, 2 * w.modez() * nreq, 0);
+    prof_work(p, FM_K_MODEZ, 2 * w.modez() * nreq, w.zflops * nreq);
     prof_work(p, FM_K_XY, w.xy() * nreq, w.xyflops * nreq);
 }
 
@@ -297,6 +300,17 @@ void add_closing_work(fm_problem *p, const Work &w, int steps) {
 // tmp: [nb][N] scratch for the staged x-y products (may be null).
 void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
                    int prec, double *min_den, double *tmp, hipStream_t st) {
+    if (p->pr.coupled) {
+        // joint z transform into tmp, the x-y slots in place there (out as their
+        // scratch: in is no longer needed), joint z transform back into out
+        timed(p, st, FM_K_MODEZ, [&] { launch_zjoint(p->pd, p->pr, nb, mask, 0, in, tmp, st); });
+        bool ok = false;
+        if (prec != FM_FP64)
+            timed(p, st, FM_K_XY, [&] { ok = launch_xy_lp(p->pd, p->pr, nb, E_dev, mask, tmp, prec, out, st); });
+        if (!ok) timed(p, st, FM_K_XY, [&] { launch_xy(p->pd, p->pr, nb, E_dev, mask, tmp, min_den, out, st); });
+        timed(p, st, FM_K_MODEZ, [&] { launch_zjoint(p->pd, p->pr, nb, mask, 1, tmp, out, st); });
+        return;
+    }
     if (prec != FM_FP64) {
         bool ok = true;
         timed(p, st, FM_K_MODEZ, [&] { launch_modez_lp(p->pd, p->pr, nb, mask, 0, in, out, st); });
@@ -621,8 +635,10 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         F.Wy32 = put(p, to32(h.Wy), err);
         F.Wx16 = put(p, to16(h.Wx), err);
         F.Wy16 = put(p, to16(h.Wy), err);
+        if (p->variant == 2) F.Zj = put(p, h.Zj, err);
         if (!err.empty()) return err;
     }
+    p->pr.coupled = p->variant == 2 ? 1 : 0;
     // coupling pairs for the tiled operator
     pd.cpl = CouplingDev{};
     if (matvec_tiled_ok(pd)) {

@@ -128,10 +128,14 @@ struct PrecCompDev {
     const signed char *tx, *ty;  // [nM][nz][nx], [nM][nz][ny]
     const float *Wz32, *Wx32, *Wy32;          // FP32 copies
     const unsigned short *Wx16, *Wy16;        // BF16 planes [hi | mid], each laid out as Wx / Wy
+    // coupled variant: joint z matrices [2][nM nz][nM nz] (0: forward, 1: backward);
+    // the x-y factors above are then indexed by slot (l, m) instead of (M', k)
+    const double *Zj;
 };
 
 struct PrecDev {
     PrecCompDev comp[3];
+    int coupled;                 // 1: coupled variant (joint z matrices), 0: block-Jacobi in M'
     const PrecDev *dev;          // device copy of this descriptor
 };
 
@@ -172,6 +176,8 @@ constexpr int MAX_RESTART = 1000;
 // zero (they stay so).  The generic path ignores cbuf and does it all in part 1.
 void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active,
                    const double *x, double *y, double *cbuf, hipStream_t st, int part = 0);
+void launch_zjoint(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
+                   double *out, hipStream_t st);
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
                   const double *in, double *out, hipStream_t st);
 // tmp ([nb][N] scratch): the four products run as batched GEMMs through tmp

@@ -7,6 +7,7 @@ namespace fm {
 
 struct HostComp {
     std::vector<double> Wz, Wx, Wy, lx, lxi, ly, lyi, P, Vs;
+    std::vector<double> Zj;      // coupled variant: joint z matrices [2][nM nz][nM nz]
     std::vector<signed char> tx, ty;
 };
 
@@ -49,6 +50,7 @@ struct DeviceBuffer {
 struct fm_problem {
     fm_problem_desc desc;
     int nM = 0, M0 = 0;
+    int variant = 1;                         // preconditioner: 1 block-Jacobi in M', 2 coupled
     long long N = 0;
     long long npts[3] = {0, 0, 0};
     long long off[3] = {0, 0, 0};
@@ -81,5 +83,12 @@ std::string setup_problem(fm_problem *p);
 std::string build_factors(fm_problem *p, HostFactors &hf);
 std::string upload(fm_problem *p, const HostFactors &hf);
 std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingHost &ch);
+// coupled preconditioner (coupled.cpp)
+double assoc_g(int l, int M, double z);
+std::string order_and_scale_z(const Basis1D &bz, int Mp, std::vector<double> &Wb, std::vector<double> &W,
+                              std::vector<double> &lre);
+std::string coupled_slots(const fm_problem *p, int nz, const std::vector<std::vector<double>> &Wbz,
+                          const std::vector<std::vector<double>> &Wz, std::vector<double> &Zj,
+                          std::vector<double> &cx, std::vector<double> &cy);
 void set_error(const std::string &msg);
 }  // namespace fm

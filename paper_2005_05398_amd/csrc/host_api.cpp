@@ -176,4 +176,96 @@ fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double 
     return FM_OK;
 }
 
+fm_status fm_host_precond(const fm_problem_desc *desc, double E, const double *r, double *z) {
+    if (!desc || !r || !z) {
+        set_error("null argument");
+        return FM_E_INVALID;
+    }
+    fm_problem p;
+    p.desc = *desc;
+    std::string e = setup_problem(&p);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_INVALID;
+    }
+    HostFactors hf;
+    e = build_factors(&p, hf);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_PENCIL;
+    }
+    const int nM = p.nM;
+    for (int a = 0; a < 3; ++a) {
+        const HostComp &h = hf.comp[a];
+        for (auto t : h.tx)
+            if (t) {
+                set_error("complex pencil pairs are not handled by the host apply");
+                return FM_E_PENCIL;
+            }
+        for (auto t : h.ty)
+            if (t) {
+                set_error("complex pencil pairs are not handled by the host apply");
+                return FM_E_PENCIL;
+            }
+        const int nx = p.bx[a].n, ny = p.by[a].n, nz = p.bz[a].n, nxy = nx * ny, n = nM * nz;
+        const double *ra = r + p.off[a];
+        double *za = z + p.off[a];
+        // z transform: rows (iM, k) -> slots
+        std::vector<double> t(size_t(n) * nxy, 0.0);
+        for (int s = 0; s < n; ++s)
+            for (int q = 0; q < n; ++q) {
+                double w;
+                if (p.variant == 2) {
+                    w = h.Zj[size_t(s) * n + q];
+                } else {
+                    const int iM = s / nz, k = s % nz;
+                    if (q / nz != iM) continue;
+                    w = h.Wz[size_t(iM) * 2 * nz * nz + size_t(k) * nz + q % nz];
+                }
+                if (w == 0.0) continue;
+                for (int c = 0; c < nxy; ++c) t[size_t(s) * nxy + c] += w * ra[size_t(q) * nxy + c];
+            }
+        // per slot: X = Wbar_x T Wbar_y^T, divide, T = W_x X W_y^T
+        std::vector<double> X(static_cast<size_t>(nxy));
+        for (int s = 0; s < n; ++s) {
+            double *T = t.data() + size_t(s) * nxy;
+            const double *Wbx = h.Wx.data() + size_t(s) * 2 * nx * nx, *Wx = Wbx + size_t(nx) * nx;
+            const double *Wby = h.Wy.data() + size_t(s) * 2 * ny * ny, *Wy = Wby + size_t(ny) * ny;
+            const double *lx = h.lx.data() + size_t(s) * nx, *ly = h.ly.data() + size_t(s) * ny;
+            auto prod = [&](const double *L, const double *R, const double *in, double *out) {
+                for (int i = 0; i < nx; ++i)
+                    for (int j = 0; j < ny; ++j) {
+                        double v = 0;
+                        for (int i2 = 0; i2 < nx; ++i2) {
+                            double u = 0;
+                            for (int j2 = 0; j2 < ny; ++j2) u += in[size_t(i2) * ny + j2] * R[size_t(j) * ny + j2];
+                            v += L[size_t(i) * nx + i2] * u;
+                        }
+                        out[size_t(i) * ny + j] = v;
+                    }
+            };
+            prod(Wbx, Wby, T, X.data());
+            for (int i = 0; i < nx; ++i)
+                for (int j = 0; j < ny; ++j) X[size_t(i) * ny + j] /= lx[i] + ly[j] - E;
+            prod(Wx, Wy, X.data(), T);
+        }
+        // back: slots -> rows (iM, k)
+        for (size_t i = 0; i < size_t(n) * nxy; ++i) za[i] = 0.0;
+        for (int q = 0; q < n; ++q)
+            for (int s = 0; s < n; ++s) {
+                double w;
+                if (p.variant == 2) {
+                    w = h.Zj[size_t(n) * n + size_t(q) * n + s];
+                } else {
+                    const int iM = q / nz, k = q % nz;
+                    if (s / nz != iM) continue;
+                    w = h.Wz[size_t(iM) * 2 * nz * nz + size_t(nz) * nz + size_t(k) * nz + s % nz];
+                }
+                if (w == 0.0) continue;
+                for (int c = 0; c < nxy; ++c) za[size_t(q) * nxy + c] += w * t[size_t(s) * nxy + c];
+            }
+    }
+    return FM_OK;
+}
+
 }  // extern "C"

@@ -928,25 +928,37 @@ __device__ __forceinline__ double divided_at(const double *__restrict__ T, int l
 // loaded (the divide of the tensor trick between the two product pairs);
 // min_den (may be null) receives the smallest |denominator| met.  Grid:
 // (tiles, slices, requests); 256 threads.
-template <bool LEFT, bool DIV>
+// JZ (LEFT only, coupled preconditioner): the "slice" is a whole component,
+// the n_M n_z x n_x n_y matrix of its [M'][z] rows, and W its joint z matrix
+// (grid.y = 3); in and out must not overlap.
+template <bool LEFT, bool DIV, bool JZ = false>
 __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
                                                     const double *__restrict__ Evec,
                                                     const int *__restrict__ active, int which,
                                                     const double *__restrict__ in, double *__restrict__ out,
                                                     double *min_den) {
+    static_assert(!JZ || (LEFT && !DIV), "joint z products are plain left products");
     const int req = blockIdx.z;
     if (active && !active[req]) return;
     int a, iM, k;
-    if (!slice_decode(pd, blockIdx.y, a, iM, k)) return;
+    if (JZ) {
+        a = blockIdx.y;
+        iM = k = 0;
+    } else if (!slice_decode(pd, blockIdx.y, a, iM, k)) {
+        return;
+    }
     const CompDev &C = pd->comp[a];
     const PrecCompDev &F = pr->comp[a];
-    const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
+    const int nz = C.z.n;
+    const int nx = JZ ? pd->nM * nz : C.x.n, ny = JZ ? C.nxy : C.y.n;
     const int tc = (ny + SG_T - 1) / SG_T;
     const int t = blockIdx.x;
     if (t >= ((nx + SG_T - 1) / SG_T) * tc) return;
     const int i0 = (t / tc) * SG_T, j0 = (t % tc) * SG_T;
     const size_t fx = (size_t)iM * nz + k;
-    const double *Wm = LEFT ? F.Wx + (fx * 2 + which) * nx * nx : F.Wy + (fx * 2 + which) * ny * ny;
+    const double *Wm = JZ     ? F.Zj + (size_t)which * nx * nx
+                       : LEFT ? F.Wx + (fx * 2 + which) * nx * nx
+                              : F.Wy + (fx * 2 + which) * ny * ny;
     const long long off = (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
     const double *g = in + off;
     double *o = out + off;
@@ -1902,6 +1914,18 @@ void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *ac
     dim3 grid(cdiv(maxnxy, MZ_COLS), 3 * MAXM, nb);
     size_t sh = sizeof(double) * (maxnz * maxnz + maxnz * MZ_COLS);
     hipLaunchKernelGGL(k_modez, grid, dim3(MZ_COLS), sh, st, pd.dev, pr.dev, active, which, in, out);
+}
+
+// Coupled preconditioner: out = Z in per component with its joint z matrix
+// (which: 0 forward, 1 backward); in and out must not overlap.
+void launch_zjoint(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
+                   double *out, hipStream_t st) {
+    int tiles = 0;
+    for (int a = 0; a < 3; ++a)
+        tiles = std::max(tiles, (int)(cdiv(pd.nM * pd.comp[a].z.n, SG_T) * cdiv(pd.comp[a].nxy, SG_T)));
+    const dim3 g(tiles, 3, nb);
+    hipLaunchKernelGGL((k_slice_gemm<true, false, true>), g, dim3(256), 0, st, pd.dev, pr.dev, nullptr, active, which,
+                       in, out, nullptr);
 }
 
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,

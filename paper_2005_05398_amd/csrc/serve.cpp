@@ -31,10 +31,28 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Problems are cached by every field of the description except the device.
 std::string desc_key(const fm_problem_desc &d) {
-    fm_problem_desc c = d;
-    c.device = 0;
-    return std::string(reinterpret_cast<const char *>(&c), sizeof(c));
+    std::string k;
+    auto put = [&k](const void *v, size_t n) { k.append(static_cast<const char *>(v), n); };
+    put(d.mass, sizeof d.mass);
+    put(d.charge, sizeof d.charge);
+    put(&d.J, sizeof d.J);
+    put(&d.tau, sizeof d.tau);
+    for (const fm_dim *dims : {d.x, d.y, d.z})
+        for (int a = 0; a < 3; ++a) {
+            put(&dims[a].degree, sizeof(int));
+            put(&dims[a].n, sizeof(int));
+            put(&dims[a].R, sizeof(double));
+            put(&dims[a].map, sizeof(int));
+        }
+    put(&d.x0, sizeof d.x0);
+    put(&d.y0, sizeof d.y0);
+    put(&d.nu, sizeof d.nu);
+    put(&d.vhat, sizeof d.vhat);
+    const int pv = d.precond == FM_PREC_COUPLED ? 2 : 1;
+    put(&pv, sizeof pv);
+    return k;
 }
 
 long long unknowns_of(const fm_problem_desc &d) {

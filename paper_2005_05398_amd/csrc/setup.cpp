@@ -6,15 +6,18 @@
 // Sec. 3.1: Vhat_a.  Sec. 3.2: the pencils whose generalized eigenvectors make
 // the tensor-trick preconditioner.
 //
-// The preconditioner is the exact inverse of the separable block L_alpha of
-// eq. (FM-fin), M'-block by M'-block (the M' +- 1 blocks are left out).  For a
-// block M' the z pencil (d_z^{M'} operator, S_z) is diagonalised first
-// (eq. (z-dec)); with mu_k = -lambda~_{z,k} each z mode k then leaves the 2D
-// operator (A_x^k (x) S_y + S_x (x) A_y^k - E S_x (x) S_y) with
+// The block-Jacobi preconditioner (variant 1) is the exact inverse of the
+// separable block L_alpha of eq. (FM-fin), M'-block by M'-block (the M' +- 1
+// blocks are left out).  For a block M' the z pencil (d_z^{M'} operator, S_z)
+// is diagonalised first (eq. (z-dec)); with mu_k = -lambda~_{z,k} each z mode k
+// then leaves the 2D operator (A_x^k (x) S_y + S_x (x) A_y^k - E S_x (x) S_y)
+// with
 //   A_x^k = -D_x + mu_k X_r2 S_x + V_a S_x,
 //   A_y^k = -D_y + (J(J+1) - 2M'^2 + mu_k) Y_r2 S_y + Vhat_a S_y,
 // whose inverse follows from eq. (MDA) with the pencils (A_x^k, S_x) and
-// (A_y^k, S_y).  All factors are independent of E; only the final divide by
+// (A_y^k, S_y).  The coupled preconditioner (variant 2, coupled.cpp) has the
+// same x-y structure with other coefficients per slot and a joint z matrix.
+// All factors are independent of E; only the final divide by
 // lambda_x + lambda_y - E sees the energy.
 #include <algorithm>
 #include <cmath>
@@ -66,6 +69,9 @@ std::string setup_problem(fm_problem *p) {
     }
     if (!(d.x0 > 0) || !(d.nu > 0) || !(d.y0 > 0)) return "cut-off parameters must be positive";
     if (d.vhat != 0) return "only vhat = 0 is defined";
+    if (d.precond != 0 && d.precond != FM_PREC_BLOCK_JACOBI && d.precond != FM_PREC_COUPLED)
+        return "precond must be FM_PREC_BLOCK_JACOBI or FM_PREC_COUPLED";
+    p->variant = d.precond == FM_PREC_COUPLED ? 2 : 1;
     for (int a = 0; a < 3; ++a) {
         std::string e = p->bx[a].init(d.x[a], false);
         if (e.empty()) e = p->by[a].init(d.y[a], false);
@@ -179,7 +185,9 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
         std::vector<double> Sz = bz.dense(0), D1z = bz.dense(1), D2z = bz.dense(2);
         std::vector<double> Sx = bx.dense(0), D2x = bx.dense(2);
         std::vector<double> Sy = by.dense(0), D2y = by.dense(2);
-        std::vector<std::vector<double>> mus(nM);
+        // per slot: x pencil coefficient of X_r2 S_x, y pencil coefficient of Y_r2 S_y
+        std::vector<double> cx(size_t(nM) * nz), cy(size_t(nM) * nz);
+        std::vector<std::vector<double>> zWb(nM), zW(nM);
         for (int iM = 0; iM < nM; ++iM) {
             int Mp = p->M0 + iM;
             std::vector<double> A1(size_t(nz) * nz);
@@ -198,15 +206,28 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
             for (int i = 0; i < nz; ++i)
                 if (ty[i] != 0) return "z pencil has complex eigenvalues";
             hf.max_err = std::max(hf.max_err, e);
+            if (p->variant == 2) {
+                r = order_and_scale_z(bz, Mp, Wb, W, lre);
+                if (!r.empty()) return "z pencil: " + r;
+            }
             std::copy(Wb.begin(), Wb.end(), hc.Wz.begin() + size_t(iM) * 2 * nz * nz);
             std::copy(W.begin(), W.end(), hc.Wz.begin() + size_t(iM) * 2 * nz * nz + size_t(nz) * nz);
-            mus[iM].resize(nz);
-            for (int k = 0; k < nz; ++k) mus[iM][k] = -lre[k];
+            for (int k = 0; k < nz; ++k) {
+                const double mu_k = -lre[k];
+                cx[size_t(iM) * nz + k] = mu_k;
+                cy[size_t(iM) * nz + k] = double(J) * (J + 1) - 2.0 * Mp * Mp + mu_k;
+            }
+            zWb[iM].swap(Wb);
+            zW[iM].swap(W);
+        }
+        if (p->variant == 2) {
+            std::string r = coupled_slots(p, nz, zWb, zW, hc.Zj, cx, cy);
+            if (!r.empty()) return r;
         }
         std::vector<double> Vx(nx), Vh(ny);
         for (int i = 0; i < nx; ++i) Vx[i] = coulomb(p, a, bx.points[i]);
         for (int j = 0; j < ny; ++j) Vh[j] = vhat(p, a, by.points[j]);
-        // x and y pencils for every (M', k), in parallel
+        // x and y pencils for every slot, in parallel
         int total = nM * nz;
         int nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         std::vector<std::thread> pool;
@@ -219,17 +240,15 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
                     int job = next.fetch_add(1);
                     if (job >= total) break;
                     int iM = job / nz, k = job % nz;
-                    int Mp = p->M0 + iM;
-                    double mu_k = mus[iM][k];
                     for (int i = 0; i < nx; ++i) {
                         double x = bx.points[i];
-                        double f = mu_k / (x * x) + Vx[i];
+                        double f = cx[job] / (x * x) + Vx[i];
                         for (int j = 0; j < nx; ++j)
                             A1x[size_t(i) * nx + j] = -D2x[size_t(i) * nx + j] + f * Sx[size_t(i) * nx + j];
                     }
                     for (int i = 0; i < ny; ++i) {
                         double y = by.points[i];
-                        double f = (double(J) * (J + 1) - 2.0 * Mp * Mp + mu_k) / (y * y) + Vh[i];
+                        double f = cy[job] / (y * y) + Vh[i];
                         for (int j = 0; j < ny; ++j)
                             A1y[size_t(i) * ny + j] = -D2y[size_t(i) * ny + j] + f * Sy[size_t(i) * ny + j];
                     }

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "FM_OK", -1: "FM_E_INVALID", -2: "FM_E_NOMEM", -3: "FM_E_HIP"
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KERNEL_CLASSES = ["matvec", "modez", "xy", "mdot", "mupdate", "finish", "restart", "coupling"]
 MAPS = {"uniform": 0, "quadratic": 1, "pow": 2, "sin": 3}
+PRECONDS = {"block_jacobi": 1, "coupled": 2}   # fm_prec_variant
 
 
 class FmDim(ctypes.Structure):
@@ -29,7 +30,7 @@ class FmDesc(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double * 3), ("charge", ctypes.c_double * 3), ("J", ctypes.c_int),
                 ("tau", ctypes.c_int), ("x", FmDim * 3), ("y", FmDim * 3), ("z", FmDim * 3),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("nu", ctypes.c_double),
-                ("vhat", ctypes.c_int), ("device", ctypes.c_int)]
+                ("vhat", ctypes.c_int), ("device", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class FmSolveOpts(ctypes.Structure):
@@ -102,6 +103,7 @@ def make_c_desc(desc, device=0):
     d.x0, d.nu, d.vhat = desc["x0"], desc["nu"], desc.get("vhat", 0)
     d.y0 = desc["y0"] if math.isfinite(desc["y0"]) else float("inf")
     d.device = device
+    d.precond = PRECONDS[desc.get("precond", "block_jacobi")]
     return d
 
 
@@ -207,7 +209,8 @@ def _host_sigs(L):
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.fm_host_coupling.argtypes = [ctypes.POINTER(FmDesc), pd, pd, ctypes.POINTER(ctypes.c_longlong),
                                    ctypes.POINTER(ctypes.c_int)]
-    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check", "fm_host_coupling"):
+    L.fm_host_precond.argtypes = [ctypes.POINTER(FmDesc), ctypes.c_double, pd, pd]
+    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check", "fm_host_coupling", "fm_host_precond"):
         getattr(L, f).restype = ci
     L._host_sigs = True
 
@@ -277,6 +280,18 @@ def host_coupling(desc, x=None):
 
 
 # -- serving (fm_server_*) ----------------------------------------------------
+
+def host_precond(desc, E, r):
+    """z = L(E)^-1 r for one request, applied on the host from the library's
+    factor tables (set-up check; small problems only)."""
+    import numpy as np
+    L = lib()
+    _host_sigs(L)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros_like(r)
+    _check(L.fm_host_precond(ctypes.byref(make_c_desc(desc)), float(E), _dptr(r), _dptr(z)))
+    return z
+
 
 class FmRequestResult(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("iters", ctypes.c_int),
@@ -348,3 +363,4 @@ class Server:
             self.close()
         except Exception:
             pass
+

@@ -135,3 +135,33 @@ def test_host_coupling_pairs_match_oracle(name, desc):
     assert npairs > 0 and 64 * ntasks >= npairs and ntasks <= npairs
     ref = _oracle_coupling(desc, x)
     assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref), name
+
+
+PREC_SETUP_CASES = [
+    ("cubic_J2", dict(J=2, tau=1, deg_xy=3, deg_z=3, nxy=8, nz=8)),
+    ("quintic_J3_odd", dict(J=3, tau=-1, deg_xy=5, deg_z=5, nxy=10, nz=6)),
+    ("cubic_J1_one_interval", dict(J=1, tau=1, deg_xy=3, deg_z=3, nxy=6, nz=4)),
+    ("cubic_J0", dict(J=0, tau=1, deg_xy=3, deg_z=3, nxy=8, nz=8)),
+    ("quintic_xy_cubic_z_J2", dict(J=2, tau=1, deg_xy=5, deg_z=3, nxy=13, nz=8)),
+]
+
+
+@pytest.mark.parametrize("variant", ["block_jacobi", "coupled"])
+@pytest.mark.parametrize("name,kw", PREC_SETUP_CASES, ids=[c[0] for c in PREC_SETUP_CASES])
+def test_host_precond_factors_match_oracle(name, kw, variant):
+    """The library's factor tables, applied on the host in the device's order,
+    against the oracle: block-Jacobi in M' (sparse LU of the separable operator
+    without the M'+-1 blocks) and the coupled variant (sparse LU of the paper's
+    approximate matrix script-L)."""
+    from oracle.assemble import Problem
+    from oracle.precond_v2 import precond_v2_reference
+    from oracle.solve import precond_reference
+    kw = dict(kw)
+    nxy, nz = kw.pop("nxy"), kw.pop("nz")
+    desc = W.make_desc(*W.PS_MINUS, nxy, nz, R=20.0, **kw)
+    P = Problem(desc)
+    E = -0.25
+    r = W.rhs(5, P.N)
+    got = fm.host_precond(dict(desc, precond=variant), E, r)
+    want = precond_v2_reference(P, E, r) if variant == "coupled" else precond_reference(P, E, r)
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
