@@ -79,6 +79,9 @@ def serve_bench(args):
     from paper_2005_05398_amd import workloads as W
 
     reqs = [W.cfg5_request(i) for i in range(args.requests)]
+    for r in reqs:                      # the preconditioner variant of the L > 0 requests
+        if r["desc"]["J"] > 0:
+            r["desc"] = dict(r["desc"], precond=args.serve_precond)
     t_gen = time.perf_counter()
     rhs = [W.rhs(r["seed"], W.n_unknowns(r["desc"])) for r in reqs]
     t_gen = time.perf_counter() - t_gen
@@ -134,7 +137,8 @@ def serve_bench(args):
         "config": {"workload": "seeded stream: quintic x,y {31,64,97,127} x cubic z {8,16,32}, L in {0,1,2}, "
                                "E in [-0.6,-0.05], two particle sets, seeded N(0,1) RHS",
                    "requests": len(reqs), "max_batch": args.max_batch, "restart": args.serve_restart,
-                   "max_iters": args.serve_max_iters, "budget_gb": args.budget_gb},
+                   "max_iters": args.serve_max_iters, "budget_gb": args.budget_gb,
+                   "precond_L_gt_0": args.serve_precond},
         "saturation": {"requests": nsat, "solves_per_s": sat_rate, "wall_s": sat_wall,
                        "ok": sum(1 for o in sat.values() if o["status"] == "FM_OK")},
         "arrival_rate_per_s": rate,
@@ -195,6 +199,8 @@ def main():
     ap.add_argument("--serve-restart", type=int, default=200)
     ap.add_argument("--serve-max-iters", type=int, default=6000)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-precond", default="coupled", choices=["block_jacobi", "coupled"],
+                    help="preconditioner of the L > 0 requests in the serving stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
