@@ -172,6 +172,53 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
 fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
                    const fm_solve_opts *opts, fm_solve_result *results, void *stream);
 
+/* y = S x for nbatch requests: S holds the basis products at the collocation
+ * points (Sec. 3.1; the right-hand matrix of H c = E S c), block diagonal over
+ * (alpha, M').  x_dev, y_dev: nbatch * N doubles, not overlapping.  Errors:
+ * FM_E_INVALID, FM_E_HIP, FM_E_BUSY. */
+fm_status fm_apply_mass(fm_problem *p, int nbatch, const double *x_dev, double *y_dev, void *stream);
+
+/* ---- Bound-state energies: shift-invert Arnoldi ------------------------
+ *
+ * The eigenvalues E of H c = E S c nearest a shift sigma (Sec. 3.1,
+ * eq. (FM-lin); Sec. 4 iterates with the inverse of H - E* S by implicitly
+ * restarted Arnoldi).  They are the eigenvalues theta = 1/(E - sigma) of
+ * largest modulus of T = (H - sigma S)^-1 S.  Each Arnoldi step applies S and
+ * solves with H - sigma S by fm_solve's flexible GMRES (opts->inner); the
+ * basis stays on the device and is orthogonalised twice by classical
+ * Gram-Schmidt.  Restarts are Krylov-Schur restarts (equivalent to the
+ * implicit shifts of IRAM): the Ritz vectors of the nev + (ncv - nev)/2
+ * largest |theta| (complex pairs kept whole) are orthonormalised and the basis
+ * is contracted onto them.  A Ritz pair is accepted when the Arnoldi estimate
+ * ||T V y - theta V y|| <= tol |theta| (||y|| = 1). */
+typedef struct {
+    int nev;                  /* eigenvalues wanted, nearest sigma */
+    int ncv;                  /* Krylov basis size: nev + 2 <= ncv <= min(256, N) */
+    double tol;               /* relative Ritz residual */
+    int max_restarts;
+    fm_solve_opts inner;      /* solves with H - sigma S (x0_is_guess ignored) */
+} fm_eigs_opts;
+
+typedef struct {
+    int nconv;                /* wanted eigenvalues whose Ritz pairs met tol */
+    int restarts;
+    int solves;               /* Arnoldi steps (one inner solve each) */
+    long long inner_iters;    /* GMRES steps over all inner solves */
+    int inner_failures;       /* inner solves that stopped short of their rtol */
+} fm_eigs_info;
+
+/* E_re, E_im, resid: host arrays of nev entries, nearest sigma first (resid:
+ * the Arnoldi estimate relative to |theta|; NaN where the Krylov space held
+ * fewer values).  vec_dev (NULL: not formed): nev * N doubles, unit-norm
+ * coefficient vectors; a complex pair fills two consecutive slots with the
+ * real and imaginary parts of the first value's vector.  v0_dev (NULL: all
+ * ones): the start vector, N doubles.  The device workspace ((2 ncv + 2) N
+ * doubles plus the inner solve's) is allocated per call.  Returns FM_OK when
+ * the nev values converged, FM_E_NOT_CONVERGED otherwise (the estimates are
+ * returned); FM_E_INVALID, FM_E_NOMEM, FM_E_HIP, FM_E_BUSY, FM_E_NONFINITE. */
+fm_status fm_eigs(fm_problem *p, double sigma, const fm_eigs_opts *opts, const double *v0_dev, double *E_re,
+                  double *E_im, double *resid, double *vec_dev, fm_eigs_info *info, void *stream);
+
 /* ---- Serving: continuous batching of solve requests --------------------
  *
  * A server owns a device-memory budget and a set of lanes.  A lane is one

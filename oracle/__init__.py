@@ -15,6 +15,8 @@ paper (Gradusov, Roudnev, Yarevsky, Yakovlev, arXiv:2005.05398):
   assemble.py  explicit collocation matrix H - E S of eq. (FM-pre) and the
                separable left-hand block L_alpha of eq. (FM-fin) (Sec. 3.1-3.2)
   solve.py     LU solves and residuals
+  eigen.py     the mass matrix S and bound-state energies of H c = E S c
+               (shift-invert ARPACK, dense QZ for tiny problems)
   precond_v2.py  the coupled L > 0 preconditioner: the approximate matrix
                script-L of Sec. 3.2 (eq. (prop-eq)) and the Appendix functions g
 

@@ -76,18 +76,6 @@ DimDev dim_dev(fm_problem *p, const Basis1D &b, std::string &err) {
     return d;
 }
 
-struct Busy {
-    fm_problem *p;
-    bool ok;
-    explicit Busy(fm_problem *q) : p(q) {
-        int z = 0;
-        ok = p->busy.compare_exchange_strong(z, 1);
-    }
-    ~Busy() {
-        if (ok) p->busy.store(0);
-    }
-};
-
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // bfloat16 round to nearest even, and back
@@ -776,7 +764,6 @@ fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const do
     const size_t cb = sizeof(double) * 2 * size_t(nbatch) * size_t(p->N);
     if (p->cbuf_bytes < cb) {
         if (p->cbuf) (void)hipFree(p->cbuf);
-    if (p->ptmp) (void)hipFree(p->ptmp);
         p->cbuf = nullptr;
         p->cbuf_bytes = 0;
         HIP_TRY(hipMalloc(&p->cbuf, cb));
@@ -833,7 +820,30 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
     Busy busy(p);
     if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
     HIP_TRY(hipSetDevice(p->desc.device));
+    return solve_locked(p, nbatch, E, b_dev, x_dev, opts, results, static_cast<hipStream_t>(stream));
+}
+
+fm_status fm_apply_mass(fm_problem *p, int nbatch, const double *x_dev, double *y_dev, void *stream) {
+    if (!p || !x_dev || !y_dev || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    if (x_dev == y_dev) return fail(FM_E_INVALID, "x and y must not overlap");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_mass(p->pd, nbatch, x_dev, y_dev, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return FM_OK;
+}
+
+}  // extern "C"
+
+namespace fm {
+
+// fm_solve after validation, with the handle held and the device set.
+fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
+                       const fm_solve_opts *opts, fm_solve_result *results, hipStream_t st) {
+    const int m = opts->restart;
     // the problem keeps the batch of its last solve for reuse
     Batch *b = p->solve_batch;
     if (!b || b->cap != nbatch || b->m != m) {
@@ -894,6 +904,10 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
     if (overall == FM_E_NONFINITE) g_err = "non-finite value in b or during the iteration";
     return overall;
 }
+
+}  // namespace fm
+
+extern "C" {
 
 fm_status fm_profile(fm_problem *p, int enable) {
     if (!p) return fail(FM_E_INVALID, "null problem");

@@ -40,6 +40,16 @@ struct Basis1D {
 
 // ---------------------------------------------------------------------------
 // Host dense linear algebra (row-major n x n).
+// All eigenvalues of the real matrix A ordered by decreasing modulus (a complex
+// pair as a + ib, a - ib with b > 0), and unit eigenvectors of the leading ones
+// by inverse iteration (up to ncols columns, pairs whole: a pair gives the real
+// and imaginary parts of the first value's vector, type 1 and 2; a real value
+// type 0) in the nv columns of V (row-major n x nv).  A vector whose residual
+// exceeds 1e-11 max(|A|, |lambda|) ends the list; fewer than nmin columns is
+// an error.  Returns "" or a message.
+std::string dense_eig_by_modulus(int n, const std::vector<double> &A, int nmin, int ncols, std::vector<double> &wr,
+                                 std::vector<double> &wi, std::vector<double> &V, std::vector<signed char> &type,
+                                 int &nv);
 bool lu_factor(int n, std::vector<double> &a, std::vector<int> &piv);
 void lu_solve(int n, const std::vector<double> &lu, const std::vector<int> &piv, double *b);
 bool invert(int n, const std::vector<double> &a, std::vector<double> &inv);
@@ -204,6 +214,18 @@ void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream
 void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,
                      hipStream_t st);
 void launch_scale0(const KrylovDev &k, hipStream_t st);
+// y = S x (the mass matrix of H c = E S c) for nb requests
+void launch_mass(const ProblemDev &pd, int nb, const double *x, double *y, hipStream_t st);
+// Column kernels of the eigenvalue iteration (columns of length N stored one after another):
+// out[c] = V_c . w (part: cols_dot_blocks(N) * ncol doubles of scratch); w -= V h (h on the
+// device); out_c = sum_j V_j Y[j k + c] (Y on the device, row-major m x k; out must not
+// overlap V); w *= s.
+int cols_dot_blocks(long long N);
+void launch_cols_dot(const double *V, int ncol, const double *w, long long N, double *part, double *out,
+                     hipStream_t st);
+void launch_cols_axpy(double *w, const double *V, int ncol, const double *h, long long N, hipStream_t st);
+void launch_cols_combine(const double *V, int m, const double *Y, int k, double *out, long long N, hipStream_t st);
+void launch_scale_vec(double *w, double s, long long N, hipStream_t st);
 void launch_bnorm(const KrylovDev &k, const double *b, const int *mask, hipStream_t st);
 void launch_zero_start(const KrylovDev &k, double *x, const int *mask, int zero_x, hipStream_t st);
 void launch_fill(double *p, long long n, double v, hipStream_t st);

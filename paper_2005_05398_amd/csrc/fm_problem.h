@@ -79,6 +79,21 @@ struct fm_problem {
 };
 
 namespace fm {
+// Holds a problem handle for one call (one call at a time per handle).
+struct Busy {
+    fm_problem *p;
+    bool ok;
+    explicit Busy(fm_problem *q) : p(q) {
+        int z = 0;
+        ok = p->busy.compare_exchange_strong(z, 1);
+    }
+    ~Busy() {
+        if (ok) p->busy.store(0);
+    }
+};
+// fm_solve on a held handle with its device current (arguments already checked).
+fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
+                       const fm_solve_opts *opts, fm_solve_result *results, hipStream_t st);
 std::string setup_problem(fm_problem *p);
 std::string build_factors(fm_problem *p, HostFactors &hf);
 std::string upload(fm_problem *p, const HostFactors &hf);

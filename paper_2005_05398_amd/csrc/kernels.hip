@@ -2122,4 +2122,149 @@ void launch_copy(double *dst, const double *src, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_copy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
 }
 
+// ---------------------------------------------------------------------------
+// Mass matrix S (Sec. 3.1: the basis products at the collocation points, the
+// right-hand matrix of H c = E S c): y = (S_z (x) S_x (x) S_y) x for every
+// component and M' block.  One point per thread, all M' blocks; grid
+// (points / 256, requests).
+__global__ void __launch_bounds__(256) k_mass(const ProblemDev *__restrict__ pd, const double *__restrict__ X,
+                                              double *__restrict__ Y) {
+    const int req = blockIdx.y;
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int a = 0;
+    while (a < 3 && p >= pd->comp[a].npts) {
+        p -= pd->comp[a].npts;
+        ++a;
+    }
+    if (a >= 3) return;
+    const CompDev &C = pd->comp[a];
+    const int nx = C.x.n, ny = C.y.n;
+    const int iz = int(p / C.nxy), rem = int(p % C.nxy), ix = rem / ny, iy = rem % ny;
+    int gz[MAXR], gx[MAXR], gy[MAXR];
+    double Sz[MAXR], Sx[MAXR], Sy[MAXR];
+    const int rz = 2 * C.z.q, rx = 2 * C.x.q, ry = 2 * C.y.q;
+    for (int t = 0; t < rz; ++t) {
+        gz[t] = C.z.idx[iz * MAXR + t];
+        Sz[t] = C.z.S[iz * MAXR + t];
+    }
+    for (int t = 0; t < rx; ++t) {
+        gx[t] = C.x.idx[ix * MAXR + t];
+        Sx[t] = C.x.S[ix * MAXR + t];
+    }
+    for (int t = 0; t < ry; ++t) {
+        gy[t] = C.y.idx[iy * MAXR + t];
+        Sy[t] = C.y.S[iy * MAXR + t];
+    }
+    for (int iM = 0; iM < pd->nM; ++iM) {
+        const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts;
+        const double *c = X + base;
+        double sum = 0;
+        for (int a1 = 0; a1 < rz; ++a1) {
+            if (gz[a1] < 0) continue;
+            double bx = 0;
+            for (int a2 = 0; a2 < rx; ++a2) {
+                if (gx[a2] < 0) continue;
+                const double *row = c + ((long long)gz[a1] * nx + gx[a2]) * ny;
+                double by = 0;
+                for (int a3 = 0; a3 < ry; ++a3)
+                    if (gy[a3] >= 0) by += Sy[a3] * row[gy[a3]];
+                bx += Sx[a2] * by;
+            }
+            sum += Sz[a1] * bx;
+        }
+        Y[base + p] = sum;
+    }
+}
+
+void launch_mass(const ProblemDev &pd, int nb, const double *x, double *y, hipStream_t st) {
+    long long pts = 0;
+    for (int a = 0; a < 3; ++a) pts += pd.comp[a].npts;
+    dim3 grid(cdiv(pts, 256), nb);
+    hipLaunchKernelGGL(k_mass, grid, dim3(256), 0, st, pd.dev, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// Column kernels of the eigenvalue iteration.  A basis of ncol columns of
+// length N is stored column after column (column c at V + c * N).
+
+// part[c * nblk + b] = (this block's share of) V_c . w; grid (nblk, ncol).
+__global__ void __launch_bounds__(256) k_cols_dot_part(const double *__restrict__ V, const double *__restrict__ w,
+                                                       long long N, double *__restrict__ part, int nblk) {
+    const int c = blockIdx.y;
+    const double *v = V + (long long)c * N;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long long)nblk * 256) s += v[i] * w[i];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)c * nblk + blockIdx.x] = red[0];
+}
+
+// out[c] = sum of the nblk partials of column c in block order; grid (ncol).
+__global__ void __launch_bounds__(256) k_cols_dot_finish(const double *__restrict__ part, int nblk,
+                                                         double *__restrict__ out) {
+    const int c = blockIdx.x;
+    double s = 0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[(long long)c * nblk + b];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// w -= sum_c V_c h[c]
+__global__ void __launch_bounds__(256) k_cols_axpy(double *__restrict__ w, const double *__restrict__ V, int ncol,
+                                                   const double *__restrict__ h, long long N) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    double s = w[i];
+    for (int c = 0; c < ncol; ++c) s -= V[(long long)c * N + i] * h[c];
+    w[i] = s;
+}
+
+// out_c = sum_j V_j Y[j * k + c] for c < k (Y row-major m x k); grid (N / 256, k)
+__global__ void __launch_bounds__(256) k_cols_combine(const double *__restrict__ V, int m, const double *__restrict__ Y,
+                                                      int k, double *__restrict__ out, long long N) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= N) return;
+    double s = 0;
+    for (int j = 0; j < m; ++j) s += V[(long long)j * N + i] * Y[j * k + c];
+    out[(long long)c * N + i] = s;
+}
+
+__global__ void __launch_bounds__(256) k_scale_vec(double *__restrict__ w, double s, long long N) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < N) w[i] *= s;
+}
+
+int cols_dot_blocks(long long N) { return (int)std::max<long long>(1, std::min<long long>(NBLK, cdiv(N, 256 * 8))); }
+
+void launch_cols_dot(const double *V, int ncol, const double *w, long long N, double *part, double *out,
+                     hipStream_t st) {
+    const int nblk = cols_dot_blocks(N);
+    hipLaunchKernelGGL(k_cols_dot_part, dim3(nblk, ncol), dim3(256), 0, st, V, w, N, part, nblk);
+    hipLaunchKernelGGL(k_cols_dot_finish, dim3(ncol), dim3(256), 0, st, part, nblk, out);
+}
+
+void launch_cols_axpy(double *w, const double *V, int ncol, const double *h, long long N, hipStream_t st) {
+    hipLaunchKernelGGL(k_cols_axpy, dim3(cdiv(N, 256)), dim3(256), 0, st, w, V, ncol, h, N);
+}
+
+void launch_cols_combine(const double *V, int m, const double *Y, int k, double *out, long long N, hipStream_t st) {
+    hipLaunchKernelGGL(k_cols_combine, dim3(cdiv(N, 256), k), dim3(256), 0, st, V, m, Y, k, out, N);
+}
+
+void launch_scale_vec(double *w, double s, long long N, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_vec, dim3(cdiv(N, 256)), dim3(256), 0, st, w, s, N);
+}
+
 }  // namespace fm

@@ -427,4 +427,81 @@ std::string pencil_diag(int n, const std::vector<double> &A1, const std::vector<
     return "";
 }
 
+std::string dense_eig_by_modulus(int n, const std::vector<double> &A, int nmin, int ncols, std::vector<double> &wr,
+                                 std::vector<double> &wi, std::vector<double> &V, std::vector<signed char> &type,
+                                 int &nv) {
+    std::vector<double> C = A, D, Q;
+    balance(n, C, D);
+    hessenberg(n, C, Q);
+    double hnorm = 0;
+    for (double v : C) hnorm = std::max(hnorm, std::fabs(v));
+    std::vector<double> r, im;
+    if (!hessenberg_eigenvalues(n, C, r, im)) return "QR iteration did not converge";
+    // decreasing modulus; a complex pair as (a + ib, a - ib), b > 0
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) {
+        const double mi = std::hypot(r[i], im[i]), mj = std::hypot(r[j], im[j]);
+        if (mi != mj) return mi > mj;
+        return im[i] > im[j];
+    });
+    wr.assign(n, 0.0);
+    wi.assign(n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        wr[c] = r[ord[c]];
+        wi[c] = im[ord[c]];
+    }
+    for (int c = 0; c + 1 < n; ++c)       // pairs must sit together (equal modulus)
+        if (wi[c] > 0.0 && !(wi[c + 1] == -wi[c] && wr[c + 1] == wr[c])) return "unpaired complex eigenvalue";
+    // eigenvectors of the leading values (at least ncols columns, pairs whole)
+    std::vector<std::vector<double>> cols;
+    type.clear();
+    double anorm = 0;
+    for (double v : A) anorm = std::max(anorm, std::fabs(v));
+    for (int c = 0; c < n && (int)cols.size() < ncols; ++c) {
+        const cplx lam(wr[c], wi[c]);
+        std::vector<cplx> y = inverse_iteration(n, C, lam, hnorm);
+        std::vector<cplx> v(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            cplx t = 0.0;
+            for (int j = 0; j < n; ++j) t += Q[size_t(i) * n + j] * y[j];
+            v[i] = t * D[i];
+        }
+        double nrm = 0;
+        for (auto &t : v) nrm += std::norm(t);
+        nrm = std::sqrt(nrm);
+        for (auto &t : v) t /= nrm;
+        // residual of the original matrix
+        double res = 0;
+        for (int i = 0; i < n; ++i) {
+            cplx t = -lam * v[i];
+            for (int j = 0; j < n; ++j) t += A[size_t(i) * n + j] * v[j];
+            res = std::max(res, std::abs(t));
+        }
+        if (!(res <= 1e-11 * std::max(anorm, std::abs(lam)))) {
+            if ((int)cols.size() < nmin) return "inverse iteration did not converge";
+            break;                                    // keep the vectors found so far
+        }
+        std::vector<double> re(n), ii(n);
+        for (int i = 0; i < n; ++i) {
+            re[i] = v[i].real();
+            ii[i] = v[i].imag();
+        }
+        cols.push_back(re);
+        if (wi[c] != 0.0) {
+            cols.push_back(ii);
+            type.push_back(1);
+            type.push_back(2);
+            ++c;                                      // the conjugate shares the pair's columns
+        } else {
+            type.push_back(0);
+        }
+    }
+    nv = int(cols.size());
+    V.assign(size_t(n) * nv, 0.0);
+    for (int c = 0; c < nv; ++c)
+        for (int i = 0; i < n; ++i) V[size_t(i) * nv + c] = cols[c][i];
+    return "";
+}
+
 }  // namespace fm

@@ -47,6 +47,16 @@ class FmSolveResult(ctypes.Structure):
                 "min_abs_denominator": self.min_abs_denominator, "status": STATUS_NAMES.get(self.status)}
 
 
+class FmEigsOpts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int), ("ncv", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_restarts", ctypes.c_int), ("inner", FmSolveOpts)]
+
+
+class FmEigsInfo(ctypes.Structure):
+    _fields_ = [("nconv", ctypes.c_int), ("restarts", ctypes.c_int), ("solves", ctypes.c_int),
+                ("inner_iters", ctypes.c_longlong), ("inner_failures", ctypes.c_int)]
+
+
 class FmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -73,10 +83,13 @@ def lib():
         L.fm_apply_operator.argtypes = [vp, ci, pd, vp, vp, vp]
         L.fm_apply_precond.argtypes = [vp, ci, pd, vp, vp, ci, vp]
         L.fm_solve.argtypes = [vp, ci, pd, vp, vp, ctypes.POINTER(FmSolveOpts), ctypes.POINTER(FmSolveResult), vp]
+        L.fm_apply_mass.argtypes = [vp, ci, vp, vp, vp]
+        L.fm_eigs.argtypes = [vp, cd, ctypes.POINTER(FmEigsOpts), vp, pd, pd, pd, vp, ctypes.POINTER(FmEigsInfo),
+                              vp]
         L.fm_profile.argtypes = [vp, ci]
         L.fm_profile_read.argtypes = [vp, ci, pd, ctypes.POINTER(ctypes.c_longlong), pd, pd]
         for f in ("fm_create_problem", "fm_destroy_problem", "fm_problem_info", "fm_apply_operator",
-                  "fm_apply_precond", "fm_solve", "fm_profile", "fm_profile_read"):
+                  "fm_apply_precond", "fm_solve", "fm_profile", "fm_profile_read", "fm_apply_mass", "fm_eigs"):
             getattr(L, f).restype = ci
         _lib = L
     return _lib
@@ -168,6 +181,35 @@ class Problem:
         _check(lib().fm_apply_precond(self._h, nb, Ec, _ptr(r, nb * self.N, "r"), _ptr(z, nb * self.N, "z"),
                                       PRECISIONS[prec], _stream(stream)))
         return z
+
+    def apply_mass(self, x, y, stream=None):
+        """y = S x for a batch of vectors (x.numel() // N of them)."""
+        nb = x.numel() // self.N
+        _check(lib().fm_apply_mass(self._h, nb, _ptr(x, nb * self.N, "x"), _ptr(y, nb * self.N, "y"),
+                                   _stream(stream)))
+        return y
+
+    def eigs(self, sigma, nev=2, ncv=20, tol=1e-10, max_restarts=50, restart=60, rtol=1e-10, max_iters=4000,
+             prec="fp64", vectors=None, v0=None, stream=None, raise_on_error=True):
+        """Energies nearest sigma by shift-invert Arnoldi.  vectors: None or a
+        device tensor of nev * N doubles.  Returns (status, energies (complex,
+        nearest first), Ritz residuals, info dict)."""
+        opts = FmEigsOpts(int(nev), int(ncv), float(tol), int(max_restarts),
+                          FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], 0))
+        Er = (ctypes.c_double * nev)()
+        Ei = (ctypes.c_double * nev)()
+        rs = (ctypes.c_double * nev)()
+        info = FmEigsInfo()
+        vp = _ptr(vectors, nev * self.N, "vectors") if vectors is not None else None
+        v0p = _ptr(v0, self.N, "v0") if v0 is not None else None
+        st = lib().fm_eigs(self._h, float(sigma), ctypes.byref(opts), v0p, Er, Ei, rs, vp, ctypes.byref(info),
+                           _stream(stream))
+        if st != FM_OK and raise_on_error and st != FM_E_NOT_CONVERGED:
+            raise FmError(st, lib().fm_last_error().decode())
+        E = [complex(Er[i], Ei[i]) for i in range(nev)]
+        inf = {"nconv": info.nconv, "restarts": info.restarts, "solves": info.solves,
+               "inner_iters": info.inner_iters, "inner_failures": info.inner_failures}
+        return st, E, list(rs), inf
 
     def profile(self, enable=True):
         """Enable (and reset) or disable per-kernel-class timing."""

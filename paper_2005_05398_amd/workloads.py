@@ -89,6 +89,48 @@ def cfg4():
 CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}
 
 
+# Helium with an infinitely heavy nucleus (1e15 a.u.), the runs of Sec. 4:
+# quintic splines, x and y nodes by eq. (map-pow), z nodes sin(pi u / 2),
+# Merkuriev cut-off x0 = 1, nu = 2.01, y0 = infinity.  Particles 1, 2 are the
+# electrons and 3 the nucleus, so components 1 and 2 hold an electron-nucleus
+# pair and component 3 the electron pair.  The paper's domain lengths are
+# distances in the unscaled Jacobi vectors: a box length R of x_alpha (y_alpha)
+# becomes R sqrt(2 mu) in the mass-scaled coordinates the equations use, mu
+# the pair's (the third particle's) reduced mass.
+HE_MASSES = (1.0, 1.0, 1e15)
+HE_CHARGES = (-1.0, -1.0, 2.0)
+
+# Table 3 (J = 1, tau = +1; domains (1: 36, 36; 3: 9, 6)): basis sizes of
+# components (1, 3) as (n_x, n_y, n_z) and the printed 2 1P and 3 1P
+# energies; the benchmark values the caption quotes.
+HE_TABLE3 = [((22, 22, 9), (19, 19, 12), (-2.12524, -2.05654)),
+             ((31, 31, 9), (22, 22, 15), (-2.12365, -2.05495)),
+             ((40, 40, 12), (25, 25, 18), (-2.12378, -2.05508)),
+             ((49, 49, 12), (28, 28, 21), (-2.12385, -2.05513)),
+             ((58, 58, 12), (28, 28, 21), (-2.12384, -2.05514))]
+HE_TABLE3_DOMAINS = ((36.0, 36.0), (9.0, 6.0))
+HE_1P_BENCHMARK = (-2.12384308649810135925, -2.05514636209194353689)
+
+
+def helium_desc(g1, g3, dom1=HE_TABLE3_DOMAINS[0], dom3=HE_TABLE3_DOMAINS[1], J=1, tau=1):
+    """Helium description with basis sizes g1 (components 1, 2) and g3
+    (component 3), each (n_x, n_y, n_z), on the paper's domains (unscaled
+    lengths, see above)."""
+    m = HE_MASSES
+    M = sum(m)
+    dims = {"x": [], "y": [], "z": []}
+    for a in range(3):
+        b, c = [i for i in range(3) if i != a]
+        mu_x = m[b] * m[c] / (m[b] + m[c])
+        mu_y = m[a] * (m[b] + m[c]) / M
+        g, dom = (g3, dom3) if a == 2 else (g1, dom1)
+        dims["x"].append({"degree": 5, "n": g[0], "R": dom[0] * math.sqrt(2.0 * mu_x), "map": "pow"})
+        dims["y"].append({"degree": 5, "n": g[1], "R": dom[1] * math.sqrt(2.0 * mu_y), "map": "pow"})
+        dims["z"].append({"degree": 5, "n": g[2], "R": 2.0, "map": "sin"})
+    return {"masses": HE_MASSES, "charges": HE_CHARGES, "J": int(J), "tau": int(tau), **dims,
+            "x0": 1.0, "y0": INF, "nu": 2.01, "vhat": 0}
+
+
 def cfg5_request(i):
     """Request i of the serving stream (seed 5001 + i): nominal x,y size in
     {32, 64, 96, 128} (quintic, taken to the nearest 3K+1), cubic z in

@@ -229,3 +229,24 @@ def test_precond_one_block_per_slice_and_staged_paths(device, name, desc):
         assert err <= 1e-9, (name, r, err)
     d = (torch.linalg.norm(Zsmall - Zbig[:2]) / torch.linalg.norm(Zbig[:2])).item()
     assert d <= 1e-11, d
+
+
+def test_precond_after_operator_grows_its_buffer(device):
+    """fm_apply_operator growing its coupling buffer must leave the
+    preconditioner's scratch alone (regression: growing it once freed the
+    scratch as well, leaving the preconditioner a dangling buffer)."""
+    fm = _fm()
+    desc = PREC_CASES[1][1]
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    rng = np.random.default_rng(21)
+    r = rng.standard_normal(O.N)
+    z = to_dev(np.zeros((1, O.N)), device)
+    P.apply_precond([-0.3], to_dev(r[None, :], device), z)
+    X = to_dev(rng.standard_normal((3, O.N)), device)
+    Y = to_dev(np.zeros((3, O.N)), device)
+    P.apply_operator([-0.3] * 3, X, Y)
+    z2 = to_dev(np.zeros((1, O.N)), device)
+    P.apply_precond([-0.3], to_dev(r[None, :], device), z2)
+    ref = precond_reference(O, -0.3, r)
+    assert np.abs(z2.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()

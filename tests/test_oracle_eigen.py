@@ -1,0 +1,60 @@
+"""Pins for the oracle's bound-state energies (Sec. 3.1, eq. (FM-lin)).
+
+P-E1  S (the basis products at the points, block diagonal) equals A(0) - A(1)
+      of the assembled operator A(E) = H - E S (eq. (FM-lin)).
+P-E2  Shift-invert ARPACK against the dense generalized eigenvalues (QZ) of
+      (H, S) on tiny problems: the k values nearest sigma agree.
+P-E3  The eigenvectors satisfy H c = E S c.
+(The helium ground and first excited S levels against the benchmark values the
+paper cites are pinned in test_oracle_physics.py.)
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem
+from oracle.eigen import dense_eigs, mass_matrix, shift_invert_eigs
+from paper_2005_05398_amd import workloads as W
+
+TINY = [
+    ("cubic_L0", W.make_desc(*W.PS_MINUS, 6, 4, J=0, deg_xy=3, deg_z=3, R=12.0)),
+    ("cubic_L1", W.make_desc(*W.H_MINUS, 6, 4, J=1, tau=1, deg_xy=3, deg_z=3, R=15.0)),
+    ("helium_L0", W.make_desc((1e15, 1.0, 1.0), (2.0, -1.0, -1.0), 6, 4, deg_xy=3, deg_z=3, R=10.0,
+                              xy_map="quadratic", x0=1.0)),
+]
+
+
+@pytest.mark.parametrize("name,desc", TINY, ids=[c[0] for c in TINY])
+def test_mass_matrix_is_the_energy_derivative(name, desc):
+    P = Problem(desc)
+    S = mass_matrix(P).toarray()
+    D = (P.assemble(0.0) - P.assemble(1.0)).toarray()
+    assert np.abs(S - D).max() <= 1e-12 * np.abs(P.assemble(0.0)).max()
+
+
+@pytest.mark.parametrize("name,desc,sigma", [(TINY[0][0], TINY[0][1], -0.3), (TINY[1][0], TINY[1][1], -0.5),
+                                             (TINY[2][0], TINY[2][1], -2.9)], ids=[c[0] for c in TINY])
+def test_shift_invert_matches_dense(name, desc, sigma):
+    P = Problem(desc)
+    ev = dense_eigs(P)
+    ev = ev[np.isfinite(ev)]
+    want = ev[np.argsort(np.abs(ev - sigma), kind="stable")][:4]
+    E, X = shift_invert_eigs(P, sigma, 4, return_vectors=True)
+    for e in E:
+        assert np.min(np.abs(want - e)) <= 1e-8 * max(1.0, abs(e)), (e, want)
+    H = P.assemble(0.0)
+    S = mass_matrix(P)
+    for i in range(4):
+        x = X[:, i]
+        r = np.linalg.norm(H @ x - E[i] * (S @ x)) / np.linalg.norm(S @ x)
+        assert r <= 1e-8 * max(1.0, abs(E[i])), (i, r)
+
+
+def test_helium_table3_workload_matches_golden():
+    """The bench's copy of the Table 3 rows equals the golden fixture."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "he_table3_1P.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == len(W.HE_TABLE3)
+    for v, (g1, g3, printed) in zip(rows, W.HE_TABLE3):
+        assert tuple(int(t) for t in v[:3]) == g1 and tuple(int(t) for t in v[3:6]) == g3
+        assert (float(v[6]), float(v[7])) == printed
