@@ -931,13 +931,15 @@ __device__ __forceinline__ double divided_at(const double *__restrict__ T, int l
 // JZ (LEFT only, coupled preconditioner): the "slice" is a whole component,
 // the n_M n_z x n_x n_y matrix of its [M'][z] rows, and W its joint z matrix
 // (grid.y = 3); in and out must not overlap.
-template <bool LEFT, bool DIV, bool JZ = false>
+template <bool LEFT, bool DIV, bool JZ = false, int BT = SG_T>
 __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
                                                     const double *__restrict__ Evec,
                                                     const int *__restrict__ active, int which,
                                                     const double *__restrict__ in, double *__restrict__ out,
                                                     double *min_den) {
     static_assert(!JZ || (LEFT && !DIV), "joint z products are plain left products");
+    static_assert(BT == 32 || BT == 64, "block tile 32 x 32 (one 16 x 16 MFMA tile per wave) or 64 x 64 (2 x 2)");
+    constexpr int WT = BT / 32;               // MFMA tiles per wave in each direction
     const int req = blockIdx.z;
     if (active && !active[req]) return;
     int a, iM, k;
@@ -951,10 +953,10 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const PrecCompDev &F = pr->comp[a];
     const int nz = C.z.n;
     const int nx = JZ ? pd->nM * nz : C.x.n, ny = JZ ? C.nxy : C.y.n;
-    const int tc = (ny + SG_T - 1) / SG_T;
+    const int tc = (ny + BT - 1) / BT;
     const int t = blockIdx.x;
-    if (t >= ((nx + SG_T - 1) / SG_T) * tc) return;
-    const int i0 = (t / tc) * SG_T, j0 = (t % tc) * SG_T;
+    if (t >= ((nx + BT - 1) / BT) * tc) return;
+    const int i0 = (t / tc) * BT, j0 = (t % tc) * BT;
     const size_t fx = (size_t)iM * nz + k;
     const double *Wm = JZ     ? F.Zj + (size_t)which * nx * nx
                        : LEFT ? F.Wx + (fx * 2 + which) * nx * nx
@@ -965,11 +967,11 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const int K = LEFT ? nx : ny;
     const double E = DIV ? Evec[req] : 0.0;
     double mind = 1e300;
-    __shared__ double As[SG_T][SG_KC + 1];   // [row][k]
-    __shared__ double Bs[SG_KC][SG_T + 1];   // [k][col]
+    __shared__ double As[BT][SG_KC + 1];   // [row][k]
+    __shared__ double Bs[SG_KC][BT + 1];   // [k][col]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
-    constexpr int PER = SG_T * SG_KC / 256;   // A and B values per thread per chunk
+    constexpr int PER = BT * SG_KC / 256;   // A and B values per thread per chunk
     double ra[PER], rb[PER];
     // the next chunk is fetched into registers while the current one is multiplied
     auto fetch = [&](int k0) {
@@ -983,7 +985,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             ra[q] = av;
             double bv = 0.0;
             if (LEFT) {
-                const int kb = e / SG_T, cb = e % SG_T;      // B[kb][cb] = in[k0 + kb][j0 + cb]
+                const int kb = e / BT, cb = e % BT;          // B[kb][cb] = in[k0 + kb][j0 + cb]
                 if (k0 + kb < K && j0 + cb < ny)
                     bv = DIV ? divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
                                           F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind)
@@ -1000,27 +1002,45 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         for (int q = 0; q < PER; ++q) {
             const int e = threadIdx.x + 256 * q;
             As[e / SG_KC][e % SG_KC] = ra[q];
-            if (LEFT) Bs[e / SG_T][e % SG_T] = rb[q];
+            if (LEFT) Bs[e / BT][e % BT] = rb[q];
             else Bs[e % SG_KC][e / SG_KC] = rb[q];
         }
     };
-    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    // wave (wi, wj) owns the (16 WT) x (16 WT) block at rows 16 WT wi, columns 16 WT wj
+    dbl4 acc[WT][WT];
+#pragma unroll
+    for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj) acc[ti][tj] = dbl4{0.0, 0.0, 0.0, 0.0};
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += SG_KC) {
         stash();
         __syncthreads();
         if (k0 + SG_KC < K) fetch(k0 + SG_KC);
 #pragma unroll
-        for (int kk = 0; kk < SG_KC; kk += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[16 * wi + r16][kk + k4], Bs[kk + k4][16 * wj + r16], acc,
-                                                       0, 0, 0);
+        for (int kk = 0; kk < SG_KC; kk += 4) {
+            double av[WT], bv[WT];
+#pragma unroll
+            for (int ti = 0; ti < WT; ++ti) av[ti] = As[16 * (WT * wi + ti) + r16][kk + k4];
+#pragma unroll
+            for (int tj = 0; tj < WT; ++tj) bv[tj] = Bs[kk + k4][16 * (WT * wj + tj) + r16];
+#pragma unroll
+            for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < WT; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+        }
         __syncthreads();
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int row = i0 + 16 * wi + k4 + 4 * v, col = j0 + 16 * wj + r16;
-        if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[v];
-    }
+    for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = i0 + 16 * (WT * wi + ti) + k4 + 4 * v, col = j0 + 16 * (WT * wj + tj) + r16;
+                if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[ti][tj][v];
+            }
     if (DIV && min_den) {
         // block minimum, then one atomic per block on the bit pattern (positive doubles)
         __shared__ double red[256];
@@ -1922,10 +1942,10 @@ void launch_zjoint(const ProblemDev &pd, const PrecDev &pr, int nb, const int *a
                    double *out, hipStream_t st) {
     int tiles = 0;
     for (int a = 0; a < 3; ++a)
-        tiles = std::max(tiles, (int)(cdiv(pd.nM * pd.comp[a].z.n, SG_T) * cdiv(pd.comp[a].nxy, SG_T)));
+        tiles = std::max(tiles, (int)(cdiv(pd.nM * pd.comp[a].z.n, 64) * cdiv(pd.comp[a].nxy, 64)));
     const dim3 g(tiles, 3, nb);
-    hipLaunchKernelGGL((k_slice_gemm<true, false, true>), g, dim3(256), 0, st, pd.dev, pr.dev, nullptr, active, which,
-                       in, out, nullptr);
+    hipLaunchKernelGGL((k_slice_gemm<true, false, true, 64>), g, dim3(256), 0, st, pd.dev, pr.dev, nullptr, active,
+                       which, in, out, nullptr);
 }
 
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
@@ -1937,15 +1957,25 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
     }
     if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
-        const dim3 g(tiles, slices, nb);
-        hipLaunchKernelGGL((k_slice_gemm<true, false>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 0, data,
-                           tmp, nullptr);
-        hipLaunchKernelGGL((k_slice_gemm<false, false>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 0, tmp,
-                           data, nullptr);
-        hipLaunchKernelGGL((k_slice_gemm<true, true>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 1, data,
-                           tmp, min_den);
-        hipLaunchKernelGGL((k_slice_gemm<false, false>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, 1, tmp,
-                           data, nullptr);
+        // 64 x 64 block tiles (2 x 2 MFMA tiles per wave) for slices wider than 32
+#define FM_SG(BT)                                                                                                      \
+    {                                                                                                                  \
+        int tl = 0;                                                                                                    \
+        for (int a = 0; a < 3; ++a)                                                                                    \
+            tl = std::max(tl, (int)(cdiv(pd.comp[a].x.n, BT) * cdiv(pd.comp[a].y.n, BT)));                             \
+        const dim3 g(tl, slices, nb);                                                                                  \
+        hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, \
+                           0, data, tmp, nullptr);                                                                     \
+        hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,        \
+                           active, 0, tmp, data, nullptr);                                                             \
+        hipLaunchKernelGGL((k_slice_gemm<true, true, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active,  \
+                           1, data, tmp, min_den);                                                                     \
+        hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,        \
+                           active, 1, tmp, data, nullptr);                                                             \
+    }
+        if (side > 32) FM_SG(64) else FM_SG(32)
+#undef FM_SG
+        (void)tiles;
         return;
     }
     // many slices of side <= 32: one block per slice, one 16 x 16 output tile per wave
