@@ -629,6 +629,8 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
     p->pr.coupled = p->variant == 2 ? 1 : 0;
     // coupling pairs for the tiled operator
     pd.cpl = CouplingDev{};
+    if (sizeof(double) * size_t(pd.tile_lds) > 64 * 1024 && matvec_tiled_ok(pd))
+        prepare_operator_lds(sizeof(double) * size_t(pd.tile_lds));
     if (matvec_tiled_ok(pd)) {
         if (2 * p->N >= (1LL << 31)) return "problem too large for the tiled operator";
         CouplingHost ch;
@@ -679,29 +681,21 @@ fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out) {
         delete p;
         return fail(FM_E_HIP, "hipSetDevice failed");
     }
-    // kernel shape limits: an x-y slice of one component must fit in LDS and the
-    // register staging of the slice products holds at most 192 rows/columns
+    // LDS per block: the fused x-y kernels (slices of side <= 32) and the tiled
+    // operator size their dynamic LDS from the problem; wider slices run as
+    // batched GEMMs with fixed tiles
     {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device) != hipSuccess) {
             delete p;
             return fail(FM_E_HIP, "cannot query LDS size");
         }
-        size_t need = 0;
+        p->pd.lds_max = lds;
         for (int a = 0; a < 3; ++a) {
-            if (p->bx[a].n > 192 || p->by[a].n > 192) {
-                delete p;
-                return fail(FM_E_INVALID, "x and y bases are limited to 192 functions");
-            }
-            need = std::max(need, sizeof(double) * size_t(p->bx[a].n) * p->by[a].n);
             size_t padded = sizeof(double) * size_t((p->bx[a].n + 15) & ~15) * (((p->by[a].n + 15) & ~15) + 4);
-            if (padded <= size_t(lds)) prepare_large_lds(padded);
+            if (p->bx[a].n <= XY_FUSED_MAX_SIDE && p->by[a].n <= XY_FUSED_MAX_SIDE && padded <= size_t(lds))
+                prepare_large_lds(padded);
         }
-        if (need > size_t(lds)) {
-            delete p;
-            return fail(FM_E_INVALID, "an x-y slice does not fit in LDS");
-        }
-        if (need > 65536) prepare_large_lds(need);
     }
     HostFactors hf;
     e = build_factors(p, hf);

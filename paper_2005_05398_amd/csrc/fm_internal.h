@@ -112,6 +112,7 @@ struct ProblemDev {
     int dlen;
     int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
     int tile_lds;                // doubles of LDS for the largest coefficient tile
+    int lds_max;                 // bytes of LDS one block may use on the device
     int nodes_total;             // doubles of LDS for all node tables
     CouplingDev cpl;             // tiled path only
     const ProblemDev *dev;       // device copy of this descriptor (kernels take this pointer)
@@ -120,12 +121,12 @@ struct ProblemDev {
 // The operator runs as two tiled kernels (coupling into a two-slot buffer, then
 // the local stencil plus that buffer) when x and y share one spline order in
 // all components, z one order, n_M <= 3, n_y <= 256 and the stencil tile fits
-// 64 KB of LDS; otherwise one generic kernel does everything.
+// the LDS of one block; otherwise one generic kernel does everything.
 inline bool matvec_tiled_ok(const ProblemDev &pd) {
     const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
     bool rows_fit = true;                // one block of 256 threads covers the y points
     for (int a = 0; a < 3; ++a) rows_fit = rows_fit && pd.comp[a].y.n <= 256;
-    return same_xy && rows_fit && pd.q[2] != 0 && pd.nM <= 3 && sizeof(double) * size_t(pd.tile_lds) <= 64 * 1024;
+    return same_xy && rows_fit && pd.q[2] != 0 && pd.nM <= 3 && sizeof(double) * size_t(pd.tile_lds) <= size_t(pd.lds_max);
 }
 
 struct PrecCompDev {
@@ -230,6 +231,8 @@ void launch_bnorm(const KrylovDev &k, const double *b, const int *mask, hipStrea
 void launch_zero_start(const KrylovDev &k, double *x, const int *mask, int zero_x, hipStream_t st);
 void launch_fill(double *p, long long n, double v, hipStream_t st);
 void prepare_large_lds(size_t bytes);
+// Allows the tiled operator kernels dynamic LDS above 64 KB.
+void prepare_operator_lds(size_t bytes);
 size_t xy_lds_limit();
 void launch_copy(double *dst, const double *src, long long n, hipStream_t st);
 

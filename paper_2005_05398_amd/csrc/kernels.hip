@@ -2137,6 +2137,17 @@ void prepare_large_lds(size_t bytes) {
     for (const void *f : lp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
+void prepare_operator_lds(size_t bytes) {
+    const void *fs[] = {
+        reinterpret_cast<const void *>(k_local_grouped<3, 3, 3>), reinterpret_cast<const void *>(k_local_grouped<3, 3, 2>),
+        reinterpret_cast<const void *>(k_local_grouped<2, 2, 3>), reinterpret_cast<const void *>(k_local_grouped<2, 2, 2>),
+        reinterpret_cast<const void *>(k_local_tiled<3, 3, 3, 2>), reinterpret_cast<const void *>(k_local_tiled<3, 3, 3, 3>),
+        reinterpret_cast<const void *>(k_local_tiled<3, 3, 2, 2>), reinterpret_cast<const void *>(k_local_tiled<3, 3, 2, 3>),
+        reinterpret_cast<const void *>(k_local_tiled<2, 2, 3, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 3, 3>),
+        reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 3>)};
+    for (const void *f : fs) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
 void launch_zero_start(const KrylovDev &k, double *x, const int *mask, int zero_x, hipStream_t st) {
     dim3 grid(cdiv(k.N, 256), k.nb);
     hipLaunchKernelGGL(k_zero_start, grid, dim3(256), 0, st, k, x, mask, zero_x);

@@ -37,6 +37,18 @@ def small(mc, nxy, nz, J=0, tau=1, dxy=5, dz=5, R=15.0, xy_map="uniform", x0=5.0
     return W.make_desc(*mc, nxy, nz, J=J, tau=tau, deg_xy=dxy, deg_z=dz, R=R, xy_map=xy_map, x0=x0)
 
 
+def wide(nx, ny, nz, dz):
+    """Slices wider than the fused kernels' 32 (and than 192, a former limit):
+    x and y sizes set separately."""
+    d = W.make_desc(*W.PS_MINUS, nx, nz, deg_xy=5, deg_z=dz, R=20.0)
+    d["y"] = W.make_desc(*W.PS_MINUS, ny, nz, deg_xy=5, deg_z=dz, R=20.0)["y"]
+    return d
+
+
+# 199 x 13: x products of side 199 in 64 x 64 tiles; 10 x 229 with quintic z:
+# the operator's stencil tile needs 66 KB of LDS (above the 64 KB default)
+WIDE_CASES = [("wide_x199_y13", wide(199, 13, 4, 3)), ("wide_x10_y229", wide(10, 229, 6, 5))]
+
 OP_CASES = [
     ("cfg1", W.cfg1()["desc"]),
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
@@ -45,7 +57,7 @@ OP_CASES = [
     ("L1_tau-1", small(W.H_MINUS, 7, 6, J=1, tau=-1, dz=5)),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
     ("cubic_ragged_10x6", small(W.PS_MINUS, 10, 6, dxy=3, dz=3)),
-]
+] + WIDE_CASES
 
 
 @pytest.mark.parametrize("name,desc", OP_CASES, ids=[c[0] for c in OP_CASES])
@@ -85,12 +97,13 @@ def test_operator_parity_full_size_sampled(device, cfg):
     assert err <= 1e-11, err
 
 
+
 PREC_CASES = [
     ("cfg1", W.cfg1()["desc"]),
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
     ("hminus_quadratic_22x22x9", small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
-]
+] + WIDE_CASES
 
 
 @pytest.mark.parametrize("name,desc", PREC_CASES, ids=[c[0] for c in PREC_CASES])
