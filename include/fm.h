@@ -91,6 +91,12 @@ typedef struct {
     int vhat;
     int device;               /* HIP device ordinal */
     int precond;              /* fm_prec_variant (0: FM_PREC_BLOCK_JACOBI) */
+    int exchange;             /* 0: all three components.  +1 / -1: particles 1 and 2 are identical
+                                 (equal masses, charges and component bases) and only the part of
+                                 parity p = exchange under their permutation is solved: components 1
+                                 and 3 (Sec. 2, "Permutational symmetry", eq. (2-sym-part): component
+                                 2 is p (-1)^{M'} times component 1 at -z); vectors then hold
+                                 [alpha = 1, 3][M'][z][x][y] and N = n_M (n_1 + n_3) */
 } fm_problem_desc;
 
 typedef struct fm_problem fm_problem;

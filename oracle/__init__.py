@@ -17,6 +17,8 @@ paper (Gradusov, Roudnev, Yarevsky, Yakovlev, arXiv:2005.05398):
   solve.py     LU solves and residuals
   eigen.py     the mass matrix S and bound-state energies of H c = E S c
                (shift-invert ARPACK, dense QZ for tiny problems)
+  symmetry.py  the exchange-reduced equations of two identical particles
+               (Sec. 2, eq. (2-sym-part))
   precond_v2.py  the coupled L > 0 preconditioner: the approximate matrix
                script-L of Sec. 3.2 (eq. (prop-eq)) and the Appendix functions g
 

@@ -1,0 +1,98 @@
+"""Oracle: the exchange-reduced equations for two identical particles (Sec. 2,
+"Permutational symmetry", eqs. (2-sym) and (2-sym-part)).
+
+Test infrastructure only (see oracle/__init__.py).
+
+With particles 1 and 2 identical and a wave function of parity p under their
+exchange, component 2 is p (-1)^{M'} times component 1 at -z (same x, y); the
+equations for components 1 and 3 with that substitution are the reduced system
+of 2 n_M equations.  Plain definition: E maps the reduced unknowns
+(psi_1, psi_3) to the full ones (psi_1, psi_2 = p (-1)^{M'} mirror(psi_1),
+psi_3); R keeps the collocation rows of components 1 and 3; then
+A_red(E) = R (H - E S) E and S_red = R S E.  mirror takes the coefficients of
+f(z) to those of f(-z): interpolation of f(-z_i) at the collocation points,
+exact when the nodes and points are symmetric about z = 0.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .eigen import mass_matrix
+
+
+def mirror_z(bz):
+    """Coefficient map f(z) -> f(-z) on the z basis."""
+    return np.linalg.solve(bz.matrix(0), bz.matrix(0, t=-bz.points))
+
+
+def expansion(prob, p):
+    """E: reduced unknowns [alpha = 1, 3][M'][z][x][y] -> full unknowns."""
+    if p not in (1, -1):
+        raise ValueError("p must be +1 or -1")
+    rows, cols, vals = [], [], []
+    nxy0 = prob.bx[0].n * prob.by[0].n
+    Mz = mirror_z(prob.bz[0])
+    nz0 = prob.bz[0].n
+    red_off = [0, None, prob.nM * prob.block[0]]
+    for iM, Mp in enumerate(prob.Mps):
+        r0 = red_off[0] + iM * prob.block[0]
+        f0 = prob.offsets[0][iM]
+        f1 = prob.offsets[1][iM]
+        for i in range(prob.block[0]):
+            rows.append(f0 + i)
+            cols.append(r0 + i)
+            vals.append(1.0)
+        sign = p * (-1.0) ** Mp
+        for k in range(nz0):
+            for q in range(nz0):
+                w = Mz[k, q]
+                if w == 0.0:
+                    continue
+                for j in range(nxy0):
+                    rows.append(f1 + k * nxy0 + j)
+                    cols.append(r0 + q * nxy0 + j)
+                    vals.append(sign * w)
+        r2 = red_off[2] + iM * prob.block[2]
+        f2 = prob.offsets[2][iM]
+        for i in range(prob.block[2]):
+            rows.append(f2 + i)
+            cols.append(r2 + i)
+            vals.append(1.0)
+    nred = prob.nM * (prob.block[0] + prob.block[2])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(prob.N, nred))
+
+
+def kept_rows(prob):
+    """Full row indices of components 1 and 3, in the reduced order."""
+    idx = []
+    for a in (0, 2):
+        for iM in range(prob.nM):
+            o = prob.offsets[a][iM]
+            idx.extend(range(o, o + prob.block[a]))
+    return np.array(idx)
+
+
+def reduced_operator(prob, E, p):
+    """A_red(E) = R (H - E S) E."""
+    return (prob.assemble(E)[kept_rows(prob)] @ expansion(prob, p)).tocsr()
+
+
+def reduced_mass(prob, p):
+    return (mass_matrix(prob)[kept_rows(prob)] @ expansion(prob, p)).tocsr()
+
+
+def reduced_shift_invert_eigs(prob, p, sigma, k, tol=1e-13, return_vectors=False):
+    """The k energies of the reduced system nearest sigma, nearest first."""
+    A = reduced_operator(prob, sigma, p).tocsc()
+    S = reduced_mass(prob, p)
+    lu = spla.splu(A)
+    n = A.shape[0]
+    op = spla.LinearOperator((n, n), matvec=lambda v: lu.solve(S @ v), dtype=float)
+    v0 = np.ones(n)
+    if return_vectors:
+        theta, X = spla.eigs(op, k=k, which="LM", tol=tol, v0=v0)
+    else:
+        theta = spla.eigs(op, k=k, which="LM", tol=tol, v0=v0, return_eigenvectors=False)
+    order = np.argsort(-np.abs(theta), kind="stable")
+    E = sigma + 1.0 / theta[order]
+    return (E, X[:, order]) if return_vectors else E

@@ -592,6 +592,14 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         }
         PrecCompDev &F = p->pr.comp[a];
         std::memset(&F, 0, sizeof(F));
+        if (p->absent(a)) {
+            // implied by component 1 (exchange symmetry): no points, slices or tiles
+            C.npts = 0;
+            C.nxy = 0;
+            C.z.n = 0;
+            C.ntiles = C.ntiles_g = 0;
+            continue;
+        }
         F.nx = p->bx[a].n;
         F.ny = p->by[a].n;
         F.nz = p->bz[a].n;
@@ -631,6 +639,9 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
     pd.cpl = CouplingDev{};
     if (sizeof(double) * size_t(pd.tile_lds) > 64 * 1024 && matvec_tiled_ok(pd))
         prepare_operator_lds(sizeof(double) * size_t(pd.tile_lds));
+    if (p->exchange != 0 && !matvec_tiled_ok(pd))
+        return "invalid: exchange-reduced problems need the tiled operator (one spline order in x, y and in z, n_M <= 3, "
+               "n_y <= 256)";
     if (matvec_tiled_ok(pd)) {
         if (2 * p->N >= (1LL << 31)) return "problem too large for the tiled operator";
         CouplingHost ch;
@@ -707,7 +718,8 @@ fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out) {
     e = upload(p, hf);
     if (!e.empty()) {
         fm_destroy_problem(p);
-        return fail(FM_E_NOMEM, e);
+        const bool invalid = e.rfind("invalid: ", 0) == 0;
+        return fail(invalid ? FM_E_INVALID : FM_E_NOMEM, invalid ? e.substr(9) : e);
     }
     *out = p;
     return FM_OK;

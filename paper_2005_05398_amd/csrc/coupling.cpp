@@ -44,7 +44,8 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
     struct Item { int a, iz; };
     std::vector<Item> items;
     for (int a = 0; a < 3; ++a)
-        for (int iz = 0; iz < p->bz[a].n; ++iz) items.push_back({a, iz});
+        if (!p->absent(a))
+            for (int iz = 0; iz < p->bz[a].n; ++iz) items.push_back({a, iz});
     const int nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::vector<Rec>> recs(nth);
     std::vector<std::vector<double>> facs(nth);
@@ -62,7 +63,11 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                     const double xc = ax.points[ix], yc = ay.points[iy];
                     for (int bb = 0; bb < 2; ++bb) {
                         const int b = (a + 1 + bb) % 3;
-                        const Basis1D &bx = p->bx[b], &by = p->by[b], &bz = p->bz[b];
+                        // exchange-reduced problems: partner 2 is p (-1)^{M''} times partner 1
+                        // at -z (eq. (2-sym-part)); its cell is looked up in component 1
+                        const bool mirror = p->absent(b);
+                        const int bc = mirror ? 0 : b;
+                        const Basis1D &bx = p->bx[bc], &by = p->by[bc], &bz = p->bz[bc];
                         const double c = p->crot[b][a], s = p->srot[b][a];
                         const double xb =
                             std::sqrt(std::fmax(c * c * xc * xc + 2.0 * s * c * xc * yc * zc + s * s * yc * yc, 0.0));
@@ -73,17 +78,18 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                         double zb = den > 0.0 ? (s * c * (yc * yc - xc * xc) + (c * c - s * s) * xc * yc * zc) / den
                                               : 0.0;
                         zb = std::fmin(1.0, std::fmax(-1.0, zb));
-                        const int mz = bz.interval(zb), mx = bx.interval(xb), my = by.interval(yb);
+                        const double zl = mirror ? -zb : zb;          // where the stored component is read
+                        const int mz = bz.interval(zl), mx = bx.interval(xb), my = by.interval(yb);
                         Rec r;
-                        r.key = keyoff[b] + (mz * bx.K + mx) * by.K + my;
+                        r.key = keyoff[bc] + (mz * bx.K + mx) * by.K + my;
                         r.out = int((p->off[a] + (long long)(iz * nx + ix) * ny + iy) * 2 + bb);
-                        r.s[0] = (zb - bz.nodes[mz]) / (bz.nodes[mz + 1] - bz.nodes[mz]);
+                        r.s[0] = (zl - bz.nodes[mz]) / (bz.nodes[mz + 1] - bz.nodes[mz]);
                         r.s[1] = (xb - bx.nodes[mx]) / (bx.nodes[mx + 1] - bx.nodes[mx]);
                         r.s[2] = (yb - by.nodes[my]) / (by.nodes[my + 1] - by.nodes[my]);
                         recs[t].push_back(r);
                         const double base = vs * xc * yc / den;
                         if (J == 0) {
-                            facs[t].push_back(base);
+                            facs[t].push_back(mirror ? p->exchange * base : base);
                             continue;
                         }
                         double arg = (-s * xc * zc + c * yc) / yb;
@@ -107,7 +113,9 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                                     sp *= sw;
                                     f = f * cw + G[k] * sp;
                                 }
-                                facs[t].push_back(base * f * sbp[jM] / sap[iM]);
+                                double w = base * f * sbp[jM] / sap[iM];
+                                if (mirror) w *= p->exchange * (((M0 + jM) & 1) ? -1.0 : 1.0);
+                                facs[t].push_back(w);
                             }
                     }
                 }

@@ -163,7 +163,7 @@ fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double 
                 val[jM] = acc;
             }
             const int o = ch.out[pr], outp = o >> 1, slot = o & 1;
-            const int a = slot == 0 ? (b + 2) % 3 : (b + 1) % 3;
+            const int a = outp >= p.off[2] ? 2 : (outp >= p.off[1] ? 1 : 0);
             std::vector<double> &dst = slot == 0 ? c0 : c1;
             for (int iM = 0; iM < nM; ++iM) {
                 double v = 0;
@@ -196,6 +196,7 @@ fm_status fm_host_precond(const fm_problem_desc *desc, double E, const double *r
     }
     const int nM = p.nM;
     for (int a = 0; a < 3; ++a) {
+        if (p.absent(a)) continue;
         const HostComp &h = hf.comp[a];
         for (auto t : h.tx)
             if (t) {

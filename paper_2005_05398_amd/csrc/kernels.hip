@@ -558,7 +558,9 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
         const int o = cp.out[pr];
         outp = o >> 1;
         slot = o & 1;
-        const int a = slot == 0 ? (b + 2) % 3 : (b + 1) % 3;
+        // the point's own component, from its offset (an exchange-reduced problem
+        // reads partner 2 from component 1, so b alone does not fix it)
+        const int a = outp >= pd->comp[2].off ? 2 : (outp >= pd->comp[1].off ? 1 : 0);
         npa = pd->comp[a].npts;
     }
     const CompDev &B = pd->comp[b];

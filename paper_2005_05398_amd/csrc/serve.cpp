@@ -52,13 +52,15 @@ std::string desc_key(const fm_problem_desc &d) {
     put(&d.vhat, sizeof d.vhat);
     const int pv = d.precond == FM_PREC_COUPLED ? 2 : 1;
     put(&pv, sizeof pv);
+    put(&d.exchange, sizeof d.exchange);
     return k;
 }
 
 long long unknowns_of(const fm_problem_desc &d) {
     int M0 = (1 - d.tau) / 2;
     long long nM = d.J - M0 + 1, s = 0;
-    for (int a = 0; a < 3; ++a) s += (long long)d.x[a].n * d.y[a].n * d.z[a].n;
+    for (int a = 0; a < 3; ++a)
+        if (!(d.exchange != 0 && a == 1)) s += (long long)d.x[a].n * d.y[a].n * d.z[a].n;
     return nM * s;
 }
 

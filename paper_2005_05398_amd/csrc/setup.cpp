@@ -72,6 +72,17 @@ std::string setup_problem(fm_problem *p) {
     if (d.precond != 0 && d.precond != FM_PREC_BLOCK_JACOBI && d.precond != FM_PREC_COUPLED)
         return "precond must be FM_PREC_BLOCK_JACOBI or FM_PREC_COUPLED";
     p->variant = d.precond == FM_PREC_COUPLED ? 2 : 1;
+    if (d.exchange != 0 && d.exchange != 1 && d.exchange != -1) return "exchange must be 0, +1 or -1";
+    p->exchange = d.exchange;
+    if (d.exchange != 0) {
+        if (d.mass[0] != d.mass[1] || d.charge[0] != d.charge[1])
+            return "exchange symmetry needs particles 1 and 2 with equal masses and charges";
+        auto same = [](const fm_dim &u, const fm_dim &v) {
+            return u.degree == v.degree && u.n == v.n && u.R == v.R && u.map == v.map;
+        };
+        if (!same(d.x[0], d.x[1]) || !same(d.y[0], d.y[1]) || !same(d.z[0], d.z[1]))
+            return "exchange symmetry needs identical bases for components 1 and 2";
+    }
     for (int a = 0; a < 3; ++a) {
         std::string e = p->bx[a].init(d.x[a], false);
         if (e.empty()) e = p->by[a].init(d.y[a], false);
@@ -98,7 +109,7 @@ std::string setup_problem(fm_problem *p) {
     // sizes
     long long off = 0;
     for (int a = 0; a < 3; ++a) {
-        p->npts[a] = (long long)p->bz[a].n * p->bx[a].n * p->by[a].n;
+        p->npts[a] = p->absent(a) ? 0 : (long long)p->bz[a].n * p->bx[a].n * p->by[a].n;
         p->off[a] = off;
         off += p->npts[a] * p->nM;
     }
@@ -170,6 +181,7 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
     std::mutex mu;
     hf.max_err = 0;
     for (int a = 0; a < 3; ++a) {
+        if (p->absent(a)) continue;
         const Basis1D &bx = p->bx[a], &by = p->by[a], &bz = p->bz[a];
         int nx = bx.n, ny = by.n, nz = bz.n;
         HostComp &hc = hf.comp[a];

@@ -30,7 +30,8 @@ class FmDesc(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double * 3), ("charge", ctypes.c_double * 3), ("J", ctypes.c_int),
                 ("tau", ctypes.c_int), ("x", FmDim * 3), ("y", FmDim * 3), ("z", FmDim * 3),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("nu", ctypes.c_double),
-                ("vhat", ctypes.c_int), ("device", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("vhat", ctypes.c_int), ("device", ctypes.c_int), ("precond", ctypes.c_int),
+                ("exchange", ctypes.c_int)]
 
 
 class FmSolveOpts(ctypes.Structure):
@@ -117,6 +118,7 @@ def make_c_desc(desc, device=0):
     d.y0 = desc["y0"] if math.isfinite(desc["y0"]) else float("inf")
     d.device = device
     d.precond = PRECONDS[desc.get("precond", "block_jacobi")]
+    d.exchange = int(desc.get("exchange", 0))
     return d
 
 

@@ -1,0 +1,111 @@
+"""GPU parity of the exchange-reduced equations (Sec. 2, "Permutational
+symmetry", eq. (2-sym-part): two identical particles, components 1 and 3
+solved, component 2 = p (-1)^{M'} component 1 at -z) against the oracle's
+reduced system R (H - E S) E, and of the energies against the full system.
+
+Tolerances as the full-system parity tests: operator 1e-11, preconditioner
+1e-9, solutions 1e-8, energies 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem as OracleProblem
+from oracle.solve import lu_solve, precond_reference, rel_residual
+from oracle.symmetry import kept_rows, reduced_operator
+from paper_2005_05398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fm():
+    from paper_2005_05398_amd import fm
+    return fm
+
+
+def to_dev(a, device):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+
+
+HE = ((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0))
+CASES = [
+    ("hminus_L0_p+1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), 1),
+    ("hminus_L0_p-1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), -1),
+    ("helium_L2_p+1", W.make_desc(*HE, 7, 4, J=2, deg_z=3, R=15.0, x0=1.0), 1),
+    ("hminus_L1_odd_p-1", W.make_desc(*W.H_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0), -1),
+]
+
+
+@pytest.mark.parametrize("name,desc,p", CASES, ids=[c[0] for c in CASES])
+def test_reduced_operator_parity(device, name, desc, p):
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=p))
+    O = OracleProblem(desc)
+    n = O.nM * (O.block[0] + O.block[2])
+    assert P.N == n
+    E = -0.35
+    A = reduced_operator(O, E, p)
+    X = np.random.default_rng(4).standard_normal((2, n))
+    Y = to_dev(np.zeros((2, n)), device)
+    P.apply_operator([E, E], to_dev(X, device), Y)
+    Yg = Y.cpu().numpy()
+    for r in range(2):
+        ref = A @ X[r]
+        assert np.abs(Yg[r] - ref).max() <= 1e-11 * np.abs(ref).max(), (name, r)
+
+
+@pytest.mark.parametrize("name,desc,p", CASES, ids=[c[0] for c in CASES])
+def test_reduced_precond_parity(device, name, desc, p):
+    """The preconditioner of the reduced system is that of components 1 and 3."""
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=p))
+    O = OracleProblem(desc)
+    keep = kept_rows(O)
+    r = np.random.default_rng(6).standard_normal(len(keep))
+    z = to_dev(np.zeros((1, len(keep))), device)
+    P.apply_precond([-0.35], to_dev(r[None, :], device), z)
+    full = np.zeros(O.N)
+    full[keep] = r
+    ref = precond_reference(O, -0.35, full)[keep]
+    assert np.abs(z.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,desc,p", [CASES[0], CASES[2]], ids=[CASES[0][0], CASES[2][0]])
+def test_reduced_solve_matches_lu(device, name, desc, p):
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=p))
+    O = OracleProblem(desc)
+    E = -0.3
+    A = reduced_operator(O, E, p)
+    b = W.rhs(11, A.shape[0])
+    xref = lu_solve(A, b)
+    x = to_dev(np.zeros((1, A.shape[0])), device)
+    st, res = P.solve([E], to_dev(b[None, :], device), x, restart=150, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    xg = x.cpu().numpy()[0]
+    assert rel_residual(A, xg, b) <= 1e-10
+    assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
+
+
+def test_helium_table3_row1_by_exchange_parity(device):
+    """Table 3's first basis set: the full system's four levels nearest -2.095
+    are 2 3P, 2 1P, 3 3P, 3 1P; p = +1 keeps the singlets (the paper's
+    reduced equations), p = -1 the triplets, with the same energies."""
+    fm = _fm()
+    g1, g3, printed = W.HE_TABLE3[0]
+    desc = dict(W.helium_desc(g1, g3), precond="coupled")
+    out = {}
+    for p in (0, 1, -1):
+        P = fm.Problem(dict(desc, exchange=p))
+        nev = 4 if p == 0 else 2
+        st, E, res, info = P.eigs(-2.095, nev=nev, ncv=20, tol=1e-10, max_restarts=40, restart=100, rtol=1e-11,
+                                  max_iters=4000)
+        assert st == fm.FM_OK, (p, info)
+        out[p] = sorted(e.real for e in E)
+    full = out[0]
+    singlets = [full[1], full[3]]
+    triplets = [full[0], full[2]]
+    np.testing.assert_allclose(out[1], singlets, rtol=1e-8)
+    np.testing.assert_allclose(out[-1], triplets, rtol=1e-8)
+    for e, want in zip(out[1], printed):
+        assert abs(e - want) <= 5.1e-6

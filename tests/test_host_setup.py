@@ -165,3 +165,36 @@ def test_host_precond_factors_match_oracle(name, kw, variant):
     got = fm.host_precond(dict(desc, precond=variant), E, r)
     want = precond_v2_reference(P, E, r) if variant == "coupled" else precond_reference(P, E, r)
     assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+
+
+EXCHANGE_CASES = [
+    ("hminus_L0_p+1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), 1),
+    ("hminus_L0_p-1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), -1),
+    ("helium_L2_p+1", W.make_desc((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0), 7, 4, J=2, deg_z=3, R=15.0, x0=1.0), 1),
+    ("hminus_L1_odd_p-1", W.make_desc(*W.H_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0), -1),
+]
+
+
+@lib_built
+@pytest.mark.parametrize("name,desc,p", EXCHANGE_CASES, ids=[c[0] for c in EXCHANGE_CASES])
+def test_host_coupling_exchange_reduced(name, desc, p):
+    """Exchange-reduced problems (components 1 and 3): the device's pairs, with
+    partner 2 read from component 1 at -z and weighted by p (-1)^{M''}, equal
+    R C E x of the oracle (C the inter-component blocks of the full operator,
+    E the expansion psi_2 = p (-1)^{M'} psi_1(-z), R the rows of components 1, 3)."""
+    from oracle.assemble import Problem as OracleProblem
+    from oracle.symmetry import expansion, kept_rows
+    O = OracleProblem(desc)
+    rdesc = dict(desc, exchange=p)
+    N = fm.host_setup_check(rdesc)[2]
+    assert N == O.nM * (O.block[0] + O.block[2])
+    x = W.rhs(78, N)
+    y, npairs, ntasks = fm.host_coupling(rdesc, x)
+    ref = _oracle_coupling(desc, expansion(O, p) @ x)[kept_rows(O)]
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref), name
+
+
+@lib_built
+def test_exchange_rejects_distinct_particles():
+    with pytest.raises(fm.FmError):
+        fm.host_setup_check(dict(W.cfg1()["desc"], exchange=1))     # Ps-: particles 1 and 2 differ

@@ -1,0 +1,45 @@
+"""Pins for the oracle's exchange-reduced equations (Sec. 2, "Permutational
+symmetry", eqs. (2-sym), (2-sym-part)).
+
+P-S1  The z mirror map takes the coefficients of a polynomial f (in the spline
+      space) to those of f(-z), and is an involution on the symmetric grids.
+P-S2  Helium (identical electrons): the lowest energies of the reduced system
+      with p = +1 and p = -1 are the full system's 1 1S and 2 3S levels (the
+      para and ortho ground states), and the reduced eigenvectors expanded to
+      three components are eigenvectors of the full system.
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem
+from oracle.basis import Basis1D
+from oracle.eigen import mass_matrix, shift_invert_eigs
+from oracle.symmetry import expansion, mirror_z, reduced_shift_invert_eigs
+from paper_2005_05398_amd import workloads as W
+
+
+@pytest.mark.parametrize("deg,n", [(3, 8), (3, 16), (5, 12), (5, 24)])
+def test_mirror_map(deg, n):
+    b = Basis1D(deg, n, "z", 2.0, "sin")
+    M = mirror_z(b)
+    np.testing.assert_allclose(M @ M, np.eye(n), atol=1e-10)
+    c = np.polynomial.Polynomial([0.3, -1.1, 0.7, 2.0])          # degree 3: in every spline space here
+    coef = np.linalg.solve(b.matrix(0), c(b.points))
+    t = np.linspace(-0.95, 0.95, 17)
+    np.testing.assert_allclose(b.matrix(0, t=t) @ (M @ coef), c(-t), atol=1e-10)
+
+
+def test_helium_para_and_ortho_levels():
+    d = W.make_desc((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0), 16, 6, deg_xy=5, deg_z=5, R=15.0,
+                    xy_map="quadratic", x0=1.0)
+    P = Problem(d)
+    full = np.sort(shift_invert_eigs(P, -2.9, 3).real)
+    para, X = reduced_shift_invert_eigs(P, +1, -2.9, 1, return_vectors=True)
+    ortho = reduced_shift_invert_eigs(P, -1, -2.9, 1)
+    assert abs(para[0].real - full[0]) <= 1e-9 * abs(full[0]), (para, full)
+    assert abs(ortho[0].real - full[1]) <= 1e-9 * abs(full[1]), (ortho, full)
+    x = expansion(P, +1) @ X[:, 0].real
+    H = P.assemble(0.0)
+    S = mass_matrix(P)
+    r = np.linalg.norm(H @ x - para[0].real * (S @ x)) / np.linalg.norm(S @ x)
+    assert r <= 1e-8, r
