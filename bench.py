@@ -270,6 +270,9 @@ def main():
     ap.add_argument("--restart", type=int, default=None, help="default: 300 (cfg2), 60 (cfg3, cfg4)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--exchange", type=int, default=0, choices=[-1, 0, 1],
+                    help="solve only the part of parity p under exchange of particles 1 and 2 (H- scan: the "
+                         "two electrons); 0: the full three-component system")
     ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "coupled"],
                     help="preconditioner variant (coupled: the approximate matrix with its M'+-1 blocks, L > 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -316,6 +319,8 @@ def main():
     if args.restart is None:
         args.restart = 300 if args.workload == "cfg2" else 60
     t_setup = time.perf_counter()
+    if args.exchange:
+        desc = dict(desc, exchange=args.exchange)
     P = fm.Problem(dict(desc, precond=args.precond))
     t_setup = time.perf_counter() - t_setup
     nreq = len(Es)
@@ -392,7 +397,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "N_per_request": P.N, "requests_per_step": nreq, "restart": args.restart,
-                   "precond": args.precond, "precond_products": args.prec, "rtol": 1e-10},
+                   "precond": args.precond, "precond_products": args.prec, "rtol": 1e-10,
+                   "exchange": args.exchange},
         "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
         "max_rel_residual": max(relres),
         "setup_s": t_setup,
