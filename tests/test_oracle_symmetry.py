@@ -43,3 +43,12 @@ def test_helium_para_and_ortho_levels():
     S = mass_matrix(P)
     r = np.linalg.norm(H @ x - para[0].real * (S @ x)) / np.linalg.norm(S @ x)
     assert r <= 1e-8, r
+
+
+def test_reduced_size_of_the_papers_largest_helium_system():
+    """Sec. 4: the largest helium basis (Fig. 4, J = 2, electron symmetry, 2 n_M
+    equations) gives a matrix of linear size 4246848."""
+    d = W.helium_desc((238, 238, 24), (52, 40, 27), dom1=(45.0, 45.0), dom3=(11.0, 6.0), J=2, tau=1)
+    P = Problem(d)
+    assert P.nM * (P.block[0] + P.block[2]) == 4246848
+    assert W.n_unknowns(dict(d, exchange=1)) == 4246848
