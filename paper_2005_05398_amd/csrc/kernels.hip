@@ -885,6 +885,16 @@ __device__ __forceinline__ bool slice_decode(const ProblemDev *pd, int s, int &a
     return true;
 }
 
+// 1/d in FP64: the hardware reciprocal estimate refined by two Newton steps
+// r <- r + r (1 - d r), each doubling the correct bits (within an ulp or two of
+// the rounded quotient, at a fraction of an IEEE division's cost).
+__device__ __forceinline__ double rcp_newton(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
 // One element of the divided slice, (Lambda_x (x) I + I (x) Lambda_y - E)^-1 T
 // at (i, j), from T and the 2x2 / 4x4 blocks of complex pairs it belongs to
 // (the same closed forms as block_divide); mind tracks min |denominator|.
@@ -976,6 +986,29 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     constexpr int PER = BT * SG_KC / 256;   // A and B values per thread per chunk
     double ra[PER], rb[PER];
     // the next chunk is fetched into registers while the current one is multiplied
+    // DIV: the x eigenvalue data of all K rows staged in LDS once, and the y data
+    // of this thread's column (a thread's B elements share one column: 256 is a
+    // multiple of BT) in registers; the divide of a real (lambda_x, lambda_y) pair
+    // then reads nothing but its element, complex pairs take divided_at
+    constexpr int DIV_ROWS = 256;
+    __shared__ double sLx[DIV ? DIV_ROWS : 1];
+    __shared__ signed char sTx[DIV ? DIV_ROWS : 1];
+    const bool staged = DIV && K <= DIV_ROWS;
+    double ly_c = 0.0;
+    int ty_c = 1;
+    if (DIV) {
+        if (staged)
+            for (int r = threadIdx.x; r < K; r += 256) {
+                sLx[r] = F.lx[fx * nx + r];
+                sTx[r] = F.tx[fx * nx + r];
+            }
+        const int jc = j0 + (int)threadIdx.x % BT;
+        if (jc < ny) {
+            ly_c = F.ly[fx * ny + jc];
+            ty_c = F.ty[fx * ny + jc];
+        }
+        __syncthreads();
+    }
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -988,15 +1021,34 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             double bv = 0.0;
             if (LEFT) {
                 const int kb = e / BT, cb = e % BT;          // B[kb][cb] = in[k0 + kb][j0 + cb]
-                if (k0 + kb < K && j0 + cb < ny)
-                    bv = DIV ? divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
-                                          F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind)
-                             : g[(size_t)(k0 + kb) * ny + j0 + cb];
+                // raw values only: the divide (DIV) is applied when the chunk is
+                // stashed, so that all loads of a chunk are in flight together
+                if (k0 + kb < K && j0 + cb < ny) bv = g[(size_t)(k0 + kb) * ny + j0 + cb];
             } else {
                 const int cb = e / SG_KC, kb = e % SG_KC;    // B[kb][cb] = W[j0 + cb][k0 + kb]
                 if (k0 + kb < K && j0 + cb < ny) bv = Wm[(size_t)(j0 + cb) * ny + k0 + kb];
             }
             rb[q] = bv;
+        }
+    };
+    // DIV: divide the fetched chunk in registers (after the products of the
+    // previous chunk, so its loads have landed)
+    auto divide = [&](int k0) {
+        if (!DIV) return;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int kb = e / BT, cb = e % BT;
+            if (k0 + kb < K && j0 + cb < ny) {
+                if (staged && ty_c == 0 && sTx[k0 + kb] == 0) {
+                    const double d = sLx[k0 + kb] + ly_c - E;
+                    mind = fmin(mind, fabs(d));
+                    rb[q] = rb[q] * rcp_newton(d);
+                } else {                           // complex pairs: closed forms over their 2x2 / 4x4 blocks
+                    rb[q] = divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
+                                       F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
+                }
+            }
         }
     };
     auto stash = [&]() {
@@ -1015,6 +1067,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
 #pragma unroll
         for (int tj = 0; tj < WT; ++tj) acc[ti][tj] = dbl4{0.0, 0.0, 0.0, 0.0};
     fetch(0);
+    divide(0);
     for (int k0 = 0; k0 < K; k0 += SG_KC) {
         stash();
         __syncthreads();
@@ -1032,6 +1085,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
                 for (int tj = 0; tj < WT; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
         }
+        if (k0 + SG_KC < K) divide(k0 + SG_KC);
         __syncthreads();
     }
 #pragma unroll
@@ -1052,7 +1106,9 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
             __syncthreads();
         }
-        if (threadIdx.x == 0)
+        // the minimum rarely changes after the first application: skip the atomic
+        // (all blocks of a request hit one address) unless this block lowers it
+        if (threadIdx.x == 0 && red[0] < __builtin_nontemporal_load(min_den + req))
             atomicMin((unsigned long long *)(min_den + req), (unsigned long long)__double_as_longlong(red[0]));
     }
 }
