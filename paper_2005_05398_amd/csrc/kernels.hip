@@ -1460,7 +1460,7 @@ __global__ void __launch_bounds__(MZ_COLS) k_modez32(const ProblemDev *__restric
 // ---------------------------------------------------------------------------
 // GMRES pieces.  V is stored [i][request][N]; Z likewise.
 constexpr int RT = 256;              // threads of the reduction kernels
-constexpr int MD_G = 16;             // vectors per group in the multi-dot
+constexpr int MD_G = 8;              // vectors per group in the multi-dot
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -1523,8 +1523,8 @@ __device__ __forceinline__ double block_sum_parts(const double *__restrict__ p, 
 // Dot pass partials, per block a row of 2m + 3 values: s_i at i, t_i at j + i,
 // U.U at 2j, U.W at 2j + 1, W.W at 2j + 2.  CLOSING: no W (the last
 // column of a cycle).
-// Grid: (blocks per request, groups of G vectors of Q, requests); G = 4, 8 or
-// 16 by j, so that few vector slots repeat.
+// Grid: (blocks per request, groups of G vectors of Q, requests); G = 4 or 8
+// by j, so that few vector slots repeat.
 template <bool CLOSING, int G>
 __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     constexpr int MD_G = G;
@@ -2114,15 +2114,16 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
     return true;
 }
 
-int dots_group(int j) { return j <= 4 ? 4 : j <= 8 ? 8 : MD_G; }
+// Groups of 8 vectors: as fast as 16 while every request iterates, and faster
+// once few are left (twice the blocks per request).
+int dots_group(int j) { return j <= 4 ? 4 : MD_G; }
 
 unsigned dots_blocks(const KrylovDev &k, int j) {
-    // about 2048 blocks in flight, but 16 to 64 elements per thread and at most NBLK per request
-    const long long groups = std::max<long long>(1, cdiv(j, dots_group(j)));
-    long long nblk = std::max<long long>(std::min<long long>(cdiv(2048, (long long)k.nb * groups),
-                                                             cdiv(k.N, (long long)RT * 16)),
-                                         cdiv(k.N, (long long)RT * 64));
-    return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
+    // 16 elements per thread whatever the batch: the host does not know how
+    // many requests are still iterating, and when few are the blocks of the
+    // others return at once, so the grid is sized for one request alone
+    (void)j;
+    return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, cdiv(k.N, (long long)RT * 16)));
 }
 
 void launch_arnoldi_dots(const KrylovDev &k, int j, int closing, hipStream_t st) {
@@ -2131,11 +2132,9 @@ void launch_arnoldi_dots(const KrylovDev &k, int j, int closing, hipStream_t st)
 #define FM_DOTS(C, GG) hipLaunchKernelGGL((k_arnoldi_dots<C, GG>), grid, dim3(RT), 0, st, k, j)
     if (closing) {
         if (G == 4) FM_DOTS(true, 4);
-        else if (G == 8) FM_DOTS(true, 8);
         else FM_DOTS(true, MD_G);
     } else {
         if (G == 4) FM_DOTS(false, 4);
-        else if (G == 8) FM_DOTS(false, 8);
         else FM_DOTS(false, MD_G);
     }
 #undef FM_DOTS
