@@ -517,6 +517,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
     std::string err;
     ProblemDev &pd = p->pd;
     pd.tile_lds = 0;
+    pd.group_lds = 0;
     pd.nodes_total = 0;
     for (int a = 0; a < 3; ++a) pd.nodes_total += 3 + p->bx[a].K + p->by[a].K + p->bz[a].K;
     pd.q[0] = p->bx[0].q;
@@ -586,6 +587,9 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
                         int g = bx.idx[size_t(i) * MAXR + s];
                         if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
                     }
+                // three z-contracted planes (rz >= 4 keeps this within tile_lds)
+                const int g_lds = 3 * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR;
+                pd.group_lds = std::max(pd.group_lds, g_lds);
                 pd.tile_lds = std::max(pd.tile_lds, rz * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR);
             }
             C.xg = put(p, xg, err);

@@ -112,6 +112,7 @@ struct ProblemDev {
     int dlen;
     int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
     int tile_lds;                // doubles of LDS for the largest coefficient tile
+    int group_lds;               // doubles of LDS for the grouped n_M = 1 tile (<= tile_lds)
     int lds_max;                 // bytes of LDS one block may use on the device
     int nodes_total;             // doubles of LDS for all node tables
     CouplingDev cpl;             // tiled path only

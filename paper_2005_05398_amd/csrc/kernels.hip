@@ -223,12 +223,14 @@ __global__ void __launch_bounds__(256) k_matvec(const ProblemDev *__restrict__ p
 // per M' block.  The coupling comes from the two-slot buffer that the coupling
 // kernel filled before.  Q*: spline orders (2 cubic, 3 quintic); NM: number of
 // M' blocks.
-// n_M = 1: one thread per (x group, y point).  The points of an x group share
-// their x support, so each stencil row's y contractions (values and second
-// derivatives) are formed once and used for all of the group's points (<= 4).
-// Block: (component, z point, gt consecutive x groups); LDS holds the stencil
-// tile (z support x x support of the groups x all y) and the x rows of the
-// block's points.
+// n_M = 1: one thread per (x group, y point).  A block covers one z point, so
+// the coefficients are contracted with that point's z row (value, first and
+// second derivative) as they are read: LDS holds three planes over (x support
+// of the block's groups) x (all y) instead of the z support's rows, and the
+// points of an x group, which share their x support, form each row's y
+// contractions once for all of the group's points (<= 4).
+// Block: (component, z point, gt consecutive x groups); LDS holds the three
+// planes and the x rows of the block's points.
 constexpr int XG_MAX = 4;
 
 template <int QX, int QY, int QZ>
@@ -250,44 +252,47 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
     const int iz = t / ntg, g0 = (t % ntg) * gt;
     const int ngt = min(gt, ngx - g0);
     const int ixs = C.xg[g0], ixe = C.xg[g0 + ngt];
-    const int kzlo = C.z.first[iz], kzhi = C.z.last[iz];
     const int kxlo = C.x.first[ixs], kxhi = C.x.last[ixe - 1];
-    const int Rz = kzhi - kzlo + 1, Rx = kxhi - kxlo + 1;
-    const int tile_n = Rz * Rx * ny;
-    double *tile = sm;
-    double *xS = sm + tile_n, *xD = xS + (ixe - ixs) * RX;
+    const int plane_n = (kxhi - kxlo + 1) * ny;
+    double *p0 = sm, *p1 = sm + plane_n, *p2 = p1 + plane_n;
+    double *xS = p2 + plane_n, *xD = xS + (ixe - ixs) * RX;
     const bool has = threadIdx.x < ngt * ny;
     const int gl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
     const int px0 = C.xg[g0 + gl], pn = C.xg[g0 + gl + 1] - px0;
     const double *x = X + (long long)req * pd->N + C.off;
 
-    int lx[RX], ly[RY];
-    double Sy[RY], D2y[RY];
-#pragma unroll
-    for (int s = 0; s < RX; ++s) {
-        const int g = C.x.idx[px0 * MAXR + s];
-        lx[s] = g >= 0 ? g - kxlo : 0;
-    }
-#pragma unroll
-    for (int s = 0; s < RY; ++s) {
-        const int g = C.y.idx[iy * MAXR + s];
-        ly[s] = g >= 0 ? g : 0;
-        Sy[s] = C.y.S[iy * MAXR + s];
-        D2y[s] = C.y.D2[iy * MAXR + s];
-    }
     {
-        // rows (kz, kx) of the tile, ny values each; rows advance without divisions
-        const int rpp = 256 / ny, sub = threadIdx.x / ny, yy = threadIdx.x - sub * ny;
-        if (sub < rpp) {
-            int kz = sub / Rx, kx = sub - kz * Rx;
-            for (int rr = sub; rr < Rz * Rx; rr += rpp) {
-                tile[rr * ny + yy] = x[((long long)(kzlo + kz) * nx + kxlo + kx) * ny + yy];
-                kx += rpp;
-                while (kx >= Rx) {
-                    kx -= Rx;
-                    ++kz;
-                }
+        // the block's z row; a dropped function (value 0 in all three rows)
+        // reads plane 0, which exists
+        const int *zidx = C.z.idx + iz * MAXR;
+        const double *zS = C.z.S + iz * MAXR, *zD1 = C.z.D1 + iz * MAXR, *zD2 = C.z.D2 + iz * MAXR;
+        long long zo[RZ];
+        double w0[RZ], w1[RZ], w2[RZ];
+#pragma unroll
+        for (int a1 = 0; a1 < RZ; ++a1) {
+            const int g = zidx[a1];
+            zo[a1] = (long long)(g >= 0 ? g : 0) * C.nxy;
+            w0[a1] = zS[a1];
+            w1[a1] = zD1[a1];
+            w2[a1] = zD2[a1];
+        }
+        // the rows kxlo..kxhi are consecutive, so a plane is one contiguous run
+        // of every z row
+        const double *xb = x + (long long)kxlo * ny;
+        for (int e = threadIdx.x; e < plane_n; e += 256) {
+            double v[RZ];
+#pragma unroll
+            for (int a1 = 0; a1 < RZ; ++a1) v[a1] = xb[zo[a1] + e];
+            double c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+            for (int a1 = 0; a1 < RZ; ++a1) {
+                c0 += w0[a1] * v[a1];
+                c1 += w1[a1] * v[a1];
+                c2 += w2[a1] * v[a1];
             }
+            p0[e] = c0;
+            p1[e] = c1;
+            p2[e] = c2;
         }
     }
     for (int e = threadIdx.x; e < (ixe - ixs) * RX; e += 256) {
@@ -297,47 +302,48 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
     }
     __syncthreads();
     if (!has) return;
+
+    int lx[RX], ly[RY];
+    double Sy[RY], D2y[RY];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+        const int g = C.x.idx[px0 * MAXR + s];
+        lx[s] = (g >= 0 ? g - kxlo : 0) * ny;
+    }
+#pragma unroll
+    for (int s = 0; s < RY; ++s) {
+        const int g = C.y.idx[iy * MAXR + s];
+        ly[s] = g >= 0 ? g : 0;
+        Sy[s] = C.y.S[iy * MAXR + s];
+        D2y[s] = C.y.D2[iy * MAXR + s];
+    }
     const double *gS = xS + (px0 - ixs) * RX, *gD = xD + (px0 - ixs) * RX;
-    const int *zidx = C.z.idx + iz * MAXR;
-    const double *zS = C.z.S + iz * MAXR, *zD1 = C.z.D1 + iz * MAXR, *zD2 = C.z.D2 + iz * MAXR;
+    // s0, s1, s2: value / z / zz derivative, sxx, syy: second x / y derivative
     double s0[XG_MAX], s1[XG_MAX], s2[XG_MAX], sxx[XG_MAX], syy[XG_MAX];
 #pragma unroll
     for (int q = 0; q < XG_MAX; ++q) s0[q] = s1[q] = s2[q] = sxx[q] = syy[q] = 0.0;
-#pragma unroll 1
-    for (int a1 = 0; a1 < RZ; ++a1) {
-        const int gzz = zidx[a1];
-        const int lz = gzz >= 0 ? gzz - kzlo : 0;
-        double b00[XG_MAX], b20[XG_MAX], b02[XG_MAX];
 #pragma unroll
-        for (int q = 0; q < XG_MAX; ++q) b00[q] = b20[q] = b02[q] = 0.0;
+    for (int a2 = 0; a2 < RX; ++a2) {
+        double t00 = 0, t02 = 0, t10 = 0, t20 = 0;
 #pragma unroll
-        for (int a2 = 0; a2 < RX; ++a2) {
-            const double *row = tile + (lz * Rx + lx[a2]) * ny;
-            double t0 = 0, t2 = 0;
+        for (int a3 = 0; a3 < RY; ++a3) {
+            const int k = lx[a2] + ly[a3];
+            const double v0 = p0[k];
+            t00 += Sy[a3] * v0;
+            t02 += D2y[a3] * v0;
+            t10 += Sy[a3] * p1[k];
+            t20 += Sy[a3] * p2[k];
+        }
 #pragma unroll
-            for (int a3 = 0; a3 < RY; ++a3) {
-                const double cv = row[ly[a3]];
-                t0 += Sy[a3] * cv;
-                t2 += D2y[a3] * cv;
+        for (int q = 0; q < XG_MAX; ++q)
+            if (q < pn) {
+                const double sx = gS[q * RX + a2], dx = gD[q * RX + a2];
+                s0[q] += sx * t00;
+                s1[q] += sx * t10;
+                s2[q] += sx * t20;
+                sxx[q] += dx * t00;
+                syy[q] += sx * t02;
             }
-#pragma unroll
-            for (int q = 0; q < XG_MAX; ++q)
-                if (q < pn) {
-                    const double sx = gS[q * RX + a2], dx = gD[q * RX + a2];
-                    b00[q] += sx * t0;
-                    b20[q] += dx * t0;
-                    b02[q] += sx * t2;
-                }
-        }
-        const double sz = zS[a1], d1 = zD1[a1], d2 = zD2[a1];
-#pragma unroll
-        for (int q = 0; q < XG_MAX; ++q) {
-            s0[q] += sz * b00[q];
-            s1[q] += d1 * b00[q];
-            s2[q] += d2 * b00[q];
-            sxx[q] += sz * b20[q];
-            syy[q] += sz * b02[q];
-        }
     }
     const double E = Evec[req];
     const double zc = C.z.pts[iz], yc = C.y.pts[iy];
@@ -1931,7 +1937,7 @@ void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *
         if (NM == 1) {
             const unsigned tiles = pd.comp[0].ntiles_g + pd.comp[1].ntiles_g + pd.comp[2].ntiles_g;
             hipLaunchKernelGGL((k_local_grouped<QXY, QXY, QZ>), dim3(tiles, nb), dim3(256),
-                               sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y, cbuf);
+                               sizeof(double) * pd.group_lds, st, pd.dev, E_dev, active, x, y, cbuf);
         } else {
             const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
             hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
