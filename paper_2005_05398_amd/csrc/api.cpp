@@ -517,6 +517,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
     std::string err;
     ProblemDev &pd = p->pd;
     pd.tile_lds = 0;
+    pd.plane_lds = 0;
     pd.group_lds = 0;
     pd.nodes_total = 0;
     for (int a = 0; a < 3; ++a) pd.nodes_total += 3 + p->bx[a].K + p->by[a].K + p->bz[a].K;
@@ -545,18 +546,11 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         C.xt = std::max(1, 256 / p->by[a].n);
         C.xt = std::min(C.xt, p->bx[a].n);
         C.ntiles = p->bz[a].n * ((p->bx[a].n + C.xt - 1) / C.xt);
-        // largest coefficient tile: z support x (x support of xt consecutive points) x ny
+        // LDS of the operator kernels: three z-contracted planes over
+        // (x support of xt consecutive points, or of gt x groups) x ny
         {
             const Basis1D &bz = p->bz[a], &bx = p->bx[a];
-            int rz = 0, rx = 0;
-            for (int i = 0; i < bz.n; ++i) {
-                int lo = 1 << 30, hi = -1;
-                for (int s = 0; s < MAXR; ++s) {
-                    int g = bz.idx[size_t(i) * MAXR + s];
-                    if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
-                }
-                rz = std::max(rz, hi - lo + 1);
-            }
+            int rx = 0;
             for (int i0 = 0; i0 < bx.n; i0 += C.xt) {
                 int lo = 1 << 30, hi = -1;
                 for (int i = i0; i < std::min(bx.n, i0 + C.xt); ++i)
@@ -566,7 +560,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
                     }
                 rx = std::max(rx, hi - lo + 1);
             }
-            pd.tile_lds = std::max(pd.tile_lds, rz * rx * p->by[a].n);
+            pd.plane_lds = std::max(pd.plane_lds, 3 * rx * p->by[a].n);
             // x groups and the grouped tiles (stencil tile plus the x rows of its points)
             std::vector<int> xg;
             for (int i = 0; i < bx.n; ++i) {
@@ -587,10 +581,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
                         int g = bx.idx[size_t(i) * MAXR + s];
                         if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
                     }
-                // three z-contracted planes (rz >= 4 keeps this within tile_lds)
-                const int g_lds = 3 * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR;
-                pd.group_lds = std::max(pd.group_lds, g_lds);
-                pd.tile_lds = std::max(pd.tile_lds, rz * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR);
+                pd.group_lds = std::max(pd.group_lds, 3 * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR);
             }
             C.xg = put(p, xg, err);
         }
@@ -639,6 +630,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         if (!err.empty()) return err;
     }
     p->pr.coupled = p->variant == 2 ? 1 : 0;
+    pd.tile_lds = std::max(pd.plane_lds, pd.group_lds);
     // coupling pairs for the tiled operator
     pd.cpl = CouplingDev{};
     if (sizeof(double) * size_t(pd.tile_lds) > 64 * 1024 && matvec_tiled_ok(pd))

@@ -111,8 +111,9 @@ struct ProblemDev {
     double dcoef[MAXM * MAXM * 16];   // Wigner-sum coefficient table (see setup)
     int dlen;
     int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
-    int tile_lds;                // doubles of LDS for the largest coefficient tile
-    int group_lds;               // doubles of LDS for the grouped n_M = 1 tile (<= tile_lds)
+    int tile_lds;                // doubles of LDS: the larger of the two below
+    int plane_lds;               // doubles of LDS for the z-contracted planes of k_local_tiled
+    int group_lds;               // doubles of LDS for the planes and x rows of k_local_grouped
     int lds_max;                 // bytes of LDS one block may use on the device
     int nodes_total;             // doubles of LDS for all node tables
     CouplingDev cpl;             // tiled path only

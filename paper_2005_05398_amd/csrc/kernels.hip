@@ -254,8 +254,8 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
     const int ixs = C.xg[g0], ixe = C.xg[g0 + ngt];
     const int kxlo = C.x.first[ixs], kxhi = C.x.last[ixe - 1];
     const int plane_n = (kxhi - kxlo + 1) * ny;
-    double *p0 = sm, *p1 = sm + plane_n, *p2 = p1 + plane_n;
-    double *xS = p2 + plane_n, *xD = xS + (ixe - ixs) * RX;
+    double *pl = sm;     // the three planes interleaved: pl[3 e + c]
+    double *xS = pl + 3 * plane_n, *xD = xS + (ixe - ixs) * RX;
     const bool has = threadIdx.x < ngt * ny;
     const int gl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
     const int px0 = C.xg[g0 + gl], pn = C.xg[g0 + gl + 1] - px0;
@@ -290,9 +290,9 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
                 c1 += w1[a1] * v[a1];
                 c2 += w2[a1] * v[a1];
             }
-            p0[e] = c0;
-            p1[e] = c1;
-            p2[e] = c2;
+            pl[3 * e] = c0;
+            pl[3 * e + 1] = c1;
+            pl[3 * e + 2] = c2;
         }
     }
     for (int e = threadIdx.x; e < (ixe - ixs) * RX; e += 256) {
@@ -308,12 +308,12 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
 #pragma unroll
     for (int s = 0; s < RX; ++s) {
         const int g = C.x.idx[px0 * MAXR + s];
-        lx[s] = (g >= 0 ? g - kxlo : 0) * ny;
+        lx[s] = 3 * (g >= 0 ? g - kxlo : 0) * ny;
     }
 #pragma unroll
     for (int s = 0; s < RY; ++s) {
         const int g = C.y.idx[iy * MAXR + s];
-        ly[s] = g >= 0 ? g : 0;
+        ly[s] = 3 * (g >= 0 ? g : 0);
         Sy[s] = C.y.S[iy * MAXR + s];
         D2y[s] = C.y.D2[iy * MAXR + s];
     }
@@ -327,12 +327,11 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
         double t00 = 0, t02 = 0, t10 = 0, t20 = 0;
 #pragma unroll
         for (int a3 = 0; a3 < RY; ++a3) {
-            const int k = lx[a2] + ly[a3];
-            const double v0 = p0[k];
-            t00 += Sy[a3] * v0;
-            t02 += D2y[a3] * v0;
-            t10 += Sy[a3] * p1[k];
-            t20 += Sy[a3] * p2[k];
+            const double *v = pl + lx[a2] + ly[a3];
+            t00 += Sy[a3] * v[0];
+            t02 += D2y[a3] * v[0];
+            t10 += Sy[a3] * v[1];
+            t20 += Sy[a3] * v[2];
         }
 #pragma unroll
         for (int q = 0; q < XG_MAX; ++q)
@@ -378,15 +377,14 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
     int t = blockIdx.x, a = 0;
     while (a < 3 && t >= pd->comp[a].ntiles) { t -= pd->comp[a].ntiles; ++a; }
     if (a >= 3) return;
-    double *tile = sm;
     const CompDev &C = pd->comp[a];
-    const int nx = C.x.n, ny = C.y.n, xt = C.xt;
-    const int ntx = (nx + xt - 1) / xt;
+    const int ny = C.y.n, xt = C.xt;
+    const int ntx = (C.x.n + xt - 1) / xt;
     const int iz = t / ntx, ix0 = (t % ntx) * xt;
-    const int nxt = min(xt, nx - ix0);
-    const int kzlo = C.z.first[iz], kzhi = C.z.last[iz];
+    const int nxt = min(xt, C.x.n - ix0);
     const int kxlo = C.x.first[ix0], kxhi = C.x.last[ix0 + nxt - 1];
-    const int Rz = kzhi - kzlo + 1, Rx = kxhi - kxlo + 1;
+    const int plane_n = (kxhi - kxlo + 1) * ny;
+    double *pl = sm;     // the three planes interleaved: pl[3 e + c]
     const bool has = threadIdx.x < nxt * ny;
     const int ixl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
     const int ix = ix0 + ixl;
@@ -394,23 +392,20 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
     const double E = Evec[req];
     const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
 
-    // local rows (tile-relative indices; dropped functions have value 0)
-    // z row: the same for the whole block (read inside the z loop)
-    const int *zidx = C.z.idx + iz * MAXR;
-    const double *zS = C.z.S + iz * MAXR, *zD1 = C.z.D1 + iz * MAXR, *zD2 = C.z.D2 + iz * MAXR;
+    // local rows (plane-relative offsets; dropped functions have value 0)
     int lx[RX], ly[RY];
     double Sx[RX], D2x[RX], Sy[RY], D2y[RY];
 #pragma unroll
     for (int s = 0; s < RX; ++s) {
         const int g = C.x.idx[ix * MAXR + s];
-        lx[s] = g >= 0 ? g - kxlo : 0;
+        lx[s] = 3 * (g >= 0 ? g - kxlo : 0) * ny;
         Sx[s] = C.x.S[ix * MAXR + s];
         D2x[s] = C.x.D2[ix * MAXR + s];
     }
 #pragma unroll
     for (int s = 0; s < RY; ++s) {
         const int g = C.y.idx[iy * MAXR + s];
-        ly[s] = g >= 0 ? g : 0;
+        ly[s] = 3 * (g >= 0 ? g : 0);
         Sy[s] = C.y.S[iy * MAXR + s];
         D2y[s] = C.y.D2[iy * MAXR + s];
     }
@@ -419,39 +414,63 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
 #pragma unroll
     for (int iM = 0; iM < NM; ++iM) {
         __syncthreads();
-        const double *c = x + C.off + (long long)iM * C.npts;
-        const int tile_n = Rz * Rx * ny;
-        for (int e = threadIdx.x; e < tile_n; e += 256) {
-            const int kz = e / (Rx * ny), rest = e - kz * (Rx * ny);
-            tile[e] = c[((long long)(kzlo + kz) * nx + kxlo) * ny + rest];
+        {
+            // the block's z row, contracted into three planes as the M' block is
+            // read (a dropped function, value 0 in all three rows, reads plane 0)
+            const int *zidx = C.z.idx + iz * MAXR;
+            long long zo[RZ];
+            double w0[RZ], w1[RZ], w2[RZ];
+#pragma unroll
+            for (int a1 = 0; a1 < RZ; ++a1) {
+                const int g = zidx[a1];
+                zo[a1] = (long long)(g >= 0 ? g : 0) * C.nxy;
+                w0[a1] = C.z.S[iz * MAXR + a1];
+                w1[a1] = C.z.D1[iz * MAXR + a1];
+                w2[a1] = C.z.D2[iz * MAXR + a1];
+            }
+            // rows kxlo..kxhi are consecutive: a plane is one contiguous run of each z row
+            const double *xb = x + C.off + (long long)iM * C.npts + (long long)kxlo * ny;
+            for (int e = threadIdx.x; e < plane_n; e += 256) {
+                double v[RZ];
+#pragma unroll
+                for (int a1 = 0; a1 < RZ; ++a1) v[a1] = xb[zo[a1] + e];
+                double c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+                for (int a1 = 0; a1 < RZ; ++a1) {
+                    c0 += w0[a1] * v[a1];
+                    c1 += w1[a1] * v[a1];
+                    c2 += w2[a1] * v[a1];
+                }
+                pl[3 * e] = c0;
+                pl[3 * e + 1] = c1;
+                pl[3 * e + 2] = c2;
+            }
         }
         __syncthreads();
         double s0 = 0, s1 = 0, s2 = 0, sxx = 0, syy = 0;
-#pragma unroll 1
-        for (int a1 = 0; a1 < RZ; ++a1) {
-            const int gzz = zidx[a1];
-            const int lz = gzz >= 0 ? gzz - kzlo : 0;
-            double b00 = 0, b20 = 0, b02 = 0;
 #pragma unroll
-            for (int a2 = 0; a2 < RX; ++a2) {
-                const double *row = tile + (lz * Rx + lx[a2]) * ny;
-                double t0 = 0, t2 = 0;
+        for (int a2 = 0; a2 < RX; ++a2) {
+            // the row offset is taken here, so that the row's addresses are
+            // formed here too (not once for all M' blocks, held in registers)
+            int ro = lx[a2];
+            asm volatile("" : "+v"(ro));
+            double t00 = 0, t02 = 0, t10 = 0, t20 = 0;
 #pragma unroll
-                for (int a3 = 0; a3 < RY; ++a3) {
-                    const double cv = row[ly[a3]];
-                    t0 += Sy[a3] * cv;
-                    t2 += D2y[a3] * cv;
-                }
-                b00 += Sx[a2] * t0;
-                b20 += D2x[a2] * t0;
-                b02 += Sx[a2] * t2;
+            for (int a3 = 0; a3 < RY; ++a3) {
+                const double *v = pl + ro + ly[a3];
+                t00 += Sy[a3] * v[0];
+                t02 += D2y[a3] * v[0];
+                t10 += Sy[a3] * v[1];
+                t20 += Sy[a3] * v[2];
             }
-            const double sz = zS[a1], d1 = zD1[a1], d2 = zD2[a1];
-            s0 += sz * b00;
-            s1 += d1 * b00;
-            s2 += d2 * b00;
-            sxx += sz * b20;
-            syy += sz * b02;
+            s0 += Sx[a2] * t00;
+            s1 += Sx[a2] * t10;
+            s2 += Sx[a2] * t20;
+            sxx += D2x[a2] * t00;
+            syy += Sx[a2] * t02;
+            // the row's products complete before the next row's reads issue
+            // (issued all at once the reads of a block take ~220 registers)
+            asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(sxx), "+v"(syy) : : "memory");
         }
         u[iM] = s0; uz[iM] = s1; uzz[iM] = s2; uxx[iM] = sxx; uyy[iM] = syy;
     }
@@ -1941,7 +1960,7 @@ void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *
         } else {
             const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
             hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
-                               sizeof(double) * pd.tile_lds, st, pd.dev, E_dev, active, x, y, cbuf, nb);
+                               sizeof(double) * pd.plane_lds, st, pd.dev, E_dev, active, x, y, cbuf, nb);
         }
     }
 }
