@@ -526,6 +526,15 @@ __device__ __forceinline__ int cell_fn(const DimDev &d, int node, int k) {
     return node * d.q + k - d.drop0 - ((d.drop0 && node == d.K) ? 1 : 0);
 }
 
+// Orders the LDS accesses of one wave before and after this point (the
+// wave's lanes run together; only the compiler and the memory model need
+// telling).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 constexpr int CPL_WAVES = 4;         // waves per block of the coupling kernel
 constexpr int CPL_REQ = 8;           // requests per block (grid y covers the rest)
 
@@ -596,7 +605,7 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     // one request, -1 for a dropped function; worked out once for all requests
     constexpr int EPL = (NM * TS + 63) / 64;
     int goff[EPL];
-    __syncthreads();                                   // fidx written
+    wave_sync();                                       // fidx written
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
         const int e = lane + 64 * q;
@@ -608,47 +617,63 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
             if (gz >= 0 && gx >= 0 && gy >= 0) goff[q] = iM * B.npts + (gz * bnx + gx) * bny + gy;
         }
     }
-    for (int req = r0; req < r1; ++req) {
-        if (active && !active[req]) continue;          // the same for the whole block
-        __syncthreads();
-        if (has) {
-            const double *x = X + (long long)req * N + B.off;
+    // Each wave works on its own tile, so waves synchronise only with
+    // themselves; the tile of the next active request is fetched into
+    // registers while the current one is evaluated.
+    auto next_active = [&](int r) {
+        while (r < r1 && active && !active[r]) ++r;
+        return r;
+    };
+    double pf[EPL];
+    auto fetch = [&](int r) {
+        const double *x = X + (long long)r * N + B.off;
 #pragma unroll
-            for (int q = 0; q < EPL; ++q) {
-                const int e = lane + 64 * q;
-                if (e < NM * TS) tile[wave][e] = goff[q] >= 0 ? x[goff[q]] : 0.0;
-            }
+        for (int q = 0; q < EPL; ++q) pf[q] = goff[q] >= 0 ? x[goff[q]] : 0.0;
+    };
+    int req = next_active(r0);
+    if (!has || req >= r1) return;
+    fetch(req);
+    while (req < r1) {
+        const int nxt = next_active(req + 1);
+        wave_sync();                                   // the previous tile is read
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) {
+            const int e = lane + 64 * q;
+            if (e < NM * TS) tile[wave][e] = pf[q];
         }
-        __syncthreads();
-        if (!mine) continue;
-        double val[NM];
+        wave_sync();                                   // this tile is written
+        if (nxt < r1) fetch(nxt);
+        if (mine) {
+            double val[NM];
 #pragma unroll
-        for (int iM = 0; iM < NM; ++iM) {
-            const double *T = tile[wave] + iM * TS;
-            double acc = 0;
+            for (int iM = 0; iM < NM; ++iM) {
+                const double *T = tile[wave] + iM * TS;
+                double acc = 0;
 #pragma unroll
-            for (int c = 0; c < RZ; ++c) {
-                double accx = 0;
+                for (int c = 0; c < RZ; ++c) {
+                    double accx = 0;
 #pragma unroll
-                for (int a = 0; a < RXY; ++a) {
-                    const double *row = T + (c * RXY + a) * RXY;
-                    double accy = 0;
+                    for (int a = 0; a < RXY; ++a) {
+                        const double *row = T + (c * RXY + a) * RXY;
+                        double accy = 0;
 #pragma unroll
-                    for (int bq = 0; bq < RXY; ++bq) accy += vy[bq] * row[bq];
-                    accx += vx[a] * accy;
+                        for (int bq = 0; bq < RXY; ++bq) accy += vy[bq] * row[bq];
+                        accx += vx[a] * accy;
+                    }
+                    acc += vz[c] * accx;
                 }
-                acc += vz[c] * accx;
+                val[iM] = acc;
             }
-            val[iM] = acc;
-        }
-        double *y = cbuf + ((long long)req * 2 + slot) * N + outp;
+            double *y = cbuf + ((long long)req * 2 + slot) * N + outp;
 #pragma unroll
-        for (int iM = 0; iM < NM; ++iM) {
-            double o = 0;
+            for (int iM = 0; iM < NM; ++iM) {
+                double o = 0;
 #pragma unroll
-            for (int jM = 0; jM < NM; ++jM) o += F[iM * NM + jM] * val[jM];
-            y[(long long)iM * npa] = o;
+                for (int jM = 0; jM < NM; ++jM) o += F[iM * NM + jM] * val[jM];
+                y[(long long)iM * npa] = o;
+            }
         }
+        req = nxt;
     }
 }
 
