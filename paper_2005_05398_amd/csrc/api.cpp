@@ -646,6 +646,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         pd.cpl.ntasks = ch.ntasks;
         pd.cpl.npairs = ch.npairs;
         pd.cpl.task = put(p, ch.task, err);
+        pd.cpl.r = put(p, ch.r, err);
         pd.cpl.out = put(p, ch.out, err);
         pd.cpl.s = put(p, ch.s, err);
         pd.cpl.F = put(p, ch.F, err);

@@ -161,22 +161,43 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
         for (int t = 0; t < nth; ++t)
             if (ri[t] != recs[t].size()) return "coupling pair merge failed";
     }
-    // tasks: (beta, cell) groups cut into chunks of at most 64 pairs
+    // tasks: (beta, cell) groups cut into chunks of at most 64 pairs, each with
+    // the cell's function indices and beta's sizes
     ch.task.clear();
+    ch.r.clear();
     for (int b = 0; b < 3; ++b) {
-        const int Kz = p->bz[b].K, Kx = p->bx[b].K, Ky = p->by[b].K;
+        const Basis1D &bz = p->bz[b], &bx = p->bx[b], &by = p->by[b];
+        const int Kz = bz.K, Kx = bx.K, Ky = by.K;
         for (int mz = 0; mz < Kz; ++mz)
             for (int mx = 0; mx < Kx; ++mx)
                 for (int my = 0; my < Ky; ++my) {
                     const int key = keyoff[b] + (mz * Kx + mx) * Ky + my;
                     for (long long q = start[key]; q < start[key + 1]; q += 64) {
-                        const int cnt = int(std::min<long long>(64, start[key + 1] - q));
-                        const int t8[8] = {b, mz, mx, my, int(q), cnt, 0, 0};
-                        ch.task.insert(ch.task.end(), t8, t8 + 8);
+                        int rec[CPL_TASK] = {};
+                        rec[CT_BETA] = b;
+                        rec[CT_MZ] = mz;
+                        rec[CT_MX] = mx;
+                        rec[CT_MY] = my;
+                        rec[CT_FIRST] = int(q);
+                        rec[CT_COUNT] = int(std::min<long long>(64, start[key + 1] - q));
+                        rec[CT_NX] = bx.n;
+                        rec[CT_NY] = by.n;
+                        rec[CT_NPTS] = int(p->npts[b]);
+                        const unsigned long long off = (unsigned long long)p->off[b];
+                        rec[CT_OFF_LO] = int(off & 0xffffffffull);
+                        rec[CT_OFF_HI] = int(off >> 32);
+                        int *f = rec + CT_FIDX;
+                        for (int k = 0; k < 2 * bz.q; ++k) *f++ = bz.global_index(mz + k / bz.q, k % bz.q);
+                        for (int k = 0; k < 2 * bx.q; ++k) *f++ = bx.global_index(mx + k / bx.q, k % bx.q);
+                        for (int k = 0; k < 2 * by.q; ++k) *f++ = by.global_index(my + k / by.q, k % by.q);
+                        ch.task.insert(ch.task.end(), rec, rec + CPL_TASK);
+                        ch.r.push_back((bz.nodes[mz + 1] - bz.nodes[mz]) / bz.hbar);
+                        ch.r.push_back((bx.nodes[mx + 1] - bx.nodes[mx]) / bx.hbar);
+                        ch.r.push_back((by.nodes[my + 1] - by.nodes[my]) / by.hbar);
                     }
                 }
     }
-    ch.ntasks = int(ch.task.size() / 8);
+    ch.ntasks = int(ch.task.size() / CPL_TASK);
     return "";
 }
 

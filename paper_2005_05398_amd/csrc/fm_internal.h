@@ -93,10 +93,21 @@ struct CompDev {
 };
 
 // Coupling pairs grouped by (beta, cell of beta); built on the host.
+// One coupling task (a (beta, cell) group of at most 64 pairs): everything a
+// wave needs before it can fetch the cell's coefficients, so that the fetch
+// waits for this record only.
+constexpr int CPL_TASK = 32;     // ints per task record
+enum {
+    CT_BETA = 0, CT_MZ, CT_MX, CT_MY, CT_FIRST, CT_COUNT,
+    CT_NX, CT_NY, CT_NPTS, CT_OFF_LO, CT_OFF_HI,
+    CT_FIDX = 11                 // 2 q_z z, 2 q x, 2 q y global function indices (-1: dropped)
+};
+
 struct CouplingDev {
     int ntasks;
     long long npairs;
-    const int *task;             // [ntasks][8]: beta, mz, mx, my, first pair, pair count (<= 64)
+    const int *task;             // [ntasks][CPL_TASK] records (layout above)
+    const double *r;             // [ntasks][3] cell width / hbar in z, x, y
     const int *out;              // [npairs] 2 * (alpha output index of M' block 0) + slot
     const double *s;             // [3][npairs] position inside the cell: z, x, y
     const double *F;             // [nM * nM][npairs] factor of beta's M'' value in alpha's M' row

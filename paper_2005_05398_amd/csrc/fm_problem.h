@@ -17,8 +17,8 @@ struct HostFactors {
 };
 
 struct CouplingHost {
-    std::vector<int> task, out;
-    std::vector<double> s, F;
+    std::vector<int> task, out;  // task: [ntasks][CPL_TASK] records
+    std::vector<double> s, F, r; // r: [ntasks][3] cell width / hbar (z, x, y)
     long long npairs = 0;
     int ntasks = 0;
 };

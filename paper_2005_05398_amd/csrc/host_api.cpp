@@ -129,7 +129,7 @@ fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double 
         }
     };
     for (int t = 0; t < ch.ntasks; ++t) {
-        const int *tk = &ch.task[size_t(t) * 8];
+        const int *tk = &ch.task[size_t(t) * CPL_TASK];
         const int b = tk[0], mz = tk[1], mx = tk[2], my = tk[3], first = tk[4], cnt = tk[5];
         const Basis1D &bz = p.bz[b], &bx = p.bx[b], &by = p.by[b];
         const double rz = (bz.nodes[mz + 1] - bz.nodes[mz]) / bz.hbar;

@@ -520,12 +520,6 @@ __device__ __forceinline__ void hermite_cell(double s, double r, double *v) {
     }
 }
 
-// Global index of the k-th function of node `node` of a dimension, -1 if dropped.
-__device__ __forceinline__ int cell_fn(const DimDev &d, int node, int k) {
-    if (d.drop0 && k == 0 && (node == 0 || node == d.K)) return -1;
-    return node * d.q + k - d.drop0 - ((d.drop0 && node == d.K) ? 1 : 0);
-}
-
 // Orders the LDS accesses of one wave before and after this point (the
 // wave's lanes run together; only the compiler and the memory model need
 // telling).
@@ -553,52 +547,43 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     constexpr int RXY = 2 * QXY, RZ = 2 * QZ, TS = RZ * RXY * RXY;
     __shared__ __align__(16) double tile[CPL_WAVES][NM * TS];
     __shared__ int fidx[CPL_WAVES][RZ + 2 * RXY];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const CouplingDev &cp = pd->cpl;
     // XCD-aware order: consecutive tasks (neighbouring cells) on one XCD's L2
     const int nblk = gridDim.x, xcd = blockIdx.x % 8, per = (nblk + 7) / 8;
     const int full = nblk % 8 == 0 ? 8 : nblk % 8;     // XCDs that get `per` blocks
     const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
-    const int task = bid * CPL_WAVES + wave;
-    const bool has = task < cp.ntasks;
-    int b = 0, count = 0;
-    long long first = 0;
-    double r_z = 0, r_x = 0, r_y = 0;
-    if (has) {
-        const int *t = cp.task + (size_t)task * 8;
-        b = t[0];
-        const int mz = t[1], mx = t[2], my = t[3];
-        first = t[4];
-        count = t[5];
-        const CompDev &B = pd->comp[b];
-        r_z = (B.z.nodes[mz + 1] - B.z.nodes[mz]) / B.z.hbar;
-        r_x = (B.x.nodes[mx + 1] - B.x.nodes[mx]) / B.x.hbar;
-        r_y = (B.y.nodes[my + 1] - B.y.nodes[my]) / B.y.hbar;
-        if (lane < RZ) fidx[wave][lane] = cell_fn(B.z, mz + lane / QZ, lane % QZ);
-        else if (lane < RZ + RXY) fidx[wave][lane] = cell_fn(B.x, mx + (lane - RZ) / QXY, (lane - RZ) % QXY);
-        else if (lane < RZ + 2 * RXY)
-            fidx[wave][lane] = cell_fn(B.y, my + (lane - RZ - RXY) / QXY, (lane - RZ - RXY) % QXY);
-    }
-    const bool mine = has && lane < count;
+    const int task = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
+    if (task >= cp.ntasks) return;                     // the whole wave (no block barriers)
+    // the task record (wave-uniform): the cell's function indices and beta's
+    // sizes come with it, so the fetch of the cell's coefficients and the
+    // pairs' data wait for this one read only
+    const int *t = cp.task + (size_t)task * CPL_TASK;
+    const int count = __builtin_amdgcn_readfirstlane(t[CT_COUNT]);
+    const long long first = __builtin_amdgcn_readfirstlane(t[CT_FIRST]);
+    const int bnx = __builtin_amdgcn_readfirstlane(t[CT_NX]), bny = __builtin_amdgcn_readfirstlane(t[CT_NY]);
+    const int bnpts = __builtin_amdgcn_readfirstlane(t[CT_NPTS]);
+    const long long boff = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(t[CT_OFF_HI]) << 32) |
+                                       (unsigned)__builtin_amdgcn_readfirstlane(t[CT_OFF_LO]));
+    if (lane < RZ + 2 * RXY) fidx[wave][lane] = t[CT_FIDX + lane];
+    const bool mine = lane < count;
     const long long pr = first + lane;
     double vz[RZ], vx[RXY], vy[RXY], F[NM * NM];
     int outp = 0, slot = 0, npa = 0;
     if (mine) {
-        hermite_cell<QZ>(cp.s[pr], r_z, vz);
-        hermite_cell<QXY>(cp.s[cp.npairs + pr], r_x, vx);
-        hermite_cell<QXY>(cp.s[2 * cp.npairs + pr], r_y, vy);
+        hermite_cell<QZ>(cp.s[pr], cp.r[3 * (size_t)task], vz);
+        hermite_cell<QXY>(cp.s[cp.npairs + pr], cp.r[3 * (size_t)task + 1], vx);
+        hermite_cell<QXY>(cp.s[2 * cp.npairs + pr], cp.r[3 * (size_t)task + 2], vy);
 #pragma unroll
         for (int f = 0; f < NM * NM; ++f) F[f] = cp.F[(size_t)f * cp.npairs + pr];
         const int o = cp.out[pr];
         outp = o >> 1;
         slot = o & 1;
         // the point's own component, from its offset (an exchange-reduced problem
-        // reads partner 2 from component 1, so b alone does not fix it)
+        // reads partner 2 from component 1, so beta alone does not fix it)
         const int a = outp >= pd->comp[2].off ? 2 : (outp >= pd->comp[1].off ? 1 : 0);
         npa = pd->comp[a].npts;
     }
-    const CompDev &B = pd->comp[b];
-    const int bnx = B.x.n, bny = B.y.n;
     const long long N = pd->N;
     const int r0 = blockIdx.y * CPL_REQ, r1 = min(nb, r0 + CPL_REQ);
     // this lane's tile entries (e = lane + 64 q): offsets into beta's block of
@@ -610,11 +595,11 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     for (int q = 0; q < EPL; ++q) {
         const int e = lane + 64 * q;
         goff[q] = -1;
-        if (has && e < NM * TS) {
+        if (e < NM * TS) {
             const int iM = e / TS, rem = e - iM * TS;
             const int c = rem / (RXY * RXY), a = (rem / RXY) % RXY, bq = rem % RXY;
             const int gz = fidx[wave][c], gx = fidx[wave][RZ + a], gy = fidx[wave][RZ + RXY + bq];
-            if (gz >= 0 && gx >= 0 && gy >= 0) goff[q] = iM * B.npts + (gz * bnx + gx) * bny + gy;
+            if (gz >= 0 && gx >= 0 && gy >= 0) goff[q] = iM * bnpts + (gz * bnx + gx) * bny + gy;
         }
     }
     // Each wave works on its own tile, so waves synchronise only with
@@ -626,12 +611,12 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     };
     double pf[EPL];
     auto fetch = [&](int r) {
-        const double *x = X + (long long)r * N + B.off;
+        const double *x = X + (long long)r * N + boff;
 #pragma unroll
         for (int q = 0; q < EPL; ++q) pf[q] = goff[q] >= 0 ? x[goff[q]] : 0.0;
     };
     int req = next_active(r0);
-    if (!has || req >= r1) return;
+    if (req >= r1) return;
     fetch(req);
     while (req < r1) {
         const int nxt = next_active(req + 1);
