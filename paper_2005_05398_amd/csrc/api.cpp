@@ -519,6 +519,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
     pd.tile_lds = 0;
     pd.plane_lds = 0;
     pd.group_lds = 0;
+    std::vector<int> gtile;              // grouped operator tiles (GT_REC ints each)
     pd.nodes_total = 0;
     for (int a = 0; a < 3; ++a) pd.nodes_total += 3 + p->bx[a].K + p->by[a].K + p->bz[a].K;
     pd.q[0] = p->bx[0].q;
@@ -584,6 +585,21 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
                 pd.group_lds = std::max(pd.group_lds, 3 * (hi - lo + 1) * p->by[a].n + (i1 - i0) * 2 * MAXR);
             }
             C.xg = put(p, xg, err);
+            // the tiles' records, in the order the kernel's blocks take them
+            const int ntg = (C.ngx + C.gt - 1) / C.gt;
+            for (int iz = 0; iz < bz.n && !p->absent(a); ++iz)
+                for (int tg = 0; tg < ntg; ++tg) {
+                    const int g0 = tg * C.gt, ngt = std::min(C.gt, C.ngx - g0);
+                    const int ixs = xg[g0], ixe = xg[g0 + ngt];
+                    int lo = 1 << 30, hi = -1;
+                    for (int i = ixs; i < ixe; ++i)
+                        for (int s = 0; s < MAXR; ++s) {
+                            int g = bx.idx[size_t(i) * MAXR + s];
+                            if (g >= 0) { lo = std::min(lo, g); hi = std::max(hi, g); }
+                        }
+                    const int rec[GT_REC] = {a, iz, g0, ngt, ixs, ixe, lo, hi};
+                    gtile.insert(gtile.end(), rec, rec + GT_REC);
+                }
         }
         PrecCompDev &F = p->pr.comp[a];
         std::memset(&F, 0, sizeof(F));
@@ -630,6 +646,8 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         if (!err.empty()) return err;
     }
     p->pr.coupled = p->variant == 2 ? 1 : 0;
+    pd.gtile = put(p, gtile, err);
+    if (!err.empty()) return err;
     pd.tile_lds = std::max(pd.plane_lds, pd.group_lds);
     // coupling pairs for the tiled operator
     pd.cpl = CouplingDev{};

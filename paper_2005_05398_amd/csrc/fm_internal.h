@@ -92,6 +92,11 @@ struct CompDev {
     int ntiles_g;                // grouped tiles: nz * ceil(ngx / gt)
 };
 
+// One grouped operator tile: component, z point, first x group and number of
+// groups, the tile's x points [ixs, ixe) and their x support [kxlo, kxhi].
+constexpr int GT_REC = 8;
+enum { GT_A = 0, GT_IZ, GT_G0, GT_NGT, GT_IXS, GT_IXE, GT_KXLO, GT_KXHI };
+
 // Coupling pairs grouped by (beta, cell of beta); built on the host.
 // One coupling task (a (beta, cell) group of at most 64 pairs): everything a
 // wave needs before it can fetch the cell's coefficients, so that the fetch
@@ -122,6 +127,7 @@ struct ProblemDev {
     double dcoef[MAXM * MAXM * 16];   // Wigner-sum coefficient table (see setup)
     int dlen;
     int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
+    const int *gtile;            // [sum ntiles_g][GT_REC] grouped tiles, in launch order (layout below)
     int tile_lds;                // doubles of LDS: the larger of the two below
     int plane_lds;               // doubles of LDS for the z-contracted planes of k_local_tiled
     int group_lds;               // doubles of LDS for the planes and x rows of k_local_grouped

@@ -243,16 +243,15 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
     const int req = blockIdx.y;
     if (active && !active[req]) return;
     extern __shared__ double sm[];
-    int t = blockIdx.x, a = 0;
-    while (a < 3 && t >= pd->comp[a].ntiles_g) { t -= pd->comp[a].ntiles_g; ++a; }
-    if (a >= 3) return;
+    // the tile's record (block-uniform): everything the coefficient reads
+    // depend on, in one read
+    const int *rec = pd->gtile + (size_t)blockIdx.x * GT_REC;
+    const int a = __builtin_amdgcn_readfirstlane(rec[GT_A]), iz = __builtin_amdgcn_readfirstlane(rec[GT_IZ]);
+    const int g0 = __builtin_amdgcn_readfirstlane(rec[GT_G0]), ngt = __builtin_amdgcn_readfirstlane(rec[GT_NGT]);
+    const int ixs = __builtin_amdgcn_readfirstlane(rec[GT_IXS]), ixe = __builtin_amdgcn_readfirstlane(rec[GT_IXE]);
+    const int kxlo = __builtin_amdgcn_readfirstlane(rec[GT_KXLO]), kxhi = __builtin_amdgcn_readfirstlane(rec[GT_KXHI]);
     const CompDev &C = pd->comp[a];
-    const int nx = C.x.n, ny = C.y.n, gt = C.gt, ngx = C.ngx;
-    const int ntg = (ngx + gt - 1) / gt;
-    const int iz = t / ntg, g0 = (t % ntg) * gt;
-    const int ngt = min(gt, ngx - g0);
-    const int ixs = C.xg[g0], ixe = C.xg[g0 + ngt];
-    const int kxlo = C.x.first[ixs], kxhi = C.x.last[ixe - 1];
+    const int ny = C.y.n;
     const int plane_n = (kxhi - kxlo + 1) * ny;
     double *pl = sm;     // the three planes interleaved: pl[3 e + c]
     double *xS = pl + 3 * plane_n, *xD = xS + (ixe - ixs) * RX;
@@ -260,6 +259,21 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
     const int gl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
     const int px0 = C.xg[g0 + gl], pn = C.xg[g0 + gl + 1] - px0;
     const double *x = X + (long long)req * pd->N + C.off;
+    // this thread's rows, read now so that they arrive with the coefficients
+    int lx[RX], ly[RY];
+    double Sy[RY], D2y[RY];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+        const int g = C.x.idx[px0 * MAXR + s];
+        lx[s] = 3 * (g >= 0 ? g - kxlo : 0) * ny;
+    }
+#pragma unroll
+    for (int s = 0; s < RY; ++s) {
+        const int g = C.y.idx[iy * MAXR + s];
+        ly[s] = 3 * (g >= 0 ? g : 0);
+        Sy[s] = C.y.S[iy * MAXR + s];
+        D2y[s] = C.y.D2[iy * MAXR + s];
+    }
 
     {
         // the block's z row; a dropped function (value 0 in all three rows)
@@ -302,21 +316,6 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
     }
     __syncthreads();
     if (!has) return;
-
-    int lx[RX], ly[RY];
-    double Sy[RY], D2y[RY];
-#pragma unroll
-    for (int s = 0; s < RX; ++s) {
-        const int g = C.x.idx[px0 * MAXR + s];
-        lx[s] = 3 * (g >= 0 ? g - kxlo : 0) * ny;
-    }
-#pragma unroll
-    for (int s = 0; s < RY; ++s) {
-        const int g = C.y.idx[iy * MAXR + s];
-        ly[s] = 3 * (g >= 0 ? g : 0);
-        Sy[s] = C.y.S[iy * MAXR + s];
-        D2y[s] = C.y.D2[iy * MAXR + s];
-    }
     const double *gS = xS + (px0 - ixs) * RX, *gD = xD + (px0 - ixs) * RX;
     // s0, s1, s2: value / z / zz derivative, sxx, syy: second x / y derivative
     double s0[XG_MAX], s1[XG_MAX], s2[XG_MAX], sxx[XG_MAX], syy[XG_MAX];
