@@ -529,7 +529,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 constexpr int CPL_WAVES = 4;         // waves per block of the coupling kernel
-constexpr int CPL_REQ = 8;           // requests per block (grid y covers the rest)
+constexpr int CPL_REQ = 16;          // requests per block (grid y covers the rest)
 
 // Coupling term of the operator for the pairs of one (beta, cell) task per
 // wave: the wave stages the cell's (2QZ x 2QXY x 2QXY) coefficients of every
