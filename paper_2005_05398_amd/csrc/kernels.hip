@@ -1808,18 +1808,48 @@ __global__ void __launch_bounds__(RT) k_arnoldi_update(KrylovDev K, int j) {
     *W = (*W - qt - t[j] * qj) * (1.0 / K.rho[req]);
 }
 
-// y = R^-1 g for the steps of this cycle (one thread per request).
-__global__ void k_cycle_solve(KrylovDev K, const int *__restrict__ running) {
-    const int req = blockIdx.x * blockDim.x + threadIdx.x;
-    if (req >= K.nb || !running[req]) return;
+// y = R^-1 g for the steps of this cycle, one block per request, by columns:
+// once y_i is known, every row above it takes its column-i term at once (the
+// block's threads share the rows), so a step costs one barrier; each thread
+// reads its rows of the next column while the current one is applied.
+constexpr int CS_ROWS = (MAX_RESTART + RT - 1) / RT;   // rows per thread
+__global__ void __launch_bounds__(RT) k_cycle_solve(KrylovDev K, const int *__restrict__ running) {
+    const int req = blockIdx.x;
+    if (!running[req]) return;
     const int m = K.m, jc = K.jcount[req];
     const double *H = K.H + (size_t)req * (m + 1) * m;
     const double *g = K.g + (size_t)req * (m + 1);
     double *y = K.y + (size_t)req * m;
+    __shared__ double yi[2];
+    double r[CS_ROWS], h[CS_ROWS], dg[CS_ROWS];
+#pragma unroll
+    for (int k = 0; k < CS_ROWS; ++k) {
+        const int row = threadIdx.x + RT * k;
+        r[k] = row < jc ? g[row] : 0.0;
+        dg[k] = row < jc ? H[(size_t)row * m + row] : 0.0;
+        h[k] = row < jc - 1 ? H[(size_t)row * m + (jc - 1)] : 0.0;
+    }
     for (int i = jc - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int k = i + 1; k < jc; ++k) s -= H[(size_t)i * m + k] * y[k];
-        y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
+        // the owner of row i finishes it
+        if ((i % RT) == (int)threadIdx.x) {
+            const int k = i / RT;
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < CS_ROWS; ++u)
+                if (u == k) v = dg[u] != 0.0 ? r[u] / dg[u] : 0.0;
+            y[i] = v;
+            yi[i & 1] = v;
+        }
+        __syncthreads();
+        const double v = yi[i & 1];
+        double hn[CS_ROWS];
+#pragma unroll
+        for (int k = 0; k < CS_ROWS; ++k) {
+            const int row = threadIdx.x + RT * k;
+            hn[k] = (i > 0 && row < i - 1) ? H[(size_t)row * m + (i - 1)] : 0.0;
+            if (row < i) r[k] -= h[k] * v;
+            h[k] = hn[k];
+        }
     }
 }
 
@@ -2189,7 +2219,7 @@ unsigned reduce_blocks(const KrylovDev &k) {
 }
 
 void launch_cycle_solve(const KrylovDev &k, const int *running, hipStream_t st) {
-    hipLaunchKernelGGL(k_cycle_solve, dim3(cdiv(k.nb, 64)), dim3(64), 0, st, k, running);
+    hipLaunchKernelGGL(k_cycle_solve, dim3(k.nb), dim3(RT), 0, st, k, running);
 }
 
 void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream_t st) {
