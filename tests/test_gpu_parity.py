@@ -187,6 +187,28 @@ def test_solve_batched_energies(device):
         assert np.linalg.norm(Xg[i] - xref) / np.linalg.norm(xref) <= 1e-8
 
 
+def test_solve_cycle_longer_than_256_steps(device):
+    """One FGMRES cycle of more than 256 steps: the cycle's back substitution
+    gives each thread of its block several rows of R.  Just below the
+    break-up threshold (E -> 0) the block-Jacobi preconditioned iteration on
+    this grid needs about 260 steps, which restart = 1000 keeps in one cycle."""
+    fm = _fm()
+    desc = small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    E = -0.005
+    b = W.rhs(2012, O.N)
+    x = to_dev(np.zeros((1, O.N)), device)
+    st, res = P.solve([E], to_dev(b[None, :], device), x, restart=1000, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    assert res[0]["iters"] > 256, res
+    A = O.assemble(E)
+    xg = x.cpu().numpy()[0]
+    assert rel_residual(A, xg, b) <= 1e-10
+    xref = lu_solve(A, b, "splu")
+    assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-7
+
+
 def test_solve_identical_particle_symmetry(device):
     from tests.test_oracle_operator import permutation_maps
     fm = _fm()
