@@ -248,11 +248,27 @@ KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_
                              "kernels.hip")
 
 
+def traffic_variant(args):
+    """The configuration a counter record belongs to: the workload, plus every
+    option that changes what the timed kernels do (the committed records are
+    for the defaults, whose name is the workload's alone)."""
+    v = args.workload
+    if args.exchange:
+        v += f"-exchange{args.exchange:+d}"
+    if args.precond != "block_jacobi":
+        v += f"-{args.precond}"
+    if args.prec != "fp64":
+        v += f"-{args.prec}"
+    if args.restart != (300 if args.workload == "cfg2" else 60):
+        v += f"-restart{args.restart}"
+    return v
+
+
 def measured_traffic(workload, kclass):
     """HBM bytes per launch of the dominant kernel class from the committed
     counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy factor),
-    or None when there is none for this workload and class or the kernel
-    source changed since the counters were taken."""
+    or None when there is none for this configuration (`traffic_variant`) and
+    class or the kernel source changed since the counters were taken."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -384,7 +400,7 @@ def main():
         roof = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GB/s"] / HBM_PEAK_GBS}
     roof.update({"kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
-                 "traffic": measured_traffic(args.workload, dom)})
+                 "traffic": measured_traffic(traffic_variant(args), dom)})
     total_kernel_ms = sum(v["ms"] for v in prof.values())
     line = {
         "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "cfg2"
