@@ -695,10 +695,14 @@ __global__ void __launch_bounds__(MZ_COLS) k_modez(const ProblemDev *__restrict_
     }
 }
 
-// Mode-z product with one (x, y) column per thread held in registers (nz <=
-// MAXNZ) and W in LDS (read by the whole wave at once): out[k'][p] =
-// sum_k W[k'][k] in[k][p].  Grid: (columns / 256, alpha x M', request); in and
-// out may alias (a thread reads its whole column before writing it).
+// Mode-z product with each (x, y) column held in registers (nz <= MAXNZ) and W
+// in LDS (read by the whole wave at once): out[k'][p] = sum_k W[k'][k] in[k][p].
+// A column's outputs are split over S threads of the block (S = 1, 2, 4 or 8,
+// chosen so that small batches still fill the chip; each of them reads the
+// whole column, the repeats from cache: sharing one read through LDS measured
+// no faster), taking groups of four outputs in turn; consecutive threads take
+// consecutive columns.  Grid: (columns / (256 / S), alpha x M', request); in
+// and out may alias (the block reads all its columns before any thread writes).
 // F32: the products in FP32 (inputs rounded to FP32, outputs widened).
 constexpr int MZ2_THREADS = 256;
 
@@ -706,7 +710,7 @@ template <int MAXNZ, bool F32>
 __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__restrict__ pd,
                                                            const PrecDev *__restrict__ pr,
                                                            const int *__restrict__ active, int which,
-                                                           const double *in, double *out) {
+                                                           const double *in, double *out, int split) {
     using T = typename std::conditional<F32, float, double>::type;
     const int req = blockIdx.z;
     if (active && !active[req]) return;
@@ -715,7 +719,8 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     const CompDev &C = pd->comp[a];
     const PrecCompDev &F = pr->comp[a];
     const int nz = C.z.n, nxy = C.nxy;
-    if ((int)blockIdx.x * MZ2_THREADS >= nxy) return;
+    const int cb = MZ2_THREADS / split;                // columns per block
+    if ((int)blockIdx.x * cb >= nxy) return;
     __shared__ T W[(MAXNZ + 3) * MAXNZ];
     if (F32) {
         const float *Wg = F.Wz32 + ((size_t)iM * 2 + which) * nz * nz;
@@ -724,15 +729,17 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
         const double *Wg = F.Wz + ((size_t)iM * 2 + which) * nz * nz;
         for (int t = threadIdx.x; t < (nz + 3) * nz; t += MZ2_THREADS) W[t] = t < nz * nz ? (T)Wg[t] : (T)0;
     }
-    __syncthreads();
-    const int col = blockIdx.x * MZ2_THREADS + threadIdx.x;
-    if (col >= nxy) return;
+    const int sub = threadIdx.x / cb;
+    const int col = blockIdx.x * cb + (threadIdx.x - sub * cb);
+    const bool ok = col < nxy;
     const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts + col;
     T v[MAXNZ];
 #pragma unroll
-    for (int k = 0; k < MAXNZ; ++k) v[k] = k < nz ? (T)in[base + (long long)k * nxy] : (T)0;
-    // four outputs at a time (independent sums; rows past nz read zeros)
-    for (int k2 = 0; k2 < nz; k2 += 4) {
+    for (int k = 0; k < MAXNZ; ++k) v[k] = (ok && k < nz) ? (T)in[base + (long long)k * nxy] : (T)0;
+    __syncthreads();                                   // W staged; every column of the block read
+    if (!ok) return;
+    // groups of four outputs (independent sums; rows past nz read zeros)
+    for (int k2 = 4 * sub; k2 < nz; k2 += 4 * split) {
         T acc[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < MAXNZ; ++k)
@@ -2034,8 +2041,14 @@ bool launch_modez_reg(const ProblemDev &pd, const PrecDev &pr, int nb, const int
         maxnxy = std::max(maxnxy, pd.comp[a].nxy);
         maxnz = std::max(maxnz, pd.comp[a].z.n);
     }
-    dim3 grid(cdiv(maxnxy, MZ2_THREADS), 3 * pd.nM, nb);
-#define FM_MZ(M) hipLaunchKernelGGL((k_modez_reg<M, F32>), grid, dim3(MZ2_THREADS), 0, st, pd.dev, pr.dev, active, which, in, out)
+    // split a column's outputs over up to 8 threads until the launch has about
+    // 256 K threads (at most as many groups of four outputs as there are)
+    // 256 K threads (at most as many groups of four outputs as there are)
+    const long long cols = (long long)maxnxy * 3 * pd.nM * nb;
+    int split = 1;
+    while (split < 8 && 4 * split < maxnz && cols * split < 256 * 1024) split *= 2;
+    dim3 grid(cdiv(maxnxy, MZ2_THREADS / split), 3 * pd.nM, nb);
+#define FM_MZ(M) hipLaunchKernelGGL((k_modez_reg<M, F32>), grid, dim3(MZ2_THREADS), 0, st, pd.dev, pr.dev, active, which, in, out, split)
     if (maxnz <= 16) FM_MZ(16);
     else if (maxnz <= 32) FM_MZ(32);
     else if (maxnz <= 48) FM_MZ(48);
