@@ -1508,13 +1508,14 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum over the block (RT threads); the result is valid in every thread.
+// Sum over the block (NT threads); the result is valid in every thread.
+template <int NT = RT>
 __device__ __forceinline__ double block_sum(double v, double *red) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = 0;
-    for (int wv = 0; wv < RT / 64; ++wv) r += red[wv];
+    for (int wv = 0; wv < NT / 64; ++wv) r += red[wv];
     __syncthreads();
     return r;
 }
@@ -1647,6 +1648,8 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     }
 }
 
+constexpr int FT = 1024;             // threads of the step-completion kernel (its waves split the blocks' partials)
+
 // Completes step j of every active request from the dot-pass partials: s, t,
 // r_j by Pythagoras (r_j = 0 when U.U - s.s is below 1e-20 U.U: U lies in the
 // span of Q), the Hessenberg column j - 1 with its Givens rotation and the
@@ -1655,22 +1658,22 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
 // t and c_j (hcol), r_j (scal) and rho_j (rho; at least 1e-8 |W|, and 1 for
 // W = 0) for the update pass.  rho holds rho_{j-1} on entry (for j = 0 the
 // norm of the residual that v_0 was scaled by).  One block per request.
-__global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int nblk, int closing) {
+__global__ void __launch_bounds__(FT) k_arnoldi_finish(KrylovDev K, int j, int nblk, int closing) {
     const int req = blockIdx.x;
     if (!K.active[req]) return;
     __shared__ double sv[MAX_RESTART + 1], tv[MAX_RESTART + 1], col[MAX_RESTART + 1];
     __shared__ double csv[MAX_RESTART], snv[MAX_RESTART];
-    __shared__ double red[RT / 64], uu_uw[3];
+    __shared__ double red[FT / 64], uu_uw[3];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = K.m;
     const double *part = K.part + (size_t)req * (2 * m + 3) * NBLK;
     // row sums of the partials, 64 rows at a time: lane = row, the waves split
     // the blocks (fixed assignment, so the sums are deterministic)
-    __shared__ double rsum[RT / 64][64];
+    __shared__ double rsum[FT / 64][64];
     const int nrows = 2 * j + 3;
     for (int r0 = 0; r0 < nrows; r0 += 64) {
         const int row = r0 + lane;
-        constexpr int NW = RT / 64, ILP = 8;
+        constexpr int NW = FT / 64, ILP = 8;
         double a[ILP];
 #pragma unroll
         for (int u = 0; u < ILP; ++u) a[u] = 0;
@@ -1693,7 +1696,7 @@ __global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int n
         __syncthreads();
         if (wave == 0 && row < nrows) {
             double s = 0;
-            for (int w = 0; w < RT / 64; ++w) s += rsum[w][lane];
+            for (int w = 0; w < FT / 64; ++w) s += rsum[w][lane];
             if (row < j) sv[row] = s;
             else if (row < 2 * j) tv[row - j] = s;
             else uu_uw[row - 2 * j] = s;
@@ -1702,23 +1705,23 @@ __global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int n
     }
     double *hc = K.hcol + (size_t)req * (m + 1);
     double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m;
-    for (int i = threadIdx.x; i < j; i += RT) col[i] = hc[i];
-    for (int i = threadIdx.x; i + 1 < j; i += RT) {
+    for (int i = threadIdx.x; i < j; i += FT) col[i] = hc[i];
+    for (int i = threadIdx.x; i + 1 < j; i += FT) {
         csv[i] = cs[i];
         snv[i] = sn[i];
     }
     __syncthreads();
     const double rho = K.rho[req];
     double ss = 0, st = 0, tt = 0;
-    for (int i = threadIdx.x; i < j; i += RT) {
+    for (int i = threadIdx.x; i < j; i += FT) {
         ss += sv[i] * sv[i];
         st += sv[i] * tv[i];
         tt += tv[i] * tv[i];
         col[i] += rho * sv[i];
     }
-    ss = block_sum(ss, red);
-    st = block_sum(st, red);
-    tt = block_sum(tt, red);
+    ss = block_sum<FT>(ss, red);
+    st = block_sum<FT>(st, red);
+    tt = block_sum<FT>(tt, red);
     const double uu = uu_uw[0], uw = uu_uw[1], ww = uu_uw[2];
     const double r2 = uu - ss;
     const double r = (r2 > 1e-20 * uu) ? sqrt(r2) : 0.0;
@@ -1763,7 +1766,7 @@ __global__ void __launch_bounds__(RT) k_arnoldi_finish(KrylovDev K, int j, int n
     __syncthreads();
     if (red[0] != 0.0) return;
     double *hp = K.hproj + (size_t)req * (m + 1);
-    for (int i = threadIdx.x; i < j; i += RT) {
+    for (int i = threadIdx.x; i < j; i += FT) {
         hp[i] = sv[i];
         hc[i] = tv[i];
     }
@@ -2218,7 +2221,7 @@ void launch_arnoldi_dots(const KrylovDev &k, int j, int closing, hipStream_t st)
 }
 
 void launch_arnoldi_finish(const KrylovDev &k, int j, int closing, hipStream_t st) {
-    hipLaunchKernelGGL(k_arnoldi_finish, dim3(k.nb), dim3(RT), 0, st, k, j, (int)dots_blocks(k, j), closing);
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(k.nb), dim3(FT), 0, st, k, j, (int)dots_blocks(k, j), closing);
 }
 
 void launch_arnoldi_update(const KrylovDev &k, int j, hipStream_t st) {
