@@ -216,6 +216,7 @@ void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *ac
 // one block per slice does all four in LDS.
 constexpr long long XY_STAGED_BELOW = 512;
 constexpr int XY_FUSED_MAX_SIDE = 32;
+constexpr long long XY_T64_MIN_BLOCKS = 1024;  // staged products: 64 x 64 tiles from this many blocks
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
                double *data, double *min_den, double *tmp, hipStream_t st);
 // reduced-precision products (mode 1: FP32 MFMA, 2: BF16x3 MFMA); false if the slice does not fit

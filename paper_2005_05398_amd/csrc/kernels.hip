@@ -2111,7 +2111,11 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,        \
                            active, 1, tmp, data, nullptr);                                                             \
     }
-        if (side > 32) FM_SG(64) else FM_SG(32)
+        // 64 x 64 tiles reuse each operand chunk twice as often, but a small
+        // batch of wide slices then leaves the chip short of blocks
+        long long t64 = 0;
+        for (int a = 0; a < 3; ++a) t64 = std::max<long long>(t64, (long long)cdiv(pd.comp[a].x.n, 64) * cdiv(pd.comp[a].y.n, 64));
+        if (side > 32 && t64 * slices * nb >= XY_T64_MIN_BLOCKS) FM_SG(64) else FM_SG(32)
 #undef FM_SG
         (void)tiles;
         return;
