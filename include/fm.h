@@ -125,9 +125,11 @@ const char *fm_last_error(void);
  * eigendecompositions (W-bar, W, Lambda) = D(A1, A2) of eq. (WW-scale),
  * potential fields) and upload it to the device.  Complex-conjugate
  * eigenvalue pairs of the x and y pencils are kept as real 2x2 blocks.
- * Errors: FM_E_INVALID (bad description), FM_E_PENCIL (a z pencil with a
- * complex spectrum, or a diagonalisation that fails its accuracy check),
- * FM_E_NOMEM, FM_E_HIP.  *out is set only on FM_OK. */
+ * Errors: FM_E_INVALID (bad description; an exchange-reduced description
+ * also needs one spline order in x and y and one in z over the components,
+ * n_M <= 3 and 2q <= n_y <= 256), FM_E_PENCIL (a z pencil with a complex
+ * spectrum, or a diagonalisation that fails its accuracy check), FM_E_NOMEM,
+ * FM_E_HIP.  *out is set only on FM_OK. */
 fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out);
 
 /* Free a problem and its device memory.  NULL is accepted. */

@@ -562,7 +562,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
                 rx = std::max(rx, hi - lo + 1);
             }
             pd.plane_lds = std::max(pd.plane_lds, 3 * rx * p->by[a].n);
-            // x groups and the grouped tiles (stencil tile plus the x rows of its points)
+            // x groups and the grouped tiles (three planes plus the x rows of the tile's points)
             std::vector<int> xg;
             for (int i = 0; i < bx.n; ++i) {
                 const bool same = i > 0 && int(i - xg.back()) < 4 &&
@@ -655,7 +655,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         prepare_operator_lds(sizeof(double) * size_t(pd.tile_lds));
     if (p->exchange != 0 && !matvec_tiled_ok(pd))
         return "invalid: exchange-reduced problems need the tiled operator (one spline order in x, y and in z, n_M <= 3, "
-               "n_y <= 256)";
+               "2q <= n_y <= 256)";
     if (matvec_tiled_ok(pd)) {
         if (2 * p->N >= (1LL << 31)) return "problem too large for the tiled operator";
         CouplingHost ch;

@@ -139,8 +139,9 @@ struct ProblemDev {
 
 // The operator runs as two tiled kernels (coupling into a two-slot buffer, then
 // the local stencil plus that buffer) when x and y share one spline order in
-// all components, z one order, n_M <= 3, n_y <= 256 and the stencil tile fits
-// the LDS of one block; otherwise one generic kernel does everything.
+// all components, z one order, n_M <= 3, 2q <= n_y <= 256 and the operator's
+// z-contracted planes fit the LDS of one block; otherwise one generic kernel
+// does everything.
 inline bool matvec_tiled_ok(const ProblemDev &pd) {
     const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
     bool rows_fit = true;                // one block of 256 threads covers the y points

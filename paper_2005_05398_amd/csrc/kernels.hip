@@ -219,10 +219,10 @@ __global__ void __launch_bounds__(256) k_matvec(const ProblemDev *__restrict__ p
 // ---------------------------------------------------------------------------
 // Operator, tiled: one block per (request, component, z point, XT consecutive
 // x points); threads cover the tile's (x, y) points.  The coefficients of the
-// tile's local stencil (z support x x support x all y) are staged in LDS once
-// per M' block.  The coupling comes from the two-slot buffer that the coupling
-// kernel filled before.  Q*: spline orders (2 cubic, 3 quintic); NM: number of
-// M' blocks.
+// tile's local stencil are read once per M' block and contracted with the
+// block's z row on the way into LDS (three planes over x support x all y).
+// The coupling comes from the two-slot buffer that the coupling kernel filled
+// before.  Q*: spline orders (2 cubic, 3 quintic); NM: number of M' blocks.
 // n_M = 1: one thread per (x group, y point).  A block covers one z point, so
 // the coefficients are contracted with that point's z row (value, first and
 // second derivative) as they are read: LDS holds three planes over (x support
