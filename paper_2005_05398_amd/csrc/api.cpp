@@ -662,6 +662,8 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         err = build_coupling(p, hf, ch);
         if (!err.empty()) return err;
         pd.cpl.ntasks = ch.ntasks;
+        pd.cpl.njobs = ch.njobs;
+        pd.cpl.job = put(p, ch.job, err);
         pd.cpl.npairs = ch.npairs;
         pd.cpl.task = put(p, ch.task, err);
         pd.cpl.r = put(p, ch.r, err);

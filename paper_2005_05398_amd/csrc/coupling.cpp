@@ -198,6 +198,22 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                 }
     }
     ch.ntasks = int(ch.task.size() / CPL_TASK);
+    // wave jobs: with one M'' block, two consecutive tasks (neighbouring cells)
+    // of at most 32 pairs share a wave, one per half, each with its own cell
+    // (so cells with few pairs do not leave most of a wave idle)
+    ch.job.clear();
+    for (int t = 0; t < ch.ntasks; ++t) {
+        const int c0 = ch.task[size_t(t) * CPL_TASK + CT_COUNT];
+        if (nM == 1 && c0 <= 32 && t + 1 < ch.ntasks && ch.task[size_t(t + 1) * CPL_TASK + CT_COUNT] <= 32) {
+            ch.job.push_back(t);
+            ch.job.push_back(t + 1);
+            ++t;
+        } else {
+            ch.job.push_back(t);
+            ch.job.push_back(-1);
+        }
+    }
+    ch.njobs = int(ch.job.size() / 2);
     return "";
 }
 

@@ -110,6 +110,8 @@ enum {
 
 struct CouplingDev {
     int ntasks;
+    int njobs;                   // wave jobs: one task, or two of <= 32 pairs (one per half-wave)
+    const int *job;              // [njobs][2]: first task, second task or -1
     long long npairs;
     const int *task;             // [ntasks][CPL_TASK] records (layout above)
     const double *r;             // [ntasks][3] cell width / hbar in z, x, y

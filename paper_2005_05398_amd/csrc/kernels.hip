@@ -532,11 +532,13 @@ constexpr int CPL_WAVES = 4;         // waves per block of the coupling kernel
 constexpr int CPL_REQ = 16;          // requests per block (grid y covers the rest)
 
 // Coupling term of the operator for the pairs of one (beta, cell) task per
-// wave: the wave stages the cell's (2QZ x 2QXY x 2QXY) coefficients of every
-// M'' block of one request in LDS (zero for dropped functions), then each lane
+// wave, or, with one M'' block, of two tasks of at most 32 pairs, one per half
+// of the wave (a host-built job list pairs neighbouring cells): the wave
+// stages each cell's (2QZ x 2QXY x 2QXY) coefficients of every M'' block of
+// one request in LDS (zero for dropped functions), then each lane
 // evaluates beta's expansion at its pair's image by the separable sum
 // sum_c v_z[c] sum_a v_x[a] sum_b v_y[b] coef[c][a][b] (LDS reads are the same
-// for the whole wave) and writes F val to cbuf[request][slot][alpha point].
+// for all lanes of a cell) and writes F val to cbuf[request][slot][alpha point].
 // The basis values and factors of a pair stay in registers over the requests.
 template <int QXY, int QZ, int NM>
 __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const ProblemDev *__restrict__ pd,
@@ -544,29 +546,35 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
                                                                    const double *__restrict__ X,
                                                                    double *__restrict__ cbuf) {
     constexpr int RXY = 2 * QXY, RZ = 2 * QZ, TS = RZ * RXY * RXY;
-    __shared__ __align__(16) double tile[CPL_WAVES][NM * TS];
-    __shared__ int fidx[CPL_WAVES][RZ + 2 * RXY];
+    // one M'' block: a wave may hold two cells, one per half (a tile each)
+    constexpr int HALVES = NM == 1 ? 2 : 1;
+    __shared__ __align__(16) double tile[CPL_WAVES][HALVES][NM * TS];
+    __shared__ int fidx[CPL_WAVES][HALVES][RZ + 2 * RXY];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const CouplingDev &cp = pd->cpl;
-    // XCD-aware order: consecutive tasks (neighbouring cells) on one XCD's L2
+    // XCD-aware order: consecutive jobs (neighbouring cells) on one XCD's L2
     const int nblk = gridDim.x, xcd = blockIdx.x % 8, per = (nblk + 7) / 8;
     const int full = nblk % 8 == 0 ? 8 : nblk % 8;     // XCDs that get `per` blocks
     const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
-    const int task = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
-    if (task >= cp.ntasks) return;                     // the whole wave (no block barriers)
-    // the task record (wave-uniform): the cell's function indices and beta's
-    // sizes come with it, so the fetch of the cell's coefficients and the
-    // pairs' data wait for this one read only
+    const int job = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
+    if (job >= cp.njobs) return;                       // the whole wave (no block barriers)
+    const int taskA = __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job]);
+    const int taskB = __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job + 1]);
+    const bool dual = HALVES == 2 && taskB >= 0;       // wave-uniform
+    const int half = dual ? lane >> 5 : 0, li = dual ? lane & 31 : lane;
+    const int W = dual ? 32 : 64;                      // lanes per cell
+    const int task = half ? taskB : taskA;
+    // the task record: the cell's function indices and beta's sizes come with
+    // it, so the fetch of the cell's coefficients and the pairs' data wait for
+    // this one read only
     const int *t = cp.task + (size_t)task * CPL_TASK;
-    const int count = __builtin_amdgcn_readfirstlane(t[CT_COUNT]);
-    const long long first = __builtin_amdgcn_readfirstlane(t[CT_FIRST]);
-    const int bnx = __builtin_amdgcn_readfirstlane(t[CT_NX]), bny = __builtin_amdgcn_readfirstlane(t[CT_NY]);
-    const int bnpts = __builtin_amdgcn_readfirstlane(t[CT_NPTS]);
-    const long long boff = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(t[CT_OFF_HI]) << 32) |
-                                       (unsigned)__builtin_amdgcn_readfirstlane(t[CT_OFF_LO]));
-    if (lane < RZ + 2 * RXY) fidx[wave][lane] = t[CT_FIDX + lane];
-    const bool mine = lane < count;
-    const long long pr = first + lane;
+    const int count = t[CT_COUNT];
+    const long long first = t[CT_FIRST];
+    const int bnx = t[CT_NX], bny = t[CT_NY], bnpts = t[CT_NPTS];
+    const long long boff = (long long)(((unsigned long long)(unsigned)t[CT_OFF_HI] << 32) | (unsigned)t[CT_OFF_LO]);
+    if (li < RZ + 2 * RXY) fidx[wave][half][li] = t[CT_FIDX + li];
+    const bool mine = li < count;
+    const long long pr = first + li;
     double vz[RZ], vx[RXY], vy[RXY], F[NM * NM];
     int outp = 0, slot = 0, npa = 0;
     if (mine) {
@@ -585,19 +593,20 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     }
     const long long N = pd->N;
     const int r0 = blockIdx.y * CPL_REQ, r1 = min(nb, r0 + CPL_REQ);
-    // this lane's tile entries (e = lane + 64 q): offsets into beta's block of
-    // one request, -1 for a dropped function; worked out once for all requests
-    constexpr int EPL = (NM * TS + 63) / 64;
+    // this lane's tile entries (e = li + W q): offsets into beta's block of one
+    // request, -1 for a dropped function or past the tile; worked out once for
+    // all requests
+    constexpr int EPL = HALVES == 2 ? (NM * TS + 31) / 32 : (NM * TS + 63) / 64;
     int goff[EPL];
     wave_sync();                                       // fidx written
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
-        const int e = lane + 64 * q;
+        const int e = li + W * q;
         goff[q] = -1;
         if (e < NM * TS) {
             const int iM = e / TS, rem = e - iM * TS;
             const int c = rem / (RXY * RXY), a = (rem / RXY) % RXY, bq = rem % RXY;
-            const int gz = fidx[wave][c], gx = fidx[wave][RZ + a], gy = fidx[wave][RZ + RXY + bq];
+            const int gz = fidx[wave][half][c], gx = fidx[wave][half][RZ + a], gy = fidx[wave][half][RZ + RXY + bq];
             if (gz >= 0 && gx >= 0 && gy >= 0) goff[q] = iM * bnpts + (gz * bnx + gx) * bny + gy;
         }
     }
@@ -622,8 +631,8 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
         wave_sync();                                   // the previous tile is read
 #pragma unroll
         for (int q = 0; q < EPL; ++q) {
-            const int e = lane + 64 * q;
-            if (e < NM * TS) tile[wave][e] = pf[q];
+            const int e = li + W * q;
+            if (e < NM * TS) tile[wave][half][e] = pf[q];
         }
         wave_sync();                                   // this tile is written
         if (nxt < r1) fetch(nxt);
@@ -631,7 +640,7 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
             double val[NM];
 #pragma unroll
             for (int iM = 0; iM < NM; ++iM) {
-                const double *T = tile[wave] + iM * TS;
+                const double *T = tile[wave][half] + iM * TS;
                 double acc = 0;
 #pragma unroll
                 for (int c = 0; c < RZ; ++c) {
@@ -1996,8 +2005,8 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 template <int QXY, int QZ, int NM>
 void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
                   double *cbuf, hipStream_t st, int part) {
-    if (part != 1 && pd.cpl.ntasks > 0) {
-        dim3 grid(cdiv(pd.cpl.ntasks, CPL_WAVES), cdiv(nb, CPL_REQ));
+    if (part != 1 && pd.cpl.njobs > 0) {
+        dim3 grid(cdiv(pd.cpl.njobs, CPL_WAVES), cdiv(nb, CPL_REQ));
         hipLaunchKernelGGL((k_coupling_cells<QXY, QZ, NM>), grid, dim3(64 * CPL_WAVES), 0, st, pd.dev, active, nb, x,
                            cbuf);
     }
