@@ -2246,7 +2246,10 @@ void launch_arnoldi_update(const KrylovDev &k, int j, hipStream_t st) {
 }
 
 unsigned reduce_blocks(const KrylovDev &k) {
-    long long nblk = std::max<long long>(cdiv(1024, k.nb), cdiv(k.N, (long long)RT * 16));
+    // every block of a request takes a ticket on one counter when it is done:
+    // about 256 blocks over the batch when it is small (1024 serialised
+    // tickets cost a single request ~50 us), 32 elements per thread otherwise
+    long long nblk = std::max<long long>(cdiv(256, k.nb), cdiv(k.N, (long long)RT * 32));
     return (unsigned)std::max<long long>(1, std::min<long long>(NBLK, nblk));
 }
 
