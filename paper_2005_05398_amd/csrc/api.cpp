@@ -663,6 +663,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         if (!err.empty()) return err;
         pd.cpl.ntasks = ch.ntasks;
         pd.cpl.njobs = ch.njobs;
+        pd.cpl.pairs_per_lane = ch.pairs_per_lane;
         pd.cpl.job = put(p, ch.job, err);
         pd.cpl.npairs = ch.npairs;
         pd.cpl.task = put(p, ch.task, err);

@@ -198,18 +198,23 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                 }
     }
     ch.ntasks = int(ch.task.size() / CPL_TASK);
-    // wave jobs: with one M'' block, two consecutive tasks (neighbouring cells)
-    // of at most 32 pairs share a wave, one per half, each with its own cell
-    // (so cells with few pairs do not leave most of a wave idle)
+    // wave jobs.  With one M'' block, two consecutive tasks (neighbouring cells)
+    // share a wave, one per half: when the tasks average more than 40 pairs,
+    // every two, with up to two pairs per lane (each staged coefficient then
+    // feeds two products); otherwise two of at most 32 pairs, one pair per lane
+    // (fewer registers; cells with few pairs still fill a wave).  With more M''
+    // blocks, one task per wave.
     ch.job.clear();
+    ch.pairs_per_lane = (nM == 1 && ch.ntasks > 0 && np > 40LL * ch.ntasks) ? 2 : 1;
+    auto cnt = [&](int t) { return ch.task[size_t(t) * CPL_TASK + CT_COUNT]; };
     for (int t = 0; t < ch.ntasks; ++t) {
-        const int c0 = ch.task[size_t(t) * CPL_TASK + CT_COUNT];
-        if (nM == 1 && c0 <= 32 && t + 1 < ch.ntasks && ch.task[size_t(t + 1) * CPL_TASK + CT_COUNT] <= 32) {
-            ch.job.push_back(t);
+        ch.job.push_back(t);
+        const bool pair = nM == 1 && t + 1 < ch.ntasks &&
+                          (ch.pairs_per_lane == 2 || (cnt(t) <= 32 && cnt(t + 1) <= 32));
+        if (pair) {
             ch.job.push_back(t + 1);
             ++t;
         } else {
-            ch.job.push_back(t);
             ch.job.push_back(-1);
         }
     }

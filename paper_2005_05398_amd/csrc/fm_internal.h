@@ -110,7 +110,8 @@ enum {
 
 struct CouplingDev {
     int ntasks;
-    int njobs;                   // wave jobs: one task, or two of <= 32 pairs (one per half-wave)
+    int njobs;                   // wave jobs: one task, or (one M'' block) two, one per half-wave
+    int pairs_per_lane;          // 2: every job two tasks of <= 64 pairs; 1: paired tasks have <= 32
     const int *job;              // [njobs][2]: first task, second task or -1
     long long npairs;
     const int *task;             // [ntasks][CPL_TASK] records (layout above)

@@ -20,6 +20,7 @@ struct CouplingHost {
     std::vector<int> task, out;  // task: [ntasks][CPL_TASK] records
     std::vector<int> job;        // [njobs][2] wave jobs (second task -1 for a single one)
     int njobs = 0;
+    int pairs_per_lane = 1;
     std::vector<double> s, F, r; // r: [ntasks][3] cell width / hbar (z, x, y)
     long long npairs = 0;
     int ntasks = 0;

@@ -531,23 +531,27 @@ __device__ __forceinline__ void wave_sync() {
 constexpr int CPL_WAVES = 4;         // waves per block of the coupling kernel
 constexpr int CPL_REQ = 16;          // requests per block (grid y covers the rest)
 
-// Coupling term of the operator for the pairs of one (beta, cell) task per
-// wave, or, with one M'' block, of two tasks of at most 32 pairs, one per half
-// of the wave (a host-built job list pairs neighbouring cells): the wave
-// stages each cell's (2QZ x 2QXY x 2QXY) coefficients of every M'' block of
-// one request in LDS (zero for dropped functions), then each lane
-// evaluates beta's expansion at its pair's image by the separable sum
+// Coupling term of the operator for the pairs of (beta, cell) tasks.  With one
+// M'' block a wave may take two tasks (neighbouring cells, from a host-built
+// job list), one per half: P = 2, each lane up to two of its cell's pairs
+// (pairs l and l + 32 of the task), so that each staged coefficient feeds two
+// products (chosen when the tasks average more than 40 pairs); P = 1, two tasks
+// of at most 32 pairs, one pair per lane.  Otherwise one task per wave, one
+// pair per lane.  The wave stages
+// each cell's (2QZ x 2QXY x 2QXY) coefficients of every M'' block of one
+// request in LDS (zero for dropped functions), then each lane evaluates beta's
+// expansion at its pairs' images by the separable sum
 // sum_c v_z[c] sum_a v_x[a] sum_b v_y[b] coef[c][a][b] (LDS reads are the same
 // for all lanes of a cell) and writes F val to cbuf[request][slot][alpha point].
 // The basis values and factors of a pair stay in registers over the requests.
-template <int QXY, int QZ, int NM>
+template <int QXY, int QZ, int NM, int P>
 __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const ProblemDev *__restrict__ pd,
                                                                    const int *__restrict__ active, int nb,
                                                                    const double *__restrict__ X,
                                                                    double *__restrict__ cbuf) {
+    static_assert(P == 1 || NM == 1, "two pairs per lane only with one M'' block");
     constexpr int RXY = 2 * QXY, RZ = 2 * QZ, TS = RZ * RXY * RXY;
-    // one M'' block: a wave may hold two cells, one per half (a tile each)
-    constexpr int HALVES = NM == 1 ? 2 : 1;
+    constexpr int HALVES = NM == 1 ? 2 : 1;            // cells a wave may hold
     __shared__ __align__(16) double tile[CPL_WAVES][HALVES][NM * TS];
     __shared__ int fidx[CPL_WAVES][HALVES][RZ + 2 * RXY];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -558,44 +562,57 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
     const int job = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
     if (job >= cp.njobs) return;                       // the whole wave (no block barriers)
-    const int taskA = __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job]);
-    const int taskB = __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job + 1]);
-    const bool dual = HALVES == 2 && taskB >= 0;       // wave-uniform
-    const int half = dual ? lane >> 5 : 0, li = dual ? lane & 31 : lane;
-    const int W = dual ? 32 : 64;                      // lanes per cell
-    const int task = half ? taskB : taskA;
+    // two cells (one per half) with two pairs per lane always, with one pair per
+    // lane when the job names a second task; else one cell over the wave
+    const bool split = HALVES == 2 && (P == 2 || __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job + 1]) >= 0);
+    const int W = split ? 32 : 64;                     // lanes per cell
+    const int half = split ? lane >> 5 : 0, li = split ? lane & 31 : lane;
+    const int task = cp.job[2 * (size_t)job + half];   // -1: this half has no task
+    const bool has = task >= 0;
     // the task record: the cell's function indices and beta's sizes come with
     // it, so the fetch of the cell's coefficients and the pairs' data wait for
     // this one read only
-    const int *t = cp.task + (size_t)task * CPL_TASK;
-    const int count = t[CT_COUNT];
+    const int *t = cp.task + (size_t)(has ? task : 0) * CPL_TASK;
+    const int count = has ? t[CT_COUNT] : 0;
     const long long first = t[CT_FIRST];
     const int bnx = t[CT_NX], bny = t[CT_NY], bnpts = t[CT_NPTS];
     const long long boff = (long long)(((unsigned long long)(unsigned)t[CT_OFF_HI] << 32) | (unsigned)t[CT_OFF_LO]);
     if (li < RZ + 2 * RXY) fidx[wave][half][li] = t[CT_FIDX + li];
-    const bool mine = li < count;
-    const long long pr = first + li;
-    double vz[RZ], vx[RXY], vy[RXY], F[NM * NM];
-    int outp = 0, slot = 0, npa = 0;
-    if (mine) {
-        hermite_cell<QZ>(cp.s[pr], cp.r[3 * (size_t)task], vz);
-        hermite_cell<QXY>(cp.s[cp.npairs + pr], cp.r[3 * (size_t)task + 1], vx);
-        hermite_cell<QXY>(cp.s[2 * cp.npairs + pr], cp.r[3 * (size_t)task + 2], vy);
+    bool mine[P];
+    double vz[P][RZ], vx[P][RXY], vy[P][RXY], F[P][NM * NM];
+    int outp[P], slot[P], npa[P];
 #pragma unroll
-        for (int f = 0; f < NM * NM; ++f) F[f] = cp.F[(size_t)f * cp.npairs + pr];
-        const int o = cp.out[pr];
-        outp = o >> 1;
-        slot = o & 1;
-        // the point's own component, from its offset (an exchange-reduced problem
-        // reads partner 2 from component 1, so beta alone does not fix it)
-        const int a = outp >= pd->comp[2].off ? 2 : (outp >= pd->comp[1].off ? 1 : 0);
-        npa = pd->comp[a].npts;
+    for (int p = 0; p < P; ++p) {
+        const long long pr = first + li + W * p;
+        mine[p] = li + W * p < count;
+        outp[p] = slot[p] = npa[p] = 0;
+        if (mine[p]) {
+            hermite_cell<QZ>(cp.s[pr], cp.r[3 * (size_t)task], vz[p]);
+            hermite_cell<QXY>(cp.s[cp.npairs + pr], cp.r[3 * (size_t)task + 1], vx[p]);
+            hermite_cell<QXY>(cp.s[2 * cp.npairs + pr], cp.r[3 * (size_t)task + 2], vy[p]);
+#pragma unroll
+            for (int f = 0; f < NM * NM; ++f) F[p][f] = cp.F[(size_t)f * cp.npairs + pr];
+            const int o = cp.out[pr];
+            outp[p] = o >> 1;
+            slot[p] = o & 1;
+            // the point's own component, from its offset (an exchange-reduced
+            // problem reads partner 2 from component 1, so beta alone does not fix it)
+            const int a = outp[p] >= pd->comp[2].off ? 2 : (outp[p] >= pd->comp[1].off ? 1 : 0);
+            npa[p] = pd->comp[a].npts;
+        } else {
+#pragma unroll
+            for (int u = 0; u < RZ; ++u) vz[p][u] = 0.0;
+#pragma unroll
+            for (int u = 0; u < RXY; ++u) vx[p][u] = vy[p][u] = 0.0;
+#pragma unroll
+            for (int f = 0; f < NM * NM; ++f) F[p][f] = 0.0;
+        }
     }
     const long long N = pd->N;
     const int r0 = blockIdx.y * CPL_REQ, r1 = min(nb, r0 + CPL_REQ);
     // this lane's tile entries (e = li + W q): offsets into beta's block of one
-    // request, -1 for a dropped function or past the tile; worked out once for
-    // all requests
+    // request, -1 for a dropped function, past the tile or without a task;
+    // worked out once for all requests
     constexpr int EPL = HALVES == 2 ? (NM * TS + 31) / 32 : (NM * TS + 63) / 64;
     int goff[EPL];
     wave_sync();                                       // fidx written
@@ -603,7 +620,7 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     for (int q = 0; q < EPL; ++q) {
         const int e = li + W * q;
         goff[q] = -1;
-        if (e < NM * TS) {
+        if (has && e < NM * TS) {
             const int iM = e / TS, rem = e - iM * TS;
             const int c = rem / (RXY * RXY), a = (rem / RXY) % RXY, bq = rem % RXY;
             const int gz = fidx[wave][half][c], gx = fidx[wave][half][RZ + a], gy = fidx[wave][half][RZ + RXY + bq];
@@ -636,35 +653,55 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
         }
         wave_sync();                                   // this tile is written
         if (nxt < r1) fetch(nxt);
-        if (mine) {
-            double val[NM];
+        if (mine[0]) {
+            double val[P][NM];
 #pragma unroll
             for (int iM = 0; iM < NM; ++iM) {
                 const double *T = tile[wave][half] + iM * TS;
-                double acc = 0;
+                double acc[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) acc[p] = 0;
 #pragma unroll
                 for (int c = 0; c < RZ; ++c) {
-                    double accx = 0;
+                    double accx[P];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) accx[p] = 0;
 #pragma unroll
                     for (int a = 0; a < RXY; ++a) {
                         const double *row = T + (c * RXY + a) * RXY;
-                        double accy = 0;
+                        double accy[P];
 #pragma unroll
-                        for (int bq = 0; bq < RXY; ++bq) accy += vy[bq] * row[bq];
-                        accx += vx[a] * accy;
+                        for (int p = 0; p < P; ++p) accy[p] = 0;
+#pragma unroll
+                        for (int bq = 0; bq < RXY; ++bq) {
+                            const double cf = row[bq];
+#pragma unroll
+                            for (int p = 0; p < P; ++p) accy[p] += vy[p][bq] * cf;
+                        }
+#pragma unroll
+                        for (int p = 0; p < P; ++p) accx[p] += vx[p][a] * accy[p];
+                        // the row's products complete before the next row's reads
+                        // issue (all of a tile's reads at once exhaust the registers)
+                        if (P == 2) asm volatile("" : "+v"(accx[0]), "+v"(accx[P - 1]) : : "memory");
                     }
-                    acc += vz[c] * accx;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) acc[p] += vz[p][c] * accx[p];
                 }
-                val[iM] = acc;
-            }
-            double *y = cbuf + ((long long)req * 2 + slot) * N + outp;
 #pragma unroll
-            for (int iM = 0; iM < NM; ++iM) {
-                double o = 0;
-#pragma unroll
-                for (int jM = 0; jM < NM; ++jM) o += F[iM * NM + jM] * val[jM];
-                y[(long long)iM * npa] = o;
+                for (int p = 0; p < P; ++p) val[p][iM] = acc[p];
             }
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (mine[p]) {
+                    double *y = cbuf + ((long long)req * 2 + slot[p]) * N + outp[p];
+#pragma unroll
+                    for (int iM = 0; iM < NM; ++iM) {
+                        double o = 0;
+#pragma unroll
+                        for (int jM = 0; jM < NM; ++jM) o += F[p][iM * NM + jM] * val[p][jM];
+                        y[(long long)iM * npa[p]] = o;
+                    }
+                }
         }
         req = nxt;
     }
@@ -2010,8 +2047,12 @@ void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *
                   double *cbuf, hipStream_t st, int part) {
     if (part != 1 && pd.cpl.njobs > 0) {
         dim3 grid(cdiv(pd.cpl.njobs, CPL_WAVES), cdiv(nb, CPL_REQ));
-        hipLaunchKernelGGL((k_coupling_cells<QXY, QZ, NM>), grid, dim3(64 * CPL_WAVES), 0, st, pd.dev, active, nb, x,
-                           cbuf);
+        if (NM == 1 && pd.cpl.pairs_per_lane == 2)
+            hipLaunchKernelGGL((k_coupling_cells<QXY, QZ, NM, NM == 1 ? 2 : 1>), grid, dim3(64 * CPL_WAVES), 0, st, pd.dev,
+                               active, nb, x, cbuf);
+        else
+            hipLaunchKernelGGL((k_coupling_cells<QXY, QZ, NM, 1>), grid, dim3(64 * CPL_WAVES), 0, st, pd.dev, active, nb, x,
+                               cbuf);
     }
     if (part != 2) {
         if (NM == 1) {
