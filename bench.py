@@ -27,10 +27,10 @@ FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector and matrix
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 WORKLOAD_TEXT = {
-    "cfg2": "H- energy scan, L=0, quintic 64x64x24, x,y in [0,40] quadratic, 32 energies in [-0.6,-0.1], "
-            "seeded N(0,1) RHS",
-    "cfg3": "Ps- like (1,1,1)/(+1,-1,-1), L=0, quintic x,y 127 on [0,20] x cubic z 32, E=-0.25, seeded RHS",
-    "cfg4": "Ps- like, L=2 tau=+1 (3 M' blocks), quintic x,y 97 on [0,20] x cubic z 32, E=-0.2, seeded RHS",
+    "hminus_scan": "H- energy scan, L=0, quintic 64x64x24, x,y in [0,40] quadratic, 32 energies in [-0.6,-0.1], "
+                   "seeded N(0,1) RHS",
+    "ps_q127": "Ps- like (1,1,1)/(+1,-1,-1), L=0, quintic x,y 127 on [0,20] x cubic z 32, E=-0.25, seeded RHS",
+    "ps_l2_q97": "Ps- like, L=2 tau=+1 (3 M' blocks), quintic x,y 97 on [0,20] x cubic z 32, E=-0.2, seeded RHS",
 }
 sys.path.insert(0, ROOT)
 
@@ -48,7 +48,7 @@ def cpu_baseline(seconds_cap=30.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    c = W.cfg2()
+    c = W.hminus_scan()
     d = W.make_desc(*W.H_MINUS, 22, 9, deg_xy=5, deg_z=5, R=40.0, xy_map="quadratic")
     O = OracleProblem(d)
     n_done = 0
@@ -165,7 +165,7 @@ def serve_bench(args):
     from paper_2005_05398_amd import fm
     from paper_2005_05398_amd import workloads as W
 
-    reqs = [W.cfg5_request(i) for i in range(args.requests)]
+    reqs = [W.serving_request(i) for i in range(args.requests)]
     for r in reqs:                      # the preconditioner variant of the L > 0 requests
         if r["desc"]["J"] > 0:
             r["desc"] = dict(r["desc"], precond=args.serve_precond)
@@ -207,7 +207,7 @@ def serve_bench(args):
     print(f"serve saturation: {nsat} requests in {sat_wall:.1f} s ({sat_rate:.2f} solves/s)", file=sys.stderr,
           flush=True)
     rate = 0.8 * sat_rate
-    arrivals = W.cfg5_arrivals(len(reqs), rate)
+    arrivals = W.serving_arrivals(len(reqs), rate)
     done, wall = run(list(range(len(reqs))), arrivals, "poisson")
     stats = srv.stats()
     srv.close()
@@ -259,7 +259,7 @@ def traffic_variant(args):
         v += f"-{args.precond}"
     if args.prec != "fp64":
         v += f"-{args.prec}"
-    if args.restart != (300 if args.workload == "cfg2" else 60):
+    if args.restart != (300 if args.workload == "hminus_scan" else 60):
         v += f"-restart{args.restart}"
     return v
 
@@ -288,8 +288,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--restart", type=int, default=None, help="default: 300 (cfg2), 60 (cfg3, cfg4)")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--restart", type=int, default=None, help="default: 300 (hminus_scan), 60 (ps_q127, ps_l2_q97)")
+    ap.add_argument("--workload", default="hminus_scan", choices=["hminus_scan", "ps_q127", "ps_l2_q97"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--exchange", type=int, default=0, choices=[-1, 0, 1],
                     help="solve only the part of parity p under exchange of particles 1 and 2 (H- scan: the "
@@ -315,7 +315,7 @@ def main():
                     help="run one plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
+        print("bench.py: the solver runs on exactly one GPU (there is no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.serve:
@@ -335,10 +335,10 @@ def main():
     from paper_2005_05398_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    c = W.CONFIGS[args.workload]()
+    c = W.WORKLOADS[args.workload]()
     desc, Es, seeds = c["desc"], c["E"], c["seeds"]
     if args.restart is None:
-        args.restart = 300 if args.workload == "cfg2" else 60
+        args.restart = 300 if args.workload == "hminus_scan" else 60
     t_setup = time.perf_counter()
     if args.exchange:
         desc = dict(desc, exchange=args.exchange)
@@ -403,7 +403,7 @@ def main():
                  "traffic": measured_traffic(traffic_variant(args), dom)})
     total_kernel_ms = sum(v["ms"] for v in prof.values())
     line = {
-        "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "cfg2"
+        "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "hminus_scan"
                    else f"solves/s to rel. residual 1e-10 ({args.workload})"),
         "value": value,
         "unit": "solves/s",
@@ -452,7 +452,7 @@ def main():
                            "max_rel_residual": max(r["rel_residual"] for r in res_lp),
                            "max_rel_error_vs_fp64_gpu": err}
         line["mixed_precision"] = mixed
-    if not args.no_cpu_baseline and args.workload == "cfg2":
+    if not args.no_cpu_baseline and args.workload == "hminus_scan":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))
 

@@ -8,7 +8,7 @@ three functions per node, support of two intervals, node maps, collocation
 at Gaussian points).  Cubic Hermite splines (two functions per node) are the
 same construction with q = 2.
 
-Readings taken where the paper is silent (listed in the design doc):
+Readings taken where the paper is silent:
   * q Gauss-Legendre points per interval; the shape functions are derived here
     by solving the Hermite interpolation conditions in the monomial basis.
   * x, y closure (Dirichlet): drop the value function at both ends.  Cubic:

@@ -57,36 +57,36 @@ PS_MINUS = ((1.0, 1.0, 1.0), (1.0, -1.0, -1.0))       # e+ e- e- : particles 2, 
 H_MINUS = ((1.0, 1.0, 1836.0), (-1.0, -1.0, 1.0))     # e- e- p  : particles 1, 2 identical
 
 
-def cfg1():
+def ps_cubic16():
     """FP64, L=0, cubic 16 x 16 x 8 on [0,20]^2 x [-1,1], E=-0.25, one RHS."""
     d = make_desc(*PS_MINUS, 16, 8, deg_xy=3, deg_z=3, R=20.0)
-    return {"name": "cfg1_cubic_16x16x8_L0", "desc": d, "E": [-0.25], "seeds": [1001]}
+    return {"name": "ps_cubic_16x16x8_L0", "desc": d, "E": [-0.25], "seeds": [1001]}
 
 
-def cfg2():
+def hminus_scan():
     """FP64, L=0, quintic 64 x 64 x 24, x,y in [0,40] graded quadratically
     toward 0, energy scan of 32 values in [-0.6, -0.1], one RHS per energy."""
     d = make_desc(*H_MINUS, 64, 24, deg_xy=5, deg_z=5, R=40.0, xy_map="quadratic")
     E = list(np.linspace(-0.6, -0.1, 32))
-    return {"name": "cfg2_quintic_64x64x24_L0_scan32", "desc": d, "E": E,
+    return {"name": "hminus_quintic_64x64x24_L0_scan32", "desc": d, "E": E,
             "seeds": [2001 + i for i in range(32)]}
 
 
-def cfg3():
+def ps_q127():
     """Mixed precision, L=0, quintic x,y (nominal 128, taken as 127 = 3*42+1,
     uniform on [0,20]) x cubic z 32."""
     d = make_desc(*PS_MINUS, admissible_xy(128), 32, deg_xy=5, deg_z=3, R=20.0)
-    return {"name": "cfg3_quintic128_cubicz32_L0", "desc": d, "E": [-0.25], "seeds": [3001]}
+    return {"name": "ps_quintic127_cubicz32_L0", "desc": d, "E": [-0.25], "seeds": [3001]}
 
 
-def cfg4():
+def ps_l2_q97():
     """L=2, tau=+1 (three M' blocks), quintic x,y (nominal 96, taken as
     97 = 3*32+1) x cubic z 32, E=-0.2."""
     d = make_desc(*PS_MINUS, admissible_xy(96), 32, J=2, tau=1, deg_xy=5, deg_z=3, R=20.0)
-    return {"name": "cfg4_L2_quintic96_cubicz32", "desc": d, "E": [-0.2], "seeds": [4001]}
+    return {"name": "ps_L2_quintic97_cubicz32", "desc": d, "E": [-0.2], "seeds": [4001]}
 
 
-CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}
+WORKLOADS = {"ps_cubic16": ps_cubic16, "hminus_scan": hminus_scan, "ps_q127": ps_q127, "ps_l2_q97": ps_l2_q97}
 
 
 # Helium with an infinitely heavy nucleus (1e15 a.u.), the runs of Sec. 4:
@@ -131,7 +131,7 @@ def helium_desc(g1, g3, dom1=HE_TABLE3_DOMAINS[0], dom3=HE_TABLE3_DOMAINS[1], J=
             "x0": 1.0, "y0": INF, "nu": 2.01, "vhat": 0}
 
 
-def cfg5_request(i):
+def serving_request(i):
     """Request i of the serving stream (seed 5001 + i): nominal x,y size in
     {32, 64, 96, 128} (quintic, taken to the nearest 3K+1), cubic z in
     {8, 16, 32}, L in {0, 1, 2} with tau = +1, E uniform in [-0.6, -0.05], and
@@ -150,7 +150,7 @@ def cfg5_request(i):
     return {"desc": desc, "E": E, "seed": 5001 + i, "nominal": {"nxy": nxy, "nz": nz, "L": L, "heavy": heavy}}
 
 
-def cfg5_arrivals(n, rate):
+def serving_arrivals(n, rate):
     """Poisson arrival times (seconds from start) of n requests at `rate` per second."""
     gaps = np.random.Generator(np.random.PCG64(5000)).exponential(1.0 / rate, n)
     return np.cumsum(gaps) - gaps[0]

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def ns(**kw):
-    d = dict(workload="cfg2", exchange=0, precond="block_jacobi", prec="fp64", restart=300)
+    d = dict(workload="hminus_scan", exchange=0, precond="block_jacobi", prec="fp64", restart=300)
     d.update(kw)
     return argparse.Namespace(**d)
 
@@ -25,11 +25,11 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_variant_names_every_option_that_changes_the_kernels():
-    assert bench.traffic_variant(ns()) == "cfg2"
-    assert bench.traffic_variant(ns(workload="cfg3", restart=60)) == "cfg3"
+    assert bench.traffic_variant(ns()) == "hminus_scan"
+    assert bench.traffic_variant(ns(workload="ps_q127", restart=60)) == "ps_q127"
     seen = {bench.traffic_variant(v) for v in (ns(exchange=1), ns(exchange=-1), ns(precond="coupled"),
                                                 ns(prec="fp32"), ns(restart=200))}
-    assert len(seen) == 5 and "cfg2" not in seen
+    assert len(seen) == 5 and "hminus_scan" not in seen
 
 
 def test_counter_records_apply_only_to_their_own_configuration(tmp_path, monkeypatch):
@@ -37,7 +37,7 @@ def test_counter_records_apply_only_to_their_own_configuration(tmp_path, monkeyp
     src.write_text("// kernels\n")
     import hashlib
     sha = hashlib.sha256(src.read_bytes()).hexdigest()
-    rec = {"entries": {"cfg2:mdot": {"kernels_hip_sha256": sha, "hbm_bytes_per_launch": 123.0}}}
+    rec = {"entries": {"hminus_scan:mdot": {"kernels_hip_sha256": sha, "hbm_bytes_per_launch": 123.0}}}
     tf = tmp_path / "hbm_traffic.json"
     tf.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tf))

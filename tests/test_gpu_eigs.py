@@ -33,7 +33,7 @@ def helium(nxy, nz, J=0, tau=1, deg_z=5, R=15.0):
 
 
 MASS_CASES = [
-    ("cfg1", W.cfg1()["desc"]),
+    ("ps_cubic16", W.ps_cubic16()["desc"]),
     ("quintic_L2_7x7x4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_xy=5, deg_z=3, R=15.0)),
     ("hminus_mixed_grids", dict(W.make_desc(*W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"),
                                 y=W.make_desc(*W.H_MINUS, 13, 9, R=25.0)["y"])),

@@ -27,7 +27,7 @@ def to_dev(a, device):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
 
 
-CASES = [("cfg1", W.cfg1()["desc"]),
+CASES = [("ps_cubic16", W.ps_cubic16()["desc"]),
          ("hminus_22x22x9", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
          ("L2_quintic7_cubic4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0))]
 
@@ -51,7 +51,7 @@ def test_precond_reduced_precision(device, name, desc, prec, tol):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("name,desc,E,restart", [
-    ("cfg1", W.cfg1()["desc"], -0.25, 30),
+    ("ps_cubic16", W.ps_cubic16()["desc"], -0.25, 30),
     ("hminus_22x22x9", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic"), -0.35, 250)])
 def test_solve_mixed_precision(device, prec, name, desc, E, restart):
     fm = _fm()
@@ -76,7 +76,7 @@ def test_long_cycle_reduced_precision_full_size(device, prec):
     full-precision solutions agree to the solve's accuracy."""
     import torch
     fm = _fm()
-    cfg = W.cfg2()
+    cfg = W.hminus_scan()
     P = fm.Problem(cfg["desc"])
     Es = [float(e) for e in np.asarray(cfg["E"])[-4:]]
     B = to_dev(np.stack([W.rhs(s, P.N) for s in cfg["seeds"][-4:]]), device)

@@ -50,7 +50,7 @@ def wide(nx, ny, nz, dz):
 WIDE_CASES = [("wide_x199_y13", wide(199, 13, 4, 3)), ("wide_x10_y229", wide(10, 229, 6, 5))]
 
 OP_CASES = [
-    ("cfg1", W.cfg1()["desc"]),
+    ("ps_cubic16", W.ps_cubic16()["desc"]),
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
     ("hminus_10x13x9_quadratic", dict(small(W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"),
                                       y=W.make_desc(*W.H_MINUS, 13, 9, R=25.0)["y"])),
@@ -78,10 +78,10 @@ def test_operator_parity(device, name, desc):
         assert err <= 1e-11, (name, r, err)
 
 
-@pytest.mark.parametrize("cfg", ["cfg2", "cfg3", "cfg4"])
+@pytest.mark.parametrize("cfg", ["hminus_scan", "ps_q127", "ps_l2_q97"])
 def test_operator_parity_full_size_sampled(device, cfg):
     fm = _fm()
-    c = W.CONFIGS[cfg]()
+    c = W.WORKLOADS[cfg]()
     desc, E = c["desc"], c["E"][0]
     P = fm.Problem(desc)
     O = OracleProblem(desc)
@@ -99,7 +99,7 @@ def test_operator_parity_full_size_sampled(device, cfg):
 
 
 PREC_CASES = [
-    ("cfg1", W.cfg1()["desc"]),
+    ("ps_cubic16", W.ps_cubic16()["desc"]),
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
     ("hminus_quadratic_22x22x9", small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
@@ -151,9 +151,9 @@ def test_solve_trivial_converges_in_one_step(device):
     assert res[0]["rel_residual"] <= 1e-12
 
 
-def test_solve_cfg1_matches_lu(device):
+def test_solve_ps_cubic16_matches_lu(device):
     fm = _fm()
-    c = W.cfg1()
+    c = W.ps_cubic16()
     desc, E = c["desc"], c["E"][0]
     P = fm.Problem(desc)
     O = OracleProblem(desc)
@@ -212,7 +212,7 @@ def test_solve_cycle_longer_than_256_steps(device):
 def test_solve_identical_particle_symmetry(device):
     from tests.test_oracle_operator import permutation_maps
     fm = _fm()
-    c = W.cfg1()
+    c = W.ps_cubic16()
     desc, E = c["desc"], c["E"][0]
     P = fm.Problem(desc)
     O = OracleProblem(desc)
@@ -228,7 +228,7 @@ def test_solve_identical_particle_symmetry(device):
 
 def test_solve_rejects_nonfinite_rhs(device):
     fm = _fm()
-    P = fm.Problem(W.cfg1()["desc"])
+    P = fm.Problem(W.ps_cubic16()["desc"])
     b = W.rhs(1, P.N)
     b[17] = np.nan
     x = to_dev(np.zeros(P.N), device)

@@ -23,7 +23,7 @@ def _fm():
     return fm
 
 
-DESCS = [W.cfg1()["desc"], W.make_desc(*W.H_MINUS, 13, 6, R=30.0, xy_map="quadratic"),
+DESCS = [W.ps_cubic16()["desc"], W.make_desc(*W.H_MINUS, 13, 6, R=30.0, xy_map="quadratic"),
          W.make_desc(*W.PS_MINUS, 7, 4, J=1, deg_z=3, R=15.0)]
 
 
@@ -70,7 +70,7 @@ def test_serving_results_match_solo_and_batch_continuously(device):
 
 def test_serving_rejects_oversize_request(device):
     fm = _fm()
-    d = W.cfg1()["desc"]
+    d = W.ps_cubic16()["desc"]
     N = W.n_unknowns(d)
     srv = fm.Server(hbm_budget_bytes=1 << 20, max_batch=2)
     b, x = W.rhs(1, N), np.zeros(N)

@@ -92,9 +92,9 @@ def test_library_pencil_on_collocation_pencils(deg, n, mu):
 
 
 @lib_built
-@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+@pytest.mark.parametrize("name", ["ps_cubic16", "hminus_scan"])
 def test_library_full_setup(name):
-    cfg = W.CONFIGS[name]()
+    cfg = W.WORKLOADS[name]()
     err, pairs, N = fm.host_setup_check(cfg["desc"])
     assert N == W.n_unknowns(cfg["desc"])
     assert err < 1e-8
@@ -116,7 +116,7 @@ def _oracle_coupling(desc, x):
 
 
 COUPLING_CASES = [
-    ("cubic_L0", W.cfg1()["desc"]),
+    ("cubic_L0", W.ps_cubic16()["desc"]),
     ("quintic_hminus_L0", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic")),
     ("quintic_cubicz_L1", W.make_desc(*W.PS_MINUS, 10, 6, J=1, deg_z=3, R=15.0)),
     ("quintic_L1_odd", W.make_desc(*W.PS_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0)),
@@ -197,4 +197,4 @@ def test_host_coupling_exchange_reduced(name, desc, p):
 @lib_built
 def test_exchange_rejects_distinct_particles():
     with pytest.raises(fm.FmError):
-        fm.host_setup_check(dict(W.cfg1()["desc"], exchange=1))     # Ps-: particles 1 and 2 differ
+        fm.host_setup_check(dict(W.ps_cubic16()["desc"], exchange=1))     # Ps-: particles 1 and 2 differ
