@@ -1026,7 +1026,10 @@ __device__ __forceinline__ double divided_at(const double *__restrict__ T, int l
 // input is divided by lambda_x + lambda_y - E element by element as it is
 // loaded (the divide of the tensor trick between the two product pairs);
 // min_den (may be null) receives the smallest |denominator| met.  Grid:
-// (tiles, slices, requests); 256 threads.
+// (slices, tiles, requests); 256 threads.  Slices run fastest because the
+// hardware deals consecutive blocks to the 8 XCDs in turn: with a slice count
+// that is a multiple of 8, every tile of a slice (and every request's copy of
+// it) lands on one XCD and shares that XCD's L2 for the slice's W and data.
 // JZ (LEFT only, coupled preconditioner): the "slice" is a whole component,
 // the n_M n_z x n_x n_y matrix of its [M'][z] rows, and W its joint z matrix
 // (grid.y = 3); in and out must not overlap.
@@ -1045,7 +1048,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     if (JZ) {
         a = blockIdx.y;
         iM = k = 0;
-    } else if (!slice_decode(pd, blockIdx.y, a, iM, k)) {
+    } else if (!slice_decode(pd, blockIdx.x, a, iM, k)) {
         return;
     }
     const CompDev &C = pd->comp[a];
@@ -1053,7 +1056,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const int nz = C.z.n;
     const int nx = JZ ? pd->nM * nz : C.x.n, ny = JZ ? C.nxy : C.y.n;
     const int tc = (ny + BT - 1) / BT;
-    const int t = blockIdx.x;
+    const int t = JZ ? blockIdx.x : blockIdx.y;
     if (t >= ((nx + BT - 1) / BT) * tc) return;
     const int i0 = (t / tc) * BT, j0 = (t % tc) * BT;
     const size_t fx = (size_t)iM * nz + k;
@@ -1372,12 +1375,12 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
     const int req = blockIdx.z;
     if (active && !active[req]) return;
     int a, iM, k;
-    if (!slice_decode(pd, blockIdx.y, a, iM, k)) return;
+    if (!slice_decode(pd, blockIdx.x, a, iM, k)) return;
     const CompDev &C = pd->comp[a];
     const PrecCompDev &F = pr->comp[a];
     const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
     const int tc = (ny + SG_T - 1) / SG_T;
-    const int t = blockIdx.x;
+    const int t = blockIdx.y;
     if (t >= ((nx + SG_T - 1) / SG_T) * tc) return;
     const int i0 = (t / tc) * SG_T, j0 = (t % tc) * SG_T;
     const size_t fx = (size_t)iM * nz + k;
@@ -2156,7 +2159,7 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         int tl = 0;                                                                                                    \
         for (int a = 0; a < 3; ++a)                                                                                    \
             tl = std::max(tl, (int)(cdiv(pd.comp[a].x.n, BT) * cdiv(pd.comp[a].y.n, BT)));                             \
-        const dim3 g(tl, slices, nb);                                                                                  \
+        const dim3 g(slices, tl, nb);                                                                                  \
         hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, \
                            0, data, tmp, nullptr);                                                                     \
         hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,        \
@@ -2210,7 +2213,7 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
             side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
         }
         if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
-            const dim3 g(tiles, slices, nb);
+            const dim3 g(slices, tiles, nb);
 #define FM_SGLP(L, D, M, W, I, O) \
     hipLaunchKernelGGL((k_slice_gemm_lp<L, D, M>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, W, I, O)
             if (mode == 1) {
