@@ -960,6 +960,14 @@ __global__ void __launch_bounds__(NW * 64) k_xy_mfma(const ProblemDev *__restric
 // its own in between.  Slices are numbered alpha-major, then M', then k.
 constexpr int SG_T = 32, SG_KC = 32;
 
+// Tiles of a slice side n at tile width bt: with 32 x 32 tiles a side of
+// 32 m + 1 (the quintic bases of 3K + 1 functions with K a multiple of 32: 97,
+// 193) takes m tiles, the last of which also computes the leftover row or
+// column with vector FMAs, instead of an (m+1)-th tile holding one useful line.
+__host__ __device__ inline int sg_tiles(int n, int bt) {
+    return bt == 32 && n > bt && n % bt == 1 ? n / bt : (n + bt - 1) / bt;
+}
+
 __device__ __forceinline__ bool slice_decode(const ProblemDev *pd, int s, int &a, int &iM, int &k) {
     a = 0;
     while (a < 3 && s >= pd->nM * pd->comp[a].z.n) {
@@ -1055,10 +1063,13 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const PrecCompDev &F = pr->comp[a];
     const int nz = C.z.n;
     const int nx = JZ ? pd->nM * nz : C.x.n, ny = JZ ? C.nxy : C.y.n;
-    const int tc = (ny + BT - 1) / BT;
+    const int tr = JZ ? (nx + BT - 1) / BT : sg_tiles(nx, BT), tc = JZ ? (ny + BT - 1) / BT : sg_tiles(ny, BT);
     const int t = JZ ? blockIdx.x : blockIdx.y;
-    if (t >= ((nx + BT - 1) / BT) * tc) return;
+    if (t >= tr * tc) return;
     const int i0 = (t / tc) * BT, j0 = (t % tc) * BT;
+    // the last tile of a side bt m + 1 also computes line n - 1 (see sg_tiles)
+    constexpr bool EXT = !JZ && BT == 32;
+    const bool erow = EXT && i0 + BT == nx - 1 && nx % BT == 1, ecol = EXT && j0 + BT == ny - 1 && ny % BT == 1;
     const size_t fx = (size_t)iM * nz + k;
     const double *Wm = JZ     ? F.Zj + (size_t)which * nx * nx
                        : LEFT ? F.Wx + (fx * 2 + which) * nx * nx
@@ -1075,6 +1086,11 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
     constexpr int PER = BT * SG_KC / 256;   // A and B values per thread per chunk
     double ra[PER], rb[PER];
+    // leftover line: A's row nx - 1 (threads 0..KC-1) and B's column ny - 1
+    // (threads 64..64+KC-1) of the chunk; threads 0..BT-1 sum row outputs,
+    // BT..2BT-1 column outputs, 2BT the corner
+    __shared__ double Ae[SG_KC], Be[SG_KC];
+    double rae = 0.0, rbe = 0.0, ext = 0.0;
     // the next chunk is fetched into registers while the current one is multiplied
     // DIV: the x eigenvalue data of all K rows staged in LDS once, and the y data
     // of this thread's column (a thread's B elements share one column: 256 is a
@@ -1120,6 +1136,14 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             }
             rb[q] = bv;
         }
+        if (erow && threadIdx.x < SG_KC) {
+            const int kk = k0 + threadIdx.x;
+            rae = kk < K ? (LEFT ? Wm[(size_t)(nx - 1) * nx + kk] : g[(size_t)(nx - 1) * ny + kk]) : 0.0;
+        }
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) {
+            const int kb = k0 + (int)threadIdx.x - 64;
+            rbe = kb < K ? (LEFT ? g[(size_t)kb * ny + ny - 1] : Wm[(size_t)(ny - 1) * ny + kb]) : 0.0;
+        }
     };
     // DIV: divide the fetched chunk in registers (after the products of the
     // previous chunk, so its loads have landed)
@@ -1140,6 +1164,9 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
                 }
             }
         }
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC && k0 + (int)threadIdx.x - 64 < K)
+            rbe = divided_at(g, ny, k0 + (int)threadIdx.x - 64, ny - 1, F.lx + fx * nx, F.lxi + fx * nx,
+                             F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
     };
     auto stash = [&]() {
 #pragma unroll
@@ -1149,6 +1176,8 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             if (LEFT) Bs[e / BT][e % BT] = rb[q];
             else Bs[e % SG_KC][e / SG_KC] = rb[q];
         }
+        if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = rbe;
     };
     // wave (wi, wj) owns the (16 WT) x (16 WT) block at rows 16 WT wi, columns 16 WT wj
     dbl4 acc[WT][WT];
@@ -1164,6 +1193,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         if (k0 + SG_KC < K) fetch(k0 + SG_KC);
 #pragma unroll
         for (int kk = 0; kk < SG_KC; kk += 4) {
+            if (kk >= K - k0) break;            // the zero padding past K
             double av[WT], bv[WT];
 #pragma unroll
             for (int ti = 0; ti < WT; ++ti) av[ti] = As[16 * (WT * wi + ti) + r16][kk + k4];
@@ -1174,6 +1204,15 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
 #pragma unroll
                 for (int tj = 0; tj < WT; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+        }
+        if (erow || ecol) {
+            const int tx = threadIdx.x, kn = min(SG_KC, K - k0);
+            if (erow && tx < BT)
+                for (int kk = 0; kk < kn; ++kk) ext += Ae[kk] * Bs[kk][tx];
+            else if (ecol && tx >= BT && tx < 2 * BT)
+                for (int kk = 0; kk < kn; ++kk) ext += As[tx - BT][kk] * Be[kk];
+            else if (erow && ecol && tx == 2 * BT)
+                for (int kk = 0; kk < kn; ++kk) ext += Ae[kk] * Be[kk];
         }
         if (k0 + SG_KC < K) divide(k0 + SG_KC);
         __syncthreads();
@@ -1187,6 +1226,12 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
                 const int row = i0 + 16 * (WT * wi + ti) + k4 + 4 * v, col = j0 + 16 * (WT * wj + tj) + r16;
                 if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[ti][tj][v];
             }
+    if (erow || ecol) {
+        const int tx = threadIdx.x;
+        if (erow && tx < BT && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = ext;
+        else if (ecol && tx >= BT && tx < 2 * BT && i0 + tx - BT < nx) o[(size_t)(i0 + tx - BT) * ny + ny - 1] = ext;
+        else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = ext;
+    }
     if (DIV && min_den) {
         // block minimum, then one atomic per block on the bit pattern (positive doubles)
         __shared__ double red[256];
@@ -1379,10 +1424,12 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
     const CompDev &C = pd->comp[a];
     const PrecCompDev &F = pr->comp[a];
     const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
-    const int tc = (ny + SG_T - 1) / SG_T;
+    const int tc = sg_tiles(ny, SG_T);
     const int t = blockIdx.y;
-    if (t >= ((nx + SG_T - 1) / SG_T) * tc) return;
+    if (t >= sg_tiles(nx, SG_T) * tc) return;
     const int i0 = (t / tc) * SG_T, j0 = (t % tc) * SG_T;
+    // the last tile of a side 32 m + 1 also computes line n - 1 (see sg_tiles)
+    const bool erow = i0 + SG_T == nx - 1 && nx % SG_T == 1, ecol = j0 + SG_T == ny - 1 && ny % SG_T == 1;
     const size_t fx = (size_t)iM * nz + k;
     const float *Wm = LEFT ? F.Wx32 + (fx * 2 + which) * nx * nx : F.Wy32 + (fx * 2 + which) * ny * ny;
     const long long off = (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
@@ -1397,6 +1444,11 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
     const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
     constexpr int PER = SG_T * SG_KC / 256;
     float ra[PER], rb[PER];
+    // leftover line (FP32 FMAs): A's row nx - 1 and B's column ny - 1 of the
+    // chunk, loaded by threads 0..31 and 64..95; threads 0..31 sum the row
+    // outputs, 32..63 the column outputs, 64 the corner
+    __shared__ float Ae[SG_KC], Be[SG_KC];
+    float rae = 0.f, rbe = 0.f, ext = 0.f;
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -1420,6 +1472,21 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
             }
             rb[q] = bv;
         }
+        if (erow && threadIdx.x < SG_KC) {
+            const int kk = k0 + threadIdx.x;
+            rae = kk < K ? (LEFT ? Wm[(size_t)(nx - 1) * nx + kk] : (float)g[(size_t)(nx - 1) * ny + kk]) : 0.f;
+        }
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) {
+            const int kb = k0 + (int)threadIdx.x - 64;
+            float bv = 0.f;
+            if (kb < K) {
+                if (!LEFT) bv = Wm[(size_t)(ny - 1) * ny + kb];
+                else if (DIV) bv = (float)divided_at(g, ny, kb, ny - 1, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
+                                                     F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
+                else bv = (float)g[(size_t)kb * ny + ny - 1];
+            }
+            rbe = bv;
+        }
     };
     auto stash = [&]() {
 #pragma unroll
@@ -1429,6 +1496,8 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
             if (LEFT) Bs[e / SG_T][e % SG_T] = rb[q];
             else Bs[e % SG_KC][e / SG_KC] = rb[q];
         }
+        if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = rbe;
     };
     flt4 acc = flt4{0.f, 0.f, 0.f, 0.f};
     fetch(0);
@@ -1438,12 +1507,15 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
         if (k0 + SG_KC < K) fetch(k0 + SG_KC);
         if (MODE == 1) {
 #pragma unroll
-            for (int kk = 0; kk < SG_KC; kk += 4)
+            for (int kk = 0; kk < SG_KC; kk += 4) {
+                if (kk >= K - k0) break;            // the zero padding past K
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(As[16 * wi + r16][kk + k4], Bs[kk + k4][16 * wj + r16], acc,
                                                            0, 0, 0);
+            }
         } else {
 #pragma unroll
             for (int kb = 0; kb < SG_KC; kb += 16) {
+                if (kb >= K - k0) break;
                 sht4 ahi, amid, bhi, bmid;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -1460,6 +1532,15 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
             }
         }
+        if (erow || ecol) {
+            const int tx = threadIdx.x, kn = min(SG_KC, K - k0);
+            if (erow && tx < SG_T)
+                for (int kk = 0; kk < kn; ++kk) ext = fmaf(Ae[kk], Bs[kk][tx], ext);
+            else if (ecol && tx >= SG_T && tx < 2 * SG_T)
+                for (int kk = 0; kk < kn; ++kk) ext = fmaf(As[tx - SG_T][kk], Be[kk], ext);
+            else if (erow && ecol && tx == 2 * SG_T)
+                for (int kk = 0; kk < kn; ++kk) ext = fmaf(Ae[kk], Be[kk], ext);
+        }
         __syncthreads();
     }
     (void)mind;
@@ -1467,6 +1548,13 @@ __global__ void __launch_bounds__(256) k_slice_gemm_lp(const ProblemDev *__restr
     for (int v = 0; v < 4; ++v) {
         const int row = i0 + 16 * wi + 4 * k4 + v, col = j0 + 16 * wj + r16;
         if (row < nx && col < ny) o[(size_t)row * ny + col] = (double)acc[v];
+    }
+    if (erow || ecol) {
+        const int tx = threadIdx.x;
+        if (erow && tx < SG_T && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = (double)ext;
+        else if (ecol && tx >= SG_T && tx < 2 * SG_T && i0 + tx - SG_T < nx)
+            o[(size_t)(i0 + tx - SG_T) * ny + ny - 1] = (double)ext;
+        else if (erow && ecol && tx == 2 * SG_T) o[(size_t)(nx - 1) * ny + ny - 1] = (double)ext;
     }
 }
 
@@ -2158,7 +2246,7 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
     {                                                                                                                  \
         int tl = 0;                                                                                                    \
         for (int a = 0; a < 3; ++a)                                                                                    \
-            tl = std::max(tl, (int)(cdiv(pd.comp[a].x.n, BT) * cdiv(pd.comp[a].y.n, BT)));                             \
+            tl = std::max(tl, sg_tiles(pd.comp[a].x.n, BT) * sg_tiles(pd.comp[a].y.n, BT));                             \
         const dim3 g(slices, tl, nb);                                                                                  \
         hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, \
                            0, data, tmp, nullptr);                                                                     \
@@ -2170,10 +2258,17 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
                            active, 1, tmp, data, nullptr);                                                             \
     }
         // 64 x 64 tiles reuse each operand chunk twice as often, but a small
-        // batch of wide slices then leaves the chip short of blocks
-        long long t64 = 0;
-        for (int a = 0; a < 3; ++a) t64 = std::max<long long>(t64, (long long)cdiv(pd.comp[a].x.n, 64) * cdiv(pd.comp[a].y.n, 64));
-        if (side > 32 && t64 * slices * nb >= XY_T64_MIN_BLOCKS) FM_SG(64) else FM_SG(32)
+        // batch of wide slices then leaves the chip short of blocks, and a side
+        // of 32 m + 1 pads to far more area in 64-wide tiles than in 32-wide
+        // ones with the leftover line (97: 128^2 against 96^2 + a line)
+        long long t64 = 0, area64 = 0, area32 = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int nx = pd.comp[a].x.n, ny = pd.comp[a].y.n;
+            t64 = std::max<long long>(t64, (long long)sg_tiles(nx, 64) * sg_tiles(ny, 64));
+            area64 += 4096LL * sg_tiles(nx, 64) * sg_tiles(ny, 64);
+            area32 += 1024LL * sg_tiles(nx, 32) * sg_tiles(ny, 32);
+        }
+        if (side > 32 && t64 * slices * nb >= XY_T64_MIN_BLOCKS && 4 * area64 <= 5 * area32) FM_SG(64) else FM_SG(32)
 #undef FM_SG
         (void)tiles;
         return;
@@ -2209,7 +2304,7 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
         int slices = 0, tiles = 0, side = 0;
         for (int a = 0; a < 3; ++a) {
             slices += pd.nM * pd.comp[a].z.n;
-            tiles = std::max(tiles, (int)(cdiv(pd.comp[a].x.n, SG_T) * cdiv(pd.comp[a].y.n, SG_T)));
+            tiles = std::max(tiles, sg_tiles(pd.comp[a].x.n, SG_T) * sg_tiles(pd.comp[a].y.n, SG_T));
             side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
         }
         if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {

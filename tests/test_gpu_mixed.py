@@ -27,9 +27,19 @@ def to_dev(a, device):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
 
 
+def wide(nx, ny, nz):
+    """Quintic x and y of different sizes, cubic z."""
+    d = W.make_desc(*W.PS_MINUS, nx, nz, deg_xy=5, deg_z=3, R=20.0)
+    d["y"] = W.make_desc(*W.PS_MINUS, ny, nz, deg_xy=5, deg_z=3, R=20.0)["y"]
+    return d
+
+
+# the 97-wide cases (97 = 3 x 32 + 1): the leftover row, column and corner of
+# the staged products
 CASES = [("ps_cubic16", W.ps_cubic16()["desc"]),
          ("hminus_22x22x9", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
-         ("L2_quintic7_cubic4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0))]
+         ("L2_quintic7_cubic4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0)),
+         ("ext_x97_y13", wide(97, 13, 4)), ("ext_x10_y97", wide(10, 97, 4)), ("ext_97x97", wide(97, 97, 4))]
 
 
 @pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])

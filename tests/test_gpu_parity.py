@@ -98,12 +98,16 @@ def test_operator_parity_full_size_sampled(device, cfg):
 
 
 
+# sides of 32 m + 1: the last 32 x 32 tile also computes the leftover row (x)
+# or column (y) of the x-y products
+EXT_CASES = [("ext_x97_y13", wide(97, 13, 4, 3)), ("ext_x10_y97", wide(10, 97, 4, 3))]
+
 PREC_CASES = [
     ("ps_cubic16", W.ps_cubic16()["desc"]),
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
     ("hminus_quadratic_22x22x9", small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
-] + WIDE_CASES
+] + WIDE_CASES + EXT_CASES
 
 
 @pytest.mark.parametrize("name,desc", PREC_CASES, ids=[c[0] for c in PREC_CASES])
@@ -121,6 +125,28 @@ def test_precond_parity(device, name, desc):
         ref = precond_reference(O, E, R[r])
         err = np.abs(Zg[r] - ref).max() / np.abs(ref).max()
         assert err <= 1e-9, (name, r, err)
+
+
+def test_precond_leftover_corner_backward_error(device):
+    """x and y sides 97 = 3 x 32 + 1: the leftover row, column and corner of
+    every x-y product.  An LU of the separable operator at this size takes
+    half a minute per right-hand side, so the check is the normwise backward
+    error of z against that operator, |L z - r| <= 1e-12 |L| |z| (max norms).
+    On the oracle's own solve at x 97, y 13 it is 9e-21; zeroing one leftover
+    row gives 9e-7 and scaling the corner by 1 + 1e-3 gives 5e-9."""
+    fm = _fm()
+    desc = wide(97, 97, 4, 3)
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    E = -0.25
+    r = np.random.default_rng(11).standard_normal(O.N)
+    z = to_dev(np.zeros(O.N), device)
+    P.apply_precond([E], to_dev(r, device), z)
+    zg = z.cpu().numpy()
+    L = O.separable(E).tocsr()
+    norm_L = np.abs(L).sum(axis=1).max()
+    back = np.abs(L @ zg - r).max() / (norm_L * np.abs(zg).max())
+    assert back <= 1e-12, back
 
 
 def test_precond_equals_kronecker_inverse_without_potentials(device):
