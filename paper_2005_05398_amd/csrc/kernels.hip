@@ -1807,8 +1807,25 @@ __global__ void __launch_bounds__(FT) k_arnoldi_finish(KrylovDev K, int j, int n
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = K.m;
     const double *part = K.part + (size_t)req * (2 * m + 3) * NBLK;
+    // the step's other inputs, requested now so that they arrive while the
+    // partials are summed (the row loop's barriers publish the LDS copies)
+    double *hc = K.hcol + (size_t)req * (m + 1);
+    double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m;
+    double *g = K.g + (size_t)req * (m + 1);
+    const double rho = K.rho[req];
+    double g_prev = 0.0, tol = 0.0;
+    if (threadIdx.x == 0 && j > 0) {
+        g_prev = g[j - 1];
+        tol = K.tol[req];
+    }
+    for (int i = threadIdx.x; i < j; i += FT) col[i] = hc[i];
+    for (int i = threadIdx.x; i + 1 < j; i += FT) {
+        csv[i] = cs[i];
+        snv[i] = sn[i];
+    }
     // row sums of the partials, 64 rows at a time: lane = row, the waves split
-    // the blocks (fixed assignment, so the sums are deterministic)
+    // the blocks (fixed assignment, so the sums are deterministic); each wave
+    // requests up to ILP of its blocks' values at once
     __shared__ double rsum[FT / 64][64];
     const int nrows = 2 * j + 3;
     for (int r0 = 0; r0 < nrows; r0 += 64) {
@@ -1819,15 +1836,13 @@ __global__ void __launch_bounds__(FT) k_arnoldi_finish(KrylovDev K, int j, int n
         for (int u = 0; u < ILP; ++u) a[u] = 0;
         if (row < nrows) {
             const size_t rs = 2 * m + 3;
-            int b = wave;
-            for (; b + (ILP - 1) * NW < nblk; b += ILP * NW) {
+            for (int b = wave; b < nblk; b += ILP * NW) {
                 double v[ILP];
 #pragma unroll
-                for (int u = 0; u < ILP; ++u) v[u] = part[(size_t)(b + u * NW) * rs + row];
+                for (int u = 0; u < ILP; ++u) v[u] = b + u * NW < nblk ? part[(size_t)(b + u * NW) * rs + row] : 0.0;
 #pragma unroll
                 for (int u = 0; u < ILP; ++u) a[u] += v[u];
             }
-            for (; b < nblk; b += NW) a[0] += part[(size_t)b * rs + row];
         }
         double tot = 0;
 #pragma unroll
@@ -1843,15 +1858,6 @@ __global__ void __launch_bounds__(FT) k_arnoldi_finish(KrylovDev K, int j, int n
         }
         __syncthreads();
     }
-    double *hc = K.hcol + (size_t)req * (m + 1);
-    double *cs = K.cs + (size_t)req * m, *sn = K.sn + (size_t)req * m;
-    for (int i = threadIdx.x; i < j; i += FT) col[i] = hc[i];
-    for (int i = threadIdx.x; i + 1 < j; i += FT) {
-        csv[i] = cs[i];
-        snv[i] = sn[i];
-    }
-    __syncthreads();
-    const double rho = K.rho[req];
     double ss = 0, st = 0, tt = 0;
     for (int i = threadIdx.x; i < j; i += FT) {
         ss += sv[i] * sv[i];
@@ -1865,7 +1871,6 @@ __global__ void __launch_bounds__(FT) k_arnoldi_finish(KrylovDev K, int j, int n
     const double uu = uu_uw[0], uw = uu_uw[1], ww = uu_uw[2];
     const double r2 = uu - ss;
     const double r = (r2 > 1e-20 * uu) ? sqrt(r2) : 0.0;
-    double *g = K.g + (size_t)req * (m + 1);
     if (threadIdx.x == 0) {
         bool stop = closing != 0 || r == 0.0;
         if (j == 0) {
@@ -1883,15 +1888,15 @@ __global__ void __launch_bounds__(FT) k_arnoldi_finish(KrylovDev K, int j, int n
             cs[j - 1] = c;
             sn[j - 1] = s;
             H[(size_t)(j - 1) * m + (j - 1)] = rr;
-            const double gj = -s * g[j - 1];
+            const double gj = -s * g_prev;
             g[j] = gj;
-            g[j - 1] = c * g[j - 1];
+            g[j - 1] = c * g_prev;
             const double est = fabs(gj);
             if (!(est == est) || !(rr == rr)) {
                 K.flags[req] |= 2;
                 stop = true;
             }
-            if (est <= K.tol[req]) stop = true;
+            if (est <= tol) stop = true;
         }
         K.jcount[req] = j;
         if (!(r == r)) {
