@@ -275,6 +275,20 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
         D2y[s] = C.y.D2[iy * MAXR + s];
     }
 
+    // the x rows of the tile's points, requested now and written to LDS after
+    // the planes (through global-memory pointers: a flat load may alias LDS, so
+    // each would wait before the next LDS write)
+    typedef const __attribute__((address_space(1))) double gdouble;
+    gdouble *gxS = (gdouble *)C.x.S, *gxD = (gdouble *)C.x.D2;
+    const int nxr = (ixe - ixs) * RX;
+    double xr[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int pp = e / RX, sx = e % RX;
+        xr[u][0] = e < nxr ? gxS[(ixs + pp) * MAXR + sx] : 0.0;
+        xr[u][1] = e < nxr ? gxD[(ixs + pp) * MAXR + sx] : 0.0;
+    }
     {
         // the block's z row; a dropped function (value 0 in all three rows)
         // reads plane 0, which exists
@@ -309,10 +323,18 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
             pl[3 * e + 2] = c2;
         }
     }
-    for (int e = threadIdx.x; e < (ixe - ixs) * RX; e += 256) {
-        const int pp = e / RX, s = e % RX;
-        xS[e] = C.x.S[(ixs + pp) * MAXR + s];
-        xD[e] = C.x.D2[(ixs + pp) * MAXR + s];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < nxr) {
+            xS[e] = xr[u][0];
+            xD[e] = xr[u][1];
+        }
+    }
+    for (int e = threadIdx.x + 512; e < nxr; e += 256) {
+        const int pp = e / RX, sx = e % RX;
+        xS[e] = gxS[(ixs + pp) * MAXR + sx];
+        xD[e] = gxD[(ixs + pp) * MAXR + sx];
     }
     __syncthreads();
     if (!has) return;
@@ -768,22 +790,51 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     const int cb = MZ2_THREADS / split;                // columns per block
     if ((int)blockIdx.x * cb >= nxy) return;
     __shared__ T W[(MAXNZ + 3) * MAXNZ];
-    if (F32) {
-        const float *Wg = F.Wz32 + ((size_t)iM * 2 + which) * nz * nz;
-        for (int t = threadIdx.x; t < (nz + 3) * nz; t += MZ2_THREADS) W[t] = t < nz * nz ? (T)Wg[t] : (T)0;
-    } else {
-        const double *Wg = F.Wz + ((size_t)iM * 2 + which) * nz * nz;
-        for (int t = threadIdx.x; t < (nz + 3) * nz; t += MZ2_THREADS) W[t] = t < nz * nz ? (T)Wg[t] : (T)0;
-    }
     const int sub = threadIdx.x / cb;
     const int col = blockIdx.x * cb + (threadIdx.x - sub * cb);
     const bool ok = col < nxy;
     const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts + col;
-    T v[MAXNZ];
+    // the column as loaded (FP64), converted once all of it is in flight: a
+    // conversion per load would wait for each load in turn
+    double vd[MAXNZ];
 #pragma unroll
-    for (int k = 0; k < MAXNZ; ++k) v[k] = (ok && k < nz) ? (T)in[base + (long long)k * nxy] : (T)0;
+    for (int k = 0; k < MAXNZ; ++k) vd[k] = (ok && k < nz) ? in[base + (long long)k * nxy] : 0.0;
+    // the factor, staged after the column loads are issued; up to nz = 32 all
+    // of its loads first, then the LDS writes, so that the block waits on one
+    // round trip (a loop that stores each value as it arrives waits once per pass)
+    // (as global-memory pointers: loads through a generic pointer are flat
+    // loads, which the compiler waits for one by one)
+    const size_t wo = ((size_t)iM * 2 + which) * nz * nz;
+    const int wn = (nz + 3) * nz;
+    typedef const __attribute__((address_space(1))) double gdouble;
+    typedef const __attribute__((address_space(1))) float gfloat;
+    gdouble *Wg64 = (gdouble *)(F.Wz + wo);
+    gfloat *Wg32 = (gfloat *)(F.Wz32 + wo);
+    if (MAXNZ <= 32) {
+        constexpr int WIT = ((MAXNZ + 3) * MAXNZ + MZ2_THREADS - 1) / MZ2_THREADS;
+        T wv[WIT];
+#pragma unroll
+        for (int i = 0; i < WIT; ++i) {
+            const int t = threadIdx.x + i * MZ2_THREADS;
+            wv[i] = t < nz * nz ? (F32 ? (T)Wg32[t] : (T)Wg64[t]) : (T)0;
+        }
+#pragma unroll
+        for (int i = 0; i < WIT; ++i) {
+            const int t = threadIdx.x + i * MZ2_THREADS;
+            if (t < wn) W[t] = wv[i];
+        }
+    } else {
+        for (int t = threadIdx.x; t < wn; t += MZ2_THREADS) W[t] = t < nz * nz ? (F32 ? (T)Wg32[t] : (T)Wg64[t]) : (T)0;
+    }
+    if (F32) {      // the column stays FP64 until all of the block's loads have issued
+#pragma unroll
+        for (int k = 0; k < MAXNZ; ++k) asm volatile("" : "+v"(vd[k]));
+    }
     __syncthreads();                                   // W staged; every column of the block read
     if (!ok) return;
+    T v[MAXNZ];
+#pragma unroll
+    for (int k = 0; k < MAXNZ; ++k) v[k] = (T)vd[k];
     // groups of four outputs (independent sums; rows past nz read zeros)
     for (int k2 = 4 * sub; k2 < nz; k2 += 4 * split) {
         T acc[4] = {0, 0, 0, 0};
