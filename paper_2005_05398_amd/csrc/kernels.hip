@@ -431,6 +431,24 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
         D2y[s] = C.y.D2[iy * MAXR + s];
     }
 
+    // the block's z row (offsets and the three weight rows), the same for every
+    // M' block: read once into LDS (published by the loop's first barrier)
+    // rather than from memory again before each block's plane loads
+    __shared__ long long zoff[RZ];
+    __shared__ double zw[3 * RZ];
+    if (threadIdx.x < RZ) {
+        // through global-memory pointers, all four before the LDS writes (a flat
+        // load may alias LDS and would wait before each write)
+        typedef const __attribute__((address_space(1))) int gint;
+        typedef const __attribute__((address_space(1))) double gdouble;
+        const int a1 = threadIdx.x, zi = iz * MAXR + a1;
+        const int g = ((gint *)C.z.idx)[zi];
+        const double zs = ((gdouble *)C.z.S)[zi], zd1 = ((gdouble *)C.z.D1)[zi], zd2 = ((gdouble *)C.z.D2)[zi];
+        zoff[a1] = (long long)(g >= 0 ? g : 0) * C.nxy;
+        zw[a1] = zs;
+        zw[RZ + a1] = zd1;
+        zw[2 * RZ + a1] = zd2;
+    }
     double u[NM], uz[NM], uzz[NM], uxx[NM], uyy[NM];
 #pragma unroll
     for (int iM = 0; iM < NM; ++iM) {
@@ -438,33 +456,44 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
         {
             // the block's z row, contracted into three planes as the M' block is
             // read (a dropped function, value 0 in all three rows, reads plane 0)
-            const int *zidx = C.z.idx + iz * MAXR;
             long long zo[RZ];
             double w0[RZ], w1[RZ], w2[RZ];
 #pragma unroll
             for (int a1 = 0; a1 < RZ; ++a1) {
-                const int g = zidx[a1];
-                zo[a1] = (long long)(g >= 0 ? g : 0) * C.nxy;
-                w0[a1] = C.z.S[iz * MAXR + a1];
-                w1[a1] = C.z.D1[iz * MAXR + a1];
-                w2[a1] = C.z.D2[iz * MAXR + a1];
+                zo[a1] = zoff[a1];
+                w0[a1] = zw[a1];
+                w1[a1] = zw[RZ + a1];
+                w2[a1] = zw[2 * RZ + a1];
             }
-            // rows kxlo..kxhi are consecutive: a plane is one contiguous run of each z row
+            // rows kxlo..kxhi are consecutive: a plane is one contiguous run of each z row;
+            // with four z rows two passes' loads are issued before the first wait
+            // (a pass waits for its loads before its LDS writes)
+            constexpr int PU = RZ <= 4 ? 2 : 1;
             const double *xb = x + C.off + (long long)iM * C.npts + (long long)kxlo * ny;
-            for (int e = threadIdx.x; e < plane_n; e += 256) {
-                double v[RZ];
+            for (int e0 = threadIdx.x; e0 < plane_n; e0 += 256 * PU) {
+                double v[PU][RZ];
 #pragma unroll
-                for (int a1 = 0; a1 < RZ; ++a1) v[a1] = xb[zo[a1] + e];
-                double c0 = 0, c1 = 0, c2 = 0;
+                for (int u = 0; u < PU; ++u) {
+                    const int e = e0 + 256 * u;
 #pragma unroll
-                for (int a1 = 0; a1 < RZ; ++a1) {
-                    c0 += w0[a1] * v[a1];
-                    c1 += w1[a1] * v[a1];
-                    c2 += w2[a1] * v[a1];
+                    for (int a1 = 0; a1 < RZ; ++a1) v[u][a1] = e < plane_n ? xb[zo[a1] + e] : 0.0;
                 }
-                pl[3 * e] = c0;
-                pl[3 * e + 1] = c1;
-                pl[3 * e + 2] = c2;
+#pragma unroll
+                for (int u = 0; u < PU; ++u) {
+                    const int e = e0 + 256 * u;
+                    if (e < plane_n) {
+                        double c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+                        for (int a1 = 0; a1 < RZ; ++a1) {
+                            c0 += w0[a1] * v[u][a1];
+                            c1 += w1[a1] * v[u][a1];
+                            c2 += w2[a1] * v[u][a1];
+                        }
+                        pl[3 * e] = c0;
+                        pl[3 * e + 1] = c1;
+                        pl[3 * e + 2] = c2;
+                    }
+                }
             }
         }
         __syncthreads();
