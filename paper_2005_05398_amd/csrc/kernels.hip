@@ -1183,15 +1183,23 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     double ly_c = 0.0;
     int ty_c = 1;
     if (DIV) {
-        if (staged)
-            for (int r = threadIdx.x; r < K; r += 256) {
-                sLx[r] = F.lx[fx * nx + r];
-                sTx[r] = F.tx[fx * nx + r];
-            }
+        // (K <= 256 when staged: one row per thread) through global-memory
+        // pointers, every load before the LDS writes: a flat load may alias LDS
+        // and would wait before each write
+        typedef const __attribute__((address_space(1))) double gdouble;
+        typedef const __attribute__((address_space(1))) signed char gschar;
+        const int r = threadIdx.x;
+        const bool st = staged && r < K;
+        const double lxv = st ? ((gdouble *)F.lx)[fx * nx + r] : 0.0;
+        const signed char txv = st ? ((gschar *)F.tx)[fx * nx + r] : (signed char)0;
         const int jc = j0 + (int)threadIdx.x % BT;
         if (jc < ny) {
-            ly_c = F.ly[fx * ny + jc];
-            ty_c = F.ty[fx * ny + jc];
+            ly_c = ((gdouble *)F.ly)[fx * ny + jc];
+            ty_c = ((gschar *)F.ty)[fx * ny + jc];
+        }
+        if (st) {
+            sLx[r] = lxv;
+            sTx[r] = txv;
         }
         __syncthreads();
     }
