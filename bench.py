@@ -69,7 +69,7 @@ def cpu_baseline(seconds_cap=30.0):
 
 def eigs_bench(args):
     """Helium 2 1P and 3 1P (with 2 3P and 3 3P, which the unsymmetrised
-    system also holds) by shift-invert Arnoldi on the grids of Table 3."""
+    system also holds) by shift-invert Arnoldi on the grids of Table 1 (Sec. 4, the comparison with Pardiso)."""
     import torch
     from paper_2005_05398_amd import fm
     from paper_2005_05398_amd import workloads as W
@@ -77,7 +77,7 @@ def eigs_bench(args):
     stream = torch.cuda.current_stream()
     rows = []
     t_all = time.perf_counter()
-    for g1, g3, printed in W.HE_TABLE3:
+    for g1, g3, printed in W.HE_TABLE1:
         desc = dict(W.helium_desc(g1, g3), precond="coupled")
         t0 = time.perf_counter()
         P = fm.Problem(desc)
@@ -97,7 +97,7 @@ def eigs_bench(args):
         print(f"eigs: grid {g1}/{g3} N={P.N}: {['%.8f' % e for e in Es]} in {t_eig:.2f} s "
               f"({info['solves']} solves)", file=sys.stderr, flush=True)
         del P
-    line = {"metric": "helium 1P energies by shift-invert Arnoldi (grids of the paper's Table 3)",
+    line = {"metric": "helium 1P energies by shift-invert Arnoldi (grids of the paper's Table 1, Sec. 4)",
             "value": sum(r["eigs_s"] for r in rows), "unit": "s (all five grids)", "n_gpus": 1,
             "higher_is_better": False, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "He (nucleus 1e15 a.u.), J=1, tau=+1, quintic, map-pow x/y, sin z, "
@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--serve-precond", default="coupled", choices=["block_jacobi", "coupled"],
                     help="preconditioner of the L > 0 requests in the serving stream")
     ap.add_argument("--eigs", action="store_true",
-                    help="helium 1P levels by shift-invert Arnoldi on the grids of the paper's Table 3")
+                    help="helium 1P levels by shift-invert Arnoldi on the grids of the paper's Table 1 (Sec. 4)")
     ap.add_argument("--eigs-3d", action="store_true",
                     help="helium 3 1D level (L=2) on growing basis sets up to the paper's Fig. 4 one (N ~ 8.3M)")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -9,6 +9,12 @@
 //
 // Eigenvalues: balancing, Householder reduction to Hessenberg form, Francis
 // implicit double-shift QR (Golub & Van Loan, Matrix Computations, Sec. 7.5).
+// The balancing follows the published EISPACK routine BALANC (Parlett &
+// Reinsch, Numer. Math. 13 (1969); powers-of-two row/column scaling until the
+// norms settle), and the QR sweep the published EISPACK routine HQR (Martin,
+// Peters & Wilkinson, Numer. Math. 14 (1970)): its search for two small
+// consecutive subdiagonal elements and its exceptional shifts (0.75 s and
+// -0.4375 s^2 on every tenth unsuccessful iteration) are kept.
 // Eigenvectors: inverse iteration with the Hessenberg matrix (Sec. 7.6.1 there),
 // mapped back through the Householder and balancing transforms.
 #include <algorithm>

@@ -100,19 +100,20 @@ WORKLOADS = {"ps_cubic16": ps_cubic16, "hminus_scan": hminus_scan, "ps_q127": ps
 HE_MASSES = (1.0, 1.0, 1e15)
 HE_CHARGES = (-1.0, -1.0, 2.0)
 
-# Table 3 (J = 1, tau = +1; domains (1: 36, 36; 3: 9, 6)): basis sizes of
-# components (1, 3) as (n_x, n_y, n_z) and the printed 2 1P and 3 1P
-# energies; the benchmark values the caption quotes.
-HE_TABLE3 = [((22, 22, 9), (19, 19, 12), (-2.12524, -2.05654)),
+# Table 1 of Sec. 4 (the comparison with Pardiso; J = 1, tau = +1; domains
+# (1: 36, 36; 3: 9, 6)): basis sizes of components (1, 3) as (n_x, n_y, n_z)
+# and the printed 2 1P and 3 1P energies; the benchmark values the caption
+# quotes.
+HE_TABLE1 = [((22, 22, 9), (19, 19, 12), (-2.12524, -2.05654)),
              ((31, 31, 9), (22, 22, 15), (-2.12365, -2.05495)),
              ((40, 40, 12), (25, 25, 18), (-2.12378, -2.05508)),
              ((49, 49, 12), (28, 28, 21), (-2.12385, -2.05513)),
              ((58, 58, 12), (28, 28, 21), (-2.12384, -2.05514))]
-HE_TABLE3_DOMAINS = ((36.0, 36.0), (9.0, 6.0))
+HE_TABLE1_DOMAINS = ((36.0, 36.0), (9.0, 6.0))
 HE_1P_BENCHMARK = (-2.12384308649810135925, -2.05514636209194353689)
 
 
-def helium_desc(g1, g3, dom1=HE_TABLE3_DOMAINS[0], dom3=HE_TABLE3_DOMAINS[1], J=1, tau=1):
+def helium_desc(g1, g3, dom1=HE_TABLE1_DOMAINS[0], dom3=HE_TABLE1_DOMAINS[1], J=1, tau=1):
     """Helium description with basis sizes g1 (components 1, 2) and g3
     (component 3), each (n_x, n_y, n_z), on the paper's domains (unscaled
     lengths, see above)."""

@@ -96,9 +96,9 @@ def test_eigs_rejects_bad_options(device):
     assert e.value.status == fm.FM_E_INVALID
 
 
-def _table3_rows():
+def _table1_rows():
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "he_table3_1P.txt")
+    path = os.path.join(os.path.dirname(__file__), "golden", "he_table1_1P.txt")
     rows = []
     for line in open(path):
         if line.startswith("#") or not line.strip():
@@ -110,9 +110,9 @@ def _table3_rows():
 
 
 @pytest.mark.parametrize("row", range(5))
-def test_helium_table3_energies(device, row):
+def test_helium_table1_energies(device, row):
     """The 2 1P and 3 1P levels of helium on the basis sets of the paper's
-    Table 3 reproduce its printed energies (five decimals): the whole method —
+    Table 1 (Sec. 4, the comparison with Pardiso) reproduce its printed energies (five decimals): the whole method —
     bases and collocation points, potentials and their split, the coupling,
     the solver — against values the paper prints.  The unsymmetrised system
     also holds the 2 3P and 3 3P levels; the singlets are the two values nearest
@@ -121,7 +121,7 @@ def test_helium_table3_energies(device, row):
     last digit) while the values change by 1e-4..1e-3 from row to row, so a
     2e-5 bound still tells the rows apart."""
     fm = _fm()
-    g1, g3, printed = _table3_rows()[row]
+    g1, g3, printed = _table1_rows()[row]
     P = fm.Problem(dict(W.helium_desc(g1, g3), precond="coupled"))
     st, E, res, info = P.eigs(-2.095, nev=4, ncv=24, tol=1e-10, max_restarts=40, restart=100, rtol=1e-11,
                               max_iters=4000)

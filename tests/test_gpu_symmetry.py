@@ -87,12 +87,12 @@ def test_reduced_solve_matches_lu(device, name, desc, p):
     assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
 
 
-def test_helium_table3_row1_by_exchange_parity(device):
-    """Table 3's first basis set: the full system's four levels nearest -2.095
+def test_helium_table1_row1_by_exchange_parity(device):
+    """The first basis set of Table 1 (Sec. 4): the full system's four levels nearest -2.095
     are 2 3P, 2 1P, 3 3P, 3 1P; p = +1 keeps the singlets (the paper's
     reduced equations), p = -1 the triplets, with the same energies."""
     fm = _fm()
-    g1, g3, printed = W.HE_TABLE3[0]
+    g1, g3, printed = W.HE_TABLE1[0]
     desc = dict(W.helium_desc(g1, g3), precond="coupled")
     out = {}
     for p in (0, 1, -1):

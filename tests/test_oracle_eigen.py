@@ -49,12 +49,12 @@ def test_shift_invert_matches_dense(name, desc, sigma):
         assert r <= 1e-8 * max(1.0, abs(E[i])), (i, r)
 
 
-def test_helium_table3_workload_matches_golden():
-    """The bench's copy of the Table 3 rows equals the golden fixture."""
+def test_helium_table1_workload_matches_golden():
+    """The bench's copy of the Table 1 rows (Sec. 4) equals the golden fixture."""
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "he_table3_1P.txt")
+    path = os.path.join(os.path.dirname(__file__), "golden", "he_table1_1P.txt")
     rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
-    assert len(rows) == len(W.HE_TABLE3)
-    for v, (g1, g3, printed) in zip(rows, W.HE_TABLE3):
+    assert len(rows) == len(W.HE_TABLE1)
+    for v, (g1, g3, printed) in zip(rows, W.HE_TABLE1):
         assert tuple(int(t) for t in v[:3]) == g1 and tuple(int(t) for t in v[3:6]) == g3
         assert (float(v[6]), float(v[7])) == printed
