@@ -8,12 +8,19 @@ one seeded N(0, 1) right-hand side per energy.  All 32 solves share the
 problem's device-resident factors and run as one batch.
 
 One step = one fm_solve call on all 32 requests, each to a true FP64 relative
-residual of 1e-10 (inputs already resident in HBM).  value = solves per second.
+residual of 1e-10 (inputs already resident in HBM).  value = solves per second
+of the FP64 path, timed with nothing but the solves in the timed region.
 
-Also reported: the roofline of the kernel class with the largest share of the
-step (HIP events recorded by the library on the solve's stream over the timed
-region, algorithmic bytes/flops from the problem sizes and step counts), and
-the CPU oracle timed on this host on a bounded sample.
+Also reported, each timed the same way: the batch with the preconditioner's
+products in FP32 and BF16x3 MFMA (error against the FP64 GPU solution); the
+other single-GPU workloads (the small cubic case beside the oracle's dense LU
+timings, the quintic 127 x 127 x 32 request at three precisions, the L = 2
+request with both preconditioner variants, a bounded sample of the serving
+stream at a sustained arrival rate).  Kernel shares, the roofline of the class
+with the largest share and the MFMA fraction of the x-y products come from a
+second pass of the same steps with the library's per-launch HIP events on the
+solve's stream (algorithmic bytes/flops from the problem sizes and step
+counts).  The CPU oracle is timed on this host on a bounded sample.
 """
 import argparse
 import json
@@ -154,90 +161,125 @@ def eigs_3d_bench(args):
     print(json.dumps(line))
 
 
-def serve_bench(args):
-    """Serving: the seeded request stream against one server.  Phase 1 submits
-    the first requests all at once (saturation throughput; it also builds the
-    problems of the shapes it meets, as a running service would have them);
-    phase 2 submits the whole stream with Poisson arrivals at 0.8 x the
-    saturated rate.  Reported: solves/s and p50/p99 of submit-to-done latency
-    in phase 2, and how many requests met the tolerance."""
+def serve_phase(srv, reqs, rhs, indices, arrivals, label, args):
+    """Submit requests `indices` at the given arrival times (s from the start)
+    and wait for all of them.  Returns (results by tag, wall time, samples of
+    the number of requests outstanding (submitted, not finished) over time)."""
     import numpy as np
-    from paper_2005_05398_amd import fm
-    from paper_2005_05398_amd import workloads as W
+    done = {}
+    xs = {}
+    qlen = []
+    t0 = time.perf_counter()
+    t_report = t0
+    t_sample = t0
+    k = 0
+    while len(done) < len(indices):
+        now = time.perf_counter() - t0
+        while k < len(indices) and arrivals[k] <= now:
+            i = indices[k]
+            r = reqs[i]
+            xs[i] = np.zeros(rhs[i].size)
+            srv.submit(r["desc"], r["E"], rhs[i], xs[i], i, restart=args.serve_restart, rtol=1e-10,
+                       max_iters=args.serve_max_iters, prec=args.serve_prec)
+            k += 1
+        block = k >= len(indices)
+        for o in srv.poll(block=block):
+            done[o["tag"]] = o
+        t = time.perf_counter()
+        if t - t_sample > 0.25:
+            t_sample = t
+            qlen.append((t - t0, k - len(done)))
+        if t - t_report > 20:
+            t_report = t
+            print(f"serve {label}: {len(done)}/{len(indices)} done, {k} submitted, {t - t0:.0f} s", file=sys.stderr,
+                  flush=True)
+        if not block:
+            time.sleep(0.001)
+    return done, time.perf_counter() - t0, qlen
 
-    reqs = [W.serving_request(i) for i in range(args.requests)]
-    for r in reqs:                      # the preconditioner variant of the L > 0 requests
-        if r["desc"]["J"] > 0:
-            r["desc"] = dict(r["desc"], precond=args.serve_precond)
-    t_gen = time.perf_counter()
-    rhs = [W.rhs(r["seed"], W.n_unknowns(r["desc"])) for r in reqs]
-    t_gen = time.perf_counter() - t_gen
-    print(f"serve: {len(reqs)} requests, right-hand sides built in {t_gen:.1f} s", file=sys.stderr, flush=True)
-    srv = fm.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
 
-    def run(indices, arrivals, label):
-        done = {}
-        xs = {}
-        t0 = time.perf_counter()
-        t_report = t0
-        k = 0
-        while len(done) < len(indices):
-            now = time.perf_counter() - t0
-            while k < len(indices) and arrivals[k] <= now:
-                i = indices[k]
-                r = reqs[i]
-                xs[(label, i)] = np.zeros(rhs[i].size)
-                srv.submit(r["desc"], r["E"], rhs[i], xs[(label, i)], i, restart=args.serve_restart,
-                           rtol=1e-10, max_iters=args.serve_max_iters, prec=args.prec)
-                k += 1
-            block = k >= len(indices)
-            for o in srv.poll(block=block):
-                done[o["tag"]] = o
-            if time.perf_counter() - t_report > 20:
-                t_report = time.perf_counter()
-                print(f"serve {label}: {len(done)}/{len(indices)} done, {k} submitted, "
-                      f"{t_report - t0:.0f} s", file=sys.stderr, flush=True)
-            if not block:
-                time.sleep(0.001)
-        return done, time.perf_counter() - t0
-
-    nsat = min(len(reqs), args.saturation_requests) if args.saturation_requests > 0 else len(reqs)
-    sat, sat_wall = run(list(range(nsat)), np.zeros(nsat), "saturation")
-    sat_rate = nsat / sat_wall
-    print(f"serve saturation: {nsat} requests in {sat_wall:.1f} s ({sat_rate:.2f} solves/s)", file=sys.stderr,
-          flush=True)
-    rate = 0.8 * sat_rate
-    arrivals = W.serving_arrivals(len(reqs), rate)
-    done, wall = run(list(range(len(reqs))), arrivals, "poisson")
-    stats = srv.stats()
-    srv.close()
+def serve_summary(done, wall, qlen):
+    """Latency percentiles, status counts and the queue-length trend of one phase."""
+    import numpy as np
     lat = np.array([o["t_done"] - o["t_submit"] for o in done.values()])
     wait = np.array([o["t_start"] - o["t_submit"] for o in done.values() if o["t_start"] > 0])
     status = {}
     for o in done.values():
         status[o["status"]] = status.get(o["status"], 0) + 1
     ok = [o for o in done.values() if o["status"] == "FM_OK"]
-    line = {
-        "metric": "serving: solves/s at rel. residual 1e-10 and p50/p99 latency (Poisson arrivals)",
-        "value": len(ok) / wall, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}", "data": "synthetic",
-        "config": {"workload": "seeded stream: quintic x,y {31,64,97,127} x cubic z {8,16,32}, L in {0,1,2}, "
-                               "E in [-0.6,-0.05], two particle sets, seeded N(0,1) RHS",
-                   "requests": len(reqs), "max_batch": args.max_batch, "restart": args.serve_restart,
-                   "max_iters": args.serve_max_iters, "budget_gb": args.budget_gb,
-                   "precond_L_gt_0": args.serve_precond},
-        "saturation": {"requests": nsat, "solves_per_s": sat_rate, "wall_s": sat_wall,
-                       "ok": sum(1 for o in sat.values() if o["status"] == "FM_OK")},
-        "arrival_rate_per_s": rate,
+    q = np.array([n for _, n in qlen]) if qlen else np.zeros(1)
+    h = max(1, q.size // 2)
+    return {
+        "solves_per_s": len(ok) / wall, "wall_s": wall,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
         "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))}
         if wait.size else None,
+        # requests outstanding (submitted, not yet finished), sampled every 0.25 s: a sustained
+        # rate keeps it flat (second-half mean close to the first-half mean)
+        "outstanding": {"mean_first_half": float(q[:h].mean()), "mean_second_half": float(q[h:].mean())
+                        if q.size > h else float(q.mean()), "max": int(q.max())},
         "status_counts": status,
-        "wall_s": wall,
+        "not_converged_tags": sorted(o["tag"] for o in done.values() if o["status"] == "FM_E_NOT_CONVERGED"),
         "iters_mean": float(np.mean([o["iters"] for o in ok])) if ok else None,
         "max_rel_residual_ok": max(o["rel_residual"] for o in ok) if ok else None,
+    }
+
+
+def serve_run(args, nreq, rates):
+    """The seeded request stream against one server: a saturation phase (the
+    requests submitted all at once, cold: every problem is built as its first
+    request arrives) measures the saturated rate; then one Poisson phase per
+    entry of `rates` (a fraction of the saturated rate) on the same requests,
+    with the problems already built, as a running service has them."""
+    from paper_2005_05398_amd import fm
+    from paper_2005_05398_amd import workloads as W
+    import numpy as np
+
+    reqs = [W.serving_request(i) for i in range(nreq)]
+    for r in reqs:                      # the preconditioner variant of the L > 0 requests
+        if r["desc"]["J"] > 0:
+            r["desc"] = dict(r["desc"], precond=args.serve_precond)
+    rhs = [W.rhs(r["seed"], W.n_unknowns(r["desc"])) for r in reqs]
+    srv = fm.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=args.max_batch)
+    idx = list(range(nreq))
+    sat, sat_wall, _ = serve_phase(srv, reqs, rhs, idx, np.zeros(nreq), "saturation", args)
+    sat_rate = nreq / sat_wall
+    print(f"serve saturation: {nreq} requests in {sat_wall:.1f} s ({sat_rate:.2f} solves/s)", file=sys.stderr,
+          flush=True)
+    phases = {}
+    for frac in rates:
+        rate = frac * sat_rate
+        done, wall, qlen = serve_phase(srv, reqs, rhs, idx, W.serving_arrivals(nreq, rate), f"poisson{frac}", args)
+        phases[f"{frac:g}x_saturated"] = dict(serve_summary(done, wall, qlen), arrival_rate_per_s=rate)
+    stats = srv.stats()
+    srv.close()
+    return {
+        "config": {"workload": "seeded stream: quintic x,y nominal {32,64,96,128} taken as {31,64,97,127} "
+                               "(3K+1 sizes), cubic z {8,16,32}, L in {0,1,2} (tau=+1), E in [-0.6,-0.05], "
+                               "masses (1,1,1) or (1,1,1836), seeded N(0,1) RHS",
+                   "requests": nreq, "max_batch": args.max_batch, "restart": args.serve_restart,
+                   "max_iters": args.serve_max_iters, "budget_gb": args.budget_gb,
+                   "precond_L_gt_0": args.serve_precond, "products": args.serve_prec},
+        "saturation": {"requests": nreq, "solves_per_s": sat_rate, "wall_s": sat_wall,
+                       "ok": sum(1 for o in sat.values() if o["status"] == "FM_OK"),
+                       "not_converged_tags": sorted(o["tag"] for o in sat.values()
+                                                    if o["status"] == "FM_E_NOT_CONVERGED")},
+        "poisson": phases,
         "server_end": stats,
+    }
+
+
+def serve_bench(args):
+    """Serving: the whole seeded stream; Poisson arrivals at a rate the server
+    sustains and at an overload rate, each reported on its own."""
+    out = serve_run(args, args.requests, (args.serve_rate, 0.8))
+    sus = out["poisson"][f"{args.serve_rate:g}x_saturated"]
+    line = {
+        "metric": "serving: solves/s at rel. residual 1e-10 and p50/p99 latency (Poisson arrivals)",
+        "value": sus["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64" if args.serve_prec == "fp64" else f"f64+{args.serve_prec}", "data": "synthetic",
+        **out,
     }
     print(json.dumps(line))
 
@@ -283,6 +325,162 @@ def measured_traffic(workload, kclass):
     return e["hbm_bytes_per_launch"]
 
 
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (vector and dense matrix)
+BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 matrix
+MFMA_PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS,
+             # BF16x3: three BF16 products per product of the definition
+             "bf16x3": BF16_PEAK_TFLOPS / 3.0}
+
+
+def kernel_table(prof):
+    """Per kernel class: summed HIP-event time, launches, average launch and
+    algorithmic GB/s and TFLOP/s."""
+    kernels = {}
+    for k, v in prof.items():
+        if v["launches"] == 0:
+            continue
+        s = v["ms"] * 1e-3
+        kernels[k] = {"ms": round(v["ms"], 3), "launches": v["launches"],
+                      "avg_launch_ms": v["ms"] / v["launches"],
+                      "GB/s": v["bytes"] / s / 1e9 if s > 0 else None,
+                      "TFLOP/s": v["flops"] / s / 1e12 if s > 0 else None}
+    return kernels
+
+
+def roofline_of(kernels, prec, traffic_key=None):
+    """Roofline of the kernel class with the largest time share: the x-y
+    products against the MFMA peak of their arithmetic, the operator classes
+    against the FP64 peak (ALU-bound), everything else against HBM."""
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    d = kernels[dom]
+    if dom == "xy":
+        roof = {"bound": "mfma", "achieved": d["TFLOP/s"], "peak": MFMA_PEAK[prec], "unit": "TFLOP/s"}
+    elif dom in ("matvec", "coupling"):
+        roof = {"bound": "alu", "achieved": d["TFLOP/s"], "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update({"kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
+                 "traffic": measured_traffic(traffic_key, dom) if traffic_key else None})
+    return roof
+
+
+def measure(P, Es, B, X, restart, prec, steps, warmup, stream, profile=True, traffic_key=None):
+    """Solves/s of `steps` fm_solve calls on the whole batch with nothing but
+    the solves in the timed region; then (profile=True) the same number of
+    calls again with the library's per-launch HIP events on the solve's
+    stream, for the kernel shares and the roofline."""
+    import numpy as np
+    import torch
+    from paper_2005_05398_amd import fm
+
+    def step():
+        st, res = P.solve(Es, B, X, restart=restart, rtol=1e-10, max_iters=20000, prec=prec, stream=stream)
+        if st != fm.FM_OK:
+            raise RuntimeError(f"solve failed: {fm.STATUS_NAMES.get(st)} {res}")
+        return res
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nreq = len(Es)
+    iters = [r["iters"] for r in res]
+    out = {"solves_per_s": nreq * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
+           "max_rel_residual": max(r["rel_residual"] for r in res)}
+    if profile:
+        P.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el_p = time.perf_counter() - t0
+        prof = P.profile_read()
+        P.profile(False)
+        kernels = kernel_table(prof)
+        total = sum(v["ms"] for v in prof.values())
+        out["profiled_ms_per_step"] = 1e3 * el_p / steps
+        out["kernel_ms_share"] = {k: round(v["ms"] / total, 4) for k, v in prof.items() if v["launches"]}
+        out["kernels"] = kernels
+        out["roofline"] = roofline_of(kernels, prec, traffic_key)
+        if "xy" in kernels:
+            out["mfma"] = {"kernel": "xy", "achieved_TFLOP/s": kernels["xy"]["TFLOP/s"],
+                           "peak_TFLOP/s": MFMA_PEAK[prec],
+                           "frac": kernels["xy"]["TFLOP/s"] / MFMA_PEAK[prec]}
+    return out
+
+
+def workload_entry(name, args, precs, precond="block_jacobi", restart=None, profile=True, traffic=False):
+    """One workload at several precisions of the preconditioner products; the
+    error of each solution against the FP64 GPU solution of the same batch."""
+    import torch
+    from paper_2005_05398_amd import fm
+    from paper_2005_05398_amd import workloads as W
+    c = W.WORKLOADS[name]()
+    restart = restart or (300 if name == "hminus_scan" else 30 if name == "ps_cubic16" else 60)
+    t0 = time.perf_counter()
+    P = fm.Problem(dict(c["desc"], precond=precond))
+    setup_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    B = torch.as_tensor(W.rhs_batch(c["seeds"], P.N), device=dev)
+    X = torch.zeros_like(B)
+    stream = torch.cuda.current_stream()
+    out = {"N_per_request": P.N, "requests_per_step": len(c["E"]), "restart": restart, "precond": precond,
+           "setup_s": setup_s}
+    X64 = None
+    for prec in precs:
+        key = None
+        if traffic:
+            key = traffic_variant(argparse.Namespace(workload=name, exchange=0, precond=precond, prec=prec,
+                                                     restart=restart))
+        e = measure(P, c["E"], B, X, restart, prec, args.steps, args.warmup, stream, profile=profile,
+                    traffic_key=key)
+        if prec == "fp64":
+            X64 = X.clone()
+        elif X64 is not None:
+            e["max_rel_error_vs_fp64_gpu"] = (torch.linalg.norm(X - X64, dim=1) /
+                                              torch.linalg.norm(X64, dim=1)).max().item()
+        out[prec] = e
+        print(f"bench: {name} {precond} {prec}: {e['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    P.close()
+    return out
+
+
+def oracle_lu_timing():
+    """The oracle on the small workload (cubic 16 x 16 x 8, N = 6144): assembly,
+    dense LU factorisation and the solve, timed separately on this host."""
+    import numpy as np
+    from oracle.assemble import Problem as OracleProblem
+    from oracle.solve import rel_residual
+    import scipy.linalg as sla
+    from paper_2005_05398_amd import workloads as W
+    c = W.ps_cubic16()
+    t0 = time.perf_counter()
+    O = OracleProblem(c["desc"])
+    A = O.assemble(c["E"][0])
+    t1 = time.perf_counter()
+    lu = sla.lu_factor(A.toarray())
+    t2 = time.perf_counter()
+    b = W.rhs(c["seeds"][0], O.N)
+    x = sla.lu_solve(lu, b)
+    t3 = time.perf_counter()
+    return {"N": O.N, "assembly_s": t1 - t0, "lu_factor_s": t2 - t1, "lu_solve_s": t3 - t2,
+            "rel_residual": rel_residual(A, x, b), "threads": blas_threads()}
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,12 +496,19 @@ def main():
                     help="preconditioner variant (coupled: the approximate matrix with its M'+-1 blocks, L > 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the reduced-precision comparison runs")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-GPU workloads (small cubic, ps_q127, ps_l2_q97, serving sample)")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--saturation-requests", type=int, default=0, help="requests of the saturation phase (0: all)")
+    ap.add_argument("--serve-sample", type=int, default=96,
+                    help="requests of the serving sample in the default run (0: none)")
+    ap.add_argument("--serve-rate", type=float, default=0.4,
+                    help="Poisson arrival rate as a fraction of the saturated rate (the sustained phase)")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--serve-restart", type=int, default=200)
     ap.add_argument("--serve-max-iters", type=int, default=6000)
+    ap.add_argument("--serve-prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the preconditioner products in the serving stream")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-precond", default="coupled", choices=["block_jacobi", "coupled"],
                     help="preconditioner of the L > 0 requests in the serving stream")
@@ -349,13 +554,6 @@ def main():
     X = torch.zeros_like(B)
     stream = torch.cuda.current_stream()
 
-    def step():
-        st, res = P.solve(Es, B, X, restart=args.restart, rtol=1e-10, max_iters=20000, prec=args.prec,
-                          stream=stream)
-        if st != fm.FM_OK:
-            raise RuntimeError(f"solve failed: {fm.STATUS_NAMES.get(st)} {res}")
-        return res
-
     if args.calibrate_copy:
         src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -363,54 +561,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    P.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = P.profile_read()
-    P.profile(False)
-
-    iters = [r["iters"] for r in res]
-    relres = [r["rel_residual"] for r in res]
-    value = nreq * args.steps / elapsed
-    # per-class achieved rates; roofline of the class with the largest time share
-    BOUND = {"xy": ("mfma", FP64_PEAK_TFLOPS), "matvec": ("alu", FP64_PEAK_TFLOPS),
-             "coupling": ("alu", FP64_PEAK_TFLOPS)}
-    kernels = {}
-    for k, v in prof.items():
-        if v["launches"] == 0:
-            continue
-        s = v["ms"] * 1e-3
-        kernels[k] = {"ms": round(v["ms"], 3), "launches": v["launches"],
-                      "avg_launch_ms": v["ms"] / v["launches"],
-                      "GB/s": v["bytes"] / s / 1e9 if s > 0 else None,
-                      "TFLOP/s": v["flops"] / s / 1e12 if s > 0 else None}
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    d = kernels[dom]
-    if dom in BOUND:
-        bound, peak = BOUND[dom]
-        roof = {"bound": bound, "achieved": d["TFLOP/s"], "peak": peak, "unit": "TFLOP/s",
-                "frac": d["TFLOP/s"] / peak}
-    else:
-        roof = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["GB/s"] / HBM_PEAK_GBS}
-    roof.update({"kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
-                 "traffic": measured_traffic(traffic_variant(args), dom)})
-    total_kernel_ms = sum(v["ms"] for v in prof.values())
+    head = measure(P, Es, B, X, args.restart, args.prec, args.steps, args.warmup, stream,
+                   traffic_key=traffic_variant(args))
+    print(f"bench: {args.workload} {args.prec}: {head['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     line = {
         "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "hminus_scan"
                    else f"solves/s to rel. residual 1e-10 ({args.workload})"),
-        "value": value,
+        "value": head["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -420,38 +582,55 @@ def main():
                    "N_per_request": P.N, "requests_per_step": nreq, "restart": args.restart,
                    "precond": args.precond, "precond_products": args.prec, "rtol": 1e-10,
                    "exchange": args.exchange},
-        "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
-        "max_rel_residual": max(relres),
+        "iters": head["iters"],
+        "max_rel_residual": head["max_rel_residual"],
         "setup_s": t_setup,
-        "kernel_ms_share": {k: round(v["ms"] / total_kernel_ms, 4) for k, v in prof.items() if v["launches"]},
-        "kernels": kernels,
-        "roofline": roof,
+        "profiled_ms_per_step": head.get("profiled_ms_per_step"),
+        "kernel_ms_share": head.get("kernel_ms_share"),
+        "kernels": head.get("kernels"),
+        "roofline": head.get("roofline"),
+        "mfma": head.get("mfma"),
     }
     if not args.no_mixed:
-        # the same workload with the preconditioner's products in FP32 / BF16x3 MFMA; FP64 Arnoldi,
-        # residual and divide; error of each solution against the FP64 GPU solution
+        # the same batch with the preconditioner's products in FP32 / BF16x3 MFMA (FP64 Arnoldi,
+        # residual and divide), timed exactly as the FP64 run; error against the FP64 GPU solution
         X64 = X.clone()
         mixed = {}
         for prec in ("fp32", "bf16x3"):
-            def step_lp():
-                st, res = P.solve(Es, B, X, restart=args.restart, rtol=1e-10, max_iters=20000, prec=prec,
-                                  stream=stream)
-                if st != fm.FM_OK:
-                    raise RuntimeError(f"solve failed: {fm.STATUS_NAMES.get(st)} {res}")
-                return res
-            step_lp()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                res_lp = step_lp()
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t1
-            err = (torch.linalg.norm(X - X64, dim=1) / torch.linalg.norm(X64, dim=1)).max().item()
-            mixed[prec] = {"solves_per_s": nreq * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-                           "iters_mean": float(np.mean([r["iters"] for r in res_lp])),
-                           "max_rel_residual": max(r["rel_residual"] for r in res_lp),
-                           "max_rel_error_vs_fp64_gpu": err}
+            if prec == args.prec:
+                continue
+            key = traffic_variant(argparse.Namespace(**dict(vars(args), prec=prec)))
+            e = measure(P, Es, B, X, args.restart, prec, args.steps, args.warmup, stream, traffic_key=key)
+            e["max_rel_error_vs_fp64_gpu"] = (torch.linalg.norm(X - X64, dim=1) /
+                                              torch.linalg.norm(X64, dim=1)).max().item()
+            e["speedup_vs_fp64"] = e["solves_per_s"] / head["solves_per_s"]
+            mixed[prec] = e
+            print(f"bench: {args.workload} {prec}: {e['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
         line["mixed_precision"] = mixed
+    P.close()
+    del B, X
+    if not args.no_configs and args.workload == "hminus_scan":
+        torch.cuda.empty_cache()
+        cfgs = {}
+        small = workload_entry("ps_cubic16", args, ("fp64",), restart=30)
+        small["config"] = "cubic 16x16x8 on [0,20]^2, Ps- like (1,1,1)/(+1,-1,-1), L=0, E=-0.25, GMRES(30), N=6144"
+        if not args.no_cpu_baseline:
+            small["oracle_dense_lu"] = oracle_lu_timing()
+        cfgs["ps_cubic16"] = small
+        q = workload_entry("ps_q127", args, ("fp64", "fp32", "bf16x3"), traffic=True)
+        q["config"] = ("quintic x,y 127 (the nominal 128 taken as 3K+1 = 127) x cubic z 32 on [0,20]^2, "
+                       "Ps- like, L=0, E=-0.25, FGMRES(60)")
+        cfgs["ps_q127"] = q
+        l2 = {"config": "L=2 tau=+1 (3 M' blocks), quintic x,y 97 (the nominal 96 taken as 3K+1 = 97) x cubic z 32 "
+                        "on [0,20]^2, Ps- like, E=-0.2, FGMRES(60); FP32 products (FP64 for reference)"}
+        for pc in ("block_jacobi", "coupled"):
+            l2[pc] = workload_entry("ps_l2_q97", args, ("fp32", "fp64"), precond=pc, traffic=True)
+        cfgs["ps_l2_q97"] = l2
+        torch.cuda.empty_cache()
+        if args.serve_sample > 0:
+            sv = serve_run(args, args.serve_sample, (args.serve_rate,))
+            cfgs["serving_sample"] = sv
+        line["configs"] = cfgs
     if not args.no_cpu_baseline and args.workload == "hminus_scan":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))

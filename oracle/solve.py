@@ -37,6 +37,27 @@ def rel_residual(A, x, b):
     return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
 
 
+def rel_residuals_by_rows(prob, Es, X, B, chunk=16384, progress=None):
+    """||b_r - A(E_r) x_r|| / ||b_r|| for several requests without holding the
+    matrix: the rows of H = A(0) and of A(1) are assembled a chunk at a time
+    (the residual-only mode for systems too large to factor or to store), and
+    A(E) x = H x - E S x with S = A(0) - A(1) (Sec. 3.1: A(E) = H - E S).
+    Es: energies; X, B: arrays of shape (len(Es), N)."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    B = np.atleast_2d(np.asarray(B, dtype=np.float64))
+    ss = np.zeros(len(Es))
+    for start in range(0, prob.N, chunk):
+        idx = np.arange(start, min(prob.N, start + chunk))
+        H = prob.rows(0.0, idx)
+        S = H - prob.rows(1.0, idx)
+        for r, E in enumerate(Es):
+            res = B[r, idx] - (H @ X[r] - E * (S @ X[r]))
+            ss[r] += float(res @ res)
+        if progress is not None:
+            progress(idx[-1] + 1, prob.N)
+    return np.sqrt(ss) / np.linalg.norm(B, axis=1)
+
+
 def precond_reference(prob, E, r, couple_m=False):
     """z = L(E)^{-1} r with L the block-diagonal separable operator."""
     L = prob.separable(E, couple_m=couple_m).tocsc()

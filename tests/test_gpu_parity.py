@@ -57,6 +57,9 @@ OP_CASES = [
     ("L1_tau-1", small(W.H_MINUS, 7, 6, J=1, tau=-1, dz=5)),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
     ("cubic_ragged_10x6", small(W.PS_MINUS, 10, 6, dxy=3, dz=3)),
+    # finite y0 of the cut-off (eq. (Mcutoff0)): V^(s) and the potential field depend on y
+    ("hminus_finite_y0", dict(small(W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"), y0=6.0)),
+    ("L2_finite_y0", dict(small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3), y0=2.5)),
 ] + WIDE_CASES
 
 

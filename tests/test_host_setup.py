@@ -121,6 +121,9 @@ COUPLING_CASES = [
     ("quintic_cubicz_L1", W.make_desc(*W.PS_MINUS, 10, 6, J=1, deg_z=3, R=15.0)),
     ("quintic_L1_odd", W.make_desc(*W.PS_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0)),
     ("quintic_L2", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0)),
+    # finite y0 of the cut-off (eq. (Mcutoff0)): V^(s) depends on y as well
+    ("quintic_hminus_L0_y0", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic", y0=6.0)),
+    ("quintic_L2_y0", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0, y0=3.0)),
 ]
 
 

@@ -29,9 +29,10 @@ from paper_2005_05398_amd import workloads as W
 P = np.polynomial.polynomial
 
 
-def small_desc(masses_charges, nxy=7, nz=6, J=0, tau=1, deg_xy=5, deg_z=5, R=12.0, xy_map="uniform"):
+def small_desc(masses_charges, nxy=7, nz=6, J=0, tau=1, deg_xy=5, deg_z=5, R=12.0, xy_map="uniform",
+               y0=W.INF):
     return W.make_desc(*masses_charges, nxy, nz, J=J, tau=tau, deg_xy=deg_xy, deg_z=deg_z, R=R,
-                       xy_map=xy_map, x0=3.0)
+                       xy_map=xy_map, x0=3.0, y0=y0)
 
 
 def manufactured(prob, rng):
@@ -92,15 +93,18 @@ def analytic(prob, polys, E):
     return out
 
 
-@pytest.mark.parametrize("mc,J,tau,deg_xy,deg_z,nxy,nz,xy_map", [
-    (W.PS_MINUS, 0, 1, 5, 5, 7, 6, "uniform"),
-    (W.H_MINUS, 0, 1, 5, 5, 10, 9, "quadratic"),
-    (W.PS_MINUS, 0, 1, 3, 3, 6, 4, "uniform"),
-    (W.PS_MINUS, 2, 1, 5, 3, 7, 4, "uniform"),
-    (W.H_MINUS, 1, -1, 3, 5, 6, 6, "uniform"),
+@pytest.mark.parametrize("mc,J,tau,deg_xy,deg_z,nxy,nz,xy_map,y0", [
+    (W.PS_MINUS, 0, 1, 5, 5, 7, 6, "uniform", W.INF),
+    (W.H_MINUS, 0, 1, 5, 5, 10, 9, "quadratic", W.INF),
+    (W.PS_MINUS, 0, 1, 3, 3, 6, 4, "uniform", W.INF),
+    (W.PS_MINUS, 2, 1, 5, 3, 7, 4, "uniform", W.INF),
+    (W.H_MINUS, 1, -1, 3, 5, 6, 6, "uniform", W.INF),
+    # a finite y0: the cut-off and V^(s) depend on y as well (eq. (Mcutoff0))
+    (W.H_MINUS, 0, 1, 5, 5, 10, 9, "quadratic", 4.0),
+    (W.PS_MINUS, 2, 1, 5, 3, 7, 4, "uniform", 2.5),
 ])
-def test_manufactured_solution(mc, J, tau, deg_xy, deg_z, nxy, nz, xy_map):
-    prob = Problem(small_desc(mc, nxy, nz, J, tau, deg_xy, deg_z, xy_map=xy_map))
+def test_manufactured_solution(mc, J, tau, deg_xy, deg_z, nxy, nz, xy_map, y0):
+    prob = Problem(small_desc(mc, nxy, nz, J, tau, deg_xy, deg_z, xy_map=xy_map, y0=y0))
     rng = np.random.default_rng(3 + J)
     polys, c = manufactured(prob, rng)
     E = -0.3
@@ -174,3 +178,23 @@ def test_block_form_matches_pointwise_assembly(J):
         Sa = (prob.rows(0.0, np.arange(o, o + n)) - prob.rows(1.0, np.arange(o, o + n))).toarray()[:, o:o + n]
         want = L + np.tile(extra, prob.nM)[:, None] * Sa
         assert np.abs(A[o:o + n, o:o + n] - want).max() <= 1e-11 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("J", [0, 2])
+def test_residual_by_row_chunks_matches_assembled(J):
+    """The residual-only mode (rows of H and of A(1) assembled a chunk at a
+    time, A(E) x = H x - E S x) equals the residual with the whole assembled
+    A(E), for several energies, chunks with a ragged last one, and an x whose
+    residual is small (an LU solution perturbed by 1e-9) or large (random)."""
+    from oracle.solve import lu_solve, rel_residual, rel_residuals_by_rows
+    prob = Problem(small_desc(W.PS_MINUS, 7, 4, J=J, tau=1, deg_z=3))
+    rng = np.random.default_rng(11)
+    Es = [-0.31, -0.05, 0.2]
+    B = rng.standard_normal((3, prob.N))
+    X = np.stack([lu_solve(prob.assemble(E), b) for E, b in zip(Es, B)])
+    X[0] += 1e-9 * rng.standard_normal(prob.N)
+    X[2] = rng.standard_normal(prob.N)
+    got = rel_residuals_by_rows(prob, Es, X, B, chunk=97)
+    want = [rel_residual(prob.assemble(E), x, b) for E, x, b in zip(Es, X, B)]
+    np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-13)   # rounding of a 1e-14 residual
+    assert got[1] < 1e-12 and got[0] > 1e-11
