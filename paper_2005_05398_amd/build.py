@@ -29,17 +29,23 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", path, "-o", obj]
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
+        cmds.append([HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", path, "-o", obj])
         objs.append(obj)
+    # the kernels file first: it takes most of the time
+    order = sorted(range(len(cmds)), key=lambda i: not SOURCES[i].endswith(".hip"))
+    with ThreadPoolExecutor(max_workers=jobs or min(8, os.cpu_count() or 1)) as ex:
+        outs = list(ex.map(lambda i: _run(cmds[i]), order))
+    if verbose:
+        for out in outs:
+            if out.strip():
+                print(out)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)
