@@ -180,6 +180,20 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
 fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
                    const fm_solve_opts *opts, fm_solve_result *results, void *stream);
 
+/* Allocation-free variant of fm_apply_operator, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, result and errors as
+ * fm_apply_operator.  Its scratch (the energies on the device and the two
+ * coupling slots, 2 * nbatch * N doubles) lives in one static device array of
+ * 64 MiB (8 Mi doubles, the first 4096 for the energies) per GPU, held until
+ * the process ends; nothing is allocated or freed.  FM_E_INVALID when
+ * nbatch > 4096 or 2 * nbatch * N > 8 Mi - 4096.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (several threads or streams) race;
+ * calls one after another are safe, each clearing the slots it uses.  Returns
+ * after the stream has finished the work. */
+fm_status fm_apply_operator_noalloc(fm_problem *p, int nbatch, const double *E, const double *x_dev,
+                                    double *y_dev, void *stream);
+
 /* y = S x for nbatch requests: S holds the basis products at the collocation
  * points (Sec. 3.1; the right-hand matrix of H c = E S c), block diagonal over
  * (alpha, M').  x_dev, y_dev: nbatch * N doubles, not overlapping.  Errors:

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["basis.cpp", "linalg.cpp", "setup.cpp", "coupled.cpp", "coupling.cpp", "api.cpp", "eigs.cpp", "host_api.cpp", "serve.cpp", "kernels.hip"]
+SOURCES = ["basis.cpp", "linalg.cpp", "setup.cpp", "coupled.cpp", "coupling.cpp", "api.cpp", "eigs.cpp", "host_api.cpp", "serve.cpp", "noalloc.cpp", "kernels.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 # gfx950 only; packed-FP32 instructions disabled in device code
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -85,12 +85,14 @@ def lib():
         L.fm_apply_precond.argtypes = [vp, ci, pd, vp, vp, ci, vp]
         L.fm_solve.argtypes = [vp, ci, pd, vp, vp, ctypes.POINTER(FmSolveOpts), ctypes.POINTER(FmSolveResult), vp]
         L.fm_apply_mass.argtypes = [vp, ci, vp, vp, vp]
+        L.fm_apply_operator_noalloc.argtypes = [vp, ci, pd, vp, vp, vp]
         L.fm_eigs.argtypes = [vp, cd, ctypes.POINTER(FmEigsOpts), vp, pd, pd, pd, vp, ctypes.POINTER(FmEigsInfo),
                               vp]
         L.fm_profile.argtypes = [vp, ci]
         L.fm_profile_read.argtypes = [vp, ci, pd, ctypes.POINTER(ctypes.c_longlong), pd, pd]
         for f in ("fm_create_problem", "fm_destroy_problem", "fm_problem_info", "fm_apply_operator",
-                  "fm_apply_precond", "fm_solve", "fm_profile", "fm_profile_read", "fm_apply_mass", "fm_eigs"):
+                  "fm_apply_precond", "fm_solve", "fm_profile", "fm_profile_read", "fm_apply_mass", "fm_eigs",
+                  "fm_apply_operator_noalloc"):
             getattr(L, f).restype = ci
         _lib = L
     return _lib
@@ -176,6 +178,14 @@ class Problem:
         Ec, nb = _energies(E)
         _check(lib().fm_apply_operator(self._h, nb, Ec, _ptr(x, nb * self.N, "x"), _ptr(y, nb * self.N, "y"),
                                        _stream(stream)))
+        return y
+
+    def apply_operator_noalloc(self, E, x, y, stream=None):
+        """fm_apply_operator_noalloc: the operator with its scratch in the
+        library's static device array (nothing allocated)."""
+        Ec, nb = _energies(E)
+        _check(lib().fm_apply_operator_noalloc(self._h, nb, Ec, _ptr(x, nb * self.N, "x"),
+                                               _ptr(y, nb * self.N, "y"), _stream(stream)))
         return y
 
     def apply_precond(self, E, r, z, prec="fp64", stream=None):
