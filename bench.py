@@ -365,7 +365,7 @@ def roofline_of(kernels, prec, traffic_key=None):
     return roof
 
 
-def measure(P, Es, B, X, restart, prec, steps, warmup, stream, profile=True, traffic_key=None):
+def measure(P, Es, B, X, restart, prec, steps, warmup, stream, profile=True, traffic_key=None, graphs=True):
     """Solves/s of `steps` fm_solve calls on the whole batch with nothing but
     the solves in the timed region; then (profile=True) the same number of
     calls again with the library's per-launch HIP events on the solve's
@@ -375,7 +375,8 @@ def measure(P, Es, B, X, restart, prec, steps, warmup, stream, profile=True, tra
     from paper_2005_05398_amd import fm
 
     def step():
-        st, res = P.solve(Es, B, X, restart=restart, rtol=1e-10, max_iters=20000, prec=prec, stream=stream)
+        st, res = P.solve(Es, B, X, restart=restart, rtol=1e-10, max_iters=20000, prec=prec, stream=stream,
+                          graphs=graphs)
         if st != fm.FM_OK:
             raise RuntimeError(f"solve failed: {fm.STATUS_NAMES.get(st)} {res}")
         return res
@@ -390,7 +391,7 @@ def measure(P, Es, B, X, restart, prec, steps, warmup, stream, profile=True, tra
     elapsed = time.perf_counter() - t0
     nreq = len(Es)
     iters = [r["iters"] for r in res]
-    out = {"solves_per_s": nreq * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+    out = {"solves_per_s": nreq * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "graphs": bool(graphs),
            "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
            "max_rel_residual": max(r["rel_residual"] for r in res)}
     if profile:
@@ -415,7 +416,8 @@ def measure(P, Es, B, X, restart, prec, steps, warmup, stream, profile=True, tra
     return out
 
 
-def workload_entry(name, args, precs, precond="block_jacobi", restart=None, profile=True, traffic=False):
+def workload_entry(name, args, precs, precond="block_jacobi", restart=None, profile=True, traffic=False,
+                   compare_eager=False):
     """One workload at several precisions of the preconditioner products; the
     error of each solution against the FP64 GPU solution of the same batch."""
     import torch
@@ -439,7 +441,13 @@ def workload_entry(name, args, precs, precond="block_jacobi", restart=None, prof
             key = traffic_variant(argparse.Namespace(workload=name, exchange=0, precond=precond, prec=prec,
                                                      restart=restart))
         e = measure(P, c["E"], B, X, restart, prec, args.steps, args.warmup, stream, profile=profile,
-                    traffic_key=key)
+                    traffic_key=key, graphs=bool(args.graphs))
+        if compare_eager:
+            # the same solves launched one kernel at a time (no captured graphs)
+            ee = measure(P, c["E"], B, X, restart, prec, args.steps, args.warmup, stream, profile=False,
+                         graphs=False)
+            e["eager_solves_per_s"] = ee["solves_per_s"]
+            e["eager_ms_per_step"] = ee["ms_per_step"]
         if prec == "fp64":
             X64 = X.clone()
         elif X64 is not None:
@@ -494,6 +502,8 @@ def main():
                          "two electrons); 0: the full three-component system")
     ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "coupled"],
                     help="preconditioner variant (coupled: the approximate matrix with its M'+-1 blocks, L > 0)")
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
+                    help="1: Arnoldi steps replayed from captured HIP graphs; 0: one launch at a time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the reduced-precision comparison runs")
     ap.add_argument("--no-configs", action="store_true",
@@ -562,7 +572,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     head = measure(P, Es, B, X, args.restart, args.prec, args.steps, args.warmup, stream,
-                   traffic_key=traffic_variant(args))
+                   traffic_key=traffic_variant(args), graphs=bool(args.graphs))
+    if args.graphs:
+        ee = measure(P, Es, B, X, args.restart, args.prec, args.steps, args.warmup, stream, profile=False,
+                     graphs=False)
+        head["eager_solves_per_s"] = ee["solves_per_s"]
     print(f"bench: {args.workload} {args.prec}: {head['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     line = {
         "metric": ("solves/s to rel. residual 1e-10 (FP64, batched energy scan)" if args.workload == "hminus_scan"
@@ -581,7 +595,8 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "N_per_request": P.N, "requests_per_step": nreq, "restart": args.restart,
                    "precond": args.precond, "precond_products": args.prec, "rtol": 1e-10,
-                   "exchange": args.exchange},
+                   "exchange": args.exchange, "graphs": bool(args.graphs)},
+        "eager_solves_per_s": head.get("eager_solves_per_s"),
         "iters": head["iters"],
         "max_rel_residual": head["max_rel_residual"],
         "setup_s": t_setup,
@@ -600,7 +615,8 @@ def main():
             if prec == args.prec:
                 continue
             key = traffic_variant(argparse.Namespace(**dict(vars(args), prec=prec)))
-            e = measure(P, Es, B, X, args.restart, prec, args.steps, args.warmup, stream, traffic_key=key)
+            e = measure(P, Es, B, X, args.restart, prec, args.steps, args.warmup, stream, traffic_key=key,
+                        graphs=bool(args.graphs))
             e["max_rel_error_vs_fp64_gpu"] = (torch.linalg.norm(X - X64, dim=1) /
                                               torch.linalg.norm(X64, dim=1)).max().item()
             e["speedup_vs_fp64"] = e["solves_per_s"] / head["solves_per_s"]
@@ -612,7 +628,7 @@ def main():
     if not args.no_configs and args.workload == "hminus_scan":
         torch.cuda.empty_cache()
         cfgs = {}
-        small = workload_entry("ps_cubic16", args, ("fp64",), restart=30)
+        small = workload_entry("ps_cubic16", args, ("fp64",), restart=30, compare_eager=True)
         small["config"] = "cubic 16x16x8 on [0,20]^2, Ps- like (1,1,1)/(+1,-1,-1), L=0, E=-0.25, GMRES(30), N=6144"
         if not args.no_cpu_baseline:
             small["oracle_dense_lu"] = oracle_lu_timing()

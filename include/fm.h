@@ -107,6 +107,9 @@ typedef struct {
     int max_iters;            /* total Arnoldi steps per request */
     int prec;                 /* fm_precision of the preconditioner's products */
     int x0_is_guess;          /* 1: x_dev holds the initial guess; 0: start from x = 0 */
+    int graphs;               /* 1: the Arnoldi steps run as replays of HIP graphs captured on first use
+                                 (four steps per graph, kept with the problem's workspace); 0: launched
+                                 one kernel at a time.  Results are the same either way */
 } fm_solve_opts;
 
 typedef struct {

@@ -100,6 +100,7 @@ struct Small {
 fm_status ensure_small(fm_problem *p, int nb, Small &s) {
     size_t need = round256(sizeof(double) * nb) * 2 + round256(sizeof(int) * nb) * 2;
     if (p->ws_small_bytes < need) {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         if (p->ws_small) (void)hipFree(p->ws_small);
         p->ws_small = nullptr;
         p->ws_small_bytes = 0;
@@ -119,6 +120,7 @@ fm_status ensure_small(fm_problem *p, int nb, Small &s) {
 
 fm_status ensure_pinned(fm_problem *p, size_t bytes) {
     if (p->host_pinned_bytes >= bytes) return FM_OK;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     if (p->host_pinned) (void)hipHostFree(p->host_pinned);
     p->host_pinned = nullptr;
     p->host_pinned_bytes = 0;
@@ -177,9 +179,12 @@ char *carve_krylov(char *c, long long N, int nb, int m, KrylovDev &K) {
 }
 
 // -- per-kernel-class timing ---------------------------------------------
+// Set while this thread enqueues work under stream capture: no events then.
+thread_local bool t_capturing = false;
+
 size_t prof_mark(fm_problem *p, hipStream_t st) {
     Profile &pf = p->prof;
-    if (!pf.on) return SIZE_MAX;
+    if (!pf.on || t_capturing) return SIZE_MAX;
     if (pf.next == pf.ev.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
@@ -322,6 +327,7 @@ size_t Batch::footprint(const fm_problem *p, int cap, int m) {
 }
 
 fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     p = pp;
     cap = c;
     m = mm;
@@ -364,10 +370,72 @@ fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
 }
 
 void Batch::release() {
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
+    for (hipGraphExec_t g : gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    gexec.clear();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    cap_st = nullptr;
     if (mem) (void)hipFree(mem);
     if (hbuf) (void)hipHostFree(hbuf);
     mem = nullptr;
     hbuf = nullptr;
+}
+
+void Batch::enqueue_step(int j, hipStream_t s, bool profile) {
+    const int nb = cap;
+    const long long N = p->N;
+    double *Vj = K.V + (long long)j * nb * N;
+    double *Zj = K.Z + (long long)j * nb * N;
+    double *Vn = K.V + (long long)(j + 1) * nb * N;
+    if (profile) {
+        apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, ptmp, s);
+        apply_operator(p, nb, K.E, K.active, Zj, Vn, cbuf, s);
+        timed(p, s, FM_K_MDOT, [&] { launch_arnoldi_dots(K, j, 0, s); });
+        timed(p, s, FM_K_FINISH, [&] { launch_arnoldi_finish(K, j, 0, s); });
+        timed(p, s, FM_K_MUPDATE, [&] { launch_arnoldi_update(K, j, s); });
+        return;
+    }
+    // the same launches without the profiling events (used under capture)
+    t_capturing = true;
+    apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, ptmp, s);
+    apply_operator(p, nb, K.E, K.active, Zj, Vn, cbuf, s);
+    t_capturing = false;
+    launch_arnoldi_dots(K, j, 0, s);
+    launch_arnoldi_finish(K, j, 0, s);
+    launch_arnoldi_update(K, j, s);
+}
+
+hipGraphExec_t Batch::step_graph(int j0, int n) {
+    const int groups = (m + GRAPH_STEPS - 1) / GRAPH_STEPS;
+    if (gexec.empty()) gexec.assign(size_t(3) * groups, nullptr);
+    const size_t idx = size_t(prec) * groups + j0 / GRAPH_STEPS;
+    if (gexec[idx]) return gexec[idx];
+    if (graphs_failed) return nullptr;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
+    if (!cap_st && hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking) != hipSuccess) {
+        cap_st = nullptr;
+        graphs_failed = true;
+        return nullptr;
+    }
+    (void)hipGetLastError();
+    if (hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        graphs_failed = true;
+        return nullptr;
+    }
+    for (int j = j0; j < j0 + n; ++j) enqueue_step(j, cap_st, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(cap_st, &g);
+    hipGraphExec_t ex = nullptr;
+    if (e_end != hipSuccess || !g || hipGetLastError() != hipSuccess ||
+        hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        ex = nullptr;
+        graphs_failed = true;        // this batch launches eagerly from now on
+        (void)hipGetLastError();     // a failed capture must not fail the next checked call
+    }
+    if (g) (void)hipGraphDestroy(g);
+    gexec[idx] = ex;
+    return ex;
 }
 
 bool Batch::any_running() const {
@@ -450,20 +518,19 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
 
 fm_status Batch::cycle(const std::function<bool()> &want_cut, int min_steps) {
     const int nb = cap;
-    const long long N = p->N;
-    const int poll = 4;
+    const int poll = GRAPH_STEPS;
     int steps = 0;
-    for (int j = 0; j < m; ++j) {
-        double *Vj = K.V + (long long)j * nb * N;
-        double *Zj = K.Z + (long long)j * nb * N;
-        double *Vn = K.V + (long long)(j + 1) * nb * N;
-        apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, ptmp, st);
-        apply_operator(p, nb, K.E, K.active, Zj, Vn, cbuf, st);
-        timed(p, st, FM_K_MDOT, [&] { launch_arnoldi_dots(K, j, 0, st); });
-        timed(p, st, FM_K_FINISH, [&] { launch_arnoldi_finish(K, j, 0, st); });
-        timed(p, st, FM_K_MUPDATE, [&] { launch_arnoldi_update(K, j, st); });
-        steps = j + 1;
-        if (steps % poll == 0 && steps < m) {
+    for (int j = 0; j < m;) {
+        const int n = std::min(poll, m - j);
+        hipGraphExec_t g = (graphs && !p->prof.on) ? step_graph(j, n) : nullptr;
+        if (g) {
+            HIP_TRY(hipGraphLaunch(g, st));
+        } else {
+            for (int i = j; i < j + n; ++i) enqueue_step(i, st, p->prof.on);
+        }
+        j += n;
+        steps = j;
+        if (steps < m) {
             HIP_TRY(hipMemcpyAsync(hbuf, K.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             bool any = false;
@@ -512,6 +579,11 @@ fm_status Batch::read_results(std::vector<double> &rel, std::vector<double> &min
 }
 
 void set_error(const std::string &msg) { g_err = msg; }
+
+std::recursive_mutex &hip_setup_mutex() {
+    static std::recursive_mutex m;
+    return m;
+}
 
 std::string upload(fm_problem *p, const HostFactors &hf) {
     std::string err;
@@ -733,7 +805,10 @@ fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out) {
         return fail(FM_E_PENCIL, e);
     }
     p->pencil_err = hf.max_err;
-    e = upload(p, hf);
+    {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
+        e = upload(p, hf);
+    }
     if (!e.empty()) {
         fm_destroy_problem(p);
         const bool invalid = e.rfind("invalid: ", 0) == 0;
@@ -745,6 +820,7 @@ fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out) {
 
 fm_status fm_destroy_problem(fm_problem *p) {
     if (!p) return FM_OK;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     (void)hipSetDevice(p->desc.device);
     for (auto &b : p->buffers) (void)hipFree(b.ptr);
     if (p->ws) (void)hipFree(p->ws);
@@ -787,6 +863,7 @@ fm_status fm_apply_operator(fm_problem *p, int nbatch, const double *E, const do
     HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
     const size_t cb = sizeof(double) * 2 * size_t(nbatch) * size_t(p->N);
     if (p->cbuf_bytes < cb) {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         if (p->cbuf) (void)hipFree(p->cbuf);
         p->cbuf = nullptr;
         p->cbuf_bytes = 0;
@@ -816,6 +893,7 @@ fm_status fm_apply_precond(fm_problem *p, int nbatch, const double *E, const dou
     HIP_TRY(hipMemcpyAsync(s.E, E, sizeof(double) * nbatch, hipMemcpyHostToDevice, st));
     const size_t tb = sizeof(double) * size_t(nbatch) * size_t(p->N);
     if (p->ptmp_bytes < tb) {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         if (p->ptmp) (void)hipFree(p->ptmp);
         p->ptmp = nullptr;
         p->ptmp_bytes = 0;
@@ -889,6 +967,7 @@ fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double 
     b->B = b_dev;
     b->X = x_dev;
     b->prec = opts->prec;
+    b->graphs = opts->graphs;
     b->rtol = opts->rtol;
     std::vector<int> all(nbatch);
     for (int i = 0; i < nbatch; ++i) {

@@ -26,6 +26,15 @@ struct Batch {
     double *X = nullptr;                                         // [cap][N]
     int prec = FM_FP64;
     double rtol = 1e-10;
+    // Arnoldi steps run as replays of captured HIP graphs, one graph per group
+    // of GRAPH_STEPS consecutive steps (per step index and precision, captured
+    // on first use on a private stream and kept with the batch); eager
+    // launches while per-launch profiling is on or if a capture fails.
+    static constexpr int GRAPH_STEPS = 4;
+    int graphs = 0;
+    bool graphs_failed = false;
+    hipStream_t cap_st = nullptr;
+    std::vector<hipGraphExec_t> gexec;          // [prec][group]
     std::vector<int> run, iters, restarts, limit, last_steps;    // host view per slot
     std::vector<double> E;
 
@@ -40,6 +49,13 @@ struct Batch {
     // or want_cut() holds after at least min_steps steps.
     fm_status cycle(const std::function<bool()> &want_cut, int min_steps);
     bool any_running() const;
+    // Enqueues Arnoldi step j (preconditioner, operator, dot pass, finish,
+    // update) on stream s; timed() wraps each launch only on the batch's own
+    // stream when profiling.
+    void enqueue_step(int j, hipStream_t s, bool profile);
+    // The replayable graph of steps j0 .. j0 + n - 1 at the current precision
+    // (nullptr if it cannot be captured).
+    hipGraphExec_t step_graph(int j0, int n);
     // Per slot: relative true residual, min |denominator|, status flags.
     fm_status read_results(std::vector<double> &rel, std::vector<double> &min_abs_den, std::vector<int> &flags);
 };

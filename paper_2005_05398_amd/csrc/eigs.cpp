@@ -38,9 +38,11 @@ fm_status efail(fm_status s, const std::string &m) {
 struct DevMem {
     std::vector<void *> ptrs;
     ~DevMem() {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         for (void *q : ptrs) (void)hipFree(q);
     }
     bool get(double **out, size_t n) {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         void *q = nullptr;
         if (hipMalloc(&q, sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess) return false;
         ptrs.push_back(q);

@@ -1,6 +1,8 @@
 // The problem handle and host-side factor storage.
 #pragma once
 
+#include <mutex>
+
 #include "fm_internal.h"
 
 namespace fm {
@@ -111,4 +113,9 @@ std::string coupled_slots(const fm_problem *p, int nz, const std::vector<std::ve
                           const std::vector<std::vector<double>> &Wz, std::vector<double> &Zj,
                           std::vector<double> &cx, std::vector<double> &cy);
 void set_error(const std::string &msg);
+// Serialises the library's own allocations, frees, stream creation and
+// synchronous copies with its stream captures: while any stream of the process
+// is being captured, HIP refuses synchronous calls on the null stream from
+// every thread.  Recursive: a holder may call code that takes it again.
+std::recursive_mutex &hip_setup_mutex();
 }  // namespace fm

@@ -236,6 +236,7 @@ void reap_lanes(fm_server *S) {
         Lane *L = S->lanes[i];
         if (L->finished) {
             if (L->th.joinable()) L->th.join();
+            std::lock_guard<std::recursive_mutex> hl(hip_setup_mutex());
             L->batch.release();
             (void)hipFree(L->B);
             (void)hipFree(L->X);
@@ -375,11 +376,15 @@ void dispatch_loop(fm_server *S) {
             L->key = lkey;
             L->prob = prob;
             L->slot.assign(slots, nullptr);
-            bool ok = hipStreamCreate(&L->st) == hipSuccess;
+            std::unique_lock<std::recursive_mutex> hl(hip_setup_mutex());
+            // non-blocking: a lane's stream has no implicit order with the null stream
+            bool ok = hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) == hipSuccess;
             ok = ok && hipMalloc(reinterpret_cast<void **>(&L->B), sizeof(double) * N * slots) == hipSuccess;
             ok = ok && hipMalloc(reinterpret_cast<void **>(&L->X), sizeof(double) * N * slots) == hipSuccess;
             ok = ok && L->batch.create(prob, slots, r->opts.restart, L->st) == FM_OK;
+            hl.unlock();
             if (!ok) {
+                hl.lock();
                 if (L->B) (void)hipFree(L->B);
                 if (L->X) (void)hipFree(L->X);
                 if (L->st) (void)hipStreamDestroy(L->st);
@@ -393,6 +398,7 @@ void dispatch_loop(fm_server *S) {
             L->batch.B = L->B;
             L->batch.X = L->X;
             L->batch.prec = r->opts.prec;
+            L->batch.graphs = r->opts.graphs;
             L->batch.rtol = r->opts.rtol;
             L->bytes = L->batch.bytes + 2 * sizeof(double) * N * slots;
             S->in_use += L->bytes;

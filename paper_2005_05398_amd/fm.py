@@ -36,7 +36,7 @@ class FmDesc(ctypes.Structure):
 
 class FmSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int),
-                ("prec", ctypes.c_int), ("x0_is_guess", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("x0_is_guess", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class FmSolveResult(ctypes.Structure):
@@ -202,12 +202,13 @@ class Problem:
         return y
 
     def eigs(self, sigma, nev=2, ncv=20, tol=1e-10, max_restarts=50, restart=60, rtol=1e-10, max_iters=4000,
-             prec="fp64", vectors=None, v0=None, stream=None, raise_on_error=True):
+             prec="fp64", vectors=None, v0=None, stream=None, raise_on_error=True, graphs=False):
         """Energies nearest sigma by shift-invert Arnoldi.  vectors: None or a
         device tensor of nev * N doubles.  Returns (status, energies (complex,
         nearest first), Ritz residuals, info dict)."""
         opts = FmEigsOpts(int(nev), int(ncv), float(tol), int(max_restarts),
-                          FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], 0))
+                          FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], 0,
+                                      int(bool(graphs))))
         Er = (ctypes.c_double * nev)()
         Ei = (ctypes.c_double * nev)()
         rs = (ctypes.c_double * nev)()
@@ -238,10 +239,11 @@ class Problem:
         return out
 
     def solve(self, E, b, x, restart=30, rtol=1e-10, max_iters=2000, prec="fp64", x0_is_guess=False,
-              stream=None, raise_on_error=True):
+              stream=None, raise_on_error=True, graphs=False):
         """Returns (status, [per-request result dicts])."""
         Ec, nb = _energies(E)
-        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], int(bool(x0_is_guess)))
+        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], int(bool(x0_is_guess)),
+                           int(bool(graphs)))
         res = (FmSolveResult * nb)()
         st = lib().fm_solve(self._h, nb, Ec, _ptr(b, nb * self.N, "b"), _ptr(x, nb * self.N, "x"),
                             ctypes.byref(opts), res, _stream(stream))
@@ -379,11 +381,11 @@ class Server:
         _check(L.fm_server_create(int(hbm_budget_bytes), int(max_batch), int(device), ctypes.byref(self._h)))
         self._keep = {}
 
-    def submit(self, desc, E, b, x, tag, restart=60, rtol=1e-10, max_iters=4000, prec="fp64"):
+    def submit(self, desc, E, b, x, tag, restart=60, rtol=1e-10, max_iters=4000, prec="fp64", graphs=True):
         """b, x: contiguous float64 numpy arrays of N; x is written when the result is polled."""
         import numpy as np
         assert b.dtype == np.float64 and x.dtype == np.float64 and b.flags.c_contiguous and x.flags.c_contiguous
-        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], 0)
+        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS[prec], 0, int(bool(graphs)))
         self._keep[int(tag)] = (b, x)
         _check(lib().fm_submit(self._h, ctypes.byref(make_c_desc(desc)), float(E), _dptr(b), _dptr(x),
                                ctypes.byref(opts), ctypes.c_uint64(int(tag))))

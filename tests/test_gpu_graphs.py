@@ -1,0 +1,76 @@
+"""Captured HIP graphs of the Arnoldi steps (fm_solve_opts.graphs = 1)
+through the C ABI.
+
+The graph path replays the same kernels with the same arguments as the eager
+path, so each replayed solve must give the eager solve's iteration counts and
+solution (compared elementwise at 1e-13 relative: no reordering of any sum is
+involved), and meet the oracle's bars (true relative residual 1e-10 against
+the assembled matrix, relative error 1e-8 against its LU solution).  Graphs
+are replayed several times per batch, with eager work and synchronisations
+of the program in between, and every replay is checked.
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem as OracleProblem
+from oracle.solve import lu_solve, rel_residual
+from paper_2005_05398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fm():
+    from paper_2005_05398_amd import fm
+    return fm
+
+
+def to_dev(a, device):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+
+
+CASES = [
+    # the small cubic workload: one request, GMRES(30)
+    ("ps_cubic16", W.ps_cubic16()["desc"], [-0.25], 30, "fp64"),
+    # batches over several restarts (energies below the spectrum, short cycles), FP64 and FP32 products
+    ("ps_cubic16_restart10_fp64", W.ps_cubic16()["desc"], [-0.35, -0.3, -0.28], 10, "fp64"),
+    ("ps_cubic16_restart10_fp32", W.ps_cubic16()["desc"], [-0.35, -0.3, -0.28], 10, "fp32"),
+    ("hminus_13x13x9", W.make_desc(*W.H_MINUS, 13, 9, R=30.0, xy_map="quadratic"),
+     [-0.75, -0.7, -0.65, -0.6], 12, "fp64"),
+    # L = 2 with the coupled preconditioner (joint z products)
+    ("L2_coupled", dict(W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0), precond="coupled"),
+     [-0.4, -0.3], 30, "fp64"),
+]
+
+
+@pytest.mark.parametrize("name,desc,Es,restart,prec", CASES, ids=[c[0] for c in CASES])
+def test_graph_solves_match_eager_and_oracle(device, name, desc, Es, restart, prec):
+    import torch
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    B = W.rhs_batch([900 + i for i in range(len(Es))], P.N)
+    Bd = to_dev(B, device)
+    Xe = torch.zeros(B.shape, dtype=torch.float64, device=device)
+    st, res_e = P.solve(Es, Bd, Xe, restart=restart, rtol=1e-10, max_iters=3000, prec=prec, graphs=False)
+    assert st == fm.FM_OK, res_e
+    xe = Xe.cpu().numpy()
+    scratch_y = torch.zeros(B.shape, dtype=torch.float64, device=device)
+    for rep in range(3):
+        Xg = torch.zeros(B.shape, dtype=torch.float64, device=device)
+        st, res_g = P.solve(Es, Bd, Xg, restart=restart, rtol=1e-10, max_iters=3000, prec=prec, graphs=True)
+        assert st == fm.FM_OK, (rep, res_g)
+        assert [r["iters"] for r in res_g] == [r["iters"] for r in res_e], (rep, res_g, res_e)
+        xg = Xg.cpu().numpy()
+        err = np.abs(xg - xe).max() / np.abs(xe).max()
+        assert err <= 1e-13, (rep, err)
+        # eager work of the program between replays
+        P.apply_operator(Es, Xg, scratch_y)
+        torch.cuda.synchronize()
+    for i, E in enumerate(Es):
+        A = O.assemble(E)
+        assert rel_residual(A, xg[i], B[i]) <= 1e-10
+        if restart < 30:
+            assert res_g[i]["restarts"] >= 2, res_g
+        xref = lu_solve(A, B[i])
+        assert np.linalg.norm(xg[i] - xref) / np.linalg.norm(xref) <= 1e-8
