@@ -233,6 +233,16 @@ __global__ void __launch_bounds__(256) k_matvec(const ProblemDev *__restrict__ p
 // planes and the x rows of the block's points.
 constexpr int XG_MAX = 4;
 
+// XCD-aware tile order of the operator kernels: a launch's blocks go to the
+// 8 XCDs in turn, and the grid's x extent is a multiple of 8 (the host pads
+// it), so block x of every request runs on XCD x % 8.  Block x takes tile
+// (x % 8) * (gridDim.x / 8) + x / 8: each XCD works through one contiguous
+// range of a request's tiles (neighbouring z points, which re-read most of
+// the same coefficient rows, meet in its L2), and every request still spreads
+// over all XCDs (few active requests keep the chip busy).  Tiles past the
+// request's count return.
+__device__ __forceinline__ int xcd_tile(int x, int padded) { return (x % 8) * (padded / 8) + x / 8; }
+
 template <int QX, int QY, int QZ>
 __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restrict__ pd,
                                                        const double *__restrict__ Evec,
@@ -240,12 +250,13 @@ __global__ void __launch_bounds__(256) k_local_grouped(const ProblemDev *__restr
                                                        const double *__restrict__ X, double *__restrict__ Y,
                                                        const double *__restrict__ cbuf) {
     constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
-    const int req = blockIdx.y;
+    const int req = blockIdx.y, tile = xcd_tile(blockIdx.x, gridDim.x);
     if (active && !active[req]) return;
+    if (tile >= pd->comp[0].ntiles_g + pd->comp[1].ntiles_g + pd->comp[2].ntiles_g) return;
     extern __shared__ double sm[];
     // the tile's record (block-uniform): everything the coefficient reads
     // depend on, in one read
-    const int *rec = pd->gtile + (size_t)blockIdx.x * GT_REC;
+    const int *rec = pd->gtile + (size_t)tile * GT_REC;
     const int a = __builtin_amdgcn_readfirstlane(rec[GT_A]), iz = __builtin_amdgcn_readfirstlane(rec[GT_IZ]);
     const int g0 = __builtin_amdgcn_readfirstlane(rec[GT_G0]), ngt = __builtin_amdgcn_readfirstlane(rec[GT_NGT]);
     const int ixs = __builtin_amdgcn_readfirstlane(rec[GT_IXS]), ixe = __builtin_amdgcn_readfirstlane(rec[GT_IXE]);
@@ -395,7 +406,7 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
     const int req = blockIdx.y;
     if (active && !active[req]) return;
     extern __shared__ double sm[];
-    int t = blockIdx.x, a = 0;
+    int t = xcd_tile(blockIdx.x, gridDim.x), a = 0;
     while (a < 3 && t >= pd->comp[a].ntiles) { t -= pd->comp[a].ntiles; ++a; }
     if (a >= 3) return;
     const CompDev &C = pd->comp[a];
@@ -2239,12 +2250,13 @@ void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *
                                cbuf);
     }
     if (part != 2) {
+        // tile counts padded to a multiple of 8 (XCD-aware tile order)
         if (NM == 1) {
-            const unsigned tiles = pd.comp[0].ntiles_g + pd.comp[1].ntiles_g + pd.comp[2].ntiles_g;
+            const unsigned tiles = (pd.comp[0].ntiles_g + pd.comp[1].ntiles_g + pd.comp[2].ntiles_g + 7) & ~7u;
             hipLaunchKernelGGL((k_local_grouped<QXY, QXY, QZ>), dim3(tiles, nb), dim3(256),
                                sizeof(double) * pd.group_lds, st, pd.dev, E_dev, active, x, y, cbuf);
         } else {
-            const unsigned tiles = pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles;
+            const unsigned tiles = (pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles + 7) & ~7u;
             hipLaunchKernelGGL((k_local_tiled<QXY, QXY, QZ, NM>), dim3(tiles, nb), dim3(256),
                                sizeof(double) * pd.plane_lds, st, pd.dev, E_dev, active, x, y, cbuf, nb);
         }
