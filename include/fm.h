@@ -104,7 +104,9 @@ typedef struct fm_problem fm_problem;
 typedef struct {
     int restart;              /* Krylov space size m per cycle (>= 1) */
     double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual) */
-    int max_iters;            /* total Arnoldi steps per request */
+    int max_iters;            /* total Arnoldi steps per request, checked at restart boundaries (a request
+                                 stops at the first boundary at or past it, so it may take up to
+                                 restart - 1 steps more) */
     int prec;                 /* fm_precision of the preconditioner's products */
     int x0_is_guess;          /* 1: x_dev holds the initial guess; 0: start from x = 0 */
     int graphs;               /* 1: the Arnoldi steps run as replays of HIP graphs captured on first use

@@ -54,6 +54,18 @@ fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double 
  * FM_E_PENCIL when an x or y pencil has complex pairs (not handled here). */
 fm_status fm_host_precond(const fm_problem_desc *desc, double E, const double *r, double *z);
 
+/* The eigenvalues of the x and y pencils of one x-y slice, as the divide of
+ * fm_apply_precond uses them (Sec. 3.2, eq. (prec-2)): the denominator of the
+ * slice's element (i, j) is lx_re[i] + ly_re[j] - E for real eigenvalues
+ * (lx_im, ly_im zero; a complex pair holds +b, -b on its two rows).  alpha:
+ * component 0..2; slot: 0 .. n_M n_z - 1 (M' n_z + k for the block-Jacobi
+ * variant, the coupled variant's (l, m) slots in the same numbering).  Output
+ * arrays hold n_x and n_y doubles; any may be NULL.  Errors as
+ * fm_host_setup_check, FM_E_INVALID for alpha or slot out of range (or a
+ * component implied by the exchange symmetry). */
+fm_status fm_host_slice_eigenvalues(const fm_problem_desc *desc, int alpha, int slot, double *lx_re, double *lx_im,
+                                    double *ly_re, double *ly_im);
+
 #ifdef __cplusplus
 }
 #endif

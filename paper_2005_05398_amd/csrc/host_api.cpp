@@ -270,3 +270,39 @@ fm_status fm_host_precond(const fm_problem_desc *desc, double E, const double *r
 }
 
 }  // extern "C"
+
+fm_status fm_host_slice_eigenvalues(const fm_problem_desc *desc, int alpha, int slot, double *lx_re, double *lx_im,
+                                    double *ly_re, double *ly_im) {
+    if (!desc) {
+        set_error("null argument");
+        return FM_E_INVALID;
+    }
+    fm_problem p;
+    p.desc = *desc;
+    std::string e = setup_problem(&p);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_INVALID;
+    }
+    if (alpha < 0 || alpha > 2 || p.absent(alpha) || slot < 0 || slot >= p.nM * p.bz[alpha].n) {
+        set_error("alpha or slot out of range");
+        return FM_E_INVALID;
+    }
+    HostFactors hf;
+    e = build_factors(&p, hf);
+    if (!e.empty()) {
+        set_error(e);
+        return FM_E_PENCIL;
+    }
+    const HostComp &h = hf.comp[alpha];
+    const int nx = p.bx[alpha].n, ny = p.by[alpha].n;
+    for (int i = 0; i < nx; ++i) {
+        if (lx_re) lx_re[i] = h.lx[size_t(slot) * nx + i];
+        if (lx_im) lx_im[i] = h.lxi[size_t(slot) * nx + i];
+    }
+    for (int i = 0; i < ny; ++i) {
+        if (ly_re) ly_re[i] = h.ly[size_t(slot) * ny + i];
+        if (ly_im) ly_im[i] = h.lyi[size_t(slot) * ny + i];
+    }
+    return FM_OK;
+}

@@ -266,7 +266,9 @@ def _host_sigs(L):
     L.fm_host_coupling.argtypes = [ctypes.POINTER(FmDesc), pd, pd, ctypes.POINTER(ctypes.c_longlong),
                                    ctypes.POINTER(ctypes.c_int)]
     L.fm_host_precond.argtypes = [ctypes.POINTER(FmDesc), ctypes.c_double, pd, pd]
-    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check", "fm_host_coupling", "fm_host_precond"):
+    L.fm_host_slice_eigenvalues.argtypes = [ctypes.POINTER(FmDesc), ci, ci, pd, pd, pd, pd]
+    for f in ("fm_host_basis", "fm_host_pencil", "fm_host_setup_check", "fm_host_coupling", "fm_host_precond",
+              "fm_host_slice_eigenvalues"):
         getattr(L, f).restype = ci
     L._host_sigs = True
 
@@ -347,6 +349,17 @@ def host_precond(desc, E, r):
     z = np.zeros_like(r)
     _check(L.fm_host_precond(ctypes.byref(make_c_desc(desc)), float(E), _dptr(r), _dptr(z)))
     return z
+
+
+def host_slice_eigenvalues(desc, alpha, slot):
+    """(lx_re, lx_im, ly_re, ly_im) of one x-y slice of the preconditioner."""
+    import numpy as np
+    L = lib()
+    _host_sigs(L)
+    nx, ny = desc["x"][alpha]["n"], desc["y"][alpha]["n"]
+    out = [np.zeros(nx), np.zeros(nx), np.zeros(ny), np.zeros(ny)]
+    _check(L.fm_host_slice_eigenvalues(ctypes.byref(make_c_desc(desc)), int(alpha), int(slot), *[_dptr(a) for a in out]))
+    return tuple(out)
 
 
 class FmRequestResult(ctypes.Structure):
