@@ -199,6 +199,39 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
 fm_status fm_apply_operator_noalloc(fm_problem *p, int nbatch, const double *E, const double *x_dev,
                                     double *y_dev, void *stream);
 
+/* ---- Complex energies --------------------------------------------------
+ *
+ * The same linear systems (H - E S) c = b with E complex and b, c complex:
+ * the paper's method works in complex arithmetic throughout (Sec. 4), and the
+ * scattering problem of Sec. 2.1 is posed at a given energy E.  H and S are
+ * real, so with c = c_re + i c_im the system is A(Re E) c_re + Im E S c_im =
+ * b_re, A(Re E) c_im - Im E S c_re = b_im; the preconditioner's factors are
+ * the real, energy-independent ones, and only its divide by
+ * lambda_x + lambda_y - E becomes complex.  Complex vectors are stored as two
+ * real rows per request: [request][re, im][N] (2N doubles per request).  The
+ * products run in FP64 only.  No boundary condition other than the bound-state
+ * one of fm_create_problem is built. */
+
+/* y = (H - E S) x for nbatch complex requests.  E_re, E_im: host arrays of
+ * nbatch.  x_dev, y_dev: nbatch * 2N doubles, not overlapping.  Errors:
+ * FM_E_INVALID, FM_E_HIP, FM_E_BUSY. */
+fm_status fm_apply_operator_complex(fm_problem *p, int nbatch, const double *E_re, const double *E_im,
+                                    const double *x_dev, double *y_dev, void *stream);
+
+/* z = L(E)^-1 r for nbatch complex requests (either variant of
+ * fm_apply_precond), FP64.  r_dev and z_dev may be the same buffer.  Errors as
+ * fm_apply_operator_complex. */
+fm_status fm_apply_precond_complex(fm_problem *p, int nbatch, const double *E_re, const double *E_im,
+                                   const double *r_dev, double *z_dev, void *stream);
+
+/* fm_solve for nbatch complex requests: right-preconditioned flexible GMRES on
+ * the 2N real unknowns of each request (the real form of the complex system),
+ * FP64 Arnoldi, true FP64 residual ||b - A x|| / ||b|| over both rows at every
+ * restart.  opts->prec must be FM_FP64.  Results and errors as fm_solve;
+ * min_abs_denominator is the least modulus of lambda - E over the divide. */
+fm_status fm_solve_complex(fm_problem *p, int nbatch, const double *E_re, const double *E_im, const double *b_dev,
+                           double *x_dev, const fm_solve_opts *opts, fm_solve_result *results, void *stream);
+
 /* y = S x for nbatch requests: S holds the basis products at the collocation
  * points (Sec. 3.1; the right-hand matrix of H c = E S c), block diagonal over
  * (alpha, M').  x_dev, y_dev: nbatch * N doubles, not overlapping.  Errors:

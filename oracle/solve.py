@@ -58,6 +58,21 @@ def rel_residuals_by_rows(prob, Es, X, B, chunk=16384, progress=None):
     return np.sqrt(ss) / np.linalg.norm(B, axis=1)
 
 
+def complex_matrix(prob, E):
+    """A(E) = H - E S for a complex energy E (Sec. 3.1; H, S real): H = A(0),
+    S = A(0) - A(1)."""
+    H = prob.assemble(0.0)
+    S = H - prob.assemble(1.0)
+    return (H.astype(np.complex128) - complex(E) * S).tocsr()
+
+
+def precond_reference_complex(prob, E, r, couple_m=False):
+    """z = L(E)^{-1} r with E and r complex (sparse LU of the complex separable
+    operator)."""
+    L = prob.separable(complex(E), couple_m=couple_m).tocsc()
+    return spla.splu(L).solve(np.asarray(r, dtype=np.complex128))
+
+
 def precond_reference(prob, E, r, couple_m=False):
     """z = L(E)^{-1} r with L the block-diagonal separable operator."""
     L = prob.separable(E, couple_m=couple_m).tocsc()

@@ -317,27 +317,73 @@ void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, 
     timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nb, mask, 1, out, out, st); });
 }
 
+// Complex energies (rows 2c, 2c + 1 = real and imaginary part of complex
+// request c): (H - E S) x = A(Re E) x + i Im E ... applied as A(Re E) on both
+// rows, then y_re += Im E (S x)_im, y_im -= Im E (S x)_re.  E2: Re E per row;
+// active: per complex request, mask2 the same per row (both may be null);
+// tmp: [2 nbc][N] scratch for S x.
+void apply_operator_complex(fm_problem *p, int nbc, const double *E2, const double *Eim, const int *active,
+                            const int *mask2, const double *x, double *y, double *cbuf, double *tmp,
+                            hipStream_t st) {
+    apply_operator(p, 2 * nbc, E2, mask2, x, y, cbuf, st);
+    timed(p, st, FM_K_MATVEC, [&] {
+        launch_mass(p->pd, 2 * nbc, x, tmp, st);
+        launch_cplx_energy(y, tmp, Eim, active, nbc, p->N, st);
+    });
+}
+
+// z = L(E)^-1 r with E complex: the real z and x-y transforms on both rows,
+// the complex divide between the forward and backward x-y products (FP64).
+// tmp: [2 nbc][N] scratch.
+void apply_precond_complex(fm_problem *p, int nbc, const double *Ere, const double *Eim, const int *active,
+                           const int *mask2, const double *in, double *out, double *min_den, double *tmp,
+                           hipStream_t st) {
+    const int nr = 2 * nbc;
+    if (p->pr.coupled) {
+        timed(p, st, FM_K_MODEZ, [&] { launch_zjoint(p->pd, p->pr, nr, mask2, 0, in, tmp, st); });
+        timed(p, st, FM_K_XY, [&] {
+            launch_xy_half(p->pd, p->pr, nr, mask2, 0, tmp, out, st);
+            launch_cdivide(p->pd, p->pr, nbc, Ere, Eim, active, tmp, min_den, st);
+            launch_xy_half(p->pd, p->pr, nr, mask2, 1, tmp, out, st);
+        });
+        timed(p, st, FM_K_MODEZ, [&] { launch_zjoint(p->pd, p->pr, nr, mask2, 1, tmp, out, st); });
+        return;
+    }
+    timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nr, mask2, 0, in, out, st); });
+    timed(p, st, FM_K_XY, [&] {
+        launch_xy_half(p->pd, p->pr, nr, mask2, 0, out, tmp, st);
+        launch_cdivide(p->pd, p->pr, nbc, Ere, Eim, active, out, min_den, st);
+        launch_xy_half(p->pd, p->pr, nr, mask2, 1, out, tmp, st);
+    });
+    timed(p, st, FM_K_MODEZ, [&] { launch_modez(p->pd, p->pr, nr, mask2, 1, out, out, st); });
+}
+
 }  // namespace
 
 // -- Batch -----------------------------------------------------------------
 
-size_t Batch::footprint(const fm_problem *p, int cap, int m) {
-    return krylov_bytes(p->N, cap, m) + 3 * round256(sizeof(int) * cap) + round256(sizeof(double) * cap) +
-           round256(sizeof(double) * 2 * size_t(cap) * size_t(p->N)) + round256(sizeof(double) * size_t(cap) * size_t(p->N));
+size_t Batch::footprint(const fm_problem *p, int cap, int m, int cplx) {
+    const long long Nv = cplx ? 2 * p->N : p->N;
+    return krylov_bytes(Nv, cap, m) + 3 * round256(sizeof(int) * cap) + round256(sizeof(double) * cap) +
+           round256(sizeof(double) * 2 * size_t(cap) * size_t(Nv)) + round256(sizeof(double) * size_t(cap) * size_t(Nv)) +
+           (cplx ? round256(sizeof(double) * 2 * cap) + round256(sizeof(double) * cap) + round256(sizeof(int) * 2 * cap)
+                 : 0);
 }
 
-fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
+fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s, int cx) {
     std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     p = pp;
     cap = c;
     m = mm;
     st = s;
-    bytes = footprint(p, cap, m);
+    cplx = cx;
+    const long long Nv = cplx ? 2 * p->N : p->N;
+    bytes = footprint(p, cap, m, cplx);
     if (hipMalloc(&mem, bytes) != hipSuccess) {
         mem = nullptr;
         return fail(FM_E_NOMEM, "Krylov workspace allocation failed");
     }
-    char *q = carve_krylov(static_cast<char *>(mem), p->N, cap, m, K);
+    char *q = carve_krylov(static_cast<char *>(mem), Nv, cap, m, K);
     running = reinterpret_cast<int *>(q);
     q += round256(sizeof(int) * cap);
     cont = reinterpret_cast<int *>(q);
@@ -347,8 +393,16 @@ fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
     min_den = reinterpret_cast<double *>(q);
     q += round256(sizeof(double) * cap);
     cbuf = reinterpret_cast<double *>(q);
-    q += round256(sizeof(double) * 2 * size_t(cap) * size_t(p->N));
+    q += round256(sizeof(double) * 2 * size_t(cap) * size_t(Nv));
     ptmp = reinterpret_cast<double *>(q);
+    if (cplx) {
+        q += round256(sizeof(double) * size_t(cap) * size_t(Nv));
+        E2 = reinterpret_cast<double *>(q);
+        q += round256(sizeof(double) * 2 * cap);
+        Eim = reinterpret_cast<double *>(q);
+        q += round256(sizeof(double) * cap);
+        mask2 = reinterpret_cast<int *>(q);
+    }
     void *h = nullptr;
     HIP_TRY(hipHostMalloc(&h, sizeof(int) * cap, hipHostMallocDefault));
     hbuf = static_cast<int *>(h);
@@ -366,6 +420,7 @@ fm_status Batch::create(fm_problem *pp, int c, int mm, hipStream_t s) {
     limit.assign(cap, 1 << 30);
     last_steps.assign(cap, 0);
     E.assign(cap, 0.0);
+    Ei.assign(cap, 0.0);
     return FM_OK;
 }
 
@@ -384,10 +439,27 @@ void Batch::release() {
 
 void Batch::enqueue_step(int j, hipStream_t s, bool profile) {
     const int nb = cap;
-    const long long N = p->N;
+    const long long N = K.N;
     double *Vj = K.V + (long long)j * nb * N;
     double *Zj = K.Z + (long long)j * nb * N;
     double *Vn = K.V + (long long)(j + 1) * nb * N;
+    if (cplx) {
+        t_capturing = !profile;
+        launch_expand_mask(K.active, mask2, nb, s);
+        apply_precond_complex(p, nb, K.E, Eim, K.active, mask2, Vj, Zj, min_den, ptmp, s);
+        apply_operator_complex(p, nb, E2, Eim, K.active, mask2, Zj, Vn, cbuf, ptmp, s);
+        t_capturing = false;
+        if (profile) {
+            timed(p, s, FM_K_MDOT, [&] { launch_arnoldi_dots(K, j, 0, s); });
+            timed(p, s, FM_K_FINISH, [&] { launch_arnoldi_finish(K, j, 0, s); });
+            timed(p, s, FM_K_MUPDATE, [&] { launch_arnoldi_update(K, j, s); });
+        } else {
+            launch_arnoldi_dots(K, j, 0, s);
+            launch_arnoldi_finish(K, j, 0, s);
+            launch_arnoldi_update(K, j, s);
+        }
+        return;
+    }
     if (profile) {
         apply_precond(p, nb, K.E, K.active, Vj, Zj, prec, min_den, ptmp, s);
         apply_operator(p, nb, K.E, K.active, Zj, Vn, cbuf, s);
@@ -456,6 +528,13 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
         restarts[s] = 0;
     }
     HIP_TRY(hipMemcpyAsync(K.E, E.data(), sizeof(double) * cap, hipMemcpyHostToDevice, st));
+    std::vector<double> e2;
+    if (cplx) {
+        e2.resize(2 * size_t(cap));
+        for (int s = 0; s < cap; ++s) e2[2 * s] = e2[2 * s + 1] = E[s];
+        HIP_TRY(hipMemcpyAsync(E2, e2.data(), sizeof(double) * 2 * cap, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(Eim, Ei.data(), sizeof(double) * cap, hipMemcpyHostToDevice, st));
+    }
     HIP_TRY(hipMemcpyAsync(cont, hcont.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(fresh, hfresh.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(running, run.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
@@ -483,7 +562,14 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
             launch_zero_start(K, X, fresh, x0_is_guess ? 0 : 1, st);
             launch_bnorm(K, B, fresh, st);
         }
-        launch_matvec(p->pd, cap, K.E, running, X, K.V, cbuf, st);
+        if (cplx) {
+            launch_expand_mask(running, mask2, cap, st);
+            launch_matvec(p->pd, 2 * cap, E2, mask2, X, K.V, cbuf, st);
+            launch_mass(p->pd, 2 * cap, X, ptmp, st);
+            launch_cplx_energy(K.V, ptmp, Eim, running, cap, p->N, st);
+        } else {
+            launch_matvec(p->pd, cap, K.E, running, X, K.V, cbuf, st);
+        }
         launch_residual(K, running, B, rtol, 0.5, st);
         launch_scale0(K, st);
     });
@@ -925,6 +1011,113 @@ fm_status fm_solve(fm_problem *p, int nbatch, const double *E, const double *b_d
     return solve_locked(p, nbatch, E, b_dev, x_dev, opts, results, static_cast<hipStream_t>(stream));
 }
 
+}  // extern "C"
+
+namespace fm {
+namespace {
+// Device energies of nbc complex requests: Re E per row (2 nbc), Re E and
+// Im E per request (nbc each), in the problem's small workspace.
+fm_status complex_energies(fm_problem *p, int nbc, const double *E_re, const double *E_im, hipStream_t st,
+                           double **E2, double **Ere, double **Eim) {
+    Small s;
+    fm_status r = ensure_small(p, 2 * nbc, s);     // s.E: 2 nbc doubles, s.min_den: 2 nbc doubles
+    if (r != FM_OK) return r;
+    std::vector<double> e2(2 * size_t(nbc)), ri(2 * size_t(nbc));
+    for (int c = 0; c < nbc; ++c) {
+        e2[2 * c] = e2[2 * c + 1] = E_re[c];
+        ri[c] = E_re[c];
+        ri[nbc + c] = E_im[c];
+    }
+    HIP_TRY(hipMemcpyAsync(s.E, e2.data(), sizeof(double) * 2 * nbc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s.min_den, ri.data(), sizeof(double) * 2 * nbc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *E2 = s.E;
+    *Ere = s.min_den;
+    *Eim = s.min_den + nbc;
+    return FM_OK;
+}
+
+fm_status grow(fm_problem *p, double *&buf, size_t &have, size_t bytes, bool zero, hipStream_t st) {
+    if (have >= bytes) return FM_OK;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    have = 0;
+    HIP_TRY(hipMalloc(&buf, bytes));
+    have = bytes;
+    if (zero) HIP_TRY(hipMemsetAsync(buf, 0, bytes, st));
+    return FM_OK;
+}
+
+bool energies_finite(int n, const double *a, const double *b) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]) || !std::isfinite(b[i])) return false;
+    return true;
+}
+}  // namespace
+}  // namespace fm
+
+extern "C" {
+
+fm_status fm_apply_operator_complex(fm_problem *p, int nbatch, const double *E_re, const double *E_im,
+                                    const double *x_dev, double *y_dev, void *stream) {
+    if (!p || !E_re || !E_im || !x_dev || !y_dev || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    if (x_dev == y_dev) return fail(FM_E_INVALID, "x and y must not overlap");
+    if (!energies_finite(nbatch, E_re, E_im)) return fail(FM_E_INVALID, "non-finite energy");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *E2, *Ere, *Eim;
+    fm_status r = complex_energies(p, nbatch, E_re, E_im, st, &E2, &Ere, &Eim);
+    if (r != FM_OK) return r;
+    const size_t rows = 2 * size_t(nbatch);
+    r = grow(p, p->cbuf, p->cbuf_bytes, sizeof(double) * 2 * rows * size_t(p->N), true, st);
+    if (r != FM_OK) return r;
+    r = grow(p, p->ptmp, p->ptmp_bytes, sizeof(double) * rows * size_t(p->N), false, st);
+    if (r != FM_OK) return r;
+    apply_operator_complex(p, nbatch, E2, Eim, nullptr, nullptr, x_dev, y_dev, p->cbuf, p->ptmp, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    prof_collect(p);
+    return FM_OK;
+}
+
+fm_status fm_apply_precond_complex(fm_problem *p, int nbatch, const double *E_re, const double *E_im,
+                                   const double *r_dev, double *z_dev, void *stream) {
+    if (!p || !E_re || !E_im || !r_dev || !z_dev || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    if (!energies_finite(nbatch, E_re, E_im)) return fail(FM_E_INVALID, "non-finite energy");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *E2, *Ere, *Eim;
+    fm_status r = complex_energies(p, nbatch, E_re, E_im, st, &E2, &Ere, &Eim);
+    if (r != FM_OK) return r;
+    r = grow(p, p->ptmp, p->ptmp_bytes, sizeof(double) * 2 * size_t(nbatch) * size_t(p->N), false, st);
+    if (r != FM_OK) return r;
+    apply_precond_complex(p, nbatch, Ere, Eim, nullptr, nullptr, r_dev, z_dev, nullptr, p->ptmp, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    prof_collect(p);
+    return FM_OK;
+}
+
+fm_status fm_solve_complex(fm_problem *p, int nbatch, const double *E_re, const double *E_im, const double *b_dev,
+                           double *x_dev, const fm_solve_opts *opts, fm_solve_result *results, void *stream) {
+    if (!p || !E_re || !E_im || !b_dev || !x_dev || !opts || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
+    const int m = opts->restart;
+    if (m < 1 || m > MAX_RESTART) return fail(FM_E_INVALID, "restart must be in [1, 1000]");
+    if (!(opts->rtol > 0)) return fail(FM_E_INVALID, "rtol must be positive");
+    if (opts->max_iters < 1) return fail(FM_E_INVALID, "max_iters must be >= 1");
+    if (opts->prec != FM_FP64) return fail(FM_E_INVALID, "complex energies run FP64 products only");
+    if (!energies_finite(nbatch, E_re, E_im)) return fail(FM_E_INVALID, "non-finite energy");
+    Busy busy(p);
+    if (!busy.ok) return fail(FM_E_BUSY, "problem handle in use");
+    HIP_TRY(hipSetDevice(p->desc.device));
+    return solve_locked(p, nbatch, E_re, b_dev, x_dev, opts, results, static_cast<hipStream_t>(stream), E_im);
+}
+
 fm_status fm_apply_mass(fm_problem *p, int nbatch, const double *x_dev, double *y_dev, void *stream) {
     if (!p || !x_dev || !y_dev || nbatch < 1) return fail(FM_E_INVALID, "bad argument");
     if (x_dev == y_dev) return fail(FM_E_INVALID, "x and y must not overlap");
@@ -944,11 +1137,12 @@ namespace fm {
 
 // fm_solve after validation, with the handle held and the device set.
 fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
-                       const fm_solve_opts *opts, fm_solve_result *results, hipStream_t st) {
+                       const fm_solve_opts *opts, fm_solve_result *results, hipStream_t st, const double *E_im) {
     const int m = opts->restart;
+    const int cplx = E_im ? 1 : 0;
     // the problem keeps the batch of its last solve for reuse
     Batch *b = p->solve_batch;
-    if (!b || b->cap != nbatch || b->m != m) {
+    if (!b || b->cap != nbatch || b->m != m || b->cplx != cplx) {
         if (b) {
             b->release();
             delete b;
@@ -956,7 +1150,7 @@ fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double 
         }
         b = new (std::nothrow) Batch();
         if (!b) return fail(FM_E_NOMEM, "host allocation failed");
-        fm_status r = b->create(p, nbatch, m, st);
+        fm_status r = b->create(p, nbatch, m, st, cplx);
         if (r != FM_OK) {
             delete b;
             return r;
@@ -973,6 +1167,7 @@ fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double 
     for (int i = 0; i < nbatch; ++i) {
         all[i] = i;
         b->E[i] = E[i];
+        if (cplx) b->Ei[i] = E_im[i];
         b->limit[i] = opts->max_iters;
     }
     fm_status r = b->boundary(all, opts->x0_is_guess);

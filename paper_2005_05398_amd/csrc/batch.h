@@ -26,6 +26,13 @@ struct Batch {
     double *X = nullptr;                                         // [cap][N]
     int prec = FM_FP64;
     double rtol = 1e-10;
+    // Complex energies: every slot is a complex request, two rows (real and
+    // imaginary part) of length N, so the Krylov vectors have length 2N.
+    int cplx = 0;
+    double *E2 = nullptr;                                        // device [2 cap]: Re E of each row
+    double *Eim = nullptr;                                       // device [cap]: Im E
+    int *mask2 = nullptr;                                        // device [2 cap]: row masks
+    std::vector<double> Ei;                                      // host Im E per slot
     // Arnoldi steps run as replays of captured HIP graphs, one graph per group
     // of GRAPH_STEPS consecutive steps (per step index and precision, captured
     // on first use on a private stream and kept with the batch); eager
@@ -38,8 +45,8 @@ struct Batch {
     std::vector<int> run, iters, restarts, limit, last_steps;    // host view per slot
     std::vector<double> E;
 
-    static size_t footprint(const fm_problem *p, int cap, int m);
-    fm_status create(fm_problem *p, int cap, int m, hipStream_t st);
+    static size_t footprint(const fm_problem *p, int cap, int m, int cplx = 0);
+    fm_status create(fm_problem *p, int cap, int m, hipStream_t st, int cplx = 0);
     void release();
     // Ends the cycle of the running slots (x += Z y, then the FP64 true
     // residual decides convergence) and starts the slots in `joining`, whose E

@@ -259,5 +259,19 @@ void prepare_large_lds(size_t bytes);
 void prepare_operator_lds(size_t bytes);
 size_t xy_lds_limit();
 void launch_copy(double *dst, const double *src, long long n, hipStream_t st);
+// Complex energies: a complex request is two rows (real, imaginary part).
+// The divide of the preconditioner with E complex, in place over the slices
+// of nbc complex requests (active: per complex request; min_den: [nbc]).
+void launch_cdivide(const ProblemDev &pd, const PrecDev &pr, int nbc, const double *Ere, const double *Eim,
+                    const int *active, double *data, double *min_den, hipStream_t st);
+// y_re += E_im sx_im, y_im -= E_im sx_re (sx = S x of both rows).
+void launch_cplx_energy(double *y, const double *sx, const double *Eim, const int *active, int nbc, long long N,
+                        hipStream_t st);
+// out[2c] = out[2c + 1] = in[c] for c < n.
+void launch_expand_mask(const int *in, int *out, int n, hipStream_t st);
+// The forward (which 0) or backward (which 1) pair of staged x-y products over
+// nrows rows, data -> tmp -> data, with no divide.
+void launch_xy_half(const ProblemDev &pd, const PrecDev &pr, int nrows, const int *active, int which, double *data,
+                    double *tmp, hipStream_t st);
 
 }  // namespace fm

@@ -99,8 +99,11 @@ struct Busy {
     }
 };
 // fm_solve on a held handle with its device current (arguments already checked).
+// E_im: imaginary parts of complex energies (nullptr: real energies); with
+// them b_dev and x_dev hold [request][re, im][N].
 fm_status solve_locked(fm_problem *p, int nbatch, const double *E, const double *b_dev, double *x_dev,
-                       const fm_solve_opts *opts, fm_solve_result *results, hipStream_t st);
+                       const fm_solve_opts *opts, fm_solve_result *results, hipStream_t st,
+                       const double *E_im = nullptr);
 std::string setup_problem(fm_problem *p);
 std::string build_factors(fm_problem *p, HostFactors &hf);
 std::string upload(fm_problem *p, const HostFactors &hf);

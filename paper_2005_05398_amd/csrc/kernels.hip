@@ -2710,4 +2710,195 @@ void launch_scale_vec(double *w, double s, long long N, hipStream_t st) {
     hipLaunchKernelGGL(k_scale_vec, dim3(cdiv(N, 256)), dim3(256), 0, st, w, s, N);
 }
 
+
+// ---------------------------------------------------------------------------
+// Complex energies.  A complex request is a pair of real rows (real part,
+// imaginary part) of one problem, [request][re, im][N]; the operator and the
+// preconditioner's transforms are real, so they act on the two rows as two
+// requests, and only the divide and the E S term couple the rows.
+
+struct cplx {
+    double re, im;
+};
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cplx cscale(double s, cplx a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ cplx cquot(cplx a, cplx b) {
+    const double q = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / q, (a.im * b.re - a.re * b.im) / q};
+}
+__device__ __forceinline__ double cabs2(cplx a) { return sqrt(a.re * a.re + a.im * a.im); }
+
+// (Lambda_x (x) I + I (x) Lambda_y - E)^-1 on one slice of every complex
+// request, in place, with E complex (Sec. 3.2, eq. (prec-2)): the closed forms
+// of the real divide (one complex division per real pair of eigenvalues; the
+// 2x2 and 4x4 blocks of complex-conjugate eigenpairs) hold with the shifted
+// diagonal d = lambda_x + lambda_y - E complex, and the data of each element
+// is complex (its two rows).  One thread per anchor element of a block; grid
+// (slices, element chunks of 256, complex requests).  min_den[c]: minimum
+// modulus over the blocks' eigenvalues of lambda - E.
+__global__ void __launch_bounds__(256) k_cdivide(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
+                                                 const double *__restrict__ Ere, const double *__restrict__ Eim,
+                                                 const int *__restrict__ active, double *data, double *min_den) {
+    const int c = blockIdx.z;
+    if (active && !active[c]) return;
+    int a, iM, k;
+    if (!slice_decode(pd, blockIdx.x, a, iM, k)) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
+    const size_t fx = (size_t)iM * nz + k;
+    const double *lx = F.lx + fx * nx, *lxi = F.lxi + fx * nx, *ly = F.ly + fx * ny, *lyi = F.lyi + fx * ny;
+    const signed char *tx = F.tx + fx * nx, *ty = F.ty + fx * ny;
+    const long long off = C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    double *re = data + (long long)(2 * c) * pd->N + off, *im = data + (long long)(2 * c + 1) * pd->N + off;
+    const cplx E = {Ere[c], Eim[c]};
+    double mind = 1e300;
+    const int e = blockIdx.y * 256 + threadIdx.x;
+    if (e < nx * ny) {
+        const int i = e / ny, j = e % ny, o = i * ny + j;
+        const int ti = tx[i], tj = ty[j];
+        if (ti != 2 && tj != 2) {
+            const cplx d = csub({lx[i] + ly[j], 0.0}, E);
+            if (ti == 0 && tj == 0) {
+                const cplx t = cquot({re[o], im[o]}, d);
+                re[o] = t.re;
+                im[o] = t.im;
+                mind = cabs2(d);
+            } else if (tj == 0 || ti == 0) {
+                // one complex pair (rows i, i + 1 or columns j, j + 1): the block
+                // [[d, b], [-b, d]] inverted; eigenvalues d +- i b
+                const double b = tj == 0 ? lxi[i] : lyi[j];
+                const int o1 = tj == 0 ? o + ny : o + 1;
+                const cplx r0 = {re[o], im[o]}, r1 = {re[o1], im[o1]};
+                const cplx det = cadd(cmul(d, d), {b * b, 0.0});
+                const cplx t0 = cquot(csub(cmul(d, r0), cscale(b, r1)), det);
+                const cplx t1 = cquot(cadd(cscale(b, r0), cmul(d, r1)), det);
+                re[o] = t0.re;
+                im[o] = t0.im;
+                re[o1] = t1.re;
+                im[o1] = t1.im;
+                mind = fmin(cabs2(cadd(d, {0.0, b})), cabs2(csub(d, {0.0, b})));
+            } else {
+                // both in pairs: split on the eigenspaces of the two commuting
+                // structures into divisions by d +- i (bx - by), d +- i (bx + by)
+                const double bx = lxi[i], by = lyi[j];
+                const cplx r00 = {re[o], im[o]}, r01 = {re[o + 1], im[o + 1]};
+                const cplx r10 = {re[o + ny], im[o + ny]}, r11 = {re[o + ny + 1], im[o + ny + 1]};
+                const cplx p00 = cscale(0.5, cadd(r00, r11)), p01 = cscale(0.5, csub(r01, r10));
+                const cplx m00 = cscale(0.5, csub(r00, r11)), m01 = cscale(0.5, cadd(r01, r10));
+                const double bp = bx - by, bm = bx + by;
+                const cplx Dp = cadd(cmul(d, d), {bp * bp, 0.0}), Dm = cadd(cmul(d, d), {bm * bm, 0.0});
+                const cplx t00 = cadd(cquot(cadd(cmul(d, p00), cscale(bp, p01)), Dp),
+                                      cquot(csub(cmul(d, m00), cscale(bm, m01)), Dm));
+                const cplx t01 = cadd(cquot(csub(cmul(d, p01), cscale(bp, p00)), Dp),
+                                      cquot(cadd(cmul(d, m01), cscale(bm, m00)), Dm));
+                const cplx t10 = cadd(cquot(cadd(cscale(-1.0, cmul(d, p01)), cscale(bp, p00)), Dp),
+                                      cquot(cadd(cmul(d, m01), cscale(bm, m00)), Dm));
+                const cplx t11 = cadd(cquot(cadd(cmul(d, p00), cscale(bp, p01)), Dp),
+                                      cquot(cadd(cscale(-1.0, cmul(d, m00)), cscale(bm, m01)), Dm));
+                re[o] = t00.re;
+                im[o] = t00.im;
+                re[o + 1] = t01.re;
+                im[o + 1] = t01.im;
+                re[o + ny] = t10.re;
+                im[o + ny] = t10.im;
+                re[o + ny + 1] = t11.re;
+                im[o + ny + 1] = t11.im;
+                mind = fmin(fmin(cabs2(cadd(d, {0.0, bp})), cabs2(csub(d, {0.0, bp}))),
+                            fmin(cabs2(cadd(d, {0.0, bm})), cabs2(csub(d, {0.0, bm}))));
+            }
+        }
+    }
+    if (min_den) {
+        __shared__ double red[256];
+        red[threadIdx.x] = mind;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            atomicMin((unsigned long long *)(min_den + c), (unsigned long long)__double_as_longlong(red[0]));
+    }
+}
+
+// y_re += E_im (S x)_im, y_im -= E_im (S x)_re for every complex request:
+// the imaginary part of the energy term of (H - E S) x once A(Re E) has been
+// applied to both rows.  sx: S x of both rows.  Grid (chunks of N, requests).
+__global__ void __launch_bounds__(256) k_cplx_energy(double *__restrict__ y, const double *__restrict__ sx,
+                                                     const double *__restrict__ Eim, const int *__restrict__ active,
+                                                     long long N) {
+    const int c = blockIdx.y;
+    if (active && !active[c]) return;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const double e = Eim[c];
+    double *yr = y + (long long)(2 * c) * N, *yi = yr + N;
+    const double *sr = sx + (long long)(2 * c) * N, *si = sr + N;
+    const double a = sr[i], b = si[i];
+    yr[i] += e * b;
+    yi[i] -= e * a;
+}
+
+// out[2c] = out[2c + 1] = in[c]: a per-request mask for the rows of complex requests.
+__global__ void k_expand_mask(const int *__restrict__ in, int *__restrict__ out, int n) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < n) {
+        const int v = in[c];
+        out[2 * c] = v;
+        out[2 * c + 1] = v;
+    }
+}
+
+void launch_cdivide(const ProblemDev &pd, const PrecDev &pr, int nbc, const double *Ere, const double *Eim,
+                    const int *active, double *data, double *min_den, hipStream_t st) {
+    int slices = 0, maxnxy = 0;
+    for (int a = 0; a < 3; ++a) {
+        slices += pd.nM * pd.comp[a].z.n;
+        maxnxy = std::max(maxnxy, pd.comp[a].nxy);
+    }
+    hipLaunchKernelGGL(k_cdivide, dim3(slices, cdiv(maxnxy, 256), nbc), dim3(256), 0, st, pd.dev, pr.dev, Ere, Eim,
+                       active, data, min_den);
+}
+
+void launch_cplx_energy(double *y, const double *sx, const double *Eim, const int *active, int nbc, long long N,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_cplx_energy, dim3(cdiv(N, 256), nbc), dim3(256), 0, st, y, sx, Eim, active, N);
+}
+
+void launch_expand_mask(const int *in, int *out, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_expand_mask, dim3(cdiv(n, 256)), dim3(256), 0, st, in, out, n);
+}
+
+// Two of the four staged x-y products over every slice of nrows rows, in
+// place through tmp: which 0, data <- Wbar_x data Wbar_y^T; which 1,
+// data <- W_x data W_y^T (no divide: the complex path divides in between).
+void launch_xy_half(const ProblemDev &pd, const PrecDev &pr, int nrows, const int *active, int which, double *data,
+                    double *tmp, hipStream_t st) {
+    int slices = 0, side = 0;
+    long long t64 = 0, area64 = 0, area32 = 0;
+    for (int a = 0; a < 3; ++a) {
+        slices += pd.nM * pd.comp[a].z.n;
+        const int nx = pd.comp[a].x.n, ny = pd.comp[a].y.n;
+        side = std::max(side, std::max(nx, ny));
+        t64 = std::max<long long>(t64, (long long)sg_tiles(nx, 64) * sg_tiles(ny, 64));
+        area64 += 4096LL * sg_tiles(nx, 64) * sg_tiles(ny, 64);
+        area32 += 1024LL * sg_tiles(nx, 32) * sg_tiles(ny, 32);
+    }
+#define FM_XYH(BT)                                                                                                   \
+    {                                                                                                                \
+        int tl = 0;                                                                                                  \
+        for (int a = 0; a < 3; ++a) tl = std::max(tl, sg_tiles(pd.comp[a].x.n, BT) * sg_tiles(pd.comp[a].y.n, BT)); \
+        const dim3 g(slices, tl, nrows);                                                                             \
+        hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, nullptr,     \
+                           active, which, data, tmp, nullptr);                                                       \
+        hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, nullptr,    \
+                           active, which, tmp, data, nullptr);                                                       \
+    }
+    if (side > 32 && t64 * slices * nrows >= XY_T64_MIN_BLOCKS && 4 * area64 <= 5 * area32) FM_XYH(64) else FM_XYH(32)
+#undef FM_XYH
+}
+
 }  // namespace fm

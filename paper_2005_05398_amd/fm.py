@@ -86,13 +86,18 @@ def lib():
         L.fm_solve.argtypes = [vp, ci, pd, vp, vp, ctypes.POINTER(FmSolveOpts), ctypes.POINTER(FmSolveResult), vp]
         L.fm_apply_mass.argtypes = [vp, ci, vp, vp, vp]
         L.fm_apply_operator_noalloc.argtypes = [vp, ci, pd, vp, vp, vp]
+        L.fm_apply_operator_complex.argtypes = [vp, ci, pd, pd, vp, vp, vp]
+        L.fm_apply_precond_complex.argtypes = [vp, ci, pd, pd, vp, vp, vp]
+        L.fm_solve_complex.argtypes = [vp, ci, pd, pd, vp, vp, ctypes.POINTER(FmSolveOpts),
+                                       ctypes.POINTER(FmSolveResult), vp]
         L.fm_eigs.argtypes = [vp, cd, ctypes.POINTER(FmEigsOpts), vp, pd, pd, pd, vp, ctypes.POINTER(FmEigsInfo),
                               vp]
         L.fm_profile.argtypes = [vp, ci]
         L.fm_profile_read.argtypes = [vp, ci, pd, ctypes.POINTER(ctypes.c_longlong), pd, pd]
         for f in ("fm_create_problem", "fm_destroy_problem", "fm_problem_info", "fm_apply_operator",
                   "fm_apply_precond", "fm_solve", "fm_profile", "fm_profile_read", "fm_apply_mass", "fm_eigs",
-                  "fm_apply_operator_noalloc"):
+                  "fm_apply_operator_noalloc", "fm_apply_operator_complex", "fm_apply_precond_complex",
+                  "fm_solve_complex"):
             getattr(L, f).restype = ci
         _lib = L
     return _lib
@@ -127,6 +132,12 @@ def make_c_desc(desc, device=0):
 def _energies(E):
     E = [float(e) for e in (E if hasattr(E, "__len__") else [E])]
     return (ctypes.c_double * len(E))(*E), len(E)
+
+
+def _complex_energies(E):
+    E = [complex(e) for e in (E if hasattr(E, "__len__") else [E])]
+    n = len(E)
+    return (ctypes.c_double * n)(*[e.real for e in E]), (ctypes.c_double * n)(*[e.imag for e in E]), n
 
 
 def _stream(stream):
@@ -187,6 +198,34 @@ class Problem:
         _check(lib().fm_apply_operator_noalloc(self._h, nb, Ec, _ptr(x, nb * self.N, "x"),
                                                _ptr(y, nb * self.N, "y"), _stream(stream)))
         return y
+
+    def apply_operator_complex(self, E, x, y, stream=None):
+        """Complex energies E; x, y: float64 tensors of len(E) * 2N ([request][re, im][N])."""
+        Er, Ei, nb = _complex_energies(E)
+        _check(lib().fm_apply_operator_complex(self._h, nb, Er, Ei, _ptr(x, 2 * nb * self.N, "x"),
+                                               _ptr(y, 2 * nb * self.N, "y"), _stream(stream)))
+        return y
+
+    def apply_precond_complex(self, E, r, z, stream=None):
+        Er, Ei, nb = _complex_energies(E)
+        _check(lib().fm_apply_precond_complex(self._h, nb, Er, Ei, _ptr(r, 2 * nb * self.N, "r"),
+                                              _ptr(z, 2 * nb * self.N, "z"), _stream(stream)))
+        return z
+
+    def solve_complex(self, E, b, x, restart=30, rtol=1e-10, max_iters=2000, x0_is_guess=False, stream=None,
+                      raise_on_error=True, graphs=False):
+        """fm_solve_complex: b, x float64 tensors of len(E) * 2N ([request][re, im][N]).
+        Returns (status, [per-request result dicts])."""
+        Er, Ei, nb = _complex_energies(E)
+        opts = FmSolveOpts(int(restart), float(rtol), int(max_iters), PRECISIONS["fp64"], int(bool(x0_is_guess)),
+                           int(bool(graphs)))
+        res = (FmSolveResult * nb)()
+        st = lib().fm_solve_complex(self._h, nb, Er, Ei, _ptr(b, 2 * nb * self.N, "b"), _ptr(x, 2 * nb * self.N, "x"),
+                                    ctypes.byref(opts), res, _stream(stream))
+        out = [r.as_dict() for r in res]
+        if st != FM_OK and raise_on_error and st != FM_E_NOT_CONVERGED:
+            raise FmError(st, lib().fm_last_error().decode())
+        return st, out
 
     def apply_precond(self, E, r, z, prec="fp64", stream=None):
         Ec, nb = _energies(E)

@@ -1,0 +1,164 @@
+"""Complex energies through the C ABI (fm_apply_operator_complex,
+fm_apply_precond_complex, fm_solve_complex) against the oracle.
+
+Complex vectors travel as two real rows per request, [request][re, im][N].
+Operator: elementwise against the oracle's complex H - E S at 1e-11 (relative
+to the largest output).  Preconditioner: against the sparse LU solve with the
+complex separable operator at 1e-9, on grids whose quintic pencils have
+complex eigenpairs (the 2x2 and 4x4 blocks of the complex divide).  Solves:
+true relative residual 1e-10 and relative error 1e-8 against the oracle's
+complex LU solution, with and without captured graphs; a zero imaginary part
+reproduces the real path's two solves; conjugate inputs give the conjugate
+solution.
+"""
+import numpy as np
+import pytest
+
+from oracle.assemble import Problem as OracleProblem
+from oracle.solve import complex_matrix, lu_solve, precond_reference_complex
+from paper_2005_05398_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fm():
+    from paper_2005_05398_amd import fm
+    return fm
+
+
+def pack(Z):
+    """complex (nb, N) -> real (nb, 2N) rows [re, im]."""
+    Z = np.atleast_2d(Z)
+    return np.ascontiguousarray(np.concatenate([Z.real, Z.imag], axis=1))
+
+
+def unpack(R, N):
+    R = np.atleast_2d(R)
+    return R[:, :N] + 1j * R[:, N:]
+
+
+def to_dev(a, device):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+
+
+def crand(nb, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+
+
+def wide(nx, ny, nz, dz):
+    d = W.make_desc(*W.PS_MINUS, nx, nz, deg_xy=5, deg_z=dz, R=20.0)
+    d["y"] = W.make_desc(*W.PS_MINUS, ny, nz, deg_xy=5, deg_z=dz, R=20.0)["y"]
+    return d
+
+
+CASES = [
+    ("ps_cubic16", W.ps_cubic16()["desc"]),
+    ("quintic_7x7x6", W.make_desc(*W.PS_MINUS, 7, 6, R=15.0)),
+    ("hminus_22x22x9_quadratic", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
+    ("L2_tau+1", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0)),
+    ("wide_x97_y13", wide(97, 13, 4, 3)),
+]
+ES = [-0.25 + 0.03j, 0.1 - 0.2j]
+
+
+@pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])
+def test_complex_operator_parity(device, name, desc):
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    X = crand(len(ES), O.N, 31)
+    Y = to_dev(np.zeros((len(ES), 2 * O.N)), device)
+    P.apply_operator_complex(ES, to_dev(pack(X), device), Y)
+    Yg = unpack(Y.cpu().numpy(), O.N)
+    for r, E in enumerate(ES):
+        ref = complex_matrix(O, E) @ X[r]
+        err = np.abs(Yg[r] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-11, (name, r, err)
+
+
+@pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])
+def test_complex_precond_parity(device, name, desc):
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    R = crand(len(ES), O.N, 32)
+    Z = to_dev(np.zeros((len(ES), 2 * O.N)), device)
+    P.apply_precond_complex(ES, to_dev(pack(R), device), Z)
+    Zg = unpack(Z.cpu().numpy(), O.N)
+    for r, E in enumerate(ES):
+        ref = precond_reference_complex(O, E, R[r])
+        err = np.abs(Zg[r] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-9, (name, r, err)
+
+
+def test_complex_pairs_are_covered():
+    """At least one preconditioner case has complex pencil pairs."""
+    fm = _fm()
+    assert sum(fm.host_setup_check(d)[1] for _, d in CASES) > 0
+
+
+SOLVE_CASES = [
+    ("ps_cubic16", W.ps_cubic16()["desc"], [-0.25 + 0.02j, -0.3 - 0.05j, 0.1 + 0.1j], 60),
+    ("L2_coupled", dict(W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0), precond="coupled"),
+     [-0.3 + 0.05j, -0.2 - 0.01j], 60),
+]
+
+
+@pytest.mark.parametrize("name,desc,Es,restart", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_complex_solve_matches_lu(device, name, desc, Es, restart):
+    import torch
+    fm = _fm()
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    B = crand(len(Es), O.N, 33)
+    Bd = to_dev(pack(B), device)
+    sols = []
+    for graphs in (False, True):
+        X = torch.zeros(Bd.shape, dtype=torch.float64, device=device)
+        st, res = P.solve_complex(Es, Bd, X, restart=restart, rtol=1e-10, max_iters=4000, graphs=graphs)
+        assert st == fm.FM_OK, (graphs, res)
+        sols.append((X.cpu().numpy(), res))
+    (x0, r0), (x1, r1) = sols
+    assert [r["iters"] for r in r0] == [r["iters"] for r in r1]
+    assert np.abs(x0 - x1).max() <= 1e-13 * np.abs(x0).max()
+    Xg = unpack(x0, O.N)
+    for i, E in enumerate(Es):
+        A = complex_matrix(O, E)
+        rel = np.linalg.norm(B[i] - A @ Xg[i]) / np.linalg.norm(B[i])
+        assert rel <= 1e-10, (i, rel)
+        assert abs(rel - r0[i]["rel_residual"]) <= 1e-12, (rel, r0[i])
+        xref = lu_solve(A, B[i])
+        assert np.linalg.norm(Xg[i] - xref) / np.linalg.norm(xref) <= 1e-8
+        assert r0[i]["min_abs_denominator"] > 0
+
+
+def test_complex_solve_with_real_energy_and_conjugate(device):
+    import torch
+    fm = _fm()
+    c = W.ps_cubic16()
+    P = fm.Problem(c["desc"])
+    N = P.N
+    B = crand(1, N, 34)
+    # Im E = 0: the real and imaginary rows are two real solves
+    X = torch.zeros((1, 2 * N), dtype=torch.float64, device=device)
+    st, _ = P.solve_complex([complex(-0.25, 0.0)], to_dev(pack(B), device), X, restart=60, rtol=1e-12,
+                            max_iters=4000)
+    assert st == fm.FM_OK
+    xc = unpack(X.cpu().numpy(), N)[0]
+    Xr = torch.zeros((2, N), dtype=torch.float64, device=device)
+    st, _ = P.solve([-0.25, -0.25], to_dev(np.stack([B[0].real, B[0].imag]), device), Xr, restart=60, rtol=1e-12,
+                    max_iters=4000)
+    assert st == fm.FM_OK
+    xr = Xr.cpu().numpy()
+    assert np.linalg.norm(xc - (xr[0] + 1j * xr[1])) <= 1e-9 * np.linalg.norm(xc)
+    # conjugate energy and right-hand side: the conjugate solution
+    E = -0.28 + 0.06j
+    sols = []
+    for e, b in ((E, B), (np.conj(E), np.conj(B))):
+        X = torch.zeros((1, 2 * N), dtype=torch.float64, device=device)
+        st, _ = P.solve_complex([e], to_dev(pack(b), device), X, restart=60, rtol=1e-12, max_iters=4000)
+        assert st == fm.FM_OK
+        sols.append(unpack(X.cpu().numpy(), N)[0])
+    assert np.linalg.norm(sols[1] - np.conj(sols[0])) <= 1e-9 * np.linalg.norm(sols[0])
