@@ -459,6 +459,47 @@ def workload_entry(name, args, precs, precond="block_jacobi", restart=None, prof
     return out
 
 
+def complex_entry(args):
+    """The energy scan at complex energies E_k + 0.01 i with complex seeded
+    right-hand sides (two real rows per request), FP64, timed like the others."""
+    import numpy as np
+    import torch
+    from paper_2005_05398_amd import fm
+    from paper_2005_05398_amd import workloads as W
+    c = W.hminus_scan()
+    P = fm.Problem(c["desc"])
+    Es = [complex(e, 0.01) for e in c["E"]]
+    B = torch.as_tensor(np.stack([np.concatenate([W.rhs(s, P.N), W.rhs(s + 500, P.N)]) for s in c["seeds"]]),
+                        device=torch.device("cuda:0"))
+    X = torch.zeros_like(B)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st, res = P.solve_complex(Es, B, X, restart=300, rtol=1e-10, max_iters=20000, stream=stream,
+                                  graphs=bool(args.graphs))
+        if st != fm.FM_OK:
+            raise RuntimeError(f"complex solve failed: {fm.STATUS_NAMES.get(st)} {res}")
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    iters = [r["iters"] for r in res]
+    P.close()
+    out = {"config": "H- scan, 32 energies E_k + 0.01 i, complex seeded RHS (re: seed 2001+k, im: 2501+k), FP64, "
+                     "restart 300",
+           "solves_per_s": len(Es) * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+           "iters": {"min": min(iters), "mean": float(np.mean(iters)), "max": max(iters)},
+           "max_rel_residual": max(r["rel_residual"] for r in res)}
+    print(f"bench: hminus_scan complex: {out['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    return out
+
+
 def oracle_lu_timing():
     """The oracle on the small workload (cubic 16 x 16 x 8, N = 6144): assembly,
     dense LU factorisation and the solve, timed separately on this host."""
@@ -642,6 +683,7 @@ def main():
         for pc in ("block_jacobi", "coupled"):
             l2[pc] = workload_entry("ps_l2_q97", args, ("fp32", "fp64"), precond=pc, traffic=True)
         cfgs["ps_l2_q97"] = l2
+        cfgs["hminus_scan_complex"] = complex_entry(args)
         torch.cuda.empty_cache()
         if args.serve_sample > 0:
             sv = serve_run(args, args.serve_sample, (args.serve_rate,))

@@ -96,7 +96,14 @@ typedef struct {
                                  parity p = exchange under their permutation is solved: components 1
                                  and 3 (Sec. 2, "Permutational symmetry", eq. (2-sym-part): component
                                  2 is p (-1)^{M'} times component 1 at -z); vectors then hold
-                                 [alpha = 1, 3][M'][z][x][y] and N = n_M (n_1 + n_3) */
+                                 [alpha = 1, 3][M'][z][x][y] and N = n_M (n_1 + n_3).
+                                 3: all three particles are identical (equal masses, charges and
+                                 component bases): psi_1 = psi_2 = psi_3 in their own coordinates
+                                 (eq. (3-sym-part)) and only component 1 is solved, its coupling
+                                 reading component 1 at both partners' rotated points; vectors hold
+                                 [M'][z][x][y] of component 1 and N = n_M n_1.  Both parities of the
+                                 full permutations are held (they are the parts of psi_1 even and odd
+                                 under psi(x, y, z) -> (-1)^{M'} psi(x, y, -z)) */
 } fm_problem_desc;
 
 typedef struct fm_problem fm_problem;

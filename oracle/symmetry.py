@@ -1,5 +1,6 @@
 """Oracle: the exchange-reduced equations for two identical particles (Sec. 2,
-"Permutational symmetry", eqs. (2-sym) and (2-sym-part)).
+"Permutational symmetry", eqs. (2-sym) and (2-sym-part)) and for three
+identical particles (eqs. (3-sym) and (3-sym-part)).
 
 Test infrastructure only (see oracle/__init__.py).
 
@@ -96,3 +97,34 @@ def reduced_shift_invert_eigs(prob, p, sigma, k, tol=1e-13, return_vectors=False
     order = np.argsort(-np.abs(theta), kind="stable")
     E = sigma + 1.0 / theta[order]
     return (E, X[:, order]) if return_vectors else E
+
+
+# -- three identical particles (eq. (3-sym-part)) ------------------------------
+# The partial components of all three sets are one function of their own
+# coordinates: psi_2 = psi_3 = psi_1 (same bases), so the coefficient vectors
+# of components 2 and 3 equal component 1's.  E3 maps component 1's unknowns
+# to the full ones, R3 keeps component 1's rows, A_red(E) = R3 (H - E S) E3.
+# Both parities p of the full permutations are held by this one equation (its
+# solutions split into the parts even and odd under psi_1(x, y, z) ->
+# (-1)^{M'} psi_1(x, y, -z)).
+
+def expansion3(prob):
+    """E3: component-1 unknowns [M'][z][x][y] -> full unknowns."""
+    n1 = prob.nM * prob.block[0]
+    if not (prob.block[0] == prob.block[1] == prob.block[2]):
+        raise ValueError("three identical particles need identical component bases")
+    I = sp.identity(n1, format="csr")
+    return sp.vstack([I, I, I], format="csr")
+
+
+def kept_rows3(prob):
+    return np.arange(prob.offsets[0][0], prob.offsets[0][0] + prob.nM * prob.block[0])
+
+
+def reduced_operator3(prob, E):
+    """A_red(E) = R3 (H - E S) E3."""
+    return (prob.assemble(E)[kept_rows3(prob)] @ expansion3(prob)).tocsr()
+
+
+def reduced_mass3(prob):
+    return (mass_matrix(prob)[kept_rows3(prob)] @ expansion3(prob)).tocsr()

@@ -64,9 +64,12 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                     for (int bb = 0; bb < 2; ++bb) {
                         const int b = (a + 1 + bb) % 3;
                         // exchange-reduced problems: partner 2 is p (-1)^{M''} times partner 1
-                        // at -z (eq. (2-sym-part)); its cell is looked up in component 1
-                        const bool mirror = p->absent(b);
-                        const int bc = mirror ? 0 : b;
+                        // at -z (eq. (2-sym-part)); with three identical particles both partners
+                        // are component 1 itself in their own coordinates (eq. (3-sym-part)).
+                        // The cell is looked up in component 1
+                        const bool implied = p->absent(b);
+                        const bool mirror = implied && p->exchange != 3;
+                        const int bc = implied ? 0 : b;
                         const Basis1D &bx = p->bx[bc], &by = p->by[bc], &bz = p->bz[bc];
                         const double c = p->crot[b][a], s = p->srot[b][a];
                         const double xb =

@@ -56,8 +56,9 @@ struct fm_problem {
     fm_problem_desc desc;
     int nM = 0, M0 = 0;
     int variant = 1;                         // preconditioner: 1 block-Jacobi in M', 2 coupled
-    int exchange = 0;                        // +-1: component 2 (index 1) is implied by component 1 (index 0)
-    bool absent(int a) const { return exchange != 0 && a == 1; }
+    int exchange = 0;                        // +-1: component 2 (index 1) is implied by component 1 (index 0);
+                                             // 3: components 2 and 3 are implied by component 1
+    bool absent(int a) const { return exchange != 0 && (a == 1 || (exchange == 3 && a == 2)); }
     long long N = 0;
     long long npts[3] = {0, 0, 0};
     long long off[3] = {0, 0, 0};

@@ -60,7 +60,8 @@ long long unknowns_of(const fm_problem_desc &d) {
     int M0 = (1 - d.tau) / 2;
     long long nM = d.J - M0 + 1, s = 0;
     for (int a = 0; a < 3; ++a)
-        if (!(d.exchange != 0 && a == 1)) s += (long long)d.x[a].n * d.y[a].n * d.z[a].n;
+        if (!(d.exchange != 0 && (a == 1 || (d.exchange == 3 && a == 2))))
+            s += (long long)d.x[a].n * d.y[a].n * d.z[a].n;
     return nM * s;
 }
 

@@ -72,16 +72,23 @@ std::string setup_problem(fm_problem *p) {
     if (d.precond != 0 && d.precond != FM_PREC_BLOCK_JACOBI && d.precond != FM_PREC_COUPLED)
         return "precond must be FM_PREC_BLOCK_JACOBI or FM_PREC_COUPLED";
     p->variant = d.precond == FM_PREC_COUPLED ? 2 : 1;
-    if (d.exchange != 0 && d.exchange != 1 && d.exchange != -1) return "exchange must be 0, +1 or -1";
+    if (d.exchange != 0 && d.exchange != 1 && d.exchange != -1 && d.exchange != 3)
+        return "exchange must be 0, +1, -1 or 3";
     p->exchange = d.exchange;
     if (d.exchange != 0) {
-        if (d.mass[0] != d.mass[1] || d.charge[0] != d.charge[1])
-            return "exchange symmetry needs particles 1 and 2 with equal masses and charges";
         auto same = [](const fm_dim &u, const fm_dim &v) {
             return u.degree == v.degree && u.n == v.n && u.R == v.R && u.map == v.map;
         };
+        if (d.mass[0] != d.mass[1] || d.charge[0] != d.charge[1])
+            return "exchange symmetry needs particles 1 and 2 with equal masses and charges";
         if (!same(d.x[0], d.x[1]) || !same(d.y[0], d.y[1]) || !same(d.z[0], d.z[1]))
             return "exchange symmetry needs identical bases for components 1 and 2";
+        if (d.exchange == 3) {
+            if (d.mass[2] != d.mass[0] || d.charge[2] != d.charge[0])
+                return "three identical particles need equal masses and charges";
+            if (!same(d.x[0], d.x[2]) || !same(d.y[0], d.y[2]) || !same(d.z[0], d.z[2]))
+                return "three identical particles need identical bases for all components";
+        }
     }
     for (int a = 0; a < 3; ++a) {
         std::string e = p->bx[a].init(d.x[a], false);

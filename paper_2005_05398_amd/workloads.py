@@ -159,10 +159,12 @@ def serving_arrivals(n, rate):
 
 def n_unknowns(desc):
     """N = n_M * sum_alpha n_z n_x n_y with n_M = J - M0 + 1, M0 = (1 - tau)/2
-    (components 1 and 3 only when the exchange symmetry is used)."""
+    (components 1 and 3 only with the exchange symmetry of two identical
+    particles, exchange = +-1; component 1 only for three, exchange = 3)."""
     m0 = (1 - desc["tau"]) // 2
     n_m = desc["J"] - m0 + 1
-    comps = (0, 2) if desc.get("exchange", 0) else (0, 1, 2)
+    ex = desc.get("exchange", 0)
+    comps = (0,) if ex == 3 else (0, 2) if ex else (0, 1, 2)
     return n_m * sum(desc["z"][a]["n"] * desc["x"][a]["n"] * desc["y"][a]["n"] for a in comps)
 
 

@@ -1,7 +1,10 @@
 """GPU parity of the exchange-reduced equations (Sec. 2, "Permutational
 symmetry", eq. (2-sym-part): two identical particles, components 1 and 3
 solved, component 2 = p (-1)^{M'} component 1 at -z) against the oracle's
-reduced system R (H - E S) E, and of the energies against the full system.
+reduced system R (H - E S) E, and of the energies against the full system;
+and of the one-component system of three identical particles (eq.
+(3-sym-part): component 1 alone, both partners read from it) against
+R3 (H - E S) E3.
 
 Tolerances as the full-system parity tests: operator 1e-11, preconditioner
 1e-9, solutions 1e-8, energies 1e-8.
@@ -109,3 +112,72 @@ def test_helium_table1_row1_by_exchange_parity(device):
     np.testing.assert_allclose(out[-1], triplets, rtol=1e-8)
     for e, want in zip(out[1], printed):
         assert abs(e - want) <= 5.1e-6
+
+
+# -- three identical particles (eq. (3-sym-part)): component 1 only ----------
+
+THREE_CASES = [
+    ("three_L0_quintic", W.make_desc((1.0, 1.0, 1.0), (-1.0, -1.0, -1.0), 10, 6, R=15.0, x0=3.0)),
+    ("three_L1_cubicz", W.make_desc((1.0, 1.0, 1.0), (1.0, 1.0, 1.0), 7, 4, J=1, deg_z=3, R=12.0, x0=3.0)),
+    ("three_L2_cubicz", W.make_desc((2.0, 2.0, 2.0), (-1.0, -1.0, -1.0), 7, 4, J=2, deg_z=3, R=12.0, x0=3.0)),
+]
+
+
+@pytest.mark.parametrize("name,desc", THREE_CASES, ids=[c[0] for c in THREE_CASES])
+def test_three_identical_operator_parity(device, name, desc):
+    from oracle.symmetry import reduced_operator3
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=3))
+    O = OracleProblem(desc)
+    n = O.nM * O.block[0]
+    assert P.N == n
+    Es = [-0.35, 0.2]
+    X = np.random.default_rng(14).standard_normal((2, n))
+    Y = to_dev(np.zeros((2, n)), device)
+    P.apply_operator(Es, to_dev(X, device), Y)
+    Yg = Y.cpu().numpy()
+    for r, E in enumerate(Es):
+        ref = reduced_operator3(O, E) @ X[r]
+        assert np.abs(Yg[r] - ref).max() <= 1e-11 * np.abs(ref).max(), (name, r)
+
+
+@pytest.mark.parametrize("name,desc", THREE_CASES, ids=[c[0] for c in THREE_CASES])
+def test_three_identical_precond_parity(device, name, desc):
+    """The preconditioner of the one-component system is component 1's."""
+    from oracle.symmetry import kept_rows3
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=3))
+    O = OracleProblem(desc)
+    keep = kept_rows3(O)
+    r = np.random.default_rng(16).standard_normal(len(keep))
+    z = to_dev(np.zeros((1, len(keep))), device)
+    P.apply_precond([-0.35], to_dev(r[None, :], device), z)
+    full = np.zeros(O.N)
+    full[keep] = r
+    ref = precond_reference(O, -0.35, full)[keep]
+    assert np.abs(z.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,desc", [THREE_CASES[0], THREE_CASES[2]], ids=[THREE_CASES[0][0], THREE_CASES[2][0]])
+def test_three_identical_solve_is_the_full_solution(device, name, desc):
+    """The one-component solve equals the oracle's LU of the reduced system,
+    and each component of the full system's solution for the right-hand side
+    repeated in all three components (1e-8)."""
+    from oracle.symmetry import reduced_operator3
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=3))
+    O = OracleProblem(desc)
+    E = -0.4
+    A = reduced_operator3(O, E)
+    n = A.shape[0]
+    b = W.rhs(12, n)
+    x = to_dev(np.zeros((1, n)), device)
+    st, res = P.solve([E], to_dev(b[None, :], device), x, restart=100, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    xg = x.cpu().numpy()[0]
+    assert rel_residual(A, xg, b) <= 1e-10
+    xref = lu_solve(A, b)
+    assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
+    xfull = lu_solve(O.assemble(E), np.concatenate([b, b, b]))
+    for a in range(3):
+        assert np.linalg.norm(xfull[a * n:(a + 1) * n] - xg) <= 1e-8 * np.linalg.norm(xg), a

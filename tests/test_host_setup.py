@@ -201,3 +201,35 @@ def test_host_coupling_exchange_reduced(name, desc, p):
 def test_exchange_rejects_distinct_particles():
     with pytest.raises(fm.FmError):
         fm.host_setup_check(dict(W.ps_cubic16()["desc"], exchange=1))     # Ps-: particles 1 and 2 differ
+
+
+THREE_CASES = [
+    ("three_L0_quintic", W.make_desc((1.0, 1.0, 1.0), (-1.0, -1.0, -1.0), 10, 6, R=15.0, x0=3.0)),
+    ("three_L1_cubicz", W.make_desc((1.0, 1.0, 1.0), (1.0, 1.0, 1.0), 7, 4, J=1, deg_z=3, R=12.0, x0=3.0)),
+    ("three_L2_cubicz", W.make_desc((2.0, 2.0, 2.0), (-1.0, -1.0, -1.0), 7, 4, J=2, deg_z=3, R=12.0, x0=3.0)),
+]
+
+
+@lib_built
+@pytest.mark.parametrize("name,desc", THREE_CASES, ids=[c[0] for c in THREE_CASES])
+def test_host_coupling_three_identical(name, desc):
+    """Three identical particles (component 1 only): the device's pairs, with
+    both partners read from component 1 at their rotated points, equal
+    R3 C E3 x of the oracle (E3 copies component 1's coefficients to all three
+    components, eq. (3-sym-part); R3 keeps component 1's rows)."""
+    from oracle.assemble import Problem as OracleProblem
+    from oracle.symmetry import expansion3, kept_rows3
+    O = OracleProblem(desc)
+    rdesc = dict(desc, exchange=3)
+    N = fm.host_setup_check(rdesc)[2]
+    assert N == O.nM * O.block[0] == W.n_unknowns(rdesc)
+    x = W.rhs(79, N)
+    y, npairs, ntasks = fm.host_coupling(rdesc, x)
+    ref = _oracle_coupling(desc, expansion3(O) @ x)[kept_rows3(O)]
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref), name
+
+
+@lib_built
+def test_three_identical_rejects_distinct_particles():
+    with pytest.raises(fm.FmError):
+        fm.host_setup_check(dict(W.make_desc(*W.H_MINUS, 7, 4, deg_z=3), exchange=3))

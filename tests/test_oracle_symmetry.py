@@ -7,6 +7,14 @@ P-S2  Helium (identical electrons): the lowest energies of the reduced system
       with p = +1 and p = -1 are the full system's 1 1S and 2 3S levels (the
       para and ortho ground states), and the reduced eigenvectors expanded to
       three components are eigenvectors of the full system.
+P-S3  Three identical particles (eqs. (3-sym), (3-sym-part)): the full system
+      with the same right-hand side in all three components' rows has the
+      same solution in all three components (the cyclic permutation of the
+      particles maps each component's equation onto the next one's), and it
+      equals the solution of the one-component reduced system; the reduced
+      system's energies near a shift are energies of the full system; the
+      reduced size of the paper's largest helium-trimer basis is the printed
+      1 342 683.
 """
 import numpy as np
 import pytest
@@ -14,7 +22,9 @@ import pytest
 from oracle.assemble import Problem
 from oracle.basis import Basis1D
 from oracle.eigen import mass_matrix, shift_invert_eigs
-from oracle.symmetry import expansion, mirror_z, reduced_shift_invert_eigs
+from oracle.symmetry import (expansion, mirror_z, reduced_mass3, reduced_operator3,
+                             reduced_shift_invert_eigs)
+from oracle.solve import lu_solve
 from paper_2005_05398_amd import workloads as W
 
 
@@ -52,3 +62,43 @@ def test_reduced_size_of_the_papers_largest_helium_system():
     P = Problem(d)
     assert P.nM * (P.block[0] + P.block[2]) == 4246848
     assert W.n_unknowns(dict(d, exchange=1)) == 4246848
+
+
+THREE = (1.0, 1.0, 1.0), (-1.0, -1.0, -1.0)          # three identical particles
+
+
+@pytest.mark.parametrize("J,deg_z", [(0, 5), (1, 3), (2, 3)])
+def test_three_identical_full_solution_is_threefold(J, deg_z):
+    prob = Problem(W.make_desc(*THREE, 7, 6 if deg_z == 5 else 4, J=J, deg_z=deg_z, R=12.0, x0=3.0))
+    n1 = prob.nM * prob.block[0]
+    E = -0.37
+    b = np.random.default_rng(40 + J).standard_normal(n1)
+    c_full = lu_solve(prob.assemble(E), np.concatenate([b, b, b]))
+    c_red = lu_solve(reduced_operator3(prob, E), b)
+    scale = np.linalg.norm(c_red)
+    for a in range(3):
+        assert np.linalg.norm(c_full[a * n1:(a + 1) * n1] - c_red) <= 1e-10 * scale, (J, a)
+
+
+def test_three_identical_energies_are_full_system_energies():
+    import scipy.sparse.linalg as spla
+    prob = Problem(W.make_desc(*THREE, 7, 6, R=12.0, x0=3.0))
+    sigma = 0.4
+    full = shift_invert_eigs(prob, sigma, 20)
+    A = reduced_operator3(prob, sigma).tocsc()
+    S = reduced_mass3(prob)
+    lu = spla.splu(A)
+    n = A.shape[0]
+    op = spla.LinearOperator((n, n), matvec=lambda v: lu.solve(S @ v), dtype=float)
+    theta = spla.eigs(op, k=3, which="LM", tol=1e-13, v0=np.ones(n), return_eigenvectors=False)
+    red = sigma + 1.0 / theta
+    for e in red:
+        assert np.min(np.abs(full - e)) <= 1e-8 * max(1.0, abs(e)), (e, full)
+
+
+def test_three_identical_reduced_size_of_the_helium_trimer_basis():
+    """The paper's largest helium-trimer system (Sec. 4, J = 0, one equation
+    by the permutational symmetry of all three atoms): basis (1: 223, 223, 27)
+    gives the printed 1 342 683 unknowns."""
+    assert 1 * 223 * 223 * 27 == 1342683
+    assert W.n_unknowns(dict(W.make_desc(*THREE, 223, 27, deg_z=5), exchange=3)) == 1342683
