@@ -228,6 +228,19 @@ void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int 
                      const double *in, double *out, hipStream_t st);
 bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
                   double *data, int mode, double *tmp, hipStream_t st);
+// The reduced-precision preconditioner (mode 1: FP32 MFMA, 2: BF16x3 MFMA)
+// with FP32 storage between its products, in three launches: the z product
+// (which 0: in -> the FP32 view of tmp; the coupled variant's joint z product
+// stays FP64, in -> tmp), the four staged x-y products through the FP32 views
+// of out and tmp with the FP64 divide, and the z product back (which 1: into
+// out, FP64).  in may equal out; tmp: [nb][N] doubles.  precond_f32_ok: the
+// staged products and the register z product apply (else the caller runs the
+// FP64-storage path).
+bool precond_f32_ok(const ProblemDev &pd, const PrecDev &pr, int nb);
+void launch_z_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
+                  double *out, double *tmp, hipStream_t st);
+void launch_xy_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, int mode,
+                   double *out, double *tmp, hipStream_t st);
 // Arnoldi / GMRES pieces (V and Z stored [i][request][N])
 // Step j: dot pass over slots 0..j+1 (0..j when closing), then the per-request
 // finish (Hessenberg column j - 1, Givens, stop test), then the update pass.

@@ -814,11 +814,11 @@ __global__ void __launch_bounds__(MZ_COLS) k_modez(const ProblemDev *__restrict_
 // F32: the products in FP32 (inputs rounded to FP32, outputs widened).
 constexpr int MZ2_THREADS = 256;
 
-template <int MAXNZ, bool F32>
+template <int MAXNZ, bool F32, class TI = double, class TO = double>
 __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__restrict__ pd,
                                                            const PrecDev *__restrict__ pr,
                                                            const int *__restrict__ active, int which,
-                                                           const double *in, double *out, int split) {
+                                                           const TI *in, TO *out, int split) {
     using T = typename std::conditional<F32, float, double>::type;
     const int req = blockIdx.z;
     if (active && !active[req]) return;
@@ -886,7 +886,7 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
             }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (k2 + u < nz) out[base + (long long)(k2 + u) * nxy] = (double)acc[u];
+            if (k2 + u < nz) out[base + (long long)(k2 + u) * nxy] = (TO)acc[u];
     }
 }
 
@@ -1084,7 +1084,8 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // One element of the divided slice, (Lambda_x (x) I + I (x) Lambda_y - E)^-1 T
 // at (i, j), from T and the 2x2 / 4x4 blocks of complex pairs it belongs to
 // (the same closed forms as block_divide); mind tracks min |denominator|.
-__device__ __forceinline__ double divided_at(const double *__restrict__ T, int ld, int i, int j,
+template <class TT>
+__device__ __forceinline__ double divided_at(const TT *__restrict__ T, int ld, int i, int j,
                                              const double *__restrict__ lx, const double *__restrict__ lxi,
                                              const signed char *__restrict__ tx, const double *__restrict__ ly,
                                              const double *__restrict__ lyi, const signed char *__restrict__ ty,
@@ -1094,7 +1095,7 @@ __device__ __forceinline__ double divided_at(const double *__restrict__ T, int l
     const double d = lx[i0] + ly[j0] - E;
     if (ti == 0 && tj == 0) {
         mind = fmin(mind, fabs(d));
-        return T[(size_t)i * ld + j] / d;
+        return (double)T[(size_t)i * ld + j] / d;
     }
     if (tj == 0) {
         const double b = lxi[i0], r0 = T[(size_t)i0 * ld + j], r1 = T[(size_t)(i0 + 1) * ld + j], det = d * d + b * b;
@@ -1504,6 +1505,228 @@ __device__ void block_divide_f32(float *T, int ld, int nx, int ny, const double 
         }
     }
     __syncthreads();
+}
+
+// Staged x-y products in reduced precision with FP32 storage between them:
+// the tiling of k_slice_gemm (BT x BT block tiles, WT x WT 16 x 16 MFMA tiles
+// per wave, K in chunks of SG_KC with the next chunk fetched during the
+// products) on FP32 MFMA (MODE 1: v_mfma_f32_16x16x4f32) or BF16x3 MFMA
+// (MODE 2: operands split into bfloat16 hi + mid as they are read, three
+// products, FP32 sums).  TI / TO: element types of in and out (FP32 between
+// the products; FP64 at the ends of the coupled variant).  DIV (LEFT only):
+// the input divided in FP64 by lambda_x + lambda_y - E as it is fetched
+// (complex pairs by their closed forms), then rounded to FP32.
+template <bool LEFT, bool DIV, int MODE, int BT, class TI, class TO>
+__global__ void __launch_bounds__(256) k_slice_gemm_f32(const ProblemDev *__restrict__ pd,
+                                                        const PrecDev *__restrict__ pr,
+                                                        const double *__restrict__ Evec,
+                                                        const int *__restrict__ active, int which,
+                                                        const TI *__restrict__ in, TO *__restrict__ out) {
+    static_assert(BT == 32 || BT == 64, "block tile 32 x 32 or 64 x 64");
+    static_assert(!DIV || LEFT, "the divide is applied by the left product");
+    constexpr int WT = BT / 32;
+    const int req = blockIdx.z;
+    if (active && !active[req]) return;
+    int a, iM, k;
+    if (!slice_decode(pd, blockIdx.x, a, iM, k)) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nz = C.z.n, nx = C.x.n, ny = C.y.n;
+    const int tr = sg_tiles(nx, BT), tc = sg_tiles(ny, BT);
+    const int t = blockIdx.y;
+    if (t >= tr * tc) return;
+    const int i0 = (t / tc) * BT, j0 = (t % tc) * BT;
+    constexpr bool EXT = BT == 32;
+    const bool erow = EXT && i0 + BT == nx - 1 && nx % BT == 1, ecol = EXT && j0 + BT == ny - 1 && ny % BT == 1;
+    const size_t fx = (size_t)iM * nz + k;
+    const float *Wm = LEFT ? F.Wx32 + (fx * 2 + which) * nx * nx : F.Wy32 + (fx * 2 + which) * ny * ny;
+    const long long off = (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    const TI *g = in + off;
+    TO *o = out + off;
+    const int K = LEFT ? nx : ny;
+    const double E = DIV ? Evec[req] : 0.0;
+    double mind = 1e300;
+    __shared__ float As[BT][SG_KC + 1];
+    __shared__ float Bs[SG_KC][BT + 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
+    constexpr int PER = BT * SG_KC / 256;
+    using RB = typename std::conditional<DIV, double, float>::type;
+    float ra[PER];
+    RB rb[PER];
+    __shared__ float Ae[SG_KC], Be[SG_KC];
+    float rae = 0.f, ext = 0.f;
+    RB rbe = 0;
+    constexpr int DIV_ROWS = 256;
+    __shared__ double sLx[DIV ? DIV_ROWS : 1];
+    __shared__ signed char sTx[DIV ? DIV_ROWS : 1];
+    const bool staged = DIV && K <= DIV_ROWS;
+    double ly_c = 0.0;
+    int ty_c = 1;
+    if (DIV) {
+        typedef const __attribute__((address_space(1))) double gdouble;
+        typedef const __attribute__((address_space(1))) signed char gschar;
+        const int r = threadIdx.x;
+        const bool st = staged && r < K;
+        const double lxv = st ? ((gdouble *)F.lx)[fx * nx + r] : 0.0;
+        const signed char txv = st ? ((gschar *)F.tx)[fx * nx + r] : (signed char)0;
+        const int jc = j0 + (int)threadIdx.x % BT;
+        if (jc < ny) {
+            ly_c = ((gdouble *)F.ly)[fx * ny + jc];
+            ty_c = ((gschar *)F.ty)[fx * ny + jc];
+        }
+        if (st) {
+            sLx[r] = lxv;
+            sTx[r] = txv;
+        }
+        __syncthreads();
+    }
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / SG_KC, c = e % SG_KC;
+            const int row = i0 + r, kk = k0 + c;
+            float av = 0.f;
+            if (row < nx && kk < K) av = LEFT ? Wm[(size_t)row * nx + kk] : (float)g[(size_t)row * ny + kk];
+            ra[q] = av;
+            RB bv = 0;
+            if (LEFT) {
+                const int kb = e / BT, cb = e % BT;
+                if (k0 + kb < K && j0 + cb < ny) bv = (RB)g[(size_t)(k0 + kb) * ny + j0 + cb];
+            } else {
+                const int cb = e / SG_KC, kb = e % SG_KC;
+                if (k0 + kb < K && j0 + cb < ny) bv = Wm[(size_t)(j0 + cb) * ny + k0 + kb];
+            }
+            rb[q] = bv;
+        }
+        if (erow && threadIdx.x < SG_KC) {
+            const int kk = k0 + threadIdx.x;
+            rae = kk < K ? (LEFT ? Wm[(size_t)(nx - 1) * nx + kk] : (float)g[(size_t)(nx - 1) * ny + kk]) : 0.f;
+        }
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) {
+            const int kb = k0 + (int)threadIdx.x - 64;
+            rbe = kb < K ? (LEFT ? (RB)g[(size_t)kb * ny + ny - 1] : (RB)Wm[(size_t)(ny - 1) * ny + kb]) : (RB)0;
+        }
+    };
+    auto divide = [&](int k0) {
+        if (!DIV) return;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int kb = e / BT, cb = e % BT;
+            if (k0 + kb < K && j0 + cb < ny) {
+                if (staged && ty_c == 0 && sTx[k0 + kb] == 0) {
+                    const double d = sLx[k0 + kb] + ly_c - E;
+                    mind = fmin(mind, fabs(d));
+                    rb[q] = (double)rb[q] * rcp_newton(d);
+                } else {
+                    rb[q] = divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
+                                       F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
+                }
+            }
+        }
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC && k0 + (int)threadIdx.x - 64 < K)
+            rbe = divided_at(g, ny, k0 + (int)threadIdx.x - 64, ny - 1, F.lx + fx * nx, F.lxi + fx * nx,
+                             F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            As[e / SG_KC][e % SG_KC] = ra[q];
+            if (LEFT) Bs[e / BT][e % BT] = (float)rb[q];
+            else Bs[e % SG_KC][e / SG_KC] = (float)rb[q];
+        }
+        if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = (float)rbe;
+    };
+    flt4 acc[WT][WT];
+#pragma unroll
+    for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj) acc[ti][tj] = flt4{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    divide(0);
+    for (int k0 = 0; k0 < K; k0 += SG_KC) {
+        stash();
+        __syncthreads();
+        if (k0 + SG_KC < K) fetch(k0 + SG_KC);
+        if (MODE == 1) {
+#pragma unroll
+            for (int kk = 0; kk < SG_KC; kk += 4) {
+                if (kk >= K - k0) break;            // the zero padding past K
+                float av[WT], bv[WT];
+#pragma unroll
+                for (int ti = 0; ti < WT; ++ti) av[ti] = As[16 * (WT * wi + ti) + r16][kk + k4];
+#pragma unroll
+                for (int tj = 0; tj < WT; ++tj) bv[tj] = Bs[kk + k4][16 * (WT * wj + tj) + r16];
+#pragma unroll
+                for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < WT; ++tj)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < SG_KC; kb += 16) {
+                if (kb >= K - k0) break;
+                sht4 ahi[WT], amid[WT], bhi[WT], bmid[WT];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                    for (int ti = 0; ti < WT; ++ti) {
+                        short h, m;
+                        split_bf16(As[16 * (WT * wi + ti) + r16][kb + 4 * k4 + e], h, m);
+                        ahi[ti][e] = h;
+                        amid[ti][e] = m;
+                    }
+#pragma unroll
+                    for (int tj = 0; tj < WT; ++tj) {
+                        short h, m;
+                        split_bf16(Bs[kb + 4 * k4 + e][16 * (WT * wj + tj) + r16], h, m);
+                        bhi[tj][e] = h;
+                        bmid[tj][e] = m;
+                    }
+                }
+#pragma unroll
+                for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < WT; ++tj) {
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(amid[ti], bhi[tj], acc[ti][tj], 0, 0, 0);
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[ti], bmid[tj], acc[ti][tj], 0, 0, 0);
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[ti], bhi[tj], acc[ti][tj], 0, 0, 0);
+                    }
+            }
+        }
+        if (erow || ecol) {
+            const int tx = threadIdx.x, kn = min(SG_KC, K - k0);
+            if (erow && tx < BT)
+                for (int kk = 0; kk < kn; ++kk) ext = fmaf(Ae[kk], Bs[kk][tx], ext);
+            else if (ecol && tx >= BT && tx < 2 * BT)
+                for (int kk = 0; kk < kn; ++kk) ext = fmaf(As[tx - BT][kk], Be[kk], ext);
+            else if (erow && ecol && tx == 2 * BT)
+                for (int kk = 0; kk < kn; ++kk) ext = fmaf(Ae[kk], Be[kk], ext);
+        }
+        if (k0 + SG_KC < K) divide(k0 + SG_KC);
+        __syncthreads();
+    }
+    (void)mind;
+#pragma unroll
+    for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = i0 + 16 * (WT * wi + ti) + 4 * k4 + v, col = j0 + 16 * (WT * wj + tj) + r16;
+                if (row < nx && col < ny) o[(size_t)row * ny + col] = (TO)acc[ti][tj][v];
+            }
+    if (erow || ecol) {
+        const int tx = threadIdx.x;
+        if (erow && tx < BT && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = (TO)ext;
+        else if (ecol && tx >= BT && tx < 2 * BT && i0 + tx - BT < nx) o[(size_t)(i0 + tx - BT) * ny + ny - 1] = (TO)ext;
+        else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = (TO)ext;
+    }
 }
 
 // Staged x-y products in reduced precision (same tiling and pipelining as
@@ -2285,9 +2508,9 @@ void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int 
 }
 
 // Launches the register-column mode-z kernel for nz <= 64, else the LDS one.
-template <bool F32>
+template <bool F32, class TI = double, class TO = double>
 bool launch_modez_reg(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
-                      const double *in, double *out, hipStream_t st) {
+                      const TI *in, TO *out, hipStream_t st) {
     int maxnxy = 0, maxnz = 0;
     for (int a = 0; a < 3; ++a) {
         maxnxy = std::max(maxnxy, pd.comp[a].nxy);
@@ -2302,7 +2525,7 @@ bool launch_modez_reg(const ProblemDev &pd, const PrecDev &pr, int nb, const int
     while (split < 8 && 4 * split < maxnz && cols * split < 256 * 1024) split *= 2;
     if (split == 1 && 4 < maxnz && cols < 512 * 1024) split = 2;
     dim3 grid(cdiv(maxnxy, MZ2_THREADS / split), 3 * pd.nM, nb);
-#define FM_MZ(M) hipLaunchKernelGGL((k_modez_reg<M, F32>), grid, dim3(MZ2_THREADS), 0, st, pd.dev, pr.dev, active, which, in, out, split)
+#define FM_MZ(M) hipLaunchKernelGGL((k_modez_reg<M, F32, TI, TO>), grid, dim3(MZ2_THREADS), 0, st, pd.dev, pr.dev, active, which, in, out, split)
     if (maxnz <= 16) FM_MZ(16);
     else if (maxnz <= 32) FM_MZ(32);
     else if (maxnz <= 48) FM_MZ(48);
@@ -2454,6 +2677,86 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
     else FM_XYLP(8, 8)
 #undef FM_XYLP
     return true;
+}
+
+bool xy_lp_staged(const ProblemDev &pd, int nb) {
+    int slices = 0, side = 0;
+    for (int a = 0; a < 3; ++a) {
+        slices += pd.nM * pd.comp[a].z.n;
+        side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
+    }
+    return side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW;
+}
+
+// The four staged x-y products with FP32 storage between them: src (TI) ->
+// A -> B -> A (with the FP64 divide) -> dst (TO); A and B: [nb][N] FP32.
+template <int MODE, int BT, class TI, class TO>
+void xy_f32_chain(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
+                  const TI *src, float *A, float *B, TO *dst, hipStream_t st) {
+    int slices = 0, tl = 0;
+    for (int a = 0; a < 3; ++a) {
+        slices += pd.nM * pd.comp[a].z.n;
+        tl = std::max(tl, sg_tiles(pd.comp[a].x.n, BT) * sg_tiles(pd.comp[a].y.n, BT));
+    }
+    const dim3 g(slices, tl, nb);
+    hipLaunchKernelGGL((k_slice_gemm_f32<true, false, MODE, BT, TI, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
+                       E_dev, active, 0, src, A);
+    hipLaunchKernelGGL((k_slice_gemm_f32<false, false, MODE, BT, float, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
+                       E_dev, active, 0, A, B);
+    hipLaunchKernelGGL((k_slice_gemm_f32<true, true, MODE, BT, float, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
+                       E_dev, active, 1, B, A);
+    hipLaunchKernelGGL((k_slice_gemm_f32<false, false, MODE, BT, float, TO>), g, dim3(256), 0, st, pd.dev, pr.dev,
+                       E_dev, active, 1, A, dst);
+}
+
+template <class TI, class TO>
+void xy_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, int mode,
+            const TI *src, float *A, float *B, TO *dst, hipStream_t st) {
+    int slices = 0, side = 0;
+    long long t64 = 0, area64 = 0, area32 = 0;
+    for (int a = 0; a < 3; ++a) {
+        slices += pd.nM * pd.comp[a].z.n;
+        const int nx = pd.comp[a].x.n, ny = pd.comp[a].y.n;
+        side = std::max(side, std::max(nx, ny));
+        t64 = std::max<long long>(t64, (long long)sg_tiles(nx, 64) * sg_tiles(ny, 64));
+        area64 += 4096LL * sg_tiles(nx, 64) * sg_tiles(ny, 64);
+        area32 += 1024LL * sg_tiles(nx, 32) * sg_tiles(ny, 32);
+    }
+    const bool t64ok = side > 32 && t64 * slices * nb >= XY_T64_MIN_BLOCKS && 4 * area64 <= 5 * area32;
+    if (mode == 1) {
+        if (t64ok) xy_f32_chain<1, 64>(pd, pr, nb, E_dev, active, src, A, B, dst, st);
+        else xy_f32_chain<1, 32>(pd, pr, nb, E_dev, active, src, A, B, dst, st);
+    } else {
+        if (t64ok) xy_f32_chain<2, 64>(pd, pr, nb, E_dev, active, src, A, B, dst, st);
+        else xy_f32_chain<2, 32>(pd, pr, nb, E_dev, active, src, A, B, dst, st);
+    }
+}
+
+bool precond_f32_ok(const ProblemDev &pd, const PrecDev &pr, int nb) {
+    if (!xy_lp_staged(pd, nb)) return false;
+    int maxnz = 0;
+    for (int a = 0; a < 3; ++a) maxnz = std::max(maxnz, pd.comp[a].z.n);
+    return pr.coupled || maxnz <= 64;
+}
+
+void launch_z_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
+                  double *out, double *tmp, hipStream_t st) {
+    float *B = reinterpret_cast<float *>(tmp);
+    if (pr.coupled) {
+        // the joint z products stay FP64 (as in every variant)
+        if (which == 0) launch_zjoint(pd, pr, nb, active, 0, in, tmp, st);
+        else launch_zjoint(pd, pr, nb, active, 1, tmp, out, st);
+        return;
+    }
+    if (which == 0) launch_modez_reg<true, double, float>(pd, pr, nb, active, 0, in, B, st);
+    else launch_modez_reg<true, float, double>(pd, pr, nb, active, 1, B, out, st);
+}
+
+void launch_xy_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, int mode,
+                   double *out, double *tmp, hipStream_t st) {
+    float *A = reinterpret_cast<float *>(out), *B = reinterpret_cast<float *>(tmp);
+    if (pr.coupled) xy_f32<double, double>(pd, pr, nb, E_dev, active, mode, tmp, A, B, tmp, st);
+    else xy_f32<float, float>(pd, pr, nb, E_dev, active, mode, B, A, B, B, st);
 }
 
 // Groups of 8 vectors: as fast as 16 while every request iterates, and faster

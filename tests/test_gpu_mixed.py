@@ -101,3 +101,26 @@ def test_long_cycle_reduced_precision_full_size(device, prec):
         assert res_lp[i]["rel_residual"] <= 1e-10
         err = (torch.linalg.norm(xlp[i] - x64[i]) / torch.linalg.norm(x64[i])).item()
         assert err <= 1e-8, (prec, i, err)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 1e-3)])
+@pytest.mark.parametrize("precond", ["block_jacobi", "coupled"])
+def test_precond_reduced_precision_wide_batch(device, prec, tol, precond):
+    """A batch large enough for the 64 x 64 block tiles of the staged products
+    (the energy scan's grid, 16 requests; L = 1 for the coupled variant, whose
+    joint z products stay FP64 around the FP32 x-y products)."""
+    import torch
+    fm = _fm()
+    desc = W.hminus_scan()["desc"]
+    if precond == "coupled":
+        desc = dict(W.make_desc(*W.H_MINUS, 64, 24, J=1, deg_z=5, R=40.0, xy_map="quadratic"), precond="coupled")
+    P = fm.Problem(desc)
+    nb = 16
+    r = to_dev(W.rhs_batch([50 + i for i in range(nb)], P.N), device)
+    z64 = torch.zeros_like(r)
+    zlp = torch.zeros_like(r)
+    Es = list(np.linspace(-0.6, -0.1, nb))
+    P.apply_precond(Es, r, z64, prec="fp64")
+    P.apply_precond(Es, r, zlp, prec=prec)
+    err = (torch.linalg.norm(zlp - z64, dim=1) / torch.linalg.norm(z64, dim=1)).max().item()
+    assert err <= tol, (prec, precond, err)
