@@ -104,6 +104,16 @@ typedef struct {
                                  [M'][z][x][y] of component 1 and N = n_M n_1.  Both parities of the
                                  full permutations are held (they are the parts of psi_1 even and odd
                                  under psi(x, y, z) -> (-1)^{M'} psi(x, y, -z)) */
+    int zhalf;                /* 0: every component on z in [-1, 1].  1 (with exchange = +-1 and n_M = 1):
+                                 component 3, symmetric or antisymmetric in z (parity
+                                 sigma = p (-1)^{M0}, eq. (2-sym-part)), is solved on z in [0, 1]: its
+                                 z basis is the part of the basis z[2] (which needs an even number of
+                                 intervals, so that z = 0 is a node) on [0, 1], with the functions at
+                                 z = 0 restricted to the parity, and its collocation points those of
+                                 z[2] in [0, 1] (z = 0 itself only for an even quintic basis); the
+                                 coupling reads it at |z_3| times sigma for z_3 < 0.  Its n_z becomes
+                                 n/2 (cubic), 3K/2 + 2 (quintic, sigma = +1) or 3K/2 + 1 (quintic,
+                                 sigma = -1) for n = 3K + 3 */
 } fm_problem_desc;
 
 typedef struct fm_problem fm_problem;

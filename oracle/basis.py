@@ -81,13 +81,43 @@ class Basis1D:
     kind "xy": Dirichlet at both ends of [0, R].  kind "z": [-1, 1], no condition.
     """
 
-    def __init__(self, degree, n, kind, R=2.0, mapname="uniform"):
+    def __init__(self, degree, n, kind, R=2.0, mapname="uniform", parity=0):
+        """kind "zhalf": the part on [0, 1] of the z basis of n functions (n of
+        the full basis, an even number K of intervals) for functions of parity
+        `parity` (+1 even, -1 odd) about z = 0 (Sec. 2, "Permutational
+        symmetry": the symmetric component's z-domain reduced to [0, 1]).  The
+        nodes and points are the full basis's ones in [0, 1]; at z = 0 the
+        functions of the other parity's derivative orders are dropped (an even
+        function has zero odd derivatives there, an odd one zero even ones),
+        and z = 0 stays a collocation point only where the full basis has it
+        (quintic) and the function can be nonzero there (even)."""
         if degree not in (3, 5):
             raise ValueError("degree must be 3 or 5")
         q = (degree + 1) // 2
-        self.degree, self.q, self.n, self.kind = degree, q, n, kind
+        self.degree, self.q, self.kind = degree, q, kind
         dropped = set()
         extra_node_point = None
+        if kind == "zhalf":
+            full = Basis1D(degree, n, "z", 2.0, mapname)
+            if full.K % 2 or parity not in (1, -1):
+                raise ValueError("half z basis needs an even number of intervals and parity +-1")
+            K = full.K // 2
+            self.parity = parity
+            self.K, self.R, self.lo = K, 1.0, 0.0
+            self.nodes = full.nodes[K:].copy()
+            self.nodes[0] = 0.0
+            self.hbar = full.hbar
+            dropped = {(0, d) for d in range(q) if (d % 2 == 0) != (parity == 1)}
+            self.funcs = [(m, d) for m in range(K + 1) for d in range(q) if (m, d) not in dropped]
+            self.index = {f: g for g, f in enumerate(self.funcs)}
+            self.n = len(self.funcs)
+            keep = full.points >= 0.0 if parity == 1 else full.points > 0.0
+            self.points = full.points[keep].copy()
+            if len(self.points) != self.n:
+                raise AssertionError("half closure does not give n points")
+            self.shape = hermite_shape_monomials(q)
+            return
+        self.n = n
         if kind == "xy":
             if degree == 3:
                 if n % 2 or n < 2:
@@ -200,3 +230,8 @@ class Basis1D:
 
 def basis_for(dim, kind):
     return Basis1D(dim["degree"], dim["n"], kind, dim.get("R", 2.0), dim.get("map", "uniform"))
+
+
+def half_z_basis(dim, parity):
+    """The z basis of dim restricted to [0, 1] for functions of the given parity."""
+    return Basis1D(dim["degree"], dim["n"], "zhalf", 2.0, dim.get("map", "uniform"), parity=parity)

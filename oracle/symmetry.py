@@ -128,3 +128,64 @@ def reduced_operator3(prob, E):
 
 def reduced_mass3(prob):
     return (mass_matrix(prob)[kept_rows3(prob)] @ expansion3(prob)).tocsr()
+
+
+# -- the symmetric component on z in [0, 1] (the last remark of Sec. 2) ---------
+# With two identical particles and n_M = 1, component 3 has the parity
+# sigma = p (-1)^{M0} about z = 0 (eq. (2-sym-part)); it is represented by the
+# half basis (oracle.basis.half_z_basis) and extended to z < 0 by the parity.
+# Plain definition: E_h maps (psi_1, psi_3 on [0, 1]) to the full unknowns
+# (psi_1, psi_2 = p (-1)^{M'} mirror(psi_1), psi_3 = extension); R_h keeps the
+# rows of component 1 and the rows of component 3 at the half basis's points;
+# A_half(E) = R_h (H - E S) E_h.
+
+def half_parity(prob, p):
+    return p * (-1) ** prob.M0
+
+
+def z_extension(bz_full, bz_half, sigma):
+    """Full-basis coefficients of f(z) = sigma^[z < 0] g(|z|), g in the half
+    basis (exact: the full basis's nodes are the half ones mirrored)."""
+    t = bz_full.points
+    sign = np.where(t < 0.0, float(sigma), 1.0)
+    vals = sign[:, None] * bz_half.matrix(0, t=np.abs(t))
+    return np.linalg.solve(bz_full.matrix(0), vals)
+
+
+def expansion_half(prob, p, bz_half):
+    if prob.nM != 1:
+        raise ValueError("the halved z-domain needs n_M = 1")
+    sigma = half_parity(prob, p)
+    Ered = expansion(prob, p).tocsr()              # (psi_1, psi_3 full) -> full unknowns
+    n1, n3 = prob.block[0], prob.block[2]
+    nxy3 = prob.bx[2].n * prob.by[2].n
+    X = z_extension(prob.bz[2], bz_half, sigma)    # nz_full x nz_half
+    ext = sp.kron(sp.csr_matrix(X), sp.identity(nxy3), format="csr")
+    T = sp.block_diag([sp.identity(n1), ext], format="csr")
+    return (Ered @ T).tocsr()
+
+
+def kept_rows_half(prob, bz_half):
+    """Rows of component 1, then rows of component 3 at the half basis's points."""
+    o1, o3 = prob.offsets[0][0], prob.offsets[2][0]
+    nxy3 = prob.bx[2].n * prob.by[2].n
+    full_pts = prob.bz[2].points
+    zi = [int(np.argmin(np.abs(full_pts - t))) for t in bz_half.points]
+    assert np.allclose(full_pts[zi], bz_half.points, atol=1e-15)
+    rows3 = np.concatenate([o3 + k * nxy3 + np.arange(nxy3) for k in zi])
+    return np.concatenate([np.arange(o1, o1 + prob.block[0]), rows3])
+
+
+def reduced_operator_half(prob, E, p, bz_half):
+    """A_half(E) = R_h (H - E S) E_h."""
+    return (prob.assemble(E)[kept_rows_half(prob, bz_half)] @ expansion_half(prob, p, bz_half)).tocsr()
+
+
+def separable_half(prob, E, bz_half):
+    """The preconditioner's separable operator of the halved system:
+    block-diagonal (L_1 on the full grid, L_3 on the half z basis)."""
+    import copy
+    q = copy.copy(prob)
+    q.bz = list(prob.bz)
+    q.bz[2] = bz_half
+    return sp.block_diag([prob.separable_block(0, E), q.separable_block(2, E)], format="csr")

@@ -11,6 +11,9 @@
 //   z degree 3:   n = 2K + 2, 2 per interval, 1 extra in each end interval.
 //   z degree 5:   n = 3K + 3, 3 per interval, 1 extra in each end interval and
 //                 1 in the middle interval (K odd) or at the middle node (K even).
+//   z halved to [0, 1] (a component of definite parity about z = 0, Sec. 2,
+//   "Permutational symmetry"): the full basis's nodes and points in [0, 1],
+//   the functions at z = 0 restricted to the parity.
 // The function of derivative order d at a node carries the factor 1/hbar^d,
 // hbar = R/K (x, y) or 2/K (z), so its coefficient is hbar^d psi^(d)(node).
 #include <algorithm>
@@ -166,7 +169,86 @@ std::string Basis1D::init(const fm_dim &d, bool is_z) {
     return "";
 }
 
+std::string Basis1D::init_half(const fm_dim &d, int sigma) {
+    degree = d.degree;
+    if (degree != 3 && degree != 5) return "degree must be 3 or 5";
+    q = (degree + 1) / 2;
+    int Kf;
+    if (degree == 3) {
+        if (d.n < 4 || d.n % 2) return "cubic z basis needs an even n >= 4";
+        Kf = (d.n - 2) / 2;
+    } else {
+        if (d.n < 6 || d.n % 3) return "quintic z basis needs n = 3K + 3";
+        Kf = d.n / 3 - 1;
+    }
+    if (Kf % 2) return "a z basis halved to [0, 1] needs an even number of intervals (z = 0 a node)";
+    if (sigma != 1 && sigma != -1) return "parity must be +1 or -1";
+    half = sigma;
+    dirichlet = false;
+    K = Kf / 2;
+    R = 1.0;
+    lo = 0.0;
+    hbar = 1.0 / K;                              // = 2 / Kf, the full basis's hbar
+    // node 0 keeps the orders of the parity: even functions have odd derivatives
+    // zero there, odd functions even ones
+    int kept0 = 0;
+    for (int o = 0; o < q; ++o) kept0 += ((o % 2 == 0) == (sigma == 1)) ? 1 : 0;
+    n = kept0 + K * q;
+    nodes.resize(K + 1);
+    for (int i = 0; i <= K; ++i) {
+        const double u = double(i) / K;
+        switch (d.map) {
+            case FM_MAP_SIN: nodes[i] = std::sin(M_PI * u / 2.0); break;
+            case FM_MAP_UNIFORM: nodes[i] = u; break;
+            default: return "z map must be sin or uniform";
+        }
+    }
+    nodes[0] = 0.0;
+    nodes[K] = 1.0;
+    // the full basis's points in [0, 1]: q Gauss points per interval, one more
+    // in the end interval at z = 1, and (quintic) the full basis's node point
+    // z = 0, which only even functions keep as a collocation point
+    std::vector<int> counts(K, q);
+    counts[K - 1] += 1;
+    points.clear();
+    for (int m = 0; m < K; ++m) {
+        std::vector<double> g = gauss_nodes(counts[m]);
+        const double a = nodes[m], b = nodes[m + 1];
+        for (double gi : g) points.push_back(0.5 * (a + b) + 0.5 * (b - a) * gi);
+    }
+    if (degree == 5 && sigma == 1) points.push_back(0.0);
+    std::sort(points.begin(), points.end());
+    if ((int)points.size() != n) return "internal: half-basis point count";
+    idx.assign(size_t(n) * MAXR, -1);
+    for (int k = 0; k < 3; ++k) val[k].assign(size_t(n) * MAXR, 0.0);
+    for (int p = 0; p < n; ++p) {
+        int g[MAXR];
+        double v[MAXR];
+        for (int k = 0; k < 3; ++k) {
+            eval_local(points[p], k, g, v);
+            for (int sl = 0; sl < 2 * q; ++sl) {
+                idx[size_t(p) * MAXR + sl] = g[sl];
+                val[k][size_t(p) * MAXR + sl] = g[sl] >= 0 ? v[sl] : 0.0;
+            }
+        }
+    }
+    return "";
+}
+
 int Basis1D::global_index(int m, int d) const {
+    if (half) {
+        // node 0 keeps the orders of the parity, numbered first; then q per node
+        auto kept = [&](int o) { return (o % 2 == 0) == (half == 1); };
+        if (m == 0) {
+            if (!kept(d)) return -1;
+            int r = 0;
+            for (int o = 0; o < d; ++o) r += kept(o) ? 1 : 0;
+            return r;
+        }
+        int k0 = 0;
+        for (int o = 0; o < q; ++o) k0 += kept(o) ? 1 : 0;
+        return k0 + (m - 1) * q + d;
+    }
     if (dirichlet && d == 0 && (m == 0 || m == K)) return -1;
     int g = m * q + d - (dirichlet ? 1 : 0);
     if (dirichlet && m == K) g -= 1;            // skip the dropped value function at node K

@@ -81,7 +81,13 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                         double zb = den > 0.0 ? (s * c * (yc * yc - xc * xc) + (c * c - s * s) * xc * yc * zc) / den
                                               : 0.0;
                         zb = std::fmin(1.0, std::fmax(-1.0, zb));
-                        const double zl = mirror ? -zb : zb;          // where the stored component is read
+                        double zl = mirror ? -zb : zb;                // where the stored component is read
+                        // component 3 stored on z in [0, 1] (zhalf): read at |z| times its parity
+                        double fold = 1.0;
+                        if (p->zhalf && bc == 2 && zl < 0.0) {
+                            zl = -zl;
+                            fold = p->zsigma;
+                        }
                         const int mz = bz.interval(zl), mx = bx.interval(xb), my = by.interval(yb);
                         Rec r;
                         r.key = keyoff[bc] + (mz * bx.K + mx) * by.K + my;
@@ -92,7 +98,7 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                         recs[t].push_back(r);
                         const double base = vs * xc * yc / den;
                         if (J == 0) {
-                            facs[t].push_back(mirror ? p->exchange * base : base);
+                            facs[t].push_back((mirror ? p->exchange * base : base) * fold);
                             continue;
                         }
                         double arg = (-s * xc * zc + c * yc) / yb;
@@ -118,7 +124,7 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                                 }
                                 double w = base * f * sbp[jM] / sap[iM];
                                 if (mirror) w *= p->exchange * (((M0 + jM) & 1) ? -1.0 : 1.0);
-                                facs[t].push_back(w);
+                                facs[t].push_back(w * fold);
                             }
                     }
                 }

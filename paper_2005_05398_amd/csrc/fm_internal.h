@@ -28,8 +28,14 @@ struct Basis1D {
     std::vector<int> idx;        // n * MAXR global function index per local slot (-1: none)
     std::vector<double> val[3];  // n * MAXR values of the 0th, 1st, 2nd derivative
 
+    int half = 0;                // z on [0, 1] with a parity at z = 0: +1 even, -1 odd (0: not halved)
     // Returns "" on success or a message.
     std::string init(const fm_dim &d, bool is_z);
+    // The z basis on [0, 1] of a function of parity sigma about z = 0, on the
+    // nodes and points of the full z basis d (an even number of intervals)
+    // that lie in [0, 1]: at the node z = 0 the functions of odd derivative
+    // order (sigma = +1) or of even order (sigma = -1) are dropped.
+    std::string init_half(const fm_dim &d, int sigma);
     int global_index(int m, int d) const;
     int interval(double t) const;
     // Values of the 2q local functions (slot e*q + d) at t; gidx may be null.

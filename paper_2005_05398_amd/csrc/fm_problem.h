@@ -59,6 +59,7 @@ struct fm_problem {
     int exchange = 0;                        // +-1: component 2 (index 1) is implied by component 1 (index 0);
                                              // 3: components 2 and 3 are implied by component 1
     bool absent(int a) const { return exchange != 0 && (a == 1 || (exchange == 3 && a == 2)); }
+    int zhalf = 0, zsigma = 1;               // component 3 on z in [0, 1] with parity zsigma
     long long N = 0;
     long long npts[3] = {0, 0, 0};
     long long off[3] = {0, 0, 0};

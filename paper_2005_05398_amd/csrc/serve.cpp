@@ -53,6 +53,7 @@ std::string desc_key(const fm_problem_desc &d) {
     const int pv = d.precond == FM_PREC_COUPLED ? 2 : 1;
     put(&pv, sizeof pv);
     put(&d.exchange, sizeof d.exchange);
+    put(&d.zhalf, sizeof d.zhalf);
     return k;
 }
 
@@ -60,8 +61,14 @@ long long unknowns_of(const fm_problem_desc &d) {
     int M0 = (1 - d.tau) / 2;
     long long nM = d.J - M0 + 1, s = 0;
     for (int a = 0; a < 3; ++a)
-        if (!(d.exchange != 0 && (a == 1 || (d.exchange == 3 && a == 2))))
-            s += (long long)d.x[a].n * d.y[a].n * d.z[a].n;
+        if (!(d.exchange != 0 && (a == 1 || (d.exchange == 3 && a == 2)))) {
+            long long nz = d.z[a].n;
+            if (a == 2 && d.zhalf) {     // component 3 on z in [0, 1] (fm_problem_desc.zhalf)
+                const int sigma = d.exchange * ((M0 & 1) ? -1 : 1);
+                nz = d.z[a].degree == 3 ? d.z[a].n / 2 : 3 * (d.z[a].n / 3 - 1) / 2 + (sigma == 1 ? 2 : 1);
+            }
+            s += (long long)d.x[a].n * d.y[a].n * nz;
+        }
     return nM * s;
 }
 

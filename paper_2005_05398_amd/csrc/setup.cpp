@@ -90,10 +90,19 @@ std::string setup_problem(fm_problem *p) {
                 return "three identical particles need identical bases for all components";
         }
     }
+    if (d.zhalf != 0 && d.zhalf != 1) return "zhalf must be 0 or 1";
+    p->zhalf = d.zhalf;
+    p->zsigma = 1;
+    if (d.zhalf) {
+        if (d.exchange != 1 && d.exchange != -1) return "zhalf needs the exchange symmetry of two particles (+1 or -1)";
+        if (p->nM != 1) return "zhalf needs one M' block (its parity (-1)^{M'} p fixes one z basis)";
+        if (d.precond == FM_PREC_COUPLED) return "zhalf is for the block-Jacobi preconditioner (n_M = 1)";
+        p->zsigma = d.exchange * ((p->M0 & 1) ? -1 : 1);
+    }
     for (int a = 0; a < 3; ++a) {
         std::string e = p->bx[a].init(d.x[a], false);
         if (e.empty()) e = p->by[a].init(d.y[a], false);
-        if (e.empty()) e = p->bz[a].init(d.z[a], true);
+        if (e.empty()) e = (a == 2 && p->zhalf) ? p->bz[a].init_half(d.z[a], p->zsigma) : p->bz[a].init(d.z[a], true);
         if (!e.empty()) return "component " + std::to_string(a) + ": " + e;
     }
     // kinematics

@@ -31,7 +31,7 @@ class FmDesc(ctypes.Structure):
                 ("tau", ctypes.c_int), ("x", FmDim * 3), ("y", FmDim * 3), ("z", FmDim * 3),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("nu", ctypes.c_double),
                 ("vhat", ctypes.c_int), ("device", ctypes.c_int), ("precond", ctypes.c_int),
-                ("exchange", ctypes.c_int)]
+                ("exchange", ctypes.c_int), ("zhalf", ctypes.c_int)]
 
 
 class FmSolveOpts(ctypes.Structure):
@@ -126,6 +126,7 @@ def make_c_desc(desc, device=0):
     d.device = device
     d.precond = PRECONDS[desc.get("precond", "block_jacobi")]
     d.exchange = int(desc.get("exchange", 0))
+    d.zhalf = int(desc.get("zhalf", 0))
     return d
 
 

@@ -165,7 +165,18 @@ def n_unknowns(desc):
     n_m = desc["J"] - m0 + 1
     ex = desc.get("exchange", 0)
     comps = (0,) if ex == 3 else (0, 2) if ex else (0, 1, 2)
-    return n_m * sum(desc["z"][a]["n"] * desc["x"][a]["n"] * desc["y"][a]["n"] for a in comps)
+
+    def nz(a):
+        z = desc["z"][a]
+        if not (a == 2 and desc.get("zhalf", 0)):
+            return z["n"]
+        # component 3 on z in [0, 1]: parity sigma = p (-1)^{M0} at z = 0
+        if z["degree"] == 3:
+            return z["n"] // 2
+        K = z["n"] // 3 - 1
+        sigma = ex * (-1) ** m0
+        return 3 * K // 2 + (2 if sigma == 1 else 1)
+    return n_m * sum(nz(a) * desc["x"][a]["n"] * desc["y"][a]["n"] for a in comps)
 
 
 def rhs(seed, n):

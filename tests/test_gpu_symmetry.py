@@ -181,3 +181,86 @@ def test_three_identical_solve_is_the_full_solution(device, name, desc):
     xfull = lu_solve(O.assemble(E), np.concatenate([b, b, b]))
     for a in range(3):
         assert np.linalg.norm(xfull[a * n:(a + 1) * n] - xg) <= 1e-8 * np.linalg.norm(xg), a
+
+
+# -- component 3 on z in [0, 1] (zhalf) ---------------------------------------
+
+HALF_CASES = [
+    ("hminus_quintic_p+1", W.make_desc(*W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"), 1),
+    ("hminus_quintic_p-1", W.make_desc(*W.H_MINUS, 10, 15, R=30.0, xy_map="quadratic"), -1),
+    ("hminus_cubicz_p+1", W.make_desc(*W.H_MINUS, 7, 10, deg_z=3, R=15.0), 1),
+    ("hminus_L1_odd_p+1", W.make_desc(*W.H_MINUS, 7, 9, J=1, tau=-1, deg_z=5, R=15.0), 1),
+]
+
+
+def _half(desc, p):
+    from oracle.basis import half_z_basis
+    from oracle.symmetry import half_parity
+    O = OracleProblem(desc)
+    return O, half_z_basis(desc["z"][2], half_parity(O, p))
+
+
+@pytest.mark.parametrize("name,desc,p", HALF_CASES, ids=[c[0] for c in HALF_CASES])
+def test_halved_operator_parity(device, name, desc, p):
+    from oracle.symmetry import reduced_operator_half
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=p, zhalf=1))
+    O, bh = _half(desc, p)
+    A = reduced_operator_half(O, -0.35, p, bh)
+    assert P.N == A.shape[0]
+    X = np.random.default_rng(17).standard_normal((2, P.N))
+    Y = to_dev(np.zeros((2, P.N)), device)
+    P.apply_operator([-0.35, -0.35], to_dev(X, device), Y)
+    Yg = Y.cpu().numpy()
+    for r in range(2):
+        ref = A @ X[r]
+        assert np.abs(Yg[r] - ref).max() <= 1e-11 * np.abs(ref).max(), (name, r)
+
+
+@pytest.mark.parametrize("name,desc,p", HALF_CASES, ids=[c[0] for c in HALF_CASES])
+def test_halved_precond_parity(device, name, desc, p):
+    import scipy.sparse.linalg as spla
+    from oracle.symmetry import separable_half
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=p, zhalf=1))
+    O, bh = _half(desc, p)
+    r = np.random.default_rng(18).standard_normal(P.N)
+    z = to_dev(np.zeros((1, P.N)), device)
+    P.apply_precond([-0.35], to_dev(r[None, :], device), z)
+    ref = spla.spsolve(separable_half(O, -0.35, bh).tocsc(), r)
+    assert np.abs(z.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,desc,p", [HALF_CASES[0], HALF_CASES[2]], ids=[HALF_CASES[0][0], HALF_CASES[2][0]])
+def test_halved_solve_matches_lu(device, name, desc, p):
+    from oracle.symmetry import reduced_operator_half
+    fm = _fm()
+    P = fm.Problem(dict(desc, exchange=p, zhalf=1))
+    O, bh = _half(desc, p)
+    E = -0.3
+    A = reduced_operator_half(O, E, p, bh)
+    b = W.rhs(13, A.shape[0])
+    x = to_dev(np.zeros((1, A.shape[0])), device)
+    st, res = P.solve([E], to_dev(b[None, :], device), x, restart=150, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    xg = x.cpu().numpy()[0]
+    assert rel_residual(A, xg, b) <= 1e-10
+    xref = lu_solve(A, b)
+    assert np.linalg.norm(xg - xref) / np.linalg.norm(xref) <= 1e-8
+
+
+def test_halved_helium_energies_equal_the_reduced_ones(device):
+    """Helium, J = 0: the lowest singlet (p = +1) and triplet (p = -1) levels
+    with component 3 on z in [0, 1] equal those of the reduced system on the
+    full z grid (the same space of solutions), to 1e-9."""
+    fm = _fm()
+    desc = W.make_desc(*HE, 13, 9, R=15.0, x0=1.0, xy_map="quadratic")
+    for p, sigma in ((1, -2.9), (-1, -2.17)):
+        out = []
+        for half in (0, 1):
+            P = fm.Problem(dict(desc, exchange=p, zhalf=half))
+            st, E, res, info = P.eigs(sigma, nev=1, ncv=16, tol=1e-12, max_restarts=40, restart=100, rtol=1e-12,
+                                      max_iters=4000)
+            assert st == fm.FM_OK, (p, half, info)
+            out.append(E[0].real)
+        assert abs(out[0] - out[1]) <= 1e-9 * abs(out[0]), (p, out)

@@ -233,3 +233,73 @@ def test_host_coupling_three_identical(name, desc):
 def test_three_identical_rejects_distinct_particles():
     with pytest.raises(fm.FmError):
         fm.host_setup_check(dict(W.make_desc(*W.H_MINUS, 7, 4, deg_z=3), exchange=3))
+
+
+HALF_CASES = [
+    ("hminus_quintic_p+1", W.make_desc(*W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"), 1),
+    ("hminus_quintic_p-1", W.make_desc(*W.H_MINUS, 10, 15, R=30.0, xy_map="quadratic"), -1),
+    ("hminus_cubicz_p+1", W.make_desc(*W.H_MINUS, 7, 10, deg_z=3, R=15.0), 1),
+    ("hminus_L1_odd_p+1", W.make_desc(*W.H_MINUS, 7, 9, J=1, tau=-1, deg_z=5, R=15.0), 1),
+]
+
+
+def _half_setup(desc, p):
+    from oracle.assemble import Problem as OracleProblem
+    from oracle.basis import half_z_basis
+    from oracle.symmetry import half_parity
+    O = OracleProblem(desc)
+    return O, half_z_basis(desc["z"][2], half_parity(O, p))
+
+
+@lib_built
+@pytest.mark.parametrize("name,desc,p", HALF_CASES, ids=[c[0] for c in HALF_CASES])
+def test_host_coupling_halved_component(name, desc, p):
+    """Component 3 on z in [0, 1] (zhalf): the device's pairs, reading it at
+    |z_3| times its parity, equal R_h C E_h x of the oracle."""
+    from oracle.symmetry import expansion_half, kept_rows_half
+    O, bh = _half_setup(desc, p)
+    rdesc = dict(desc, exchange=p, zhalf=1)
+    N = fm.host_setup_check(rdesc)[2]
+    assert N == W.n_unknowns(rdesc) == O.block[0] + bh.n * O.bx[2].n * O.by[2].n
+    x = W.rhs(80, N)
+    y, npairs, ntasks = fm.host_coupling(rdesc, x)
+    ref = _oracle_coupling(desc, expansion_half(O, p, bh) @ x)[kept_rows_half(O, bh)]
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref), name
+
+
+# cubic x, y (the host apply takes real pencil spectra only)
+HALF_PREC_CASES = [
+    ("hminus_quintic_z_p+1", W.make_desc(*W.H_MINUS, 8, 9, deg_xy=3, deg_z=5, R=30.0), 1),
+    ("hminus_quintic_z_p-1", W.make_desc(*W.H_MINUS, 8, 15, deg_xy=3, deg_z=5, R=30.0), -1),
+    ("hminus_cubicz_p-1", W.make_desc(*W.H_MINUS, 8, 10, deg_xy=3, deg_z=3, R=15.0), -1),
+    ("hminus_L1_odd_p+1", W.make_desc(*W.H_MINUS, 6, 9, J=1, tau=-1, deg_xy=3, deg_z=5, R=15.0), 1),
+]
+
+
+@lib_built
+@pytest.mark.parametrize("name,desc,p", HALF_PREC_CASES, ids=[c[0] for c in HALF_PREC_CASES])
+def test_host_precond_halved_component(name, desc, p):
+    """The preconditioner's tables with component 3 on the half z basis equal
+    the inverse of the separable operator built on that basis."""
+    import scipy.sparse.linalg as spla
+    from oracle.symmetry import separable_half
+    O, bh = _half_setup(desc, p)
+    rdesc = dict(desc, exchange=p, zhalf=1)
+    N = W.n_unknowns(rdesc)
+    r = W.rhs(81, N)
+    E = -0.3
+    got = fm.host_precond(rdesc, E, r)
+    ref = spla.spsolve(separable_half(O, E, bh).tocsc(), r)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), name
+
+
+@lib_built
+def test_halved_z_rejects_unsupported_problems():
+    d = W.make_desc(*W.H_MINUS, 7, 12, deg_z=5, R=15.0)           # 3 intervals: z = 0 is no node
+    with pytest.raises(fm.FmError):
+        fm.host_setup_check(dict(d, exchange=1, zhalf=1))
+    d = W.make_desc(*W.H_MINUS, 7, 9, J=2, deg_z=5, R=15.0)       # three M' blocks
+    with pytest.raises(fm.FmError):
+        fm.host_setup_check(dict(d, exchange=1, zhalf=1))
+    with pytest.raises(fm.FmError):
+        fm.host_setup_check(dict(W.make_desc(*W.H_MINUS, 7, 9, R=15.0), zhalf=1))   # no exchange symmetry

@@ -102,3 +102,58 @@ def test_three_identical_reduced_size_of_the_helium_trimer_basis():
     gives the printed 1 342 683 unknowns."""
     assert 1 * 223 * 223 * 27 == 1342683
     assert W.n_unknowns(dict(W.make_desc(*THREE, 223, 27, deg_z=5), exchange=3)) == 1342683
+
+
+# -- component 3 on z in [0, 1] ------------------------------------------------
+
+@pytest.mark.parametrize("deg,n", [(3, 6), (3, 10), (5, 9), (5, 15)])
+@pytest.mark.parametrize("parity", [1, -1])
+def test_half_z_basis_reproduces_polynomials_of_its_parity(deg, n, parity):
+    from oracle.basis import half_z_basis
+    b = half_z_basis({"degree": deg, "n": n, "map": "sin"}, parity)
+    P = np.polynomial.Polynomial
+    powers = [k for k in range(2 * b.q) if (k % 2 == 0) == (parity == 1)]
+    rng = np.random.default_rng(deg * 10 + n)
+    f = P(np.array([rng.standard_normal() if k in powers else 0.0 for k in range(2 * b.q)]))
+    c = np.linalg.solve(b.matrix(0), f(b.points))
+    t = np.linspace(0.0, 1.0, 23)
+    for d in range(3):
+        np.testing.assert_allclose(b.matrix(d, t=t) @ c, f.deriv(d)(t) if d else f(t), atol=1e-9)
+
+
+@pytest.mark.parametrize("p,deg_z,nz", [(1, 5, 9), (-1, 5, 9), (1, 3, 6), (-1, 3, 10)])
+def test_halved_system_solution_is_the_reduced_solution(p, deg_z, nz):
+    """With a right-hand side of component 3 of parity sigma the reduced
+    system's component 3 has that parity; the halved system (component 3 on
+    [0, 1]) has the same solution: its component 1 and the parity extension of
+    its component 3."""
+    from oracle.basis import half_z_basis
+    from oracle.symmetry import (expansion_half, half_parity, kept_rows, kept_rows_half,
+                                 reduced_operator, reduced_operator_half, z_extension)
+    desc = W.make_desc(*W.H_MINUS, 7, nz, deg_z=deg_z, R=15.0)
+    prob = Problem(desc)
+    sigma = half_parity(prob, p)
+    bh = half_z_basis(desc["z"][2], sigma)
+    E = -0.35
+    rng = np.random.default_rng(7)
+    n1, n3 = prob.block[0], prob.block[2]
+    nxy = prob.bx[2].n * prob.by[2].n
+    b1 = rng.standard_normal(n1)
+    # component 3's rows with parity sigma: b(-z) = sigma b(z) on the symmetric points
+    pts = prob.bz[2].points
+    b3 = rng.standard_normal((len(pts), nxy))
+    for k in range(len(pts)):
+        kk = int(np.argmin(np.abs(pts + pts[k])))
+        if kk > k:
+            b3[kk] = sigma * b3[k]
+        elif kk == k:
+            b3[k] = 0.0 if sigma == -1 else b3[k]
+    c_red = lu_solve(reduced_operator(prob, E, p), np.concatenate([b1, b3.ravel()]))
+    zi = [int(np.argmin(np.abs(pts - t))) for t in bh.points]
+    b_half = np.concatenate([b1, b3[zi].ravel()])
+    c_half = lu_solve(reduced_operator_half(prob, E, p, bh), b_half)
+    assert np.linalg.norm(c_half[:n1] - c_red[:n1]) <= 1e-9 * np.linalg.norm(c_red)
+    X = z_extension(prob.bz[2], bh, sigma)
+    c3 = (X @ c_half[n1:].reshape(bh.n, nxy)).ravel()
+    assert np.linalg.norm(c3 - c_red[n1:]) <= 1e-9 * np.linalg.norm(c_red)
+    assert W.n_unknowns(dict(desc, exchange=p, zhalf=1)) == n1 + bh.n * nxy
