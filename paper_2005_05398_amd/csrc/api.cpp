@@ -811,6 +811,25 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         if (!err.empty()) return err;
     }
     p->pr.coupled = p->variant == 2 ? 1 : 0;
+    {
+        // the slices with complex pencil pairs, in the kernels' slice numbering
+        std::vector<int> ps;
+        int base = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (p->absent(a)) continue;
+            const HostComp &h = hf.comp[a];
+            const int nx = p->bx[a].n, ny = p->by[a].n, ns = p->nM * p->bz[a].n;
+            for (int sl = 0; sl < ns; ++sl) {
+                bool any = false;
+                for (int i = 0; i < nx && !any; ++i) any = h.tx[size_t(sl) * nx + i] != 0;
+                for (int j = 0; j < ny && !any; ++j) any = h.ty[size_t(sl) * ny + j] != 0;
+                if (any) ps.push_back(base + sl);
+            }
+            base += ns;
+        }
+        p->pr.npair_slices = int(ps.size());
+        p->pr.pair_slices = put(p, ps, err);
+    }
     pd.gtile = put(p, gtile, err);
     if (!err.empty()) return err;
     pd.tile_lds = std::max(pd.plane_lds, pd.group_lds);

@@ -176,6 +176,8 @@ struct PrecCompDev {
 struct PrecDev {
     PrecCompDev comp[3];
     int coupled;                 // 1: coupled variant (joint z matrices), 0: block-Jacobi in M'
+    const int *pair_slices;      // slices (numbered over the components) whose x or y pencil has
+    int npair_slices;            // complex eigenpairs; the staged divide leaves their blocks to k_divide_pairs
     const PrecDev *dev;          // device copy of this descriptor
 };
 

@@ -1133,13 +1133,18 @@ __device__ __forceinline__ double divided_at(const TT *__restrict__ T, int ld, i
 // JZ (LEFT only, coupled preconditioner): the "slice" is a whole component,
 // the n_M n_z x n_x n_y matrix of its [M'][z] rows, and W its joint z matrix
 // (grid.y = 3); in and out must not overlap.
-template <bool LEFT, bool DIV, bool JZ = false, int BT = SG_T>
+// DIVOUT (right products only): each output element whose x and y
+// eigenvalues are both real is divided by lambda_x + lambda_y - E as it is
+// stored (the elements of complex pairs are stored undivided for
+// k_divide_pairs), so the next left product needs no divide.
+template <bool LEFT, bool DIV, bool JZ = false, int BT = SG_T, bool DIVOUT = false>
 __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
                                                     const double *__restrict__ Evec,
                                                     const int *__restrict__ active, int which,
                                                     const double *__restrict__ in, double *__restrict__ out,
                                                     double *min_den) {
     static_assert(!JZ || (LEFT && !DIV), "joint z products are plain left products");
+    static_assert(!DIVOUT || (!LEFT && !DIV && !JZ), "the divide on store follows a right product");
     static_assert(BT == 32 || BT == 64, "block tile 32 x 32 (one 16 x 16 MFMA tile per wave) or 64 x 64 (2 x 2)");
     constexpr int WT = BT / 32;               // MFMA tiles per wave in each direction
     const int req = blockIdx.z;
@@ -1171,9 +1176,13 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     double *o = out + off;
     const int K = LEFT ? nx : ny;
     const double E = DIV ? Evec[req] : 0.0;
+    const double E2 = DIVOUT ? Evec[req] : 0.0;
     double mind = 1e300;
-    __shared__ double As[BT][SG_KC + 1];   // [row][k]
-    __shared__ double Bs[SG_KC][BT + 1];   // [k][col]
+    // the operand tiles, one buffer: DIVOUT reuses it for the output tile
+    __shared__ double sg_buf[BT * (SG_KC + 1) + SG_KC * (BT + 1)];
+    static_assert(BT * (SG_KC + 1) + SG_KC * (BT + 1) >= BT * (BT + 1), "output tile fits the operand tiles");
+    double (*As)[SG_KC + 1] = reinterpret_cast<double (*)[SG_KC + 1]>(sg_buf);              // [row][k]
+    double (*Bs)[BT + 1] = reinterpret_cast<double (*)[BT + 1]>(sg_buf + BT * (SG_KC + 1));   // [k][col]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
     constexpr int PER = BT * SG_KC / 256;   // A and B values per thread per chunk
@@ -1279,6 +1288,27 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
         if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = rbe;
     };
+    // DIVOUT: the eigenvalues and types of this lane's output rows and columns,
+    // requested now so that they arrive during the products (a type of 1 marks
+    // a row or column outside the slice, which is not divided)
+    // (rows through LDS, written here and read after the products: the first
+    // barrier of the chunk loop orders them)
+    __shared__ double dv_sl[DIVOUT ? BT : 1];
+    __shared__ int dv_st[DIVOUT ? BT : 1];
+    double dv_c = 0.0;                     // the thread's output column in the epilogue: threadIdx.x % BT
+    int dv_ct = 1;
+    if (DIVOUT) {
+        if (threadIdx.x < BT) {
+            const int row = i0 + (int)threadIdx.x;
+            dv_sl[threadIdx.x] = row < nx ? F.lx[fx * nx + row] : 0.0;
+            dv_st[threadIdx.x] = row < nx ? F.tx[fx * nx + row] : 1;
+        }
+        const int col = j0 + (int)threadIdx.x % BT;
+        if (col < ny) {
+            dv_c = F.ly[fx * ny + col];
+            dv_ct = F.ty[fx * ny + col];
+        }
+    }
     // wave (wi, wj) owns the (16 WT) x (16 WT) block at rows 16 WT wi, columns 16 WT wj
     dbl4 acc[WT][WT];
 #pragma unroll
@@ -1317,22 +1347,64 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         if (k0 + SG_KC < K) divide(k0 + SG_KC);
         __syncthreads();
     }
+    // DIVOUT: the divisor of an element (i, j), real eigenvalue pairs only
+    // (the lane's rows and columns were read before the products)
+    auto divout = [&](int row, int col, double v) {
+        if (!DIVOUT) return v;
+        const int ti = F.tx[fx * nx + row], tj = F.ty[fx * ny + col];
+        if (ti != 0 || tj != 0) return v;                  // complex pairs: k_divide_pairs
+        const double d = F.lx[fx * nx + row] + F.ly[fx * ny + col] - E2;
+        mind = fmin(mind, fabs(d));
+        return v * rcp_newton(d);
+    };
+    if (DIVOUT) {
+        // the tile through LDS (the operand tiles are free after the last
+        // barrier): the accumulators die at once, and each thread then divides
+        // and stores whole rows' worth of one column, coalesced
+        // (rows padded to BT + 1: the four rows a wave writes at once fall in
+        // different banks)
+        double *ot = sg_buf;
 #pragma unroll
-    for (int ti = 0; ti < WT; ++ti)
+        for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj)
+            for (int tj = 0; tj < WT; ++tj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = i0 + 16 * (WT * wi + ti) + k4 + 4 * v, col = j0 + 16 * (WT * wj + tj) + r16;
-                if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[ti][tj][v];
+                for (int v = 0; v < 4; ++v)
+                    ot[(16 * (WT * wi + ti) + k4 + 4 * v) * (BT + 1) + 16 * (WT * wj + tj) + r16] = acc[ti][tj][v];
+        __syncthreads();
+        const int c = (int)threadIdx.x % BT, col = j0 + c;
+#pragma unroll 2
+        for (int r = (int)threadIdx.x / BT; r < BT; r += 256 / BT) {
+            const int row = i0 + r;
+            if (row < nx && col < ny) {
+                double val = ot[r * (BT + 1) + c];
+                if ((dv_st[r] | dv_ct) == 0) {
+                    const double d = dv_sl[r] + dv_c - E2;
+                    mind = fmin(mind, fabs(d));
+                    val *= rcp_newton(d);
+                }
+                o[(size_t)row * ny + col] = val;
             }
+        }
+    } else {
+#pragma unroll
+        for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < WT; ++tj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = i0 + 16 * (WT * wi + ti) + k4 + 4 * v, col = j0 + 16 * (WT * wj + tj) + r16;
+                    if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[ti][tj][v];
+                }
+    }
     if (erow || ecol) {
         const int tx = threadIdx.x;
-        if (erow && tx < BT && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = ext;
-        else if (ecol && tx >= BT && tx < 2 * BT && i0 + tx - BT < nx) o[(size_t)(i0 + tx - BT) * ny + ny - 1] = ext;
-        else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = ext;
+        if (erow && tx < BT && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = divout(nx - 1, j0 + tx, ext);
+        else if (ecol && tx >= BT && tx < 2 * BT && i0 + tx - BT < nx)
+            o[(size_t)(i0 + tx - BT) * ny + ny - 1] = divout(i0 + tx - BT, ny - 1, ext);
+        else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = divout(nx - 1, ny - 1, ext);
     }
-    if (DIV && min_den) {
+    if ((DIV || DIVOUT) && min_den) {
         // block minimum, then one atomic per block on the bit pattern (positive doubles)
         __shared__ double red[256];
         red[threadIdx.x] = mind;
@@ -1348,6 +1420,96 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     }
 }
 
+
+// The divide of the elements in complex-conjugate eigenpair blocks, in place,
+// after a right product stored with DIVOUT (which divided every element of
+// two real eigenvalues): the 2 x 2 blocks of an x pair (rows i, i + 1) or a
+// y pair (columns j, j + 1) and the 4 x 4 blocks of both, by the closed forms
+// of block_divide.  One block per (slice with complex pairs, request).
+constexpr int DP_MAXP = 512;
+
+__global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
+                                                      const double *__restrict__ Evec, const int *__restrict__ active,
+                                                      double *data, double *min_den) {
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    int a, iM, k;
+    if (!slice_decode(pd, pr->pair_slices[blockIdx.x], a, iM, k)) return;
+    const CompDev &C = pd->comp[a];
+    const PrecCompDev &F = pr->comp[a];
+    const int nx = C.x.n, ny = C.y.n, nz = C.z.n;
+    const size_t fx = (size_t)iM * nz + k;
+    const double *lx = F.lx + fx * nx, *lxi = F.lxi + fx * nx, *ly = F.ly + fx * ny, *lyi = F.lyi + fx * ny;
+    const signed char *tx = F.tx + fx * nx, *ty = F.ty + fx * ny;
+    __shared__ int xs[DP_MAXP], ys[DP_MAXP];
+    __shared__ int nxp, nyp;
+    if (threadIdx.x == 0) nxp = nyp = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nx; i += 256)
+        if (tx[i] == 1) {
+            const int s = atomicAdd(&nxp, 1);
+            if (s < DP_MAXP) xs[s] = i;
+        }
+    for (int j = threadIdx.x; j < ny; j += 256)
+        if (ty[j] == 1) {
+            const int s = atomicAdd(&nyp, 1);
+            if (s < DP_MAXP) ys[s] = j;
+        }
+    __syncthreads();
+    const int px = min(nxp, DP_MAXP), py = min(nyp, DP_MAXP);
+    if (px == 0 && py == 0) return;
+    double *T = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    const double E = Evec[req];
+    double mind = 1e300;
+    // x pairs: rows i, i + 1 against every column (4 x 4 where the column is in a pair too)
+    for (int t = threadIdx.x; t < px * ny; t += 256) {
+        const int i = xs[t / ny], j = t % ny;
+        const int tj = ty[j];
+        if (tj == 2) continue;
+        const double d = lx[i] + ly[j] - E;
+        const int o = i * ny + j;
+        if (tj == 0) {
+            const double b = lxi[i], r0 = T[o], r1 = T[o + ny], det = d * d + b * b;
+            T[o] = (d * r0 - b * r1) / det;
+            T[o + ny] = (b * r0 + d * r1) / det;
+            mind = fmin(mind, sqrt(det));
+        } else {
+            const double bx = lxi[i], by = lyi[j];
+            const double r00 = T[o], r01 = T[o + 1], r10 = T[o + ny], r11 = T[o + ny + 1];
+            const double p00 = 0.5 * (r00 + r11), p01 = 0.5 * (r01 - r10);
+            const double m00 = 0.5 * (r00 - r11), m01 = 0.5 * (r01 + r10);
+            const double bp = bx - by, bm = bx + by;
+            const double Dp = d * d + bp * bp, Dm = d * d + bm * bm;
+            T[o] = (d * p00 + bp * p01) / Dp + (d * m00 - bm * m01) / Dm;
+            T[o + 1] = (d * p01 - bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
+            T[o + ny] = (-d * p01 + bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
+            T[o + ny + 1] = (d * p00 + bp * p01) / Dp + (-d * m00 + bm * m01) / Dm;
+            mind = fmin(mind, sqrt(fmin(Dp, Dm)));
+        }
+    }
+    // y pairs: columns j, j + 1 in the rows of real x eigenvalues
+    for (int t = threadIdx.x; t < nx * py; t += 256) {
+        const int i = t / py, j = ys[t % py];
+        if (tx[i] != 0) continue;
+        const double d = lx[i] + ly[j] - E;
+        const int o = i * ny + j;
+        const double b = lyi[j], r0 = T[o], r1 = T[o + 1], det = d * d + b * b;
+        T[o] = (d * r0 - b * r1) / det;
+        T[o + 1] = (b * r0 + d * r1) / det;
+        mind = fmin(mind, sqrt(det));
+    }
+    if (min_den) {
+        __shared__ double red[256];
+        red[threadIdx.x] = mind;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && red[0] < min_den[req])
+            atomicMin((unsigned long long *)(min_den + req), (unsigned long long)__double_as_longlong(red[0]));
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Reduced-precision preconditioner products (the divide stays FP64).
@@ -2578,10 +2740,13 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         const dim3 g(slices, tl, nb);                                                                                  \
         hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, \
                            0, data, tmp, nullptr);                                                                     \
-        hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,        \
-                           active, 0, tmp, data, nullptr);                                                             \
-        hipLaunchKernelGGL((k_slice_gemm<true, true, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active,  \
-                           1, data, tmp, min_den);                                                                     \
+        hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT, true>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,  \
+                           active, 0, tmp, data, min_den);                                                             \
+        if (pr.npair_slices > 0)                                                                                       \
+            hipLaunchKernelGGL(k_divide_pairs, dim3(pr.npair_slices, nb), dim3(256), 0, st, pd.dev, pr.dev, E_dev,     \
+                               active, data, min_den);                                                                 \
+        hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, \
+                           1, data, tmp, nullptr);                                                                     \
         hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,        \
                            active, 1, tmp, data, nullptr);                                                             \
     }
