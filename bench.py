@@ -272,8 +272,9 @@ def serve_run(args, nreq, rates):
 
 def serve_bench(args):
     """Serving: the whole seeded stream; Poisson arrivals at a rate the server
-    sustains and at an overload rate, each reported on its own."""
-    out = serve_run(args, args.requests, (args.serve_rate, 0.8))
+    sustains, at 0.8 x and at 1.0 x the saturated rate, each reported on its
+    own."""
+    out = serve_run(args, args.requests, (args.serve_rate, 0.8, 1.0))
     sus = out["poisson"][f"{args.serve_rate:g}x_saturated"]
     line = {
         "metric": "serving: solves/s at rel. residual 1e-10 and p50/p99 latency (Poisson arrivals)",
@@ -553,7 +554,7 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--serve-sample", type=int, default=96,
                     help="requests of the serving sample in the default run (0: none)")
-    ap.add_argument("--serve-rate", type=float, default=0.4,
+    ap.add_argument("--serve-rate", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the saturated rate (the sustained phase)")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--serve-restart", type=int, default=200)

@@ -300,8 +300,11 @@ fm_status fm_eigs(fm_problem *p, double sigma, const fm_eigs_opts *opts, const d
  *
  * A server owns a device-memory budget and a set of lanes.  A lane is one
  * (problem description, precision, restart length) with its own HIP stream,
- * host thread and Krylov workspace of max_batch slots; lanes run
- * concurrently, so their kernels overlap on the device.  Problems (the
+ * host thread and Krylov workspace; its slots are the requests of that shape
+ * waiting when the lane is made (at least 2, at most max_batch, fewer when
+ * one slot is large).  Lanes run concurrently, so their kernels overlap on
+ * the device.  An idle lane keeps its workspace until a new lane needs the
+ * memory; then the longest idle lanes give it back, as many as needed.  Problems (the
  * energy-independent factors of fm_create_problem) are cached by description.
  * A submitted request is admitted when its lane has a free slot and the
  * budget covers the lane's workspace (and the problem, if it is new); it joins
@@ -322,7 +325,7 @@ typedef struct {
 } fm_request_result;
 
 /* hbm_budget_bytes: device bytes the server may hold (factors + workspaces).
- * max_batch: slots per lane (>= 1).  device: HIP device ordinal.
+ * max_batch: most slots per lane (>= 1).  device: HIP device ordinal.
  * Errors: FM_E_INVALID, FM_E_HIP, FM_E_NOMEM. */
 fm_status fm_server_create(size_t hbm_budget_bytes, int max_batch, int device, fm_server **out);
 

@@ -3,9 +3,12 @@
 // A dispatcher thread admits submitted requests by device-memory footprint and
 // routes each to a lane: one lane per (problem description, precision,
 // restart length), each with its own HIP stream, its own Krylov workspace
-// (a Batch of max_batch slots) and its own host thread, so the lanes' kernels
-// overlap on the device.  Problems (the energy-independent factors) are cached
-// by description.  A request joins its lane at the lane's next restart
+// (a Batch with one slot per request of that shape waiting when the lane is
+// made, at least 2 and at most max_batch) and its own host thread, so the
+// lanes' kernels overlap on the device.  An idle lane keeps its workspace
+// until a new lane needs the memory; then the longest idle lanes give it back,
+// as many as needed.  Problems (the energy-independent factors) are cached by
+// description.  A request joins its lane at the lane's next restart
 // boundary; a lane with waiting requests and free slots ends its cycle early
 // (after at least a minimum number of Arnoldi steps) so that they can join.
 // Finished requests leave their slot, their solution is copied to the caller's
@@ -97,6 +100,10 @@ struct Lane {
     hipStream_t st = nullptr;
     bool finished = false;             // thread has exited
     size_t bytes = 0;
+    // guarded by the server mutex: waiting for work since idle_since, and
+    // chosen to give its memory back
+    bool idle = false, evict = false;
+    double idle_since = 0;
 };
 
 }  // namespace fm
@@ -114,7 +121,6 @@ struct fm_server {
     std::map<std::string, int> setting_up;   // problem keys being built (value unused)
     int setups_running = 0;
     std::vector<std::thread> setup_threads;  // joined when the dispatcher ends
-    bool evict_idle = false;           // set when a new lane waits for memory
     std::vector<fm::Lane *> lanes;
     size_t in_use = 0;
     long long outstanding = 0;         // submitted and not yet finished
@@ -150,20 +156,22 @@ void lane_loop(fm_server *S, Lane *L) {
                         joiners.push_back({s, L->slot[s]});
                     }
                 bool busy = L->batch.any_running() || !joiners.empty();
-                if (busy) break;
-                if (S->stop) {
+                if (busy) {
+                    L->idle = false;
+                    break;
+                }
+                if (S->stop || L->evict) {
                     L->finished = true;
                     S->cv.notify_all();
                     return;
                 }
                 // idle: keep the workspace for the next request of this shape
-                // until a new lane needs the memory
-                S->cv.wait_for(lk, std::chrono::milliseconds(50));
-                if (S->evict_idle && L->joinq.empty() && !L->batch.any_running()) {
-                    L->finished = true;
-                    S->cv.notify_all();
-                    return;
+                // until the dispatcher picks this lane to make room for another
+                if (!L->idle) {
+                    L->idle = true;
+                    L->idle_since = now_s();
                 }
+                S->cv.wait_for(lk, std::chrono::milliseconds(50));
             }
         }
         std::vector<int> js;
@@ -319,6 +327,7 @@ void dispatch_loop(fm_server *S) {
             for (auto *L : S->lanes)
                 if (L->key == lkey && !L->finished) lane = L;
             if (lane) {
+                lane->evict = false;       // wanted again
                 lane->joinq.push_back(r);
                 it = S->pending.erase(it);
                 progressed = true;
@@ -366,7 +375,15 @@ void dispatch_loop(fm_server *S) {
             fm_problem tmp;
             tmp.N = N;
             const size_t per_slot = Batch::footprint(&tmp, 1, r->opts.restart) + 2 * size_t(N) * 8;
-            const int slots = int(std::max<size_t>(1, std::min<size_t>(S->max_batch, (S->budget / 4) / per_slot)));
+            // as many slots as requests of this shape are waiting (at least 2, so
+            // that a request arriving during a solve can join it), capped by
+            // max_batch and by memory
+            int want = 0;
+            for (auto *q : S->pending)
+                if (desc_key(q->desc) + std::to_string(q->opts.prec) + ":" + std::to_string(q->opts.restart) == lkey)
+                    ++want;
+            const int slots = int(std::max<size_t>(
+                1, std::min<size_t>({size_t(S->max_batch), size_t(std::max(2, want)), (S->budget / 4) / per_slot})));
             size_t need = Batch::footprint(&tmp, slots, r->opts.restart) + 2 * size_t(N) * 8 * slots;
             if (need > S->budget) {
                 r->status = FM_E_REJECTED;
@@ -375,7 +392,21 @@ void dispatch_loop(fm_server *S) {
                 continue;
             }
             if (S->in_use + need > S->budget) {
-                S->evict_idle = true;      // idle lanes give their memory back
+                // idle lanes give their memory back, the longest idle first,
+                // as many as this lane needs
+                size_t freeing = 0;
+                std::vector<Lane *> idle;
+                for (auto *L : S->lanes)
+                    if (!L->finished) {
+                        if (L->evict) freeing += L->bytes;
+                        else if (L->idle && L->joinq.empty()) idle.push_back(L);
+                    }
+                std::sort(idle.begin(), idle.end(), [](Lane *a, Lane *b) { return a->idle_since < b->idle_since; });
+                for (auto *L : idle) {
+                    if (S->in_use - std::min(S->in_use, freeing) + need <= S->budget) break;
+                    L->evict = true;
+                    freeing += L->bytes;
+                }
                 S->cv.notify_all();
                 ++it;
                 continue;
@@ -414,7 +445,6 @@ void dispatch_loop(fm_server *S) {
             it = S->pending.erase(it);
             S->lanes.push_back(L);
             L->th = std::thread(lane_loop, S, L);
-            S->evict_idle = false;
             progressed = true;
             break;                         // back to the attach pass
         }

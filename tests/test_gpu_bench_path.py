@@ -1,11 +1,12 @@
 """The benchmark's own path under the oracle, through the C ABI.
 
 * Operator batches wider than one coupling block: the coupling kernel takes
-  16 requests per block, so requests 16-31 and 32-34 run in the second and
-  third block row.  Every request of a 35-request batch is compared
-  elementwise with the oracle's assembled matrix (small grids), and sampled
-  rows of every request of a 34-request batch at the energy scan's full size
-  (the bench's kernel variants: quintic 64 x 64 x 24, two pairs per lane).
+  16 requests per block row, so requests 16-31 and 32-34 of a 35-request
+  batch run in its second and third row, and a 12-request batch leaves most
+  of one row empty.  Every request is compared elementwise with the oracle's
+  assembled matrix (small grids; all spline-order variants of the kernel).
+* Sampled rows of every request of a 34-request batch at the energy scan's
+  full size (the bench's kernel variants: quintic 64 x 64 x 24).
 * The 32-energy scan itself, solved as the bench solves it (one batch,
   restart 300, rtol 1e-10): the oracle's residual-only mode (rows of H and of
   A(1) assembled a chunk at a time, no factorisation) gives the true relative
@@ -39,16 +40,20 @@ def to_dev(a, device):
 BATCH_CASES = [
     ("quintic_7x7x6", W.make_desc(*W.PS_MINUS, 7, 6, R=15.0)),
     ("hminus_13x13x9_quadratic", W.make_desc(*W.H_MINUS, 13, 9, R=30.0, xy_map="quadratic")),
+    # the other spline orders of the one-block coupling kernel
+    ("quintic_xy_cubic_z_10x8", W.make_desc(*W.PS_MINUS, 10, 8, deg_z=3, R=15.0)),
+    ("cubic_xy_quintic_z_10x6", W.make_desc(*W.PS_MINUS, 10, 6, deg_xy=3, R=15.0)),
+    ("cubic_10x6", W.make_desc(*W.PS_MINUS, 10, 6, deg_xy=3, deg_z=3, R=15.0)),
     ("L2_quintic_cubicz", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0)),
 ]
 
 
+@pytest.mark.parametrize("nb", [35, 12])
 @pytest.mark.parametrize("name,desc", BATCH_CASES, ids=[c[0] for c in BATCH_CASES])
-def test_operator_parity_35_requests(device, name, desc):
+def test_operator_parity_many_requests(device, name, desc, nb):
     fm = _fm()
     P = fm.Problem(desc)
     O = OracleProblem(desc)
-    nb = 35
     rng = np.random.default_rng(21)
     Es = list(np.linspace(-0.6, 0.1, nb))
     X = rng.standard_normal((nb, O.N))
@@ -108,3 +113,28 @@ def test_hminus_scan_batch_oracle_residual(device):
     for k, i in enumerate(pick):
         assert rel[k] <= 1e-10, (i, rel[k], res[i])
         assert abs(rel[k] - res[i]["rel_residual"]) <= 1e-12, (i, rel[k], res[i])
+
+
+def test_batched_solve_masks_running_requests(device):
+    """Nine energies that converge at different steps: the operator kernels
+    skip the requests that have finished, and every solution meets the
+    oracle's LU."""
+    import torch
+    from oracle.solve import lu_solve, rel_residual
+    fm = _fm()
+    desc = W.make_desc(*W.H_MINUS, 13, 9, R=30.0, xy_map="quadratic")
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    Es = [-0.9, -0.8, -0.7, -0.62, -0.58, -0.48, -0.45, -0.4, -0.35]
+    B = W.rhs_batch([5100 + i for i in range(len(Es))], O.N)
+    X = torch.zeros(B.shape, dtype=torch.float64, device=device)
+    st, res = P.solve(Es, to_dev(B, device), X, restart=100, rtol=1e-10, max_iters=4000)
+    assert st == fm.FM_OK, res
+    its = [r["iters"] for r in res]
+    assert len(set(its)) > 2, its
+    Xg = X.cpu().numpy()
+    for i, E in enumerate(Es):
+        A = O.assemble(E)
+        assert rel_residual(A, Xg[i], B[i]) <= 1e-10, (i, res[i])
+        xref = lu_solve(A, B[i])
+        assert np.linalg.norm(Xg[i] - xref) / np.linalg.norm(xref) <= 1e-8, i
