@@ -69,9 +69,23 @@ def cpu_baseline(seconds_cap=30.0):
         if time.perf_counter() - t0 > seconds_cap:
             break
     dt = time.perf_counter() - t0
+    # the oracle at the scan's full size: its row assembly, timed on chunks of
+    # rows for about 10 s and extrapolated to one whole matrix (an LU of it,
+    # N = 294,912 with ~620 nonzeros per row, does not fit a host's memory)
+    Of = OracleProblem(c["desc"])
+    nrows, nnz = 0, 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < 10.0 and nrows < Of.N:
+        rows = np.arange(nrows, min(Of.N, nrows + 4096))
+        nnz += Of.rows(c["E"][0], rows).nnz
+        nrows += rows.size
+    rate = nrows / (time.perf_counter() - t1)
     return {"value": n_done / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle assembly + dense LU of the same H^- scan on a reduced quintic 22x22x9 grid "
-                      f"(N={O.N}), {n_done} of the 32 energies, {dt:.1f} s"}
+                      f"(N={O.N}), {n_done} of the 32 energies, {dt:.1f} s",
+            "full_size_assembly": {"N": Of.N, "rows_timed": nrows, "rows_per_s": rate,
+                                   "nonzeros_per_row": nnz / max(1, nrows),
+                                   "seconds_per_matrix_extrapolated": Of.N / rate}}
 
 
 def eigs_bench(args):
@@ -612,6 +626,10 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
+        # a second calibration of the read counter: a pure read of the same bytes
+        total = float(src.sum())
+        torch.cuda.synchronize()
+        assert total == float(src.numel())
         del src, dst
     head = measure(P, Es, B, X, args.restart, args.prec, args.steps, args.warmup, stream,
                    traffic_key=traffic_variant(args), graphs=bool(args.graphs))
