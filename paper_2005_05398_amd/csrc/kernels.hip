@@ -834,11 +834,12 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     const int col = blockIdx.x * cb + (threadIdx.x - sub * cb);
     const bool ok = col < nxy;
     const long long base = (long long)req * pd->N + C.off + (long long)iM * C.npts + col;
-    // the column as loaded (FP64), converted once all of it is in flight: a
-    // conversion per load would wait for each load in turn
-    double vd[MAXNZ];
+    // the column as loaded (FP64 input: converted once all of it is in
+    // flight, since a conversion per load would wait for each load in turn)
+    using TL = typename std::conditional<std::is_same<TI, float>::value, float, double>::type;
+    TL vd[MAXNZ];
 #pragma unroll
-    for (int k = 0; k < MAXNZ; ++k) vd[k] = (ok && k < nz) ? in[base + (long long)k * nxy] : 0.0;
+    for (int k = 0; k < MAXNZ; ++k) vd[k] = (ok && k < nz) ? in[base + (long long)k * nxy] : (TL)0;
     // the factor, staged after the column loads are issued; up to nz = 32 all
     // of its loads first, then the LDS writes, so that the block waits on one
     // round trip (a loop that stores each value as it arrives waits once per pass)
@@ -866,7 +867,7 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     } else {
         for (int t = threadIdx.x; t < wn; t += MZ2_THREADS) W[t] = t < nz * nz ? (F32 ? (T)Wg32[t] : (T)Wg64[t]) : (T)0;
     }
-    if (F32) {      // the column stays FP64 until all of the block's loads have issued
+    if (F32 && !std::is_same<TI, float>::value) {   // the column stays FP64 until all of the block's loads have issued
 #pragma unroll
         for (int k = 0; k < MAXNZ; ++k) asm volatile("" : "+v"(vd[k]));
     }
@@ -1428,9 +1429,10 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
 // of block_divide.  One block per (slice with complex pairs, request).
 constexpr int DP_MAXP = 512;
 
+template <class TD>
 __global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restrict__ pd, const PrecDev *__restrict__ pr,
                                                       const double *__restrict__ Evec, const int *__restrict__ active,
-                                                      double *data, double *min_den) {
+                                                      TD *data, double *min_den) {
     const int req = blockIdx.y;
     if (active && !active[req]) return;
     int a, iM, k;
@@ -1458,7 +1460,7 @@ __global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restri
     __syncthreads();
     const int px = min(nxp, DP_MAXP), py = min(nyp, DP_MAXP);
     if (px == 0 && py == 0) return;
-    double *T = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
+    TD *T = data + (long long)req * pd->N + C.off + (long long)iM * C.npts + (long long)k * C.nxy;
     const double E = Evec[req];
     double mind = 1e300;
     // x pairs: rows i, i + 1 against every column (4 x 4 where the column is in a pair too)
@@ -1470,8 +1472,8 @@ __global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restri
         const int o = i * ny + j;
         if (tj == 0) {
             const double b = lxi[i], r0 = T[o], r1 = T[o + ny], det = d * d + b * b;
-            T[o] = (d * r0 - b * r1) / det;
-            T[o + ny] = (b * r0 + d * r1) / det;
+            T[o] = (TD)((d * r0 - b * r1) / det);
+            T[o + ny] = (TD)((b * r0 + d * r1) / det);
             mind = fmin(mind, sqrt(det));
         } else {
             const double bx = lxi[i], by = lyi[j];
@@ -1480,10 +1482,10 @@ __global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restri
             const double m00 = 0.5 * (r00 - r11), m01 = 0.5 * (r01 + r10);
             const double bp = bx - by, bm = bx + by;
             const double Dp = d * d + bp * bp, Dm = d * d + bm * bm;
-            T[o] = (d * p00 + bp * p01) / Dp + (d * m00 - bm * m01) / Dm;
-            T[o + 1] = (d * p01 - bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
-            T[o + ny] = (-d * p01 + bp * p00) / Dp + (d * m01 + bm * m00) / Dm;
-            T[o + ny + 1] = (d * p00 + bp * p01) / Dp + (-d * m00 + bm * m01) / Dm;
+            T[o] = (TD)((d * p00 + bp * p01) / Dp + (d * m00 - bm * m01) / Dm);
+            T[o + 1] = (TD)((d * p01 - bp * p00) / Dp + (d * m01 + bm * m00) / Dm);
+            T[o + ny] = (TD)((-d * p01 + bp * p00) / Dp + (d * m01 + bm * m00) / Dm);
+            T[o + ny + 1] = (TD)((d * p00 + bp * p01) / Dp + (-d * m00 + bm * m01) / Dm);
             mind = fmin(mind, sqrt(fmin(Dp, Dm)));
         }
     }
@@ -1494,8 +1496,8 @@ __global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restri
         const double d = lx[i] + ly[j] - E;
         const int o = i * ny + j;
         const double b = lyi[j], r0 = T[o], r1 = T[o + 1], det = d * d + b * b;
-        T[o] = (d * r0 - b * r1) / det;
-        T[o + 1] = (b * r0 + d * r1) / det;
+        T[o] = (TD)((d * r0 - b * r1) / det);
+        T[o + 1] = (TD)((b * r0 + d * r1) / det);
         mind = fmin(mind, sqrt(det));
     }
     if (min_den) {
@@ -1675,17 +1677,19 @@ __device__ void block_divide_f32(float *T, int ld, int nx, int ny, const double 
 // products) on FP32 MFMA (MODE 1: v_mfma_f32_16x16x4f32) or BF16x3 MFMA
 // (MODE 2: operands split into bfloat16 hi + mid as they are read, three
 // products, FP32 sums).  TI / TO: element types of in and out (FP32 between
-// the products; FP64 at the ends of the coupled variant).  DIV (LEFT only):
-// the input divided in FP64 by lambda_x + lambda_y - E as it is fetched
-// (complex pairs by their closed forms), then rounded to FP32.
-template <bool LEFT, bool DIV, int MODE, int BT, class TI, class TO>
+// the products; FP64 at the ends of the coupled variant).  DIVOUT (right
+// products only): each output element whose x and y eigenvalues are both real
+// is divided in FP64 by lambda_x + lambda_y - E as it is stored, then rounded
+// to FP32 (the elements of complex pairs are stored undivided for
+// k_divide_pairs), so the next left product needs no divide.
+template <bool LEFT, int MODE, int BT, class TI, class TO, bool DIVOUT = false>
 __global__ void __launch_bounds__(256) k_slice_gemm_f32(const ProblemDev *__restrict__ pd,
                                                         const PrecDev *__restrict__ pr,
                                                         const double *__restrict__ Evec,
                                                         const int *__restrict__ active, int which,
                                                         const TI *__restrict__ in, TO *__restrict__ out) {
     static_assert(BT == 32 || BT == 64, "block tile 32 x 32 or 64 x 64");
-    static_assert(!DIV || LEFT, "the divide is applied by the left product");
+    static_assert(!DIVOUT || !LEFT, "the divide on store follows a right product");
     constexpr int WT = BT / 32;
     const int req = blockIdx.z;
     if (active && !active[req]) return;
@@ -1706,43 +1710,18 @@ __global__ void __launch_bounds__(256) k_slice_gemm_f32(const ProblemDev *__rest
     const TI *g = in + off;
     TO *o = out + off;
     const int K = LEFT ? nx : ny;
-    const double E = DIV ? Evec[req] : 0.0;
-    double mind = 1e300;
-    __shared__ float As[BT][SG_KC + 1];
-    __shared__ float Bs[SG_KC][BT + 1];
+    const double E = DIVOUT ? Evec[req] : 0.0;
+    // the operand tiles, one buffer: DIVOUT reuses it for the output tile
+    __shared__ float sg32[BT * (SG_KC + 1) + SG_KC * (BT + 1)];
+    static_assert(BT * (SG_KC + 1) + SG_KC * (BT + 1) >= BT * (BT + 1), "output tile fits the operand tiles");
+    float (*As)[SG_KC + 1] = reinterpret_cast<float (*)[SG_KC + 1]>(sg32);              // [row][k]
+    float (*Bs)[BT + 1] = reinterpret_cast<float (*)[BT + 1]>(sg32 + BT * (SG_KC + 1));   // [k][col]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r16 = lane & 15, k4 = lane >> 4, wi = wave >> 1, wj = wave & 1;
     constexpr int PER = BT * SG_KC / 256;
-    using RB = typename std::conditional<DIV, double, float>::type;
-    float ra[PER];
-    RB rb[PER];
+    float ra[PER], rb[PER];
     __shared__ float Ae[SG_KC], Be[SG_KC];
-    float rae = 0.f, ext = 0.f;
-    RB rbe = 0;
-    constexpr int DIV_ROWS = 256;
-    __shared__ double sLx[DIV ? DIV_ROWS : 1];
-    __shared__ signed char sTx[DIV ? DIV_ROWS : 1];
-    const bool staged = DIV && K <= DIV_ROWS;
-    double ly_c = 0.0;
-    int ty_c = 1;
-    if (DIV) {
-        typedef const __attribute__((address_space(1))) double gdouble;
-        typedef const __attribute__((address_space(1))) signed char gschar;
-        const int r = threadIdx.x;
-        const bool st = staged && r < K;
-        const double lxv = st ? ((gdouble *)F.lx)[fx * nx + r] : 0.0;
-        const signed char txv = st ? ((gschar *)F.tx)[fx * nx + r] : (signed char)0;
-        const int jc = j0 + (int)threadIdx.x % BT;
-        if (jc < ny) {
-            ly_c = ((gdouble *)F.ly)[fx * ny + jc];
-            ty_c = ((gschar *)F.ty)[fx * ny + jc];
-        }
-        if (st) {
-            sLx[r] = lxv;
-            sTx[r] = txv;
-        }
-        __syncthreads();
-    }
+    float rae = 0.f, ext = 0.f, rbe = 0.f;
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -1752,10 +1731,10 @@ __global__ void __launch_bounds__(256) k_slice_gemm_f32(const ProblemDev *__rest
             float av = 0.f;
             if (row < nx && kk < K) av = LEFT ? Wm[(size_t)row * nx + kk] : (float)g[(size_t)row * ny + kk];
             ra[q] = av;
-            RB bv = 0;
+            float bv = 0.f;
             if (LEFT) {
                 const int kb = e / BT, cb = e % BT;
-                if (k0 + kb < K && j0 + cb < ny) bv = (RB)g[(size_t)(k0 + kb) * ny + j0 + cb];
+                if (k0 + kb < K && j0 + cb < ny) bv = (float)g[(size_t)(k0 + kb) * ny + j0 + cb];
             } else {
                 const int cb = e / SG_KC, kb = e % SG_KC;
                 if (k0 + kb < K && j0 + cb < ny) bv = Wm[(size_t)(j0 + cb) * ny + k0 + kb];
@@ -1768,48 +1747,46 @@ __global__ void __launch_bounds__(256) k_slice_gemm_f32(const ProblemDev *__rest
         }
         if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) {
             const int kb = k0 + (int)threadIdx.x - 64;
-            rbe = kb < K ? (LEFT ? (RB)g[(size_t)kb * ny + ny - 1] : (RB)Wm[(size_t)(ny - 1) * ny + kb]) : (RB)0;
+            rbe = kb < K ? (LEFT ? (float)g[(size_t)kb * ny + ny - 1] : Wm[(size_t)(ny - 1) * ny + kb]) : 0.f;
         }
-    };
-    auto divide = [&](int k0) {
-        if (!DIV) return;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            const int kb = e / BT, cb = e % BT;
-            if (k0 + kb < K && j0 + cb < ny) {
-                if (staged && ty_c == 0 && sTx[k0 + kb] == 0) {
-                    const double d = sLx[k0 + kb] + ly_c - E;
-                    mind = fmin(mind, fabs(d));
-                    rb[q] = (double)rb[q] * rcp_newton(d);
-                } else {
-                    rb[q] = divided_at(g, ny, k0 + kb, j0 + cb, F.lx + fx * nx, F.lxi + fx * nx, F.tx + fx * nx,
-                                       F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
-                }
-            }
-        }
-        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC && k0 + (int)threadIdx.x - 64 < K)
-            rbe = divided_at(g, ny, k0 + (int)threadIdx.x - 64, ny - 1, F.lx + fx * nx, F.lxi + fx * nx,
-                             F.tx + fx * nx, F.ly + fx * ny, F.lyi + fx * ny, F.ty + fx * ny, E, mind);
     };
     auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = threadIdx.x + 256 * q;
             As[e / SG_KC][e % SG_KC] = ra[q];
-            if (LEFT) Bs[e / BT][e % BT] = (float)rb[q];
-            else Bs[e % SG_KC][e / SG_KC] = (float)rb[q];
+            if (LEFT) Bs[e / BT][e % BT] = rb[q];
+            else Bs[e % SG_KC][e / SG_KC] = rb[q];
         }
         if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
-        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = (float)rbe;
+        if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = rbe;
     };
+    // DIVOUT: the eigenvalues and types of the tile's rows (LDS, ordered by the
+    // chunk loop's first barrier) and of the thread's epilogue column
+    // (threadIdx.x % BT), requested before the products; a type of 1 marks a
+    // row or column outside the slice
+    __shared__ double dv_sl[DIVOUT ? BT : 1];
+    __shared__ int dv_st[DIVOUT ? BT : 1];
+    double dv_c = 0.0;
+    int dv_ct = 1;
+    if (DIVOUT) {
+        if (threadIdx.x < BT) {
+            const int row = i0 + (int)threadIdx.x;
+            dv_sl[threadIdx.x] = row < nx ? F.lx[fx * nx + row] : 0.0;
+            dv_st[threadIdx.x] = row < nx ? F.tx[fx * nx + row] : 1;
+        }
+        const int col = j0 + (int)threadIdx.x % BT;
+        if (col < ny) {
+            dv_c = F.ly[fx * ny + col];
+            dv_ct = F.ty[fx * ny + col];
+        }
+    }
     flt4 acc[WT][WT];
 #pragma unroll
     for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
         for (int tj = 0; tj < WT; ++tj) acc[ti][tj] = flt4{0.f, 0.f, 0.f, 0.f};
     fetch(0);
-    divide(0);
     for (int k0 = 0; k0 < K; k0 += SG_KC) {
         stash();
         __syncthreads();
@@ -1870,24 +1847,57 @@ __global__ void __launch_bounds__(256) k_slice_gemm_f32(const ProblemDev *__rest
             else if (erow && ecol && tx == 2 * BT)
                 for (int kk = 0; kk < kn; ++kk) ext = fmaf(Ae[kk], Be[kk], ext);
         }
-        if (k0 + SG_KC < K) divide(k0 + SG_KC);
         __syncthreads();
     }
-    (void)mind;
+    // DIVOUT: an element (i, j) with real x and y eigenvalues divided by
+    // lambda_x + lambda_y - E in FP64 as it is stored (complex pairs are
+    // stored undivided for k_divide_pairs)
+    auto divout = [&](int row, int col, float v) -> float {
+        if (!DIVOUT) return v;
+        const int ti = F.tx[fx * nx + row], tj = F.ty[fx * ny + col];
+        if (ti != 0 || tj != 0) return v;
+        return (float)((double)v * rcp_newton(F.lx[fx * nx + row] + F.ly[fx * ny + col] - E));
+    };
+    if (DIVOUT) {
+        // the tile through LDS (the operand tiles are free after the last
+        // barrier), then each thread divides and stores rows of one column
+        // (rows padded to BT + 1)
+        float *ot = sg32;
 #pragma unroll
-    for (int ti = 0; ti < WT; ++ti)
+        for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj)
+            for (int tj = 0; tj < WT; ++tj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = i0 + 16 * (WT * wi + ti) + 4 * k4 + v, col = j0 + 16 * (WT * wj + tj) + r16;
-                if (row < nx && col < ny) o[(size_t)row * ny + col] = (TO)acc[ti][tj][v];
+                for (int v = 0; v < 4; ++v)
+                    ot[(16 * (WT * wi + ti) + 4 * k4 + v) * (BT + 1) + 16 * (WT * wj + tj) + r16] = acc[ti][tj][v];
+        __syncthreads();
+        const int c = (int)threadIdx.x % BT, col = j0 + c;
+#pragma unroll 2
+        for (int r = (int)threadIdx.x / BT; r < BT; r += 256 / BT) {
+            const int row = i0 + r;
+            if (row < nx && col < ny) {
+                float val = ot[r * (BT + 1) + c];
+                if ((dv_st[r] | dv_ct) == 0) val = (float)((double)val * rcp_newton(dv_sl[r] + dv_c - E));
+                o[(size_t)row * ny + col] = (TO)val;
             }
+        }
+    } else {
+#pragma unroll
+        for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < WT; ++tj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = i0 + 16 * (WT * wi + ti) + 4 * k4 + v, col = j0 + 16 * (WT * wj + tj) + r16;
+                    if (row < nx && col < ny) o[(size_t)row * ny + col] = (TO)acc[ti][tj][v];
+                }
+    }
     if (erow || ecol) {
         const int tx = threadIdx.x;
-        if (erow && tx < BT && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = (TO)ext;
-        else if (ecol && tx >= BT && tx < 2 * BT && i0 + tx - BT < nx) o[(size_t)(i0 + tx - BT) * ny + ny - 1] = (TO)ext;
-        else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = (TO)ext;
+        if (erow && tx < BT && j0 + tx < ny) o[(size_t)(nx - 1) * ny + j0 + tx] = (TO)divout(nx - 1, j0 + tx, ext);
+        else if (ecol && tx >= BT && tx < 2 * BT && i0 + tx - BT < nx)
+            o[(size_t)(i0 + tx - BT) * ny + ny - 1] = (TO)divout(i0 + tx - BT, ny - 1, ext);
+        else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = (TO)divout(nx - 1, ny - 1, ext);
     }
 }
 
@@ -2743,7 +2753,7 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         hipLaunchKernelGGL((k_slice_gemm<false, false, false, BT, true>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev,  \
                            active, 0, tmp, data, min_den);                                                             \
         if (pr.npair_slices > 0)                                                                                       \
-            hipLaunchKernelGGL(k_divide_pairs, dim3(pr.npair_slices, nb), dim3(256), 0, st, pd.dev, pr.dev, E_dev,     \
+            hipLaunchKernelGGL(k_divide_pairs<double>, dim3(pr.npair_slices, nb), dim3(256), 0, st, pd.dev, pr.dev, E_dev,     \
                                active, data, min_den);                                                                 \
         hipLaunchKernelGGL((k_slice_gemm<true, false, false, BT>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, \
                            1, data, tmp, nullptr);                                                                     \
@@ -2864,13 +2874,18 @@ void xy_f32_chain(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
         tl = std::max(tl, sg_tiles(pd.comp[a].x.n, BT) * sg_tiles(pd.comp[a].y.n, BT));
     }
     const dim3 g(slices, tl, nb);
-    hipLaunchKernelGGL((k_slice_gemm_f32<true, false, MODE, BT, TI, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
+    hipLaunchKernelGGL((k_slice_gemm_f32<true, MODE, BT, TI, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
                        E_dev, active, 0, src, A);
-    hipLaunchKernelGGL((k_slice_gemm_f32<false, false, MODE, BT, float, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
-                       E_dev, active, 0, A, B);
-    hipLaunchKernelGGL((k_slice_gemm_f32<true, true, MODE, BT, float, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
+    // the divide on the store of the second product (real eigenvalue pairs),
+    // the complex-pair blocks in place after it, then a plain left product
+    hipLaunchKernelGGL((k_slice_gemm_f32<false, MODE, BT, float, float, true>), g, dim3(256), 0, st, pd.dev,
+                       pr.dev, E_dev, active, 0, A, B);
+    if (pr.npair_slices > 0)
+        hipLaunchKernelGGL(k_divide_pairs<float>, dim3(pr.npair_slices, nb), dim3(256), 0, st, pd.dev, pr.dev, E_dev,
+                           active, B, (double *)nullptr);
+    hipLaunchKernelGGL((k_slice_gemm_f32<true, MODE, BT, float, float>), g, dim3(256), 0, st, pd.dev, pr.dev,
                        E_dev, active, 1, B, A);
-    hipLaunchKernelGGL((k_slice_gemm_f32<false, false, MODE, BT, float, TO>), g, dim3(256), 0, st, pd.dev, pr.dev,
+    hipLaunchKernelGGL((k_slice_gemm_f32<false, MODE, BT, float, TO>), g, dim3(256), 0, st, pd.dev, pr.dev,
                        E_dev, active, 1, A, dst);
 }
 
