@@ -86,6 +86,17 @@ def ps_l2_q97():
     return {"name": "ps_L2_quintic97_cubicz32", "desc": d, "E": [-0.2], "seeds": [4001]}
 
 
+def pair_pair_desc(nz=4, deg_z=3):
+    """A small Ps- like L=0 grid (quintic x 43 on [0,30], y 19 on [0,24],
+    uniform) on which one preconditioner slice of component 1 has complex
+    eigenvalue pairs in both its x and its y pencil, so that the divide meets
+    the 4 x 4 real blocks of an x pair against a y pair (no workload grid
+    has them)."""
+    d = make_desc(*PS_MINUS, 43, nz, deg_xy=5, deg_z=deg_z, R=30.0)
+    d["y"] = make_desc(*PS_MINUS, 19, nz, deg_xy=5, deg_z=deg_z, R=24.0)["y"]
+    return d
+
+
 WORKLOADS = {"ps_cubic16": ps_cubic16, "hminus_scan": hminus_scan, "ps_q127": ps_q127, "ps_l2_q97": ps_l2_q97}
 
 

@@ -59,6 +59,7 @@ CASES = [
     ("hminus_22x22x9_quadratic", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
     ("L2_tau+1", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0)),
     ("wide_x97_y13", wide(97, 13, 4, 3)),
+    ("x_and_y_pairs_43x19", W.pair_pair_desc()),
 ]
 ES = [-0.25 + 0.03j, 0.1 - 0.2j]
 

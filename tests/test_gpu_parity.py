@@ -110,6 +110,8 @@ PREC_CASES = [
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
     ("hminus_quadratic_22x22x9", small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
+    # complex pairs in the x and in the y pencil of one slice: the 4 x 4 blocks
+    ("x_and_y_pairs_43x19", W.pair_pair_desc()),
 ] + WIDE_CASES + EXT_CASES
 
 

@@ -170,6 +170,21 @@ def test_host_precond_factors_match_oracle(name, kw, variant):
     assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
 
 
+@lib_built
+def test_pair_pair_grid_has_x_and_y_pairs_in_one_slice():
+    """The grid of workloads.pair_pair_desc has a preconditioner slice whose x
+    and y pencils both have complex eigenvalue pairs (the 4 x 4 blocks of the
+    divide), for both z bases used in the tests."""
+    for nz, dz in ((4, 3), (6, 5)):
+        d = W.pair_pair_desc(nz, dz)
+        hits = []
+        for slot in range(nz):
+            lxr, lxi, lyr, lyi = fm.host_slice_eigenvalues(d, 0, slot)
+            if np.any(lxi != 0) and np.any(lyi != 0):
+                hits.append(slot)
+        assert hits, (nz, dz)
+
+
 EXCHANGE_CASES = [
     ("hminus_L0_p+1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), 1),
     ("hminus_L0_p-1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), -1),
