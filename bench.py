@@ -700,7 +700,7 @@ def main():
         l2 = {"config": "L=2 tau=+1 (3 M' blocks), quintic x,y 97 (the nominal 96 taken as 3K+1 = 97) x cubic z 32 "
                         "on [0,20]^2, Ps- like, E=-0.2, FGMRES(60); FP32 products (FP64 for reference)"}
         for pc in ("block_jacobi", "coupled"):
-            l2[pc] = workload_entry("ps_l2_q97", args, ("fp32", "fp64"), precond=pc, traffic=True)
+            l2[pc] = workload_entry("ps_l2_q97", args, ("fp64", "fp32"), precond=pc, traffic=True)
         cfgs["ps_l2_q97"] = l2
         cfgs["hminus_scan_complex"] = complex_entry(args)
         torch.cuda.empty_cache()

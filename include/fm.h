@@ -312,16 +312,24 @@ fm_status fm_eigs(fm_problem *p, double sigma, const fm_eigs_opts *opts, const d
  * after at least 24 Arnoldi steps, when requests wait for its free slots).
  * Each request is the same flexible GMRES solve as fm_solve; restarts may
  * differ from a solve alone, so a result alone and in a mix agree to the
- * solve's accuracy, not bitwise.  A request whose footprint exceeds the whole
- * budget is finished with FM_E_REJECTED. */
+ * solve's accuracy, not bitwise.  A request whose true residual falls by less
+ * than a factor 10 over a full cycle has stalled at its restart length (GMRES(m)
+ * can stagnate for energies high in the continuum): it leaves its lane and is
+ * queued again with twice the restart length (up to 1000, and while one slot
+ * fits a quarter of the budget), from x = 0, with the Arnoldi steps it has
+ * left (at least the new restart length); its result reports the steps of
+ * every lane and the restart length it finished with.  A request whose
+ * footprint exceeds the whole budget is finished with FM_E_REJECTED. */
 typedef struct fm_server fm_server;
 
 typedef struct {
     uint64_t tag;             /* the caller's tag from fm_submit */
     int status;               /* fm_status of the request */
-    int iters;                /* Arnoldi steps */
+    int iters;                /* Arnoldi steps (all lanes it ran in) */
     double rel_residual;      /* final true ||b - A x|| / ||b|| */
     double t_submit, t_start, t_done;  /* seconds (steady clock): submitted, joined a lane, finished */
+    int restart;              /* restart length of the lane it finished in (the submitted one, or
+                                 larger after stalls) */
 } fm_request_result;
 
 /* hbm_budget_bytes: device bytes the server may hold (factors + workspaces).

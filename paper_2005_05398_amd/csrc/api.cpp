@@ -592,20 +592,21 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
     std::vector<int> over;
     for (int s = 0; s < cap; ++s) {
         run[s] = hbuf[s];
-        if (run[s] && iters[s] >= limit[s]) {
-            run[s] = 0;
-            over.push_back(s);
-        }
+        if (run[s] && iters[s] >= limit[s]) over.push_back(s);
     }
-    if (!over.empty()) {
-        HIP_TRY(hipMemcpyAsync(running, run.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
-        std::vector<int> act(cap);
-        HIP_TRY(hipMemcpyAsync(act.data(), K.active, sizeof(int) * cap, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int s : over) act[s] = 0;
-        HIP_TRY(hipMemcpyAsync(K.active, act.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    }
+    return stop(over);
+}
+
+fm_status Batch::stop(const std::vector<int> &slots) {
+    if (slots.empty()) return FM_OK;
+    for (int s : slots) run[s] = 0;
+    HIP_TRY(hipMemcpyAsync(running, run.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+    std::vector<int> act(cap);
+    HIP_TRY(hipMemcpyAsync(act.data(), K.active, sizeof(int) * cap, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int s : slots) act[s] = 0;
+    HIP_TRY(hipMemcpyAsync(K.active, act.data(), sizeof(int) * cap, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return FM_OK;
 }
 

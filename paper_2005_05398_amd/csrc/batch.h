@@ -52,6 +52,9 @@ struct Batch {
     // residual decides convergence) and starts the slots in `joining`, whose E
     // and B rows must already be set.  A slot over its step limit stops here.
     fm_status boundary(const std::vector<int> &joining, int x0_is_guess);
+    // Stops running slots at a restart boundary (they leave the batch's
+    // kernels; their X rows keep the last iterate).
+    fm_status stop(const std::vector<int> &slots);
     // Arnoldi steps for the active slots until every slot stops, j reaches m,
     // or want_cut() holds after at least min_steps steps.
     fm_status cycle(const std::function<bool()> &want_cut, int min_steps);

@@ -86,6 +86,10 @@ struct ServeReq {
     fm_solve_opts opts{};
     double t_submit = 0, t_start = 0, t_done = 0;
     int status = FM_OK, iters = 0;
+    // restart escalation: steps taken in lanes of shorter restarts, and the
+    // true residual at the end of the last full cycle in this lane
+    int iters_before = 0;
+    double prev_rel = 1.0;
     double rel = 0;
 };
 
@@ -132,6 +136,8 @@ struct fm_server {
 namespace fm {
 
 namespace {
+
+constexpr double STALL_FACTOR = 0.1;   // least residual reduction per full cycle before a restart escalation
 
 void finish(fm_server *S, ServeReq *r) {
     r->t_done = now_s();
@@ -200,7 +206,7 @@ void lane_loop(fm_server *S, Lane *L) {
                 (void)hipMemcpyAsync(r->x_host, L->X + (long long)s * N, sizeof(double) * N, hipMemcpyDeviceToHost,
                                      L->st);
                 (void)hipStreamSynchronize(L->st);
-                r->iters = L->batch.iters[s];
+                r->iters = r->iters_before + L->batch.iters[s];
                 r->rel = rel.empty() ? 0.0 : rel[s];
                 if (st != FM_OK) r->status = st;
                 else if (fl[s]) r->status = FM_E_NONFINITE;
@@ -229,6 +235,46 @@ void lane_loop(fm_server *S, Lane *L) {
             S->error = "lane stopped after a HIP error";
             S->cv.notify_all();
             return;
+        }
+        if (st == FM_OK) {
+            // a request whose true residual fell by less than STALL_FACTOR over a
+            // full cycle has stalled at this restart length (GMRES(m) can stagnate
+            // high in the continuum): it leaves the lane and is queued again with
+            // twice the restart length, from x = 0, with the steps it has left
+            std::vector<int> full;
+            for (int s = 0; s < cap; ++s)
+                if (L->slot[s] && was[s] && L->batch.run[s] && L->batch.last_steps[s] >= L->batch.m) full.push_back(s);
+            std::vector<int> up;
+            if (!full.empty()) {
+                std::vector<double> rel, md;
+                std::vector<int> fl;
+                if (L->batch.read_results(rel, md, fl) == FM_OK)
+                    for (int s : full) {
+                        ServeReq *r = L->slot[s];
+                        const bool stalled = rel[s] > STALL_FACTOR * r->prev_rel;
+                        r->prev_rel = rel[s];
+                        fm_problem one;
+                        one.N = N;
+                        const int m2 = 2 * L->batch.m;
+                        if (stalled && m2 <= MAX_RESTART &&
+                            Batch::footprint(&one, 1, m2) + 2 * size_t(N) * 8 <= S->budget / 4)
+                            up.push_back(s);
+                    }
+            }
+            if (!up.empty() && L->batch.stop(up) == FM_OK) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (int s : up) {
+                    ServeReq *r = L->slot[s];
+                    const int used = L->batch.iters[s];
+                    r->iters_before += used;
+                    r->opts.max_iters = std::max(r->opts.max_iters - used, 2 * L->batch.m);
+                    r->opts.restart = 2 * L->batch.m;
+                    r->prev_rel = 1.0;
+                    L->slot[s] = nullptr;
+                    S->pending.push_back(r);
+                }
+                S->cv.notify_all();
+            }
         }
         if (L->batch.any_running()) {
             auto want_cut = [S, L, cap]() {
@@ -540,6 +586,7 @@ fm_status fm_poll(fm_server *S, fm_request_result *results, int max, int *n_done
         o.t_submit = r->t_submit;
         o.t_start = r->t_start;
         o.t_done = r->t_done;
+        o.restart = r->opts.restart;
         delete r;
     }
     *n_done = n;

@@ -405,7 +405,7 @@ def host_slice_eigenvalues(desc, alpha, slot):
 class FmRequestResult(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("iters", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
-                ("t_done", ctypes.c_double)]
+                ("t_done", ctypes.c_double), ("restart", ctypes.c_int)]
 
 
 def _server_sigs(L):
@@ -453,7 +453,7 @@ class Server:
             self._keep.pop(int(r.tag), None)
             out.append({"tag": int(r.tag), "status": STATUS_NAMES.get(r.status, r.status), "iters": r.iters,
                         "rel_residual": r.rel_residual, "t_submit": r.t_submit, "t_start": r.t_start,
-                        "t_done": r.t_done})
+                        "t_done": r.t_done, "restart": r.restart})
         return out
 
     def stats(self):

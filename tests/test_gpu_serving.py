@@ -4,7 +4,8 @@ Each served result must equal the same request solved alone with fm_solve, to
 the solve's own accuracy (relative difference 1e-8, the solution-error bar),
 and meet the FP64 residual bar against the oracle; requests submitted while
 others iterate must join before those finish; a request larger than the whole
-memory budget is rejected.
+memory budget is rejected; a request that stalls at its restart length is
+solved again with a longer one.
 """
 import time
 
@@ -78,3 +79,30 @@ def test_serving_rejects_oversize_request(device):
     out = srv.poll(block=True)
     srv.close()
     assert out and out[0]["tag"] == 5 and out[0]["status"] == "FM_E_REJECTED"
+
+
+def test_serving_escalates_the_restart_of_a_stalled_request(device):
+    """Above the break-up threshold GMRES with a short restart stalls: the
+    server takes such a request out of its lane and solves it again with
+    twice the restart length until it converges; the result meets the
+    oracle's residual and LU bars and reports the restart it finished with."""
+    from oracle.solve import lu_solve
+    fm = _fm()
+    d = W.make_desc(*W.H_MINUS, 13, 9, R=30.0, xy_map="quadratic")
+    N = W.n_unknowns(d)
+    E = -0.05
+    b = W.rhs(7301, N)
+    x = np.zeros(N)
+    srv = fm.Server(hbm_budget_bytes=8 << 30, max_batch=2)
+    srv.submit(d, E, b, x, 1, restart=6, rtol=1e-10, max_iters=4000)
+    out = []
+    while not out:
+        out += srv.poll(block=True)
+    srv.close()
+    o = out[0]
+    assert o["status"] == "FM_OK", o
+    assert o["restart"] > 6, o
+    A = OracleProblem(d).assemble(E)
+    assert rel_residual(A, x, b) <= 1e-10
+    xref = lu_solve(A, b)
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) <= 1e-8
