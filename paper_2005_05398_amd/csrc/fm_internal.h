@@ -15,7 +15,7 @@
 namespace fm {
 
 constexpr int MAXR = 6;      // at most 2q = 6 nonzero 1D basis functions per point
-constexpr int MAXM = 8;      // at most 8 M' blocks (J <= 7)
+constexpr int MAXM = 16;     // at most 16 M' blocks (J <= 15)
 
 // ---------------------------------------------------------------------------
 // Host: 1D Hermite spline basis with Gauss collocation points.
@@ -133,7 +133,7 @@ struct ProblemDev {
     long long N;                 // unknowns per request
     // angular coupling constants (L > 0)
     double lhp[MAXM], lhm[MAXM]; // lambda-hat^{J, M'} and lambda-hat^{J, -M'} per M' index
-    double dcoef[MAXM * MAXM * 16];   // Wigner-sum coefficient table (see setup)
+    double dcoef[MAXM * MAXM * 2 * MAXM]; // Wigner-sum coefficient table (see setup): 2J + 1 <= 2 MAXM terms
     int dlen;
     int q[3];                    // spline order of x, y, z (same for all components), 0 if mixed
     const int *gtile;            // [sum ntiles_g][GT_REC] grouped tiles, in launch order (layout below)

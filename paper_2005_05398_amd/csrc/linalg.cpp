@@ -323,6 +323,72 @@ std::vector<cplx> inverse_iteration(int n, const std::vector<double> &H, cplx la
     return b;
 }
 
+
+// Fallback for a value whose Hessenberg-form vector misses the residual test
+// (a tight cluster, or a balancing with a wide range): inverse iteration on the
+// original matrix A with a full LU (partial pivoting), from a start vector
+// orthogonalised against the vectors already accepted, up to six steps, each
+// checked on ||A v - lambda v||.  Returns the residual reached.
+double inverse_iteration_full(int n, const std::vector<double> &A, cplx lambda, double tol,
+                              const std::vector<std::vector<cplx>> &prev, std::vector<cplx> &v) {
+    std::vector<cplx> U(size_t(n) * n);
+    double anorm = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            U[size_t(i) * n + j] = A[size_t(i) * n + j] - (i == j ? lambda : 0.0);
+            anorm = std::max(anorm, std::fabs(A[size_t(i) * n + j]));
+        }
+    const double tiny = 1e-15 * std::max(anorm, 1e-300);
+    std::vector<int> piv(n);
+    for (int k = 0; k < n; ++k) {
+        int pr = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::abs(U[size_t(i) * n + k]) > std::abs(U[size_t(pr) * n + k])) pr = i;
+        piv[k] = pr;
+        if (pr != k)
+            for (int j = 0; j < n; ++j) std::swap(U[size_t(k) * n + j], U[size_t(pr) * n + j]);
+        if (std::abs(U[size_t(k) * n + k]) < tiny) U[size_t(k) * n + k] = tiny;
+        for (int i = k + 1; i < n; ++i) {
+            const cplx l = U[size_t(i) * n + k] / U[size_t(k) * n + k];
+            U[size_t(i) * n + k] = l;
+            for (int j = k + 1; j < n; ++j) U[size_t(i) * n + j] -= l * U[size_t(k) * n + j];
+        }
+    }
+    auto normalise = [&](std::vector<cplx> &b) {
+        double nrm = 0;
+        for (auto &t : b) nrm += std::norm(t);
+        nrm = std::sqrt(nrm);
+        for (auto &t : b) t /= nrm;
+    };
+    v.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) v[i] = cplx(1.0 + 0.3 * std::sin(2.0 + 5.1 * i), 0.2 * std::cos(1.0 + 3.7 * i));
+    for (const auto &u : prev) {                       // away from the vectors already found
+        cplx d = 0.0;
+        for (int i = 0; i < n; ++i) d += std::conj(u[i]) * v[i];
+        for (int i = 0; i < n; ++i) v[i] -= d * u[i];
+    }
+    normalise(v);
+    double res = 1e300;
+    for (int it = 0; it < 6 && !(res <= tol); ++it) {
+        for (int k = 0; k < n; ++k) std::swap(v[k], v[piv[k]]);
+        for (int i = 1; i < n; ++i)
+            for (int j = 0; j < i; ++j) v[i] -= U[size_t(i) * n + j] * v[j];
+        for (int i = n - 1; i >= 0; --i) {
+            cplx t = v[i];
+            for (int j = i + 1; j < n; ++j) t -= U[size_t(i) * n + j] * v[j];
+            v[i] = t / U[size_t(i) * n + i];
+        }
+        normalise(v);
+        res = 0;
+        for (int i = 0; i < n; ++i) {
+            cplx t = -lambda * v[i];
+            for (int j = 0; j < n; ++j) t += A[size_t(i) * n + j] * v[j];
+            res = std::max(res, std::abs(t));
+        }
+    }
+    return res;
+}
+
 }  // namespace
 
 std::string pencil_diag(int n, const std::vector<double> &A1, const std::vector<double> &A2,
@@ -461,6 +527,7 @@ std::string dense_eig_by_modulus(int n, const std::vector<double> &A, int nmin, 
         if (wi[c] > 0.0 && !(wi[c + 1] == -wi[c] && wr[c + 1] == wr[c])) return "unpaired complex eigenvalue";
     // eigenvectors of the leading values (at least ncols columns, pairs whole)
     std::vector<std::vector<double>> cols;
+    std::vector<std::vector<cplx>> found;             // accepted vectors (unit, complex)
     type.clear();
     double anorm = 0;
     for (double v : A) anorm = std::max(anorm, std::fabs(v));
@@ -484,10 +551,13 @@ std::string dense_eig_by_modulus(int n, const std::vector<double> &A, int nmin, 
             for (int j = 0; j < n; ++j) t += A[size_t(i) * n + j] * v[j];
             res = std::max(res, std::abs(t));
         }
-        if (!(res <= 1e-11 * std::max(anorm, std::abs(lam)))) {
+        const double tol = 1e-11 * std::max(anorm, std::abs(lam));
+        if (!(res <= tol)) res = inverse_iteration_full(n, A, lam, tol, found, v);
+        if (!(res <= tol)) {
             if ((int)cols.size() < nmin) return "inverse iteration did not converge";
             break;                                    // keep the vectors found so far
         }
+        found.push_back(v);
         std::vector<double> re(n), ii(n);
         for (int i = 0; i < n; ++i) {
             re[i] = v[i].real();

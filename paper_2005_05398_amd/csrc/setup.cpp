@@ -62,7 +62,7 @@ std::string setup_problem(fm_problem *p) {
     p->M0 = (1 - d.tau) / 2;
     p->nM = d.J - p->M0 + 1;
     if (p->nM < 1) return "no M' blocks for this J, tau";
-    if (p->nM > MAXM) return "J too large (at most 8 M' blocks)";
+    if (p->nM > MAXM) return "J too large (at most 16 M' blocks)";
     for (int a = 0; a < 3; ++a) {
         if (!(d.mass[a] > 0) || !std::isfinite(d.mass[a])) return "masses must be positive";
         if (!std::isfinite(d.charge[a])) return "charges must be finite";

@@ -123,6 +123,15 @@ HE_TABLE1 = [((22, 22, 9), (19, 19, 12), (-2.12524, -2.05654)),
 HE_TABLE1_DOMAINS = ((36.0, 36.0), (9.0, 6.0))
 HE_1P_BENCHMARK = (-2.12384308649810135925, -2.05514636209194353689)
 
+# Table 3 of Sec. 4 (the high-J runs: J = 10, tau = +1, p = +1, eleven M'
+# blocks; domains (1: 280, 280; 3: 2, 2)): basis sizes of components (1, 3)
+# and the printed ground and first excited energies.
+HE_TABLE3_J10 = [((58, 58, 6), (4, 4, 6), (-2.00398, -2.00332)),
+                 ((88, 88, 9), (7, 7, 9), (-2.00412, -2.00346)),
+                 ((118, 118, 9), (7, 7, 9), (-2.00413, -2.00347)),
+                 ((118, 118, 12), (7, 7, 12), (-2.00413, -2.00347))]
+HE_TABLE3_DOMAINS = ((280.0, 280.0), (2.0, 2.0))
+
 
 def helium_desc(g1, g3, dom1=HE_TABLE1_DOMAINS[0], dom3=HE_TABLE1_DOMAINS[1], J=1, tau=1):
     """Helium description with basis sizes g1 (components 1, 2) and g3

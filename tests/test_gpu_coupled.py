@@ -38,6 +38,8 @@ CASES = [
     ("quintic_xy_cubic_z_L2_13x13x8", W.make_desc(*W.PS_MINUS, 13, 8, J=2, tau=1, deg_xy=5, deg_z=3, R=20.0)),
     ("quintic_L3_odd_10x10x6", W.make_desc(*W.PS_MINUS, 10, 6, J=3, tau=-1, deg_xy=5, deg_z=5, R=20.0)),
     ("quintic_xy_cubic_z_L2_31x31x16", W.make_desc(*W.PS_MINUS, 31, 16, J=2, tau=1, deg_xy=5, deg_z=3, R=20.0)),
+    # eleven M' blocks (the helium runs of the paper's high-J table have J = 10)
+    ("cubic_L10_8x8x4", W.make_desc(*W.H_MINUS, 8, 4, J=10, tau=1, deg_xy=3, deg_z=3, R=15.0)),
 ]
 
 

@@ -60,6 +60,9 @@ OP_CASES = [
     # finite y0 of the cut-off (eq. (Mcutoff0)): V^(s) and the potential field depend on y
     ("hminus_finite_y0", dict(small(W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"), y0=6.0)),
     ("L2_finite_y0", dict(small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3), y0=2.5)),
+    # more than three M' blocks: the generic operator kernel (up to 16 blocks)
+    ("L5_tau+1_generic", small(W.PS_MINUS, 7, 4, J=5, tau=1, dz=3)),
+    ("L10_tau+1_generic", small(W.H_MINUS, 7, 4, J=10, tau=1, dz=3)),
 ] + WIDE_CASES
 
 
@@ -110,6 +113,7 @@ PREC_CASES = [
     ("quintic_7x7x6", small(W.PS_MINUS, 7, 6)),
     ("hminus_quadratic_22x22x9", small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
     ("L2_tau+1", small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3)),
+    ("L5_tau+1", small(W.PS_MINUS, 7, 4, J=5, tau=1, dz=3)),
     # complex pairs in the x and in the y pencil of one slice: the 4 x 4 blocks
     ("x_and_y_pairs_43x19", W.pair_pair_desc()),
 ] + WIDE_CASES + EXT_CASES

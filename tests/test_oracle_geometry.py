@@ -136,7 +136,7 @@ def F(J, tau, M, Mp, ang):
     return (D(J, M, Mp, ang) + tau * (-1) ** Mp * D(J, M, -Mp, ang)) / math.sqrt(2 + 2 * (Mp == 0))
 
 
-@pytest.mark.parametrize("J,tau", [(1, 1), (2, 1), (2, -1), (3, 1)])
+@pytest.mark.parametrize("J,tau", [(1, 1), (2, 1), (2, -1), (3, 1), (10, 1)])
 def test_F_addition_theorem(J, tau):
     """F_{MM'}(Omega_b) = sum_{M''=M0}^J (-1)^{M'-M''} 2/sqrt(2+2 delta_{M'0})
     F_{M'M''}(0, w_ba, 0) F_{MM''}(Omega_a), eq. (F-ba)."""

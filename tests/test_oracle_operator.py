@@ -102,6 +102,8 @@ def analytic(prob, polys, E):
     # a finite y0: the cut-off and V^(s) depend on y as well (eq. (Mcutoff0))
     (W.H_MINUS, 0, 1, 5, 5, 10, 9, "quadratic", 4.0),
     (W.PS_MINUS, 2, 1, 5, 3, 7, 4, "uniform", 2.5),
+    # many M' blocks (the paper's high-J runs have J = 10, eleven blocks)
+    (W.H_MINUS, 10, 1, 3, 3, 6, 4, "uniform", W.INF),
 ])
 def test_manufactured_solution(mc, J, tau, deg_xy, deg_z, nxy, nz, xy_map, y0):
     prob = Problem(small_desc(mc, nxy, nz, J, tau, deg_xy, deg_z, xy_map=xy_map, y0=y0))
