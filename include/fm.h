@@ -114,7 +114,16 @@ typedef struct {
                                  coupling reads it at |z_3| times sigma for z_3 < 0.  Its n_z becomes
                                  n/2 (cubic), 3K/2 + 2 (quintic, sigma = +1) or 3K/2 + 1 (quintic,
                                  sigma = -1) for n = 3K + 3 */
+    double mode_fit_tol;      /* coupled preconditioner only (Sec. 3.2, eq. (prop-eq)): a z mode (M', k)
+                                 whose computed eigenvector matches g_{M'+k}^{M'} at the collocation
+                                 points with a relative least-squares residual above this keeps its
+                                 computed eigenvalue and has no M' +- 1 coupling (the block-Jacobi
+                                 treatment of that mode); the substitution of eq. (prop-eq) is made for
+                                 the others.  <= 0: FM_DEFAULT_MODE_FIT_TOL; >= 1: every mode (the
+                                 paper's matrix as printed) */
 } fm_problem_desc;
+
+#define FM_DEFAULT_MODE_FIT_TOL 0.02
 
 typedef struct fm_problem fm_problem;
 
@@ -148,8 +157,8 @@ const char *fm_last_error(void);
  * potential fields) and upload it to the device.  Complex-conjugate
  * eigenvalue pairs of the x and y pencils are kept as real 2x2 blocks.
  * Errors: FM_E_INVALID (bad description; an exchange-reduced description
- * also needs one spline order in x and y and one in z over the components,
- * n_M <= 3 and 2q <= n_y <= 256), FM_E_PENCIL (a z pencil with a complex
+ * also needs one spline order in x and y and one in z over the components
+ * and 2q <= n_y <= 256), FM_E_PENCIL (a z pencil with a complex
  * spectrum, or a diagonalisation that fails its accuracy check), FM_E_NOMEM,
  * FM_E_HIP.  *out is set only on FM_OK. */
 fm_status fm_create_problem(const fm_problem_desc *desc, fm_problem **out);

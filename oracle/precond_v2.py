@@ -25,6 +25,17 @@ ascending |lambda~| (column k <-> l = M'+k) and each is scaled by the
 least-squares factor that maps its values at the collocation points onto
 g_{M'+k}^{M'} there.  W-bar_z^{M'} = (S_z W_z^{M'})^-1 then keeps
 W-bar_z S_z W_z = I of eq. (z-dec).
+
+Only the pencil's lower modes are such functions: the spline space
+reproduces g_l^{M'} (a polynomial of degree l - M') exactly up to its
+polynomial degree, and approximately for a while beyond; the highest modes'
+eigenvectors can be nearly orthogonal to their g (a least-squares scale near
+zero, which would blow W-bar_z up).  The substitution is therefore made for
+the modes whose fit has a relative residual of at most a tolerance (the
+description's mode_fit_tol, default DEFAULT_MODE_FIT_TOL); the others keep
+their computed eigenvalue and lose the M'+-1 entries that touch them, as in
+the block-Jacobi variant.  With every mode resolved this is the paper's
+script-L; with none, the block-Jacobi operator.
 """
 import math
 
@@ -87,10 +98,24 @@ def z_operators(bz, Mp):
     return d0, dp, dm
 
 
-def z_pencil(bz, Mp):
-    """(W-bar_z^{M'}, W_z^{M'}, lambda~) = D(D_z^{M'}, S_z) (eq. (z-dec)),
-    ordered by ascending |lambda~| and scaled to g_{M'+k}^{M'} (module
-    docstring)."""
+DEFAULT_MODE_FIT_TOL = 0.02
+
+
+def mode_fit_tol(desc):
+    """The description's tolerance of the z-mode fit (the default where it
+    gives none or a value <= 0)."""
+    t = float(desc.get("mode_fit_tol", 0.0))
+    return t if t > 0 else DEFAULT_MODE_FIT_TOL
+
+
+def z_modes(bz, Mp, fit_tol):
+    """(W-bar_z^{M'}, W_z^{M'}, lambda~, resolved) of the z pencil (D_z^{M'},
+    S_z) (eq. (z-dec)): eigenvectors ordered by ascending |lambda~| (column k
+    <-> l = M'+k).  Column k is fitted to g_{M'+k}^{M'} at the collocation
+    points in least squares; where the relative residual of the fit is at most
+    fit_tol the mode is resolved and the column takes the fitted scale (the
+    functions that eq. (prop-eq) presupposes), otherwise it is left as the
+    pencil gave it.  fit_tol None: every mode resolved."""
     Sz = bz.matrix(0)
     d0, _, _ = z_operators(bz, Mp)
     lam_t, W = sla.eig(d0, Sz)
@@ -100,19 +125,35 @@ def z_pencil(bz, Mp):
     order = np.argsort(np.abs(lam_t), kind="stable")
     lam_t, W = lam_t[order], W[:, order]
     vals = Sz @ W
+    resolved = np.zeros(W.shape[1], dtype=bool)
     for k in range(W.shape[1]):
         g = g_assoc(Mp + k, Mp, bz.points)
-        W[:, k] *= (g @ vals[:, k]) / (vals[:, k] @ vals[:, k])
+        s = (g @ vals[:, k]) / (vals[:, k] @ vals[:, k])
+        if fit_tol is None or np.linalg.norm(s * vals[:, k] - g) <= fit_tol * np.linalg.norm(g):
+            resolved[k] = True
+            W[:, k] *= s
     Wbar = np.linalg.inv(Sz @ W)
-    return Wbar, W, lam_t
+    return Wbar, W, lam_t, resolved
 
 
-def approx_block(prob, a, E):
+def z_pencil(bz, Mp):
+    """(W-bar_z^{M'}, W_z^{M'}, lambda~) = D(D_z^{M'}, S_z) (eq. (z-dec)),
+    ordered by ascending |lambda~| and every column scaled to g_{M'+k}^{M'}
+    (module docstring)."""
+    return z_modes(bz, Mp, None)[:3]
+
+
+def approx_block(prob, a, E, fit_tol=None):
     """(script-L_alpha^xy, W-bar_z, W_z) for component alpha at energy E: the
     blocks of eq. (L-exact) / (L-pm-exact) after the substitutions of
-    eq. (prop-eq), as sparse matrices over the [M'][k][x][y] index."""
+    eq. (prop-eq), as sparse matrices over the [M'][k][x][y] index.  The
+    substitution is made for the resolved z modes (z_modes with the
+    description's tolerance, or fit_tol): a mode that is not resolved keeps its
+    computed eigenvalue and the M'+-1 entries that touch it are dropped (the
+    block-Jacobi treatment of that mode)."""
     d = prob.desc
     J = prob.J
+    tol = mode_fit_tol(d) if fit_tol is None else fit_tol
     bz, bx, by = prob.bz[a], prob.bx[a], prob.by[a]
     nz = bz.n
     Sx, D2x = bx.matrix(0), bx.matrix(2)
@@ -127,40 +168,41 @@ def approx_block(prob, a, E):
     SxYr = K(Sx, Yr2 @ Sy)
     XrSy = K(Xr2 @ Sx, Sy)
     common = -K(Sx, D2y) - K(D2x, Sy) + K(Vx @ Sx, Sy) + K(Sx, Vh @ Sy) - E * K(Sx, Sy)
+    modes = [z_modes(bz, Mp, tol) for Mp in prob.Mps]
     blocks = [[None] * prob.nM for _ in range(prob.nM)]
-    Wbars, Ws = [], []
     for iM, Mp in enumerate(prob.Mps):
-        Wbar, W, _ = z_pencil(bz, Mp)
-        Wbars.append(Wbar)
-        Ws.append(W)
-        blocks[iM][iM] = K(Iz, common + (J * (J + 1) - 2 * Mp * Mp) * SxYr) - K(lam_z(Mp, nz), SxYr + XrSy)
+        _, _, lam_t, res = modes[iM]
+        Lz = np.where(res, np.diag(lam_z(Mp, nz)), lam_t)
+        blocks[iM][iM] = K(Iz, common + (J * (J + 1) - 2 * Mp * Mp) * SxYr) - K(np.diag(Lz), SxYr + XrSy)
         if iM + 1 < prob.nM:
-            blocks[iM][iM + 1] = lam_hat_plus(J, Mp) * K(lam_z_plus(Mp, nz), SxYr)
+            Lp = lam_z_plus(Mp, nz) * np.outer(res, modes[iM + 1][3])
+            blocks[iM][iM + 1] = lam_hat_plus(J, Mp) * K(Lp, SxYr)
         if iM - 1 >= 0:
-            blocks[iM][iM - 1] = -lam_hat_minus(J, Mp) * K(lam_z_minus(Mp, nz), SxYr)
+            Lm = lam_z_minus(Mp, nz) * np.outer(res, modes[iM - 1][3])
+            blocks[iM][iM - 1] = -lam_hat_minus(J, Mp) * K(Lm, SxYr)
     Lxy = sp.bmat(blocks, format="csc")
     nxy = bx.n * by.n
-    Wbar_z = sp.block_diag([K(Wb, sp.identity(nxy)) for Wb in Wbars], format="csr")
-    W_z = sp.block_diag([K(W, sp.identity(nxy)) for W in Ws], format="csr")
+    Wbar_z = sp.block_diag([K(m[0], sp.identity(nxy)) for m in modes], format="csr")
+    W_z = sp.block_diag([K(m[1], sp.identity(nxy)) for m in modes], format="csr")
     return Lxy, Wbar_z, W_z
 
 
-def approx_operator(prob, E):
+def approx_operator(prob, E, fit_tol=None):
     """script-L = diag{script-L_1, script-L_2, script-L_3} as a dense matrix
     (tiny grids only)."""
     mats = []
     for a in range(3):
-        Lxy, Wbar_z, W_z = approx_block(prob, a, E)
+        Lxy, Wbar_z, W_z = approx_block(prob, a, E, fit_tol)
         mats.append(np.linalg.inv(Wbar_z.toarray()) @ Lxy.toarray() @ np.linalg.inv(W_z.toarray()))
     return sla.block_diag(*mats)
 
 
-def precond_v2_factory(prob, E):
+def precond_v2_factory(prob, E, fit_tol=None):
     """The map r -> script-L(E)^-1 r (eqs. (prec-1), (prec-2)), component by
     component, with each script-L_alpha^xy factorised once."""
     parts = []
     for a in range(3):
-        Lxy, Wbar_z, W_z = approx_block(prob, a, E)
+        Lxy, Wbar_z, W_z = approx_block(prob, a, E, fit_tol)
         parts.append((prob.nM * prob.block[a], spla.splu(Lxy), Wbar_z, W_z))
 
     def apply(r):
@@ -175,6 +217,6 @@ def precond_v2_factory(prob, E):
     return apply
 
 
-def precond_v2_reference(prob, E, r):
+def precond_v2_reference(prob, E, r, fit_tol=None):
     """z = script-L(E)^-1 r."""
-    return precond_v2_factory(prob, E)(r)
+    return precond_v2_factory(prob, E, fit_tol)(r)

@@ -839,7 +839,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
     if (sizeof(double) * size_t(pd.tile_lds) > 64 * 1024 && matvec_tiled_ok(pd))
         prepare_operator_lds(sizeof(double) * size_t(pd.tile_lds));
     if (p->exchange != 0 && !matvec_tiled_ok(pd))
-        return "invalid: exchange-reduced problems need the tiled operator (one spline order in x, y and in z, n_M <= 3, "
+        return "invalid: exchange-reduced problems need the tiled operator (one spline order in x, y and in z, "
                "2q <= n_y <= 256)";
     if (matvec_tiled_ok(pd)) {
         if (2 * p->N >= (1LL << 31)) return "problem too large for the tiled operator";

@@ -25,6 +25,13 @@
 // y pencil of (l, m); the slots replace the (M', k) slices of the block-Jacobi
 // variant one for one (sum_l n_l = n_M n_z), and the z transform and the M'
 // mixing fold into one n_M n_z x n_M n_z matrix per direction.
+//
+// The substitution of eq. (prop-eq) (analytic eigenvalues, the bidiagonal
+// Lambda^{M'+-}) presupposes z eigenvectors that represent g_l^{M'}; the
+// pencil's highest modes do not (the spline space reproduces g_l^{M'} only up
+// to its polynomial degree, roughly beyond), and a mode nearly orthogonal to
+// its g would take a near-zero scale.  Such modes keep their computed
+// eigenvalue and no M' coupling, one slot each, as in the block-Jacobi variant.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -61,11 +68,15 @@ double assoc_g(int l, int M, double z) {
 }
 
 // Orders the z pencil of block M' (Wbar, W row-major n x n, W's columns the
-// eigenvectors) by ascending |lambda~| and scales column k so that its values
-// at the collocation points fit g_{M'+k}^{M'} there in least squares; Wbar's
-// rows take the inverse factors, which keeps Wbar S_z W = I.
-std::string order_and_scale_z(const Basis1D &bz, int Mp, std::vector<double> &Wb, std::vector<double> &W,
-                              std::vector<double> &lre) {
+// eigenvectors) by ascending |lambda~| and fits column k to g_{M'+k}^{M'} at
+// the collocation points in least squares.  Where the fit's relative residual
+// is at most fit_tol the column takes the fitted scale (Wbar's row the inverse
+// factor, which keeps Wbar S_z W = I) and the mode is marked resolved: the
+// substitution of eq. (prop-eq) presupposes exactly these functions.  A mode
+// that its eigenvector does not represent (the pencil's higher modes, beyond
+// what the spline space reproduces) stays unscaled and unresolved.
+std::string order_and_scale_z(const Basis1D &bz, int Mp, double fit_tol, std::vector<double> &Wb,
+                              std::vector<double> &W, std::vector<double> &lre, std::vector<char> &resolved) {
     const int n = bz.n;
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
@@ -80,16 +91,25 @@ std::string order_and_scale_z(const Basis1D &bz, int Mp, std::vector<double> &Wb
         }
     }
     const std::vector<double> S = bz.dense(0);
+    resolved.assign(n, 0);
+    std::vector<double> v(n), g(n);
     for (int c = 0; c < n; ++c) {
-        double gv = 0, vv = 0;
+        double gv = 0, vv = 0, gg = 0;
         for (int i = 0; i < n; ++i) {
-            double v = 0;
-            for (int j = 0; j < n; ++j) v += S[size_t(i) * n + j] * W2[size_t(j) * n + c];
-            gv += assoc_g(Mp + c, Mp, bz.points[i]) * v;
-            vv += v * v;
+            double t = 0;
+            for (int j = 0; j < n; ++j) t += S[size_t(i) * n + j] * W2[size_t(j) * n + c];
+            v[i] = t;
+            g[i] = assoc_g(Mp + c, Mp, bz.points[i]);
+            gv += g[i] * t;
+            vv += t * t;
+            gg += g[i] * g[i];
         }
         const double s = gv / vv;
+        double rr = 0;
+        for (int i = 0; i < n; ++i) rr += (s * v[i] - g[i]) * (s * v[i] - g[i]);
+        if (!(std::sqrt(rr / gg) <= fit_tol)) continue;
         if (!(std::fabs(s) > 0) || !std::isfinite(s)) return "z eigenvector orthogonal to its Legendre function";
+        resolved[c] = 1;
         for (int i = 0; i < n; ++i) {
             W2[size_t(i) * n + c] *= s;
             Wb2[size_t(c) * n + i] /= s;
@@ -101,13 +121,18 @@ std::string order_and_scale_z(const Basis1D &bz, int Mp, std::vector<double> &Wb
     return "";
 }
 
-// From the ordered and scaled z pencils of every M' block of one component
-// (Wbz[iM], Wz[iM], n_z x n_z row-major), builds the joint z matrices
-// Zj = [forward | backward], each (n_M n_z)^2 row-major over (slot, (iM, k)),
-// and per slot the x and y pencil coefficients: A_x = -D_x + cx X_r2 S_x +
-// V S_x, A_y = -D_y + cy Y_r2 S_y + Vhat S_y.
+// From the ordered z pencils of every M' block of one component (Wbz[iM],
+// Wz[iM], n_z x n_z row-major; lz[iM] their eigenvalues; resolved[iM] the
+// modes of order_and_scale_z), builds the joint z matrices Zj = [forward |
+// backward], each (n_M n_z)^2 row-major over (slot, (iM, k)), and per slot
+// the x and y pencil coefficients: A_x = -D_x + cx X_r2 S_x + V S_x,
+// A_y = -D_y + cy Y_r2 S_y + Vhat S_y.  For each l the resolved modes
+// (M', l - M') of consecutive M' form one chain of T_l; a mode that is not
+// resolved is a slot of its own with its computed eigenvalue (cx = -lambda~,
+// cy = J(J+1) - 2M'^2 - lambda~), as in the block-Jacobi variant.
 std::string coupled_slots(const fm_problem *p, int nz, const std::vector<std::vector<double>> &Wbz,
-                          const std::vector<std::vector<double>> &Wz, std::vector<double> &Zj,
+                          const std::vector<std::vector<double>> &Wz, const std::vector<std::vector<double>> &lz,
+                          const std::vector<std::vector<char>> &resolved, std::vector<double> &Zj,
                           std::vector<double> &cx, std::vector<double> &cy) {
     const int nM = p->nM, M0 = p->M0, J = p->desc.J;
     const int n = nM * nz;
@@ -117,44 +142,61 @@ std::string coupled_slots(const fm_problem *p, int nz, const std::vector<std::ve
     double *Zf = Zj.data(), *Zb = Zj.data() + size_t(n) * n;
     int slot = 0;
     for (int l = M0; l <= J + nz - 1; ++l) {
-        std::vector<int> ms;    // M' indices present for this l
+        // the resolved modes of this l, cut into chains of consecutive M'
+        std::vector<std::vector<int>> chains;
         for (int iM = 0; iM < nM; ++iM) {
             const int k = l - (M0 + iM);
-            if (k >= 0 && k < nz) ms.push_back(iM);
+            if (k < 0 || k >= nz || !resolved[iM][k]) continue;
+            if (chains.empty() || chains.back().back() != iM - 1) chains.emplace_back();
+            chains.back().push_back(iM);
         }
-        const int nl = int(ms.size());
-        std::vector<double> T(size_t(nl) * nl, 0.0), I(size_t(nl) * nl, 0.0);
-        for (int q = 0; q < nl; ++q) {
-            const int Mp = M0 + ms[q];
-            I[size_t(q) * nl + q] = 1.0;
-            T[size_t(q) * nl + q] = double(J) * (J + 1) - 2.0 * Mp * Mp + double(l) * (l + 1);
-            if (q + 1 < nl) T[size_t(q) * nl + q + 1] = -lam_of(J, Mp) * std::sqrt(1.0 + (Mp == 0)) * lam_of(l, Mp);
-            if (q >= 1) T[size_t(q) * nl + q - 1] = -lam_of(J, -Mp) * std::sqrt(1.0 + (Mp == 1)) * lam_of(l, -Mp);
-        }
-        std::vector<double> Ub, U, tre, tim;
-        std::vector<signed char> ty;
-        if (nl == 1) {          // a single M' for this l: nothing to diagonalise
-            Ub = U = {1.0};
-            tre = {T[0]};
-        } else {
-            std::string r = pencil_diag(nl, T, I, Ub, U, tre, tim, ty, nullptr);
-            if (!r.empty()) return "M' coupling matrix: " + r;
-            for (int q = 0; q < nl; ++q)
-                if (ty[q] != 0) return "M' coupling matrix has complex eigenvalues";
-        }
-        for (int m = 0; m < nl; ++m, ++slot) {
-            cx[slot] = double(l) * (l + 1);
-            cy[slot] = tre[m];
+        for (const std::vector<int> &ms : chains) {
+            const int nl = int(ms.size());
+            std::vector<double> T(size_t(nl) * nl, 0.0), I(size_t(nl) * nl, 0.0);
             for (int q = 0; q < nl; ++q) {
-                const int iM = ms[q], k = l - (M0 + iM);
-                const double uf = Ub[size_t(m) * nl + q], ub = U[size_t(q) * nl + m];
-                const double *wb = Wbz[iM].data() + size_t(k) * nz;   // row k of Wbar_z
-                for (int kk = 0; kk < nz; ++kk) Zf[size_t(slot) * n + iM * nz + kk] += uf * wb[kk];
-                for (int kk = 0; kk < nz; ++kk)                       // column k of W_z
-                    Zb[size_t(iM * nz + kk) * n + slot] += Wz[iM][size_t(kk) * nz + k] * ub;
+                const int Mp = M0 + ms[q];
+                I[size_t(q) * nl + q] = 1.0;
+                T[size_t(q) * nl + q] = double(J) * (J + 1) - 2.0 * Mp * Mp + double(l) * (l + 1);
+                if (q + 1 < nl) T[size_t(q) * nl + q + 1] = -lam_of(J, Mp) * std::sqrt(1.0 + (Mp == 0)) * lam_of(l, Mp);
+                if (q >= 1) T[size_t(q) * nl + q - 1] = -lam_of(J, -Mp) * std::sqrt(1.0 + (Mp == 1)) * lam_of(l, -Mp);
+            }
+            std::vector<double> Ub, U, tre, tim;
+            std::vector<signed char> ty;
+            if (nl == 1) {      // a single M' for this l: nothing to diagonalise
+                Ub = U = {1.0};
+                tre = {T[0]};
+            } else {
+                std::string r = pencil_diag(nl, T, I, Ub, U, tre, tim, ty, nullptr);
+                if (!r.empty()) return "M' coupling matrix: " + r;
+                for (int q = 0; q < nl; ++q)
+                    if (ty[q] != 0) return "M' coupling matrix has complex eigenvalues";
+            }
+            for (int m = 0; m < nl; ++m, ++slot) {
+                cx[slot] = double(l) * (l + 1);
+                cy[slot] = tre[m];
+                for (int q = 0; q < nl; ++q) {
+                    const int iM = ms[q], k = l - (M0 + iM);
+                    const double uf = Ub[size_t(m) * nl + q], ub = U[size_t(q) * nl + m];
+                    const double *wb = Wbz[iM].data() + size_t(k) * nz;   // row k of Wbar_z
+                    for (int kk = 0; kk < nz; ++kk) Zf[size_t(slot) * n + iM * nz + kk] += uf * wb[kk];
+                    for (int kk = 0; kk < nz; ++kk)                       // column k of W_z
+                        Zb[size_t(iM * nz + kk) * n + slot] += Wz[iM][size_t(kk) * nz + k] * ub;
+                }
             }
         }
     }
+    // the modes that are not resolved, one slot each
+    for (int iM = 0; iM < nM; ++iM)
+        for (int k = 0; k < nz; ++k) {
+            if (resolved[iM][k]) continue;
+            const int Mp = M0 + iM;
+            cx[slot] = -lz[iM][k];
+            cy[slot] = double(J) * (J + 1) - 2.0 * Mp * Mp - lz[iM][k];
+            const double *wb = Wbz[iM].data() + size_t(k) * nz;
+            for (int kk = 0; kk < nz; ++kk) Zf[size_t(slot) * n + iM * nz + kk] = wb[kk];
+            for (int kk = 0; kk < nz; ++kk) Zb[size_t(iM * nz + kk) * n + slot] = Wz[iM][size_t(kk) * nz + k];
+            ++slot;
+        }
     if (slot != n) return "slot count mismatch";
     return "";
 }

@@ -148,14 +148,15 @@ struct ProblemDev {
 
 // The operator runs as two tiled kernels (coupling into a two-slot buffer, then
 // the local stencil plus that buffer) when x and y share one spline order in
-// all components, z one order, n_M <= 3, 2q <= n_y <= 256 and the operator's
-// z-contracted planes fit the LDS of one block; otherwise one generic kernel
-// does everything.
+// all components, z one order, 2q <= n_y <= 256 and the operator's
+// z-contracted planes fit the LDS of one block (n_M <= 3: kernels specialised
+// for the block count; more blocks: kernels that take them one at a time);
+// otherwise one generic kernel does everything.
 inline bool matvec_tiled_ok(const ProblemDev &pd) {
     const bool same_xy = pd.q[0] != 0 && pd.q[0] == pd.q[1];
     bool rows_fit = true;                // one block of 256 threads covers the y points
     for (int a = 0; a < 3; ++a) rows_fit = rows_fit && pd.comp[a].y.n <= 256;
-    return same_xy && rows_fit && pd.q[2] != 0 && pd.nM <= 3 && sizeof(double) * size_t(pd.tile_lds) <= size_t(pd.lds_max);
+    return same_xy && rows_fit && pd.q[2] != 0 && pd.nM <= MAXM && sizeof(double) * size_t(pd.tile_lds) <= size_t(pd.lds_max);
 }
 
 struct PrecCompDev {

@@ -56,6 +56,7 @@ struct fm_problem {
     fm_problem_desc desc;
     int nM = 0, M0 = 0;
     int variant = 1;                         // preconditioner: 1 block-Jacobi in M', 2 coupled
+    double mode_fit_tol = FM_DEFAULT_MODE_FIT_TOL;   // coupled: z modes fitting g_l^{M'} within this
     int exchange = 0;                        // +-1: component 2 (index 1) is implied by component 1 (index 0);
                                              // 3: components 2 and 3 are implied by component 1
     bool absent(int a) const { return exchange != 0 && (a == 1 || (exchange == 3 && a == 2)); }
@@ -112,10 +113,11 @@ std::string upload(fm_problem *p, const HostFactors &hf);
 std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingHost &ch);
 // coupled preconditioner (coupled.cpp)
 double assoc_g(int l, int M, double z);
-std::string order_and_scale_z(const Basis1D &bz, int Mp, std::vector<double> &Wb, std::vector<double> &W,
-                              std::vector<double> &lre);
+std::string order_and_scale_z(const Basis1D &bz, int Mp, double fit_tol, std::vector<double> &Wb,
+                              std::vector<double> &W, std::vector<double> &lre, std::vector<char> &resolved);
 std::string coupled_slots(const fm_problem *p, int nz, const std::vector<std::vector<double>> &Wbz,
-                          const std::vector<std::vector<double>> &Wz, std::vector<double> &Zj,
+                          const std::vector<std::vector<double>> &Wz, const std::vector<std::vector<double>> &lz,
+                          const std::vector<std::vector<char>> &resolved, std::vector<double> &Zj,
                           std::vector<double> &cx, std::vector<double> &cy);
 void set_error(const std::string &msg);
 // Serialises the library's own allocations, frees, stream creation and

@@ -560,6 +560,154 @@ __global__ void __launch_bounds__(256) k_local_tiled(const ProblemDev *__restric
     for (int iM = 0; iM < NM; ++iM) y[(long long)iM * C.npts] = out[iM] + c0[(long long)iM * C.npts] + c1[(long long)iM * C.npts];
 }
 
+// Operator without the coupling for more M' blocks (n_M > 3, runtime count):
+// the tiling and staging of k_local_tiled, the blocks taken one after another.
+// Block M''s output needs block M'+1's value and z derivative and block
+// M'-1's z derivative (the M'+-1 terms), so it is completed and stored one
+// block late: three blocks' sums are held at a time, whatever n_M.
+template <int QX, int QY, int QZ>
+__global__ void __launch_bounds__(256) k_local_many(const ProblemDev *__restrict__ pd, const double *__restrict__ Evec,
+                                                     const int *__restrict__ active, const double *__restrict__ X,
+                                                     double *__restrict__ Y, const double *__restrict__ cbuf) {
+    constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    extern __shared__ double sm[];
+    int t = xcd_tile(blockIdx.x, gridDim.x), a = 0;
+    while (a < 3 && t >= pd->comp[a].ntiles) { t -= pd->comp[a].ntiles; ++a; }
+    if (a >= 3) return;
+    const CompDev &C = pd->comp[a];
+    const int ny = C.y.n, xt = C.xt;
+    const int ntx = (C.x.n + xt - 1) / xt;
+    const int iz = t / ntx, ix0 = (t % ntx) * xt;
+    const int nxt = min(xt, C.x.n - ix0);
+    const int kxlo = C.x.first[ix0], kxhi = C.x.last[ix0 + nxt - 1];
+    const int plane_n = (kxhi - kxlo + 1) * ny;
+    double *pl = sm;     // the three planes interleaved: pl[3 e + c]
+    const bool has = threadIdx.x < nxt * ny;
+    const int ixl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
+    const int ix = ix0 + ixl;
+    const double *x = X + (long long)req * pd->N;
+    const double E = Evec[req];
+    const double zc = C.z.pts[iz], xc = C.x.pts[ix], yc = C.y.pts[iy];
+
+    int lx[RX], ly[RY];
+    double Sx[RX], D2x[RX], Sy[RY], D2y[RY];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+        const int g = C.x.idx[ix * MAXR + s];
+        lx[s] = 3 * (g >= 0 ? g - kxlo : 0) * ny;
+        Sx[s] = C.x.S[ix * MAXR + s];
+        D2x[s] = C.x.D2[ix * MAXR + s];
+    }
+#pragma unroll
+    for (int s = 0; s < RY; ++s) {
+        const int g = C.y.idx[iy * MAXR + s];
+        ly[s] = 3 * (g >= 0 ? g : 0);
+        Sy[s] = C.y.S[iy * MAXR + s];
+        D2y[s] = C.y.D2[iy * MAXR + s];
+    }
+    __shared__ long long zoff[RZ];
+    __shared__ double zw[3 * RZ];
+    if (threadIdx.x < RZ) {
+        typedef const __attribute__((address_space(1))) int gint;
+        typedef const __attribute__((address_space(1))) double gdouble;
+        const int a1 = threadIdx.x, zi = iz * MAXR + a1;
+        const int g = ((gint *)C.z.idx)[zi];
+        const double zs = ((gdouble *)C.z.S)[zi], zd1 = ((gdouble *)C.z.D1)[zi], zd2 = ((gdouble *)C.z.D2)[zi];
+        zoff[a1] = (long long)(g >= 0 ? g : 0) * C.nxy;
+        zw[a1] = zs;
+        zw[RZ + a1] = zd1;
+        zw[2 * RZ + a1] = zd2;
+    }
+    const long long p = (long long)iz * C.nxy + ix * ny + iy;
+    const double P = has ? C.P[p] : 0.0;
+    const double iy2 = 1.0 / (yc * yc), inv2 = 1.0 / (xc * xc) + iy2, omz = 1.0 - zc * zc;
+    const int J = pd->J, M0 = pd->M0, nM = pd->nM;
+    const double *c0 = cbuf + (long long)req * 2 * pd->N + C.off + p, *c1 = c0 + pd->N;
+    double *y = Y + (long long)req * pd->N + C.off + p;
+    // sums of the previous block (its output is stored this step) and the z
+    // derivative of the one before
+    double pu = 0, puz = 0, puzz = 0, puxx = 0, puyy = 0, ppuz = 0;
+    for (int iM = 0; iM <= nM; ++iM) {
+        double s0 = 0, s1 = 0, s2 = 0, sxx = 0, syy = 0;
+        if (iM < nM) {          // the same for every thread: the barriers are uniform
+            __syncthreads();
+            {
+                long long zo[RZ];
+                double w0[RZ], w1[RZ], w2[RZ];
+#pragma unroll
+                for (int a1 = 0; a1 < RZ; ++a1) {
+                    zo[a1] = zoff[a1];
+                    w0[a1] = zw[a1];
+                    w1[a1] = zw[RZ + a1];
+                    w2[a1] = zw[2 * RZ + a1];
+                }
+                constexpr int PU = RZ <= 4 ? 2 : 1;
+                const double *xb = x + C.off + (long long)iM * C.npts + (long long)kxlo * ny;
+                for (int e0 = threadIdx.x; e0 < plane_n; e0 += 256 * PU) {
+                    double v[PU][RZ];
+#pragma unroll
+                    for (int u = 0; u < PU; ++u) {
+                        const int e = e0 + 256 * u;
+#pragma unroll
+                        for (int a1 = 0; a1 < RZ; ++a1) v[u][a1] = e < plane_n ? xb[zo[a1] + e] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < PU; ++u) {
+                        const int e = e0 + 256 * u;
+                        if (e < plane_n) {
+                            double q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+                            for (int a1 = 0; a1 < RZ; ++a1) {
+                                q0 += w0[a1] * v[u][a1];
+                                q1 += w1[a1] * v[u][a1];
+                                q2 += w2[a1] * v[u][a1];
+                            }
+                            pl[3 * e] = q0;
+                            pl[3 * e + 1] = q1;
+                            pl[3 * e + 2] = q2;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a2 = 0; a2 < RX; ++a2) {
+                int ro = lx[a2];
+                asm volatile("" : "+v"(ro));
+                double t00 = 0, t02 = 0, t10 = 0, t20 = 0;
+#pragma unroll
+                for (int a3 = 0; a3 < RY; ++a3) {
+                    const double *v = pl + ro + ly[a3];
+                    t00 += Sy[a3] * v[0];
+                    t02 += D2y[a3] * v[0];
+                    t10 += Sy[a3] * v[1];
+                    t20 += Sy[a3] * v[2];
+                }
+                s0 += Sx[a2] * t00;
+                s1 += Sx[a2] * t10;
+                s2 += Sx[a2] * t20;
+                sxx += D2x[a2] * t00;
+                syy += Sx[a2] * t02;
+                asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(sxx), "+v"(syy) : : "memory");
+            }
+        }
+        if (iM > 0 && has) {
+            // block iM - 1, with block iM's sums (zero past the last block)
+            const int jM = iM - 1, Mp = M0 + jM;
+            double o = -puyy - puxx - inv2 * (omz * puzz - 2.0 * (Mp + 1) * zc * puz - double(Mp) * (Mp + 1) * pu) +
+                       ((double(J) * (J + 1) - 2.0 * Mp * Mp) * iy2 + P - E) * pu;
+            if (iM < nM) o += pd->lhp[jM] * iy2 * (-omz * s1 + 2.0 * (Mp + 1) * zc * s0);
+            if (jM > 0) o += pd->lhm[jM] * iy2 * ppuz;
+            const long long q = (long long)jM * C.npts;
+            y[q] = o + c0[q] + c1[q];
+        }
+        ppuz = puz;
+        pu = s0; puz = s1; puzz = s2; puxx = sxx; puyy = syy;
+    }
+}
+
 // Hermite values at s in [0, 1] of the 2Q functions of one cell of width h,
 // r = h / hbar (each function carries (h/hbar)^k of its derivative order k).
 template <int Q>
@@ -766,6 +914,137 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
                 }
         }
         req = nxt;
+    }
+}
+
+// Coupling term for more M'' blocks (n_M > 3, runtime count up to MAXM): one
+// wave per (beta, cell) task, one pair per lane.  For each request the wave
+// stages one M'' block of the cell's coefficients at a time in LDS (the next
+// block, or the next running request's first, is fetched into registers while
+// the current one is evaluated), evaluates beta's expansion of that block at
+// every lane's image by the separable sum, and adds it times the pair's factor
+// column of that block to the lane's n_M outputs.  The factors (n_M x n_M per
+// pair, column by column) are read from memory for each request.
+template <int QXY, int QZ>
+__global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_many(const ProblemDev *__restrict__ pd,
+                                                                  const int *__restrict__ active, int nb,
+                                                                  const double *__restrict__ X,
+                                                                  double *__restrict__ cbuf) {
+    constexpr int RXY = 2 * QXY, RZ = 2 * QZ, TS = RZ * RXY * RXY;
+    constexpr int EPL = (TS + 63) / 64;
+    __shared__ __align__(16) double tile[CPL_WAVES][TS];
+    __shared__ int fidx[CPL_WAVES][RZ + 2 * RXY];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const CouplingDev &cp = pd->cpl;
+    const int nblk = gridDim.x, xcd = blockIdx.x % 8, per = (nblk + 7) / 8;
+    const int full = nblk % 8 == 0 ? 8 : nblk % 8;
+    const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
+    const int job = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
+    if (job >= cp.njobs) return;                       // the whole wave (no block barriers)
+    const int task = __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job]);
+    const int *t = cp.task + (size_t)task * CPL_TASK;
+    const int count = t[CT_COUNT];
+    const long long first = t[CT_FIRST];
+    const int bnx = t[CT_NX], bny = t[CT_NY], bnpts = t[CT_NPTS];
+    const long long boff = (long long)(((unsigned long long)(unsigned)t[CT_OFF_HI] << 32) | (unsigned)t[CT_OFF_LO]);
+    if (lane < RZ + 2 * RXY) fidx[wave][lane] = t[CT_FIDX + lane];
+    const int nM = pd->nM;
+    const long long np = cp.npairs;
+    const long long pr = first + lane;
+    const bool mine = lane < count;
+    double vz[RZ], vx[RXY], vy[RXY];
+    int outp = 0, slot = 0, npa = 0;
+    if (mine) {
+        hermite_cell<QZ>(cp.s[pr], cp.r[3 * (size_t)task], vz);
+        hermite_cell<QXY>(cp.s[np + pr], cp.r[3 * (size_t)task + 1], vx);
+        hermite_cell<QXY>(cp.s[2 * np + pr], cp.r[3 * (size_t)task + 2], vy);
+        const int o = cp.out[pr];
+        outp = o >> 1;
+        slot = o & 1;
+        const int a = outp >= pd->comp[2].off ? 2 : (outp >= pd->comp[1].off ? 1 : 0);
+        npa = pd->comp[a].npts;
+    } else {
+#pragma unroll
+        for (int u = 0; u < RZ; ++u) vz[u] = 0.0;
+#pragma unroll
+        for (int u = 0; u < RXY; ++u) vx[u] = vy[u] = 0.0;
+    }
+    const long long N = pd->N;
+    const int r0 = blockIdx.y * CPL_REQ, r1 = min(nb, r0 + CPL_REQ);
+    int goff[EPL];
+    wave_sync();                                       // fidx written
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+        const int e = lane + 64 * q;
+        goff[q] = -1;
+        if (e < TS) {
+            const int c = e / (RXY * RXY), a = (e / RXY) % RXY, bq = e % RXY;
+            const int gz = fidx[wave][c], gx = fidx[wave][RZ + a], gy = fidx[wave][RZ + RXY + bq];
+            if (gz >= 0 && gx >= 0 && gy >= 0) goff[q] = (gz * bnx + gx) * bny + gy;
+        }
+    }
+    auto next_active = [&](int r) {
+        while (r < r1 && active && !active[r]) ++r;
+        return r;
+    };
+    double pf[EPL];
+    auto fetch = [&](int r, int jM) {
+        const double *x = X + (long long)r * N + boff + (long long)jM * bnpts;
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) pf[q] = goff[q] >= 0 ? x[goff[q]] : 0.0;
+    };
+    int req = next_active(r0);
+    if (req >= r1) return;
+    fetch(req, 0);
+    double o[MAXM];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) o[i] = 0.0;
+    int jM = 0;
+    while (req < r1) {
+        // the block after this one: the next M'' block, or the next running request's first
+        const int njM = jM + 1 < nM ? jM + 1 : 0;
+        const int nreq = jM + 1 < nM ? req : next_active(req + 1);
+        wave_sync();                                   // the previous tile is read
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) {
+            const int e = lane + 64 * q;
+            if (e < TS) tile[wave][e] = pf[q];
+        }
+        wave_sync();                                   // this tile is written
+        if (nreq < r1) fetch(nreq, njM);
+        if (mine) {
+            // the pair's factor column of this block, loaded before the contraction
+            double f[MAXM];
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) f[i] = i < nM ? cp.F[(size_t)(i * nM + jM) * np + pr] : 0.0;
+            const double *T = tile[wave];
+            double acc = 0;
+#pragma unroll
+            for (int c = 0; c < RZ; ++c) {
+                double accx = 0;
+#pragma unroll
+                for (int a = 0; a < RXY; ++a) {
+                    const double *row = T + (c * RXY + a) * RXY;
+                    double accy = 0;
+#pragma unroll
+                    for (int bq = 0; bq < RXY; ++bq) accy += vy[bq] * row[bq];
+                    accx += vx[a] * accy;
+                }
+                acc += vz[c] * accx;
+            }
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) o[i] += f[i] * acc;
+            if (jM + 1 == nM) {
+                double *y = cbuf + ((long long)req * 2 + slot) * N + outp;
+#pragma unroll
+                for (int i = 0; i < MAXM; ++i)
+                    if (i < nM) y[(long long)i * npa] = o[i];
+#pragma unroll
+                for (int i = 0; i < MAXM; ++i) o[i] = 0.0;
+            }
+        }
+        req = nreq;
+        jM = njM;
     }
 }
 
@@ -2658,8 +2937,32 @@ void launch_tiled(const ProblemDev &pd, int nb, const double *E_dev, const int *
     }
 }
 
+// More M' blocks (n_M > 3): the coupling and local kernels that take the
+// blocks one at a time.
+template <int QXY, int QZ>
+void launch_many(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
+                 double *cbuf, hipStream_t st, int part) {
+    if (part != 1 && pd.cpl.njobs > 0) {
+        dim3 grid(cdiv(pd.cpl.njobs, CPL_WAVES), cdiv(nb, CPL_REQ));
+        hipLaunchKernelGGL((k_coupling_many<QXY, QZ>), grid, dim3(64 * CPL_WAVES), 0, st, pd.dev, active, nb, x, cbuf);
+    }
+    if (part != 2) {
+        const unsigned tiles = (pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles + 7) & ~7u;
+        hipLaunchKernelGGL((k_local_many<QXY, QXY, QZ>), dim3(tiles, nb), dim3(256), sizeof(double) * pd.plane_lds, st,
+                           pd.dev, E_dev, active, x, y, cbuf);
+    }
+}
+
 void launch_matvec(const ProblemDev &pd, int nb, const double *E_dev, const int *active, const double *x, double *y,
                    double *cbuf, hipStream_t st, int part) {
+    if (matvec_tiled_ok(pd) && pd.nM > 3) {
+        switch ((pd.q[0] == 3 ? 2 : 0) + (pd.q[2] == 3 ? 1 : 0)) {
+            case 3: launch_many<3, 3>(pd, nb, E_dev, active, x, y, cbuf, st, part); return;
+            case 2: launch_many<3, 2>(pd, nb, E_dev, active, x, y, cbuf, st, part); return;
+            case 1: launch_many<2, 3>(pd, nb, E_dev, active, x, y, cbuf, st, part); return;
+            default: launch_many<2, 2>(pd, nb, E_dev, active, x, y, cbuf, st, part); return;
+        }
+    }
     if (matvec_tiled_ok(pd)) {
         const int key = (pd.q[0] == 3 ? 4 : 0) + (pd.q[2] == 3 ? 2 : 0);
         switch (key * 4 + pd.nM) {
@@ -3029,7 +3332,9 @@ void prepare_operator_lds(size_t bytes) {
         reinterpret_cast<const void *>(k_local_tiled<3, 3, 3, 2>), reinterpret_cast<const void *>(k_local_tiled<3, 3, 3, 3>),
         reinterpret_cast<const void *>(k_local_tiled<3, 3, 2, 2>), reinterpret_cast<const void *>(k_local_tiled<3, 3, 2, 3>),
         reinterpret_cast<const void *>(k_local_tiled<2, 2, 3, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 3, 3>),
-        reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 3>)};
+        reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 3>),
+        reinterpret_cast<const void *>(k_local_many<3, 3, 3>), reinterpret_cast<const void *>(k_local_many<3, 3, 2>),
+        reinterpret_cast<const void *>(k_local_many<2, 2, 3>), reinterpret_cast<const void *>(k_local_many<2, 2, 2>)};
     for (const void *f : fs) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 

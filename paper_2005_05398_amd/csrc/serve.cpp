@@ -57,6 +57,8 @@ std::string desc_key(const fm_problem_desc &d) {
     put(&pv, sizeof pv);
     put(&d.exchange, sizeof d.exchange);
     put(&d.zhalf, sizeof d.zhalf);
+    const double tol = d.precond == FM_PREC_COUPLED ? (d.mode_fit_tol > 0 ? d.mode_fit_tol : FM_DEFAULT_MODE_FIT_TOL) : 0.0;
+    put(&tol, sizeof tol);
     return k;
 }
 

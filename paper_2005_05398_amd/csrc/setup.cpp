@@ -72,6 +72,8 @@ std::string setup_problem(fm_problem *p) {
     if (d.precond != 0 && d.precond != FM_PREC_BLOCK_JACOBI && d.precond != FM_PREC_COUPLED)
         return "precond must be FM_PREC_BLOCK_JACOBI or FM_PREC_COUPLED";
     p->variant = d.precond == FM_PREC_COUPLED ? 2 : 1;
+    if (!std::isfinite(d.mode_fit_tol)) return "mode_fit_tol must be finite";
+    p->mode_fit_tol = d.mode_fit_tol > 0 ? d.mode_fit_tol : FM_DEFAULT_MODE_FIT_TOL;
     if (d.exchange != 0 && d.exchange != 1 && d.exchange != -1 && d.exchange != 3)
         return "exchange must be 0, +1, -1 or 3";
     p->exchange = d.exchange;
@@ -215,7 +217,8 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
         std::vector<double> Sy = by.dense(0), D2y = by.dense(2);
         // per slot: x pencil coefficient of X_r2 S_x, y pencil coefficient of Y_r2 S_y
         std::vector<double> cx(size_t(nM) * nz), cy(size_t(nM) * nz);
-        std::vector<std::vector<double>> zWb(nM), zW(nM);
+        std::vector<std::vector<double>> zWb(nM), zW(nM), zl(nM);
+        std::vector<std::vector<char>> zres(nM);
         for (int iM = 0; iM < nM; ++iM) {
             int Mp = p->M0 + iM;
             std::vector<double> A1(size_t(nz) * nz);
@@ -235,8 +238,9 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
                 if (ty[i] != 0) return "z pencil has complex eigenvalues";
             hf.max_err = std::max(hf.max_err, e);
             if (p->variant == 2) {
-                r = order_and_scale_z(bz, Mp, Wb, W, lre);
+                r = order_and_scale_z(bz, Mp, p->mode_fit_tol, Wb, W, lre, zres[iM]);
                 if (!r.empty()) return "z pencil: " + r;
+                zl[iM] = lre;
             }
             std::copy(Wb.begin(), Wb.end(), hc.Wz.begin() + size_t(iM) * 2 * nz * nz);
             std::copy(W.begin(), W.end(), hc.Wz.begin() + size_t(iM) * 2 * nz * nz + size_t(nz) * nz);
@@ -249,7 +253,7 @@ std::string build_factors(fm_problem *p, HostFactors &hf) {
             zW[iM].swap(W);
         }
         if (p->variant == 2) {
-            std::string r = coupled_slots(p, nz, zWb, zW, hc.Zj, cx, cy);
+            std::string r = coupled_slots(p, nz, zWb, zW, zl, zres, hc.Zj, cx, cy);
             if (!r.empty()) return r;
         }
         std::vector<double> Vx(nx), Vh(ny);

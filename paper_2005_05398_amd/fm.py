@@ -31,7 +31,7 @@ class FmDesc(ctypes.Structure):
                 ("tau", ctypes.c_int), ("x", FmDim * 3), ("y", FmDim * 3), ("z", FmDim * 3),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("nu", ctypes.c_double),
                 ("vhat", ctypes.c_int), ("device", ctypes.c_int), ("precond", ctypes.c_int),
-                ("exchange", ctypes.c_int), ("zhalf", ctypes.c_int)]
+                ("exchange", ctypes.c_int), ("zhalf", ctypes.c_int), ("mode_fit_tol", ctypes.c_double)]
 
 
 class FmSolveOpts(ctypes.Structure):
@@ -127,6 +127,7 @@ def make_c_desc(desc, device=0):
     d.precond = PRECONDS[desc.get("precond", "block_jacobi")]
     d.exchange = int(desc.get("exchange", 0))
     d.zhalf = int(desc.get("zhalf", 0))
+    d.mode_fit_tol = float(desc.get("mode_fit_tol", 0.0))
     return d
 
 

@@ -4,7 +4,8 @@
   16 requests per block row, so requests 16-31 and 32-34 of a 35-request
   batch run in its second and third row, and a 12-request batch leaves most
   of one row empty.  Every request is compared elementwise with the oracle's
-  assembled matrix (small grids; all spline-order variants of the kernel).
+  assembled matrix (small grids; all spline-order variants of the kernel, and
+  the kernel for more than three M' blocks).
 * Sampled rows of every request of a 34-request batch at the energy scan's
   full size (the bench's kernel variants: quintic 64 x 64 x 24).
 * The 32-energy scan itself, solved as the bench solves it (one batch,
@@ -45,6 +46,8 @@ BATCH_CASES = [
     ("cubic_xy_quintic_z_10x6", W.make_desc(*W.PS_MINUS, 10, 6, deg_xy=3, R=15.0)),
     ("cubic_10x6", W.make_desc(*W.PS_MINUS, 10, 6, deg_xy=3, deg_z=3, R=15.0)),
     ("L2_quintic_cubicz", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0)),
+    # six M' blocks: the coupling kernel that takes the blocks one at a time
+    ("L5_quintic_cubicz", W.make_desc(*W.PS_MINUS, 7, 4, J=5, tau=1, deg_z=3, R=15.0)),
 ]
 
 

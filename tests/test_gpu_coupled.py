@@ -40,6 +40,14 @@ CASES = [
     ("quintic_xy_cubic_z_L2_31x31x16", W.make_desc(*W.PS_MINUS, 31, 16, J=2, tau=1, deg_xy=5, deg_z=3, R=20.0)),
     # eleven M' blocks (the helium runs of the paper's high-J table have J = 10)
     ("cubic_L10_8x8x4", W.make_desc(*W.H_MINUS, 8, 4, J=10, tau=1, deg_xy=3, deg_z=3, R=15.0)),
+    # three quintic z intervals: the highest z modes do not fit g_l^{M'} and
+    # keep the block-Jacobi treatment (default tolerance; the paper's matrix
+    # with every mode; a looser tolerance)
+    ("quintic_z12_L3", W.make_desc(*W.PS_MINUS, 7, 12, J=3, tau=1, deg_xy=5, deg_z=5, R=20.0)),
+    ("quintic_z12_L3_every_mode", dict(W.make_desc(*W.PS_MINUS, 7, 12, J=3, tau=1, deg_xy=5, deg_z=5, R=20.0),
+                                       mode_fit_tol=2.0)),
+    ("quintic_z12_L5_tol0.3", dict(W.make_desc(*W.H_MINUS, 7, 12, J=5, tau=1, deg_xy=5, deg_z=5, R=15.0),
+                                   mode_fit_tol=0.3)),
 ]
 
 

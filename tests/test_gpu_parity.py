@@ -60,9 +60,16 @@ OP_CASES = [
     # finite y0 of the cut-off (eq. (Mcutoff0)): V^(s) and the potential field depend on y
     ("hminus_finite_y0", dict(small(W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"), y0=6.0)),
     ("L2_finite_y0", dict(small(W.PS_MINUS, 7, 4, J=2, tau=1, dz=3), y0=2.5)),
-    # more than three M' blocks: the generic operator kernel (up to 16 blocks)
-    ("L5_tau+1_generic", small(W.PS_MINUS, 7, 4, J=5, tau=1, dz=3)),
-    ("L10_tau+1_generic", small(W.H_MINUS, 7, 4, J=10, tau=1, dz=3)),
+    # more than three M' blocks (up to 16): the kernels that take the blocks one
+    # at a time, every spline-order variant
+    ("L5_tau+1", small(W.PS_MINUS, 7, 4, J=5, tau=1, dz=3)),
+    ("L10_tau+1", small(W.H_MINUS, 7, 4, J=10, tau=1, dz=3)),
+    ("L4_tau-1_quintic", small(W.H_MINUS, 7, 6, J=4, tau=-1, dz=5)),
+    ("L5_cubic_xy_quintic_z", small(W.PS_MINUS, 10, 6, J=5, tau=1, dxy=3, dz=5)),
+    ("L6_cubic", small(W.PS_MINUS, 10, 4, J=6, tau=1, dxy=3, dz=3)),
+    # ... and the generic kernel (x and y of different spline orders)
+    ("L5_generic_mixed_xy", dict(small(W.PS_MINUS, 7, 4, J=5, tau=1, dz=3),
+                                 y=small(W.PS_MINUS, 10, 4, J=5, tau=1, dxy=3, dz=3)["y"])),
 ] + WIDE_CASES
 
 

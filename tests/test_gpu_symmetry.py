@@ -36,6 +36,9 @@ CASES = [
     ("hminus_L0_p-1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), -1),
     ("helium_L2_p+1", W.make_desc(*HE, 7, 4, J=2, deg_z=3, R=15.0, x0=1.0), 1),
     ("hminus_L1_odd_p-1", W.make_desc(*W.H_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0), -1),
+    # more than three M' blocks (the operator kernels that take them one at a time)
+    ("helium_L5_p+1", W.make_desc(*HE, 7, 4, J=5, deg_z=3, R=15.0, x0=1.0), 1),
+    ("helium_L4_odd_p-1", W.make_desc(*HE, 7, 4, J=4, tau=-1, deg_z=3, R=15.0, x0=1.0), -1),
 ]
 
 
@@ -120,6 +123,7 @@ THREE_CASES = [
     ("three_L0_quintic", W.make_desc((1.0, 1.0, 1.0), (-1.0, -1.0, -1.0), 10, 6, R=15.0, x0=3.0)),
     ("three_L1_cubicz", W.make_desc((1.0, 1.0, 1.0), (1.0, 1.0, 1.0), 7, 4, J=1, deg_z=3, R=12.0, x0=3.0)),
     ("three_L2_cubicz", W.make_desc((2.0, 2.0, 2.0), (-1.0, -1.0, -1.0), 7, 4, J=2, deg_z=3, R=12.0, x0=3.0)),
+    ("three_L4_cubicz", W.make_desc((2.0, 2.0, 2.0), (-1.0, -1.0, -1.0), 7, 4, J=4, deg_z=3, R=12.0, x0=3.0)),
 ]
 
 

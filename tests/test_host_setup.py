@@ -124,6 +124,9 @@ COUPLING_CASES = [
     # finite y0 of the cut-off (eq. (Mcutoff0)): V^(s) depends on y as well
     ("quintic_hminus_L0_y0", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic", y0=6.0)),
     ("quintic_L2_y0", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0, y0=3.0)),
+    # more than three M' blocks: n_M x n_M factors per pair
+    ("quintic_cubicz_L5", W.make_desc(*W.PS_MINUS, 7, 4, J=5, deg_z=3, R=15.0)),
+    ("quintic_L4_odd", W.make_desc(*W.H_MINUS, 7, 6, J=4, tau=-1, deg_z=5, R=15.0)),
 ]
 
 
@@ -146,6 +149,12 @@ PREC_SETUP_CASES = [
     ("cubic_J1_one_interval", dict(J=1, tau=1, deg_xy=3, deg_z=3, nxy=6, nz=4)),
     ("cubic_J0", dict(J=0, tau=1, deg_xy=3, deg_z=3, nxy=8, nz=8)),
     ("quintic_xy_cubic_z_J2", dict(J=2, tau=1, deg_xy=5, deg_z=3, nxy=13, nz=8)),
+    # three quintic z intervals: the highest z modes do not fit their g_l^{M'}
+    # and keep the block-Jacobi treatment (default tolerance, a tighter one,
+    # and every mode: the paper's matrix as printed)
+    ("quintic_z12_J3", dict(J=3, tau=1, deg_xy=3, deg_z=5, nxy=6, nz=12)),
+    ("quintic_z12_J3_tol0.05", dict(J=3, tau=1, deg_xy=3, deg_z=5, nxy=6, nz=12, mode_fit_tol=0.05)),
+    ("quintic_z12_J3_every_mode", dict(J=3, tau=1, deg_xy=3, deg_z=5, nxy=6, nz=12, mode_fit_tol=2.0)),
 ]
 
 
@@ -160,8 +169,8 @@ def test_host_precond_factors_match_oracle(name, kw, variant):
     from oracle.precond_v2 import precond_v2_reference
     from oracle.solve import precond_reference
     kw = dict(kw)
-    nxy, nz = kw.pop("nxy"), kw.pop("nz")
-    desc = W.make_desc(*W.PS_MINUS, nxy, nz, R=20.0, **kw)
+    nxy, nz, tol = kw.pop("nxy"), kw.pop("nz"), kw.pop("mode_fit_tol", 0.0)
+    desc = dict(W.make_desc(*W.PS_MINUS, nxy, nz, R=20.0, **kw), mode_fit_tol=tol)
     P = Problem(desc)
     E = -0.25
     r = W.rhs(5, P.N)
@@ -190,6 +199,9 @@ EXCHANGE_CASES = [
     ("hminus_L0_p-1", W.make_desc(*W.H_MINUS, 13, 6, R=40.0, xy_map="quadratic"), -1),
     ("helium_L2_p+1", W.make_desc((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0), 7, 4, J=2, deg_z=3, R=15.0, x0=1.0), 1),
     ("hminus_L1_odd_p-1", W.make_desc(*W.H_MINUS, 7, 6, J=1, tau=-1, deg_z=5, R=15.0), -1),
+    ("helium_L5_p+1", W.make_desc((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0), 7, 4, J=5, deg_z=3, R=15.0, x0=1.0), 1),
+    ("helium_L4_odd_p-1", W.make_desc((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0), 7, 4, J=4, tau=-1, deg_z=3, R=15.0, x0=1.0),
+     -1),
 ]
 
 
@@ -222,6 +234,7 @@ THREE_CASES = [
     ("three_L0_quintic", W.make_desc((1.0, 1.0, 1.0), (-1.0, -1.0, -1.0), 10, 6, R=15.0, x0=3.0)),
     ("three_L1_cubicz", W.make_desc((1.0, 1.0, 1.0), (1.0, 1.0, 1.0), 7, 4, J=1, deg_z=3, R=12.0, x0=3.0)),
     ("three_L2_cubicz", W.make_desc((2.0, 2.0, 2.0), (-1.0, -1.0, -1.0), 7, 4, J=2, deg_z=3, R=12.0, x0=3.0)),
+    ("three_L4_cubicz", W.make_desc((2.0, 2.0, 2.0), (-1.0, -1.0, -1.0), 7, 4, J=4, deg_z=3, R=12.0, x0=3.0)),
 ]
 
 
