@@ -129,6 +129,21 @@ def eigs_bench(args):
     print(json.dumps(line))
 
 
+def calibration_copy():
+    """One plain device copy of COPY_BYTES and one pure read of the same bytes,
+    the reference dispatches for scaling the HBM counters of a counter run."""
+    import torch
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    total = float(src.sum())
+    torch.cuda.synchronize()
+    assert total == float(src.numel())
+    del src, dst
+
+
 def eigs_j10_bench(args):
     """Helium at J = 10 (tau = +1, eleven M' blocks) by shift-invert Arnoldi on
     the basis sets of the paper's Table 3 (Sec. 4, the high-J runs; domains
@@ -652,6 +667,8 @@ def main():
     if args.serve:
         serve_bench(args)
         return
+    if args.calibrate_copy:
+        calibration_copy()
     if args.eigs:
         eigs_bench(args)
         return
@@ -683,17 +700,6 @@ def main():
     X = torch.zeros_like(B)
     stream = torch.cuda.current_stream()
 
-    if args.calibrate_copy:
-        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        # a second calibration of the read counter: a pure read of the same bytes
-        total = float(src.sum())
-        torch.cuda.synchronize()
-        assert total == float(src.numel())
-        del src, dst
     head = measure(P, Es, B, X, args.restart, args.prec, args.steps, args.warmup, stream,
                    traffic_key=traffic_variant(args), graphs=bool(args.graphs))
     if args.graphs:
