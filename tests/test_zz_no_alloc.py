@@ -59,3 +59,16 @@ def test_noalloc_operator_rejects_batches_beyond_its_scratch(device):
     rng = np.random.default_rng(2)
     Es = list(np.linspace(-0.6, -0.1, cap))
     assert _compare(P, Es, rng.standard_normal((cap, P.N)), device) <= 1e-11
+
+
+def test_noalloc_operator_many_blocks(device):
+    """Six M' blocks (the operator kernels that take the blocks one at a time),
+    then a one-block problem, then the six-block one again with a smaller batch."""
+    from paper_2005_05398_amd import fm
+    rng = np.random.default_rng(9)
+    many = fm.Problem(W.make_desc(*W.PS_MINUS, 7, 4, J=5, tau=1, deg_z=3, R=15.0))
+    Es = [-0.4, -0.2, 0.1]
+    assert _compare(many, Es, rng.standard_normal((3, many.N)), device) <= 1e-11
+    one = fm.Problem(W.make_desc(*W.PS_MINUS, 7, 6, R=15.0))
+    assert _compare(one, [-0.25], rng.standard_normal((1, one.N)), device) <= 1e-11
+    assert _compare(many, Es[:1], rng.standard_normal((1, many.N)), device) <= 1e-11
