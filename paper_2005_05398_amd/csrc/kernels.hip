@@ -1170,6 +1170,24 @@ __global__ void __launch_bounds__(MZ2_THREADS) k_modez_reg(const ProblemDev *__r
     }
 }
 
+// The smallest |denominator| the block met (each thread's v), into *dst by
+// one atomic per block on the bit pattern (nonnegative doubles order as their
+// bits), skipped unless the block lowers the stored value (which only falls).
+// Every thread of the block calls it; one barrier (a wave minimum by
+// shuffles, then one LDS slot per wave).
+__device__ __forceinline__ void block_min_store(double v, double *dst) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    __shared__ double wmin[16];
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmin[0];
+        for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = fmin(m, wmin[w]);
+        if (m < __builtin_nontemporal_load(dst))
+            atomicMin((unsigned long long *)dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Preconditioner, per (request, alpha, M', k) slice T (nx x ny):
 //   T <- Wbar_x T Wbar_y^T;  solve (Lambda_x (x) I + I (x) Lambda_y - E) T' = T;
@@ -1216,18 +1234,7 @@ __device__ void block_divide(double *T, int ld, int nx, int ny, const double *lx
             mind = fmin(mind, sqrt(fmin(Dp, Dm)));
         }
     }
-    if (min_den) {
-        // block minimum, then one atomic per block on the bit pattern (positive doubles)
-        __shared__ double red[512];
-        red[threadIdx.x] = mind;
-        __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0)
-            atomicMin((unsigned long long *)min_den, (unsigned long long)__double_as_longlong(red[0]));
-    }
+    if (min_den) block_min_store(mind, min_den);
     __syncthreads();
 }
 
@@ -1458,9 +1465,8 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     const double E = DIV ? Evec[req] : 0.0;
     const double E2 = DIVOUT ? Evec[req] : 0.0;
     double mind = 1e300;
-    // the operand tiles, one buffer: DIVOUT reuses it for the output tile
+    // the operand tiles, one buffer
     __shared__ double sg_buf[BT * (SG_KC + 1) + SG_KC * (BT + 1)];
-    static_assert(BT * (SG_KC + 1) + SG_KC * (BT + 1) >= BT * (BT + 1), "output tile fits the operand tiles");
     double (*As)[SG_KC + 1] = reinterpret_cast<double (*)[SG_KC + 1]>(sg_buf);              // [row][k]
     double (*Bs)[BT + 1] = reinterpret_cast<double (*)[BT + 1]>(sg_buf + BT * (SG_KC + 1));   // [k][col]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1568,26 +1574,16 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
         if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = rbe;
     };
-    // DIVOUT: the eigenvalues and types of this lane's output rows and columns,
-    // requested now so that they arrive during the products (a type of 1 marks
-    // a row or column outside the slice, which is not divided)
-    // (rows through LDS, written here and read after the products: the first
-    // barrier of the chunk loop orders them)
+    // DIVOUT: the eigenvalues and types of the tile's rows, requested now so
+    // that they arrive during the products (a type of 1 marks a row outside
+    // the slice, which is not divided); through LDS, written here and read
+    // after the products (the first barrier of the chunk loop orders them)
     __shared__ double dv_sl[DIVOUT ? BT : 1];
     __shared__ int dv_st[DIVOUT ? BT : 1];
-    double dv_c = 0.0;                     // the thread's output column in the epilogue: threadIdx.x % BT
-    int dv_ct = 1;
-    if (DIVOUT) {
-        if (threadIdx.x < BT) {
-            const int row = i0 + (int)threadIdx.x;
-            dv_sl[threadIdx.x] = row < nx ? F.lx[fx * nx + row] : 0.0;
-            dv_st[threadIdx.x] = row < nx ? F.tx[fx * nx + row] : 1;
-        }
-        const int col = j0 + (int)threadIdx.x % BT;
-        if (col < ny) {
-            dv_c = F.ly[fx * ny + col];
-            dv_ct = F.ty[fx * ny + col];
-        }
+    if (DIVOUT && threadIdx.x < BT) {
+        const int row = i0 + (int)threadIdx.x;
+        dv_sl[threadIdx.x] = row < nx ? F.lx[fx * nx + row] : 0.0;
+        dv_st[threadIdx.x] = row < nx ? F.tx[fx * nx + row] : 1;
     }
     // wave (wi, wj) owns the (16 WT) x (16 WT) block at rows 16 WT wi, columns 16 WT wj
     dbl4 acc[WT][WT];
@@ -1637,44 +1633,38 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         mind = fmin(mind, fabs(d));
         return v * rcp_newton(d);
     };
-    if (DIVOUT) {
-        // the tile through LDS (the operand tiles are free after the last
-        // barrier): the accumulators die at once, and each thread then divides
-        // and stores whole rows' worth of one column, coalesced
-        // (rows padded to BT + 1: the four rows a wave writes at once fall in
-        // different banks)
-        double *ot = sg_buf;
+    {
+        // stores straight from the accumulators; DIVOUT divides on the way, with
+        // the rows' eigenvalues from LDS and the lane's columns' read here
+        double cl[WT];
+        int ct[WT];
 #pragma unroll
-        for (int ti = 0; ti < WT; ++ti)
-#pragma unroll
-            for (int tj = 0; tj < WT; ++tj)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    ot[(16 * (WT * wi + ti) + k4 + 4 * v) * (BT + 1) + 16 * (WT * wj + tj) + r16] = acc[ti][tj][v];
-        __syncthreads();
-        const int c = (int)threadIdx.x % BT, col = j0 + c;
-#pragma unroll 2
-        for (int r = (int)threadIdx.x / BT; r < BT; r += 256 / BT) {
-            const int row = i0 + r;
-            if (row < nx && col < ny) {
-                double val = ot[r * (BT + 1) + c];
-                if ((dv_st[r] | dv_ct) == 0) {
-                    const double d = dv_sl[r] + dv_c - E2;
-                    mind = fmin(mind, fabs(d));
-                    val *= rcp_newton(d);
-                }
-                o[(size_t)row * ny + col] = val;
+        for (int tj = 0; tj < WT; ++tj) {
+            const int col = j0 + 16 * (WT * wj + tj) + r16;
+            cl[tj] = 0.0;
+            ct[tj] = 1;
+            if (DIVOUT && col < ny) {
+                cl[tj] = F.ly[fx * ny + col];
+                ct[tj] = F.ty[fx * ny + col];
             }
         }
-    } else {
 #pragma unroll
         for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
             for (int tj = 0; tj < WT; ++tj)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int row = i0 + 16 * (WT * wi + ti) + k4 + 4 * v, col = j0 + 16 * (WT * wj + tj) + r16;
-                    if (row < nx && col < ny) o[(size_t)row * ny + col] = acc[ti][tj][v];
+                    const int rl = 16 * (WT * wi + ti) + k4 + 4 * v;
+                    const int row = i0 + rl, col = j0 + 16 * (WT * wj + tj) + r16;
+                    if (row < nx && col < ny) {
+                        double val = acc[ti][tj][v];
+                        if (DIVOUT && (dv_st[rl] | ct[tj]) == 0) {
+                            const double d = dv_sl[rl] + cl[tj] - E2;
+                            mind = fmin(mind, fabs(d));
+                            val *= rcp_newton(d);
+                        }
+                        o[(size_t)row * ny + col] = val;
+                    }
                 }
     }
     if (erow || ecol) {
@@ -1684,20 +1674,7 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
             o[(size_t)(i0 + tx - BT) * ny + ny - 1] = divout(i0 + tx - BT, ny - 1, ext);
         else if (erow && ecol && tx == 2 * BT) o[(size_t)(nx - 1) * ny + ny - 1] = divout(nx - 1, ny - 1, ext);
     }
-    if ((DIV || DIVOUT) && min_den) {
-        // block minimum, then one atomic per block on the bit pattern (positive doubles)
-        __shared__ double red[256];
-        red[threadIdx.x] = mind;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-            __syncthreads();
-        }
-        // the minimum rarely changes after the first application: skip the atomic
-        // (all blocks of a request hit one address) unless this block lowers it
-        if (threadIdx.x == 0 && red[0] < __builtin_nontemporal_load(min_den + req))
-            atomicMin((unsigned long long *)(min_den + req), (unsigned long long)__double_as_longlong(red[0]));
-    }
+    if ((DIV || DIVOUT) && min_den) block_min_store(mind, min_den + req);
 }
 
 
@@ -1779,17 +1756,7 @@ __global__ void __launch_bounds__(256) k_divide_pairs(const ProblemDev *__restri
         T[o + 1] = (TD)((b * r0 + d * r1) / det);
         mind = fmin(mind, sqrt(det));
     }
-    if (min_den) {
-        __shared__ double red[256];
-        red[threadIdx.x] = mind;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0 && red[0] < min_den[req])
-            atomicMin((unsigned long long *)(min_den + req), (unsigned long long)__double_as_longlong(red[0]));
-    }
+    if (min_den) block_min_store(mind, min_den + req);
 }
 
 // ---------------------------------------------------------------------------
@@ -3599,17 +3566,7 @@ __global__ void __launch_bounds__(256) k_cdivide(const ProblemDev *__restrict__ 
             }
         }
     }
-    if (min_den) {
-        __shared__ double red[256];
-        red[threadIdx.x] = mind;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0)
-            atomicMin((unsigned long long *)(min_den + c), (unsigned long long)__double_as_longlong(red[0]));
-    }
+    if (min_den) block_min_store(mind, min_den + c);
 }
 
 // y_re += E_im (S x)_im, y_im -= E_im (S x)_re for every complex request:

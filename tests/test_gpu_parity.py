@@ -327,3 +327,31 @@ def test_precond_after_operator_grows_its_buffer(device):
     P.apply_precond([-0.3], to_dev(r[None, :], device), z2)
     ref = precond_reference(O, -0.3, r)
     assert np.abs(z2.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nb", [1, 24])
+def test_solve_reports_the_smallest_denominator(device, nb):
+    """min_abs_denominator of a solve is the smallest |lambda_x + lambda_y - E|
+    over every slice of the preconditioner (eq. (prec-2)); on a cubic grid
+    every pencil eigenvalue is real.  One request runs the staged x-y products
+    (divide on the store of the right product), 24 requests (576 slices) the
+    one-block-per-slice kernel.  The host side is the library's own slice
+    eigenvalues (fm_host_slice_eigenvalues) with the same FP64 sum, so the two
+    agree exactly."""
+    import torch
+    fm = _fm()
+    desc = W.ps_cubic16()["desc"]
+    P = fm.Problem(desc)
+    E = -0.3141
+    want = np.inf
+    for a in range(3):
+        for slot in range(desc["z"][a]["n"]):
+            lx, lxi, ly, lyi = fm.host_slice_eigenvalues(desc, a, slot)
+            assert not lxi.any() and not lyi.any()
+            want = min(want, np.abs((lx[:, None] + ly[None, :]) - E).min())
+    b = torch.as_tensor(W.rhs_batch([31 + i for i in range(nb)], P.N), device=device)
+    x = torch.zeros_like(b)
+    st, res = P.solve([E] * nb, b, x, restart=30, rtol=1e-10, max_iters=400)
+    assert st == fm.FM_OK
+    for r in res:
+        assert r["min_abs_denominator"] == want, (r["min_abs_denominator"], want)
