@@ -248,6 +248,17 @@ struct Work {
                                        2.0 * nM * nM);
         }
     }
+    // a complex request: two real rows (both parts), every operation's work twice
+    // (the E_i S term of its operator is not counted)
+    Work &rows(int r) {
+        N *= r;
+        pts *= r;
+        xyflops *= r;
+        zflops *= r;
+        localflops *= r;
+        coupflops *= r;
+        return *this;
+    }
     double matvec() const { return 8 * (2 * N + pts); }
     double coupling() const { return 8 * 3 * N; }
     double modez() const { return 8 * 2 * N; }
@@ -334,7 +345,7 @@ void apply_operator_complex(fm_problem *p, int nbc, const double *E2, const doub
                             hipStream_t st) {
     apply_operator(p, 2 * nbc, E2, mask2, x, y, cbuf, st);
     timed(p, st, FM_K_MATVEC, [&] {
-        launch_mass(p->pd, 2 * nbc, x, tmp, st);
+        launch_mass(p->pd, 2 * nbc, x, tmp, st, mask2);
         launch_cplx_energy(y, tmp, Eim, active, nbc, p->N, st);
     });
 }
@@ -572,7 +583,7 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
         if (cplx) {
             launch_expand_mask(running, mask2, cap, st);
             launch_matvec(p->pd, 2 * cap, E2, mask2, X, K.V, cbuf, st);
-            launch_mass(p->pd, 2 * cap, X, ptmp, st);
+            launch_mass(p->pd, 2 * cap, X, ptmp, st, mask2);
             launch_cplx_energy(K.V, ptmp, Eim, running, cap, p->N, st);
         } else {
             launch_matvec(p->pd, cap, K.E, running, X, K.V, cbuf, st);
@@ -583,6 +594,7 @@ fm_status Batch::boundary(const std::vector<int> &joining, int x0_is_guess) {
     HIP_TRY(hipGetLastError());
     if (any_cont) {
         Work w(p);
+        w.rows(cplx ? 2 : 1);
         for (int s = 0; s < cap; ++s)
             if (hcont[s]) prof_work(p, FM_K_RESTART, 8.0 * (last_steps[s] + 2) * w.N + w.matvec() + 8 * 5 * w.N, 0);
     }
@@ -643,6 +655,7 @@ fm_status Batch::cycle(const std::function<bool()> &want_cut, int min_steps) {
     HIP_TRY(hipStreamSynchronize(st));
     prof_collect(p);
     Work w(p);
+    w.rows(cplx ? 2 : 1);
     for (int i = 0; i < nb; ++i)
         if (run[i]) {
             const int jc = hbuf[i];

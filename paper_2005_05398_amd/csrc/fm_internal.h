@@ -261,8 +261,10 @@ void launch_xupdate(const KrylovDev &k, const int *running, double *x, hipStream
 void launch_residual(const KrylovDev &k, int *running, const double *b, double rtol, double inner_safety,
                      hipStream_t st);
 void launch_scale0(const KrylovDev &k, hipStream_t st);
-// y = S x (the mass matrix of H c = E S c) for nb requests
-void launch_mass(const ProblemDev &pd, int nb, const double *x, double *y, hipStream_t st);
+// y = S x (the mass matrix of H c = E S c) for nb requests; active (may be
+// null): the requests to compute (the others' rows of y are left as they are)
+void launch_mass(const ProblemDev &pd, int nb, const double *x, double *y, hipStream_t st,
+                 const int *active = nullptr);
 // Column kernels of the eigenvalue iteration (columns of length N stored one after another):
 // out[c] = V_c . w (part: cols_dot_blocks(N) * ncol doubles of scratch); w -= V h (h on the
 // device); out_c = sum_j V_j Y[j k + c] (Y on the device, row-major m x k; out must not

@@ -3292,6 +3292,10 @@ void prepare_large_lds(size_t bytes) {
     for (const void *f : lp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
+template <int QX, int QY, int QZ>
+__global__ void __launch_bounds__(256) k_mass_tiled(const ProblemDev *__restrict__ pd, const int *__restrict__ active,
+                                                     const double *__restrict__ X, double *__restrict__ Y);
+
 void prepare_operator_lds(size_t bytes) {
     const void *fs[] = {
         reinterpret_cast<const void *>(k_local_grouped<3, 3, 3>), reinterpret_cast<const void *>(k_local_grouped<3, 3, 2>),
@@ -3301,7 +3305,9 @@ void prepare_operator_lds(size_t bytes) {
         reinterpret_cast<const void *>(k_local_tiled<2, 2, 3, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 3, 3>),
         reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 2>), reinterpret_cast<const void *>(k_local_tiled<2, 2, 2, 3>),
         reinterpret_cast<const void *>(k_local_many<3, 3, 3>), reinterpret_cast<const void *>(k_local_many<3, 3, 2>),
-        reinterpret_cast<const void *>(k_local_many<2, 2, 3>), reinterpret_cast<const void *>(k_local_many<2, 2, 2>)};
+        reinterpret_cast<const void *>(k_local_many<2, 2, 3>), reinterpret_cast<const void *>(k_local_many<2, 2, 2>),
+        reinterpret_cast<const void *>(k_mass_tiled<3, 3, 3>), reinterpret_cast<const void *>(k_mass_tiled<3, 3, 2>),
+        reinterpret_cast<const void *>(k_mass_tiled<2, 2, 3>), reinterpret_cast<const void *>(k_mass_tiled<2, 2, 2>)};
     for (const void *f : fs) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
@@ -3324,10 +3330,12 @@ void launch_copy(double *dst, const double *src, long long n, hipStream_t st) {
 // Mass matrix S (Sec. 3.1: the basis products at the collocation points, the
 // right-hand matrix of H c = E S c): y = (S_z (x) S_x (x) S_y) x for every
 // component and M' block.  One point per thread, all M' blocks; grid
-// (points / 256, requests).
-__global__ void __launch_bounds__(256) k_mass(const ProblemDev *__restrict__ pd, const double *__restrict__ X,
-                                              double *__restrict__ Y) {
+// (points / 256, requests).  For grids that the operator's tiled kernels do
+// not cover (k_mass_tiled below for the others).
+__global__ void __launch_bounds__(256) k_mass(const ProblemDev *__restrict__ pd, const int *__restrict__ active,
+                                              const double *__restrict__ X, double *__restrict__ Y) {
     const int req = blockIdx.y;
+    if (active && !active[req]) return;
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int a = 0;
     while (a < 3 && p >= pd->comp[a].npts) {
@@ -3374,11 +3382,97 @@ __global__ void __launch_bounds__(256) k_mass(const ProblemDev *__restrict__ pd,
     }
 }
 
-void launch_mass(const ProblemDev &pd, int nb, const double *x, double *y, hipStream_t st) {
+// The same product on the tiling of the operator's local kernels (a block per
+// z point and run of x points, XCD-aware tile order): each M' block's
+// coefficients are contracted with the block's z row of S as they are read
+// into LDS (one plane over the run's x support x all y), then with each
+// point's x and y rows (dropped functions carry the value 0).  active (may be
+// null): the rows of the batch to compute.
+template <int QX, int QY, int QZ>
+__global__ void __launch_bounds__(256) k_mass_tiled(const ProblemDev *__restrict__ pd, const int *__restrict__ active,
+                                                     const double *__restrict__ X, double *__restrict__ Y) {
+    constexpr int RX = 2 * QX, RY = 2 * QY, RZ = 2 * QZ;
+    const int req = blockIdx.y;
+    if (active && !active[req]) return;
+    extern __shared__ double sm[];
+    int t = xcd_tile(blockIdx.x, gridDim.x), a = 0;
+    while (a < 3 && t >= pd->comp[a].ntiles) { t -= pd->comp[a].ntiles; ++a; }
+    if (a >= 3) return;
+    const CompDev &C = pd->comp[a];
+    const int ny = C.y.n, xt = C.xt;
+    const int ntx = (C.x.n + xt - 1) / xt;
+    const int iz = t / ntx, ix0 = (t % ntx) * xt;
+    const int nxt = min(xt, C.x.n - ix0);
+    const int kxlo = C.x.first[ix0], kxhi = C.x.last[ix0 + nxt - 1];
+    const int plane_n = (kxhi - kxlo + 1) * ny;
+    const bool has = threadIdx.x < nxt * ny;
+    const int ixl = has ? threadIdx.x / ny : 0, iy = has ? threadIdx.x % ny : 0;
+    const int ix = ix0 + ixl;
+    int lx[RX], ly[RY];
+    double Sx[RX], Sy[RY], wz[RZ];
+    long long zo[RZ];
+#pragma unroll
+    for (int q = 0; q < RX; ++q) {
+        const int g = C.x.idx[ix * MAXR + q];
+        lx[q] = (g >= 0 ? g - kxlo : 0) * ny;
+        Sx[q] = C.x.S[ix * MAXR + q];
+    }
+#pragma unroll
+    for (int q = 0; q < RY; ++q) {
+        const int g = C.y.idx[iy * MAXR + q];
+        ly[q] = g >= 0 ? g : 0;
+        Sy[q] = C.y.S[iy * MAXR + q];
+    }
+#pragma unroll
+    for (int q = 0; q < RZ; ++q) {
+        const int g = C.z.idx[iz * MAXR + q];
+        zo[q] = (long long)(g >= 0 ? g : 0) * C.nxy;
+        wz[q] = C.z.S[iz * MAXR + q];
+    }
+    const long long p = (long long)iz * C.nxy + ix * ny + iy;
+    const double *xr = X + (long long)req * pd->N + C.off + (long long)kxlo * ny;
+    double *yr = Y + (long long)req * pd->N + C.off + p;
+    const int nM = pd->nM;
+    for (int iM = 0; iM < nM; ++iM) {
+        __syncthreads();                     // the previous block's plane is read
+        const double *xb = xr + (long long)iM * C.npts;
+        for (int e = threadIdx.x; e < plane_n; e += 256) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < RZ; ++q) v += wz[q] * xb[zo[q] + e];
+            sm[e] = v;
+        }
+        __syncthreads();
+        if (has) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q2 = 0; q2 < RX; ++q2) {
+                double ty = 0.0;
+#pragma unroll
+                for (int q3 = 0; q3 < RY; ++q3) ty += Sy[q3] * sm[lx[q2] + ly[q3]];
+                sum += Sx[q2] * ty;
+            }
+            yr[(long long)iM * C.npts] = sum;
+        }
+    }
+}
+
+void launch_mass(const ProblemDev &pd, int nb, const double *x, double *y, hipStream_t st, const int *active) {
+    if (matvec_tiled_ok(pd)) {
+        const unsigned tiles = (pd.comp[0].ntiles + pd.comp[1].ntiles + pd.comp[2].ntiles + 7) & ~7u;
+        const size_t lds = sizeof(double) * size_t(pd.plane_lds / 3 + 1);
+        dim3 grid(tiles, nb);
+        switch ((pd.q[0] == 3 ? 2 : 0) + (pd.q[2] == 3 ? 1 : 0)) {
+            case 3: hipLaunchKernelGGL((k_mass_tiled<3, 3, 3>), grid, dim3(256), lds, st, pd.dev, active, x, y); return;
+            case 2: hipLaunchKernelGGL((k_mass_tiled<3, 3, 2>), grid, dim3(256), lds, st, pd.dev, active, x, y); return;
+            case 1: hipLaunchKernelGGL((k_mass_tiled<2, 2, 3>), grid, dim3(256), lds, st, pd.dev, active, x, y); return;
+            default: hipLaunchKernelGGL((k_mass_tiled<2, 2, 2>), grid, dim3(256), lds, st, pd.dev, active, x, y); return;
+        }
+    }
     long long pts = 0;
     for (int a = 0; a < 3; ++a) pts += pd.comp[a].npts;
     dim3 grid(cdiv(pts, 256), nb);
-    hipLaunchKernelGGL(k_mass, grid, dim3(256), 0, st, pd.dev, x, y);
+    hipLaunchKernelGGL(k_mass, grid, dim3(256), 0, st, pd.dev, active, x, y);
 }
 
 // ---------------------------------------------------------------------------

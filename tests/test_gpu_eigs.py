@@ -37,6 +37,12 @@ MASS_CASES = [
     ("quintic_L2_7x7x4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_xy=5, deg_z=3, R=15.0)),
     ("hminus_mixed_grids", dict(W.make_desc(*W.H_MINUS, 10, 9, R=30.0, xy_map="quadratic"),
                                 y=W.make_desc(*W.H_MINUS, 13, 9, R=25.0)["y"])),
+    # the tiled kernel's other spline orders, more M' blocks, a wide y side
+    ("quintic_7x7x6", W.make_desc(*W.PS_MINUS, 7, 6, R=15.0)),
+    ("cubic_xy_quintic_z_10x6", W.make_desc(*W.PS_MINUS, 10, 6, deg_xy=3, R=15.0)),
+    ("cubic_L5_10x4", W.make_desc(*W.PS_MINUS, 10, 4, J=5, tau=1, deg_xy=3, deg_z=3, R=15.0)),
+    ("wide_x10_y229", dict(W.make_desc(*W.PS_MINUS, 10, 6, deg_xy=5, deg_z=5, R=20.0),
+                           y=W.make_desc(*W.PS_MINUS, 229, 6, deg_xy=5, deg_z=5, R=20.0)["y"])),
 ]
 
 
@@ -45,14 +51,33 @@ def test_mass_parity(device, name, desc):
     fm = _fm()
     P = fm.Problem(desc)
     O = OracleProblem(desc)
-    X = np.random.default_rng(2).standard_normal((2, O.N))
-    Y = to_dev(np.zeros((2, O.N)), device)
+    X = np.random.default_rng(2).standard_normal((3, O.N))
+    Y = to_dev(np.zeros((3, O.N)), device)
     P.apply_mass(to_dev(X, device), Y)
     S = mass_matrix(O)
     Yg = Y.cpu().numpy()
-    for r in range(2):
+    for r in range(3):
         ref = S @ X[r]
         assert np.abs(Yg[r] - ref).max() <= 1e-12 * np.abs(ref).max(), (name, r)
+
+
+@pytest.mark.parametrize("J,tau,p", [(0, 1, 1), (4, -1, -1)])
+def test_mass_parity_exchange_reduced(device, J, tau, p):
+    """S on the exchange-reduced system (components 1 and 3) against the
+    oracle's R S E."""
+    from oracle.symmetry import reduced_mass
+    fm = _fm()
+    desc = W.make_desc((1.0, 1.0, 1e15), (-1.0, -1.0, 2.0), 7, 4, J=J, tau=tau, deg_z=3, R=15.0, x0=1.0)
+    P = fm.Problem(dict(desc, exchange=p))
+    O = OracleProblem(desc)
+    S = reduced_mass(O, p)
+    X = np.random.default_rng(3).standard_normal((2, P.N))
+    Y = to_dev(np.zeros((2, P.N)), device)
+    P.apply_mass(to_dev(X, device), Y)
+    Yg = Y.cpu().numpy()
+    for r in range(2):
+        ref = S @ X[r]
+        assert np.abs(Yg[r] - ref).max() <= 1e-12 * np.abs(ref).max(), r
 
 
 EIG_CASES = [
