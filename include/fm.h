@@ -84,7 +84,7 @@ typedef enum { FM_PREC_BLOCK_JACOBI = 1, FM_PREC_COUPLED = 2 } fm_prec_variant;
 typedef struct {
     double mass[3];
     double charge[3];
-    int J;
+    int J;                    /* total orbital momentum, 0 <= J <= 15 (n_M = J - M0 + 1 <= 16 blocks) */
     int tau;                  /* +1 or -1 */
     fm_dim x[3], y[3], z[3];  /* per component alpha */
     double x0, y0, nu;

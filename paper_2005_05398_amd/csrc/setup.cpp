@@ -58,11 +58,11 @@ void wigner_poly(int J, int M, int Mp, std::vector<double> &f) {
 std::string setup_problem(fm_problem *p) {
     const fm_problem_desc &d = p->desc;
     if (d.tau != 1 && d.tau != -1) return "tau must be +1 or -1";
-    if (d.J < 0) return "J must be >= 0";
+    if (d.J < 0 || d.J > MAXM - 1) return "J must be between 0 and 15 (at most 16 M' blocks)";
     p->M0 = (1 - d.tau) / 2;
     p->nM = d.J - p->M0 + 1;
     if (p->nM < 1) return "no M' blocks for this J, tau";
-    if (p->nM > MAXM) return "J too large (at most 16 M' blocks)";
+    if (p->nM > MAXM) return "too many M' blocks";
     for (int a = 0; a < 3; ++a) {
         if (!(d.mass[a] > 0) || !std::isfinite(d.mass[a])) return "masses must be positive";
         if (!std::isfinite(d.charge[a])) return "charges must be finite";

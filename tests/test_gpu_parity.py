@@ -64,6 +64,7 @@ OP_CASES = [
     # at a time, every spline-order variant
     ("L5_tau+1", small(W.PS_MINUS, 7, 4, J=5, tau=1, dz=3)),
     ("L10_tau+1", small(W.H_MINUS, 7, 4, J=10, tau=1, dz=3)),
+    ("L15_tau+1_most_blocks", small(W.PS_MINUS, 7, 4, J=15, tau=1, dz=3)),
     ("L4_tau-1_quintic", small(W.H_MINUS, 7, 6, J=4, tau=-1, dz=5)),
     ("L5_cubic_xy_quintic_z", small(W.PS_MINUS, 10, 6, J=5, tau=1, dxy=3, dz=5)),
     ("L6_cubic", small(W.PS_MINUS, 10, 4, J=6, tau=1, dxy=3, dz=3)),

@@ -331,3 +331,15 @@ def test_halved_z_rejects_unsupported_problems():
         fm.host_setup_check(dict(d, exchange=1, zhalf=1))
     with pytest.raises(fm.FmError):
         fm.host_setup_check(dict(W.make_desc(*W.H_MINUS, 7, 9, R=15.0), zhalf=1))   # no exchange symmetry
+
+
+@lib_built
+def test_block_count_limit():
+    """J up to 15 (16 M' blocks at tau = +1, 15 at tau = -1) is set up; a
+    larger J is rejected with FM_E_INVALID before any work."""
+    assert fm.host_setup_check(W.make_desc(*W.PS_MINUS, 7, 4, J=15, tau=1, deg_z=3, R=15.0))[2] == 16 * 3 * 7 * 7 * 4
+    assert fm.host_setup_check(W.make_desc(*W.PS_MINUS, 7, 4, J=15, tau=-1, deg_z=3, R=15.0))[2] == 15 * 3 * 7 * 7 * 4
+    for J, tau in ((16, 1), (16, -1)):
+        with pytest.raises(fm.FmError) as e:
+            fm.host_setup_check(W.make_desc(*W.PS_MINUS, 7, 4, J=J, tau=tau, deg_z=3, R=15.0))
+        assert e.value.status == fm.FM_E_INVALID
