@@ -144,28 +144,15 @@ def calibration_copy():
     del src, dst
 
 
-def eigs_j10_bench(args):
-    """Helium at J = 10 (tau = +1, eleven M' blocks) by shift-invert Arnoldi on
-    the basis sets of the paper's Table 3 (Sec. 4, the high-J runs; domains
-    (1: 280, 280; 3: 2, 2)), electron-exchange parity p = +1 (the paper's
-    printed system sizes), coupled preconditioner; the same with the
-    block-Jacobi one, and the first basis set unreduced (each level then
-    appears for both parities)."""
-    import torch
+PAPER_TABLE3_IRAM_MIN = (6.3, 33.0, 60.0, 280.0)     # the paper's IRAM wall time per basis set, minutes
+
+
+def j10_runs(runs, stream, echo=True):
+    """fm_eigs on helium J = 10 for each (basis 1, basis 3, printed energies,
+    preconditioner, exchange) of runs; one result row each."""
     from paper_2005_05398_amd import fm
     from paper_2005_05398_amd import workloads as W
-    torch.zeros(1, device="cuda:0")
-    stream = torch.cuda.current_stream()
     rows = []
-    t_all = time.perf_counter()
-    # the paper's systems: electron-exchange parity p = +1 (its printed sizes),
-    # coupled preconditioner; then the block-Jacobi one, and the first basis
-    # set unreduced (both parities)
-    runs = [(g1, g3, printed, "coupled", 1) for g1, g3, printed in W.HE_TABLE3_J10]
-    runs += [(g1, g3, printed, "block_jacobi", 1) for g1, g3, printed in W.HE_TABLE3_J10]
-    runs += [(*W.HE_TABLE3_J10[0], "coupled", 0)]
-    if args.j10_runs:
-        runs = [runs[int(i)] for i in args.j10_runs.split(",")]
     for g1, g3, printed, pc, ex in runs:
         desc = dict(W.helium_desc(g1, g3, dom1=W.HE_TABLE3_DOMAINS[0], dom3=W.HE_TABLE3_DOMAINS[1], J=10, tau=1),
                     precond=pc, exchange=ex)
@@ -183,9 +170,54 @@ def eigs_j10_bench(args):
                      "status": fm.STATUS_NAMES.get(st), "energies": Es, "E_ground": got[0], "E_first_excited": got[1],
                      "paper_printed": printed, "diff_vs_printed": [a - b for a, b in zip(got, printed)],
                      "setup_s": t_setup, "eigs_s": t_eig, "info": info, "max_ritz_residual": max(res)})
-        print(f"eigs-j10: grid {g1}/{g3} {pc} exchange {ex} N={P.N}: {['%.6f' % e for e in Es]} in {t_eig:.1f} s "
-              f"({info['solves']} solves, {info['inner_iters']} inner steps)", file=sys.stderr, flush=True)
+        if echo:
+            print(f"eigs-j10: grid {g1}/{g3} {pc} exchange {ex} N={P.N}: {['%.6f' % e for e in Es]} in {t_eig:.1f} s "
+                  f"({info['solves']} solves, {info['inner_iters']} inner steps)", file=sys.stderr, flush=True)
         P.close()
+    return rows
+
+
+def j10_table3_entry():
+    """The default bench's sub-object: the four basis sets of the paper's
+    Table 3 (p = +1, coupled preconditioner), each energy pair against the
+    printed one and the eigs time beside the paper's IRAM wall time."""
+    import torch
+    from paper_2005_05398_amd import workloads as W
+    rows = j10_runs([(g1, g3, pr, "coupled", 1) for g1, g3, pr in W.HE_TABLE3_J10], torch.cuda.current_stream(),
+                    echo=False)
+    out = {"config": "helium J=10 tau=+1 p=+1 (the paper's Table 3 systems, Sec. 4), shift-invert Arnoldi at "
+                     "sigma=-2.0045, nev=6, ncv=24, coupled preconditioner, inner FGMRES(200) to 1e-10",
+           "rows": [{"basis": f"{r['grid']['1']}/{r['grid']['3']}", "N": r["N"], "status": r["status"],
+                     "E": [r["E_ground"], r["E_first_excited"]], "printed": list(r["paper_printed"]),
+                     "max_abs_diff": max(abs(d) for d in r["diff_vs_printed"]), "eigs_s": r["eigs_s"],
+                     "paper_iram_min": PAPER_TABLE3_IRAM_MIN[i], "inner_steps": r["info"]["inner_iters"]}
+                    for i, r in enumerate(rows)],
+           "eigs_s_total": sum(r["eigs_s"] for r in rows)}
+    print(f"bench: helium J=10 Table 3: {out['eigs_s_total']:.2f} s for the four basis sets", file=sys.stderr,
+          flush=True)
+    return out
+
+
+def eigs_j10_bench(args):
+    """Helium at J = 10 (tau = +1, eleven M' blocks) by shift-invert Arnoldi on
+    the basis sets of the paper's Table 3 (Sec. 4, the high-J runs; domains
+    (1: 280, 280; 3: 2, 2)), electron-exchange parity p = +1 (the paper's
+    printed system sizes), coupled preconditioner; the same with the
+    block-Jacobi one, and the first basis set unreduced (each level then
+    appears for both parities)."""
+    import torch
+    from paper_2005_05398_amd import workloads as W
+    torch.zeros(1, device="cuda:0")
+    t_all = time.perf_counter()
+    # the paper's systems: electron-exchange parity p = +1 (its printed sizes),
+    # coupled preconditioner; then the block-Jacobi one, and the first basis
+    # set unreduced (both parities)
+    runs = [(g1, g3, printed, "coupled", 1) for g1, g3, printed in W.HE_TABLE3_J10]
+    runs += [(g1, g3, printed, "block_jacobi", 1) for g1, g3, printed in W.HE_TABLE3_J10]
+    runs += [(*W.HE_TABLE3_J10[0], "coupled", 0)]
+    if args.j10_runs:
+        runs = [runs[int(i)] for i in args.j10_runs.split(",")]
+    rows = j10_runs(runs, torch.cuda.current_stream())
     line = {"metric": "helium J=10 energies by shift-invert Arnoldi (basis sets of the paper's Table 3, Sec. 4)",
             "value": sum(r["eigs_s"] for r in rows if r["precond"] == "coupled" and r["exchange"] == 1),
             "unit": "s (the basis sets run, coupled preconditioner, p = +1)", "n_gpus": 1,
@@ -772,6 +804,8 @@ def main():
             l2[pc] = workload_entry("ps_l2_q97", args, ("fp64", "fp32"), precond=pc, traffic=True)
         cfgs["ps_l2_q97"] = l2
         cfgs["hminus_scan_complex"] = complex_entry(args)
+        torch.cuda.empty_cache()
+        cfgs["helium_j10_table3"] = j10_table3_entry()
         torch.cuda.empty_cache()
         if args.serve_sample > 0:
             sv = serve_run(args, args.serve_sample, (args.serve_rate,))
