@@ -58,6 +58,32 @@ def rel_residuals_by_rows(prob, Es, X, B, chunk=16384, progress=None):
     return np.sqrt(ss) / np.linalg.norm(B, axis=1)
 
 
+def rel_residuals_by_rows_complex(prob, Es, X, B, chunk=16384, progress=None):
+    """||b - A(E) x|| / ||b|| for complex energies E (Sec. 3.1 with H and S
+    real) in the residual-only mode: x = x_r + i x_i and b = b_r + i b_i are
+    given as the rows [real part, imaginary part] of X and B (shape
+    (len(Es), 2N)); A(E) x = H x - E S x splits into
+    H x_r - Re E S x_r + Im E S x_i and H x_i - Re E S x_i - Im E S x_r."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    B = np.atleast_2d(np.asarray(B, dtype=np.float64))
+    N = prob.N
+    ss = np.zeros(len(Es))
+    for start in range(0, N, chunk):
+        idx = np.arange(start, min(N, start + chunk))
+        H = prob.rows(0.0, idx)
+        S = H - prob.rows(1.0, idx)
+        for r, E in enumerate(Es):
+            E = complex(E)
+            xr, xi = X[r, :N], X[r, N:]
+            sxr, sxi = S @ xr, S @ xi
+            rr = B[r, idx] - (H @ xr - E.real * sxr + E.imag * sxi)
+            ri = B[r, N + idx] - (H @ xi - E.real * sxi - E.imag * sxr)
+            ss[r] += float(rr @ rr) + float(ri @ ri)
+        if progress is not None:
+            progress(idx[-1] + 1, N)
+    return np.sqrt(ss) / np.linalg.norm(B, axis=1)
+
+
 def complex_matrix(prob, E):
     """A(E) = H - E S for a complex energy E (Sec. 3.1; H, S real): H = A(0),
     S = A(0) - A(1)."""

@@ -11,7 +11,8 @@
 * The 32-energy scan itself, solved as the bench solves it (one batch,
   restart 300, rtol 1e-10): the oracle's residual-only mode (rows of H and of
   A(1) assembled a chunk at a time, no factorisation) gives the true relative
-  residual of requests from both coupling block rows, and it must meet 1e-10.
+  residual of requests from both coupling block rows, and it must meet 1e-10;
+  the same at complex energies E_k + 0.01 i.
 Tolerances: operator outputs elementwise relative to the largest, 1e-11 (FP64
 sums of a few hundred terms); residuals 1e-10 (the metric's target) and the
 GPU's own FP64 residual within 1e-12 of the oracle's.
@@ -22,7 +23,7 @@ import numpy as np
 import pytest
 
 from oracle.assemble import Problem as OracleProblem
-from oracle.solve import rel_residuals_by_rows
+from oracle.solve import rel_residuals_by_rows, rel_residuals_by_rows_complex
 from paper_2005_05398_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -113,6 +114,35 @@ def test_hminus_scan_batch_oracle_residual(device):
         print(f"oracle residual rows {done}/{total}", file=sys.stderr, flush=True)
 
     rel = rel_residuals_by_rows(O, [Es[i] for i in pick], Xg[pick], B[pick], progress=progress)
+    for k, i in enumerate(pick):
+        assert rel[k] <= 1e-10, (i, rel[k], res[i])
+        assert abs(rel[k] - res[i]["rel_residual"]) <= 1e-12, (i, rel[k], res[i])
+
+
+def test_hminus_scan_complex_oracle_residual(device):
+    """The bench's scan at complex energies E_k + 0.01 i (complex seeded
+    right-hand sides, two real rows per request): the oracle's complex
+    residual-only mode gives the true relative residual of requests 3 and 31
+    (the coupling kernel's first and second block rows), which must meet 1e-10
+    and equal the GPU's own FP64 residual."""
+    import torch
+    fm = _fm()
+    c = W.hminus_scan()
+    desc, seeds = c["desc"], c["seeds"]
+    Es = [complex(e, 0.01) for e in c["E"]]
+    P = fm.Problem(desc)
+    B = np.stack([np.concatenate([W.rhs(s, P.N), W.rhs(s + 500, P.N)]) for s in seeds])
+    X = torch.zeros(B.shape, dtype=torch.float64, device=device)
+    st, res = P.solve_complex(Es, to_dev(B, device), X, restart=300, rtol=1e-10, max_iters=20000)
+    assert st == fm.FM_OK, res
+    Xg = X.cpu().numpy()
+    pick = [3, 31]
+    O = OracleProblem(desc)
+
+    def progress(done, total):
+        print(f"oracle complex residual rows {done}/{total}", file=sys.stderr, flush=True)
+
+    rel = rel_residuals_by_rows_complex(O, [Es[i] for i in pick], Xg[pick], B[pick], progress=progress)
     for k, i in enumerate(pick):
         assert rel[k] <= 1e-10, (i, rel[k], res[i])
         assert abs(rel[k] - res[i]["rel_residual"]) <= 1e-12, (i, rel[k], res[i])

@@ -5,6 +5,9 @@
 * The complex LU solution equals the solution of the real block form
   [[A(Re E), Im E S], [-Im E S, A(Re E)]] [c_re; c_im] = [b_re; b_im].
 * Conjugation: (conj E, conj b) gives conj c (H, S real).
+* The residual-only mode for complex energies (rows of H and S a chunk at a
+  time) equals the residual through the assembled complex matrix, across
+  chunk boundaries, and is zero at the LU solution.
 * The complex separable operator of the preconditioner (Sec. 3.2) with the
   potentials off, inverted through the eigenvectors of the generalized
   eigenproblem of (L(0), S_z (x) S_x (x) S_y) (an independent route: the
@@ -16,7 +19,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from oracle.assemble import Problem
-from oracle.solve import complex_matrix, lu_solve, precond_reference_complex
+from oracle.solve import complex_matrix, lu_solve, precond_reference_complex, rel_residuals_by_rows_complex
 from paper_2005_05398_amd import workloads as W
 
 
@@ -73,3 +76,23 @@ def test_complex_separable_inverse_through_eigenvectors():
     z_eig = V @ (np.linalg.solve(V, np.linalg.solve(M, r)) / (lam - E))
     z = precond_reference_complex(O, E, r)
     assert np.linalg.norm(z - z_eig) <= 1e-9 * np.linalg.norm(z)
+
+
+def test_complex_residual_by_rows_matches_assembled_matrix():
+    O = _prob(1)
+    Es = [-0.31 + 0.07j, 0.2 - 0.01j]
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((2, 2 * O.N))
+    Bm = rng.standard_normal((2, 2 * O.N))
+    want = []
+    for r, E in enumerate(Es):
+        x = X[r, :O.N] + 1j * X[r, O.N:]
+        b = Bm[r, :O.N] + 1j * Bm[r, O.N:]
+        want.append(np.linalg.norm(b - complex_matrix(O, E) @ x) / np.linalg.norm(b))
+    got = rel_residuals_by_rows_complex(O, Es, X, Bm, chunk=997)     # chunks end inside blocks
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+    # at the LU solution the residual is at rounding level
+    b = Bm[0, :O.N] + 1j * Bm[0, O.N:]
+    c = lu_solve(complex_matrix(O, Es[0]), b)
+    xs = np.concatenate([c.real, c.imag])[None, :]
+    assert rel_residuals_by_rows_complex(O, Es[:1], xs, Bm[:1], chunk=997)[0] <= 1e-12
