@@ -12,7 +12,8 @@
   restart 300, rtol 1e-10): the oracle's residual-only mode (rows of H and of
   A(1) assembled a chunk at a time, no factorisation) gives the true relative
   residual of requests from both coupling block rows, and it must meet 1e-10;
-  the same at complex energies E_k + 0.01 i.
+  the same at complex energies E_k + 0.01 i, and for the single large request
+  (ps_q127) solved with each precision of the preconditioner products.
 Tolerances: operator outputs elementwise relative to the largest, 1e-11 (FP64
 sums of a few hundred terms); residuals 1e-10 (the metric's target) and the
 GPU's own FP64 residual within 1e-12 of the oracle's.
@@ -146,6 +147,36 @@ def test_hminus_scan_complex_oracle_residual(device):
     for k, i in enumerate(pick):
         assert rel[k] <= 1e-10, (i, rel[k], res[i])
         assert abs(rel[k] - res[i]["rel_residual"]) <= 1e-12, (i, rel[k], res[i])
+
+
+def test_ps_q127_solves_oracle_residual_every_precision(device):
+    """The single large request (quintic 127 x 127 x cubic 32, N = 1 548 288)
+    solved as the bench solves it with FP64, FP32 and BF16x3 preconditioner
+    products: the oracle's residual-only mode gives each solution's true
+    relative residual, which must meet 1e-10 and equal the GPU's own."""
+    import torch
+    fm = _fm()
+    c = W.ps_q127()
+    desc, E = c["desc"], c["E"][0]
+    P = fm.Problem(desc)
+    b = W.rhs(c["seeds"][0], P.N)
+    precs = ("fp64", "fp32", "bf16x3")
+    X, res = [], []
+    for prec in precs:
+        x = torch.zeros((1, P.N), dtype=torch.float64, device=device)
+        st, r = P.solve([E], to_dev(b[None, :], device), x, restart=60, rtol=1e-10, max_iters=2000, prec=prec)
+        assert st == fm.FM_OK, (prec, r)
+        X.append(x.cpu().numpy()[0])
+        res.append(r[0])
+    O = OracleProblem(desc)
+
+    def progress(done, total):
+        print(f"oracle residual rows {done}/{total}", file=sys.stderr, flush=True)
+
+    rel = rel_residuals_by_rows(O, [E] * 3, np.stack(X), np.stack([b] * 3), chunk=65536, progress=progress)
+    for k, prec in enumerate(precs):
+        assert rel[k] <= 1e-10, (prec, rel[k], res[k])
+        assert abs(rel[k] - res[k]["rel_residual"]) <= 1e-12, (prec, rel[k], res[k])
 
 
 def test_batched_solve_masks_running_requests(device):
