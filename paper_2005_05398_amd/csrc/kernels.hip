@@ -2468,22 +2468,41 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     for (int t = 0; t < MD_G; ++t) as[t] = at[t] = 0;
     long long e = lo + threadIdx.x;
     if (ng > 0) {
-        // every vector slot loads (slots past the group repeat its last vector,
-        // whose sums are dropped), so all loads of an iteration are in flight at once
-        const double *qp[MD_G];
+        // U and W of this thread's elements (16 per chunk of the block) in
+        // registers, then the group's vectors streamed one after another: one
+        // basis vector in flight per wave at a time, as in the update pass
+        // (each thread still sums its elements in order)
+        constexpr int EPT = 16;
+        for (long long e0 = lo; e0 < hi; e0 += (long long)RT * EPT) {
+            double u[EPT], w[EPT];
 #pragma unroll
-        for (int t = 0; t < MD_G; ++t) qp[t] = q0 + (long long)min(t, ng - 1) * vstride;
-        for (; e < hi; e += RT) {
-            const double u0 = U[e], w0 = CLOSING ? 0.0 : W[e];
-            uu += u0 * u0;
-            uw += u0 * w0;
-            ww += w0 * w0;
-#pragma unroll
-            for (int t = 0; t < MD_G; ++t) {
-                const double a = __builtin_nontemporal_load(qp[t] + e);
-                as[t] += a * u0;
-                if (!CLOSING) at[t] += a * w0;
+            for (int i = 0; i < EPT; ++i) {
+                const long long ee = e0 + threadIdx.x + (long long)RT * i;
+                u[i] = ee < hi ? U[ee] : 0.0;
+                w[i] = (!CLOSING && ee < hi) ? W[ee] : 0.0;
             }
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) {
+                uu += u[i] * u[i];
+                uw += u[i] * w[i];
+                ww += w[i] * w[i];
+            }
+#pragma unroll
+            for (int t = 0; t < MD_G; ++t)
+                if (t < ng) {
+                    const double *q = q0 + (long long)t * vstride;
+                    double qa[EPT];
+#pragma unroll
+                    for (int i = 0; i < EPT; ++i) {
+                        const long long ee = e0 + threadIdx.x + (long long)RT * i;
+                        qa[i] = ee < hi ? __builtin_nontemporal_load(q + ee) : 0.0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < EPT; ++i) {
+                        as[t] += qa[i] * u[i];
+                        if (!CLOSING) at[t] += qa[i] * w[i];
+                    }
+                }
         }
     } else {
         for (; e < hi; e += RT) {
