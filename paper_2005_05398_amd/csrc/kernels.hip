@@ -2378,6 +2378,9 @@ __global__ void __launch_bounds__(MZ_COLS) k_modez32(const ProblemDev *__restric
 // ---------------------------------------------------------------------------
 // GMRES pieces.  V is stored [i][request][N]; Z likewise.
 constexpr int RT = 256;              // threads of the reduction kernels
+// two doubles as one 16-byte load or store (a clang vector type: the
+// non-temporal builtins take it)
+typedef double dv2 __attribute__((ext_vector_type(2)));
 constexpr int MD_G = 8;              // vectors per group in the multi-dot
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -2470,16 +2473,40 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
     if (ng > 0) {
         // U and W of this thread's elements (16 per chunk of the block) in
         // registers, then the group's vectors streamed one after another: one
-        // basis vector in flight per wave at a time, as in the update pass
-        // (each thread still sums its elements in order)
+        // basis vector in flight per wave at a time, as in the update pass.
+        // With N and the block's chunk even, a thread's elements are pairs of
+        // neighbours read with 16-byte loads; otherwise single elements.
         constexpr int EPT = 16;
+        const long long per = (K.N + gridDim.x - 1) / gridDim.x;
+        const bool pairs = (K.N & 1) == 0 && (per & 1) == 0;
+        // element i of this thread in the chunk starting at e0
+        auto elem = [&](long long e0, int i) {
+            return pairs ? e0 + 2 * (long long)threadIdx.x + 2LL * RT * (i >> 1) + (i & 1)
+                         : e0 + threadIdx.x + (long long)RT * i;
+        };
         for (long long e0 = lo; e0 < hi; e0 += (long long)RT * EPT) {
             double u[EPT], w[EPT];
+            if (pairs) {
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const long long ee = e0 + threadIdx.x + (long long)RT * i;
-                u[i] = ee < hi ? U[ee] : 0.0;
-                w[i] = (!CLOSING && ee < hi) ? W[ee] : 0.0;
+                for (int i = 0; i < EPT; i += 2) {
+                    const long long ee = elem(e0, i);
+                    dv2 a = {0.0, 0.0}, b = {0.0, 0.0};
+                    if (ee < hi) {
+                        a = *reinterpret_cast<const dv2 *>(U + ee);
+                        if (!CLOSING) b = *reinterpret_cast<const dv2 *>(W + ee);
+                    }
+                    u[i] = a.x;
+                    u[i + 1] = a.y;
+                    w[i] = b.x;
+                    w[i + 1] = b.y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < EPT; ++i) {
+                    const long long ee = elem(e0, i);
+                    u[i] = ee < hi ? U[ee] : 0.0;
+                    w[i] = (!CLOSING && ee < hi) ? W[ee] : 0.0;
+                }
             }
 #pragma unroll
             for (int i = 0; i < EPT; ++i) {
@@ -2492,10 +2519,21 @@ __global__ void __launch_bounds__(RT) k_arnoldi_dots(KrylovDev K, int j) {
                 if (t < ng) {
                     const double *q = q0 + (long long)t * vstride;
                     double qa[EPT];
+                    if (pairs) {
 #pragma unroll
-                    for (int i = 0; i < EPT; ++i) {
-                        const long long ee = e0 + threadIdx.x + (long long)RT * i;
-                        qa[i] = ee < hi ? __builtin_nontemporal_load(q + ee) : 0.0;
+                        for (int i = 0; i < EPT; i += 2) {
+                            const long long ee = elem(e0, i);
+                            dv2 a = {0.0, 0.0};
+                            if (ee < hi) a = __builtin_nontemporal_load(reinterpret_cast<const dv2 *>(q + ee));
+                            qa[i] = a.x;
+                            qa[i + 1] = a.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < EPT; ++i) {
+                            const long long ee = elem(e0, i);
+                            qa[i] = ee < hi ? __builtin_nontemporal_load(q + ee) : 0.0;
+                        }
                     }
 #pragma unroll
                     for (int i = 0; i < EPT; ++i) {
@@ -2720,6 +2758,56 @@ __global__ void __launch_bounds__(RT) k_arnoldi_update(KrylovDev K, int j) {
     const double qj = (*U - qs) * inv;
     *U = qj;
     *W = (*W - qt - t[j] * qj) * (1.0 / K.rho[req]);
+}
+
+// Two adjacent elements per thread with 16-byte loads and stores (N even, so
+// that every vector of the basis starts on a 16-byte boundary).
+__global__ void __launch_bounds__(RT) k_arnoldi_update2(KrylovDev K, int j) {
+    const int req = blockIdx.y;
+    if (!K.active[req]) return;
+    extern __shared__ double coef[];
+    double *s = coef, *t = coef + j;
+    const double *hp = K.hproj + (size_t)req * (K.m + 1), *hc = K.hcol + (size_t)req * (K.m + 1);
+    for (int i = threadIdx.x; i < j; i += RT) s[i] = hp[i];
+    for (int i = threadIdx.x; i <= j; i += RT) t[i] = hc[i];
+    __syncthreads();
+    const long long e = 2 * ((long long)blockIdx.x * RT + threadIdx.x);
+    if (e >= K.N) return;
+    const long long vstride = (long long)K.nb * K.N;
+    const dv2 *q = reinterpret_cast<const dv2 *>(K.V + (long long)req * K.N + e);
+    const long long vs2 = vstride / 2;
+    double qs0 = 0, qt0 = 0, qs1 = 0, qt1 = 0;
+    int i = 0;
+    for (; i + 7 < j; i += 8) {
+        dv2 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(q + (i + u) * vs2);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            qs0 += a[u].x * s[i + u];
+            qt0 += a[u].x * t[i + u];
+            qs1 += a[u].y * s[i + u];
+            qt1 += a[u].y * t[i + u];
+        }
+    }
+    for (; i < j; ++i) {
+        const dv2 a = __builtin_nontemporal_load(q + i * vs2);
+        qs0 += a.x * s[i];
+        qt0 += a.x * t[i];
+        qs1 += a.y * s[i];
+        qt1 += a.y * t[i];
+    }
+    dv2 *U = reinterpret_cast<dv2 *>(K.V + (long long)j * vstride + (long long)req * K.N + e);
+    dv2 *W = U + vs2;
+    const double inv = 1.0 / K.scal[req], rinv = 1.0 / K.rho[req];
+    const dv2 u = *U, w = *W;
+    dv2 qj, wn;
+    qj.x = (u.x - qs0) * inv;
+    qj.y = (u.y - qs1) * inv;
+    wn.x = (w.x - qt0 - t[j] * qj.x) * rinv;
+    wn.y = (w.y - qt1 - t[j] * qj.y) * rinv;
+    *U = qj;
+    *W = wn;
 }
 
 // y = R^-1 g for the steps of this cycle, one block per request, by columns:
@@ -3259,6 +3347,11 @@ void launch_arnoldi_finish(const KrylovDev &k, int j, int closing, hipStream_t s
 }
 
 void launch_arnoldi_update(const KrylovDev &k, int j, hipStream_t st) {
+    if (k.N % 2 == 0) {
+        dim3 grid(cdiv(k.N / 2, RT), k.nb);
+        hipLaunchKernelGGL(k_arnoldi_update2, grid, dim3(RT), sizeof(double) * (2 * j + 1), st, k, j);
+        return;
+    }
     dim3 grid(cdiv(k.N, RT), k.nb);
     hipLaunchKernelGGL(k_arnoldi_update, grid, dim3(RT), sizeof(double) * (2 * j + 1), st, k, j);
 }

@@ -212,6 +212,30 @@ def test_solve_ps_cubic16_matches_lu(device):
     assert abs(res[0]["rel_residual"] - rel_residual(A, xg, b)) <= 1e-12
 
 
+@pytest.mark.parametrize("nxy,nz", [(7, 9), (7, 8)])
+def test_solve_odd_and_even_sizes_match_lu(device, nxy, nz):
+    """N odd (quintic 7 x 7 x 9: 1323 unknowns) takes the Arnoldi passes one
+    element at a time, N even (cubic z 8: 1176) their 16-byte paired loads;
+    two requests each, against the oracle's LU."""
+    import torch
+    fm = _fm()
+    desc = W.make_desc(*W.PS_MINUS, nxy, nz, deg_z=5 if nz % 3 == 0 else 3, R=15.0)
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    assert O.N % 2 == nz % 2
+    Es = [-0.3, -0.17]
+    B = np.stack([W.rhs(41, O.N), W.rhs(42, O.N)])
+    X = torch.zeros(B.shape, dtype=torch.float64, device=device)
+    st, res = P.solve(Es, to_dev(B, device), X, restart=40, rtol=1e-10, max_iters=3000)
+    assert st == fm.FM_OK, res
+    Xg = X.cpu().numpy()
+    for r, E in enumerate(Es):
+        A = O.assemble(E)
+        assert rel_residual(A, Xg[r], B[r]) <= 1e-10
+        xref = lu_solve(A, B[r], "dense")
+        assert np.linalg.norm(Xg[r] - xref) / np.linalg.norm(xref) <= 1e-8
+
+
 def test_solve_batched_energies(device):
     fm = _fm()
     desc = small(W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")
