@@ -212,17 +212,19 @@ def test_solve_ps_cubic16_matches_lu(device):
     assert abs(res[0]["rel_residual"] - rel_residual(A, xg, b)) <= 1e-12
 
 
-@pytest.mark.parametrize("nxy,nz", [(7, 9), (7, 8)])
+@pytest.mark.parametrize("nxy,nz", [(7, 9), (7, 8), (7, 30)])
 def test_solve_odd_and_even_sizes_match_lu(device, nxy, nz):
     """N odd (quintic 7 x 7 x 9: 1323 unknowns) takes the Arnoldi passes one
     element at a time, N even (cubic z 8: 1176) their 16-byte paired loads;
-    two requests each, against the oracle's LU."""
+    N = 4410 (quintic z 30) is even but its two dot-pass chunks of 2205 are
+    not, so the dot pass reads single elements while the update pass reads
+    pairs.  Two requests each, against the oracle's LU."""
     import torch
     fm = _fm()
     desc = W.make_desc(*W.PS_MINUS, nxy, nz, deg_z=5 if nz % 3 == 0 else 3, R=15.0)
     P = fm.Problem(desc)
     O = OracleProblem(desc)
-    assert O.N % 2 == nz % 2
+    assert O.N % 2 == (nz % 2) and (nz != 30 or O.N == 4410)
     Es = [-0.3, -0.17]
     B = np.stack([W.rhs(41, O.N), W.rhs(42, O.N)])
     X = torch.zeros(B.shape, dtype=torch.float64, device=device)
