@@ -60,6 +60,8 @@ CASES = [
     ("L2_tau+1", W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0)),
     ("wide_x97_y13", wide(97, 13, 4, 3)),
     ("x_and_y_pairs_43x19", W.pair_pair_desc()),
+    # six M' blocks: the operator kernels that take the blocks one at a time
+    ("L5_tau+1", W.make_desc(*W.PS_MINUS, 7, 4, J=5, tau=1, deg_z=3, R=15.0)),
 ]
 ES = [-0.25 + 0.03j, 0.1 - 0.2j]
 
@@ -104,6 +106,8 @@ SOLVE_CASES = [
     ("ps_cubic16", W.ps_cubic16()["desc"], [-0.25 + 0.02j, -0.3 - 0.05j, 0.1 + 0.1j], 60),
     ("L2_coupled", dict(W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0), precond="coupled"),
      [-0.3 + 0.05j, -0.2 - 0.01j], 60),
+    ("L5_coupled", dict(W.make_desc(*W.PS_MINUS, 7, 4, J=5, tau=1, deg_z=3, R=15.0), precond="coupled"),
+     [-0.3 + 0.05j, -0.2 - 0.01j], 80),
 ]
 
 
