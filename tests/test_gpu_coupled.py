@@ -102,6 +102,7 @@ LP_CASES = [
     # 2.5e-4), and BF16x3 products (about 16 significant bits) lose the slot
     # altogether, so only FP32 is checked here
     (CASES[4][0], CASES[4][1], "fp32", 5e-3),
+    (CASES[5][0], CASES[5][1], "fp32", 1e-4),
 ]
 
 

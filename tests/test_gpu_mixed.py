@@ -40,7 +40,8 @@ CASES = [("ps_cubic16", W.ps_cubic16()["desc"]),
          ("hminus_22x22x9", W.make_desc(*W.H_MINUS, 22, 9, R=40.0, xy_map="quadratic")),
          ("L2_quintic7_cubic4", W.make_desc(*W.PS_MINUS, 7, 4, J=2, deg_z=3, R=15.0)),
          ("ext_x97_y13", wide(97, 13, 4)), ("ext_x10_y97", wide(10, 97, 4)), ("ext_97x97", wide(97, 97, 4)),
-         ("x_and_y_pairs_43x19", W.pair_pair_desc())]
+         ("x_and_y_pairs_43x19", W.pair_pair_desc()),
+         ("L5_quintic7_cubic4", W.make_desc(*W.PS_MINUS, 7, 4, J=5, deg_z=3, R=15.0))]
 
 
 @pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])
