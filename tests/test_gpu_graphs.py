@@ -40,6 +40,9 @@ CASES = [
     # L = 2 with the coupled preconditioner (joint z products)
     ("L2_coupled", dict(W.make_desc(*W.PS_MINUS, 7, 4, J=2, tau=1, deg_z=3, R=15.0), precond="coupled"),
      [-0.4, -0.3], 30, "fp64"),
+    # six M' blocks (the operator kernels that take the blocks one at a time)
+    ("L5_coupled", dict(W.make_desc(*W.PS_MINUS, 7, 4, J=5, tau=1, deg_z=3, R=15.0), precond="coupled"),
+     [-0.4, -0.3], 30, "fp64"),
 ]
 
 
