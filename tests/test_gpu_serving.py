@@ -25,7 +25,9 @@ def _fm():
 
 
 DESCS = [W.ps_cubic16()["desc"], W.make_desc(*W.H_MINUS, 13, 6, R=30.0, xy_map="quadratic"),
-         W.make_desc(*W.PS_MINUS, 7, 4, J=1, deg_z=3, R=15.0)]
+         W.make_desc(*W.PS_MINUS, 7, 4, J=1, deg_z=3, R=15.0),
+         # six M' blocks with the coupled preconditioner
+         dict(W.make_desc(*W.PS_MINUS, 7, 4, J=5, deg_z=3, R=15.0), precond="coupled")]
 
 
 def test_serving_results_match_solo_and_batch_continuously(device):
