@@ -112,6 +112,29 @@ def test_operator_parity_full_size_sampled(device, cfg):
 
 
 
+def test_operator_parity_full_size_sampled_helium_J10(device):
+    """The fourth J = 10 basis set of the paper's Table 3 (eleven M' blocks,
+    unreduced: N = 3 682 404) on the kernels that take the blocks one at a
+    time: sampled rows against the oracle's."""
+    fm = _fm()
+    g1, g3, _ = W.HE_TABLE3_J10[3]
+    desc = W.helium_desc(g1, g3, dom1=W.HE_TABLE3_DOMAINS[0], dom3=W.HE_TABLE3_DOMAINS[1], J=10, tau=1)
+    P = fm.Problem(desc)
+    O = OracleProblem(desc)
+    assert P.N == O.N == 3682404
+    E = -2.0045
+    x = W.rhs(5, O.N)
+    y = to_dev(np.zeros(O.N), device)
+    P.apply_operator([E], to_dev(x, device), y)
+    yg = y.cpu().numpy()
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.integers(0, O.N, 600), [0, O.N - 1],
+                                     [O.offsets[a][0] for a in range(3)]]))
+    ref = O.rows(E, rows) @ x
+    err = np.abs(yg[rows] - ref).max() / np.abs(ref).max()
+    assert err <= 1e-11, err
+
+
 # sides of 32 m + 1: the last 32 x 32 tile also computes the leftover row (x)
 # or column (y) of the x-y products
 EXT_CASES = [("ext_x97_y13", wide(97, 13, 4, 3)), ("ext_x10_y97", wide(10, 97, 4, 3))]
