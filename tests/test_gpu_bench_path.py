@@ -179,6 +179,34 @@ def test_ps_q127_solves_oracle_residual_every_precision(device):
         assert abs(rel[k] - res[k]["rel_residual"]) <= 1e-12, (prec, rel[k], res[k])
 
 
+@pytest.mark.parametrize("precond", ["block_jacobi", "coupled"])
+def test_ps_l2_q97_solutions_sampled_residual(device, precond):
+    """The L = 2 request at full size (three M' blocks, N = 2 709 792; too large
+    for the oracle's whole residual in a test) solved as the bench solves it
+    with FP64 and FP32 products: at 3000 sampled rows (and the ends of every
+    block) each residual component |b_i - (A x)_i| is at most the whole
+    residual's bound 1e-10 ||b||, by the oracle's rows."""
+    import torch
+    fm = _fm()
+    c = W.ps_l2_q97()
+    desc, E = c["desc"], c["E"][0]
+    P = fm.Problem(dict(desc, precond=precond))
+    b = W.rhs(c["seeds"][0], P.N)
+    O = OracleProblem(desc)
+    assert O.N == P.N
+    rng = np.random.default_rng(12)
+    rows = np.unique(np.concatenate([rng.integers(0, O.N, 3000)] +
+                                    [[o, o + O.block[a] - 1] for a in range(3) for o in O.offsets[a]]))
+    A = O.rows(E, rows)
+    nb = np.linalg.norm(b)
+    for prec in ("fp64", "fp32"):
+        x = torch.zeros((1, P.N), dtype=torch.float64, device=device)
+        st, r = P.solve([E], to_dev(b[None, :], device), x, restart=60, rtol=1e-10, max_iters=2000, prec=prec)
+        assert st == fm.FM_OK, (prec, r)
+        res = b[rows] - A @ x.cpu().numpy()[0]
+        assert np.abs(res).max() <= 1e-10 * nb, (prec, np.abs(res).max() / nb, r)
+
+
 def test_batched_solve_masks_running_requests(device):
     """Nine energies that converge at different steps: the operator kernels
     skip the requests that have finished, and every solution meets the
