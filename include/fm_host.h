@@ -38,10 +38,13 @@ fm_status fm_host_setup_check(const fm_problem_desc *desc, double *max_err, int 
 /* The coupling term of the operator (the off-diagonal blocks in alpha of
  * H - E S: V_alpha^(s) times the partners' expansions at the rotated points,
  * Sec. 2 and eq. (FM-pre)) applied to x, evaluated on the host from the same
- * grouped coupling pairs that the device operator uses: y = C x (N doubles
- * each; both may be NULL to count only).  npairs: (point, partner) pairs with
- * a nonzero factor inside the partner's box; ntasks: groups of at most 64
- * pairs that share one partner cell.  Errors as fm_host_setup_check. */
+ * grouped coupling pairs that the device operator uses, walked as the device
+ * kernels walk them (per wave job and lane, from the task record that lane
+ * reads): y = C x (N doubles each; both may be NULL to count only).  npairs:
+ * (point, partner) pairs with a nonzero factor inside the partner's box;
+ * ntasks: groups of at most 64 pairs that share one partner cell.  Errors as
+ * fm_host_setup_check, and FM_E_INVALID if the jobs do not take every pair
+ * exactly once. */
 fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double *y, long long *npairs, int *ntasks);
 
 /* z = L(E)^-1 r for one request on the host, from the same factor tables that

@@ -862,7 +862,7 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         pd.cpl.ntasks = ch.ntasks;
         pd.cpl.njobs = ch.njobs;
         pd.cpl.pairs_per_lane = ch.pairs_per_lane;
-        pd.cpl.job = put(p, ch.job, err);
+        pd.cpl.jrec = put(p, ch.jrec, err);
         pd.cpl.npairs = ch.npairs;
         pd.cpl.task = put(p, ch.task, err);
         pd.cpl.r = put(p, ch.r, err);

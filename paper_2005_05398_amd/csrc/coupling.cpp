@@ -195,6 +195,7 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
                         const unsigned long long off = (unsigned long long)p->off[b];
                         rec[CT_OFF_LO] = int(off & 0xffffffffull);
                         rec[CT_OFF_HI] = int(off >> 32);
+                        rec[CT_TASK] = int(ch.task.size() / CPL_TASK);
                         int *f = rec + CT_FIDX;
                         for (int k = 0; k < 2 * bz.q; ++k) *f++ = bz.global_index(mz + k / bz.q, k % bz.q);
                         for (int k = 0; k < 2 * bx.q; ++k) *f++ = bx.global_index(mx + k / bx.q, k % bx.q);
@@ -228,6 +229,33 @@ std::string build_coupling(const fm_problem *p, const HostFactors &hf, CouplingH
         }
     }
     ch.njobs = int(ch.job.size() / 2);
+    // job-ordered records (one M'' block): each half's own task record; a job
+    // of one task repeats it in the second half (unsplit) or, when every job is
+    // split, leaves that half empty.  More M'' blocks: job j must be task j.
+    ch.jrec.clear();
+    if (nM == 1) {
+        ch.jrec.assign(size_t(ch.njobs) * 2 * CPL_TASK, 0);
+        for (int j = 0; j < ch.njobs; ++j) {
+            const int t0 = ch.job[2 * j], t1 = ch.job[2 * j + 1];
+            const bool split = t1 >= 0;
+            int *r0 = &ch.jrec[size_t(2 * j) * CPL_TASK], *r1 = r0 + CPL_TASK;
+            std::copy_n(&ch.task[size_t(t0) * CPL_TASK], CPL_TASK, r0);
+            if (split) {
+                std::copy_n(&ch.task[size_t(t1) * CPL_TASK], CPL_TASK, r1);
+            } else if (ch.pairs_per_lane == 1) {
+                std::copy_n(r0, CPL_TASK, r1);
+            } else {
+                r1[CT_TASK] = -1;               // count 0: no pairs
+                r1[CT_SPLIT] = 1;
+            }
+            r0[CT_SPLIT] = split ? 1 : 0;
+            if (split || ch.pairs_per_lane == 1) r1[CT_SPLIT] = r0[CT_SPLIT];
+        }
+    } else {
+        for (int j = 0; j < ch.njobs; ++j)
+            if (ch.job[2 * j] != j || ch.job[2 * j + 1] != -1) return "coupling jobs out of task order";
+        if (ch.njobs != ch.ntasks) return "coupling jobs out of task order";
+    }
     return "";
 }
 

@@ -111,14 +111,22 @@ constexpr int CPL_TASK = 32;     // ints per task record
 enum {
     CT_BETA = 0, CT_MZ, CT_MX, CT_MY, CT_FIRST, CT_COUNT,
     CT_NX, CT_NY, CT_NPTS, CT_OFF_LO, CT_OFF_HI,
-    CT_FIDX = 11                 // 2 q_z z, 2 q x, 2 q y global function indices (-1: dropped)
+    CT_FIDX = 11,                // 2 q_z z, 2 q x, 2 q y global function indices (-1: dropped)
+    CT_SPLIT = 30,               // job records: 1 when the job's two halves hold a task each
+    CT_TASK = 31                 // the task's index (its cell widths in r), -1 in an empty record
 };
+static_assert(CT_FIDX + 3 * MAXR <= CT_SPLIT, "function indices overlap the job fields");
 
 struct CouplingDev {
     int ntasks;
     int njobs;                   // wave jobs: one task, or (one M'' block) two, one per half-wave
     int pairs_per_lane;          // 2: every job two tasks of <= 64 pairs; 1: paired tasks have <= 32
-    const int *job;              // [njobs][2]: first task, second task or -1
+    // one M'' block: [njobs][2][CPL_TASK], the records of each job's two halves,
+    // so that a lane finds its task without a dependent read; a job of one task
+    // repeats its record in the second half (CT_SPLIT 0, the task over the whole
+    // wave) or, with two pairs per lane, has an empty one (count 0, CT_TASK -1).
+    // More M'' blocks: null; job j is task j.
+    const int *jrec;
     long long npairs;
     const int *task;             // [ntasks][CPL_TASK] records (layout above)
     const double *r;             // [ntasks][3] cell width / hbar in z, x, y

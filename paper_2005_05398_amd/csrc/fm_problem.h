@@ -21,6 +21,7 @@ struct HostFactors {
 struct CouplingHost {
     std::vector<int> task, out;  // task: [ntasks][CPL_TASK] records
     std::vector<int> job;        // [njobs][2] wave jobs (second task -1 for a single one)
+    std::vector<int> jrec;       // one M'' block: [njobs][2][CPL_TASK] job-ordered records (CouplingDev::jrec)
     int njobs = 0;
     int pairs_per_lane = 1;
     std::vector<double> s, F, r; // r: [ntasks][3] cell width / hbar (z, x, y)

@@ -128,50 +128,73 @@ fm_status fm_host_coupling(const fm_problem_desc *desc, const double *x, double 
             v[5] = r2 * 0.5 * (s3 - 2.0 * s4 + s5);
         }
     };
-    for (int t = 0; t < ch.ntasks; ++t) {
-        const int *tk = &ch.task[size_t(t) * CPL_TASK];
-        const int b = tk[0], mz = tk[1], mx = tk[2], my = tk[3], first = tk[4], cnt = tk[5];
-        const Basis1D &bz = p.bz[b], &bx = p.bx[b], &by = p.by[b];
-        const double rz = (bz.nodes[mz + 1] - bz.nodes[mz]) / bz.hbar;
-        const double rx = (bx.nodes[mx + 1] - bx.nodes[mx]) / bx.hbar;
-        const double ry = (by.nodes[my + 1] - by.nodes[my]) / by.hbar;
-        int gz[MAXR], gx[MAXR], gy[MAXR];
-        for (int k = 0; k < 2 * bz.q; ++k) gz[k] = bz.global_index(mz + k / bz.q, k % bz.q);
-        for (int k = 0; k < 2 * bx.q; ++k) gx[k] = bx.global_index(mx + k / bx.q, k % bx.q);
-        for (int k = 0; k < 2 * by.q; ++k) gy[k] = by.global_index(my + k / by.q, k % by.q);
-        for (long long pr = first; pr < first + cnt; ++pr) {
-            double vz[MAXR], vx[MAXR], vy[MAXR];
-            shapes(bz.q, ch.s[pr], rz, vz);
-            shapes(bx.q, ch.s[np + pr], rx, vx);
-            shapes(by.q, ch.s[2 * np + pr], ry, vy);
-            double val[MAXM];
-            for (int jM = 0; jM < nM; ++jM) {
-                const double *cb = x + p.off[b] + (long long)jM * p.npts[b];
-                double acc = 0;
-                for (int cz = 0; cz < 2 * bz.q; ++cz) {
-                    if (gz[cz] < 0) continue;
-                    double accx = 0;
-                    for (int ax = 0; ax < 2 * bx.q; ++ax) {
-                        if (gx[ax] < 0) continue;
-                        double accy = 0;
-                        for (int ay = 0; ay < 2 * by.q; ++ay)
-                            if (gy[ay] >= 0) accy += vy[ay] * cb[((long long)gz[cz] * bx.n + gx[ax]) * by.n + gy[ay]];
-                        accx += vx[ax] * accy;
-                    }
-                    acc += vz[cz] * accx;
+    // one pair as a coupling kernel lane evaluates it, from the task record the
+    // lane reads (function indices, beta's sizes and offset, the task index for
+    // the cell widths)
+    std::vector<unsigned char> seen(size_t(np), 0);
+    auto eval_pair = [&](const int *tk, long long pr) {
+        const int b = tk[CT_BETA], task = tk[CT_TASK];
+        const int bnx = tk[CT_NX], bny = tk[CT_NY], bnpts = tk[CT_NPTS];
+        const long long boff = (long long)(((unsigned long long)(unsigned)tk[CT_OFF_HI] << 32) | (unsigned)tk[CT_OFF_LO]);
+        const int qz = p.bz[b].q, qx = p.bx[b].q, qy = p.by[b].q;
+        const int *gz = tk + CT_FIDX, *gx = gz + 2 * qz, *gy = gx + 2 * qx;
+        double vz[MAXR], vx[MAXR], vy[MAXR];
+        shapes(qz, ch.s[pr], ch.r[3 * size_t(task)], vz);
+        shapes(qx, ch.s[np + pr], ch.r[3 * size_t(task) + 1], vx);
+        shapes(qy, ch.s[2 * np + pr], ch.r[3 * size_t(task) + 2], vy);
+        double val[MAXM];
+        for (int jM = 0; jM < nM; ++jM) {
+            const double *cb = x + boff + (long long)jM * bnpts;
+            double acc = 0;
+            for (int cz = 0; cz < 2 * qz; ++cz) {
+                if (gz[cz] < 0) continue;
+                double accx = 0;
+                for (int ax = 0; ax < 2 * qx; ++ax) {
+                    if (gx[ax] < 0) continue;
+                    double accy = 0;
+                    for (int ay = 0; ay < 2 * qy; ++ay)
+                        if (gy[ay] >= 0) accy += vy[ay] * cb[((long long)gz[cz] * bnx + gx[ax]) * bny + gy[ay]];
+                    accx += vx[ax] * accy;
                 }
-                val[jM] = acc;
+                acc += vz[cz] * accx;
             }
-            const int o = ch.out[pr], outp = o >> 1, slot = o & 1;
-            const int a = outp >= p.off[2] ? 2 : (outp >= p.off[1] ? 1 : 0);
-            std::vector<double> &dst = slot == 0 ? c0 : c1;
-            for (int iM = 0; iM < nM; ++iM) {
-                double v = 0;
-                for (int jM = 0; jM < nM; ++jM) v += ch.F[size_t(iM * nM + jM) * np + pr] * val[jM];
-                dst[outp + (long long)iM * p.npts[a]] = v;
+            val[jM] = acc;
+        }
+        const int o = ch.out[pr], outp = o >> 1, slot = o & 1;
+        const int a = outp >= p.off[2] ? 2 : (outp >= p.off[1] ? 1 : 0);
+        std::vector<double> &dst = slot == 0 ? c0 : c1;
+        for (int iM = 0; iM < nM; ++iM) {
+            double v = 0;
+            for (int jM = 0; jM < nM; ++jM) v += ch.F[size_t(iM * nM + jM) * np + pr] * val[jM];
+            dst[outp + (long long)iM * p.npts[a]] = v;
+        }
+        ++seen[pr];
+    };
+    // the pairs in the kernels' order: per wave job and lane, the record the
+    // lane reads and the pair(s) it takes
+    if (nM == 1) {
+        const int P = ch.pairs_per_lane;
+        for (int j = 0; j < ch.njobs; ++j) {
+            const bool split = P == 2 || ch.jrec[size_t(2 * j) * CPL_TASK + CT_SPLIT] != 0;
+            for (int lane = 0; lane < 64; ++lane) {
+                const int *tk = &ch.jrec[size_t(2 * j + (lane >> 5)) * CPL_TASK];
+                const int W = split ? 32 : 64, li = split ? lane & 31 : lane;
+                for (int q = 0; q < P; ++q)
+                    if (li + W * q < tk[CT_COUNT]) eval_pair(tk, tk[CT_FIRST] + li + W * q);
             }
         }
+    } else {
+        for (int j = 0; j < ch.njobs; ++j) {
+            const int *tk = &ch.task[size_t(j) * CPL_TASK];
+            for (int lane = 0; lane < 64; ++lane)
+                if (lane < tk[CT_COUNT]) eval_pair(tk, tk[CT_FIRST] + lane);
+        }
     }
+    for (long long pr = 0; pr < np; ++pr)
+        if (seen[pr] != 1) {
+            set_error("coupling jobs do not take every pair exactly once");
+            return FM_E_INVALID;
+        }
     for (long long i = 0; i < N; ++i) y[i] = c0[i] + c1[i];
     return FM_OK;
 }

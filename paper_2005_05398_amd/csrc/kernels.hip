@@ -772,18 +772,21 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_cells(const Problem
     const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
     const int job = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
     if (job >= cp.njobs) return;                       // the whole wave (no block barriers)
+    // the lane's task record, found from the job index alone (with two halves,
+    // the job-ordered record of the lane's half; with one, job j is task j): the
+    // cell's function indices and beta's sizes come with it, so the fetch of the
+    // cell's coefficients and the pairs' data wait for this one read only
+    const int *t = HALVES == 2 ? cp.jrec + (2 * (size_t)job + (lane >> 5)) * CPL_TASK
+                               : cp.task + (size_t)job * CPL_TASK;
     // two cells (one per half) with two pairs per lane always, with one pair per
-    // lane when the job names a second task; else one cell over the wave
-    const bool split = HALVES == 2 && (P == 2 || __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job + 1]) >= 0);
+    // lane when the job holds a second task; else one cell over the wave (both
+    // halves then read the same record)
+    const bool split = HALVES == 2 && (P == 2 || __builtin_amdgcn_readfirstlane(t[CT_SPLIT]) != 0);
     const int W = split ? 32 : 64;                     // lanes per cell
     const int half = split ? lane >> 5 : 0, li = split ? lane & 31 : lane;
-    const int task = cp.job[2 * (size_t)job + half];   // -1: this half has no task
-    const bool has = task >= 0;
-    // the task record: the cell's function indices and beta's sizes come with
-    // it, so the fetch of the cell's coefficients and the pairs' data wait for
-    // this one read only
-    const int *t = cp.task + (size_t)(has ? task : 0) * CPL_TASK;
-    const int count = has ? t[CT_COUNT] : 0;
+    const int count = t[CT_COUNT];                     // 0: this half has no task
+    const bool has = count > 0;
+    const int task = t[CT_TASK];
     const long long first = t[CT_FIRST];
     const int bnx = t[CT_NX], bny = t[CT_NY], bnpts = t[CT_NPTS];
     const long long boff = (long long)(((unsigned long long)(unsigned)t[CT_OFF_HI] << 32) | (unsigned)t[CT_OFF_LO]);
@@ -941,7 +944,7 @@ __global__ void __launch_bounds__(64 * CPL_WAVES) k_coupling_many(const ProblemD
     const int bid = xcd < full ? xcd * per + blockIdx.x / 8 : full * per + (xcd - full) * (per - 1) + blockIdx.x / 8;
     const int job = __builtin_amdgcn_readfirstlane(bid * CPL_WAVES + wave);
     if (job >= cp.njobs) return;                       // the whole wave (no block barriers)
-    const int task = __builtin_amdgcn_readfirstlane(cp.job[2 * (size_t)job]);
+    const int task = job;                              // with several M'' blocks job j is task j
     const int *t = cp.task + (size_t)task * CPL_TASK;
     const int count = t[CT_COUNT];
     const long long first = t[CT_FIRST];
