@@ -1577,16 +1577,21 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
         if (erow && threadIdx.x < SG_KC) Ae[threadIdx.x] = rae;
         if (ecol && threadIdx.x >= 64 && threadIdx.x < 64 + SG_KC) Be[threadIdx.x - 64] = rbe;
     };
-    // DIVOUT: the eigenvalues and types of the tile's rows, requested now so
-    // that they arrive during the products (a type of 1 marks a row outside
-    // the slice, which is not divided); through LDS, written here and read
-    // after the products (the first barrier of the chunk loop orders them)
-    __shared__ double dv_sl[DIVOUT ? BT : 1];
-    __shared__ int dv_st[DIVOUT ? BT : 1];
+    // DIVOUT: the eigenvalues and types of the tile's rows and columns,
+    // requested now so that they arrive during the products (a type of 1 marks
+    // a line outside the slice, which is not divided); through LDS, written
+    // here and read after the products (the first barrier of the chunk loop
+    // orders them), so that no register is held over the products
+    __shared__ double dv_sl[DIVOUT ? BT : 1], dv_cl[DIVOUT ? BT : 1];
+    __shared__ int dv_st[DIVOUT ? BT : 1], dv_ct[DIVOUT ? BT : 1];
     if (DIVOUT && threadIdx.x < BT) {
         const int row = i0 + (int)threadIdx.x;
         dv_sl[threadIdx.x] = row < nx ? F.lx[fx * nx + row] : 0.0;
         dv_st[threadIdx.x] = row < nx ? F.tx[fx * nx + row] : 1;
+    } else if (DIVOUT && threadIdx.x < 2 * BT) {
+        const int c = (int)threadIdx.x - BT, col = j0 + c;
+        dv_cl[c] = col < ny ? F.ly[fx * ny + col] : 0.0;
+        dv_ct[c] = col < ny ? F.ty[fx * ny + col] : 1;
     }
     // wave (wi, wj) owns the (16 WT) x (16 WT) block at rows 16 WT wi, columns 16 WT wj
     dbl4 acc[WT][WT];
@@ -1638,18 +1643,13 @@ __global__ void __launch_bounds__(256) k_slice_gemm(const ProblemDev *__restrict
     };
     {
         // stores straight from the accumulators; DIVOUT divides on the way, with
-        // the rows' eigenvalues from LDS and the lane's columns' read here
+        // the rows' and the lane's columns' eigenvalues from LDS
         double cl[WT];
         int ct[WT];
 #pragma unroll
         for (int tj = 0; tj < WT; ++tj) {
-            const int col = j0 + 16 * (WT * wj + tj) + r16;
-            cl[tj] = 0.0;
-            ct[tj] = 1;
-            if (DIVOUT && col < ny) {
-                cl[tj] = F.ly[fx * ny + col];
-                ct[tj] = F.ty[fx * ny + col];
-            }
+            cl[tj] = DIVOUT ? dv_cl[16 * (WT * wj + tj) + r16] : 0.0;
+            ct[tj] = DIVOUT ? dv_ct[16 * (WT * wj + tj) + r16] : 1;
         }
 #pragma unroll
         for (int ti = 0; ti < WT; ++ti)
