@@ -864,7 +864,8 @@ std::string upload(fm_problem *p, const HostFactors &hf) {
         pd.cpl.pairs_per_lane = ch.pairs_per_lane;
         pd.cpl.jrec = put(p, ch.jrec, err);
         pd.cpl.npairs = ch.npairs;
-        pd.cpl.task = put(p, ch.task, err);
+        // with one M'' block the kernels read the job-ordered copies only
+        pd.cpl.task = p->nM == 1 ? nullptr : put(p, ch.task, err);
         pd.cpl.r = put(p, ch.r, err);
         pd.cpl.out = put(p, ch.out, err);
         pd.cpl.s = put(p, ch.s, err);

@@ -128,7 +128,7 @@ struct CouplingDev {
     // More M'' blocks: null; job j is task j.
     const int *jrec;
     long long npairs;
-    const int *task;             // [ntasks][CPL_TASK] records (layout above)
+    const int *task;             // [ntasks][CPL_TASK] records (layout above); more M'' blocks only (else null)
     const double *r;             // [ntasks][3] cell width / hbar in z, x, y
     const int *out;              // [npairs] 2 * (alpha output index of M' block 0) + slot
     const double *s;             // [3][npairs] position inside the cell: z, x, y
