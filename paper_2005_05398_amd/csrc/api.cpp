@@ -304,7 +304,7 @@ void add_closing_work(fm_problem *p, const Work &w, int steps) {
 // tmp: [nb][N] scratch for the staged x-y products (may be null).
 void apply_precond(fm_problem *p, int nb, const double *E_dev, const int *mask, const double *in, double *out,
                    int prec, double *min_den, double *tmp, hipStream_t st) {
-    if (prec != FM_FP64 && precond_f32_ok(p->pd, p->pr, nb)) {
+    if (prec != FM_FP64 && precond_f32_ok(p->pd, p->pr, nb, prec)) {
         // FP32 storage between the reduced-precision products
         timed(p, st, FM_K_MODEZ, [&] { launch_z_f32(p->pd, p->pr, nb, mask, 0, in, out, tmp, st); });
         timed(p, st, FM_K_XY, [&] { launch_xy_f32(p->pd, p->pr, nb, E_dev, mask, prec, out, tmp, st); });

@@ -232,11 +232,13 @@ void launch_zjoint(const ProblemDev &pd, const PrecDev &pr, int nb, const int *a
 void launch_modez(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which,
                   const double *in, double *out, hipStream_t st);
 // tmp ([nb][N] scratch): the four products run as batched GEMMs through tmp
-// over all slices at once when a slice side exceeds XY_FUSED_MAX_SIDE or the
-// batch has fewer than XY_STAGED_BELOW slices; otherwise (many small slices)
-// one block per slice does all four in LDS.
-constexpr long long XY_STAGED_BELOW = 512;
+// over all slices at once when a slice side exceeds XY_FUSED_MAX_SIDE;
+// otherwise one block per slice does all four in LDS, however few the slices
+// (measured faster from 24 slices up: a single launch instead of five).
 constexpr int XY_FUSED_MAX_SIDE = 32;
+// BF16x3 products: the staged chain below this many slices (measured faster at
+// 384 slices of side 31; FP64 and FP32 take the fused kernel at any count)
+constexpr long long XY_BF16_FUSED_FROM = 512;
 constexpr long long XY_T64_MIN_BLOCKS = 1024;  // staged products: 64 x 64 tiles from this many blocks
 void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active,
                double *data, double *min_den, double *tmp, hipStream_t st);
@@ -251,9 +253,9 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
 // stays FP64, in -> tmp), the four staged x-y products through the FP32 views
 // of out and tmp with the FP64 divide, and the z product back (which 1: into
 // out, FP64).  in may equal out; tmp: [nb][N] doubles.  precond_f32_ok: the
-// staged products and the register z product apply (else the caller runs the
-// FP64-storage path).
-bool precond_f32_ok(const ProblemDev &pd, const PrecDev &pr, int nb);
+// staged products (for this mode) and the register z product apply (else the
+// caller runs the FP64-storage path).
+bool precond_f32_ok(const ProblemDev &pd, const PrecDev &pr, int nb, int mode);
 void launch_z_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const int *active, int which, const double *in,
                   double *out, double *tmp, hipStream_t st);
 void launch_xy_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, int mode,

@@ -1334,8 +1334,8 @@ __global__ void __launch_bounds__(NW * 64) k_xy_mfma(const ProblemDev *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Staged x-y products, for batches with too few slices to fill the chip at one
-// block per slice: each of the four products is a batched FP64 MFMA GEMM over
+// Staged x-y products, for slices wider than one block's LDS tile of the
+// fused kernel holds: each of the four products is a batched FP64 MFMA GEMM over
 // all (request, alpha, M', k) slices with 32 x 32 output tiles (a 16 x 16 tile
 // per wave), reading one buffer and writing the other; the divide is a pass of
 // its own in between.  Slices are numbered alpha-major, then M', then k.
@@ -3120,7 +3120,7 @@ void launch_xy(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_
         tiles = std::max(tiles, (int)(cdiv(pd.comp[a].x.n, SG_T) * cdiv(pd.comp[a].y.n, SG_T)));
         side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
     }
-    if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
+    if (side > XY_FUSED_MAX_SIDE) {
         // 64 x 64 block tiles (2 x 2 MFMA tiles per wave) for slices wider than 32
 #define FM_SG(BT)                                                                                                      \
     {                                                                                                                  \
@@ -3181,6 +3181,8 @@ void launch_modez_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const int 
     hipLaunchKernelGGL(k_modez32, grid, dim3(MZ_COLS), sh, st, pd.dev, pr.dev, active, which, in, out);
 }
 
+bool xy_lp_staged(const ProblemDev &pd, int nb, int mode);
+
 bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev, const int *active, double *data,
                   int mode, double *tmp, hipStream_t st) {
     {
@@ -3190,7 +3192,7 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
             tiles = std::max(tiles, sg_tiles(pd.comp[a].x.n, SG_T) * sg_tiles(pd.comp[a].y.n, SG_T));
             side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
         }
-        if (side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW) {
+        if (xy_lp_staged(pd, nb, mode)) {
             const dim3 g(slices, tiles, nb);
 #define FM_SGLP(L, D, M, W, I, O) \
     hipLaunchKernelGGL((k_slice_gemm_lp<L, D, M>), g, dim3(256), 0, st, pd.dev, pr.dev, E_dev, active, W, I, O)
@@ -3234,13 +3236,16 @@ bool launch_xy_lp(const ProblemDev &pd, const PrecDev &pr, int nb, const double 
     return true;
 }
 
-bool xy_lp_staged(const ProblemDev &pd, int nb) {
-    int slices = 0, side = 0;
+bool xy_lp_staged(const ProblemDev &pd, int nb, int mode) {
+    long long slices = 0;
+    int side = 0;
     for (int a = 0; a < 3; ++a) {
-        slices += pd.nM * pd.comp[a].z.n;
+        slices += (long long)pd.nM * pd.comp[a].z.n;
         side = std::max(side, std::max(pd.comp[a].x.n, pd.comp[a].y.n));
     }
-    return side > XY_FUSED_MAX_SIDE || (long long)slices * nb < XY_STAGED_BELOW;
+    // BF16x3 (three products per product) keeps the staged chain below
+    // XY_BF16_FUSED_FROM slices, where its one-block-per-slice kernel is slower
+    return side > XY_FUSED_MAX_SIDE || (mode == 2 && slices * nb < XY_BF16_FUSED_FROM);
 }
 
 // The four staged x-y products with FP32 storage between them: src (TI) ->
@@ -3292,8 +3297,8 @@ void xy_f32(const ProblemDev &pd, const PrecDev &pr, int nb, const double *E_dev
     }
 }
 
-bool precond_f32_ok(const ProblemDev &pd, const PrecDev &pr, int nb) {
-    if (!xy_lp_staged(pd, nb)) return false;
+bool precond_f32_ok(const ProblemDev &pd, const PrecDev &pr, int nb, int mode) {
+    if (!xy_lp_staged(pd, nb, mode)) return false;
     int maxnz = 0;
     for (int a = 0; a < 3; ++a) maxnz = std::max(maxnz, pd.comp[a].z.n);
     return pr.coupled || maxnz <= 64;

@@ -53,8 +53,9 @@ CASES = [
 
 @pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])
 def test_coupled_precond_parity(device, name, desc):
-    """Staged x-y products (two requests) and, for small slices, the one block
-    per slice path (enough requests for 512 slices) against the oracle."""
+    """Two requests and a batch of 512 slices or more (one block per slice
+    for sides <= 32, batched GEMMs for wider ones) against the oracle, and
+    against each other."""
     import torch
     fm = _fm()
     P = fm.Problem(coupled(desc))

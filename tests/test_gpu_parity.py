@@ -331,11 +331,12 @@ def test_solve_rejects_nonfinite_rhs(device):
 
 @pytest.mark.parametrize("name,desc", PREC_CASES, ids=[c[0] for c in PREC_CASES])
 def test_precond_one_block_per_slice_and_staged_paths(device, name, desc):
-    """Batches of many small slices (side <= 32, 512 slices or more) run the
-    x-y products with one block per slice, the others as batched GEMMs over
-    all slices.  Both must match the oracle's separable inverse, and each
-    other.  Slices whose sides are not multiples of 16 exercise the MFMA
-    output rows that fall outside the slice (they must map back inside it)."""
+    """Slices of side <= 32 run the x-y products with one block per slice,
+    wider ones as batched GEMMs over all slices, whatever the batch: a batch
+    of 512 slices or more and one of two requests must both match the
+    oracle's separable inverse, and each other.  Slices whose sides are not
+    multiples of 16 exercise the MFMA output rows that fall outside the slice
+    (they must map back inside it)."""
     import torch
     fm = _fm()
     P = fm.Problem(desc)
@@ -347,7 +348,7 @@ def test_precond_one_block_per_slice_and_staged_paths(device, name, desc):
     R = rng.standard_normal((nb_big, O.N))
     Zbig = to_dev(np.zeros((nb_big, O.N)), device)
     P.apply_precond(Es, to_dev(R, device), Zbig)
-    Zsmall = to_dev(np.zeros((2, O.N)), device)           # staged
+    Zsmall = to_dev(np.zeros((2, O.N)), device)
     P.apply_precond(Es[:2], to_dev(R[:2], device), Zsmall)
     Zb = Zbig.cpu().numpy()
     for r in (0, 1, nb_big - 1):
@@ -379,18 +380,18 @@ def test_precond_after_operator_grows_its_buffer(device):
     assert np.abs(z2.cpu().numpy()[0] - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("nb", [1, 24])
-def test_solve_reports_the_smallest_denominator(device, nb):
+@pytest.mark.parametrize("nxy,nb", [(16, 1), (16, 24), (34, 1)])
+def test_solve_reports_the_smallest_denominator(device, nxy, nb):
     """min_abs_denominator of a solve is the smallest |lambda_x + lambda_y - E|
     over every slice of the preconditioner (eq. (prec-2)); on a cubic grid
-    every pencil eigenvalue is real.  One request runs the staged x-y products
-    (divide on the store of the right product), 24 requests (576 slices) the
-    one-block-per-slice kernel.  The host side is the library's own slice
-    eigenvalues (fm_host_slice_eigenvalues) with the same FP64 sum, so the two
-    agree exactly."""
+    every pencil eigenvalue is real.  Side 16 runs the one-block-per-slice
+    kernel (one request, and 24 requests), side 34 the staged x-y products
+    (divide on the store of the right product).  The host side is the
+    library's own slice eigenvalues (fm_host_slice_eigenvalues) with the same
+    FP64 sum, so the two agree exactly."""
     import torch
     fm = _fm()
-    desc = W.ps_cubic16()["desc"]
+    desc = W.ps_cubic16()["desc"] if nxy == 16 else W.make_desc(*W.PS_MINUS, nxy, 8, deg_xy=3, deg_z=3, R=20.0)
     P = fm.Problem(desc)
     E = -0.3141
     want = np.inf
