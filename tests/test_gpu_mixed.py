@@ -126,3 +126,24 @@ def test_precond_reduced_precision_wide_batch(device, prec, tol, precond):
     P.apply_precond(Es, r, zlp, prec=prec)
     err = (torch.linalg.norm(zlp - z64, dim=1) / torch.linalg.norm(z64, dim=1)).max().item()
     assert err <= tol, (prec, precond, err)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 1e-3)])
+def test_precond_reduced_precision_many_small_slices(device, prec, tol):
+    """A batch of 512 slices or more of side 16 (23 requests of the cubic
+    16 x 16 x 8 grid, 552 slices): one block per slice for both reduced
+    precisions (BF16x3 takes its staged chain only below 512 slices), each
+    request against the FP64 preconditioner at its precision's bound."""
+    import torch
+    fm = _fm()
+    desc = W.ps_cubic16()["desc"]
+    P = fm.Problem(desc)
+    nb = -(-512 // (3 * desc["z"][0]["n"])) + 1
+    r = to_dev(W.rhs_batch([70 + i for i in range(nb)], P.N), device)
+    z64 = torch.zeros_like(r)
+    zlp = torch.zeros_like(r)
+    Es = list(np.linspace(-0.6, -0.1, nb))
+    P.apply_precond(Es, r, z64, prec="fp64")
+    P.apply_precond(Es, r, zlp, prec=prec)
+    err = (torch.linalg.norm(zlp - z64, dim=1) / torch.linalg.norm(z64, dim=1)).max().item()
+    assert err <= tol, (prec, nb, err)
